@@ -1,0 +1,217 @@
+"""Seeded synthetic workloads for the generalized-Neumann-kernel solver.
+
+Every workload is a list of boundary components sampled on the trapezoidal
+mesh, plus the coefficient A (and A') and one or more right-hand sides.
+Seeds: ``numpy.random.default_rng([13085351, cfg])`` and, for the batched
+workload, ``[13085351, 3, d]`` for domain d.
+
+Shapes and value distributions follow the paper's workloads (Sec. 7):
+multiply connected domains of circles / ellipses / piecewise smooth curves on
+Kress-graded meshes, with boundaries close to each other. The concrete layouts
+below are seeded stand-ins; the paper's own layouts only exist in figures.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import geometry as geo
+
+SEED = 13085351
+
+
+@dataclass
+class Domain:
+    """Discretised boundary of an (m+1)-connected domain (paper Sec. 2.1, 2.4).
+
+    All arrays are complex128 of length N = m1 * n in component-major order."""
+    m1: int
+    n: int
+    eta: np.ndarray
+    etap: np.ndarray
+    etapp: np.ndarray
+    A: np.ndarray
+    Ap: np.ndarray
+    bounded: bool
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return self.m1 * self.n
+
+    @property
+    def c(self) -> int:
+        """+1 for bounded, -1 for unbounded (eq. (e:c))."""
+        return 1 if self.bounded else -1
+
+    def comp(self, k):
+        return slice(k * self.n, (k + 1) * self.n)
+
+
+def _assemble(curves, n, bounded, A_kind, alpha=0j, theta=None, name="", meta=None):
+    """curves: list of callables t -> (eta, eta', eta''). A_kind: 'one' | 'eta-alpha'."""
+    t = geo.nodes(n)
+    parts = [c(t) for c in curves]
+    eta = np.concatenate([p[0] for p in parts])
+    etap = np.concatenate([p[1] for p in parts])
+    etapp = np.concatenate([p[2] for p in parts])
+    m1 = len(curves)
+    if theta is None:
+        rot = np.ones(eta.shape, np.complex128)
+    else:
+        th = np.repeat(np.asarray(theta, np.float64), n)
+        rot = np.exp(1j * (np.pi / 2 - th))
+    if A_kind == "one":
+        A = np.ones_like(eta) if theta is None else rot.copy()
+        Ap = np.zeros_like(eta)
+    elif A_kind == "eta-alpha":
+        # eq. (e:A), bounded case: A = e^{i(pi/2-theta)} (eta - alpha)
+        A = rot * (eta - alpha)
+        Ap = rot * etap
+    else:
+        raise ValueError(A_kind)
+    return Domain(m1, n, eta, etap, etapp, A, Ap, bounded, name, meta or {})
+
+
+# ----------------------------------------------------------------------------
+# Small closed-form domains used as pins (disk, annulus, circles).
+# ----------------------------------------------------------------------------
+def disk(n: int, A_kind="eta-alpha"):
+    """Unit disk, alpha = 0, theta = pi/2 -> A = eta (eq. (e:A))."""
+    return _assemble([lambda t: geo.circle(t, 0j, 1.0, True)], n, True, A_kind, 0j, name="disk")
+
+
+def annulus(n: int, r_in=0.4, alpha=0.7j * 0 + 0.7, center_in=0j):
+    """Bounded annulus: outer unit circle ccw, inner circle cw; A = eta - alpha."""
+    curves = [lambda t: geo.circle(t, 0j, 1.0, True),
+              lambda t: geo.circle(t, center_in, r_in, False)]
+    return _assemble(curves, n, True, "eta-alpha", alpha, name="annulus")
+
+
+def circles_unbounded(n: int, centers, radii, theta=None):
+    """Exterior of several circles (all cw), A = e^{i(pi/2 - theta)} (eq. (e:A))."""
+    curves = [(lambda t, c=c, r=r: geo.circle(t, c, r, False)) for c, r in zip(centers, radii)]
+    return _assemble(curves, n, False, "one", theta=theta, name="circles")
+
+
+def example2_circles(n: int, eps: float, theta=None):
+    """Paper Example 2: unit circle and four inner circles at separation eps."""
+    s = 2.0 + 2.0 * np.sqrt(2.0)
+    r = (2.0 - eps * s) / s
+    off = (2.0 - eps) / s
+    cs = [off + 1j * off, -off + 1j * off, -off - 1j * off, off - 1j * off]
+    curves = [lambda t: geo.circle(t, 0j, 1.0, True)] + \
+             [(lambda t, c=c: geo.circle(t, c, r, False)) for c in cs]
+    return _assemble(curves, n, True, "eta-alpha", 0j, theta=theta, name=f"ex2-eps{eps:g}")
+
+
+def example4_circles(n: int, eps: float, theta=None):
+    """Paper Example 4: unbounded, five circles at mutual distance eps."""
+    cs = [0j, 1 + 1j, -1 + 1j, -1 - 1j, 1 - 1j]
+    rs = [np.sqrt(2.0) - 1.0 - eps / 2] + [1.0 - eps / 2] * 4
+    return circles_unbounded(n, cs, rs, theta)
+
+
+# ----------------------------------------------------------------------------
+# Benchmark workloads.
+# ----------------------------------------------------------------------------
+def _point_outside_ellipse(z, c, a, b, phi, margin):
+    w = (z - c) * np.exp(-1j * phi)
+    return (w.real / (a + margin)) ** 2 + (w.imag / (b + margin)) ** 2 > 1.0
+
+
+def config0(A_kind="one"):
+    """Doubly connected, bounded: unit circle + cw ellipse; n = 256; alpha = 0.5.
+
+    A_kind='one' is the workload as stated (A = 1 on a bounded domain);
+    A_kind='eta-alpha' is the admissible companion A = eta - 0.5."""
+    rng = np.random.default_rng([SEED, 0])
+    alpha = 0.5 + 0j
+    while True:
+        r0 = 0.2 * np.sqrt(rng.uniform())
+        c = r0 * np.exp(1j * rng.uniform(0, 2 * np.pi))
+        a = rng.uniform(0.2, 0.35)
+        b = rng.uniform(0.1, 0.2)
+        phi = rng.uniform(0, np.pi)
+        if _point_outside_ellipse(alpha, c, a, b, phi, 0.05 * a):
+            break
+    n = 256
+    curves = [lambda t: geo.circle(t, 0j, 1.0, True),
+              lambda t: geo.ellipse(t, c, a, b, phi, ccw=False)]
+    dom = _assemble(curves, n, True, A_kind, alpha, name="cfg0" + ("" if A_kind == "one" else "b"),
+                    meta=dict(alpha=alpha, ellipse=(c, a, b, phi)))
+    gam = np.log(np.abs(dom.eta - alpha))
+    return dom, gam[:, None]
+
+
+def config1(n: int = 1024, m_inner: int = 16):
+    """Bounded, unit circle + 16 seeded cw ellipses; A = eta (alpha = 0); gamma = -log|eta|."""
+    rng = np.random.default_rng([SEED, 1])
+    placed = []   # (center, a, b, phi)
+    gap = 0.04
+    while len(placed) < m_inner:
+        a = rng.uniform(0.03, 0.08)
+        b = rng.uniform(0.03, 0.08)
+        phi = rng.uniform(0, np.pi)
+        R = max(a, b)
+        rho = (1.0 - R - gap) * np.sqrt(rng.uniform())
+        c = rho * np.exp(1j * rng.uniform(0, 2 * np.pi))
+        if abs(c) < R + gap:          # keep alpha = 0 in G
+            continue
+        ok = all(abs(c - c2) >= R + max(a2, b2) + gap for c2, a2, b2, _ in placed)
+        if ok:
+            placed.append((c, a, b, phi))
+    curves = [lambda t: geo.circle(t, 0j, 1.0, True)] + \
+             [(lambda t, p=p: geo.ellipse(t, p[0], p[1], p[2], p[3], ccw=False)) for p in placed]
+    dom = _assemble(curves, n, True, "eta-alpha", 0j, name="cfg1", meta=dict(ellipses=placed))
+    gam = -np.log(np.abs(dom.eta))
+    return dom, gam[:, None]
+
+
+def fourier_perturbed_circles(m1: int, n: int, seed, side=13.0, dmin=1.0,
+                              rrange=(0.25, 0.35), nterms=16, amp=0.1):
+    """Unbounded domain exterior to m1 perturbed circles, each a 16-term Fourier
+    series eta_j(t) = sum_{k=-7..8} c_{j,k} e^{-ikt} (clockwise)."""
+    rng = np.random.default_rng(seed)
+    centers = []
+    while len(centers) < m1:
+        c = complex(*rng.uniform(-side / 2, side / 2, 2))
+        if all(abs(c - c2) >= dmin for c2 in centers):
+            centers.append(c)
+    kmin = -7
+    coeffs = np.zeros((m1, nterms), np.complex128)
+    for j, c in enumerate(centers):
+        r = rng.uniform(*rrange)
+        cj = (rng.uniform(-1, 1, nterms) + 1j * rng.uniform(-1, 1, nterms)) * amp * r / np.sqrt(2)
+        ks = np.arange(kmin, kmin + nterms)
+        cj[ks == 0] = c
+        cj[ks == 1] = r
+        pert = (ks != 0) & (ks != 1)
+        s = np.sum(np.abs(ks[pert]) * np.abs(cj[pert]))
+        if s > 0.5 * r:
+            cj[pert] *= 0.5 * r / s
+        coeffs[j] = cj
+    return coeffs, kmin
+
+
+def config4(n: int = 2048, m1: int = 129):
+    """Unbounded, 129 perturbed circles (16 Fourier coefficients each); A = 1; gamma = Re(eta^2)."""
+    coeffs, kmin = fourier_perturbed_circles(m1, n, [SEED, 4])
+    dom = domain_from_fourier(coeffs, kmin, n)
+    gam = (dom.eta ** 2).real
+    return dom, gam[:, None]
+
+
+def domain_from_fourier(coeffs, kmin, n, name="fourier"):
+    curves = [(lambda t, cj=cj: geo.fourier_curve(t, cj, kmin, ccw=False)) for cj in coeffs]
+    d = _assemble(curves, n, False, "one", name=name)
+    d.meta.update(coeffs=np.array(coeffs), kmin=kmin)
+    return d
+
+
+def closed_form_rhs(dom: Domain, f):
+    """gamma = Re[A f(eta)], exact mu = Im[A f(eta)], h = 0 (paper eq. (e:ex-gam))."""
+    v = dom.A * f(dom.eta)
+    return v.real.copy(), v.imag.copy()
