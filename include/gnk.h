@@ -1,0 +1,191 @@
+/*
+ * gnk.h -- C ABI of the MI355X (gfx950) solver for boundary integral equations
+ * with the generalized Neumann kernel (Nasser, "Fast solution of boundary
+ * integral equations with the generalized Neumann kernel").
+ *
+ * Problem statement (paper Sec. 1, eqs. (e:ie), (e:h), (e:ie*)):
+ *   (I - N) mu = -M gamma,   h = [M mu - (I - N) gamma] / 2,
+ *   (I + N* + J) mu = gamma,
+ * discretised by the trapezoidal-rule Nystrom method with singularity
+ * subtraction (Sec. 3.1-3.2 and 4.1-4.2):
+ *   (2I + diag(B1) - B) mu = -y,  y = (D - diag(D1) + Lhat) gamma    (eqs. (e:sys), (e:y))
+ *   h = [(D - diag(D1) + Lhat) mu - (2I + diag(B1) - B) gamma] / 2   (eq. (e:bh))
+ *   (diag(e) + B^T + Phat) mu = gamma                                  (eq. (e:sys*))
+ * and solved by restarted GMRES (Sec. 3.5, 4.5) whose matrix-vector product is
+ * the Cauchy sum (E w)_i = sum_{j != i} w_j / (eta_i - eta_j) (eq. (e:fmm-E)),
+ * evaluated directly on the GPU, plus the m+1 circulant blocks L of Sec. 3.3
+ * applied by FFT (eq. (e:L-bs)).
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE pointers on the context's device (for example
+ *     torch tensor data pointers). Complex arrays are interleaved pairs of
+ *     doubles {re, im} (the layout of complex128). Real arrays are double.
+ *   - Node ordering is component-major: node i = k*n + p, component
+ *     k = 0..m, node p = 0..n-1 at parameter t = 2*pi*p/n (eq. (e:ti-skp)).
+ *   - Multi-column arrays (nrhs right-hand sides) are column-major with
+ *     leading dimension N = (m+1)*n: column r starts at element r*N.
+ *   - The caller owns every input and output buffer. The library owns its
+ *     workspace inside the context (grown on demand, released by gnk_destroy)
+ *     and keeps no caller pointer after a call returns.
+ *   - Work is enqueued on the context stream; every call returns after the
+ *     stream has completed that work, so outputs and info are valid on return.
+ *   - Errors are reported by status codes; no exception crosses the ABI.
+ *     A negative status means no output was written. GNK_NOT_CONVERGED (> 0)
+ *     means the best iterate was written (the "flag = 1" of MATLAB's gmres).
+ *     gnk_last_error() returns a message for the last failing call.
+ *   - One context per host thread; a context is not thread-safe.
+ */
+#ifndef GNK_H
+#define GNK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Exported entry points (the library is built with hidden default visibility). */
+#define GNK_API __attribute__((visibility("default")))
+
+typedef struct gnk_ctx gnk_ctx;
+
+typedef enum {
+  GNK_OK = 0,
+  GNK_NOT_CONVERGED = 1,   /* result written; GMRES stopped at maxit above tol */
+  GNK_ERR_ARG = -1,        /* null pointer, bad size, bad option */
+  GNK_ERR_ODD_N = -2,      /* n must be even (Sec. 2.4) */
+  GNK_ERR_ZERO_A = -3,     /* A(t_i) == 0 at some node */
+  GNK_ERR_ZERO_ETAP = -4,  /* eta'(t_i) == 0 where the adjoint equation divides by it */
+  GNK_ERR_NONFINITE = -5,  /* NaN or Inf in an input */
+  GNK_ERR_HIP = -10,       /* a HIP runtime call failed */
+  GNK_ERR_OOM = -11        /* workspace allocation failed or exceeds GNK_WORKSPACE_MB */
+} gnk_status;
+
+typedef enum { GNK_FP64 = 0, GNK_MIXED = 1 } gnk_precision;
+
+/* Operators for gnk_apply (x real N x nrhs -> y real N x nrhs). */
+typedef enum {
+  GNK_OP_FB = 0,    /* (2I + diag(B1) - B) x                    eq. (e:f_B)          */
+  GNK_OP_FC = 1,    /* (D - diag(D1) + Lhat) x                  eqs. (e:y), (e:bh)   */
+  GNK_OP_GB = 2,    /* (diag(e) + B^T + Phat) x                 eq. (e:g_B)          */
+  GNK_OP_FB_T = 3,  /* (2I + diag(B1) - B)^T x                  transpose of FB      */
+  GNK_OP_FC_T = 4,  /* (D - diag(D1) + Lhat)^T x = (D^T - diag(D1) - Lhat) x         */
+  GNK_OP_GB_T = 5,  /* (diag(e) + B + Phat) x                   transpose of GB      */
+  GNK_OP_LHAT = 6   /* Lhat x, the circulant blocks alone       eq. (e:L-bs)         */
+} gnk_op;
+
+/* Boundary data of an (m+1)-connected domain (Sec. 2.1-2.2).
+ *   eta, etap : N complex, eta(t_i) and eta'(t_i).
+ *   A         : N complex, nonzero; eq. (e:A) gives the admissible choices
+ *               e^{i(pi/2-theta)}(eta-alpha) (bounded) and e^{i(pi/2-theta)}
+ *               (unbounded); any nonzero values are accepted.
+ *   etapp, Ap : N complex, eta'' and A'; used only by the adjoint equation
+ *               (may be NULL for the FBIE entry points).
+ *   c         : +1 bounded, -1 unbounded (eq. (e:c)); adjoint equation only. */
+typedef struct {
+  int64_t m1;        /* number of boundary components m+1 (>= 1) */
+  int64_t n;         /* nodes per component (even, >= 2) */
+  const void* eta;
+  const void* etap;
+  const void* etapp;
+  const void* A;
+  const void* Ap;
+  int c;
+} gnk_domain;
+
+/* Solver options (the restart / gmrestol / maxit arguments of Sec. 3.5).
+ *   restart    : inner iterations per cycle (1..64)
+ *   maxit      : maximum number of restart cycles (>= 1)
+ *   tol        : relative residual ||b - A x||_2 / ||b||_2 per right-hand side
+ *   prec       : GNK_FP64, or GNK_MIXED (FP32 well-separated pairs inside an
+ *                FP64 iterative refinement; converges to the same tol)
+ *   inner_tol  : relative tolerance of each inner solve in GNK_MIXED (0: 1e-6)
+ *   max_refine : maximum refinement steps in GNK_MIXED (0: 20)
+ *   x0         : optional device initial guess (N x nrhs) or NULL for zero */
+typedef struct {
+  int restart;
+  int maxit;
+  double tol;
+  int prec;
+  double inner_tol;
+  int max_refine;
+  const double* x0;
+} gnk_opts;
+
+/* Per right-hand side outcome (host memory, one entry per column).
+ *   flag        : 0 converged, 1 not converged
+ *   outer_it    : restart cycles used;  inner_it: total Arnoldi steps
+ *   relres      : GMRES residual estimate at exit
+ *   true_relres : ||b - A x|| / ||b|| recomputed with an FP64 product
+ *   refine_steps: refinement steps (GNK_MIXED), 0 otherwise */
+typedef struct {
+  int flag;
+  int outer_it;
+  int inner_it;
+  int refine_steps;
+  double relres;
+  double true_relres;
+} gnk_info;
+
+/* Context lifetime. device: HIP device ordinal. The default stream is the
+ * null stream; gnk_set_stream installs a caller stream (hipStream_t). */
+GNK_API gnk_status gnk_create(gnk_ctx** ctx, int device);
+GNK_API gnk_status gnk_destroy(gnk_ctx* ctx);
+GNK_API gnk_status gnk_set_stream(gnk_ctx* ctx, void* hip_stream);
+GNK_API const char* gnk_last_error(const gnk_ctx* ctx);
+/* Library version string (static storage). */
+GNK_API const char* gnk_version(void);
+
+/* Timing of the Cauchy-sum launches (the hot kernel), measured with HIP
+ * events recorded on the context stream around every launch while enabled.
+ *   launches, ms      : all launches and their summed duration
+ *   pair_cols         : sum over launches of N(N-1) * columns
+ *   flops             : N(N-1) * (16 + 8 (columns - 1)) summed (16 flops per
+ *                       pair and column 1, 8 per further column sharing it)
+ *   launches1, ms1, pairs1 : the single-column launches alone */
+typedef struct {
+  int64_t launches;
+  double ms;
+  double pair_cols;
+  double flops;
+  int64_t launches1;
+  double ms1;
+  double pairs1;
+} gnk_prof;
+
+/* enable: 1 starts recording, 0 stops (already recorded launches are kept). */
+GNK_API gnk_status gnk_profile(gnk_ctx* ctx, int enable);
+/* Waits for the stream, folds the recorded launches into the totals, copies
+ * them to *out (may be NULL), and clears them when reset != 0. */
+GNK_API gnk_status gnk_profile_read(gnk_ctx* ctx, gnk_prof* out, int reset);
+
+/* Cauchy sum S = E w (eq. (e:fmm-E), the product that the paper computes with
+ * zfmm2dpart, eq. (e:E-fmm)):  S_i = sum_{j != i} w_j / (eta_i - eta_j).
+ *   N     : number of nodes; eta: N complex.
+ *   w     : N x nrhs complex; S: N x nrhs complex (output, must not alias w).
+ * FP64; every pair is evaluated directly (no far-field approximation).
+ * Coincident nodes (eta_i == eta_j, i != j) give non-finite sums. */
+GNK_API gnk_status gnk_cauchy_sum(gnk_ctx* ctx, int64_t N, const void* eta, const void* w, int nrhs,
+                          void* S);
+
+/* Operator application y = op(x) for one domain (see gnk_op). x and y are
+ * real N x nrhs and must not alias. GB and GB_T need etapp, Ap and c. */
+GNK_API gnk_status gnk_apply(gnk_ctx* ctx, const gnk_domain* dom, int op, const double* x, int nrhs,
+                     double* y);
+
+/* FBIE (Sec. 3): solve (I - N) mu = -M gamma and compute h for nrhs columns.
+ *   gam : N x nrhs real (input);  mu, h : N x nrhs real (outputs).
+ *   h may be NULL to skip it. info: host array of nrhs entries or NULL. */
+GNK_API gnk_status gnk_fbie(gnk_ctx* ctx, const gnk_domain* dom, const double* gam, int nrhs,
+                    const gnk_opts* opts, double* mu, double* h, gnk_info* info);
+
+/* FBIEad (Sec. 4): solve (I + N* + J) mu = gamma for nrhs columns.
+ * Needs dom->etapp, dom->Ap and dom->c; eta' must be nonzero at every node. */
+GNK_API gnk_status gnk_fbie_ad(gnk_ctx* ctx, const gnk_domain* dom, const double* gam, int nrhs,
+                       const gnk_opts* opts, double* mu, gnk_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GNK_H */

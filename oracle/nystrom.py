@@ -180,3 +180,15 @@ def rel_linf(x, ref, scale=None):
     if scale is not None:
         den = max(den, scale)
     return float(np.max(np.abs(np.asarray(x) - ref)) / den)
+
+
+def kernel_rows(eta, etap, A, n, rows):
+    """Rows `rows` (a slice) of K_ij = (2/n)(A_i/A_j) eta'_j/(eta_j - eta_i), K_ii = 0:
+    the same definition as kernel_matrix, restricted to a block of targets."""
+    idx = np.arange(eta.shape[0])[rows]
+    diff = eta[None, :] - eta[idx][:, None]
+    self_ = idx[:, None] == np.arange(eta.shape[0])[None, :]
+    diff[self_] = 1.0
+    K = (2.0 / n) * (A[idx][:, None] / A[None, :]) * (etap[None, :] / diff)
+    K[self_] = 0.0
+    return K

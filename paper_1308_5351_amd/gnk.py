@@ -1,0 +1,236 @@
+"""Python binding of libgnk (ctypes). Argument marshalling only: every step of
+the solver runs in the HIP library; PyTorch provides device memory and the
+stream. The library must be built (``python -m paper_1308_5351_amd.build``);
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgnk.so")
+
+# status codes (include/gnk.h)
+OK, NOT_CONVERGED = 0, 1
+ERR_ARG, ERR_ODD_N, ERR_ZERO_A, ERR_ZERO_ETAP, ERR_NONFINITE, ERR_HIP, ERR_OOM = -1, -2, -3, -4, -5, -10, -11
+FP64, MIXED = 0, 1
+OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT = range(7)
+
+EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
+            "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad")
+
+
+class GnkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gnk status {status}: {msg}")
+        self.status = status
+
+
+class _Domain(C.Structure):
+    _fields_ = [("m1", C.c_int64), ("n", C.c_int64), ("eta", C.c_void_p), ("etap", C.c_void_p),
+                ("etapp", C.c_void_p), ("A", C.c_void_p), ("Ap", C.c_void_p), ("c", C.c_int)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double), ("prec", C.c_int),
+                ("inner_tol", C.c_double), ("max_refine", C.c_int), ("x0", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("flag", C.c_int), ("outer_it", C.c_int), ("inner_it", C.c_int), ("refine_steps", C.c_int),
+                ("relres", C.c_double), ("true_relres", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Prof(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("pair_cols", C.c_double), ("flops", C.c_double),
+                ("launches1", C.c_int64), ("ms1", C.c_double), ("pairs1", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgnk.so and declare the C signatures. Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_1308_5351_amd.build`")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.gnk_create.argtypes = [C.POINTER(P), C.c_int]
+    lib.gnk_destroy.argtypes = [P]
+    lib.gnk_set_stream.argtypes = [P, P]
+    lib.gnk_last_error.argtypes = [P]
+    lib.gnk_last_error.restype = C.c_char_p
+    lib.gnk_version.restype = C.c_char_p
+    lib.gnk_profile.argtypes = [P, C.c_int]
+    lib.gnk_profile_read.argtypes = [P, C.POINTER(Prof), C.c_int]
+    lib.gnk_cauchy_sum.argtypes = [P, C.c_int64, P, P, C.c_int, P]
+    lib.gnk_apply.argtypes = [P, C.POINTER(_Domain), C.c_int, P, C.c_int, P]
+    lib.gnk_fbie.argtypes = [P, C.POINTER(_Domain), P, C.c_int, C.POINTER(_Opts), P, P, C.POINTER(Info)]
+    lib.gnk_fbie_ad.argtypes = [P, C.POINTER(_Domain), P, C.c_int, C.POINTER(_Opts), P, C.POINTER(Info)]
+    for f in EXPORTED:
+        if f not in ("gnk_last_error", "gnk_version"):
+            getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+@dataclass
+class DeviceDomain:
+    """Boundary data resident on the GPU (complex128 tensors of length N)."""
+    m1: int
+    n: int
+    eta: torch.Tensor
+    etap: torch.Tensor
+    A: torch.Tensor
+    etapp: Optional[torch.Tensor] = None
+    Ap: Optional[torch.Tensor] = None
+    c: int = 1
+
+    @property
+    def N(self):
+        return self.m1 * self.n
+
+    @classmethod
+    def from_host(cls, dom, device="cuda"):
+        """From a workloads.Domain (NumPy arrays)."""
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(device)
+        return cls(dom.m1, dom.n, t(dom.eta), t(dom.etap), t(dom.A), t(dom.etapp), t(dom.Ap), dom.c)
+
+    def _struct(self):
+        p = lambda x: None if x is None else x.data_ptr()
+        return _Domain(self.m1, self.n, p(self.eta), p(self.etap), p(self.etapp), p(self.A), p(self.Ap), self.c)
+
+
+def _check_real(x: torch.Tensor, N: int, name: str):
+    if x.dtype != torch.float64 or not x.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if x.dim() == 1:
+        x = x.unsqueeze(1)
+    if x.shape[0] != N:
+        raise ValueError(f"{name} has {x.shape[0]} rows, expected N = {N}")
+    # column-major N x nrhs == row-major nrhs x N
+    return x.t().contiguous(), x.shape[1]
+
+
+def _from_cols(buf: torch.Tensor, like_1d: bool):
+    out = buf.t()
+    return out[:, 0] if like_1d else out
+
+
+class Context:
+    """A libgnk context bound to one device and to torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = C.c_void_p()
+        st = self.lib.gnk_create(C.byref(h), device)
+        if st != OK:
+            raise GnkError(st, "gnk_create failed")
+        self.h = h
+        self._stream = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gnk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            self.lib.gnk_set_stream(self.h, C.c_void_p(s))
+            self._stream = s
+
+    def _raise(self, st, allow_not_converged=True):
+        if st == OK or (allow_not_converged and st == NOT_CONVERGED):
+            return
+        raise GnkError(st, self.lib.gnk_last_error(self.h).decode())
+
+    # ------------------------------------------------------------------ calls
+    def profile(self, enable: bool):
+        """Start/stop HIP-event timing of the Cauchy-sum launches."""
+        self._raise(self.lib.gnk_profile(self.h, 1 if enable else 0), False)
+
+    def profile_read(self, reset: bool = True) -> dict:
+        p = Prof()
+        self._raise(self.lib.gnk_profile_read(self.h, C.byref(p), 1 if reset else 0), False)
+        return p.as_dict()
+
+    def cauchy_sum(self, eta: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
+        """S = E w, S_i = sum_{j != i} w_j / (eta_i - eta_j); w: (N,) or (N, nrhs) complex128."""
+        self._bind_stream()
+        N = eta.shape[0]
+        one = w.dim() == 1
+        wc = (w.unsqueeze(1) if one else w).t().contiguous()
+        S = torch.empty_like(wc)
+        st = self.lib.gnk_cauchy_sum(self.h, N, eta.data_ptr(), wc.data_ptr(), wc.shape[0], S.data_ptr())
+        self._raise(st, False)
+        return _from_cols(S, one)
+
+    def apply(self, dom: DeviceDomain, op: int, x: torch.Tensor) -> torch.Tensor:
+        self._bind_stream()
+        one = x.dim() == 1
+        xc, nrhs = _check_real(x, dom.N, "x")
+        y = torch.empty_like(xc)
+        d = dom._struct()
+        st = self.lib.gnk_apply(self.h, C.byref(d), op, xc.data_ptr(), nrhs, y.data_ptr())
+        self._raise(st, False)
+        return _from_cols(y, one)
+
+    @staticmethod
+    def _opts(restart, maxit, tol, prec, inner_tol, max_refine, x0):
+        return _Opts(restart, maxit, tol, prec, inner_tol, max_refine, None if x0 is None else x0.data_ptr())
+
+    def fbie(self, dom: DeviceDomain, gam: torch.Tensor, restart=25, maxit=40, tol=1e-12, prec=FP64,
+             inner_tol=0.0, max_refine=0, x0=None, want_h=True):
+        """Solve (I - N) mu = -M gamma and h = [M mu - (I - N) gamma]/2. Returns (mu, h, infos, status)."""
+        self._bind_stream()
+        one = gam.dim() == 1
+        g, nrhs = _check_real(gam, dom.N, "gam")
+        mu = torch.empty_like(g)
+        h = torch.empty_like(g) if want_h else None
+        x0c = None if x0 is None else _check_real(x0, dom.N, "x0")[0]
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c)
+        infos = (Info * nrhs)()
+        d = dom._struct()
+        st = self.lib.gnk_fbie(self.h, C.byref(d), g.data_ptr(), nrhs, C.byref(o), mu.data_ptr(),
+                               None if h is None else h.data_ptr(), infos)
+        self._raise(st)
+        return (_from_cols(mu, one), None if h is None else _from_cols(h, one),
+                [i.as_dict() for i in infos], st)
+
+    def fbie_ad(self, dom: DeviceDomain, gam: torch.Tensor, restart=25, maxit=40, tol=1e-12, prec=FP64,
+                inner_tol=0.0, max_refine=0, x0=None):
+        """Solve (I + N* + J) mu = gamma. Returns (mu, infos, status)."""
+        self._bind_stream()
+        one = gam.dim() == 1
+        g, nrhs = _check_real(gam, dom.N, "gam")
+        mu = torch.empty_like(g)
+        x0c = None if x0 is None else _check_real(x0, dom.N, "x0")[0]
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c)
+        infos = (Info * nrhs)()
+        d = dom._struct()
+        st = self.lib.gnk_fbie_ad(self.h, C.byref(d), g.data_ptr(), nrhs, C.byref(o), mu.data_ptr(), infos)
+        self._raise(st)
+        return _from_cols(mu, one), [i.as_dict() for i in infos], st

@@ -275,3 +275,10 @@ def test_config0_as_stated_is_nonsingular():
     assert np.max(np.abs(rs - 1.0)) < 1e-8
     s = np.linalg.svd(Aop, compute_uv=False)
     assert s[-1] > 1e-3
+
+
+def test_kernel_rows_equal_full_matrix():
+    d = wl.annulus(32)
+    K = orc.kernel_matrix(d.eta, d.etap, d.A, d.n)
+    for sl in (slice(0, 5), slice(30, 40), slice(60, 64)):
+        assert np.array_equal(orc.kernel_rows(d.eta, d.etap, d.A, d.n, sl), K[sl])
