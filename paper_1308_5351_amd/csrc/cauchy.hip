@@ -6,18 +6,26 @@
 // (eq. (e:BTx)); w = eta' gives the vector e (eq. (e:bve)).
 //
 // Mapping (VALU-bound, no matrix cores: every pair needs its own reciprocal):
-//   * one target node per lane, 64 consecutive targets per wavefront;
-//   * the source loop index is wave-uniform, so eta_j and w_j are fetched with
-//     scalar loads into SGPRs and broadcast to all lanes for free (no LDS
-//     traffic, no bank conflicts); the targets stay in VGPRs;
-//   * the source range is split over grid.y so that small problems still
-//     launch >> 256 workgroups; the partial sums of the splits are reduced in a
-//     fixed order by the consumer, so results are bitwise reproducible;
-//   * 1/|d|^2 comes from v_rcp_f64 refined by one Newton step; two sources share one reciprocal: 1/a = b/(ab), 1/b = a/(ab)
-//     (Montgomery's simultaneous inversion), which removes half of the
-//     quarter-rate v_rcp_f64 issues;
-//   * only the 64-source window that contains the wave's own targets needs
-//     the j != i test; it runs a separate masked loop.
+//   * sources are packed records {eta_j, w_j,0 .. w_j,ncols-1} (16 B each
+//     field); the source loop index is wave-uniform, so whole records arrive
+//     with wide scalar loads into SGPRs and are broadcast to all lanes (no LDS
+//     traffic, no bank conflicts); four sources are fetched per iteration so
+//     one wait covers four reciprocals;
+//   * each lane owns TPT target nodes (TPT*64 consecutive targets per wave),
+//     which reuses every fetched source TPT times and gives independent chains;
+//   * the source range is split over grid.y; the split count is chosen so the
+//     grid fills whole rounds of the chip's wave slots (no straggler round);
+//     the partial sums of the splits are reduced in a fixed order by the
+//     consumer, so results are bitwise reproducible;
+//   * 1/|d|^2 comes from v_rcp_f64 refined by one Newton step; two sources
+//     share one reciprocal: 1/a = b/(ab), 1/b = a/(ab) (simultaneous
+//     inversion), which halves the v_rcp_f64 issues;
+//   * only the window of sources equal to the wave's own targets needs the
+//     j != i test; it runs a separate masked loop.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
 #include "gnk_internal.h"
 
 namespace gnk {
@@ -26,135 +34,187 @@ namespace {
 
 // v_rcp_f64 is accurate to about 2^-24 on gfx950; one Newton step brings the
 // reciprocal to about 2^-48 (a few ulp), below the rounding of the sums.
-constexpr int kNewton = 1;
-
 __device__ __forceinline__ double refine_rcp(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-#pragma unroll
-  for (int k = 0; k < kNewton; ++k) {
-    const double e = __builtin_fma(-d, r, 1.0);
-    r = __builtin_fma(r, e, r);
-  }
-  return r;
+  const double r = __builtin_amdgcn_rcp(d);
+  const double e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
 }
 
-// acc += w * q for NR columns, q = conj(d)/|d|^2 = (qx, qy)
-template <int NR>
-__device__ __forceinline__ void accumulate(double (&ax)[NR], double (&ay)[NR], const double2* __restrict__ wj,
-                                           double qx, double qy) {
+template <int NR, int TPT>
+struct Acc {
+  double x[TPT][NR];
+  double y[TPT][NR];
+};
+
+// acc[t] += w * q for NR columns, q = conj(d)/|d|^2 = (qx, qy)
+template <int NR, int TPT>
+__device__ __forceinline__ void accumulate(Acc<NR, TPT>& a, int t, const double2* __restrict__ wj, double qx,
+                                           double qy) {
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const double2 w = wj[r];
-    ax[r] = __builtin_fma(w.x, qx, ax[r]);
-    ax[r] = __builtin_fma(-w.y, qy, ax[r]);
-    ay[r] = __builtin_fma(w.x, qy, ay[r]);
-    ay[r] = __builtin_fma(w.y, qx, ay[r]);
+    a.x[t][r] = __builtin_fma(w.x, qx, a.x[t][r]);
+    a.x[t][r] = __builtin_fma(-w.y, qy, a.x[t][r]);
+    a.y[t][r] = __builtin_fma(w.x, qy, a.y[t][r]);
+    a.y[t][r] = __builtin_fma(w.y, qx, a.y[t][r]);
   }
 }
 
-template <int NR>
-__global__ __launch_bounds__(256) void k_cauchy_fp64(const double2* __restrict__ eta, const double2* __restrict__ W,
-                                                     int N, int nrhs, int r0, int chunk,
-                                                     double2* __restrict__ part) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// two sources a, b (records ra, rb) against every target of the lane
+// ra, rb: source records (eta at [0]); the launch's weight columns start at [wo]
+template <int NR, int TPT>
+__device__ __forceinline__ void pair_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], const double2* __restrict__ ra,
+                                          const double2* __restrict__ rb, int wo) {
+  const double2 ea = ra[0], eb = rb[0];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const double dxa = tg[t].x - ea.x, dya = tg[t].y - ea.y;
+    const double dxb = tg[t].x - eb.x, dyb = tg[t].y - eb.y;
+    const double da = __builtin_fma(dya, dya, dxa * dxa);
+    const double db = __builtin_fma(dyb, dyb, dxb * dxb);
+    const double R = refine_rcp(da * db);
+    const double qa = db * R, qb = da * R;
+    accumulate<NR, TPT>(acc, t, ra + wo, dxa * qa, -dya * qa);
+    accumulate<NR, TPT>(acc, t, rb + wo, dxb * qb, -dyb * qb);
+  }
+}
+
+template <int NR, int TPT>
+__device__ __forceinline__ void single_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], const int (&ti)[TPT],
+                                            const double2* __restrict__ rj, int wo, int j, bool masked) {
+  const double2 e = rj[0];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const double dx = tg[t].x - e.x, dy = tg[t].y - e.y;
+    double r = refine_rcp(__builtin_fma(dy, dy, dx * dx));
+    if (masked) r = (j == ti[t]) ? 0.0 : r;
+    accumulate<NR, TPT>(acc, t, rj + wo, dx * r, -dy * r);
+  }
+}
+
+// rec: N records of `stride` double2 {eta, w_0, .., w_{ncols-1}}; this launch
+// handles columns r0 .. r0+NR-1. part[(g*ncols + r)*N + i].
+template <int NR, int TPT>
+__global__ __launch_bounds__(256) void k_cauchy_fp64(const double2* __restrict__ rec, int N, int stride, int ncols,
+                                                     int r0, int chunk, double2* __restrict__ part) {
+  constexpr int kWaveTargets = 64 * TPT;
+  const int lane = threadIdx.x & 63;
   // first target of this wavefront (uniform)
-  const int iw = __builtin_amdgcn_readfirstlane(blockIdx.x * blockDim.x + (threadIdx.x & ~63));
+  const int base = __builtin_amdgcn_readfirstlane((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) *
+                                                  kWaveTargets);
+  if (base >= N) return;   // whole wave past the last target (grid rounding)
   const int g = blockIdx.y;
   const int j0 = g * chunk;
   const int j1 = min(N, j0 + chunk);
-  const double2 t = eta[min(i, N - 1)];
-  const double2* __restrict__ Wr = W + r0;
+  const int wo = 1 + r0;   // w_q of source j at rec[j*stride + wo + q]
 
-  double ax[NR], ay[NR];
+  double2 tg[TPT];
+  int ti[TPT];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) { ax[r] = 0.0; ay[r] = 0.0; }
+  for (int t = 0; t < TPT; ++t) {
+    ti[t] = base + t * 64 + lane;
+    tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
+  }
+  Acc<NR, TPT> acc;
+#pragma unroll
+  for (int t = 0; t < TPT; ++t)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) { acc.x[t][r] = 0.0; acc.y[t][r] = 0.0; }
 
-  // sources before / after the wave's own 64-node window need no j != i test
+  // sources outside the wave's own window need no j != i test
   auto plain = [&](int ja, int jb) {
     int j = ja;
+    for (; j + 3 < jb; j += 4) {
+      const double2* r = rec + (size_t)j * stride;
+      pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
+      pair_step<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
+    }
     for (; j + 1 < jb; j += 2) {
-      const double2 ea = eta[j], eb = eta[j + 1];
-      const double dxa = t.x - ea.x, dya = t.y - ea.y;
-      const double dxb = t.x - eb.x, dyb = t.y - eb.y;
-      const double da = __builtin_fma(dya, dya, dxa * dxa);
-      const double db = __builtin_fma(dyb, dyb, dxb * dxb);
-      const double R = refine_rcp(da * db);
-      const double ra = db * R, rb = da * R;
-      accumulate<NR>(ax, ay, Wr + (size_t)j * nrhs, dxa * ra, -dya * ra);
-      accumulate<NR>(ax, ay, Wr + (size_t)(j + 1) * nrhs, dxb * rb, -dyb * rb);
+      const double2* r = rec + (size_t)j * stride;
+      pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
     }
-    if (j < jb) {
-      const double2 ea = eta[j];
-      const double dx = t.x - ea.x, dy = t.y - ea.y;
-      const double r = refine_rcp(__builtin_fma(dy, dy, dx * dx));
-      accumulate<NR>(ax, ay, Wr + (size_t)j * nrhs, dx * r, -dy * r);
-    }
+    if (j < jb) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, false);
   };
 
-  plain(j0, min(j1, iw));
+  plain(j0, min(j1, base));
   {
-    const int ja = max(j0, iw), jb = min(j1, iw + 64);
-    for (int j = ja; j < jb; ++j) {
-      const double2 e = eta[j];
-      const double dx = t.x - e.x, dy = t.y - e.y;
-      double r = refine_rcp(__builtin_fma(dy, dy, dx * dx));
-      r = (j == i) ? 0.0 : r;
-      accumulate<NR>(ax, ay, Wr + (size_t)j * nrhs, dx * r, -dy * r);
+    const int ja = max(j0, base), jb = min(j1, base + kWaveTargets);
+    for (int j = ja; j < jb; ++j) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
+  }
+  plain(max(j0, base + kWaveTargets), j1);
+
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    if (ti[t] < N) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        part[((size_t)g * ncols + r0 + r) * N + ti[t]] = make_double2(acc.x[t][r], acc.y[t][r]);
     }
   }
-  plain(max(j0, iw + 64), j1);
+}
 
-  if (i < N) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-      part[((size_t)g * nrhs + r0 + r) * N + i] = make_double2(ax[r], ay[r]);
+template <int NR, int TPT>
+void launch_one(const double2* rec, int64_t N, int ncols, int r0, const CauchyPlan& plan, double2* part,
+                hipStream_t st) {
+  const int64_t wave_targets = 64 * TPT;
+  const int64_t waves = (N + wave_targets - 1) / wave_targets;
+  const int wpb = plan.tpb / 64;
+  dim3 grid((unsigned)((waves + wpb - 1) / wpb), (unsigned)plan.splits);
+  k_cauchy_fp64<NR, TPT><<<grid, plan.tpb, 0, st>>>(rec, (int)N, ncols + 1, ncols, r0, (int)plan.chunk, part);
+}
+
+template <int TPT>
+void launch_cols(const double2* rec, int64_t N, int ncols, const CauchyPlan& plan, double2* part, hipStream_t st) {
+  int r0 = 0;
+  while (r0 < ncols) {
+    const int left = ncols - r0;
+    if (left >= 8) { launch_one<8, TPT>(rec, N, ncols, r0, plan, part, st); r0 += 8; }
+    else if (left >= 4) { launch_one<4, TPT>(rec, N, ncols, r0, plan, part, st); r0 += 4; }
+    else if (left >= 2) { launch_one<2, TPT>(rec, N, ncols, r0, plan, part, st); r0 += 2; }
+    else { launch_one<1, TPT>(rec, N, ncols, r0, plan, part, st); r0 += 1; }
   }
 }
 
 }  // namespace
 
-CauchyPlan plan_cauchy(int64_t N, int nrhs, int num_cu) {
+CauchyPlan plan_cauchy(int64_t N, int ncols, int num_cu) {
   CauchyPlan p;
   p.tpb = 256;
-  const int64_t blocks = (N + p.tpb - 1) / p.tpb;
-  // aim for about 8 resident workgroups per CU over the whole launch
-  const int64_t want = 8LL * num_cu;
-  int64_t s = (want + blocks - 1) / blocks;
-  // keep at least ~512 sources per split so the loop overhead stays small
-  const int64_t max_s = N / 512 > 1 ? N / 512 : 1;
-  if (s > max_s) s = max_s;
-  if (s < 1) s = 1;
-  if (s > 64) s = 64;
-  p.splits = (int)s;
-  int64_t chunk = (N + s - 1) / s;
-  chunk = (chunk + 1) & ~int64_t(1);
+  // targets per lane: two once there are enough target waves to fill the chip
+  const int64_t slots = (int64_t)num_cu * 4 * 8;   // 4 SIMDs x 8 resident waves per CU
+  p.tpt = (N >= 64 * 2 * slots / 8) ? 2 : 1;
+  if (const char* s = getenv("GNK_CAUCHY_TPT")) p.tpt = atoi(s) == 2 ? 2 : 1;
+  const int64_t twaves = (N + 64 * p.tpt - 1) / (64 * p.tpt);
+  // split count: smallest waste of the last round of wave slots, with at
+  // least 256 sources per split and at most 64 splits
+  int64_t best_s = 1;
+  double best_eff = -1.0;
+  const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, N / 256));
+  for (int64_t s = 1; s <= max_s; ++s) {
+    const double waves = (double)(twaves * s);
+    const double rounds = waves / (double)slots;
+    const double eff = rounds / std::ceil(rounds);   // busy fraction of the slot-rounds
+    // prefer at least one full round; ties go to fewer splits
+    const double score = eff * std::min(1.0, rounds);
+    if (score > best_eff + 1e-9) {
+      best_eff = score;
+      best_s = s;
+    }
+  }
+  if (const char* s = getenv("GNK_CAUCHY_SPLITS")) best_s = std::max(1, atoi(s));
+  int64_t chunk = (N + best_s - 1) / best_s;
+  chunk = (chunk + 3) & ~int64_t(3);
   p.chunk = chunk;
   p.splits = (int)((N + chunk - 1) / chunk);
-  (void)nrhs;
+  (void)ncols;
   return p;
 }
 
-hipError_t launch_cauchy_fp64(const double2* eta, const double2* W, int64_t N, int nrhs, const CauchyPlan& plan,
-                              double2* S_part, hipStream_t st) {
+hipError_t launch_cauchy_fp64(const double2* rec, int64_t N, int ncols, const CauchyPlan& plan, double2* S_part,
+                              hipStream_t st) {
   if (N <= 0) return hipSuccess;
-  dim3 grid((unsigned)((N + plan.tpb - 1) / plan.tpb), (unsigned)plan.splits);
-  int r0 = 0;
-  while (r0 < nrhs) {
-    const int left = nrhs - r0;
-    if (left >= 8) {
-      k_cauchy_fp64<8><<<grid, plan.tpb, 0, st>>>(eta, W, (int)N, nrhs, r0, (int)plan.chunk, S_part);
-      r0 += 8;
-    } else if (left >= 4) {
-      k_cauchy_fp64<4><<<grid, plan.tpb, 0, st>>>(eta, W, (int)N, nrhs, r0, (int)plan.chunk, S_part);
-      r0 += 4;
-    } else if (left >= 2) {
-      k_cauchy_fp64<2><<<grid, plan.tpb, 0, st>>>(eta, W, (int)N, nrhs, r0, (int)plan.chunk, S_part);
-      r0 += 2;
-    } else {
-      k_cauchy_fp64<1><<<grid, plan.tpb, 0, st>>>(eta, W, (int)N, nrhs, r0, (int)plan.chunk, S_part);
-      r0 += 1;
-    }
-  }
+  if (plan.tpt == 2) launch_cols<2>(rec, N, ncols, plan, S_part, st);
+  else launch_cols<1>(rec, N, ncols, plan, S_part, st);
   return hipGetLastError();
 }
 

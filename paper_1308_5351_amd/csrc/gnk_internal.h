@@ -13,16 +13,18 @@ namespace gnk {
 
 // Launch-shape parameters of the Cauchy pair kernel, picked per problem size.
 struct CauchyPlan {
-  int tpb = 256;      // threads per block; one target node per thread
+  int tpb = 256;      // threads per block (4 wavefronts)
+  int tpt = 1;        // target nodes per lane
   int splits = 1;     // number of source ranges (grid.y); partial sums reduced in order
-  int64_t chunk = 0;  // sources per split (even)
+  int64_t chunk = 0;  // sources per split (multiple of 4)
 };
 
-CauchyPlan plan_cauchy(int64_t N, int nrhs, int num_cu);
+CauchyPlan plan_cauchy(int64_t N, int ncols, int num_cu);
 
-// S_part[(g*nrhs + r)*N + i] = sum_{j in split g, j != i} W[j*nrhs + r] / (eta_i - eta_j)
-hipError_t launch_cauchy_fp64(const double2* eta, const double2* W, int64_t N, int nrhs,
-                              const CauchyPlan& plan, double2* S_part, hipStream_t st);
+// Source records: rec[j*(ncols+1)] = eta_j, rec[j*(ncols+1) + 1 + r] = w_j,r.
+// S_part[(g*ncols + r)*N + i] = sum_{j in split g, j != i} w_j,r / (eta_i - eta_j)
+hipError_t launch_cauchy_fp64(const double2* rec, int64_t N, int ncols, const CauchyPlan& plan,
+                              double2* S_part, hipStream_t st);
 
 // y_k += sign * L x_k for every component k and column r (circulant blocks of Sec. 3.3).
 hipError_t launch_circulant(const double* x, double* y, int64_t m1, int64_t n, int nrhs, double sign,

@@ -6,6 +6,7 @@
 namespace gnk {
 
 constexpr int kMaxRestart = 64;
+constexpr int kMaxChunk = 2048;   // elements per block of the Gram-Schmidt kernels
 
 struct GmresState {
   double* bnorm;        // ||b_r||

@@ -213,15 +213,14 @@ hipEvent_t pool_event(gnk_ctx* c) {
 }
 
 // One Cauchy-sum launch (all column groups), timed when profiling is on.
-void cauchy(gnk_ctx* c, const double2* eta, const double2* W, int64_t N, int ncols, const CauchyPlan& plan,
-            double2* parts) {
+void cauchy(gnk_ctx* c, const double2* rec, int64_t N, int ncols, const CauchyPlan& plan, double2* parts) {
   if (!c->prof) {
-    HIPCHK(c, launch_cauchy_fp64(eta, W, N, ncols, plan, parts, c->stream));
+    HIPCHK(c, launch_cauchy_fp64(rec, N, ncols, plan, parts, c->stream));
     return;
   }
   gnk_ctx::ProfRec r{pool_event(c), pool_event(c), N, ncols};
   HIPCHK(c, hipEventRecord(r.a, c->stream));
-  HIPCHK(c, launch_cauchy_fp64(eta, W, N, ncols, plan, parts, c->stream));
+  HIPCHK(c, launch_cauchy_fp64(rec, N, ncols, plan, parts, c->stream));
   HIPCHK(c, hipEventRecord(r.b, c->stream));
   c->prof_pending.push_back(r);
 }
@@ -235,6 +234,16 @@ void ensure_twiddles(gnk_ctx* c, Prep& P) {
   }
 }
 
+// S = E w for one complex column w (setup products)
+double2* cauchy_single(gnk_ctx* c, const Prep& P, const double2* w) {
+  double2* rec = ws<double2>(c, "rec", (size_t)P.N * 2);
+  k_pack_records<<<nblocks(P.N), kT, 0, c->stream>>>(P.eta, w, (int)P.N, 1, rec);
+  LAUNCHCHK(c);
+  double2* parts = cauchy_parts(c, P, 1);
+  cauchy(c, rec, P.N, 1, P.plan, parts);
+  return parts;
+}
+
 // rho = eta'/A and, from S = E(rho), diag(B1) and diag(D1)
 void setup_fbie(gnk_ctx* c, Prep& P) {
   P.rho = ws<double2>(c, "rho", P.N);
@@ -242,8 +251,7 @@ void setup_fbie(gnk_ctx* c, Prep& P) {
   P.dD = ws<double>(c, "dD", P.N);
   k_rho<<<nblocks(P.N), kT, 0, c->stream>>>(P.etap, P.A, P.rho, (int)P.N);
   LAUNCHCHK(c);
-  double2* parts = cauchy_parts(c, P, 1);
-  cauchy(c, P.eta, P.rho, P.N, 1, P.plan, parts);
+  double2* parts = cauchy_single(c, P, P.rho);
   k_diag_fbie<<<nblocks(P.N), kT, 0, c->stream>>>(parts, P.plan.splits, 1, P.A, (int)P.N, 2.0 / P.n, P.dB,
                                                    P.dD);
   LAUNCHCHK(c);
@@ -257,8 +265,7 @@ void setup_fbiead(gnk_ctx* c, Prep& P) {
     LAUNCHCHK(c);
   }
   P.e = ws<double>(c, "evec", P.N);
-  double2* parts = cauchy_parts(c, P, 1);
-  cauchy(c, P.eta, P.etap, P.N, 1, P.plan, parts);
+  double2* parts = cauchy_single(c, P, P.etap);
   k_evec<<<nblocks(P.N), kT, 0, c->stream>>>(parts, P.plan.splits, P.etap, P.etapp, P.A, P.Ap, (int)P.N,
                                               2.0 / P.n, (double)P.c, P.e);
   LAUNCHCHK(c);
@@ -304,15 +311,15 @@ void apply_op(gnk_ctx* c, Prep& P, int op, const double* x, int nrhs, double* y,
       set_err(c, "unknown operator %d", op);
       throw Fail{GNK_ERR_ARG};
   }
-  double2* W = ws<double2>(c, "W", (size_t)P.N * nrhs);
+  double2* rec = ws<double2>(c, "rec", (size_t)P.N * (nrhs + 1));
   double* mean = need_mean ? ws<double>(c, "mean", (size_t)P.m1 * nrhs) : nullptr;
   dim3 gw((unsigned)P.m1, (unsigned)nrhs);
-  k_weights<<<gw, kT, 0, c->stream>>>(Cw, x, a.scale, a.active, a.xout, W, (int)P.N, (int)P.n, (int)P.m1, nrhs, 0,
-                                      0, mean);
+  k_weights<<<gw, kT, 0, c->stream>>>(P.eta, Cw, x, a.scale, a.active, a.xout, rec, (int)P.N, (int)P.n, (int)P.m1,
+                                      nrhs + 1, 0, 0, mean);
   LAUNCHCHK(c);
   const double* xin = a.xout ? a.xout : x;
   double2* parts = cauchy_parts(c, P, nrhs);
-  cauchy(c, P.eta, W, P.N, nrhs, P.plan, parts);
+  cauchy(c, rec, P.N, nrhs, P.plan, parts);
   dim3 ge(nblocks(P.N), (unsigned)nrhs);
   k_epilogue<<<ge, kT, 0, c->stream>>>(parts, P.plan.splits, nrhs, 0, xin, Cout, dg, a0, dsign, cI, cR, mean,
                                        (int)P.n, (int)P.m1, a.active, y, (int)P.N);
@@ -333,8 +340,8 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
   const int64_t N = P.N;
   const int restart = o.restart;
   const int ldp = kMaxRestart + 1;
-  // vector-kernel blocking: about 2048 elements per block
-  const int per_blk = (int)std::max<int64_t>(kT, std::min<int64_t>(4096, (N + 255) / 256));
+  // vector-kernel blocking: 256..kMaxChunk elements per block, about 256 blocks
+  const int per_blk = (int)std::max<int64_t>(kT, std::min<int64_t>(kMaxChunk, (N + 255) / 256));
   const int nblk = (int)((N + per_blk - 1) / per_blk);
 
   double* V = ws<double>(c, "V", (size_t)(restart + 1) * nrhs * N);
@@ -424,7 +431,7 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
       k_gs_update<<<gv, kT, 0, c->stream>>>(V, l + 1, w, (int)N, nrhs, per_blk, st.active, P2, P1, ldp, st.H,
                                             st.ldh, st.hstride, l, 1, 0);
       LAUNCHCHK(c);
-      k_arnoldi_finish<<<1, tb, 0, c->stream>>>(P1, nblk, ldp, nrhs, l, restart, o.tol, st);
+      k_arnoldi_finish<<<(unsigned)nrhs, 64, 0, c->stream>>>(P1, nblk, ldp, l, restart, o.tol, st);
       LAUNCHCHK(c);
       HIPCHK(c, hipMemcpyAsync(c->pinned + l, st.live, sizeof(int), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipEventRecord(c->step_ev[l], c->stream));
@@ -613,14 +620,11 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
     }
     CauchyPlan plan = plan_cauchy(N, nrhs, c->num_cu);
     double2* parts = ws<double2>(c, "parts", (size_t)plan.splits * nrhs * N);
-    const double2* Wk = static_cast<const double2*>(w);
-    if (nrhs > 1) {
-      double2* Wt = ws<double2>(c, "Wt", (size_t)N * nrhs);
-      k_cols_to_rows<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(Wk, (int)N, nrhs, Wt);
-      LAUNCHCHK(c);
-      Wk = Wt;
-    }
-    cauchy(c, static_cast<const double2*>(eta), Wk, N, nrhs, plan, parts);
+    double2* rec = ws<double2>(c, "rec", (size_t)N * (nrhs + 1));
+    k_pack_records<<<nblocks(N), kT, 0, c->stream>>>(static_cast<const double2*>(eta),
+                                                      static_cast<const double2*>(w), (int)N, nrhs, rec);
+    LAUNCHCHK(c);
+    cauchy(c, rec, N, nrhs, plan, parts);
     // reduce the splits in order: S[r*N + i] = sum_g parts
     // (reuse the epilogue-free path: a dedicated small kernel)
     k_reduce_parts<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(parts, plan.splits, nrhs, (int)N,
@@ -671,13 +675,13 @@ gnk_status gnk_fbie(gnk_ctx* c, const gnk_domain* d, const double* gam, int nrhs
     k_rho<<<nblocks(N), kT, 0, c->stream>>>(P.etap, P.A, P.rho, (int)N);
     LAUNCHCHK(c);
     const int nc = nrhs + 1;
-    double2* W = ws<double2>(c, "W0", (size_t)N * nc);
+    double2* rec0 = ws<double2>(c, "rec0", (size_t)N * (nc + 1));
     k_weights<<<dim3((unsigned)P.m1, (unsigned)nrhs), kT, 0, c->stream>>>(
-        P.rho, gam, nullptr, nullptr, nullptr, W, (int)N, (int)P.n, (int)P.m1, nc, 1, 1, nullptr);
+        P.eta, P.rho, gam, nullptr, nullptr, nullptr, rec0, (int)N, (int)P.n, (int)P.m1, nc + 1, 1, 1, nullptr);
     LAUNCHCHK(c);
     CauchyPlan plan0 = plan_cauchy(N, nc, c->num_cu);
     double2* parts0 = ws<double2>(c, "parts0", (size_t)plan0.splits * nc * N);
-    cauchy(c, P.eta, W, N, nc, plan0, parts0);
+    cauchy(c, rec0, N, nc, plan0, parts0);
     k_diag_fbie<<<nblocks(N), kT, 0, c->stream>>>(parts0, plan0.splits, nc, P.A, (int)N, two_n, P.dB, P.dD);
     LAUNCHCHK(c);
     // b = -y = -(D - diag(D1) + Lhat) gamma

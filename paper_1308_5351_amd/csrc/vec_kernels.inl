@@ -27,6 +27,12 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __device__ __forceinline__ bool finite2(double2 v) { return isfinite(v.x) && isfinite(v.y); }
 
 }  // namespace
@@ -100,15 +106,18 @@ __global__ void k_evec(const double2* part, int splits, const double2* etap, con
 }
 
 // ----------------------------------------------- source weights and means
-// For column r (component k = blockIdx.x, column r = blockIdx.y):
+// Source records for the Cauchy kernel: rec[j*stride] = eta_j,
+// rec[j*stride + 1 + col0 + r] = C_j * v_j for column r (block (k, r) covers
+// component k of column r), with
 //   v = x * scale[r]                 (optional; written back to xout)
-//   W[j*ncols + col0 + r] = C_j * v_j  (complex times real)
 //   mean[r*m1 + k] = (1/n) sum_p v_{k n + p}   (optional)
-// If lead_one, column 0 of W is C itself (x == 1) and data columns start at 1.
-__global__ __launch_bounds__(kT) void k_weights(const double2* __restrict__ C, const double* __restrict__ x,
-                                                const double* __restrict__ scale, const int* __restrict__ active,
-                                                double* __restrict__ xout, double2* __restrict__ W, int N, int n, int m1,
-                                                int ncols, int col0, int lead_one, double* __restrict__ mean) {
+// If lead_one, record field 1 is C_j itself (x == 1) and data columns start
+// at col0 = 1.
+__global__ __launch_bounds__(kT) void k_weights(const double2* __restrict__ eta, const double2* __restrict__ C,
+                                                const double* __restrict__ x, const double* __restrict__ scale,
+                                                const int* __restrict__ active, double* __restrict__ xout,
+                                                double2* __restrict__ rec, int N, int n, int m1, int stride,
+                                                int col0, int lead_one, double* __restrict__ mean) {
   __shared__ double sh[kT / 64];
   const int k = blockIdx.x, r = blockIdx.y;
   if (active && !active[r]) return;
@@ -120,14 +129,28 @@ __global__ __launch_bounds__(kT) void k_weights(const double2* __restrict__ C, c
     const double v = xr[p] * s;
     if (xout) xout[(size_t)r * N + j] = v;
     const double2 c = C[j];
-    W[(size_t)j * ncols + col0 + r] = make_double2(c.x * v, c.y * v);
-    if (lead_one && r == 0) W[(size_t)j * ncols] = c;
+    double2* rj = rec + (size_t)j * stride;
+    rj[1 + col0 + r] = make_double2(c.x * v, c.y * v);
+    if (r == 0) {
+      rj[0] = eta[j];
+      if (lead_one) rj[1] = c;
+    }
     acc += v;
   }
   if (mean) {
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) mean[(size_t)r * m1 + k] = t / (double)n;
   }
+}
+
+// records from eta and column-major complex weights w (N x ncols)
+__global__ void k_pack_records(const double2* __restrict__ eta, const double2* __restrict__ w, int N, int ncols,
+                               double2* __restrict__ rec) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double2* rj = rec + (size_t)j * (ncols + 1);
+  rj[0] = eta[j];
+  for (int r = 0; r < ncols; ++r) rj[1 + r] = w[(size_t)r * N + j];
 }
 
 // Operator epilogue, for column r (grid.y) of x (N x nrhs), S from column (col0 + r):
@@ -159,13 +182,6 @@ __global__ void k_reduce_parts(const double2* __restrict__ part, int splits, int
   S[(size_t)r * N + i] = reduce_parts(part, splits, ncols, r, N, i);
 }
 
-// source-major weights for the Cauchy kernel: W[j*ncols + r] = w[r*N + j]
-__global__ void k_cols_to_rows(const double2* __restrict__ w, int N, int ncols, double2* __restrict__ W) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (j < N) W[(size_t)j * ncols + r] = w[(size_t)r * N + j];
-}
-
 // y = a x + b y  (elementwise over len)
 __global__ void k_axpby(double a, const double* x, double b, double* y, int64_t len) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -175,39 +191,49 @@ __global__ void k_axpby(double a, const double* x, double b, double* y, int64_t 
 // ------------------------------------------------------------------ GMRES
 // V holds the Krylov vectors: V_l column r at V + ((size_t)l*nrhs + r)*N.
 
-// partial[(r*nblk + blk)*ldp + l] = sum_{i in blk} V_l,r[i] w_r[i],  l < nvec
-__global__ __launch_bounds__(kT) void k_gs_dot(const double* __restrict__ V, int nvec, const double* __restrict__ w,
-                                               int N, int nrhs, int per_blk, const int* __restrict__ active,
-                                               double* __restrict__ partial, int ldp) {
-  __shared__ double sh[kT / 64];
-  const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
-  if (!active[r]) return;
-  const int i0 = blk * per_blk, i1 = min(N, i0 + per_blk);
-  const double* wr = w + (size_t)r * N;
-  for (int l = 0; l < nvec; ++l) {
+// Dots of the block's chunk of w_r with V_0..V_{nvec-1}: wavefront q takes
+// vectors l = q, q+4, ...; each lane sums its strided elements and the wave
+// reduces by shuffles. partial[(r*nblk + blk)*ldp + l].
+__device__ __forceinline__ void chunk_dots(const double* __restrict__ V, int nvec, const double* __restrict__ w,
+                                           int i0, int i1, int N, int nrhs, int r, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int l = wv; l < nvec; l += nw) {
     const double* vl = V + ((size_t)l * nrhs + r) * N;
     double acc = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) acc = __builtin_fma(vl[i], wr[i], acc);
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[((size_t)r * nblk + blk) * ldp + l] = s;
+    for (int i = i0 + lane; i < i1; i += 64) acc = __builtin_fma(vl[i], w[i - i0], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) out[l] = acc;
   }
 }
 
-// h_l = sum_blk partial_in; w -= sum_l h_l V_l; H[:, col] += h (block 0);
-// then partial_out = dots of the updated w with V_0..V_{nvec-1} (do_dots) or ||w||^2 (index 0).
-__global__ __launch_bounds__(kT) void k_gs_update(const double* __restrict__ V, int nvec, double* __restrict__ w,
-                                                  int N, int nrhs, int per_blk, const int* __restrict__ active,
-                                                  const double* __restrict__ pin,
-                                                  double* __restrict__ pout, int ldp, double* __restrict__ H, int ldh,
-                                                  int hstride, int col, int accumulate_h, int do_dots) {
-  __shared__ double sh[kT / 64];
-  __shared__ double h[kMaxRestart + 1];
+__global__ __launch_bounds__(kT) void k_gs_dot(const double* __restrict__ V, int nvec, const double* __restrict__ w,
+                                               int N, int nrhs, int per_blk, const int* __restrict__ active,
+                                               double* __restrict__ partial, int ldp) {
   const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
   if (!active[r]) return;
-  for (int l = threadIdx.x; l < nvec; l += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += pin[((size_t)r * nblk + b) * ldp + l];
-    h[l] = s;
+  const int i0 = blk * per_blk, i1 = min(N, i0 + per_blk);
+  chunk_dots(V, nvec, w + (size_t)r * N + i0, i0, i1, N, nrhs, r, partial + ((size_t)r * nblk + blk) * ldp);
+}
+
+// h_l = sum over blocks of pin (fixed order); w -= sum_l h_l V_l on this
+// block's chunk; H[:, col] (+)= h (block 0); then pout = the chunk's dots of the
+// updated w with V_0..V_{nvec-1} (do_dots) or its squared norm (entry 0).
+__global__ __launch_bounds__(kT) void k_gs_update(const double* __restrict__ V, int nvec, double* __restrict__ w,
+                                                  int N, int nrhs, int per_blk, const int* __restrict__ active,
+                                                  const double* __restrict__ pin, double* __restrict__ pout, int ldp,
+                                                  double* __restrict__ H, int ldh, int hstride, int col,
+                                                  int accumulate_h, int do_dots) {
+  __shared__ double h[kMaxRestart + 1];
+  __shared__ double sw[kMaxChunk];
+  __shared__ double sh[kT / 64];
+  const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  if (!active[r]) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int l = wv; l < nvec; l += nw) {
+    double acc = 0.0;
+    for (int b = lane; b < nblk; b += 64) acc += pin[((size_t)r * nblk + b) * ldp + l];
+    acc = wave_sum(acc);
+    if (lane == 0) h[l] = acc;
   }
   __syncthreads();
   if (blk == 0) {
@@ -216,26 +242,21 @@ __global__ __launch_bounds__(kT) void k_gs_update(const double* __restrict__ V, 
   }
   const int i0 = blk * per_blk, i1 = min(N, i0 + per_blk);
   double* wr = w + (size_t)r * N;
-  // each thread keeps its (few) elements; nvec passes over V
+  double nrm = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     double v = wr[i];
     for (int l = 0; l < nvec; ++l) v = __builtin_fma(-h[l], V[((size_t)l * nrhs + r) * N + i], v);
     wr[i] = v;
+    sw[i - i0] = v;
+    nrm = __builtin_fma(v, v, nrm);
   }
-  __syncthreads();
+  double* out = pout + ((size_t)r * nblk + blk) * ldp;
   if (do_dots) {
-    for (int l = 0; l < nvec; ++l) {
-      const double* vl = V + ((size_t)l * nrhs + r) * N;
-      double acc = 0.0;
-      for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) acc = __builtin_fma(vl[i], wr[i], acc);
-      const double s = block_sum(acc, sh);
-      if (threadIdx.x == 0) pout[((size_t)r * nblk + blk) * ldp + l] = s;
-    }
+    __syncthreads();
+    chunk_dots(V, nvec, sw, i0, i1, N, nrhs, r, out);
   } else {
-    double acc = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) acc = __builtin_fma(wr[i], wr[i], acc);
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) pout[((size_t)r * nblk + blk) * ldp] = s;
+    const double t = block_sum(nrm, sh);
+    if (threadIdx.x == 0) out[0] = t;
   }
 }
 
@@ -307,51 +328,64 @@ __global__ void k_cycle_start(const double* partial, int nblk, int ldp, int nrhs
   }
 }
 
-// End of Arnoldi step `col`, one thread per column: beta = ||w|| from the
-// partials, H(col+1, col) = beta, Givens rotations, residual estimate,
-// stop test for this cycle.
-__global__ void k_arnoldi_finish(const double* partial, int nblk, int ldp, int nrhs, int col, int restart,
-                                 double tol, GmresState st) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nrhs && st.active[r]) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[((size_t)r * nblk + b) * ldp];
-    const double beta = sqrt(s);
-    double* Hc = st.H + (size_t)r * st.hstride + (size_t)col * st.ldh;
-    double* cs = st.cs + (size_t)r * kMaxRestart;
-    double* sn = st.sn + (size_t)r * kMaxRestart;
-    double* g = st.g + (size_t)r * (kMaxRestart + 1);
-    for (int k = 0; k < col; ++k) {
-      const double t = cs[k] * Hc[k] + sn[k] * Hc[k + 1];
-      Hc[k + 1] = -sn[k] * Hc[k] + cs[k] * Hc[k + 1];
-      Hc[k] = t;
+// End of Arnoldi step `col`; one 64-lane block per column r: beta = ||w||
+// from the partials, H(col+1, col) = beta, Givens rotations applied in LDS,
+// residual estimate, stop test for this cycle.
+__global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, int nblk, int ldp, int col,
+                                                       int restart, double tol, GmresState st) {
+  __shared__ double hc[kMaxRestart + 2];
+  __shared__ double cs_[kMaxRestart + 1];
+  __shared__ double sn_[kMaxRestart + 1];
+  const int r = blockIdx.x, lane = threadIdx.x;
+  if (!st.active[r]) return;
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += partial[((size_t)r * nblk + b) * ldp];
+  s = wave_sum(s);
+  const double beta = sqrt(s);
+  double* Hc = st.H + (size_t)r * st.hstride + (size_t)col * st.ldh;
+  double* cs = st.cs + (size_t)r * kMaxRestart;
+  double* sn = st.sn + (size_t)r * kMaxRestart;
+  for (int k = lane; k <= col; k += 64) {
+    hc[k] = Hc[k];
+    if (k < col) {
+      cs_[k] = cs[k];
+      sn_[k] = sn[k];
     }
-    const double a = Hc[col];
+  }
+  __syncthreads();
+  if (lane == 0) {
+    hc[col + 1] = beta;
+    for (int k = 0; k < col; ++k) {
+      const double t = cs_[k] * hc[k] + sn_[k] * hc[k + 1];
+      hc[k + 1] = -sn_[k] * hc[k] + cs_[k] * hc[k + 1];
+      hc[k] = t;
+    }
+    const double a = hc[col];
     const double den = hypot(a, beta);
     double c = 1.0, sv = 0.0;
     if (den > 0.0) { c = a / den; sv = beta / den; }
     cs[col] = c;
     sn[col] = sv;
-    Hc[col] = den;
-    Hc[col + 1] = 0.0;
-    g[col + 1] = -sv * g[col];
-    g[col] = c * g[col];
-    const double est = fabs(g[col + 1]) / st.bnorm[r];
+    hc[col] = den;
+    hc[col + 1] = 0.0;
+    double* g = st.g + (size_t)r * (kMaxRestart + 1);
+    const double gc = g[col];
+    g[col + 1] = -sv * gc;
+    g[col] = c * gc;
+    const double est = fabs(sv * gc) / st.bnorm[r];
     st.relres[r] = est;
     st.kdim[r] = col + 1;
     st.inner_it[r] += 1;
     const bool stop = (est <= tol) || (beta == 0.0) || (col + 1 >= restart) || (den == 0.0);
-    if (stop) st.active[r] = 0;
-    else st.invbeta[r] = 1.0 / beta;
+    if (stop) {
+      st.active[r] = 0;
+      atomicSub(st.live, 1);
+    } else {
+      st.invbeta[r] = 1.0 / beta;
+    }
   }
   __syncthreads();
-  // number of columns still iterating (single-block launch; writes above are
-  // visible to the block after the barrier)
-  if (threadIdx.x == 0) {
-    int cnt = 0;
-    for (int q = 0; q < nrhs; ++q) cnt += st.active[q];
-    *st.live = cnt;
-  }
+  for (int k = lane; k <= col + 1; k += 64) Hc[k] = hc[k];
 }
 
 // Back substitution H y = g (upper triangular kdim x kdim), one thread per column.

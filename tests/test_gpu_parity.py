@@ -60,9 +60,30 @@ def test_cauchy_sum_matches_dense(ctx, N, nrhs):
     ref = E @ w
     scale = (np.abs(E) @ np.abs(w)).max()
     S = ctx.cauchy_sum(_cuda(eta), _cuda(w)).cpu().numpy()
+    if N == 1:                      # empty sum
+        assert np.all(S == 0)
+        return
     err = np.max(np.abs(S - ref)) / scale
     print(f"  err/scale = {err:.2e}")
     assert err < 1e-13
+
+
+@pytest.mark.parametrize("tpt,splits", [("1", "1"), ("2", "1"), ("2", "3"), ("1", "7"), ("2", "64")])
+def test_cauchy_sum_launch_shapes(ctx, monkeypatch, tpt, splits):
+    """Every launch shape (targets per lane, source splits) gives the same sums,
+    including ragged tails, the masked self window and whole waves past N."""
+    monkeypatch.setenv("GNK_CAUCHY_TPT", tpt)
+    monkeypatch.setenv("GNK_CAUCHY_SPLITS", splits)
+    for N, nrhs in ((131, 1), (1030, 5), (2049, 2)):
+        print(f"[shape] tpt={tpt} splits={splits} N={N} nrhs={nrhs}", flush=True)
+        rng = np.random.default_rng([8, N])
+        eta = rng.uniform(-1, 1, N) + 1j * rng.uniform(-1, 1, N)
+        w = rng.normal(size=(N, nrhs)) + 1j * rng.normal(size=(N, nrhs))
+        E = _dense_E(eta)
+        ref = E @ w
+        scale = (np.abs(E) @ np.abs(w)).max()
+        S = ctx.cauchy_sum(_cuda(eta), _cuda(w)).cpu().numpy()
+        assert np.max(np.abs(S - ref)) / scale < 1e-13
 
 
 def test_cauchy_sum_deterministic(ctx):
