@@ -11,12 +11,14 @@
 //     with wide scalar loads into SGPRs and are broadcast to all lanes (no LDS
 //     traffic, no bank conflicts); four sources are fetched per iteration so
 //     one wait covers four reciprocals;
-//   * each lane owns TPT target nodes (TPT*64 consecutive targets per wave),
+//   * each lane owns TPT target nodes (a tile of TPT*64 consecutive targets),
 //     which reuses every fetched source TPT times and gives independent chains;
-//   * the source range is split over grid.y; the split count is chosen so the
-//     grid fills whole rounds of the chip's wave slots (no straggler round);
-//     the partial sums of the splits are reduced in a fixed order by the
-//     consumer, so results are bitwise reproducible;
+//   * the four wavefronts of a workgroup share the tile and split its source
+//     chunk four ways, then add their sums through LDS in wave order;
+//   * the source range is further split over grid.y; the split count is chosen
+//     so the grid fills whole rounds of the chip's wave slots (no straggler
+//     round); the consumer adds the split partial sums in a fixed order, so
+//     results are bitwise reproducible;
 //   * 1/|d|^2 comes from v_rcp_f64 refined by one Newton step; two sources
 //     share one reciprocal: 1/a = b/(ab), 1/b = a/(ab) (simultaneous
 //     inversion), which halves the v_rcp_f64 issues;
@@ -93,19 +95,24 @@ __device__ __forceinline__ void single_step(Acc<NR, TPT>& acc, const double2 (&t
 }
 
 // rec: N records of `stride` double2 {eta, w_0, .., w_{ncols-1}}; this launch
-// handles columns r0 .. r0+NR-1. part[(g*ncols + r)*N + i].
+// handles columns r0 .. r0+NR-1. The four wavefronts of a workgroup share one
+// tile of 64*TPT targets and take consecutive quarters of the workgroup's
+// source chunk; their sums are added through LDS in wave order.
+// part[(g*ncols + r)*N + i], g = blockIdx.y.
 template <int NR, int TPT>
 __global__ __launch_bounds__(256) void k_cauchy_fp64(const double2* __restrict__ rec, int N, int stride, int ncols,
                                                      int r0, int chunk, double2* __restrict__ part) {
   constexpr int kWaveTargets = 64 * TPT;
+  __shared__ double red[3][TPT][2][64];
   const int lane = threadIdx.x & 63;
-  // first target of this wavefront (uniform)
-  const int base = __builtin_amdgcn_readfirstlane((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) *
-                                                  kWaveTargets);
-  if (base >= N) return;   // whole wave past the last target (grid rounding)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int base = blockIdx.x * kWaveTargets;     // first target of the tile (uniform)
   const int g = blockIdx.y;
-  const int j0 = g * chunk;
-  const int j1 = min(N, j0 + chunk);
+  const int jb0 = g * chunk;
+  const int jb1 = min(N, jb0 + chunk);
+  const int wchunk = ((chunk + 15) >> 4) << 2;    // quarter of the chunk, multiple of 4
+  const int j0 = min(jb1, jb0 + wv * wchunk);
+  const int j1 = min(jb1, j0 + wchunk);
   const int wo = 1 + r0;   // w_q of source j at rec[j*stride + wo + q]
 
   double2 tg[TPT];
@@ -121,7 +128,7 @@ __global__ __launch_bounds__(256) void k_cauchy_fp64(const double2* __restrict__
 #pragma unroll
     for (int r = 0; r < NR; ++r) { acc.x[t][r] = 0.0; acc.y[t][r] = 0.0; }
 
-  // sources outside the wave's own window need no j != i test
+  // sources outside the tile's own window need no j != i test
   auto plain = [&](int ja, int jb) {
     int j = ja;
     for (; j + 3 < jb; j += 4) {
@@ -143,23 +150,38 @@ __global__ __launch_bounds__(256) void k_cauchy_fp64(const double2* __restrict__
   }
   plain(max(j0, base + kWaveTargets), j1);
 
+  // fixed-order reduction over the four wavefronts, one column at a time
 #pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    if (ti[t] < N) {
+  for (int r = 0; r < NR; ++r) {
+    if (wv > 0) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        part[((size_t)g * ncols + r0 + r) * N + ti[t]] = make_double2(acc.x[t][r], acc.y[t][r]);
+      for (int t = 0; t < TPT; ++t) {
+        red[wv - 1][t][0][lane] = acc.x[t][r];
+        red[wv - 1][t][1][lane] = acc.y[t][r];
+      }
     }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int t = 0; t < TPT; ++t) {
+        double x = acc.x[t][r], y = acc.y[t][r];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          x += red[q][t][0][lane];
+          y += red[q][t][1][lane];
+        }
+        if (ti[t] < N) part[((size_t)g * ncols + r0 + r) * N + ti[t]] = make_double2(x, y);
+      }
+    }
+    __syncthreads();
   }
 }
 
 template <int NR, int TPT>
 void launch_one(const double2* rec, int64_t N, int ncols, int r0, const CauchyPlan& plan, double2* part,
                 hipStream_t st) {
-  const int64_t wave_targets = 64 * TPT;
-  const int64_t waves = (N + wave_targets - 1) / wave_targets;
-  const int wpb = plan.tpb / 64;
-  dim3 grid((unsigned)((waves + wpb - 1) / wpb), (unsigned)plan.splits);
+  const int64_t tile = 64 * TPT;
+  dim3 grid((unsigned)((N + tile - 1) / tile), (unsigned)plan.splits);
   k_cauchy_fp64<NR, TPT><<<grid, plan.tpb, 0, st>>>(rec, (int)N, ncols + 1, ncols, r0, (int)plan.chunk, part);
 }
 
@@ -180,30 +202,28 @@ void launch_cols(const double2* rec, int64_t N, int ncols, const CauchyPlan& pla
 CauchyPlan plan_cauchy(int64_t N, int ncols, int num_cu) {
   CauchyPlan p;
   p.tpb = 256;
-  // targets per lane: two once there are enough target waves to fill the chip
   const int64_t slots = (int64_t)num_cu * 4 * 8;   // 4 SIMDs x 8 resident waves per CU
-  p.tpt = (N >= 64 * 2 * slots / 8) ? 2 : 1;
+  // two targets per lane once 128-target tiles x 64 source splits fill the chip
+  p.tpt = ((N + 127) / 128) * 64 >= slots ? 2 : 1;
   if (const char* s = getenv("GNK_CAUCHY_TPT")) p.tpt = atoi(s) == 2 ? 2 : 1;
-  const int64_t twaves = (N + 64 * p.tpt - 1) / (64 * p.tpt);
-  // split count: smallest waste of the last round of wave slots, with at
-  // least 256 sources per split and at most 64 splits
+  const int64_t tiles = (N + 64 * p.tpt - 1) / (64 * p.tpt);
+  // workgroups = tiles x splits, 4 waves each; pick the split count whose
+  // waves fill whole rounds of the wave slots best (at least 32 sources per
+  // workgroup, at most 64 splits); ties go to fewer splits
   int64_t best_s = 1;
-  double best_eff = -1.0;
-  const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, N / 256));
+  double best = -1.0;
+  const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, N / 32));
   for (int64_t s = 1; s <= max_s; ++s) {
-    const double waves = (double)(twaves * s);
-    const double rounds = waves / (double)slots;
-    const double eff = rounds / std::ceil(rounds);   // busy fraction of the slot-rounds
-    // prefer at least one full round; ties go to fewer splits
-    const double score = eff * std::min(1.0, rounds);
-    if (score > best_eff + 1e-9) {
-      best_eff = score;
+    const double rounds = (double)(tiles * s * 4) / (double)slots;
+    const double score = rounds / std::ceil(rounds) * std::min(1.0, rounds);
+    if (score > best + 1e-9) {
+      best = score;
       best_s = s;
     }
   }
   if (const char* s = getenv("GNK_CAUCHY_SPLITS")) best_s = std::max(1, atoi(s));
   int64_t chunk = (N + best_s - 1) / best_s;
-  chunk = (chunk + 3) & ~int64_t(3);
+  chunk = (chunk + 15) & ~int64_t(15);
   p.chunk = chunk;
   p.splits = (int)((N + chunk - 1) / chunk);
   (void)ncols;

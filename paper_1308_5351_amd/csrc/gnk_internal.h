@@ -16,7 +16,7 @@ struct CauchyPlan {
   int tpb = 256;      // threads per block (4 wavefronts)
   int tpt = 1;        // target nodes per lane
   int splits = 1;     // number of source ranges (grid.y); partial sums reduced in order
-  int64_t chunk = 0;  // sources per split (multiple of 4)
+  int64_t chunk = 0;  // sources per split (multiple of 16: four wave quarters of 4)
 };
 
 CauchyPlan plan_cauchy(int64_t N, int ncols, int num_cu);
