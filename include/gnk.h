@@ -94,13 +94,20 @@ typedef struct {
 } gnk_domain;
 
 /* Solver options (the restart / gmrestol / maxit arguments of Sec. 3.5).
- *   restart    : inner iterations per cycle (1..64)
+ *   restart    : inner iterations per cycle (1..256); the Krylov basis takes
+ *                (restart+1) * N * nrhs doubles of workspace
  *   maxit      : maximum number of restart cycles (>= 1)
  *   tol        : relative residual ||b - A x||_2 / ||b||_2 per right-hand side
- *   prec       : GNK_FP64, or GNK_MIXED (FP32 well-separated pairs inside an
- *                FP64 iterative refinement; converges to the same tol)
- *   inner_tol  : relative tolerance of each inner solve in GNK_MIXED (0: 1e-6)
- *   max_refine : maximum refinement steps in GNK_MIXED (0: 20)
+ *   prec       : GNK_FP64, or GNK_MIXED: the Arnoldi products switch to FP32
+ *                for well-separated 64-node tiles (FP64 for all other pairs,
+ *                the epilogues, the orthogonalisation) once every column's
+ *                residual estimate is below inner_tol; the residual starting
+ *                each restart cycle is recomputed with FP64 products, so
+ *                restarts act as FP64 iterative refinement and the same tol
+ *                is reached
+ *   inner_tol  : GNK_MIXED switch level (0: min(1e-4, tol * 1e8), since the
+ *                mixed products have a relative error below 1e-8)
+ *   max_refine : reserved (0)
  *   x0         : optional device initial guess (N x nrhs) or NULL for zero */
 typedef struct {
   int restart;
@@ -117,7 +124,7 @@ typedef struct {
  *   outer_it    : restart cycles used;  inner_it: total Arnoldi steps
  *   relres      : GMRES residual estimate at exit
  *   true_relres : ||b - A x|| / ||b|| recomputed with an FP64 product
- *   refine_steps: refinement steps (GNK_MIXED), 0 otherwise */
+ *   refine_steps: restart cycles run with mixed-precision products (GNK_MIXED) */
 typedef struct {
   int flag;
   int outer_it;
@@ -142,7 +149,8 @@ GNK_API const char* gnk_version(void);
  *   pair_cols         : sum over launches of N(N-1) * columns
  *   flops             : N(N-1) * (16 + 8 (columns - 1)) summed (16 flops per
  *                       pair and column 1, 8 per further column sharing it)
- *   launches1, ms1, pairs1 : the single-column launches alone */
+ *   launches1, ms1, pairs1 : the single-column FP64 launches alone
+ *   *_mixed           : the mixed-precision launches (also in the totals) */
 typedef struct {
   int64_t launches;
   double ms;
@@ -151,6 +159,9 @@ typedef struct {
   int64_t launches1;
   double ms1;
   double pairs1;
+  int64_t launches_mixed;   /* mixed-precision launches (any column count) */
+  double ms_mixed;
+  double pair_cols_mixed;
 } gnk_prof;
 
 /* enable: 1 starts recording, 0 stops (already recorded launches are kept). */
@@ -169,9 +180,12 @@ GNK_API gnk_status gnk_cauchy_sum(gnk_ctx* ctx, int64_t N, const void* eta, cons
                           void* S);
 
 /* Operator application y = op(x) for one domain (see gnk_op). x and y are
- * real N x nrhs and must not alias. GB and GB_T need etapp, Ap and c. */
-GNK_API gnk_status gnk_apply(gnk_ctx* ctx, const gnk_domain* dom, int op, const double* x, int nrhs,
-                     double* y);
+ * real N x nrhs and must not alias. GB and GB_T need etapp, Ap and c.
+ * prec: GNK_FP64, or GNK_MIXED (Cauchy sums over well-separated 64-node tiles
+ * in FP32 on tile-local coordinates, all other pairs and every epilogue in
+ * FP64; the relative error of the product is about 1e-7). */
+GNK_API gnk_status gnk_apply(gnk_ctx* ctx, const gnk_domain* dom, int op, int prec, const double* x, int nrhs,
+                             double* y);
 
 /* FBIE (Sec. 3): solve (I - N) mu = -M gamma and compute h for nrhs columns.
  *   gam : N x nrhs real (input);  mu, h : N x nrhs real (outputs).

@@ -192,3 +192,19 @@ def kernel_rows(eta, etap, A, n, rows):
     K = (2.0 / n) * (A[idx][:, None] / A[None, :]) * (etap[None, :] / diff)
     K[self_] = 0.0
     return K
+
+
+def fbie_residual_rows(eta, etap, A, gam, mu, n, rows):
+    """Rows `rows` of r = (2I + diag(B1) - B) mu + (D - diag(D1) + Lhat) gamma,
+    the residual of eq. (e:sys) with y from (e:y), evaluated from the kernel
+    definitions (no full matrix is formed)."""
+    K = kernel_rows(eta, etap, A, n, rows)
+    idx = np.arange(eta.shape[0])[rows]
+    B, D = K.imag, K.real
+    amu = 2.0 * mu[idx] + np.sum(B * (mu[idx][:, None] - mu[None, :]), axis=1)
+    y = np.sum(D * (gam[None, :] - gam[idx][:, None]), axis=1)
+    L = circulant_L(n)
+    k, p = np.divmod(idx, n)
+    for q, (kk, pp) in enumerate(zip(k, p)):
+        y[q] += L[pp] @ gam[kk * n:(kk + 1) * n]
+    return amu + y, y

@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <vector>
 
 #include "gnk_internal.h"
 
@@ -177,6 +178,210 @@ __global__ __launch_bounds__(256) void k_cauchy_fp64(const double2* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Mixed precision: well-separated source tiles in FP32, the rest in FP64.
+// A source tile is 64 consecutive nodes with bounding circle (c_s, r_s); the
+// workgroup's target tile has (c_t, r_t). The tile pair is far when
+// |c_t - c_s| > (1 + theta)(r_t + r_s). For a far tile every lane forms
+// u = (eta_i - c_s) in FP64 and rounds it to FP32; the records hold
+// v_j = (eta_j - c_s) in FP32, so d = u - v keeps a relative error of a few
+// FP32 ulps however far the tiles are from the origin. The tile's 64 terms
+// are summed in FP32 and added to the FP64 accumulators.
+template <int NR, int TPT>
+struct Acc32 {
+  float x[TPT][NR];
+  float y[TPT][NR];
+};
+
+template <int NR, int TPT>
+__device__ __forceinline__ void accumulate32(Acc32<NR, TPT>& a, int t, const float2* __restrict__ wj, float qx,
+                                             float qy) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const float2 w = wj[r];
+    a.x[t][r] = __builtin_fmaf(w.x, qx, a.x[t][r]);
+    a.x[t][r] = __builtin_fmaf(-w.y, qy, a.x[t][r]);
+    a.y[t][r] = __builtin_fmaf(w.x, qy, a.y[t][r]);
+    a.y[t][r] = __builtin_fmaf(w.y, qx, a.y[t][r]);
+  }
+}
+
+template <int NR, int TPT>
+__device__ __forceinline__ void pair_step32(Acc32<NR, TPT>& acc, const float2 (&u)[TPT], const float2* __restrict__ ra,
+                                            const float2* __restrict__ rb, int wo) {
+  const float2 ea = ra[0], eb = rb[0];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const float dxa = u[t].x - ea.x, dya = u[t].y - ea.y;
+    const float dxb = u[t].x - eb.x, dyb = u[t].y - eb.y;
+    const float da = __builtin_fmaf(dya, dya, dxa * dxa);
+    const float db = __builtin_fmaf(dyb, dyb, dxb * dxb);
+    const float R = __builtin_amdgcn_rcpf(da * db);
+    const float qa = db * R, qb = da * R;
+    accumulate32<NR, TPT>(acc, t, ra + wo, dxa * qa, -dya * qa);
+    accumulate32<NR, TPT>(acc, t, rb + wo, dxb * qb, -dyb * qb);
+  }
+}
+
+// rec: FP64 records (stride double2); rec32: FP32 records {v_j, w_j,0..} (stride float2);
+// sb: per 64-node source tile {cx, cy, r, 0}; tb: per target tile {cx, cy, r, 0}.
+template <int NR, int TPT>
+__global__ __launch_bounds__(256) void k_cauchy_mixed(const double2* __restrict__ rec, const float2* __restrict__ rec32,
+                                                      const double4* __restrict__ sb, const double4* __restrict__ tb,
+                                                      int N, int stride, int ncols, int r0, int chunk, double far2,
+                                                      double2* __restrict__ part) {
+  constexpr int kWaveTargets = 64 * TPT;
+  __shared__ double red[3][TPT][2][64];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int base = blockIdx.x * kWaveTargets;
+  const int g = blockIdx.y;
+  const int jb0 = g * chunk;                      // chunk is a multiple of 256
+  const int jb1 = min(N, jb0 + chunk);
+  const int wchunk = chunk >> 2;                  // multiple of 64: whole source tiles
+  const int j0 = min(jb1, jb0 + wv * wchunk);
+  const int j1 = min(jb1, j0 + wchunk);
+  const int wo = 1 + r0;
+  const double4 tbd = tb[blockIdx.x];
+
+  double2 tg[TPT];
+  int ti[TPT];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    ti[t] = base + t * 64 + lane;
+    tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
+  }
+  Acc<NR, TPT> acc;
+#pragma unroll
+  for (int t = 0; t < TPT; ++t)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) { acc.x[t][r] = 0.0; acc.y[t][r] = 0.0; }
+
+  auto plain = [&](int ja, int jb) {
+    int j = ja;
+    for (; j + 1 < jb; j += 2) {
+      const double2* r = rec + (size_t)j * stride;
+      pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
+    }
+    if (j < jb) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, false);
+  };
+
+  for (int ts = j0; ts < j1; ts += 64) {
+    const int te = min(ts + 64, j1);
+    const double4 sbd = sb[ts >> 6];
+    const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
+    const double rr = tbd.z + sbd.z;
+    const bool far = (dcx * dcx + dcy * dcy) > far2 * rr * rr;
+    if (far) {
+      float2 u[TPT];
+#pragma unroll
+      for (int t = 0; t < TPT; ++t) u[t] = make_float2((float)(tg[t].x - sbd.x), (float)(tg[t].y - sbd.y));
+      Acc32<NR, TPT> a32;
+#pragma unroll
+      for (int t = 0; t < TPT; ++t)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) { a32.x[t][r] = 0.f; a32.y[t][r] = 0.f; }
+      int j = ts;
+#pragma unroll 2
+      for (; j + 1 < te; j += 2) {
+        const float2* r = rec32 + (size_t)j * stride;
+        pair_step32<NR, TPT>(a32, u, r, r + stride, wo);
+      }
+      if (j < te) {
+        const float2* r = rec32 + (size_t)j * stride;
+        const float2 e = r[0];
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) {
+          const float dx = u[t].x - e.x, dy = u[t].y - e.y;
+          const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
+          accumulate32<NR, TPT>(a32, t, r + wo, dx * q, -dy * q);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TPT; ++t)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          acc.x[t][r] += (double)a32.x[t][r];
+          acc.y[t][r] += (double)a32.y[t][r];
+        }
+    } else {
+      // near tile: FP64, with the j != i test where it meets the target tile
+      plain(ts, min(te, base));
+      const int ja = max(ts, base), jb = min(te, base + kWaveTargets);
+      for (int j = ja; j < jb; ++j) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
+      plain(max(ts, base + kWaveTargets), te);
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (wv > 0) {
+#pragma unroll
+      for (int t = 0; t < TPT; ++t) {
+        red[wv - 1][t][0][lane] = acc.x[t][r];
+        red[wv - 1][t][1][lane] = acc.y[t][r];
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int t = 0; t < TPT; ++t) {
+        double x = acc.x[t][r], y = acc.y[t][r];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          x += red[q][t][0][lane];
+          y += red[q][t][1][lane];
+        }
+        if (ti[t] < N) part[((size_t)g * ncols + r0 + r) * N + ti[t]] = make_double2(x, y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// bounding circle {cx, cy, r, 0} of each tile of `tile` consecutive nodes
+// (centre of the bounding box); one wavefront per tile
+__global__ __launch_bounds__(64) void k_tile_bounds(const double2* __restrict__ rec, int N, int stride, int tile,
+                                                    double4* __restrict__ out) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int i0 = b * tile, i1 = min(N, i0 + tile);
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+  for (int i = i0 + lane; i < i1; i += 64) {
+    const double2 e = rec[(size_t)i * stride];
+    xmin = fmin(xmin, e.x); xmax = fmax(xmax, e.x);
+    ymin = fmin(ymin, e.y); ymax = fmax(ymax, e.y);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    xmin = fmin(xmin, __shfl_xor(xmin, off, 64));
+    xmax = fmax(xmax, __shfl_xor(xmax, off, 64));
+    ymin = fmin(ymin, __shfl_xor(ymin, off, 64));
+    ymax = fmax(ymax, __shfl_xor(ymax, off, 64));
+  }
+  const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax);
+  double r = 0.0;
+  for (int i = i0 + lane; i < i1; i += 64) {
+    const double2 e = rec[(size_t)i * stride];
+    r = fmax(r, sqrt((e.x - cx) * (e.x - cx) + (e.y - cy) * (e.y - cy)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
+  // widen by a relative margin so rounding of the centre cannot hide a node
+  if (lane == 0) out[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
+}
+
+// FP32 records: v_j = eta_j - c_{tile(j)}, then the weights rounded to FP32
+__global__ void k_records32(const double2* __restrict__ rec, const double4* __restrict__ sb, int N, int stride,
+                            float2* __restrict__ rec32) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double2* r = rec + (size_t)j * stride;
+  float2* o = rec32 + (size_t)j * stride;
+  const double4 c = sb[j >> 6];
+  o[0] = make_float2((float)(r[0].x - c.x), (float)(r[0].y - c.y));
+  for (int q = 1; q < stride; ++q) o[q] = make_float2((float)r[q].x, (float)r[q].y);
+}
+
 template <int NR, int TPT>
 void launch_one(const double2* rec, int64_t N, int ncols, int r0, const CauchyPlan& plan, double2* part,
                 hipStream_t st) {
@@ -197,9 +402,50 @@ void launch_cols(const double2* rec, int64_t N, int ncols, const CauchyPlan& pla
   }
 }
 
+template <int NR, int TPT>
+void launch_mixed_one(const MixedArgs& m, int64_t N, int ncols, int r0, const CauchyPlan& plan, double2* part,
+                      hipStream_t st) {
+  const int64_t tile = 64 * TPT;
+  dim3 grid((unsigned)((N + tile - 1) / tile), (unsigned)plan.splits);
+  k_cauchy_mixed<NR, TPT><<<grid, plan.tpb, 0, st>>>(m.rec, m.rec32, m.src_bounds, m.tgt_bounds, (int)N, ncols + 1,
+                                                     ncols, r0, (int)plan.chunk, m.far2, part);
+}
+
+template <int TPT>
+void launch_mixed_cols(const MixedArgs& m, int64_t N, int ncols, const CauchyPlan& plan, double2* part,
+                       hipStream_t st) {
+  int r0 = 0;
+  while (r0 < ncols) {
+    const int left = ncols - r0;
+    if (left >= 4) { launch_mixed_one<4, TPT>(m, N, ncols, r0, plan, part, st); r0 += 4; }
+    else if (left >= 2) { launch_mixed_one<2, TPT>(m, N, ncols, r0, plan, part, st); r0 += 2; }
+    else { launch_mixed_one<1, TPT>(m, N, ncols, r0, plan, part, st); r0 += 1; }
+  }
+}
+
 }  // namespace
 
-CauchyPlan plan_cauchy(int64_t N, int ncols, int num_cu) {
+hipError_t launch_tile_bounds(const double2* rec, int64_t N, int ncols, int tile, double4* out, hipStream_t st) {
+  const int64_t tiles = (N + tile - 1) / tile;
+  k_tile_bounds<<<(unsigned)tiles, 64, 0, st>>>(rec, (int)N, ncols + 1, tile, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_records32(const double2* rec, const double4* src_bounds, int64_t N, int ncols, float2* rec32,
+                            hipStream_t st) {
+  k_records32<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(rec, src_bounds, (int)N, ncols + 1, rec32);
+  return hipGetLastError();
+}
+
+hipError_t launch_cauchy_mixed(const MixedArgs& m, int64_t N, int ncols, const CauchyPlan& plan, double2* S_part,
+                               hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  if (plan.tpt == 2) launch_mixed_cols<2>(m, N, ncols, plan, S_part, st);
+  else launch_mixed_cols<1>(m, N, ncols, plan, S_part, st);
+  return hipGetLastError();
+}
+
+CauchyPlan plan_cauchy(int64_t N, int ncols, int num_cu, int align) {
   CauchyPlan p;
   p.tpb = 256;
   const int64_t slots = (int64_t)num_cu * 4 * 8;   // 4 SIMDs x 8 resident waves per CU
@@ -207,23 +453,23 @@ CauchyPlan plan_cauchy(int64_t N, int ncols, int num_cu) {
   p.tpt = ((N + 127) / 128) * 64 >= slots ? 2 : 1;
   if (const char* s = getenv("GNK_CAUCHY_TPT")) p.tpt = atoi(s) == 2 ? 2 : 1;
   const int64_t tiles = (N + 64 * p.tpt - 1) / (64 * p.tpt);
-  // workgroups = tiles x splits, 4 waves each; pick the split count whose
-  // waves fill whole rounds of the wave slots best (at least 32 sources per
-  // workgroup, at most 64 splits); ties go to fewer splits
-  int64_t best_s = 1;
-  double best = -1.0;
+  // workgroups = tiles x splits, 4 waves each; score each split count by how
+  // well its waves fill whole rounds of the wave slots (at least 32 sources
+  // per workgroup, at most 64 splits)
   const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, N / 32));
+  std::vector<double> score((size_t)max_s + 1, 0.0);
+  double best = 0.0;
   for (int64_t s = 1; s <= max_s; ++s) {
     const double rounds = (double)(tiles * s * 4) / (double)slots;
-    const double score = rounds / std::ceil(rounds) * std::min(1.0, rounds);
-    if (score > best + 1e-9) {
-      best = score;
-      best_s = s;
-    }
+    score[s] = rounds / std::ceil(rounds) * std::min(1.0, rounds);
+    best = std::max(best, score[s]);
   }
+  // fewest splits within 1% of the best fill (fewer partial sums to reduce)
+  int64_t best_s = 1;
+  while (best_s < max_s && score[best_s] < best - 0.01) ++best_s;
   if (const char* s = getenv("GNK_CAUCHY_SPLITS")) best_s = std::max(1, atoi(s));
   int64_t chunk = (N + best_s - 1) / best_s;
-  chunk = (chunk + 15) & ~int64_t(15);
+  chunk = (chunk + align - 1) / align * align;
   p.chunk = chunk;
   p.splits = (int)((N + chunk - 1) / chunk);
   (void)ncols;

@@ -5,7 +5,7 @@
 
 namespace gnk {
 
-constexpr int kMaxRestart = 64;
+constexpr int kMaxRestart = 256;
 constexpr int kMaxChunk = 2048;   // elements per block of the Gram-Schmidt kernels
 
 struct GmresState {

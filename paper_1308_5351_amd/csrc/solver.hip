@@ -38,6 +38,8 @@ struct gnk_ctx {
   int64_t tw_n = -1;     // n of the cached circulant table
   // pipelined convergence read-back of the GMRES iterations
   int* pinned = nullptr;                 // host-pinned, one int per Arnoldi step
+  double* pinned_rel = nullptr;          // host-pinned residual estimates (mixed switch)
+  size_t pinned_rel_n = 0;
   std::vector<hipEvent_t> step_ev;       // one event per Arnoldi step
   // optional timing of the Cauchy-sum launches (HIP events on the context stream)
   bool prof = false;
@@ -45,6 +47,7 @@ struct gnk_ctx {
     hipEvent_t a, b;
     int64_t N;
     int ncols;
+    bool mixed;
   };
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -124,6 +127,11 @@ struct Prep {
   double* e = nullptr;      // vector e (adjoint equation)
   double2* tw = nullptr;    // circulant table
   CauchyPlan plan;
+  // mixed precision (FP32 far tiles)
+  CauchyPlan mplan;
+  double4* sb = nullptr;    // 64-node source tile bounds
+  double4* tb = nullptr;    // target tile bounds (64 * mplan.tpt nodes)
+  double far2 = 4.0;
 };
 
 void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint) {
@@ -218,9 +226,21 @@ void cauchy(gnk_ctx* c, const double2* rec, int64_t N, int ncols, const CauchyPl
     HIPCHK(c, launch_cauchy_fp64(rec, N, ncols, plan, parts, c->stream));
     return;
   }
-  gnk_ctx::ProfRec r{pool_event(c), pool_event(c), N, ncols};
+  gnk_ctx::ProfRec r{pool_event(c), pool_event(c), N, ncols, false};
   HIPCHK(c, hipEventRecord(r.a, c->stream));
   HIPCHK(c, launch_cauchy_fp64(rec, N, ncols, plan, parts, c->stream));
+  HIPCHK(c, hipEventRecord(r.b, c->stream));
+  c->prof_pending.push_back(r);
+}
+
+void cauchy_mixed(gnk_ctx* c, const MixedArgs& m, int64_t N, int ncols, const CauchyPlan& plan, double2* parts) {
+  if (!c->prof) {
+    HIPCHK(c, launch_cauchy_mixed(m, N, ncols, plan, parts, c->stream));
+    return;
+  }
+  gnk_ctx::ProfRec r{pool_event(c), pool_event(c), N, ncols, true};
+  HIPCHK(c, hipEventRecord(r.a, c->stream));
+  HIPCHK(c, launch_cauchy_mixed(m, N, ncols, plan, parts, c->stream));
   HIPCHK(c, hipEventRecord(r.b, c->stream));
   c->prof_pending.push_back(r);
 }
@@ -271,6 +291,19 @@ void setup_fbiead(gnk_ctx* c, Prep& P) {
   LAUNCHCHK(c);
 }
 
+// tile bounds for the mixed-precision pair kernel
+void setup_mixed(gnk_ctx* c, Prep& P) {
+  P.mplan = plan_cauchy(P.N, 1, c->num_cu, 256);
+  const int ttile = 64 * P.mplan.tpt;
+  P.sb = ws<double4>(c, "sbnd", (size_t)(P.N + 63) / 64);
+  P.tb = ws<double4>(c, "tbnd", (size_t)(P.N + ttile - 1) / ttile);
+  HIPCHK(c, launch_tile_bounds(P.eta, P.N, 0, 64, P.sb, c->stream));
+  HIPCHK(c, launch_tile_bounds(P.eta, P.N, 0, ttile, P.tb, c->stream));
+  double theta = 1.0;
+  if (const char* e = getenv("GNK_MIXED_THETA")) theta = atof(e);
+  P.far2 = (1.0 + theta) * (1.0 + theta);
+}
+
 // --------------------------------------------------------- operator product
 // y = op(x) for nrhs columns. scale/xout: optional per-column scaling of x
 // written back (GMRES normalisation); active: optional per-column GMRES mask.
@@ -278,6 +311,7 @@ struct ApplyArgs {
   const double* scale = nullptr;
   double* xout = nullptr;
   const int* active = nullptr;
+  bool mixed = false;      // FP32 far tiles (needs setup_mixed)
 };
 
 void apply_op(gnk_ctx* c, Prep& P, int op, const double* x, int nrhs, double* y, const ApplyArgs& a = {}) {
@@ -318,10 +352,22 @@ void apply_op(gnk_ctx* c, Prep& P, int op, const double* x, int nrhs, double* y,
                                       nrhs + 1, 0, 0, mean);
   LAUNCHCHK(c);
   const double* xin = a.xout ? a.xout : x;
-  double2* parts = cauchy_parts(c, P, nrhs);
-  cauchy(c, rec, P.N, nrhs, P.plan, parts);
+  double2* parts;
+  int splits;
+  if (a.mixed) {
+    float2* rec32 = ws<float2>(c, "rec32", (size_t)P.N * (nrhs + 1));
+    HIPCHK(c, launch_records32(rec, P.sb, P.N, nrhs, rec32, c->stream));
+    parts = ws<double2>(c, "parts", (size_t)P.mplan.splits * nrhs * P.N);
+    splits = P.mplan.splits;
+    MixedArgs m{rec, rec32, P.sb, P.tb, P.far2};
+    cauchy_mixed(c, m, P.N, nrhs, P.mplan, parts);
+  } else {
+    parts = cauchy_parts(c, P, nrhs);
+    splits = P.plan.splits;
+    cauchy(c, rec, P.N, nrhs, P.plan, parts);
+  }
   dim3 ge(nblocks(P.N), (unsigned)nrhs);
-  k_epilogue<<<ge, kT, 0, c->stream>>>(parts, P.plan.splits, nrhs, 0, xin, Cout, dg, a0, dsign, cI, cR, mean,
+  k_epilogue<<<ge, kT, 0, c->stream>>>(parts, splits, nrhs, 0, xin, Cout, dg, a0, dsign, cI, cR, mean,
                                        (int)P.n, (int)P.m1, a.active, y, (int)P.N);
   LAUNCHCHK(c);
   if (op == GNK_OP_FC || op == GNK_OP_FC_T) {
@@ -336,7 +382,16 @@ struct GmresOut {
   bool all_converged = false;
 };
 
-GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk_opts& o, double* x) {
+// Restarted GMRES. With `mixed`, the Arnoldi products switch to the
+// mixed-precision pair kernel once the residual estimate of every column is
+// below o.inner_tol (relaxed products: an error of relative size e in a
+// product made when the residual is r perturbs the final residual by about
+// e*r, so FP32 far tiles are harmless once r <= tol / e). The residual that
+// starts every cycle is always recomputed with the FP64 product, so each
+// restart is a step of FP64 iterative refinement.
+GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk_opts& o, double* x,
+               bool mixed = false) {
+  const ApplyArgs am;   // FP64 products for every true residual
   const int64_t N = P.N;
   const int restart = o.restart;
   const int ldp = kMaxRestart + 1;
@@ -384,7 +439,7 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
   const size_t colbytes = sizeof(double) * N * nrhs;
   if (o.x0) {
     if (o.x0 != x) HIPCHK(c, hipMemcpyAsync(x, o.x0, colbytes, hipMemcpyDeviceToDevice, c->stream));
-    apply_op(c, P, op, x, nrhs, V);
+    apply_op(c, P, op, x, nrhs, V, am);
     k_residual<<<gv, kT, 0, c->stream>>>(b, V, (int)N, per_blk, P1, ldp);
   } else {
     HIPCHK(c, hipMemsetAsync(x, 0, colbytes, c->stream));
@@ -397,7 +452,15 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
 
   std::vector<int> outer(nrhs, 0);
   std::vector<int> conv(nrhs, 0);
+  std::vector<int> mixed_cycles(nrhs, 0);
+  bool mixed_now = false;
   if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(int) * (kMaxRestart + 1), 0));
+  if (c->pinned_rel_n < (size_t)nrhs * kMaxRestart) {
+    if (c->pinned_rel) HIPCHK(c, hipHostFree(c->pinned_rel));
+    c->pinned_rel = nullptr;
+    HIPCHK(c, hipHostMalloc((void**)&c->pinned_rel, sizeof(double) * nrhs * kMaxRestart, 0));
+    c->pinned_rel_n = (size_t)nrhs * kMaxRestart;
+  }
   while ((int)c->step_ev.size() < kMaxRestart) {
     hipEvent_t e;
     HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -410,7 +473,10 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (live == 0) break;
     for (int r = 0; r < nrhs; ++r)
-      if (!conv[r]) outer[r] += 1;
+      if (!conv[r]) {
+        outer[r] += 1;
+        if (mixed_now) mixed_cycles[r] += 1;
+      }
     // Arnoldi steps. The host looks one step behind the device: before
     // enqueuing step l+1 it waits for step l-1 and reads how many columns are
     // still iterating, so the queue never drains and at most one speculative
@@ -422,6 +488,7 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
       aa.scale = st.invbeta;
       aa.xout = vl;
       aa.active = st.active;
+      aa.mixed = mixed && mixed_now;
       apply_op(c, P, op, vl, nrhs, w, aa);
       k_gs_dot<<<gv, kT, 0, c->stream>>>(V, l + 1, w, (int)N, nrhs, per_blk, st.active, P1, ldp);
       LAUNCHCHK(c);
@@ -434,18 +501,26 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
       k_arnoldi_finish<<<(unsigned)nrhs, 64, 0, c->stream>>>(P1, nblk, ldp, l, restart, o.tol, st);
       LAUNCHCHK(c);
       HIPCHK(c, hipMemcpyAsync(c->pinned + l, st.live, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      if (mixed && !mixed_now)
+        HIPCHK(c, hipMemcpyAsync(c->pinned_rel + (size_t)l * nrhs, st.relres, sizeof(double) * nrhs,
+                                 hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipEventRecord(c->step_ev[l], c->stream));
       if (l >= 1) {
         HIPCHK(c, hipEventSynchronize(c->step_ev[l - 1]));
         if (c->pinned[l - 1] == 0) break;
+        if (mixed && !mixed_now) {
+          double mx = 0.0;
+          for (int r = 0; r < nrhs; ++r) mx = std::max(mx, c->pinned_rel[(size_t)(l - 1) * nrhs + r]);
+          if (mx <= o.inner_tol) mixed_now = true;
+        }
       }
     }
-    k_backsolve<<<1, tb, 0, c->stream>>>(nrhs, st);
+    k_backsolve<<<(unsigned)nrhs, 64, 0, c->stream>>>(st);
     LAUNCHCHK(c);
     k_xupdate<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(V, x, (int)N, nrhs, st);
     LAUNCHCHK(c);
     // true residual of the new iterate (FP64 product) and the next cycle's start
-    apply_op(c, P, op, x, nrhs, V);
+    apply_op(c, P, op, x, nrhs, V, am);
     k_residual<<<gv, kT, 0, c->stream>>>(b, V, (int)N, per_blk, P1, ldp);
     LAUNCHCHK(c);
     k_cycle_start<<<1, tb, 0, c->stream>>>(P1, nblk, ldp, nrhs, o.tol, st);
@@ -474,7 +549,7 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
     I.flag = conv[r] ? 0 : 1;
     I.outer_it = outer[r];
     I.inner_it = inner[r];
-    I.refine_steps = 0;
+    I.refine_steps = mixed_cycles[r];
     I.relres = rel[r];
     I.true_relres = trel[r];
     if (!conv[r]) out.all_converged = false;
@@ -488,14 +563,13 @@ gnk_opts resolve_opts(gnk_ctx* c, const gnk_opts* o) {
   r.maxit = 40;
   r.tol = 1e-12;
   r.prec = GNK_FP64;
-  r.inner_tol = 1e-6;
-  r.max_refine = 20;
+  r.inner_tol = 0.0;
+  r.max_refine = 0;
   r.x0 = nullptr;
-  if (o) {
-    r = *o;
-    if (r.inner_tol <= 0) r.inner_tol = 1e-6;
-    if (r.max_refine <= 0) r.max_refine = 20;
-  }
+  if (o) r = *o;
+  // mixed products once the residual estimate is below tol / 1e-8 (their
+  // relative error is below 1e-8), but not before 1e-4
+  if (r.inner_tol <= 0) r.inner_tol = std::min(1e-4, r.tol * 1e8);
   if (r.restart < 1 || r.restart > kMaxRestart || r.maxit < 1 || !(r.tol > 0.0) || r.tol >= 1.0 ||
       (r.prec != GNK_FP64 && r.prec != GNK_MIXED)) {
     set_err(c, "bad options: restart %d (1..%d), maxit %d (>=1), tol %g (0..1), prec %d", r.restart, kMaxRestart,
@@ -567,6 +641,7 @@ gnk_status gnk_destroy(gnk_ctx* c) {
   }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->pinned_rel) (void)hipHostFree(c->pinned_rel);
   delete c;
   return GNK_OK;
 }
@@ -597,7 +672,11 @@ gnk_status gnk_profile_read(gnk_ctx* c, gnk_prof* out, int reset) {
       A.ms += ms;
       A.pair_cols += pairs * r.ncols;
       A.flops += pairs * (16.0 + 8.0 * (r.ncols - 1));
-      if (r.ncols == 1) {
+      if (r.mixed) {
+        A.launches_mixed += 1;
+        A.ms_mixed += ms;
+        A.pair_cols_mixed += pairs * r.ncols;
+      } else if (r.ncols == 1) {
         A.launches1 += 1;
         A.ms1 += ms;
         A.pairs1 += pairs;
@@ -635,11 +714,11 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
   });
 }
 
-gnk_status gnk_apply(gnk_ctx* c, const gnk_domain* d, int op, const double* x, int nrhs, double* y) {
+gnk_status gnk_apply(gnk_ctx* c, const gnk_domain* d, int op, int prec, const double* x, int nrhs, double* y) {
   return guarded(c, [&]() -> gnk_status {
     const bool adj = (op == GNK_OP_GB || op == GNK_OP_GB_T);
     check_domain(c, d, adj);
-    if (!x || !y || x == y || nrhs < 1 || op < 0 || op > GNK_OP_LHAT) {
+    if (!x || !y || x == y || nrhs < 1 || op < 0 || op > GNK_OP_LHAT || (prec != GNK_FP64 && prec != GNK_MIXED)) {
       set_err(c, "bad arguments to gnk_apply");
       throw Fail{GNK_ERR_ARG};
     }
@@ -649,7 +728,12 @@ gnk_status gnk_apply(gnk_ctx* c, const gnk_domain* d, int op, const double* x, i
       setup_fbie(c, P);
       if (adj) setup_fbiead(c, P);
     }
-    apply_op(c, P, op, x, nrhs, y);
+    ApplyArgs a;
+    if (prec == GNK_MIXED && op != GNK_OP_LHAT) {
+      setup_mixed(c, P);
+      a.mixed = true;
+    }
+    apply_op(c, P, op, x, nrhs, y, a);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GNK_OK;
   });
@@ -693,7 +777,8 @@ gnk_status gnk_fbie(gnk_ctx* c, const gnk_domain* d, const double* gam, int nrhs
     ensure_twiddles(c, P);
     HIPCHK(c, launch_circulant(gam, b, P.m1, P.n, nrhs, -1.0, P.tw, c->stream));
     // (2I + diag(B1) - B) mu = b
-    GmresOut g = gmres(c, P, GNK_OP_FB, b, nrhs, o, mu);
+    if (o.prec == GNK_MIXED) setup_mixed(c, P);
+    GmresOut g = gmres(c, P, GNK_OP_FB, b, nrhs, o, mu, o.prec == GNK_MIXED);
     if (h) {
       // h = [(D - diag(D1) + Lhat) mu - (2I + diag(B1) - B) gamma] / 2, f_B(gamma) from the first launch
       double* fbg = ws<double>(c, "fbg", (size_t)N * nrhs);
@@ -723,7 +808,8 @@ gnk_status gnk_fbie_ad(gnk_ctx* c, const gnk_domain* d, const double* gam, int n
     Prep P = make_prep(c, d, true);
     validate_inputs(c, P, true, gam, nrhs);
     setup_fbiead(c, P);
-    GmresOut g = gmres(c, P, GNK_OP_GB, gam, nrhs, o, mu);
+    if (o.prec == GNK_MIXED) setup_mixed(c, P);
+    GmresOut g = gmres(c, P, GNK_OP_GB, gam, nrhs, o, mu, o.prec == GNK_MIXED);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (info)
       for (int r = 0; r < nrhs; ++r) info[r] = g.info[r];

@@ -182,6 +182,17 @@ __global__ void k_reduce_parts(const double2* __restrict__ part, int splits, int
   S[(size_t)r * N + i] = reduce_parts(part, splits, ncols, r, N, i);
 }
 
+// out[r] = ||x_r||_2, one block per column, fixed-order reduction
+__global__ __launch_bounds__(kT) void k_col_norms(const double* __restrict__ x, int N, double* __restrict__ out) {
+  __shared__ double sh[kT / 64];
+  const int r = blockIdx.x;
+  const double* xr = x + (size_t)r * N;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) acc = __builtin_fma(xr[i], xr[i], acc);
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[r] = sqrt(t);
+}
+
 // y = a x + b y  (elementwise over len)
 __global__ void k_axpby(double a, const double* x, double b, double* y, int64_t len) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -312,6 +323,7 @@ __global__ void k_cycle_start(const double* partial, int nblk, int ldp, int nrhs
   const double bn = st.bnorm[r];
   const double rel = bn > 0.0 ? beta / bn : 0.0;
   st.true_relres[r] = rel;
+  st.relres[r] = rel;
   st.kdim[r] = 0;
   double* g = st.g + (size_t)r * (kMaxRestart + 1);
   if (bn == 0.0 || rel <= tol || beta == 0.0) {
@@ -388,21 +400,26 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, in
   for (int k = lane; k <= col + 1; k += 64) Hc[k] = hc[k];
 }
 
-// Back substitution H y = g (upper triangular kdim x kdim), one thread per column.
-__global__ void k_backsolve(int nrhs, GmresState st) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
+// Back substitution H y = g (upper triangular kdim x kdim after the Givens
+// rotations); one 64-lane block per column, each row sum split over lanes.
+__global__ __launch_bounds__(64) void k_backsolve(GmresState st) {
+  __shared__ double ys[kMaxRestart];
+  const int r = blockIdx.x, lane = threadIdx.x;
   const int k = st.converged[r] ? 0 : st.kdim[r];
   const double* Hr = st.H + (size_t)r * st.hstride;
   const double* g = st.g + (size_t)r * (kMaxRestart + 1);
-  double* y = st.y + (size_t)r * kMaxRestart;
   for (int l = k - 1; l >= 0; --l) {
-    double s = g[l];
-    for (int q = l + 1; q < k; ++q) s -= Hr[(size_t)q * st.ldh + l] * y[q];
-    const double d = Hr[(size_t)l * st.ldh + l];
-    y[l] = d != 0.0 ? s / d : 0.0;
+    double s = 0.0;
+    for (int q = l + 1 + lane; q < k; q += 64) s = __builtin_fma(Hr[(size_t)q * st.ldh + l], ys[q], s);
+    s = wave_sum(s);
+    if (lane == 0) {
+      const double d = Hr[(size_t)l * st.ldh + l];
+      ys[l] = d != 0.0 ? (g[l] - s) / d : 0.0;
+    }
+    __syncthreads();
   }
-  for (int l = k; l < kMaxRestart; ++l) y[l] = 0.0;
+  double* y = st.y + (size_t)r * kMaxRestart;
+  for (int l = lane; l < kMaxRestart; l += 64) y[l] = l < k ? ys[l] : 0.0;
 }
 
 // x_r += sum_{l < kdim_r} y_l V_l,r

@@ -52,7 +52,8 @@ class Info(C.Structure):
 
 class Prof(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("pair_cols", C.c_double), ("flops", C.c_double),
-                ("launches1", C.c_int64), ("ms1", C.c_double), ("pairs1", C.c_double)]
+                ("launches1", C.c_int64), ("ms1", C.c_double), ("pairs1", C.c_double),
+                ("launches_mixed", C.c_int64), ("ms_mixed", C.c_double), ("pair_cols_mixed", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,7 +80,7 @@ def load_library(path: str = LIB_PATH):
     lib.gnk_profile.argtypes = [P, C.c_int]
     lib.gnk_profile_read.argtypes = [P, C.POINTER(Prof), C.c_int]
     lib.gnk_cauchy_sum.argtypes = [P, C.c_int64, P, P, C.c_int, P]
-    lib.gnk_apply.argtypes = [P, C.POINTER(_Domain), C.c_int, P, C.c_int, P]
+    lib.gnk_apply.argtypes = [P, C.POINTER(_Domain), C.c_int, C.c_int, P, C.c_int, P]
     lib.gnk_fbie.argtypes = [P, C.POINTER(_Domain), P, C.c_int, C.POINTER(_Opts), P, P, C.POINTER(Info)]
     lib.gnk_fbie_ad.argtypes = [P, C.POINTER(_Domain), P, C.c_int, C.POINTER(_Opts), P, C.POINTER(Info)]
     for f in EXPORTED:
@@ -188,13 +189,13 @@ class Context:
         self._raise(st, False)
         return _from_cols(S, one)
 
-    def apply(self, dom: DeviceDomain, op: int, x: torch.Tensor) -> torch.Tensor:
+    def apply(self, dom: DeviceDomain, op: int, x: torch.Tensor, prec: int = FP64) -> torch.Tensor:
         self._bind_stream()
         one = x.dim() == 1
         xc, nrhs = _check_real(x, dom.N, "x")
         y = torch.empty_like(xc)
         d = dom._struct()
-        st = self.lib.gnk_apply(self.h, C.byref(d), op, xc.data_ptr(), nrhs, y.data_ptr())
+        st = self.lib.gnk_apply(self.h, C.byref(d), op, prec, xc.data_ptr(), nrhs, y.data_ptr())
         self._raise(st, False)
         return _from_cols(y, one)
 

@@ -1,0 +1,104 @@
+"""Mixed precision (FP32 far tiles, FP64 near tiles, FP64 refinement) through the C ABI.
+
+Bar: the refined solution matches the FP64 oracle to the same 1e-10 relative
+L-infinity as the FP64 path."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import nystrom as orc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gk():
+    from paper_1308_5351_amd import gnk
+    assert torch.cuda.is_available()
+    return gnk
+
+
+@pytest.fixture(scope="module")
+def ctx(gk):
+    c = gk.Context(0)
+    yield c
+    c.close()
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def small_close():
+    return wl.config2(n=256, m1=9)
+
+
+def test_mixed_products_close_to_fp64(gk, ctx, small_close):
+    """Mixed products differ from FP64 by about FP32 rounding (and the FP32
+    branch is really taken)."""
+    dom, _ = small_close
+    dd = gk.DeviceDomain.from_host(dom)
+    rng = np.random.default_rng(4)
+    x = _cuda(rng.normal(size=(dom.N, 2)))
+    for op in (gk.OP_FB, gk.OP_FC, gk.OP_FB_T, gk.OP_FC_T):
+        y64 = ctx.apply(dd, op, x).cpu().numpy()
+        y32 = ctx.apply(dd, op, x, prec=gk.MIXED).cpu().numpy()
+        err = np.max(np.abs(y32 - y64)) / np.max(np.abs(y64))
+        print(f"[mixed] op {op} rel err {err:.2e}", flush=True)
+        assert 1e-12 < err < 1e-5
+
+
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_fbie_mixed_matches_oracle_reduced(gk, ctx, small_close, nrhs):
+    """9 close boundaries (3 graded polygons), n = 256: mixed + refinement vs the dense oracle."""
+    dom, gam = small_close
+    if nrhs == 2:
+        gam = np.concatenate([gam, (dom.eta ** 3).real[:, None] * 0.1], axis=1)
+    dd = gk.DeviceDomain.from_host(dom)
+    mu, h, infos, st = ctx.fbie(dd, _cuda(gam), prec=gk.MIXED, tol=1e-13, restart=64)
+    mu_o, h_o = orc.fbie(dom.eta, dom.etap, dom.A, gam, dom.n)
+    s = np.max(np.abs(gam))
+    e_mu = orc.rel_linf(mu.cpu().numpy(), mu_o, s)
+    e_h = orc.rel_linf(h.cpu().numpy(), h_o, s)
+    print(f"[mixed] reduced close: err mu {e_mu:.2e} h {e_h:.2e} infos {infos}", flush=True)
+    assert st == 0 and all(i["refine_steps"] >= 1 for i in infos)
+    assert e_mu < 1e-10 and e_h < 1e-10
+
+
+def test_fbiead_mixed_matches_oracle(gk, ctx):
+    dom = wl.example4_circles(256, 1e-2)
+    gam = (dom.eta ** 2).real
+    dd = gk.DeviceDomain.from_host(dom)
+    mu, infos, st = ctx.fbie_ad(dd, _cuda(gam), prec=gk.MIXED, tol=1e-13, restart=64)
+    ref = orc.fbiead(dom.eta, dom.etap, dom.etapp, dom.A, dom.Ap, gam, dom.n, dom.c)
+    err = orc.rel_linf(mu.cpu().numpy(), ref, np.max(np.abs(gam)))
+    print(f"[mixed] fbiead ex4: err {err:.2e} infos {infos}", flush=True)
+    assert st == 0 and err < 1e-10
+
+
+def test_close_boundary_full_size(gk, ctx):
+    """65 close boundaries, n = 2048 (N = 133120): mixed and FP64 GPU solves agree
+    to 1e-10, and the oracle's residual on sampled rows is at the solver tolerance."""
+    dom, gam = wl.config2()
+    g = gam[:, 0]
+    dd = gk.DeviceDomain.from_host(dom)
+    gt = _cuda(g)
+    print("[full] fp64 solve", flush=True)
+    mu64, h64, inf64, st64 = ctx.fbie(dd, gt, tol=1e-14, restart=256, maxit=8)
+    print(f"  {inf64}", flush=True)
+    print("[full] mixed solve", flush=True)
+    mu32, h32, inf32, st32 = ctx.fbie(dd, gt, tol=1e-14, restart=256, maxit=8, prec=gk.MIXED)
+    print(f"  {inf32}", flush=True)
+    assert st64 == 0 and st32 == 0
+    a64, a32 = mu64.cpu().numpy(), mu32.cpu().numpy()
+    s = np.max(np.abs(g))
+    assert orc.rel_linf(a32, a64, s) < 1e-10
+    assert orc.rel_linf(h32.cpu().numpy(), h64.cpu().numpy(), s) < 1e-10
+    rng = np.random.default_rng(21)
+    rows = np.sort(rng.choice(dom.N, 48, replace=False))
+    res, y = orc.fbie_residual_rows(dom.eta, dom.etap, dom.A, g, a32, dom.n, rows)
+    rel = np.max(np.abs(res)) / np.max(np.abs(y))
+    print(f"[full] oracle residual on {len(rows)} rows: {rel:.2e}", flush=True)
+    assert rel < 1e-9

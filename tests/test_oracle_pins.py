@@ -282,3 +282,15 @@ def test_kernel_rows_equal_full_matrix():
     K = orc.kernel_matrix(d.eta, d.etap, d.A, d.n)
     for sl in (slice(0, 5), slice(30, 40), slice(60, 64)):
         assert np.array_equal(orc.kernel_rows(d.eta, d.etap, d.A, d.n, sl), K[sl])
+
+
+def test_residual_rows_equal_dense_residual():
+    d = wl.annulus(24)
+    gam = np.log(np.abs(d.eta - 0.55))
+    Aop, Cop = orc.fbie_operators(d.eta, d.etap, d.A, d.n)
+    mu = np.random.default_rng(2).normal(size=d.N)
+    full = Aop @ mu + Cop @ gam
+    rows = np.array([0, 5, 23, 24, 40, 47])
+    res, y = orc.fbie_residual_rows(d.eta, d.etap, d.A, gam, mu, d.n, rows)
+    assert np.max(np.abs(res - full[rows])) < 1e-13
+    assert np.max(np.abs(y - (Cop @ gam)[rows])) < 1e-13

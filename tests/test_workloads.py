@@ -76,3 +76,25 @@ def test_config_orientation_and_determinism():
     for (c, a, b, _) in d1.meta["ellipses"]:
         assert abs(c) > max(a, b)
     assert np.all(np.isfinite(g1))
+
+
+def test_close_boundary_workload_prefix():
+    """Close-boundary generator: clockwise components, true gaps in
+    [1e-3, 1e-2] x size to the anchor, no overlaps, graded polygons with eta' = 0
+    at the corner parameter t = 0."""
+    d9, g9 = wl.config2(n=256, m1=9)
+    assert d9.m1 == 9 and d9.N == 9 * 256 and not d9.bounded
+    for k in range(9):
+        assert _signed_area(d9.eta[d9.comp(k)], d9.etap[d9.comp(k)], 256) < 0
+    kinds = d9.meta["kinds"]
+    assert kinds[0] == "poly" and kinds[4] == "poly" and kinds[1] == "ellipse"
+    assert abs(d9.etap[0]) < 1e-12               # corner at t = 0 of a graded polygon
+    from scipy.spatial import cKDTree
+    e = d9.eta.reshape(9, 256)
+    for k in range(1, 9):
+        others = np.concatenate([e[:k], e[k + 1:]]).ravel()
+        dmin, _ = cKDTree(np.c_[others.real, others.imag]).query(np.c_[e[k].real, e[k].imag])
+        assert dmin.min() > 3e-4
+    shapes = wl.close_shapes(9, [wl.SEED, 2])
+    for s in shapes:
+        assert s.size > 0.3

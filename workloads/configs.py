@@ -215,3 +215,152 @@ def closed_form_rhs(dom: Domain, f):
     """gamma = Re[A f(eta)], exact mu = Im[A f(eta)], h = 0 (paper eq. (e:ex-gam))."""
     v = dom.A * f(dom.eta)
     return v.real.copy(), v.imag.copy()
+
+
+# ----------------------------------------------------------------------------
+# Close-boundary workload: sequential adjacency growth of ellipses and
+# Kress-graded rounded polygons (unbounded domain, all boundaries clockwise).
+# ----------------------------------------------------------------------------
+class _Shape:
+    """A convex boundary template placed at `center`.
+
+    `pts(m)` gives m boundary samples relative to the centre (counter-clockwise)."""
+
+    def __init__(self, kind, size, params):
+        self.kind = kind
+        self.size = size
+        self.params = params
+        self.center = 0j
+        self._cache = {}
+
+    def rel_curve(self, t):
+        if self.kind == "ellipse":
+            a, b, phi = self.params
+            return geo.ellipse(t, 0j, a, b, phi, ccw=True)
+        return self.params["poly_ccw"](t)
+
+    def pts(self, m):
+        if m not in self._cache:
+            t = 2 * np.pi * np.arange(m) / m
+            self._cache[m] = self.rel_curve(t)[0]
+        return self._cache[m]
+
+    @property
+    def R(self):
+        return float(np.max(np.abs(self.pts(512))))
+
+
+def _inside_convex(poly_ccw, p):
+    """Points p (complex) strictly inside the convex polygon with ccw vertices poly_ccw."""
+    e = np.roll(poly_ccw, -1) - poly_ccw
+    rel = p[:, None] - poly_ccw[None, :]
+    cross = (np.conj(e)[None, :] * rel).imag
+    return np.all(cross > 0, axis=1)
+
+
+def _gap(sa, sb, m_in=256, m_dist=2048):
+    """Distance between the boundaries of two placed convex shapes, -1 if they overlap."""
+    from scipy.spatial import cKDTree
+    A = sa.pts(m_in) + sa.center
+    B = sb.pts(m_in) + sb.center
+    if np.any(_inside_convex(A, B)) or np.any(_inside_convex(B, A)):
+        return -1.0
+    Ad = sa.pts(m_dist) + sa.center
+    Bd = sb.pts(m_dist) + sb.center
+    tree = cKDTree(np.c_[Ad.real, Ad.imag])
+    d, _ = tree.query(np.c_[Bd.real, Bd.imag])
+    return float(d.min())
+
+
+def _make_shape(rng, kind):
+    a = rng.uniform(0.8, 1.0)
+    if kind == "ellipse":
+        b = a * rng.uniform(0.5, 0.8)
+        return _Shape("ellipse", b, (a, b, rng.uniform(0, np.pi)))
+    p = int(rng.integers(4, 7))
+    ang = 2 * np.pi * np.arange(p) / p + rng.uniform(-0.2, 0.2, p) * 2 * np.pi / p + rng.uniform(0, 2 * np.pi)
+    verts = a * np.exp(1j * np.sort(ang % (2 * np.pi)))
+    side = np.min(np.abs(np.roll(verts, -1) - verts))
+    rad = 0.1 * side
+    poly_ccw = geo.RoundedPolygon(verts, rad, ccw=True)
+    poly_cw = geo.RoundedPolygon(verts, rad, ccw=False)
+    inr = a * np.cos(np.pi / p) * 0.8
+    return _Shape("poly", inr, {"verts": verts, "rad": rad, "p": p, "poly_ccw": poly_ccw, "poly_cw": poly_cw})
+
+
+_SHAPES_CACHE = {}
+
+
+def close_shapes(m1, seed, gap_range=(1e-3, 1e-2), poly_every=4):
+    key = (m1, tuple(np.atleast_1d(seed)), gap_range, poly_every)
+    if key not in _SHAPES_CACHE:
+        _SHAPES_CACHE[key] = _close_shapes(m1, seed, gap_range, poly_every)
+    return _SHAPES_CACHE[key]
+
+
+def _close_shapes(m1, seed, gap_range, poly_every):
+    """Place m1 convex shapes by adjacency growth with boundary gaps g * size,
+    g log-uniform in gap_range, by bisection on the centre distance."""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for k in range(m1):
+        kind = "poly" if (poly_every and k % poly_every == 0) else "ellipse"
+        s = _make_shape(rng, kind)
+        if not shapes:
+            shapes.append(s)
+            continue
+        for _attempt in range(500):
+            anchor = shapes[int(rng.integers(len(shapes)))]
+            d = np.exp(1j * rng.uniform(0, 2 * np.pi))
+            g = 10 ** rng.uniform(np.log10(gap_range[0]), np.log10(gap_range[1]))
+            target = g * min(s.size, anchor.size)
+            lo, hi = 0.0, anchor.R + s.R + 4 * target
+            for _ in range(60):
+                mid = 0.5 * (lo + hi)
+                s.center = anchor.center + mid * d
+                gm = _gap(anchor, s)
+                if gm < 0 or gm < target:
+                    lo = mid
+                else:
+                    hi = mid
+                if gm > 0 and abs(gm - target) < 0.02 * target:
+                    break
+            s.center = anchor.center + hi * d
+            ok = True
+            for o in shapes:
+                if o is anchor:
+                    continue
+                if abs(o.center - s.center) > o.R + s.R + 1e-2:
+                    continue
+                go = _gap(o, s)
+                if go < 1e-3 * min(o.size, s.size):
+                    ok = False
+                    break
+            if ok:
+                shapes.append(s)
+                break
+        else:
+            raise RuntimeError("could not place shape %d" % k)
+    return shapes
+
+
+def config2(n: int = 2048, m1: int = 65, grade: int = 3):
+    """Unbounded domain exterior to m1 close boundaries (every 4th a rounded
+    polygon on a Kress-graded mesh); A = 1; gamma = Re(eta^2)."""
+    shapes = close_shapes(m1, [SEED, 2])
+    curves = []
+    for s in shapes:
+        if s.kind == "ellipse":
+            a, b, phi = s.params
+            curves.append(lambda t, c=s.center, a=a, b=b, phi=phi: geo.ellipse(t, c, a, b, phi, ccw=False))
+        else:
+            poly = s.params["poly_cw"]
+
+            def cv(t, poly=poly, c=s.center):
+                z, dz, ddz = geo.graded_polygon(t, poly, grade)
+                return z + c, dz, ddz
+            curves.append(cv)
+    dom = _assemble(curves, n, False, "one", name=f"cfg2-m{m1}-n{n}",
+                    meta=dict(kinds=[s.kind for s in shapes], centers=[s.center for s in shapes]))
+    gam = (dom.eta ** 2).real
+    return dom, gam[:, None]
