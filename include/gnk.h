@@ -124,12 +124,12 @@ typedef struct {
  *   outer_it    : restart cycles used;  inner_it: total Arnoldi steps
  *   relres      : GMRES residual estimate at exit
  *   true_relres : ||b - A x|| / ||b|| recomputed with an FP64 product
- *   refine_steps: restart cycles run with mixed-precision products (GNK_MIXED) */
+ *   mixed_steps : Arnoldi steps whose product used FP32 far tiles (GNK_MIXED) */
 typedef struct {
   int flag;
   int outer_it;
   int inner_it;
-  int refine_steps;
+  int mixed_steps;
   double relres;
   double true_relres;
 } gnk_info;
@@ -197,6 +197,20 @@ GNK_API gnk_status gnk_fbie(gnk_ctx* ctx, const gnk_domain* dom, const double* g
  * Needs dom->etapp, dom->Ap and dom->c; eta' must be nonzero at every node. */
 GNK_API gnk_status gnk_fbie_ad(gnk_ctx* ctx, const gnk_domain* dom, const double* gam, int nrhs,
                        const gnk_opts* opts, double* mu, gnk_info* info);
+
+/* Batched FBIE: ndom independent domains, each with its own nrhs[d] columns,
+ * solved together (every Cauchy-sum launch covers all domains and columns;
+ * the GMRES steps run for all columns at once, converged columns are masked).
+ *   doms  : host array of ndom domains
+ *   gam   : host array of ndom device pointers, gam[d] is N_d x nrhs[d]
+ *   mu, h : host arrays of ndom device pointers (h may be NULL, or h[d] NULL)
+ *   info  : host array of sum(nrhs) entries, domain-major, or NULL
+ * The pair-kernel launch shape is chosen by a built-in autotuner (timed once
+ * per batch signature; GNK_TUNE=0 disables it, GNK_TUNE_CACHE=path keeps the
+ * choices in a text file). opts->x0 must be NULL. */
+GNK_API gnk_status gnk_fbie_batched(gnk_ctx* ctx, int ndom, const gnk_domain* doms, const double* const* gam,
+                                    const int* nrhs, const gnk_opts* opts, double* const* mu, double* const* h,
+                                    gnk_info* info);
 
 #ifdef __cplusplus
 }

@@ -15,10 +15,11 @@
 //     which reuses every fetched source TPT times and gives independent chains;
 //   * the four wavefronts of a workgroup share the tile and split its source
 //     chunk four ways, then add their sums through LDS in wave order;
-//   * the source range is further split over grid.y; the split count is chosen
-//     so the grid fills whole rounds of the chip's wave slots (no straggler
-//     round); the consumer adds the split partial sums in a fixed order, so
-//     results are bitwise reproducible;
+//   * the work is a list of items (domain, target tile, source split, column
+//     group) covering every domain of a batch in one launch per column-group
+//     width; workgroups stride over the list (largest domains first); the
+//     consumer adds the split partial sums in a fixed order, so results are
+//     bitwise reproducible;
 //   * 1/|d|^2 comes from v_rcp_f64 refined by one Newton step; two sources
 //     share one reciprocal: 1/a = b/(ab), 1/b = a/(ab) (simultaneous
 //     inversion), which halves the v_rcp_f64 issues;
@@ -95,89 +96,6 @@ __device__ __forceinline__ void single_step(Acc<NR, TPT>& acc, const double2 (&t
   }
 }
 
-// rec: N records of `stride` double2 {eta, w_0, .., w_{ncols-1}}; this launch
-// handles columns r0 .. r0+NR-1. The four wavefronts of a workgroup share one
-// tile of 64*TPT targets and take consecutive quarters of the workgroup's
-// source chunk; their sums are added through LDS in wave order.
-// part[(g*ncols + r)*N + i], g = blockIdx.y.
-template <int NR, int TPT>
-__global__ __launch_bounds__(256) void k_cauchy_fp64(const double2* __restrict__ rec, int N, int stride, int ncols,
-                                                     int r0, int chunk, double2* __restrict__ part) {
-  constexpr int kWaveTargets = 64 * TPT;
-  __shared__ double red[3][TPT][2][64];
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int base = blockIdx.x * kWaveTargets;     // first target of the tile (uniform)
-  const int g = blockIdx.y;
-  const int jb0 = g * chunk;
-  const int jb1 = min(N, jb0 + chunk);
-  const int wchunk = ((chunk + 15) >> 4) << 2;    // quarter of the chunk, multiple of 4
-  const int j0 = min(jb1, jb0 + wv * wchunk);
-  const int j1 = min(jb1, j0 + wchunk);
-  const int wo = 1 + r0;   // w_q of source j at rec[j*stride + wo + q]
-
-  double2 tg[TPT];
-  int ti[TPT];
-#pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    ti[t] = base + t * 64 + lane;
-    tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
-  }
-  Acc<NR, TPT> acc;
-#pragma unroll
-  for (int t = 0; t < TPT; ++t)
-#pragma unroll
-    for (int r = 0; r < NR; ++r) { acc.x[t][r] = 0.0; acc.y[t][r] = 0.0; }
-
-  // sources outside the tile's own window need no j != i test
-  auto plain = [&](int ja, int jb) {
-    int j = ja;
-    for (; j + 3 < jb; j += 4) {
-      const double2* r = rec + (size_t)j * stride;
-      pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
-      pair_step<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
-    }
-    for (; j + 1 < jb; j += 2) {
-      const double2* r = rec + (size_t)j * stride;
-      pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
-    }
-    if (j < jb) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, false);
-  };
-
-  plain(j0, min(j1, base));
-  {
-    const int ja = max(j0, base), jb = min(j1, base + kWaveTargets);
-    for (int j = ja; j < jb; ++j) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
-  }
-  plain(max(j0, base + kWaveTargets), j1);
-
-  // fixed-order reduction over the four wavefronts, one column at a time
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    if (wv > 0) {
-#pragma unroll
-      for (int t = 0; t < TPT; ++t) {
-        red[wv - 1][t][0][lane] = acc.x[t][r];
-        red[wv - 1][t][1][lane] = acc.y[t][r];
-      }
-    }
-    __syncthreads();
-    if (wv == 0) {
-#pragma unroll
-      for (int t = 0; t < TPT; ++t) {
-        double x = acc.x[t][r], y = acc.y[t][r];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          x += red[q][t][0][lane];
-          y += red[q][t][1][lane];
-        }
-        if (ti[t] < N) part[((size_t)g * ncols + r0 + r) * N + ti[t]] = make_double2(x, y);
-      }
-    }
-    __syncthreads();
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Mixed precision: well-separated source tiles in FP32, the rest in FP64.
 // A source tile is 64 consecutive nodes with bounding circle (c_s, r_s); the
@@ -223,131 +141,166 @@ __device__ __forceinline__ void pair_step32(Acc32<NR, TPT>& acc, const float2 (&
   }
 }
 
-// rec: FP64 records (stride double2); rec32: FP32 records {v_j, w_j,0..} (stride float2);
-// sb: per 64-node source tile {cx, cy, r, 0}; tb: per target tile {cx, cy, r, 0}.
-template <int NR, int TPT>
-__global__ __launch_bounds__(256) void k_cauchy_mixed(const double2* __restrict__ rec, const float2* __restrict__ rec32,
-                                                      const double4* __restrict__ sb, const double4* __restrict__ tb,
-                                                      int N, int stride, int ncols, int r0, int chunk, double far2,
-                                                      double2* __restrict__ part) {
-  constexpr int kWaveTargets = 64 * TPT;
+// One launch: every item of the list. The four wavefronts of a workgroup share
+// the item's tile of 64*TPT targets and take consecutive quarters of its source
+// chunk; their sums are added through LDS in wave order. MIXED: far source
+// tiles of 64 nodes are summed in FP32 (see above).
+template <int NR, int TPT, bool MIXED>
+__global__ __launch_bounds__(256) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+                                               int nitems, int lead, int data, const int* __restrict__ active) {
+  constexpr int kTile = 64 * TPT;
   __shared__ double red[3][TPT][2][64];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int base = blockIdx.x * kWaveTargets;
-  const int g = blockIdx.y;
-  const int jb0 = g * chunk;                      // chunk is a multiple of 256
-  const int jb1 = min(N, jb0 + chunk);
-  const int wchunk = chunk >> 2;                  // multiple of 64: whole source tiles
-  const int j0 = min(jb1, jb0 + wv * wchunk);
-  const int j1 = min(jb1, j0 + wchunk);
-  const int wo = 1 + r0;
-  const double4 tbd = tb[blockIdx.x];
-
-  double2 tg[TPT];
-  int ti[TPT];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 w = items[it];
+    const DomDev& D = doms[w.x];
+    const int N = D.N;
+    const int wcols = lead + data * D.ncols;
+    const int stride = wcols + 1;
+    const double2* __restrict__ rec = D.rec;
+    if (active != nullptr) {
+      bool any = false;
 #pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    ti[t] = base + t * 64 + lane;
-    tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
-  }
-  Acc<NR, TPT> acc;
-#pragma unroll
-  for (int t = 0; t < TPT; ++t)
-#pragma unroll
-    for (int r = 0; r < NR; ++r) { acc.x[t][r] = 0.0; acc.y[t][r] = 0.0; }
-
-  auto plain = [&](int ja, int jb) {
-    int j = ja;
-    for (; j + 1 < jb; j += 2) {
-      const double2* r = rec + (size_t)j * stride;
-      pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
-    }
-    if (j < jb) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, false);
-  };
-
-  for (int ts = j0; ts < j1; ts += 64) {
-    const int te = min(ts + 64, j1);
-    const double4 sbd = sb[ts >> 6];
-    const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
-    const double rr = tbd.z + sbd.z;
-    const bool far = (dcx * dcx + dcy * dcy) > far2 * rr * rr;
-    if (far) {
-      float2 u[TPT];
-#pragma unroll
-      for (int t = 0; t < TPT; ++t) u[t] = make_float2((float)(tg[t].x - sbd.x), (float)(tg[t].y - sbd.y));
-      Acc32<NR, TPT> a32;
-#pragma unroll
-      for (int t = 0; t < TPT; ++t)
-#pragma unroll
-        for (int r = 0; r < NR; ++r) { a32.x[t][r] = 0.f; a32.y[t][r] = 0.f; }
-      int j = ts;
-#pragma unroll 2
-      for (; j + 1 < te; j += 2) {
-        const float2* r = rec32 + (size_t)j * stride;
-        pair_step32<NR, TPT>(a32, u, r, r + stride, wo);
+      for (int q = 0; q < NR; ++q) {
+        const int col = w.w + q - lead;
+        any = any || col < 0 || active[D.c0 + col] != 0;
       }
-      if (j < te) {
-        const float2* r = rec32 + (size_t)j * stride;
-        const float2 e = r[0];
+      if (!any) continue;
+    }
+    const int base = w.y * kTile;
+    const int g = w.z;
+    const int chunk = D.chunk;
+    const int jb0 = g * chunk;
+    const int jb1 = min(N, jb0 + chunk);
+    // quarter of the chunk per wave: multiple of 4 (FP64) or whole 64-node tiles (mixed)
+    const int wchunk = MIXED ? (chunk >> 2) : (((chunk + 15) >> 4) << 2);
+    const int j0 = min(jb1, jb0 + wv * wchunk);
+    const int j1 = min(jb1, j0 + wchunk);
+    const int wo = 1 + w.w;
+
+    double2 tg[TPT];
+    int ti[TPT];
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+      ti[t] = base + t * 64 + lane;
+      tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
+    }
+    Acc<NR, TPT> acc;
+#pragma unroll
+    for (int t = 0; t < TPT; ++t)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) { acc.x[t][r] = 0.0; acc.y[t][r] = 0.0; }
+
+    // sources outside the tile's own window need no j != i test
+    auto plain = [&](int ja, int jb) {
+      int j = ja;
+      for (; j + 3 < jb; j += 4) {
+        const double2* r = rec + (size_t)j * stride;
+        pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
+        pair_step<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
+      }
+      for (; j + 1 < jb; j += 2) {
+        const double2* r = rec + (size_t)j * stride;
+        pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
+      }
+      if (j < jb) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, false);
+    };
+    auto fp64_range = [&](int ja, int jb) {
+      plain(ja, min(jb, base));
+      const int ma = max(ja, base), mb = min(jb, base + kTile);
+      for (int j = ma; j < mb; ++j) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
+      plain(max(ja, base + kTile), jb);
+    };
+
+    if (!MIXED) {
+      fp64_range(j0, j1);
+    } else {
+      const double4 tbd = D.tb[w.y];
+      const float2* __restrict__ rec32 = D.rec32;
+      for (int ts = j0; ts < j1; ts += 64) {
+        const int te = min(ts + 64, j1);
+        const double4 sbd = D.sb[ts >> 6];
+        const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
+        const double rr = tbd.z + sbd.z;
+        if ((dcx * dcx + dcy * dcy) > D.far2 * rr * rr) {
+          float2 u[TPT];
+#pragma unroll
+          for (int t = 0; t < TPT; ++t) u[t] = make_float2((float)(tg[t].x - sbd.x), (float)(tg[t].y - sbd.y));
+          Acc32<NR, TPT> a32;
+#pragma unroll
+          for (int t = 0; t < TPT; ++t)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) { a32.x[t][r] = 0.f; a32.y[t][r] = 0.f; }
+          int j = ts;
+#pragma unroll 2
+          for (; j + 1 < te; j += 2) {
+            const float2* r = rec32 + (size_t)j * stride;
+            pair_step32<NR, TPT>(a32, u, r, r + stride, wo);
+          }
+          if (j < te) {
+            const float2* r = rec32 + (size_t)j * stride;
+            const float2 e = r[0];
+#pragma unroll
+            for (int t = 0; t < TPT; ++t) {
+              const float dx = u[t].x - e.x, dy = u[t].y - e.y;
+              const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
+              accumulate32<NR, TPT>(a32, t, r + wo, dx * q, -dy * q);
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < TPT; ++t)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+              acc.x[t][r] += (double)a32.x[t][r];
+              acc.y[t][r] += (double)a32.y[t][r];
+            }
+        } else {
+          fp64_range(ts, te);
+        }
+      }
+    }
+
+    // fixed-order reduction over the four wavefronts, one column at a time
+    double2* __restrict__ part = D.parts;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (wv > 0) {
 #pragma unroll
         for (int t = 0; t < TPT; ++t) {
-          const float dx = u[t].x - e.x, dy = u[t].y - e.y;
-          const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
-          accumulate32<NR, TPT>(a32, t, r + wo, dx * q, -dy * q);
+          red[wv - 1][t][0][lane] = acc.x[t][r];
+          red[wv - 1][t][1][lane] = acc.y[t][r];
         }
       }
+      __syncthreads();
+      if (wv == 0) {
 #pragma unroll
-      for (int t = 0; t < TPT; ++t)
+        for (int t = 0; t < TPT; ++t) {
+          double x = acc.x[t][r], y = acc.y[t][r];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          acc.x[t][r] += (double)a32.x[t][r];
-          acc.y[t][r] += (double)a32.y[t][r];
+          for (int q = 0; q < 3; ++q) {
+            x += red[q][t][0][lane];
+            y += red[q][t][1][lane];
+          }
+          if (ti[t] < N) part[((size_t)g * wcols + w.w + r) * N + ti[t]] = make_double2(x, y);
         }
-    } else {
-      // near tile: FP64, with the j != i test where it meets the target tile
-      plain(ts, min(te, base));
-      const int ja = max(ts, base), jb = min(te, base + kWaveTargets);
-      for (int j = ja; j < jb; ++j) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
-      plain(max(ts, base + kWaveTargets), te);
-    }
-  }
-
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    if (wv > 0) {
-#pragma unroll
-      for (int t = 0; t < TPT; ++t) {
-        red[wv - 1][t][0][lane] = acc.x[t][r];
-        red[wv - 1][t][1][lane] = acc.y[t][r];
       }
+      __syncthreads();
     }
-    __syncthreads();
-    if (wv == 0) {
-#pragma unroll
-      for (int t = 0; t < TPT; ++t) {
-        double x = acc.x[t][r], y = acc.y[t][r];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          x += red[q][t][0][lane];
-          y += red[q][t][1][lane];
-        }
-        if (ti[t] < N) part[((size_t)g * ncols + r0 + r) * N + ti[t]] = make_double2(x, y);
-      }
-    }
-    __syncthreads();
   }
 }
 
-// bounding circle {cx, cy, r, 0} of each tile of `tile` consecutive nodes
-// (centre of the bounding box); one wavefront per tile
-__global__ __launch_bounds__(64) void k_tile_bounds(const double2* __restrict__ rec, int N, int stride, int tile,
-                                                    double4* __restrict__ out) {
+// bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of
+// `tile` consecutive nodes; one wavefront per (tile, domain)
+__global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ doms, int tile, int target) {
+  const DomDev& D = doms[blockIdx.y];
   const int b = blockIdx.x, lane = threadIdx.x;
-  const int i0 = b * tile, i1 = min(N, i0 + tile);
+  const int i0 = b * tile;
+  if (i0 >= D.N) return;
+  const int i1 = min(D.N, i0 + tile);
   double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
   for (int i = i0 + lane; i < i1; i += 64) {
-    const double2 e = rec[(size_t)i * stride];
+    const double2 e = D.eta[i];
     xmin = fmin(xmin, e.x); xmax = fmax(xmax, e.x);
     ymin = fmin(ymin, e.y); ymax = fmax(ymax, e.y);
   }
@@ -361,126 +314,70 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const double2* __restrict__ 
   const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax);
   double r = 0.0;
   for (int i = i0 + lane; i < i1; i += 64) {
-    const double2 e = rec[(size_t)i * stride];
+    const double2 e = D.eta[i];
     r = fmax(r, sqrt((e.x - cx) * (e.x - cx) + (e.y - cy) * (e.y - cy)));
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
   // widen by a relative margin so rounding of the centre cannot hide a node
-  if (lane == 0) out[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
+  if (lane == 0) (target ? D.tb : D.sb)[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
 }
 
 // FP32 records: v_j = eta_j - c_{tile(j)}, then the weights rounded to FP32
-__global__ void k_records32(const double2* __restrict__ rec, const double4* __restrict__ sb, int N, int stride,
-                            float2* __restrict__ rec32) {
+__global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data) {
+  const DomDev& D = doms[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  const double2* r = rec + (size_t)j * stride;
-  float2* o = rec32 + (size_t)j * stride;
-  const double4 c = sb[j >> 6];
+  if (j >= D.N) return;
+  const int stride = lead + data * D.ncols + 1;
+  const double2* r = D.rec + (size_t)j * stride;
+  float2* o = D.rec32 + (size_t)j * stride;
+  const double4 c = D.sb[j >> 6];
   o[0] = make_float2((float)(r[0].x - c.x), (float)(r[0].y - c.y));
   for (int q = 1; q < stride; ++q) o[q] = make_float2((float)r[q].x, (float)r[q].y);
 }
 
-template <int NR, int TPT>
-void launch_one(const double2* rec, int64_t N, int ncols, int r0, const CauchyPlan& plan, double2* part,
-                hipStream_t st) {
-  const int64_t tile = 64 * TPT;
-  dim3 grid((unsigned)((N + tile - 1) / tile), (unsigned)plan.splits);
-  k_cauchy_fp64<NR, TPT><<<grid, plan.tpb, 0, st>>>(rec, (int)N, ncols + 1, ncols, r0, (int)plan.chunk, part);
+template <int NR, int TPT, bool MIXED>
+void launch_k(const DomDev* doms, const int4* items, int nitems, int lead, int data, const int* active, int grid,
+              hipStream_t st) {
+  k_pairs<NR, TPT, MIXED><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
 }
 
-template <int TPT>
-void launch_cols(const double2* rec, int64_t N, int ncols, const CauchyPlan& plan, double2* part, hipStream_t st) {
-  int r0 = 0;
-  while (r0 < ncols) {
-    const int left = ncols - r0;
-    if (left >= 8) { launch_one<8, TPT>(rec, N, ncols, r0, plan, part, st); r0 += 8; }
-    else if (left >= 4) { launch_one<4, TPT>(rec, N, ncols, r0, plan, part, st); r0 += 4; }
-    else if (left >= 2) { launch_one<2, TPT>(rec, N, ncols, r0, plan, part, st); r0 += 2; }
-    else { launch_one<1, TPT>(rec, N, ncols, r0, plan, part, st); r0 += 1; }
-  }
-}
-
-template <int NR, int TPT>
-void launch_mixed_one(const MixedArgs& m, int64_t N, int ncols, int r0, const CauchyPlan& plan, double2* part,
-                      hipStream_t st) {
-  const int64_t tile = 64 * TPT;
-  dim3 grid((unsigned)((N + tile - 1) / tile), (unsigned)plan.splits);
-  k_cauchy_mixed<NR, TPT><<<grid, plan.tpb, 0, st>>>(m.rec, m.rec32, m.src_bounds, m.tgt_bounds, (int)N, ncols + 1,
-                                                     ncols, r0, (int)plan.chunk, m.far2, part);
-}
-
-template <int TPT>
-void launch_mixed_cols(const MixedArgs& m, int64_t N, int ncols, const CauchyPlan& plan, double2* part,
-                       hipStream_t st) {
-  int r0 = 0;
-  while (r0 < ncols) {
-    const int left = ncols - r0;
-    if (left >= 4) { launch_mixed_one<4, TPT>(m, N, ncols, r0, plan, part, st); r0 += 4; }
-    else if (left >= 2) { launch_mixed_one<2, TPT>(m, N, ncols, r0, plan, part, st); r0 += 2; }
-    else { launch_mixed_one<1, TPT>(m, N, ncols, r0, plan, part, st); r0 += 1; }
+template <int NR>
+void launch_w(const DomDev* doms, const int4* items, int nitems, int tpt, int lead, int data, bool mixed,
+              const int* active, int grid, hipStream_t st) {
+  if (tpt == 2) {
+    if (mixed) launch_k<NR, 2, true>(doms, items, nitems, lead, data, active, grid, st);
+    else launch_k<NR, 2, false>(doms, items, nitems, lead, data, active, grid, st);
+  } else {
+    if (mixed) launch_k<NR, 1, true>(doms, items, nitems, lead, data, active, grid, st);
+    else launch_k<NR, 1, false>(doms, items, nitems, lead, data, active, grid, st);
   }
 }
 
 }  // namespace
 
-hipError_t launch_tile_bounds(const double2* rec, int64_t N, int ncols, int tile, double4* out, hipStream_t st) {
-  const int64_t tiles = (N + tile - 1) / tile;
-  k_tile_bounds<<<(unsigned)tiles, 64, 0, st>>>(rec, (int)N, ncols + 1, tile, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_records32(const double2* rec, const double4* src_bounds, int64_t N, int ncols, float2* rec32,
-                            hipStream_t st) {
-  k_records32<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(rec, src_bounds, (int)N, ncols + 1, rec32);
-  return hipGetLastError();
-}
-
-hipError_t launch_cauchy_mixed(const MixedArgs& m, int64_t N, int ncols, const CauchyPlan& plan, double2* S_part,
-                               hipStream_t st) {
-  if (N <= 0) return hipSuccess;
-  if (plan.tpt == 2) launch_mixed_cols<2>(m, N, ncols, plan, S_part, st);
-  else launch_mixed_cols<1>(m, N, ncols, plan, S_part, st);
-  return hipGetLastError();
-}
-
-CauchyPlan plan_cauchy(int64_t N, int ncols, int num_cu, int align) {
-  CauchyPlan p;
-  p.tpb = 256;
-  const int64_t slots = (int64_t)num_cu * 4 * 8;   // 4 SIMDs x 8 resident waves per CU
-  // two targets per lane once 128-target tiles x 64 source splits fill the chip
-  p.tpt = ((N + 127) / 128) * 64 >= slots ? 2 : 1;
-  if (const char* s = getenv("GNK_CAUCHY_TPT")) p.tpt = atoi(s) == 2 ? 2 : 1;
-  const int64_t tiles = (N + 64 * p.tpt - 1) / (64 * p.tpt);
-  // workgroups = tiles x splits, 4 waves each; score each split count by how
-  // well its waves fill whole rounds of the wave slots (at least 32 sources
-  // per workgroup, at most 64 splits)
-  const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, N / 32));
-  std::vector<double> score((size_t)max_s + 1, 0.0);
-  double best = 0.0;
-  for (int64_t s = 1; s <= max_s; ++s) {
-    const double rounds = (double)(tiles * s * 4) / (double)slots;
-    score[s] = rounds / std::ceil(rounds) * std::min(1.0, rounds);
-    best = std::max(best, score[s]);
+hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
+                        bool mixed, const int* active, int grid, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (grid <= 0 || grid > nitems) grid = nitems;
+  switch (width) {
+    case 8: launch_w<8>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;
+    case 4: launch_w<4>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;
+    case 2: launch_w<2>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;
+    default: launch_w<1>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;
   }
-  // fewest splits within 1% of the best fill (fewer partial sums to reduce)
-  int64_t best_s = 1;
-  while (best_s < max_s && score[best_s] < best - 0.01) ++best_s;
-  if (const char* s = getenv("GNK_CAUCHY_SPLITS")) best_s = std::max(1, atoi(s));
-  int64_t chunk = (N + best_s - 1) / best_s;
-  chunk = (chunk + align - 1) / align * align;
-  p.chunk = chunk;
-  p.splits = (int)((N + chunk - 1) / chunk);
-  (void)ncols;
-  return p;
+  return hipGetLastError();
 }
 
-hipError_t launch_cauchy_fp64(const double2* rec, int64_t N, int ncols, const CauchyPlan& plan, double2* S_part,
-                              hipStream_t st) {
-  if (N <= 0) return hipSuccess;
-  if (plan.tpt == 2) launch_cols<2>(rec, N, ncols, plan, S_part, st);
-  else launch_cols<1>(rec, N, ncols, plan, S_part, st);
+hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, bool target, hipStream_t st) {
+  dim3 grid((unsigned)((maxN + tile - 1) / tile), (unsigned)ndom);
+  k_tile_bounds<<<grid, 64, 0, st>>>(doms, tile, target ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_records32(const DomDev* doms, int ndom, int maxN, int lead, int data, hipStream_t st) {
+  dim3 grid((unsigned)((maxN + 255) / 256), (unsigned)ndom);
+  k_records32<<<grid, 256, 0, st>>>(doms, lead, data);
   return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@
 // the symbol multiply in bit-reversed order, then a decimation-in-time inverse
 // pass (bit-reversed in, natural out), so no permutation pass is needed.
 // Global traffic is one read of x and one read-modify-write of y per element.
+// The vectors are given as a list of flat offsets, so one launch covers every
+// component of every column (and of every domain with this n).
 // Powers of two up to 4096 use the FFT; other even n use a direct O(n^2)
 // circulant product with the closed-form first column.
 #include "gnk_internal.h"
@@ -54,15 +56,18 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {   // a * conj(b
   return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
+// vectors: offs[v] is the flat offset of length-n vector v; block b takes v = 2b, 2b+1
 __global__ __launch_bounds__(kFftThreads) void k_circulant_fft(const double* __restrict__ x, double* __restrict__ y,
-                                                               int n, int logn, int V, double sign,
-                                                               const double2* __restrict__ tw) {
+                                                               const int64_t* __restrict__ offs, int n, int logn,
+                                                               int V, double sign, const double2* __restrict__ tw) {
   extern __shared__ double2 z[];
   const int va = 2 * blockIdx.x;
   const int vb = va + 1;
   const bool hasb = vb < V;
-  const double* xa = x + (size_t)va * n;
-  const double* xb = x + (size_t)vb * n;
+  const int64_t oa = offs[va];
+  const int64_t ob = hasb ? offs[vb] : 0;
+  const double* xa = x + oa;
+  const double* xb = x + ob;
   for (int p = threadIdx.x; p < n; p += blockDim.x) z[p] = make_double2(xa[p], hasb ? xb[p] : 0.0);
 
   const int half = n >> 1;
@@ -106,8 +111,8 @@ __global__ __launch_bounds__(kFftThreads) void k_circulant_fft(const double* __r
     }
   }
   __syncthreads();
-  double* ya = y + (size_t)va * n;
-  double* yb = y + (size_t)vb * n;
+  double* ya = y + oa;
+  double* yb = y + ob;
   for (int p = threadIdx.x; p < n; p += blockDim.x) {
     const double2 v = z[p];
     ya[p] += sign * v.x;
@@ -116,19 +121,20 @@ __global__ __launch_bounds__(kFftThreads) void k_circulant_fft(const double* __r
 }
 
 // direct fallback: y_p += sign * sum_q b_{(p-q) mod n} x_q
-__global__ __launch_bounds__(256) void k_circulant_direct(const double* __restrict__ x, double* __restrict__ y, int n,
-                                                          double sign, const double* __restrict__ b) {
+__global__ __launch_bounds__(256) void k_circulant_direct(const double* __restrict__ x, double* __restrict__ y,
+                                                          const int64_t* __restrict__ offs, int n, double sign,
+                                                          const double* __restrict__ b) {
   const int v = blockIdx.y;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const double* xv = x + (size_t)v * n;
+  const double* xv = x + offs[v];
   double acc = 0.0;
   for (int q = 0; q < n; ++q) {
     int d = p - q;
     d += (d < 0) ? n : 0;
     acc = __builtin_fma(b[d], xv[q], acc);
   }
-  y[(size_t)v * n + p] += sign * acc;
+  y[offs[v] + p] += sign * acc;
 }
 
 int ilog2(int64_t n) {
@@ -152,17 +158,16 @@ hipError_t launch_twiddles(double2* tw, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_circulant(const double* x, double* y, int64_t m1, int64_t n, int nrhs, double sign,
+hipError_t launch_circulant(const double* x, double* y, const int64_t* offs, int nvec, int64_t n, double sign,
                             const double2* twiddle, hipStream_t st) {
-  const int64_t V = m1 * (int64_t)nrhs;
-  if (V == 0) return hipSuccess;
+  if (nvec <= 0) return hipSuccess;
   if (circulant_uses_fft(n)) {
-    const unsigned pairs = (unsigned)((V + 1) / 2);
+    const unsigned pairs = (unsigned)((nvec + 1) / 2);
     const size_t lds = (size_t)n * sizeof(double2);
-    k_circulant_fft<<<pairs, kFftThreads, lds, st>>>(x, y, (int)n, ilog2(n), (int)V, sign, twiddle);
+    k_circulant_fft<<<pairs, kFftThreads, lds, st>>>(x, y, offs, (int)n, ilog2(n), nvec, sign, twiddle);
   } else {
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)V);
-    k_circulant_direct<<<grid, 256, 0, st>>>(x, y, (int)n, sign, reinterpret_cast<const double*>(twiddle));
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)nvec);
+    k_circulant_direct<<<grid, 256, 0, st>>>(x, y, offs, (int)n, sign, reinterpret_cast<const double*>(twiddle));
   }
   return hipGetLastError();
 }

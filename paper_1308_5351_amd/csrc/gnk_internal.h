@@ -1,4 +1,9 @@
 // Internal declarations shared by the HIP sources of libgnk (not part of the ABI).
+//
+// Every solve works on a batch of domains (one domain for the single-domain
+// entry points). Domain d has N_d = m1_d * n_d nodes and ncols_d real columns;
+// column (d, r) is a vector of length N_d stored at a flat offset. The device
+// keeps one DomDev per domain and one ColDev per column.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,39 +16,59 @@
 
 namespace gnk {
 
-// Launch-shape parameters of the Cauchy pair kernel, picked per problem size.
-struct CauchyPlan {
-  int tpb = 256;      // threads per block (4 wavefronts)
-  int tpt = 1;        // target nodes per lane
-  int splits = 1;     // number of source ranges (grid.y); partial sums reduced in order
-  int64_t chunk = 0;  // sources per split (multiple of 16: four wave quarters of 4)
+struct DomDev {
+  // boundary data (caller-owned)
+  const double2* eta;
+  const double2* etap;
+  const double2* etapp;
+  const double2* A;
+  const double2* Ap;
+  // per-node workspace
+  double2* rho;      // eta' / A
+  double* dB;        // diag(B1)
+  double* dD;        // diag(D1)
+  double* e;         // vector e of the adjoint equation
+  // Cauchy-sum workspace: records rec[j*stride + f], f = 0: eta_j, f = 1 + q: weight column q
+  double2* rec;
+  float2* rec32;     // FP32 records (tile-local eta offsets, weights)
+  double2* parts;    // partial sums [splits][wcols][N]
+  double4* sb;       // bounds of the 64-node source tiles {cx, cy, r, 0}
+  double4* tb;       // bounds of the 64*tpt-node target tiles
+  double far2;       // mixed precision: far when |c_t - c_s|^2 > far2 (r_t + r_s)^2
+  int N, n, m1;
+  int ncols;         // real columns of the domain
+  int c0;            // first global column index
+  int splits;        // source splits
+  int chunk;         // sources per split
+  int c;             // +1 bounded, -1 unbounded
 };
 
-// align: the split length is a multiple of it (16 for FP64; 256 for the mixed
-// kernel, whose four wavefronts each take whole 64-node source tiles)
-CauchyPlan plan_cauchy(int64_t N, int ncols, int num_cu, int align = 16);
-
-// Source records: rec[j*(ncols+1)] = eta_j, rec[j*(ncols+1) + 1 + r] = w_j,r.
-// S_part[(g*ncols + r)*N + i] = sum_{j in split g, j != i} w_j,r / (eta_i - eta_j)
-hipError_t launch_cauchy_fp64(const double2* rec, int64_t N, int ncols, const CauchyPlan& plan,
-                              double2* S_part, hipStream_t st);
-
-// Mixed-precision Cauchy sum: FP32 for far 64-node source tiles, FP64 otherwise.
-struct MixedArgs {
-  const double2* rec;          // FP64 records (as launch_cauchy_fp64)
-  const float2* rec32;         // FP32 records: tile-local eta offsets and weights
-  const double4* src_bounds;   // per 64-node tile {cx, cy, r, 0}
-  const double4* tgt_bounds;   // per target tile of 64*tpt nodes {cx, cy, r, 0}
-  double far2;                 // (1 + theta)^2: far when |c_t - c_s|^2 > far2 (r_t + r_s)^2
+struct ColDev {
+  int d;             // domain
+  int r;             // column within the domain
+  int64_t off;       // offset of the column in flat vectors
 };
-hipError_t launch_tile_bounds(const double2* rec, int64_t N, int ncols, int tile, double4* out, hipStream_t st);
-hipError_t launch_records32(const double2* rec, const double4* src_bounds, int64_t N, int ncols, float2* rec32,
-                            hipStream_t st);
-hipError_t launch_cauchy_mixed(const MixedArgs& m, int64_t N, int ncols, const CauchyPlan& plan, double2* S_part,
-                               hipStream_t st);
 
-// y_k += sign * L x_k for every component k and column r (circulant blocks of Sec. 3.3).
-hipError_t launch_circulant(const double* x, double* y, int64_t m1, int64_t n, int nrhs, double sign,
+// Cauchy sums S = E w for every domain of the batch and every weight column
+// (wcols_d = lead + data * ncols_d: an optional leading column, then the
+// domain's data columns):
+//   parts_d[(g*wcols_d + q)*N_d + i] = sum_{j in split g, j != i} w_jq / (eta_i - eta_j)
+// items: int4 {d, target tile, split, first weight column}; `width` columns per
+// item (8, 4, 2 or 1). mixed: FP32 for far 64-node source tiles (rec32, sb, tb).
+// active: optional per global column mask; an item whose data columns are all
+// inactive is skipped. grid: number of workgroups (they stride over the items).
+hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
+                        bool mixed, const int* active, int grid, hipStream_t st);
+
+// bounding circles of the tiles of `tile` nodes of every domain (source tiles
+// of 64 nodes into sb, target tiles into tb)
+hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, bool target, hipStream_t st);
+// FP32 records from the FP64 records of every domain
+hipError_t launch_records32(const DomDev* doms, int ndom, int maxN, int lead, int data, hipStream_t st);
+
+// y_k += sign * L x_k for a list of length-n vectors at the given flat offsets
+// (the circulant blocks of Sec. 3.3); twiddle: the table for this n.
+hipError_t launch_circulant(const double* x, double* y, const int64_t* offs, int nvec, int64_t n, double sign,
                             const double2* twiddle, hipStream_t st);
 hipError_t launch_twiddles(double2* tw, int64_t n, hipStream_t st);
 bool circulant_uses_fft(int64_t n);

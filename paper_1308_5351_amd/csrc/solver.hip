@@ -1,6 +1,6 @@
-// Host driver of libgnk: context and workspace, input validation, operator
-// application, the device-resident restarted GMRES, and the C ABI entry points
-// declared in include/gnk.h.
+// Host driver of libgnk: context and workspace, batches of domains, input
+// validation, operator application, the device-resident restarted GMRES, the
+// launch-shape autotuner, and the C ABI entry points declared in include/gnk.h.
 //
 // Method (paper Sec. 3 and 4):
 //   FBIE   : y = (D - diag(D1) + Lhat) gamma; solve (2I + diag(B1) - B) mu = -y;
@@ -8,14 +8,20 @@
 //   FBIEad : e from eq. (e:bve); solve (diag(e) + B^T + Phat) mu = gamma.
 // Every product with B, D, B^T, D^T is one Cauchy sum S = E w followed by a
 // per-node epilogue; the circulant blocks use the LDS FFT kernel.
+//
+// Every call works on a batch: one or more domains, each with its own columns
+// (right-hand sides). A single-domain call is a batch of one whose flat
+// vectors are the caller's arrays.
 #include <algorithm>
-#include <cstdarg>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -35,7 +41,7 @@ struct gnk_ctx {
     size_t bytes = 0;
   };
   std::map<std::string, Buf> bufs;
-  int64_t tw_n = -1;     // n of the cached circulant table
+  std::map<int64_t, int> tw_ready;       // n -> 1 when the circulant table "tw<n>" is filled
   // pipelined convergence read-back of the GMRES iterations
   int* pinned = nullptr;                 // host-pinned, one int per Arnoldi step
   double* pinned_rel = nullptr;          // host-pinned residual estimates (mixed switch)
@@ -45,13 +51,17 @@ struct gnk_ctx {
   bool prof = false;
   struct ProfRec {
     hipEvent_t a, b;
-    int64_t N;
-    int ncols;
-    bool mixed;
+    double pair_cols, flops, pairs1;
+    bool mixed, single;
   };
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
   gnk_prof prof_acc{};
+  // autotuner results: key -> "tpt chunk persistent"
+  std::map<std::string, std::string> tune;
+  bool tune_loaded = false;
+  // host copies of uploaded tables stay alive until the next call
+  std::vector<std::vector<char>> host_keep;
 };
 
 namespace gnk {
@@ -110,28 +120,61 @@ T* ws(gnk_ctx* c, const std::string& name, size_t count) {
   return static_cast<T*>(p);
 }
 
+// copy a host vector to a named device buffer (the host copy is kept alive
+// until the next call, so the asynchronous copy may still read it)
+template <class T>
+T* upload(gnk_ctx* c, const std::string& name, const std::vector<T>& v) {
+  T* d = ws<T>(c, name, std::max<size_t>(v.size(), 1));
+  if (!v.empty()) {
+    std::vector<char> keep(sizeof(T) * v.size());
+    memcpy(keep.data(), v.data(), keep.size());
+    c->host_keep.push_back(std::move(keep));
+    HIPCHK(c, hipMemcpyAsync(d, c->host_keep.back().data(), sizeof(T) * v.size(), hipMemcpyHostToDevice,
+                             c->stream));
+  }
+  return d;
+}
+
 unsigned nblocks(int64_t n, int t = kT) { return (unsigned)((n + t - 1) / t); }
 
-// ----------------------------------------------------------- prepared domain
-struct Prep {
-  int64_t N = 0, n = 0, m1 = 0;
-  const double2* eta = nullptr;
-  const double2* etap = nullptr;
-  const double2* etapp = nullptr;
-  const double2* A = nullptr;
-  const double2* Ap = nullptr;
-  int c = 1;
-  double2* rho = nullptr;   // eta'/A
-  double* dB = nullptr;     // diag(B1)
-  double* dD = nullptr;     // diag(D1)
-  double* e = nullptr;      // vector e (adjoint equation)
-  double2* tw = nullptr;    // circulant table
-  CauchyPlan plan;
-  // mixed precision (FP32 far tiles)
-  CauchyPlan mplan;
-  double4* sb = nullptr;    // 64-node source tile bounds
-  double4* tb = nullptr;    // target tile bounds (64 * mplan.tpt nodes)
-  double far2 = 4.0;
+int64_t slots_of(const gnk_ctx* c) { return (int64_t)c->num_cu * 4 * 8; }   // 4 SIMDs x 8 waves
+
+// ------------------------------------------------------------------ batches
+enum Pattern { P_GM = 0, P_SETUP = 1, P_LEAD = 2 };   // (lead, data) = (0,1), (1,1), (1,0)
+constexpr int kLead[3] = {0, 1, 1};
+constexpr int kData[3] = {1, 1, 0};
+constexpr int kWidths[4] = {8, 4, 2, 1};
+
+struct PairShape {
+  int tpt = 1;
+  int chunk = 0;        // sources per workgroup (0: single-domain plan)
+  int persistent = 0;   // workgroups striding over the items (0: one per item)
+};
+
+struct Batch {
+  int ndom = 0, ncol = 0, maxN = 0, maxm1 = 0;
+  int64_t T = 0;        // flat vector length
+  std::vector<DomDev> dom;
+  std::vector<ColDev> col;
+  DomDev* d_dom = nullptr;
+  ColDev* d_col = nullptr;
+  PairShape shape;
+  bool mixed = false;
+  bool adjoint = false;
+  struct ItemSet {
+    int4* d[4] = {nullptr, nullptr, nullptr, nullptr};
+    int cnt[4] = {0, 0, 0, 0};
+    double pair_cols = 0, flops = 0, pairs1 = 0;
+    bool built = false;
+  } sets[3];
+  struct Circ {
+    int64_t n;
+    int64_t* offs;
+    int nvec;
+    double2* tw;
+  };
+  std::vector<Circ> circ;
+  bool circ_built = false;
 };
 
 void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint) {
@@ -161,14 +204,236 @@ void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint) {
   }
 }
 
-void validate_inputs(gnk_ctx* c, const Prep& P, bool adjoint, const double* x, int nrhs) {
+// Single-domain split plan: the split count whose waves fill whole rounds of
+// the wave slots best (fewest splits within 1% of the best), at least 32
+// sources per workgroup, at most 64 splits.
+void plan_single(gnk_ctx* c, int64_t N, int align, int* tpt, int* chunk, int* splits) {
+  const int64_t slots = slots_of(c);
+  int t = ((N + 127) / 128) * 64 >= slots ? 2 : 1;
+  if (const char* s = getenv("GNK_CAUCHY_TPT")) t = atoi(s) == 2 ? 2 : 1;
+  const int64_t tiles = (N + 64 * t - 1) / (64 * t);
+  const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, N / 32));
+  std::vector<double> score((size_t)max_s + 1, 0.0);
+  double best = 0.0;
+  for (int64_t s = 1; s <= max_s; ++s) {
+    const double rounds = (double)(tiles * s * 4) / (double)slots;
+    score[s] = rounds / std::ceil(rounds) * std::min(1.0, rounds);
+    best = std::max(best, score[s]);
+  }
+  int64_t bs = 1;
+  while (bs < max_s && score[bs] < best - 0.01) ++bs;
+  if (const char* s = getenv("GNK_CAUCHY_SPLITS")) bs = std::max(1, atoi(s));
+  int64_t ch = (N + bs - 1) / bs;
+  ch = (ch + align - 1) / align * align;
+  *tpt = t;
+  *chunk = (int)ch;
+  *splits = (int)((N + ch - 1) / ch);
+}
+
+// Builds the batch tables and workspace. doms: host array; ncols: columns per
+// domain; col_off: flat offset of column 0 of each domain (the columns of a
+// domain are contiguous, N_d apart).
+void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const int* ncols,
+                 const std::vector<int64_t>& col_off, int64_t T, bool adjoint, bool mixed, const PairShape& shape,
+                 int64_t force_N = 0) {
+  B = Batch();
+  B.ndom = ndom;
+  B.T = T;
+  B.mixed = mixed;
+  B.adjoint = adjoint;
+  B.shape = shape;
+  const int align = mixed ? 256 : 16;
+  int64_t Ntot = 0, rec_total = 0, part_total = 0, sb_total = 0, tb_total = 0;
+  B.dom.resize(ndom);
+  int c0 = 0;
+  for (int d = 0; d < ndom; ++d) {
+    check_domain(c, &doms[d], adjoint);
+    DomDev& D = B.dom[d];
+    memset(&D, 0, sizeof D);
+    D.eta = static_cast<const double2*>(doms[d].eta);
+    D.etap = static_cast<const double2*>(doms[d].etap);
+    D.etapp = static_cast<const double2*>(doms[d].etapp);
+    D.A = static_cast<const double2*>(doms[d].A);
+    D.Ap = static_cast<const double2*>(doms[d].Ap);
+    D.N = force_N ? (int)force_N : (int)(doms[d].m1 * doms[d].n);
+    D.n = (int)doms[d].n;
+    D.m1 = (int)doms[d].m1;
+    D.ncols = ncols[d];
+    D.c0 = c0;
+    D.c = doms[d].c;
+    c0 += ncols[d];
+    if (ndom == 1 && shape.chunk == 0) {
+      int t, ch, sp;
+      plan_single(c, D.N, align, &t, &ch, &sp);
+      B.shape.tpt = t;
+      D.chunk = ch;
+      D.splits = sp;
+    } else {
+      int64_t ch = std::max(align, shape.chunk > 0 ? shape.chunk : 2048);
+      ch = (ch + align - 1) / align * align;
+      const int64_t Nr = ((int64_t)D.N + align - 1) / align * align;
+      ch = std::min(ch, Nr);
+      D.chunk = (int)ch;
+      D.splits = (int)((D.N + ch - 1) / ch);
+    }
+    B.maxN = std::max(B.maxN, D.N);
+    B.maxm1 = std::max(B.maxm1, D.m1);
+    Ntot += D.N;
+    rec_total += (int64_t)D.N * (D.ncols + 2);
+    part_total += (int64_t)D.splits * (D.ncols + 1) * D.N;
+    sb_total += (D.N + 63) / 64;
+    tb_total += (D.N + 63) / 64;
+  }
+  B.ncol = c0;
+  double2* rho = ws<double2>(c, "b_rho", Ntot);
+  double* dB = ws<double>(c, "b_dB", Ntot);
+  double* dD = ws<double>(c, "b_dD", Ntot);
+  double* ev = adjoint ? ws<double>(c, "b_e", Ntot) : nullptr;
+  double2* rec = ws<double2>(c, "b_rec", rec_total);
+  float2* rec32 = mixed ? ws<float2>(c, "b_rec32", rec_total) : nullptr;
+  double2* parts = ws<double2>(c, "b_parts", part_total);
+  double4* sb = mixed ? ws<double4>(c, "b_sb", sb_total) : nullptr;
+  double4* tb = mixed ? ws<double4>(c, "b_tb", tb_total) : nullptr;
+  double theta = 1.0;
+  if (const char* e = getenv("GNK_MIXED_THETA")) theta = atof(e);
+  int64_t on = 0, orc = 0, op = 0, osb = 0, otb = 0;
+  for (int d = 0; d < ndom; ++d) {
+    DomDev& D = B.dom[d];
+    D.rho = rho + on;
+    D.dB = dB + on;
+    D.dD = dD + on;
+    D.e = ev ? ev + on : nullptr;
+    D.rec = rec + orc;
+    D.rec32 = rec32 ? rec32 + orc : nullptr;
+    D.parts = parts + op;
+    D.sb = sb ? sb + osb : nullptr;
+    D.tb = tb ? tb + otb : nullptr;
+    D.far2 = (1.0 + theta) * (1.0 + theta);
+    on += D.N;
+    orc += (int64_t)D.N * (D.ncols + 2);
+    op += (int64_t)D.splits * (D.ncols + 1) * D.N;
+    osb += (D.N + 63) / 64;
+    otb += (D.N + 63) / 64;
+    for (int r = 0; r < D.ncols; ++r) B.col.push_back(ColDev{d, r, col_off[d] + (int64_t)r * D.N});
+  }
+  B.d_dom = upload(c, "b_dom", B.dom);
+  B.d_col = upload(c, "b_col", B.col);
+  if (mixed) {
+    HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64, false, c->stream));
+    HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64 * B.shape.tpt, true, c->stream));
+  }
+}
+
+// Work items of a pattern: every domain (largest first), column group, target
+// tile and source split; grouped by column-group width.
+void build_items(gnk_ctx* c, Batch& B, int p) {
+  auto& S = B.sets[p];
+  if (S.built) return;
+  const int lead = kLead[p], data = kData[p];
+  std::vector<int> order(B.ndom);
+  for (int d = 0; d < B.ndom; ++d) order[d] = d;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.dom[a].N > B.dom[b].N; });
+  std::vector<int4> lists[4];
+  S.pair_cols = S.flops = S.pairs1 = 0;
+  for (int d : order) {
+    const DomDev& D = B.dom[d];
+    const int wcols = lead + data * D.ncols;
+    const int tile = 64 * B.shape.tpt;
+    const int tiles = (D.N + tile - 1) / tile;
+    const double pairs = (double)D.N * (double)(D.N - 1);
+    S.pair_cols += pairs * wcols;
+    S.flops += pairs * (16.0 + 8.0 * (wcols - 1));
+    if (wcols == 1) S.pairs1 += pairs;
+    int r0 = 0;
+    while (r0 < wcols) {
+      int wi = 3;
+      for (int k = 0; k < 4; ++k)
+        if (kWidths[k] <= wcols - r0) {
+          wi = k;
+          break;
+        }
+      for (int t = 0; t < tiles; ++t)
+        for (int g = 0; g < D.splits; ++g) lists[wi].push_back(make_int4(d, t, g, r0));
+      r0 += kWidths[wi];
+    }
+  }
+  for (int k = 0; k < 4; ++k) {
+    S.cnt[k] = (int)lists[k].size();
+    S.d[k] = upload(c, "b_items" + std::to_string(p) + "_" + std::to_string(k), lists[k]);
+  }
+  S.built = true;
+}
+
+hipEvent_t pool_event(gnk_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(c, hipEventCreate(&e));
+  return e;
+}
+
+// All Cauchy sums of a pattern for the batch (one launch per column-group width).
+void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
+  build_items(c, B, p);
+  auto& S = B.sets[p];
+  if (mixed) HIPCHK(c, launch_records32(B.d_dom, B.ndom, B.maxN, kLead[p], kData[p], c->stream));
+  gnk_ctx::ProfRec pr{};
+  if (c->prof) {
+    pr = gnk_ctx::ProfRec{pool_event(c), pool_event(c), S.pair_cols, S.flops, S.pairs1, mixed,
+                          S.pairs1 > 0 && S.pairs1 == S.pair_cols};
+    HIPCHK(c, hipEventRecord(pr.a, c->stream));
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (!S.cnt[k]) continue;
+    const int grid = B.shape.persistent > 0 ? std::min(S.cnt[k], B.shape.persistent) : S.cnt[k];
+    HIPCHK(c, launch_pairs(B.d_dom, S.d[k], S.cnt[k], kWidths[k], B.shape.tpt, kLead[p], kData[p], mixed, active,
+                           grid, c->stream));
+  }
+  if (c->prof) {
+    HIPCHK(c, hipEventRecord(pr.b, c->stream));
+    c->prof_pending.push_back(pr);
+  }
+}
+
+void build_circ(gnk_ctx* c, Batch& B) {
+  if (B.circ_built) return;
+  std::map<int64_t, std::vector<int64_t>> byn;
+  for (const ColDev& C : B.col) {
+    const DomDev& D = B.dom[C.d];
+    for (int k = 0; k < D.m1; ++k) byn[D.n].push_back(C.off + (int64_t)k * D.n);
+  }
+  for (auto& kv : byn) {
+    const int64_t n = kv.first;
+    const std::string tn = "tw" + std::to_string(n);
+    const size_t cnt = circulant_uses_fft(n) ? (size_t)n / 2 : (size_t)(n + 1) / 2;
+    double2* tw = ws<double2>(c, tn, cnt + 1);
+    if (!c->tw_ready[n]) {
+      HIPCHK(c, launch_twiddles(tw, n, c->stream));
+      c->tw_ready[n] = 1;
+    }
+    int64_t* offs = upload(c, "circ" + std::to_string(n), kv.second);
+    B.circ.push_back(Batch::Circ{n, offs, (int)kv.second.size(), tw});
+  }
+  B.circ_built = true;
+}
+
+void circulant(gnk_ctx* c, Batch& B, const double* x, double* y, double sign) {
+  build_circ(c, B);
+  for (auto& ci : B.circ) HIPCHK(c, launch_circulant(x, y, ci.offs, ci.nvec, ci.n, sign, ci.tw, c->stream));
+}
+
+dim3 node_grid(const Batch& B) { return dim3(nblocks(B.maxN), (unsigned)B.ndom); }
+dim3 col_grid(const Batch& B) { return dim3(nblocks(B.maxN), (unsigned)B.ncol); }
+
+void validate(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
   int* flags = ws<int>(c, "flags", 1);
   HIPCHK(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
-  k_validate<<<nblocks(P.N), kT, 0, c->stream>>>(P.eta, P.etap, P.A, adjoint ? P.etapp : nullptr,
-                                                  adjoint ? P.Ap : nullptr, (int)P.N, adjoint ? 1 : 0, flags);
+  k_validate<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, B.adjoint ? 1 : 0, flags);
   LAUNCHCHK(c);
-  if (x) {
-    const int64_t len = P.N * nrhs;
+  if (x && len > 0) {
     k_check_finite<<<nblocks(len), kT, 0, c->stream>>>(x, len, flags);
     LAUNCHCHK(c);
   }
@@ -189,191 +454,74 @@ void validate_inputs(gnk_ctx* c, const Prep& P, bool adjoint, const double* x, i
   }
 }
 
-Prep make_prep(gnk_ctx* c, const gnk_domain* d, bool adjoint) {
-  Prep P;
-  P.m1 = d->m1;
-  P.n = d->n;
-  P.N = d->m1 * d->n;
-  P.eta = static_cast<const double2*>(d->eta);
-  P.etap = static_cast<const double2*>(d->etap);
-  P.etapp = static_cast<const double2*>(d->etapp);
-  P.A = static_cast<const double2*>(d->A);
-  P.Ap = static_cast<const double2*>(d->Ap);
-  P.c = d->c;
-  P.plan = plan_cauchy(P.N, 1, c->num_cu);
-  (void)adjoint;
-  return P;
-}
-
-double2* cauchy_parts(gnk_ctx* c, const Prep& P, int ncols) {
-  return ws<double2>(c, "parts", (size_t)P.plan.splits * ncols * P.N);
-}
-
-hipEvent_t pool_event(gnk_ctx* c) {
-  if (!c->ev_pool.empty()) {
-    hipEvent_t e = c->ev_pool.back();
-    c->ev_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e;
-  HIPCHK(c, hipEventCreate(&e));
-  return e;
-}
-
-// One Cauchy-sum launch (all column groups), timed when profiling is on.
-void cauchy(gnk_ctx* c, const double2* rec, int64_t N, int ncols, const CauchyPlan& plan, double2* parts) {
-  if (!c->prof) {
-    HIPCHK(c, launch_cauchy_fp64(rec, N, ncols, plan, parts, c->stream));
-    return;
-  }
-  gnk_ctx::ProfRec r{pool_event(c), pool_event(c), N, ncols, false};
-  HIPCHK(c, hipEventRecord(r.a, c->stream));
-  HIPCHK(c, launch_cauchy_fp64(rec, N, ncols, plan, parts, c->stream));
-  HIPCHK(c, hipEventRecord(r.b, c->stream));
-  c->prof_pending.push_back(r);
-}
-
-void cauchy_mixed(gnk_ctx* c, const MixedArgs& m, int64_t N, int ncols, const CauchyPlan& plan, double2* parts) {
-  if (!c->prof) {
-    HIPCHK(c, launch_cauchy_mixed(m, N, ncols, plan, parts, c->stream));
-    return;
-  }
-  gnk_ctx::ProfRec r{pool_event(c), pool_event(c), N, ncols, true};
-  HIPCHK(c, hipEventRecord(r.a, c->stream));
-  HIPCHK(c, launch_cauchy_mixed(m, N, ncols, plan, parts, c->stream));
-  HIPCHK(c, hipEventRecord(r.b, c->stream));
-  c->prof_pending.push_back(r);
-}
-
-void ensure_twiddles(gnk_ctx* c, Prep& P) {
-  const size_t cnt = circulant_uses_fft(P.n) ? (size_t)P.n / 2 : (size_t)(P.n + 1) / 2;
-  P.tw = ws<double2>(c, "twiddle", cnt + 1);
-  if (c->tw_n != P.n) {
-    HIPCHK(c, launch_twiddles(P.tw, P.n, c->stream));
-    c->tw_n = P.n;
-  }
-}
-
-// S = E w for one complex column w (setup products)
-double2* cauchy_single(gnk_ctx* c, const Prep& P, const double2* w) {
-  double2* rec = ws<double2>(c, "rec", (size_t)P.N * 2);
-  k_pack_records<<<nblocks(P.N), kT, 0, c->stream>>>(P.eta, w, (int)P.N, 1, rec);
+// rho, and diag(B1), diag(D1) from S = E(rho) (leading column only)
+void setup_diag(gnk_ctx* c, Batch& B) {
+  k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
   LAUNCHCHK(c);
-  double2* parts = cauchy_parts(c, P, 1);
-  cauchy(c, rec, P.N, 1, P.plan, parts);
-  return parts;
-}
-
-// rho = eta'/A and, from S = E(rho), diag(B1) and diag(D1)
-void setup_fbie(gnk_ctx* c, Prep& P) {
-  P.rho = ws<double2>(c, "rho", P.N);
-  P.dB = ws<double>(c, "dB", P.N);
-  P.dD = ws<double>(c, "dD", P.N);
-  k_rho<<<nblocks(P.N), kT, 0, c->stream>>>(P.etap, P.A, P.rho, (int)P.N);
+  k_lead_records<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, C_RHO);
   LAUNCHCHK(c);
-  double2* parts = cauchy_single(c, P, P.rho);
-  k_diag_fbie<<<nblocks(P.N), kT, 0, c->stream>>>(parts, P.plan.splits, 1, P.A, (int)P.N, 2.0 / P.n, P.dB,
-                                                   P.dD);
+  pairs(c, B, P_LEAD, false, nullptr);
+  k_diag_fbie<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, 1, 0);
   LAUNCHCHK(c);
 }
 
 // e of eq. (e:bve) from S = E eta'
-void setup_fbiead(gnk_ctx* c, Prep& P) {
-  if (!P.rho) {
-    P.rho = ws<double2>(c, "rho", P.N);
-    k_rho<<<nblocks(P.N), kT, 0, c->stream>>>(P.etap, P.A, P.rho, (int)P.N);
-    LAUNCHCHK(c);
-  }
-  P.e = ws<double>(c, "evec", P.N);
-  double2* parts = cauchy_single(c, P, P.etap);
-  k_evec<<<nblocks(P.N), kT, 0, c->stream>>>(parts, P.plan.splits, P.etap, P.etapp, P.A, P.Ap, (int)P.N,
-                                              2.0 / P.n, (double)P.c, P.e);
+void setup_evec(gnk_ctx* c, Batch& B) {
+  k_lead_records<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, C_ETAP);
+  LAUNCHCHK(c);
+  pairs(c, B, P_LEAD, false, nullptr);
+  k_evec<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
   LAUNCHCHK(c);
 }
 
-// tile bounds for the mixed-precision pair kernel
-void setup_mixed(gnk_ctx* c, Prep& P) {
-  P.mplan = plan_cauchy(P.N, 1, c->num_cu, 256);
-  const int ttile = 64 * P.mplan.tpt;
-  P.sb = ws<double4>(c, "sbnd", (size_t)(P.N + 63) / 64);
-  P.tb = ws<double4>(c, "tbnd", (size_t)(P.N + ttile - 1) / ttile);
-  HIPCHK(c, launch_tile_bounds(P.eta, P.N, 0, 64, P.sb, c->stream));
-  HIPCHK(c, launch_tile_bounds(P.eta, P.N, 0, ttile, P.tb, c->stream));
-  double theta = 1.0;
-  if (const char* e = getenv("GNK_MIXED_THETA")) theta = atof(e);
-  P.far2 = (1.0 + theta) * (1.0 + theta);
-}
-
 // --------------------------------------------------------- operator product
-// y = op(x) for nrhs columns. scale/xout: optional per-column scaling of x
-// written back (GMRES normalisation); active: optional per-column GMRES mask.
+// y = op(x) for every column of the batch. scale/xout: optional per-column
+// scaling of x written back (GMRES normalisation); active: optional mask.
 struct ApplyArgs {
   const double* scale = nullptr;
   double* xout = nullptr;
   const int* active = nullptr;
-  bool mixed = false;      // FP32 far tiles (needs setup_mixed)
+  bool mixed = false;      // FP32 far tiles (batch built with mixed records)
 };
 
-void apply_op(gnk_ctx* c, Prep& P, int op, const double* x, int nrhs, double* y, const ApplyArgs& a = {}) {
-  const double two_n = 2.0 / (double)P.n;
-  const bool need_mean = (op == GNK_OP_GB || op == GNK_OP_GB_T);
+void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const ApplyArgs& a = {}) {
   if (op == GNK_OP_LHAT) {
-    ensure_twiddles(c, P);
-    HIPCHK(c, hipMemsetAsync(y, 0, sizeof(double) * P.N * nrhs, c->stream));
-    HIPCHK(c, launch_circulant(x, y, P.m1, P.n, nrhs, 1.0, P.tw, c->stream));
+    k_axpby<<<nblocks(B.T), kT, 0, c->stream>>>(0.0, x, 0.0, y, B.T);
+    LAUNCHCHK(c);
+    circulant(c, B, x, y, 1.0);
     return;
   }
-  // weight factor C: rho for B x, D x, B^T... (see eqs. (e:(I-B)x), (e:hD-bt), (e:BTx))
-  const double2* Cw = nullptr;
-  const double2* Cout = nullptr;
+  const bool need_mean = (op == GNK_OP_GB || op == GNK_OP_GB_T);
+  int cw = C_RHO, cout = C_A, dsel = D_NONE;
   double a0 = 0.0, dsign = 0.0, cI = 0.0, cR = 0.0;
-  const double* dg = nullptr;
   switch (op) {
     case GNK_OP_FB:   // 2x + diag(B1) x - B x,  B x = -(2/n) Im(A E(rho x))
-      Cw = P.rho; Cout = P.A; a0 = 2.0; dg = P.dB; dsign = 1.0; cI = two_n; break;
+      cw = C_RHO; cout = C_A; a0 = 2.0; dsel = D_B; dsign = 1.0; cI = 1.0; break;
     case GNK_OP_FC:   // D x - diag(D1) x (+ Lhat x),  D x = -(2/n) Re(A E(rho x))
-      Cw = P.rho; Cout = P.A; dg = P.dD; dsign = -1.0; cR = -two_n; break;
+      cw = C_RHO; cout = C_A; dsel = D_D; dsign = -1.0; cR = -1.0; break;
     case GNK_OP_GB:   // e x + B^T x + Phat x,  B^T x = (2/n) Im(rho E(A x))
-      Cw = P.A; Cout = P.rho; dg = P.e; dsign = 1.0; cI = two_n; break;
+      cw = C_A; cout = C_RHO; dsel = D_E; dsign = 1.0; cI = 1.0; break;
     case GNK_OP_FB_T: // 2x + diag(B1) x - B^T x
-      Cw = P.A; Cout = P.rho; a0 = 2.0; dg = P.dB; dsign = 1.0; cI = -two_n; break;
+      cw = C_A; cout = C_RHO; a0 = 2.0; dsel = D_B; dsign = 1.0; cI = -1.0; break;
     case GNK_OP_FC_T: // D^T x - diag(D1) x - Lhat x,  D^T x = (2/n) Re(rho E(A x))
-      Cw = P.A; Cout = P.rho; dg = P.dD; dsign = -1.0; cR = two_n; break;
+      cw = C_A; cout = C_RHO; dsel = D_D; dsign = -1.0; cR = 1.0; break;
     case GNK_OP_GB_T: // e x + B x + Phat x
-      Cw = P.rho; Cout = P.A; dg = P.e; dsign = 1.0; cI = -two_n; break;
+      cw = C_RHO; cout = C_A; dsel = D_E; dsign = 1.0; cI = -1.0; break;
     default:
       set_err(c, "unknown operator %d", op);
       throw Fail{GNK_ERR_ARG};
   }
-  double2* rec = ws<double2>(c, "rec", (size_t)P.N * (nrhs + 1));
-  double* mean = need_mean ? ws<double>(c, "mean", (size_t)P.m1 * nrhs) : nullptr;
-  dim3 gw((unsigned)P.m1, (unsigned)nrhs);
-  k_weights<<<gw, kT, 0, c->stream>>>(P.eta, Cw, x, a.scale, a.active, a.xout, rec, (int)P.N, (int)P.n, (int)P.m1,
-                                      nrhs + 1, 0, 0, mean);
+  const int M = B.maxm1;
+  double* mean = need_mean ? ws<double>(c, "mean", (size_t)B.ncol * M) : nullptr;
+  k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(B.d_dom, B.d_col, cw, x, a.scale,
+                                                                            a.active, a.xout, 0, mean, M);
   LAUNCHCHK(c);
   const double* xin = a.xout ? a.xout : x;
-  double2* parts;
-  int splits;
-  if (a.mixed) {
-    float2* rec32 = ws<float2>(c, "rec32", (size_t)P.N * (nrhs + 1));
-    HIPCHK(c, launch_records32(rec, P.sb, P.N, nrhs, rec32, c->stream));
-    parts = ws<double2>(c, "parts", (size_t)P.mplan.splits * nrhs * P.N);
-    splits = P.mplan.splits;
-    MixedArgs m{rec, rec32, P.sb, P.tb, P.far2};
-    cauchy_mixed(c, m, P.N, nrhs, P.mplan, parts);
-  } else {
-    parts = cauchy_parts(c, P, nrhs);
-    splits = P.plan.splits;
-    cauchy(c, rec, P.N, nrhs, P.plan, parts);
-  }
-  dim3 ge(nblocks(P.N), (unsigned)nrhs);
-  k_epilogue<<<ge, kT, 0, c->stream>>>(parts, splits, nrhs, 0, xin, Cout, dg, a0, dsign, cI, cR, mean,
-                                       (int)P.n, (int)P.m1, a.active, y, (int)P.N);
+  pairs(c, B, P_GM, a.mixed, a.active);
+  k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, xin, cout, dsel, a0, dsign, cI, cR, mean, M,
+                                                a.active, 0, y);
   LAUNCHCHK(c);
-  if (op == GNK_OP_FC || op == GNK_OP_FC_T) {
-    ensure_twiddles(c, P);
-    HIPCHK(c, launch_circulant(xin, y, P.m1, P.n, nrhs, op == GNK_OP_FC ? 1.0 : -1.0, P.tw, c->stream));
-  }
+  if (op == GNK_OP_FC || op == GNK_OP_FC_T) circulant(c, B, xin, y, op == GNK_OP_FC ? 1.0 : -1.0);
 }
 
 // ------------------------------------------------------------------ GMRES
@@ -382,84 +530,88 @@ struct GmresOut {
   bool all_converged = false;
 };
 
-// Restarted GMRES. With `mixed`, the Arnoldi products switch to the
-// mixed-precision pair kernel once the residual estimate of every column is
-// below o.inner_tol (relaxed products: an error of relative size e in a
-// product made when the residual is r perturbs the final residual by about
-// e*r, so FP32 far tiles are harmless once r <= tol / e). The residual that
-// starts every cycle is always recomputed with the FP64 product, so each
-// restart is a step of FP64 iterative refinement.
-GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk_opts& o, double* x,
-               bool mixed = false) {
+// Restarted GMRES on every column of the batch (x, b: flat). With `mixed`,
+// the Arnoldi products switch to the mixed-precision pair kernel once the
+// residual estimate of every column is below o.inner_tol (relaxed products:
+// an error of relative size e in a product made when the residual is r
+// perturbs the final residual by about e*r, so FP32 far tiles are harmless
+// once r <= tol / e). The residual that starts every cycle is always
+// recomputed with FP64 products, so each restart is a step of FP64 iterative
+// refinement.
+GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o, double* x, bool mixed = false) {
   const ApplyArgs am;   // FP64 products for every true residual
-  const int64_t N = P.N;
+  const int ncol = B.ncol;
+  const int64_t T = B.T;
   const int restart = o.restart;
-  const int ldp = kMaxRestart + 1;
+  const int ldp = restart + 1;
   // vector-kernel blocking: 256..kMaxChunk elements per block, about 256 blocks
-  const int per_blk = (int)std::max<int64_t>(kT, std::min<int64_t>(kMaxChunk, (N + 255) / 256));
-  const int nblk = (int)((N + per_blk - 1) / per_blk);
+  const int per_blk = (int)std::max<int64_t>(kT, std::min<int64_t>(kMaxChunk, ((int64_t)B.maxN + 255) / 256));
+  const int nblk = (B.maxN + per_blk - 1) / per_blk;
 
-  double* V = ws<double>(c, "V", (size_t)(restart + 1) * nrhs * N);
-  double* P1 = ws<double>(c, "gmP1", (size_t)nrhs * nblk * ldp);
-  double* P2 = ws<double>(c, "gmP2", (size_t)nrhs * nblk * ldp);
+  double* V = ws<double>(c, "V", (size_t)(restart + 1) * T);
+  double* P1 = ws<double>(c, "gmP1", (size_t)ncol * nblk * ldp);
+  double* P2 = ws<double>(c, "gmP2", (size_t)ncol * nblk * ldp);
   GmresState st;
   st.ldh = restart + 1;
   st.hstride = st.ldh * restart;
-  double* dbl = ws<double>(c, "gmdbl", (size_t)nrhs * (4 + st.hstride + 2 * kMaxRestart + (kMaxRestart + 1) +
-                                                      kMaxRestart));
-  int* ints = ws<int>(c, "gmint", (size_t)nrhs * 5 + 1);
+  double* dbl = ws<double>(c, "gmdbl", (size_t)ncol * (4 + st.hstride + 2 * kMaxRestart + (kMaxRestart + 1) +
+                                                     kMaxRestart));
+  int* ints = ws<int>(c, "gmint", (size_t)ncol * 5 + 1);
   {
     double* q = dbl;
-    st.bnorm = q; q += nrhs;
-    st.true_relres = q; q += nrhs;
-    st.relres = q; q += nrhs;
-    st.invbeta = q; q += nrhs;
-    st.H = q; q += (size_t)nrhs * st.hstride;
-    st.cs = q; q += (size_t)nrhs * kMaxRestart;
-    st.sn = q; q += (size_t)nrhs * kMaxRestart;
-    st.g = q; q += (size_t)nrhs * (kMaxRestart + 1);
+    st.bnorm = q; q += ncol;
+    st.true_relres = q; q += ncol;
+    st.relres = q; q += ncol;
+    st.invbeta = q; q += ncol;
+    st.H = q; q += (size_t)ncol * st.hstride;
+    st.cs = q; q += (size_t)ncol * kMaxRestart;
+    st.sn = q; q += (size_t)ncol * kMaxRestart;
+    st.g = q; q += (size_t)ncol * (kMaxRestart + 1);
     st.y = q;
     int* r = ints;
-    st.active = r; r += nrhs;
-    st.converged = r; r += nrhs;
-    st.kdim = r; r += nrhs;
-    st.inner_it = r; r += nrhs;
+    st.active = r; r += ncol;
+    st.converged = r; r += ncol;
+    st.kdim = r; r += ncol;
+    st.inner_it = r; r += ncol;
     st.live = r;
   }
-  const unsigned tb = (unsigned)std::min(1024, ((nrhs + 63) / 64) * 64);
-  k_gmres_init<<<1, tb, 0, c->stream>>>(nrhs, st);
+  const unsigned cb = nblocks(ncol, 256);
+  k_gmres_init<<<cb, 256, 0, c->stream>>>(ncol, st);
   LAUNCHCHK(c);
-  dim3 gv((unsigned)nblk, (unsigned)nrhs);
-  k_norm_partial<<<gv, kT, 0, c->stream>>>(b, (int)N, per_blk, P1, ldp);
+  dim3 gv((unsigned)nblk, (unsigned)ncol);
+  k_norm_partial<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, b, per_blk, P1, ldp);
   LAUNCHCHK(c);
-  k_bnorm<<<1, tb, 0, c->stream>>>(P1, nblk, ldp, nrhs, st);
+  k_bnorm<<<cb, 256, 0, c->stream>>>(P1, nblk, ldp, ncol, st);
   LAUNCHCHK(c);
 
+  auto cycle_start = [&](const double* partial) {
+    k_zero_int<<<1, 1, 0, c->stream>>>(st.live);
+    LAUNCHCHK(c);
+    k_cycle_start<<<cb, 256, 0, c->stream>>>(partial, nblk, ldp, ncol, o.tol, st);
+    LAUNCHCHK(c);
+  };
   // r0 = b - A x0 into V_0
-  const size_t colbytes = sizeof(double) * N * nrhs;
+  const size_t bytes = sizeof(double) * T;
   if (o.x0) {
-    if (o.x0 != x) HIPCHK(c, hipMemcpyAsync(x, o.x0, colbytes, hipMemcpyDeviceToDevice, c->stream));
-    apply_op(c, P, op, x, nrhs, V, am);
-    k_residual<<<gv, kT, 0, c->stream>>>(b, V, (int)N, per_blk, P1, ldp);
+    if (o.x0 != x) HIPCHK(c, hipMemcpyAsync(x, o.x0, bytes, hipMemcpyDeviceToDevice, c->stream));
+    apply_op(c, B, op, x, V, am);
+    k_residual<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, b, V, per_blk, P1, ldp);
   } else {
-    HIPCHK(c, hipMemsetAsync(x, 0, colbytes, c->stream));
-    HIPCHK(c, hipMemcpyAsync(V, b, colbytes, hipMemcpyDeviceToDevice, c->stream));
-    k_norm_partial<<<gv, kT, 0, c->stream>>>(V, (int)N, per_blk, P1, ldp);
+    HIPCHK(c, hipMemsetAsync(x, 0, bytes, c->stream));
+    HIPCHK(c, hipMemcpyAsync(V, b, bytes, hipMemcpyDeviceToDevice, c->stream));
+    k_norm_partial<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, per_blk, P1, ldp);
   }
   LAUNCHCHK(c);
-  k_cycle_start<<<1, tb, 0, c->stream>>>(P1, nblk, ldp, nrhs, o.tol, st);
-  LAUNCHCHK(c);
+  cycle_start(P1);
 
-  std::vector<int> outer(nrhs, 0);
-  std::vector<int> conv(nrhs, 0);
-  std::vector<int> mixed_cycles(nrhs, 0);
+  std::vector<int> outer(ncol, 0), conv(ncol, 0), mixed_steps(ncol, 0);
   bool mixed_now = false;
   if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(int) * (kMaxRestart + 1), 0));
-  if (c->pinned_rel_n < (size_t)nrhs * kMaxRestart) {
+  if (c->pinned_rel_n < (size_t)ncol * kMaxRestart) {
     if (c->pinned_rel) HIPCHK(c, hipHostFree(c->pinned_rel));
     c->pinned_rel = nullptr;
-    HIPCHK(c, hipHostMalloc((void**)&c->pinned_rel, sizeof(double) * nrhs * kMaxRestart, 0));
-    c->pinned_rel_n = (size_t)nrhs * kMaxRestart;
+    HIPCHK(c, hipHostMalloc((void**)&c->pinned_rel, sizeof(double) * ncol * kMaxRestart, 0));
+    c->pinned_rel_n = (size_t)ncol * kMaxRestart;
   }
   while ((int)c->step_ev.size() < kMaxRestart) {
     hipEvent_t e;
@@ -469,40 +621,40 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
   for (int cyc = 0; cyc < o.maxit; ++cyc) {
     int live = 0;
     HIPCHK(c, hipMemcpyAsync(&live, st.live, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(conv.data(), st.converged, sizeof(int) * nrhs, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(conv.data(), st.converged, sizeof(int) * ncol, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (live == 0) break;
-    for (int r = 0; r < nrhs; ++r)
-      if (!conv[r]) {
-        outer[r] += 1;
-        if (mixed_now) mixed_cycles[r] += 1;
-      }
+    for (int q = 0; q < ncol; ++q)
+      if (!conv[q]) outer[q] += 1;
     // Arnoldi steps. The host looks one step behind the device: before
     // enqueuing step l+1 it waits for step l-1 and reads how many columns are
     // still iterating, so the queue never drains and at most one speculative
     // step runs (fully masked) after the last column stops.
     for (int l = 0; l < restart; ++l) {
-      double* vl = V + (size_t)l * nrhs * N;
-      double* w = V + (size_t)(l + 1) * nrhs * N;
+      double* vl = V + (size_t)l * T;
+      double* w = V + (size_t)(l + 1) * T;
       ApplyArgs aa;
       aa.scale = st.invbeta;
       aa.xout = vl;
       aa.active = st.active;
       aa.mixed = mixed && mixed_now;
-      apply_op(c, P, op, vl, nrhs, w, aa);
-      k_gs_dot<<<gv, kT, 0, c->stream>>>(V, l + 1, w, (int)N, nrhs, per_blk, st.active, P1, ldp);
+      if (aa.mixed)
+        for (int q = 0; q < ncol; ++q)
+          if (!conv[q]) mixed_steps[q] += 1;
+      apply_op(c, B, op, vl, w, aa);
+      k_gs_dot<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, l + 1, w, per_blk, st.active, P1, ldp);
       LAUNCHCHK(c);
-      k_gs_update<<<gv, kT, 0, c->stream>>>(V, l + 1, w, (int)N, nrhs, per_blk, st.active, P1, P2, ldp, st.H,
-                                            st.ldh, st.hstride, l, 0, 1);
+      k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, l + 1, w, per_blk, st.active, P1, P2, ldp, st,
+                                            l, 0, 1);
       LAUNCHCHK(c);
-      k_gs_update<<<gv, kT, 0, c->stream>>>(V, l + 1, w, (int)N, nrhs, per_blk, st.active, P2, P1, ldp, st.H,
-                                            st.ldh, st.hstride, l, 1, 0);
+      k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, l + 1, w, per_blk, st.active, P2, P1, ldp, st,
+                                            l, 1, 0);
       LAUNCHCHK(c);
-      k_arnoldi_finish<<<(unsigned)nrhs, 64, 0, c->stream>>>(P1, nblk, ldp, l, restart, o.tol, st);
+      k_arnoldi_finish<<<(unsigned)ncol, 64, 0, c->stream>>>(P1, nblk, ldp, l, restart, o.tol, st);
       LAUNCHCHK(c);
       HIPCHK(c, hipMemcpyAsync(c->pinned + l, st.live, sizeof(int), hipMemcpyDeviceToHost, c->stream));
       if (mixed && !mixed_now)
-        HIPCHK(c, hipMemcpyAsync(c->pinned_rel + (size_t)l * nrhs, st.relres, sizeof(double) * nrhs,
+        HIPCHK(c, hipMemcpyAsync(c->pinned_rel + (size_t)l * ncol, st.relres, sizeof(double) * ncol,
                                  hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipEventRecord(c->step_ev[l], c->stream));
       if (l >= 1) {
@@ -510,49 +662,49 @@ GmresOut gmres(gnk_ctx* c, Prep& P, int op, const double* b, int nrhs, const gnk
         if (c->pinned[l - 1] == 0) break;
         if (mixed && !mixed_now) {
           double mx = 0.0;
-          for (int r = 0; r < nrhs; ++r) mx = std::max(mx, c->pinned_rel[(size_t)(l - 1) * nrhs + r]);
+          for (int q = 0; q < ncol; ++q) mx = std::max(mx, c->pinned_rel[(size_t)(l - 1) * ncol + q]);
           if (mx <= o.inner_tol) mixed_now = true;
         }
       }
     }
-    k_backsolve<<<(unsigned)nrhs, 64, 0, c->stream>>>(st);
+    k_backsolve<<<(unsigned)ncol, 64, 0, c->stream>>>(st);
     LAUNCHCHK(c);
-    k_xupdate<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(V, x, (int)N, nrhs, st);
+    k_xupdate<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, x, st);
     LAUNCHCHK(c);
     // true residual of the new iterate (FP64 product) and the next cycle's start
-    apply_op(c, P, op, x, nrhs, V, am);
-    k_residual<<<gv, kT, 0, c->stream>>>(b, V, (int)N, per_blk, P1, ldp);
+    apply_op(c, B, op, x, V, am);
+    k_residual<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, b, V, per_blk, P1, ldp);
     LAUNCHCHK(c);
-    k_cycle_start<<<1, tb, 0, c->stream>>>(P1, nblk, ldp, nrhs, o.tol, st);
-    LAUNCHCHK(c);
+    cycle_start(P1);
     if (c->log) {
-      std::vector<double> tr(nrhs);
-      HIPCHK(c, hipMemcpyAsync(tr.data(), st.true_relres, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
+      std::vector<double> tr(ncol);
+      HIPCHK(c, hipMemcpyAsync(tr.data(), st.true_relres, sizeof(double) * ncol, hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
       double mx = 0;
       for (double v : tr) mx = std::max(mx, v);
-      fprintf(stderr, "[gnk] op %d cycle %d max true relres %.3e\n", op, cyc + 1, mx);
+      fprintf(stderr, "[gnk] op %d cycle %d max true relres %.3e%s\n", op, cyc + 1, mx,
+              mixed_now ? " (mixed products)" : "");
     }
   }
   GmresOut out;
-  out.info.resize(nrhs);
-  std::vector<double> rel(nrhs), trel(nrhs);
-  std::vector<int> inner(nrhs);
-  HIPCHK(c, hipMemcpyAsync(conv.data(), st.converged, sizeof(int) * nrhs, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(rel.data(), st.relres, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(trel.data(), st.true_relres, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(inner.data(), st.inner_it, sizeof(int) * nrhs, hipMemcpyDeviceToHost, c->stream));
+  out.info.resize(ncol);
+  std::vector<double> rel(ncol), trel(ncol);
+  std::vector<int> inner(ncol);
+  HIPCHK(c, hipMemcpyAsync(conv.data(), st.converged, sizeof(int) * ncol, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(rel.data(), st.relres, sizeof(double) * ncol, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(trel.data(), st.true_relres, sizeof(double) * ncol, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(inner.data(), st.inner_it, sizeof(int) * ncol, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   out.all_converged = true;
-  for (int r = 0; r < nrhs; ++r) {
-    gnk_info& I = out.info[r];
-    I.flag = conv[r] ? 0 : 1;
-    I.outer_it = outer[r];
-    I.inner_it = inner[r];
-    I.refine_steps = mixed_cycles[r];
-    I.relres = rel[r];
-    I.true_relres = trel[r];
-    if (!conv[r]) out.all_converged = false;
+  for (int q = 0; q < ncol; ++q) {
+    gnk_info& I = out.info[q];
+    I.flag = conv[q] ? 0 : 1;
+    I.outer_it = outer[q];
+    I.inner_it = inner[q];
+    I.mixed_steps = mixed_steps[q];
+    I.relres = rel[q];
+    I.true_relres = trel[q];
+    if (!conv[q]) out.all_converged = false;
   }
   return out;
 }
@@ -564,19 +716,160 @@ gnk_opts resolve_opts(gnk_ctx* c, const gnk_opts* o) {
   r.tol = 1e-12;
   r.prec = GNK_FP64;
   r.inner_tol = 0.0;
-  r.max_refine = 0;
   r.x0 = nullptr;
   if (o) r = *o;
-  // mixed products once the residual estimate is below tol / 1e-8 (their
-  // relative error is below 1e-8), but not before 1e-4
-  if (r.inner_tol <= 0) r.inner_tol = std::min(1e-4, r.tol * 1e8);
   if (r.restart < 1 || r.restart > kMaxRestart || r.maxit < 1 || !(r.tol > 0.0) || r.tol >= 1.0 ||
       (r.prec != GNK_FP64 && r.prec != GNK_MIXED)) {
     set_err(c, "bad options: restart %d (1..%d), maxit %d (>=1), tol %g (0..1), prec %d", r.restart, kMaxRestart,
             r.maxit, r.tol, r.prec);
     throw Fail{GNK_ERR_ARG};
   }
+  // mixed products once the residual estimate is below tol / 1e-8 (their
+  // relative error is below 1e-8), but not before 1e-4
+  if (r.inner_tol <= 0) r.inner_tol = std::min(1e-4, r.tol * 1e8);
   return r;
+}
+
+// ------------------------------------------------------------- autotuner
+// Picks the pair-kernel launch shape (targets per lane, sources per workgroup,
+// persistent grid) for a batch by timing the Cauchy sums of one product per
+// candidate; results are cached per batch signature in the context and, with
+// GNK_TUNE_CACHE=path, in a text file ("key tpt chunk persistent" per line).
+std::string tune_key(const gnk_ctx* c, int ndom, const gnk_domain* doms, const int* ncols, bool mixed) {
+  std::vector<std::pair<int64_t, int>> v;
+  for (int d = 0; d < ndom; ++d) v.push_back({doms[d].m1 * doms[d].n, ncols[d]});
+  std::sort(v.begin(), v.end());
+  uint64_t h = 1469598103934665603ull;   // FNV-1a over the sorted (N, ncols) list
+  for (auto& p : v) {
+    h = (h ^ (uint64_t)p.first) * 1099511628211ull;
+    h = (h ^ (uint64_t)p.second) * 1099511628211ull;
+  }
+  std::ostringstream k;
+  k << "cu" << c->num_cu << (mixed ? "m" : "d") << "_" << v.size() << "_" << std::hex << h;
+  return k.str();
+}
+
+void load_tune_cache(gnk_ctx* c) {
+  if (c->tune_loaded) return;
+  c->tune_loaded = true;
+  const char* path = getenv("GNK_TUNE_CACHE");
+  if (!path) return;
+  std::ifstream f(path);
+  std::string key, rest;
+  while (f >> key && std::getline(f, rest)) c->tune[key] = rest;
+}
+
+void store_tune_cache(gnk_ctx* c, const std::string& key, const std::string& val) {
+  c->tune[key] = val;
+  if (const char* path = getenv("GNK_TUNE_CACHE")) {
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << val << "\n";
+  }
+}
+
+PairShape tuned_shape(gnk_ctx* c, int ndom, const gnk_domain* doms, const int* ncols, bool mixed,
+                      const double* x_flat, const std::vector<int64_t>& col_off, int64_t T) {
+  PairShape def;
+  def.tpt = 1;
+  def.chunk = 2048;
+  def.persistent = 0;
+  const char* env = getenv("GNK_TUNE");
+  if (env && atoi(env) == 0) return def;
+  load_tune_cache(c);
+  const std::string key = tune_key(c, ndom, doms, ncols, mixed);
+  auto it = c->tune.find(key);
+  if (it != c->tune.end()) {
+    std::istringstream s(it->second);
+    PairShape p;
+    if (s >> p.tpt >> p.chunk >> p.persistent) return p;
+  }
+  const int64_t slots = slots_of(c);
+  std::vector<PairShape> cand;
+  for (int tpt : {1, 2})
+    for (int chunk : {1024, 2048, 4096, 8192})
+      for (int pers : {0, (int)(slots / 4)}) cand.push_back(PairShape{tpt, chunk, pers});
+  hipEvent_t a, b;
+  HIPCHK(c, hipEventCreate(&a));
+  HIPCHK(c, hipEventCreate(&b));
+  double best = 1e300;
+  PairShape bestp = def;
+  const bool prof = c->prof;
+  c->prof = false;
+  for (const PairShape& p : cand) {
+    Batch B;
+    build_batch(c, B, ndom, doms, ncols, col_off, T, false, mixed, p);
+    k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
+    LAUNCHCHK(c);
+    k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
+        B.d_dom, B.d_col, C_RHO, x_flat, nullptr, nullptr, nullptr, 0, nullptr, B.maxm1);
+    LAUNCHCHK(c);
+    pairs(c, B, P_GM, mixed, nullptr);   // warm-up; builds the items
+    HIPCHK(c, hipEventRecord(a, c->stream));
+    pairs(c, B, P_GM, mixed, nullptr);
+    HIPCHK(c, hipEventRecord(b, c->stream));
+    HIPCHK(c, hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, a, b));
+    if (c->log) fprintf(stderr, "[gnk] tune tpt %d chunk %d grid %d: %.3f ms\n", p.tpt, p.chunk, p.persistent, ms);
+    if (ms < best) {
+      best = ms;
+      bestp = p;
+    }
+  }
+  c->prof = prof;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::ostringstream v;
+  v << bestp.tpt << " " << bestp.chunk << " " << bestp.persistent;
+  store_tune_cache(c, key, v.str());
+  return bestp;
+}
+
+// ----------------------------------------------------------- FBIE / FBIEad
+// gam, mu, h: flat vectors of the batch (h may be null).
+GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, double* mu, double* h) {
+  const int64_t T = B.T;
+  validate(c, B, gam, T);
+  k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
+  LAUNCHCHK(c);
+  // one launch for E(rho) (leading column) and E(rho gamma) (data columns)
+  k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
+      B.d_dom, B.d_col, C_RHO, gam, nullptr, nullptr, nullptr, 1, nullptr, B.maxm1);
+  LAUNCHCHK(c);
+  pairs(c, B, P_SETUP, false, nullptr);
+  k_diag_fbie<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, 1, 1);
+  LAUNCHCHK(c);
+  // b = -y = -(D - diag(D1) + Lhat) gamma
+  double* b = ws<double>(c, "rhs", T);
+  k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_D, 0.0, 1.0, 0.0, 1.0, nullptr, 0,
+                                                nullptr, 1, b);
+  LAUNCHCHK(c);
+  circulant(c, B, gam, b, -1.0);
+  // f_B(gamma) from the same sums, for h
+  double* fbg = nullptr;
+  if (h) {
+    fbg = ws<double>(c, "fbg", T);
+    k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_B, 2.0, 1.0, 1.0, 0.0, nullptr, 0,
+                                                  nullptr, 1, fbg);
+    LAUNCHCHK(c);
+  }
+  // (2I + diag(B1) - B) mu = b
+  GmresOut g = gmres(c, B, GNK_OP_FB, b, o, mu, o.prec == GNK_MIXED);
+  if (h) {
+    // h = [(D - diag(D1) + Lhat) mu - (2I + diag(B1) - B) gamma] / 2
+    apply_op(c, B, GNK_OP_FC, mu, h);
+    k_axpby<<<nblocks(T), kT, 0, c->stream>>>(-0.5, fbg, 0.5, h, T);
+    LAUNCHCHK(c);
+  }
+  return g;
+}
+
+GmresOut fbiead_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, double* mu) {
+  validate(c, B, gam, B.T);
+  k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
+  LAUNCHCHK(c);
+  setup_evec(c, B);
+  return gmres(c, B, GNK_OP_GB, gam, o, mu, o.prec == GNK_MIXED);
 }
 
 template <class F>
@@ -585,13 +878,24 @@ gnk_status guarded(gnk_ctx* c, F&& f) {
   c->err.clear();
   try {
     HIPCHK(c, hipSetDevice(c->device));
+    // uploads of the previous call have completed (every call ends synchronised)
+    c->host_keep.clear();
     return f();
   } catch (const Fail& e) {
+    (void)hipStreamSynchronize(c->stream);
     return e.st;
   } catch (const std::bad_alloc&) {
     set_err(c, "host allocation failed");
+    (void)hipStreamSynchronize(c->stream);
     return GNK_ERR_OOM;
   }
+}
+
+// Batch of one domain whose flat vectors are the caller's N x nrhs arrays.
+void single_batch(gnk_ctx* c, Batch& B, const gnk_domain* d, int nrhs, bool adjoint, bool mixed) {
+  check_domain(c, d, adjoint);
+  std::vector<int64_t> off{0};
+  build_batch(c, B, 1, d, &nrhs, off, d->m1 * d->n * (int64_t)nrhs, adjoint, mixed, PairShape{});
 }
 
 }  // namespace
@@ -601,7 +905,7 @@ using namespace gnk;
 
 extern "C" {
 
-const char* gnk_version(void) { return "gnk 0.1.0 (gfx950, FP64 direct Cauchy sums)"; }
+const char* gnk_version(void) { return "gnk 0.2.0 (gfx950, direct Cauchy sums, batched)"; }
 
 gnk_status gnk_create(gnk_ctx** out, int device) {
   if (!out) return GNK_ERR_ARG;
@@ -666,20 +970,19 @@ gnk_status gnk_profile_read(gnk_ctx* c, gnk_prof* out, int reset) {
     for (auto& r : c->prof_pending) {
       float ms = 0.f;
       HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
-      const double pairs = (double)r.N * (double)(r.N - 1);
       gnk_prof& A = c->prof_acc;
       A.launches += 1;
       A.ms += ms;
-      A.pair_cols += pairs * r.ncols;
-      A.flops += pairs * (16.0 + 8.0 * (r.ncols - 1));
+      A.pair_cols += r.pair_cols;
+      A.flops += r.flops;
       if (r.mixed) {
         A.launches_mixed += 1;
         A.ms_mixed += ms;
-        A.pair_cols_mixed += pairs * r.ncols;
-      } else if (r.ncols == 1) {
+        A.pair_cols_mixed += r.pair_cols;
+      } else if (r.single) {
         A.launches1 += 1;
         A.ms1 += ms;
-        A.pairs1 += pairs;
+        A.pairs1 += r.pairs1;
       }
       c->ev_pool.push_back(r.a);
       c->ev_pool.push_back(r.b);
@@ -697,17 +1000,20 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
       set_err(c, "bad arguments to gnk_cauchy_sum");
       throw Fail{GNK_ERR_ARG};
     }
-    CauchyPlan plan = plan_cauchy(N, nrhs, c->num_cu);
-    double2* parts = ws<double2>(c, "parts", (size_t)plan.splits * nrhs * N);
-    double2* rec = ws<double2>(c, "rec", (size_t)N * (nrhs + 1));
+    // a pseudo-domain of one component holding the N nodes (the even mesh
+    // size only passes the domain check; the node count is N)
+    gnk_domain d{};
+    d.m1 = 1;
+    d.n = N + (N & 1);
+    d.eta = d.etap = d.A = eta;
+    Batch B;
+    std::vector<int64_t> off{0};
+    build_batch(c, B, 1, &d, &nrhs, off, N * (int64_t)nrhs, false, false, PairShape{}, N);
     k_pack_records<<<nblocks(N), kT, 0, c->stream>>>(static_cast<const double2*>(eta),
-                                                      static_cast<const double2*>(w), (int)N, nrhs, rec);
+                                                      static_cast<const double2*>(w), (int)N, nrhs, B.dom[0].rec);
     LAUNCHCHK(c);
-    cauchy(c, rec, N, nrhs, plan, parts);
-    // reduce the splits in order: S[r*N + i] = sum_g parts
-    // (reuse the epilogue-free path: a dedicated small kernel)
-    k_reduce_parts<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(parts, plan.splits, nrhs, (int)N,
-                                                                           static_cast<double2*>(S));
+    pairs(c, B, P_GM, false, nullptr);
+    k_reduce_parts<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(B.d_dom, static_cast<double2*>(S));
     LAUNCHCHK(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GNK_OK;
@@ -717,23 +1023,21 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
 gnk_status gnk_apply(gnk_ctx* c, const gnk_domain* d, int op, int prec, const double* x, int nrhs, double* y) {
   return guarded(c, [&]() -> gnk_status {
     const bool adj = (op == GNK_OP_GB || op == GNK_OP_GB_T);
-    check_domain(c, d, adj);
     if (!x || !y || x == y || nrhs < 1 || op < 0 || op > GNK_OP_LHAT || (prec != GNK_FP64 && prec != GNK_MIXED)) {
       set_err(c, "bad arguments to gnk_apply");
       throw Fail{GNK_ERR_ARG};
     }
-    Prep P = make_prep(c, d, adj);
-    validate_inputs(c, P, adj, x, nrhs);
+    Batch B;
+    const bool mixed = prec == GNK_MIXED && op != GNK_OP_LHAT;
+    single_batch(c, B, d, nrhs, adj, mixed);
+    validate(c, B, x, B.T);
     if (op != GNK_OP_LHAT) {
-      setup_fbie(c, P);
-      if (adj) setup_fbiead(c, P);
+      setup_diag(c, B);
+      if (adj) setup_evec(c, B);
     }
     ApplyArgs a;
-    if (prec == GNK_MIXED && op != GNK_OP_LHAT) {
-      setup_mixed(c, P);
-      a.mixed = true;
-    }
-    apply_op(c, P, op, x, nrhs, y, a);
+    a.mixed = mixed;
+    apply_op(c, B, op, x, y, a);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GNK_OK;
   });
@@ -742,53 +1046,14 @@ gnk_status gnk_apply(gnk_ctx* c, const gnk_domain* d, int op, int prec, const do
 gnk_status gnk_fbie(gnk_ctx* c, const gnk_domain* d, const double* gam, int nrhs, const gnk_opts* opts, double* mu,
                     double* h, gnk_info* info) {
   return guarded(c, [&]() -> gnk_status {
-    check_domain(c, d, false);
-    if (!gam || !mu || nrhs < 1 || nrhs > 1024 || mu == gam || h == gam || (h && h == mu)) {
+    if (!gam || !mu || nrhs < 1 || mu == gam || h == gam || (h && h == mu)) {
       set_err(c, "bad arguments to gnk_fbie");
       throw Fail{GNK_ERR_ARG};
     }
     gnk_opts o = resolve_opts(c, opts);
-    Prep P = make_prep(c, d, false);
-    validate_inputs(c, P, false, gam, nrhs);
-    const int64_t N = P.N;
-    const double two_n = 2.0 / (double)P.n;
-    // rho = eta'/A; one Cauchy launch for E(rho) and E(rho gamma)
-    P.rho = ws<double2>(c, "rho", N);
-    P.dB = ws<double>(c, "dB", N);
-    P.dD = ws<double>(c, "dD", N);
-    k_rho<<<nblocks(N), kT, 0, c->stream>>>(P.etap, P.A, P.rho, (int)N);
-    LAUNCHCHK(c);
-    const int nc = nrhs + 1;
-    double2* rec0 = ws<double2>(c, "rec0", (size_t)N * (nc + 1));
-    k_weights<<<dim3((unsigned)P.m1, (unsigned)nrhs), kT, 0, c->stream>>>(
-        P.eta, P.rho, gam, nullptr, nullptr, nullptr, rec0, (int)N, (int)P.n, (int)P.m1, nc + 1, 1, 1, nullptr);
-    LAUNCHCHK(c);
-    CauchyPlan plan0 = plan_cauchy(N, nc, c->num_cu);
-    double2* parts0 = ws<double2>(c, "parts0", (size_t)plan0.splits * nc * N);
-    cauchy(c, rec0, N, nc, plan0, parts0);
-    k_diag_fbie<<<nblocks(N), kT, 0, c->stream>>>(parts0, plan0.splits, nc, P.A, (int)N, two_n, P.dB, P.dD);
-    LAUNCHCHK(c);
-    // b = -y = -(D - diag(D1) + Lhat) gamma
-    double* b = ws<double>(c, "rhs", (size_t)N * nrhs);
-    dim3 ge(nblocks(N), (unsigned)nrhs);
-    k_epilogue<<<ge, kT, 0, c->stream>>>(parts0, plan0.splits, nc, 1, gam, P.A, P.dD, 0.0, 1.0, 0.0, two_n,
-                                         nullptr, (int)P.n, (int)P.m1, nullptr, b, (int)N);
-    LAUNCHCHK(c);
-    ensure_twiddles(c, P);
-    HIPCHK(c, launch_circulant(gam, b, P.m1, P.n, nrhs, -1.0, P.tw, c->stream));
-    // (2I + diag(B1) - B) mu = b
-    if (o.prec == GNK_MIXED) setup_mixed(c, P);
-    GmresOut g = gmres(c, P, GNK_OP_FB, b, nrhs, o, mu, o.prec == GNK_MIXED);
-    if (h) {
-      // h = [(D - diag(D1) + Lhat) mu - (2I + diag(B1) - B) gamma] / 2, f_B(gamma) from the first launch
-      double* fbg = ws<double>(c, "fbg", (size_t)N * nrhs);
-      k_epilogue<<<ge, kT, 0, c->stream>>>(parts0, plan0.splits, nc, 1, gam, P.A, P.dB, 2.0, 1.0, two_n, 0.0,
-                                           nullptr, (int)P.n, (int)P.m1, nullptr, fbg, (int)N);
-      LAUNCHCHK(c);
-      apply_op(c, P, GNK_OP_FC, mu, nrhs, h);
-      k_axpby<<<nblocks(N * nrhs), kT, 0, c->stream>>>(-0.5, fbg, 0.5, h, N * nrhs);
-      LAUNCHCHK(c);
-    }
+    Batch B;
+    single_batch(c, B, d, nrhs, false, o.prec == GNK_MIXED);
+    GmresOut g = fbie_batch(c, B, gam, o, mu, h);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (info)
       for (int r = 0; r < nrhs; ++r) info[r] = g.info[r];
@@ -799,21 +1064,67 @@ gnk_status gnk_fbie(gnk_ctx* c, const gnk_domain* d, const double* gam, int nrhs
 gnk_status gnk_fbie_ad(gnk_ctx* c, const gnk_domain* d, const double* gam, int nrhs, const gnk_opts* opts, double* mu,
                        gnk_info* info) {
   return guarded(c, [&]() -> gnk_status {
-    check_domain(c, d, true);
-    if (!gam || !mu || nrhs < 1 || nrhs > 1024 || mu == gam) {
+    if (!gam || !mu || nrhs < 1 || mu == gam) {
       set_err(c, "bad arguments to gnk_fbie_ad");
       throw Fail{GNK_ERR_ARG};
     }
     gnk_opts o = resolve_opts(c, opts);
-    Prep P = make_prep(c, d, true);
-    validate_inputs(c, P, true, gam, nrhs);
-    setup_fbiead(c, P);
-    if (o.prec == GNK_MIXED) setup_mixed(c, P);
-    GmresOut g = gmres(c, P, GNK_OP_GB, gam, nrhs, o, mu, o.prec == GNK_MIXED);
+    Batch B;
+    single_batch(c, B, d, nrhs, true, o.prec == GNK_MIXED);
+    GmresOut g = fbiead_batch(c, B, gam, o, mu);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (info)
       for (int r = 0; r < nrhs; ++r) info[r] = g.info[r];
     return g.all_converged ? GNK_OK : GNK_NOT_CONVERGED;
+  });
+}
+
+gnk_status gnk_fbie_batched(gnk_ctx* c, int ndom, const gnk_domain* doms, const double* const* gam, const int* nrhs,
+                            const gnk_opts* opts, double* const* mu, double* const* h, gnk_info* info) {
+  return guarded(c, [&]() -> gnk_status {
+    if (ndom < 1 || !doms || !gam || !nrhs || !mu) {
+      set_err(c, "bad arguments to gnk_fbie_batched");
+      throw Fail{GNK_ERR_ARG};
+    }
+    gnk_opts o = resolve_opts(c, opts);
+    if (o.x0) {
+      set_err(c, "gnk_fbie_batched takes no initial guess");
+      throw Fail{GNK_ERR_ARG};
+    }
+    std::vector<int64_t> off(ndom);
+    int64_t T = 0;
+    int ncol = 0;
+    for (int d = 0; d < ndom; ++d) {
+      check_domain(c, &doms[d], false);
+      if (nrhs[d] < 1 || !gam[d] || !mu[d]) {
+        set_err(c, "domain %d: need nrhs >= 1, gam and mu", d);
+        throw Fail{GNK_ERR_ARG};
+      }
+      off[d] = T;
+      T += doms[d].m1 * doms[d].n * (int64_t)nrhs[d];
+      ncol += nrhs[d];
+    }
+    // gather the right-hand sides into one flat vector set
+    double* g = ws<double>(c, "bat_gam", T);
+    double* m = ws<double>(c, "bat_mu", T);
+    double* hh = h ? ws<double>(c, "bat_h", T) : nullptr;
+    for (int d = 0; d < ndom; ++d)
+      HIPCHK(c, hipMemcpyAsync(g + off[d], gam[d], sizeof(double) * doms[d].m1 * doms[d].n * nrhs[d],
+                               hipMemcpyDeviceToDevice, c->stream));
+    const bool mixed = o.prec == GNK_MIXED;
+    const PairShape p = tuned_shape(c, ndom, doms, nrhs, mixed, g, off, T);
+    Batch B;
+    build_batch(c, B, ndom, doms, nrhs, off, T, false, mixed, p);
+    GmresOut go = fbie_batch(c, B, g, o, m, hh);
+    for (int d = 0; d < ndom; ++d) {
+      const size_t bytes = sizeof(double) * doms[d].m1 * doms[d].n * nrhs[d];
+      HIPCHK(c, hipMemcpyAsync(mu[d], m + off[d], bytes, hipMemcpyDeviceToDevice, c->stream));
+      if (h && h[d]) HIPCHK(c, hipMemcpyAsync(h[d], hh + off[d], bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (info)
+      for (int q = 0; q < ncol; ++q) info[q] = go.info[q];
+    return go.all_converged ? GNK_OK : GNK_NOT_CONVERGED;
   });
 }
 

@@ -1,8 +1,10 @@
-// Per-node kernels around the Cauchy sum (preparation of source weights,
-// operator epilogues, validation) and the kernels of the device-resident
+// Per-node and per-column kernels around the Cauchy sums (validation, source
+// records, operator epilogues) and the kernels of the device-resident
 // restarted GMRES (classical Gram-Schmidt with one re-orthogonalisation,
-// Givens rotations, back substitution). All reductions run in a fixed order,
-// so repeated runs are bitwise identical.
+// Givens rotations, back substitution), for a batch of domains and ragged
+// columns. Column c (domain d = cols[c].d, local column r) has N_d entries
+// at flat offset cols[c].off. All reductions run in a fixed order, so
+// repeated runs are bitwise identical.
 // Included by solver.hip (one translation unit with the host driver).
 #pragma once
 #include "gnk_vec.h"
@@ -13,10 +15,14 @@ namespace {
 
 constexpr int kT = 256;   // threads per block of the vector kernels
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  // wave reduction by shuffles, then across the waves of the block through LDS
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sh[wv] = v;
@@ -27,29 +33,40 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 __device__ __forceinline__ bool finite2(double2 v) { return isfinite(v.x) && isfinite(v.y); }
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
 
 }  // namespace
 
+// per-node coefficient selectors of the records and epilogues
+enum CSel : int { C_RHO = 0, C_A = 1, C_ETAP = 2 };
+enum DSel : int { D_NONE = 0, D_B = 1, D_D = 2, D_E = 3 };
+
+__device__ __forceinline__ double2 coef(const DomDev& D, int sel, int i) {
+  return sel == C_RHO ? D.rho[i] : (sel == C_A ? D.A[i] : D.etap[i]);
+}
+__device__ __forceinline__ double diagv(const DomDev& D, int sel, int i) {
+  return sel == D_B ? D.dB[i] : (sel == D_D ? D.dD[i] : (sel == D_E ? D.e[i] : 0.0));
+}
+
 // ---------------------------------------------------------------- validation
-__global__ void k_validate(const double2* eta, const double2* etap, const double2* A, const double2* etapp,
-                           const double2* Ap, int N, int need_etap_nonzero, int* flags) {
+// grid (blocks over max N, ndom)
+__global__ void k_validate(const DomDev* __restrict__ doms, int adjoint, int* flags) {
+  const DomDev& D = doms[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  if (i >= D.N) return;
   int f = 0;
-  const double2 a = A[i];
-  const double2 e = eta[i], ep = etap[i];
-  if (!finite2(a) || !finite2(e) || !finite2(ep)) f |= 1;
+  const double2 a = D.A[i];
+  if (!finite2(a) || !finite2(D.eta[i]) || !finite2(D.etap[i])) f |= 1;
   if (a.x == 0.0 && a.y == 0.0) f |= 2;
-  if (etapp && !finite2(etapp[i])) f |= 1;
-  if (Ap && !finite2(Ap[i])) f |= 1;
-  if (need_etap_nonzero && ep.x == 0.0 && ep.y == 0.0) f |= 4;
+  if (adjoint) {
+    if (!finite2(D.etapp[i]) || !finite2(D.Ap[i])) f |= 1;
+    const double2 ep = D.etap[i];
+    if (ep.x == 0.0 && ep.y == 0.0) f |= 4;
+  }
   if (f) atomicOr(flags, f);
 }
 
@@ -60,90 +77,106 @@ __global__ void k_check_finite(const double* x, int64_t n, int* flags) {
 
 // ------------------------------------------------------------ per-node setup
 // rho = eta' / A  (the weight factor of eqs. (e:hD-bt), (e:(I-B)x))
-__global__ void k_rho(const double2* etap, const double2* A, double2* rho, int N) {
+__global__ void k_rho(const DomDev* __restrict__ doms) {
+  const DomDev& D = doms[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double2 p = etap[i], a = A[i];
+  if (i >= D.N) return;
+  const double2 p = D.etap[i], a = D.A[i];
   const double d = a.x * a.x + a.y * a.y;
-  rho[i] = make_double2((p.x * a.x + p.y * a.y) / d, (p.y * a.x - p.x * a.y) / d);
+  D.rho[i] = make_double2((p.x * a.x + p.y * a.y) / d, (p.y * a.x - p.x * a.y) / d);
 }
 
-// reduce the split partial sums of column col of a Cauchy launch with ncols columns
-__device__ __forceinline__ double2 reduce_parts(const double2* part, int splits, int ncols, int col, int N, int i) {
+// sum over the splits of weight column q (of wcols) of a domain's partial sums
+__device__ __forceinline__ double2 reduce_parts(const DomDev& D, int wcols, int q, int i) {
   double2 s = make_double2(0.0, 0.0);
-  for (int g = 0; g < splits; ++g) {
-    const double2 v = part[((size_t)g * ncols + col) * N + i];
+  for (int g = 0; g < D.splits; ++g) {
+    const double2 v = D.parts[((size_t)g * wcols + q) * D.N + i];
     s.x += v.x;
     s.y += v.y;
   }
   return s;
 }
 
-// From S = E(eta'/A):  dB = diag(B1) = -(2/n) Im(A S),  dD = diag(D1) = -(2/n) Re(A S)
-// (eqs. (e:(I-B)x), (e:hD-bt) with x = 1).
-__global__ void k_diag_fbie(const double2* part, int splits, int ncols, const double2* A, int N, double two_n,
-                            double* dB, double* dD) {
+// From S = E(eta'/A) in weight column 0 (wcols columns):
+//   dB = diag(B1) = -(2/n) Im(A S),  dD = diag(D1) = -(2/n) Re(A S)
+// (eqs. (e:(I-B)x), (e:hD-bt) with x = 1)
+__global__ void k_diag_fbie(const DomDev* __restrict__ doms, int lead, int data) {
+  const DomDev& D = doms[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double2 s = reduce_parts(part, splits, ncols, 0, N, i);
-  const double2 a = A[i];
-  const double re = a.x * s.x - a.y * s.y, im = a.x * s.y + a.y * s.x;
-  dB[i] = -two_n * im;
-  dD[i] = -two_n * re;
+  if (i >= D.N) return;
+  const int wcols = lead + data * D.ncols;
+  const double2 s = reduce_parts(D, wcols, 0, i);
+  const double2 as = cmul(D.A[i], s);
+  const double two_n = 2.0 / (double)D.n;
+  D.dB[i] = -two_n * as.y;
+  D.dD[i] = -two_n * as.x;
 }
 
-// From S = E eta':  e = 1 - c - (2/n) Im(S) + (2/n) Im(eta''/eta' - A'/A)   (eq. (e:bve))
-__global__ void k_evec(const double2* part, int splits, const double2* etap, const double2* etapp, const double2* A,
-                       const double2* Ap, int N, double two_n, double c, double* e) {
+// From S = E eta' (weight column 0 of wcols = 1):
+//   e = 1 - c - (2/n) Im(S) + (2/n) Im(eta''/eta' - A'/A)   (eq. (e:bve))
+__global__ void k_evec(const DomDev* __restrict__ doms) {
+  const DomDev& D = doms[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double2 s = reduce_parts(part, splits, 1, 0, N, i);
-  const double2 p = etap[i], pp = etapp[i], a = A[i], ap = Ap[i];
+  if (i >= D.N) return;
+  const double2 s = reduce_parts(D, 1, 0, i);
+  const double2 p = D.etap[i], pp = D.etapp[i], a = D.A[i], ap = D.Ap[i];
   const double dp = p.x * p.x + p.y * p.y, da = a.x * a.x + a.y * a.y;
   const double im1 = (pp.y * p.x - pp.x * p.y) / dp;   // Im(eta''/eta')
   const double im2 = (ap.y * a.x - ap.x * a.y) / da;   // Im(A'/A)
-  e[i] = 1.0 - c - two_n * s.y + two_n * (im1 - im2);
+  const double two_n = 2.0 / (double)D.n;
+  D.e[i] = 1.0 - (double)D.c - two_n * s.y + two_n * (im1 - im2);
 }
 
-// ----------------------------------------------- source weights and means
-// Source records for the Cauchy kernel: rec[j*stride] = eta_j,
-// rec[j*stride + 1 + col0 + r] = C_j * v_j for column r (block (k, r) covers
-// component k of column r), with
-//   v = x * scale[r]                 (optional; written back to xout)
-//   mean[r*m1 + k] = (1/n) sum_p v_{k n + p}   (optional)
-// If lead_one, record field 1 is C_j itself (x == 1) and data columns start
-// at col0 = 1.
-__global__ __launch_bounds__(kT) void k_weights(const double2* __restrict__ eta, const double2* __restrict__ C,
-                                                const double* __restrict__ x, const double* __restrict__ scale,
-                                                const int* __restrict__ active, double* __restrict__ xout,
-                                                double2* __restrict__ rec, int N, int n, int m1, int stride,
-                                                int col0, int lead_one, double* __restrict__ mean) {
+// ----------------------------------------------- source records and means
+// Records rec_d[j*stride]: eta_j; field 1 = C_j when lead; fields 1+lead+r =
+// C_j * v_j for the domain's column r, with
+//   v = x * scale[c]                  (optional; written back to xout)
+//   mean[c*M + k] = (1/n) sum_p v_{k n + p}   (optional, component means)
+// grid (max m1, ncol): block (k, c) covers component k of column c.
+__global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
+                                                int csel, const double* __restrict__ x,
+                                                const double* __restrict__ scale, const int* __restrict__ active,
+                                                double* __restrict__ xout, int lead, double* __restrict__ mean,
+                                                int M) {
   __shared__ double sh[kT / 64];
-  const int k = blockIdx.x, r = blockIdx.y;
-  if (active && !active[r]) return;
-  const double s = scale ? scale[r] : 1.0;
-  const double* xr = x + (size_t)r * N + (size_t)k * n;
+  const int k = blockIdx.x, c = blockIdx.y;
+  const ColDev C = cols[c];
+  const DomDev& D = doms[C.d];
+  if (k >= D.m1) return;
+  if (active && !active[c]) return;
+  const double s = scale ? scale[c] : 1.0;
+  const int stride = lead + D.ncols + 1;
+  const double* xr = x + C.off + (size_t)k * D.n;
   double acc = 0.0;
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    const int j = k * n + p;
+  for (int p = threadIdx.x; p < D.n; p += blockDim.x) {
+    const int j = k * D.n + p;
     const double v = xr[p] * s;
-    if (xout) xout[(size_t)r * N + j] = v;
-    const double2 c = C[j];
-    double2* rj = rec + (size_t)j * stride;
-    rj[1 + col0 + r] = make_double2(c.x * v, c.y * v);
-    if (r == 0) {
-      rj[0] = eta[j];
-      if (lead_one) rj[1] = c;
+    if (xout) xout[C.off + j] = v;
+    const double2 cf = coef(D, csel, j);
+    double2* rj = D.rec + (size_t)j * stride;
+    rj[1 + lead + C.r] = make_double2(cf.x * v, cf.y * v);
+    if (C.r == 0) {
+      rj[0] = D.eta[j];
+      if (lead) rj[1] = cf;
     }
     acc += v;
   }
   if (mean) {
     const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) mean[(size_t)r * m1 + k] = t / (double)n;
+    if (threadIdx.x == 0) mean[(size_t)c * M + k] = t / (double)D.n;
   }
 }
 
-// records from eta and column-major complex weights w (N x ncols)
+// records holding only the leading column: rec_d[j*2] = eta_j, rec_d[j*2+1] = C_j
+__global__ void k_lead_records(const DomDev* __restrict__ doms, int csel) {
+  const DomDev& D = doms[blockIdx.y];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= D.N) return;
+  D.rec[(size_t)j * 2] = D.eta[j];
+  D.rec[(size_t)j * 2 + 1] = coef(D, csel, j);
+}
+
+// records from eta and column-major complex weights w (N x ncols), one domain
 __global__ void k_pack_records(const double2* __restrict__ eta, const double2* __restrict__ w, int N, int ncols,
                                double2* __restrict__ rec) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,44 +186,36 @@ __global__ void k_pack_records(const double2* __restrict__ eta, const double2* _
   for (int r = 0; r < ncols; ++r) rj[1 + r] = w[(size_t)r * N + j];
 }
 
-// Operator epilogue, for column r (grid.y) of x (N x nrhs), S from column (col0 + r):
-//   y = a0 x + dsign dg x + cI Im(Cout S) + cR Re(Cout S) + mean[r][k(i)]
-__global__ void k_epilogue(const double2* __restrict__ part, int splits, int ncols, int col0,
-                           const double* __restrict__ x, const double2* __restrict__ Cout,
-                           const double* __restrict__ dg, double a0, double dsign, double cI, double cR,
-                           const double* __restrict__ mean, int n, int m1, const int* __restrict__ active,
-                           double* __restrict__ y, int N) {
+// S[r*N + i] = sum over the splits of column r (one domain, no lead column)
+__global__ void k_reduce_parts(const DomDev* __restrict__ doms, double2* __restrict__ S) {
+  const DomDev& D = doms[0];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (i >= N) return;
-  if (active && !active[r]) return;
-  const double2 s = reduce_parts(part, splits, ncols, col0 + r, N, i);
-  const double2 c = Cout[i];
-  const double re = c.x * s.x - c.y * s.y, im = c.x * s.y + c.y * s.x;
-  const double xv = x[(size_t)r * N + i];
-  double v = a0 * xv + cI * im + cR * re;
-  if (dg) v += dsign * dg[i] * xv;
-  if (mean) v += mean[(size_t)r * m1 + i / n];
-  y[(size_t)r * N + i] = v;
+  if (i >= D.N) return;
+  S[(size_t)r * D.N + i] = reduce_parts(D, D.ncols, r, i);
 }
 
-// S[r*N + i] = sum over the splits of the partial Cauchy sums (fixed order)
-__global__ void k_reduce_parts(const double2* __restrict__ part, int splits, int ncols, int N, double2* __restrict__ S) {
+// Operator epilogue for column c (grid (blocks over max N, ncol)), S from
+// weight column lead + r of the domain's last Cauchy launch:
+//   y = a0 x + dsign dg x + cI Im(Cout S) + cR Re(Cout S) + mean[c][k(i)]
+__global__ void k_epilogue(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
+                           const double* __restrict__ x, int csel_out, int dsel, double a0, double dsign, double cI,
+                           double cR, const double* __restrict__ mean, int M, const int* __restrict__ active,
+                           int lead, double* __restrict__ y) {
+  const int c = blockIdx.y;
+  const ColDev C = cols[c];
+  const DomDev& D = doms[C.d];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (i >= N) return;
-  S[(size_t)r * N + i] = reduce_parts(part, splits, ncols, r, N, i);
-}
-
-// out[r] = ||x_r||_2, one block per column, fixed-order reduction
-__global__ __launch_bounds__(kT) void k_col_norms(const double* __restrict__ x, int N, double* __restrict__ out) {
-  __shared__ double sh[kT / 64];
-  const int r = blockIdx.x;
-  const double* xr = x + (size_t)r * N;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) acc = __builtin_fma(xr[i], xr[i], acc);
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[r] = sqrt(t);
+  if (i >= D.N) return;
+  if (active && !active[c]) return;
+  const double2 s = reduce_parts(D, lead + D.ncols, lead + C.r, i);
+  const double2 cs = cmul(coef(D, csel_out, i), s);
+  const double two_n = 2.0 / (double)D.n;
+  const double xv = x[C.off + i];
+  double v = a0 * xv + two_n * (cI * cs.y + cR * cs.x);
+  if (dsel != D_NONE) v += dsign * diagv(D, dsel, i) * xv;
+  if (mean) v += mean[(size_t)c * M + i / D.n];
+  y[C.off + i] = v;
 }
 
 // y = a x + b y  (elementwise over len)
@@ -199,17 +224,31 @@ __global__ void k_axpby(double a, const double* x, double b, double* y, int64_t 
   if (i < len) y[i] = a * x[i] + b * y[i];
 }
 
-// ------------------------------------------------------------------ GMRES
-// V holds the Krylov vectors: V_l column r at V + ((size_t)l*nrhs + r)*N.
+// out[c] = ||x_c||_2, one block per column, fixed-order reduction
+__global__ __launch_bounds__(kT) void k_col_norms(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
+                                                  const double* __restrict__ x, double* __restrict__ out) {
+  __shared__ double sh[kT / 64];
+  const ColDev C = cols[blockIdx.x];
+  const int N = doms[C.d].N;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) acc = __builtin_fma(x[C.off + i], x[C.off + i], acc);
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = sqrt(t);
+}
 
-// Dots of the block's chunk of w_r with V_0..V_{nvec-1}: wavefront q takes
+// ------------------------------------------------------------------ GMRES
+// Krylov vector l of column c: V + l*T + off_c (T = flat length of a vector set).
+// Partial sums: P[(c*nblk + blk)*ldp + l]; blocks past the column's end write 0.
+
+// Dots of the block's chunk of w with V_0..V_{nvec-1}: wavefront q takes
 // vectors l = q, q+4, ...; each lane sums its strided elements and the wave
-// reduces by shuffles. partial[(r*nblk + blk)*ldp + l].
-__device__ __forceinline__ void chunk_dots(const double* __restrict__ V, int nvec, const double* __restrict__ w,
-                                           int i0, int i1, int N, int nrhs, int r, double* __restrict__ out) {
+// reduces by shuffles.
+__device__ __forceinline__ void chunk_dots(const double* __restrict__ V, int64_t T, int64_t off, int nvec,
+                                           const double* __restrict__ w, int i0, int i1,
+                                           double* __restrict__ out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int l = wv; l < nvec; l += nw) {
-    const double* vl = V + ((size_t)l * nrhs + r) * N;
+    const double* vl = V + (size_t)l * T + off;
     double acc = 0.0;
     for (int i = i0 + lane; i < i1; i += 64) acc = __builtin_fma(vl[i], w[i - i0], acc);
     acc = wave_sum(acc);
@@ -217,130 +256,153 @@ __device__ __forceinline__ void chunk_dots(const double* __restrict__ V, int nve
   }
 }
 
-__global__ __launch_bounds__(kT) void k_gs_dot(const double* __restrict__ V, int nvec, const double* __restrict__ w,
-                                               int N, int nrhs, int per_blk, const int* __restrict__ active,
-                                               double* __restrict__ partial, int ldp) {
-  const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
-  if (!active[r]) return;
+__global__ __launch_bounds__(kT) void k_gs_dot(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
+                                               const double* __restrict__ V, int64_t T, int nvec,
+                                               const double* __restrict__ w, int per_blk,
+                                               const int* __restrict__ active, double* __restrict__ partial,
+                                               int ldp) {
+  const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  if (!active[c]) return;
+  const ColDev C = cols[c];
+  const int N = doms[C.d].N;
+  double* out = partial + ((size_t)c * nblk + blk) * ldp;
   const int i0 = blk * per_blk, i1 = min(N, i0 + per_blk);
-  chunk_dots(V, nvec, w + (size_t)r * N + i0, i0, i1, N, nrhs, r, partial + ((size_t)r * nblk + blk) * ldp);
+  if (i0 >= N) {
+    for (int l = threadIdx.x; l < nvec; l += blockDim.x) out[l] = 0.0;
+    return;
+  }
+  chunk_dots(V, T, C.off, nvec, w + C.off + i0, i0, i1, out);
 }
 
 // h_l = sum over blocks of pin (fixed order); w -= sum_l h_l V_l on this
-// block's chunk; H[:, col] (+)= h (block 0); then pout = the chunk's dots of the
-// updated w with V_0..V_{nvec-1} (do_dots) or its squared norm (entry 0).
-__global__ __launch_bounds__(kT) void k_gs_update(const double* __restrict__ V, int nvec, double* __restrict__ w,
-                                                  int N, int nrhs, int per_blk, const int* __restrict__ active,
-                                                  const double* __restrict__ pin, double* __restrict__ pout, int ldp,
-                                                  double* __restrict__ H, int ldh, int hstride, int col,
+// block's chunk; H[:, col] (+)= h (block 0); then pout = the chunk's dots of
+// the updated w with V_0..V_{nvec-1} (do_dots) or its squared norm (entry 0).
+__global__ __launch_bounds__(kT) void k_gs_update(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
+                                                  const double* __restrict__ V, int64_t T, int nvec,
+                                                  double* __restrict__ w, int per_blk,
+                                                  const int* __restrict__ active, const double* __restrict__ pin,
+                                                  double* __restrict__ pout, int ldp, GmresState st, int col,
                                                   int accumulate_h, int do_dots) {
   __shared__ double h[kMaxRestart + 1];
   __shared__ double sw[kMaxChunk];
   __shared__ double sh[kT / 64];
-  const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
-  if (!active[r]) return;
+  const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  if (!active[c]) return;
+  const ColDev C = cols[c];
+  const int N = doms[C.d].N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int l = wv; l < nvec; l += nw) {
     double acc = 0.0;
-    for (int b = lane; b < nblk; b += 64) acc += pin[((size_t)r * nblk + b) * ldp + l];
+    for (int b = lane; b < nblk; b += 64) acc += pin[((size_t)c * nblk + b) * ldp + l];
     acc = wave_sum(acc);
     if (lane == 0) h[l] = acc;
   }
   __syncthreads();
   if (blk == 0) {
-    double* Hr = H + (size_t)r * hstride + (size_t)col * ldh;
+    double* Hr = st.H + (size_t)c * st.hstride + (size_t)col * st.ldh;
     for (int l = threadIdx.x; l < nvec; l += blockDim.x) Hr[l] = accumulate_h ? Hr[l] + h[l] : h[l];
   }
+  double* out = pout + ((size_t)c * nblk + blk) * ldp;
   const int i0 = blk * per_blk, i1 = min(N, i0 + per_blk);
-  double* wr = w + (size_t)r * N;
+  if (i0 >= N) {
+    const int nout = do_dots ? nvec : 1;
+    for (int l = threadIdx.x; l < nout; l += blockDim.x) out[l] = 0.0;
+    return;
+  }
+  double* wr = w + C.off;
   double nrm = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     double v = wr[i];
-    for (int l = 0; l < nvec; ++l) v = __builtin_fma(-h[l], V[((size_t)l * nrhs + r) * N + i], v);
+    for (int l = 0; l < nvec; ++l) v = __builtin_fma(-h[l], V[(size_t)l * T + C.off + i], v);
     wr[i] = v;
     sw[i - i0] = v;
     nrm = __builtin_fma(v, v, nrm);
   }
-  double* out = pout + ((size_t)r * nblk + blk) * ldp;
   if (do_dots) {
     __syncthreads();
-    chunk_dots(V, nvec, sw, i0, i1, N, nrhs, r, out);
+    chunk_dots(V, T, C.off, nvec, sw, i0, i1, out);
   } else {
     const double t = block_sum(nrm, sh);
     if (threadIdx.x == 0) out[0] = t;
   }
 }
 
-// partial norms^2 of columns of x (grid (nblk, nrhs)); entry (r*nblk + blk)*ldp
-__global__ __launch_bounds__(kT) void k_norm_partial(const double* __restrict__ x, int N, int per_blk,
-                                                     double* __restrict__ partial, int ldp) {
+// partial norms^2 of the columns of x (grid (nblk, ncol)); entry (c*nblk + blk)*ldp
+__global__ __launch_bounds__(kT) void k_norm_partial(const DomDev* __restrict__ doms,
+                                                     const ColDev* __restrict__ cols, const double* __restrict__ x,
+                                                     int per_blk, double* __restrict__ partial, int ldp) {
   __shared__ double sh[kT / 64];
-  const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  const ColDev C = cols[c];
+  const int N = doms[C.d].N;
   const int i0 = blk * per_blk, i1 = min(N, i0 + per_blk);
-  const double* xr = x + (size_t)r * N;
   double acc = 0.0;
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) acc = __builtin_fma(xr[i], xr[i], acc);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) acc = __builtin_fma(x[C.off + i], x[C.off + i], acc);
   const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[((size_t)r * nblk + blk) * ldp] = s;
+  if (threadIdx.x == 0) partial[((size_t)c * nblk + blk) * ldp] = s;
 }
 
 // r = b - Ax (in place into ax) and partial ||r||^2
-__global__ __launch_bounds__(kT) void k_residual(const double* __restrict__ b, double* __restrict__ ax, int N,
-                                                 int per_blk, double* __restrict__ partial, int ldp) {
+__global__ __launch_bounds__(kT) void k_residual(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
+                                                 const double* __restrict__ b, double* __restrict__ ax, int per_blk,
+                                                 double* __restrict__ partial, int ldp) {
   __shared__ double sh[kT / 64];
-  const int r = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  const ColDev C = cols[c];
+  const int N = doms[C.d].N;
   const int i0 = blk * per_blk, i1 = min(N, i0 + per_blk);
   double acc = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const size_t idx = (size_t)r * N + i;
+    const size_t idx = (size_t)C.off + i;
     const double v = b[idx] - ax[idx];
     ax[idx] = v;
     acc = __builtin_fma(v, v, acc);
   }
   const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[((size_t)r * nblk + blk) * ldp] = s;
+  if (threadIdx.x == 0) partial[((size_t)c * nblk + blk) * ldp] = s;
 }
 
 // One thread per column: ||b|| from partials.
-__global__ void k_bnorm(const double* partial, int nblk, int ldp, int nrhs, GmresState st) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
+__global__ void k_bnorm(const double* partial, int nblk, int ldp, int ncol, GmresState st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[((size_t)r * nblk + b) * ldp];
-  st.bnorm[r] = sqrt(s);
+  for (int b = 0; b < nblk; ++b) s += partial[((size_t)c * nblk + b) * ldp];
+  st.bnorm[c] = sqrt(s);
 }
 
 // Start of a restart cycle, one thread per column: beta0 = ||r|| from the
-// partials, true relative residual, convergence test, g = beta0 e_1.
-__global__ void k_cycle_start(const double* partial, int nblk, int ldp, int nrhs, double tol, GmresState st) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r == 0) *st.live = 0;
-  __syncthreads();
-  if (r >= nrhs) return;
+// partials, true relative residual, convergence test, g = beta0 e_1. The
+// number of iterating columns is accumulated in *st.live (zeroed before).
+__global__ void k_cycle_start(const double* partial, int nblk, int ldp, int ncol, double tol, GmresState st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[((size_t)r * nblk + b) * ldp];
+  for (int b = 0; b < nblk; ++b) s += partial[((size_t)c * nblk + b) * ldp];
   const double beta = sqrt(s);
-  const double bn = st.bnorm[r];
+  const double bn = st.bnorm[c];
   const double rel = bn > 0.0 ? beta / bn : 0.0;
-  st.true_relres[r] = rel;
-  st.relres[r] = rel;
-  st.kdim[r] = 0;
-  double* g = st.g + (size_t)r * (kMaxRestart + 1);
+  st.true_relres[c] = rel;
+  st.relres[c] = rel;
+  st.kdim[c] = 0;
+  double* g = st.g + (size_t)c * (kMaxRestart + 1);
   if (bn == 0.0 || rel <= tol || beta == 0.0) {
-    st.converged[r] = 1;
-    st.active[r] = 0;
-    st.invbeta[r] = 0.0;
+    st.converged[c] = 1;
+    st.active[c] = 0;
+    st.invbeta[c] = 0.0;
     g[0] = 0.0;
   } else {
-    st.converged[r] = 0;
-    st.active[r] = 1;
-    st.invbeta[r] = 1.0 / beta;
+    st.converged[c] = 0;
+    st.active[c] = 1;
+    st.invbeta[c] = 1.0 / beta;
     g[0] = beta;
     atomicAdd(st.live, 1);
   }
 }
 
-// End of Arnoldi step `col`; one 64-lane block per column r: beta = ||w||
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+// End of Arnoldi step `col`; one 64-lane block per column c: beta = ||w||
 // from the partials, H(col+1, col) = beta, Givens rotations applied in LDS,
 // residual estimate, stop test for this cycle.
 __global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, int nblk, int ldp, int col,
@@ -348,15 +410,15 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, in
   __shared__ double hc[kMaxRestart + 2];
   __shared__ double cs_[kMaxRestart + 1];
   __shared__ double sn_[kMaxRestart + 1];
-  const int r = blockIdx.x, lane = threadIdx.x;
-  if (!st.active[r]) return;
+  const int c = blockIdx.x, lane = threadIdx.x;
+  if (!st.active[c]) return;
   double s = 0.0;
-  for (int b = lane; b < nblk; b += 64) s += partial[((size_t)r * nblk + b) * ldp];
+  for (int b = lane; b < nblk; b += 64) s += partial[((size_t)c * nblk + b) * ldp];
   s = wave_sum(s);
   const double beta = sqrt(s);
-  double* Hc = st.H + (size_t)r * st.hstride + (size_t)col * st.ldh;
-  double* cs = st.cs + (size_t)r * kMaxRestart;
-  double* sn = st.sn + (size_t)r * kMaxRestart;
+  double* Hc = st.H + (size_t)c * st.hstride + (size_t)col * st.ldh;
+  double* cs = st.cs + (size_t)c * kMaxRestart;
+  double* sn = st.sn + (size_t)c * kMaxRestart;
   for (int k = lane; k <= col; k += 64) {
     hc[k] = Hc[k];
     if (k < col) {
@@ -374,26 +436,26 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, in
     }
     const double a = hc[col];
     const double den = hypot(a, beta);
-    double c = 1.0, sv = 0.0;
-    if (den > 0.0) { c = a / den; sv = beta / den; }
-    cs[col] = c;
+    double cv = 1.0, sv = 0.0;
+    if (den > 0.0) { cv = a / den; sv = beta / den; }
+    cs[col] = cv;
     sn[col] = sv;
     hc[col] = den;
     hc[col + 1] = 0.0;
-    double* g = st.g + (size_t)r * (kMaxRestart + 1);
+    double* g = st.g + (size_t)c * (kMaxRestart + 1);
     const double gc = g[col];
     g[col + 1] = -sv * gc;
-    g[col] = c * gc;
-    const double est = fabs(sv * gc) / st.bnorm[r];
-    st.relres[r] = est;
-    st.kdim[r] = col + 1;
-    st.inner_it[r] += 1;
+    g[col] = cv * gc;
+    const double est = fabs(sv * gc) / st.bnorm[c];
+    st.relres[c] = est;
+    st.kdim[c] = col + 1;
+    st.inner_it[c] += 1;
     const bool stop = (est <= tol) || (beta == 0.0) || (col + 1 >= restart) || (den == 0.0);
     if (stop) {
-      st.active[r] = 0;
+      st.active[c] = 0;
       atomicSub(st.live, 1);
     } else {
-      st.invbeta[r] = 1.0 / beta;
+      st.invbeta[c] = 1.0 / beta;
     }
   }
   __syncthreads();
@@ -404,10 +466,10 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, in
 // rotations); one 64-lane block per column, each row sum split over lanes.
 __global__ __launch_bounds__(64) void k_backsolve(GmresState st) {
   __shared__ double ys[kMaxRestart];
-  const int r = blockIdx.x, lane = threadIdx.x;
-  const int k = st.converged[r] ? 0 : st.kdim[r];
-  const double* Hr = st.H + (size_t)r * st.hstride;
-  const double* g = st.g + (size_t)r * (kMaxRestart + 1);
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int k = st.converged[c] ? 0 : st.kdim[c];
+  const double* Hr = st.H + (size_t)c * st.hstride;
+  const double* g = st.g + (size_t)c * (kMaxRestart + 1);
   for (int l = k - 1; l >= 0; --l) {
     double s = 0.0;
     for (int q = l + 1 + lane; q < k; q += 64) s = __builtin_fma(Hr[(size_t)q * st.ldh + l], ys[q], s);
@@ -418,33 +480,35 @@ __global__ __launch_bounds__(64) void k_backsolve(GmresState st) {
     }
     __syncthreads();
   }
-  double* y = st.y + (size_t)r * kMaxRestart;
+  double* y = st.y + (size_t)c * kMaxRestart;
   for (int l = lane; l < kMaxRestart; l += 64) y[l] = l < k ? ys[l] : 0.0;
 }
 
-// x_r += sum_{l < kdim_r} y_l V_l,r
-__global__ void k_xupdate(const double* __restrict__ V, double* __restrict__ x, int N, int nrhs, GmresState st) {
+// x_c += sum_{l < kdim_c} y_l V_l,c   (grid (blocks over max N, ncol))
+__global__ void k_xupdate(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
+                          const double* __restrict__ V, int64_t T, double* __restrict__ x, GmresState st) {
+  const int c = blockIdx.y;
+  const ColDev C = cols[c];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (i >= N) return;
-  const int k = st.converged[r] ? 0 : st.kdim[r];
+  if (i >= doms[C.d].N) return;
+  const int k = st.converged[c] ? 0 : st.kdim[c];
   if (k == 0) return;
-  const double* y = st.y + (size_t)r * kMaxRestart;
-  double v = x[(size_t)r * N + i];
-  for (int l = 0; l < k; ++l) v = __builtin_fma(y[l], V[((size_t)l * nrhs + r) * N + i], v);
-  x[(size_t)r * N + i] = v;
+  const double* y = st.y + (size_t)c * kMaxRestart;
+  double v = x[C.off + i];
+  for (int l = 0; l < k; ++l) v = __builtin_fma(y[l], V[(size_t)l * T + C.off + i], v);
+  x[C.off + i] = v;
 }
 
 // inner_it counters etc. to zero
-__global__ void k_gmres_init(int nrhs, GmresState st) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  st.inner_it[r] = 0;
-  st.relres[r] = 1.0;
-  st.true_relres[r] = 1.0;
-  st.converged[r] = 0;
-  st.active[r] = 0;
-  st.kdim[r] = 0;
+__global__ void k_gmres_init(int ncol, GmresState st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  st.inner_it[c] = 0;
+  st.relres[c] = 1.0;
+  st.true_relres[c] = 1.0;
+  st.converged[c] = 0;
+  st.active[c] = 0;
+  st.kdim[c] = 0;
 }
 
 }  // namespace gnk

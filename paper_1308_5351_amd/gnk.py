@@ -23,7 +23,8 @@ FP64, MIXED = 0, 1
 OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT = range(7)
 
 EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
-            "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad")
+            "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad",
+            "gnk_fbie_batched")
 
 
 class GnkError(RuntimeError):
@@ -43,7 +44,7 @@ class _Opts(C.Structure):
 
 
 class Info(C.Structure):
-    _fields_ = [("flag", C.c_int), ("outer_it", C.c_int), ("inner_it", C.c_int), ("refine_steps", C.c_int),
+    _fields_ = [("flag", C.c_int), ("outer_it", C.c_int), ("inner_it", C.c_int), ("mixed_steps", C.c_int),
                 ("relres", C.c_double), ("true_relres", C.c_double)]
 
     def as_dict(self):
@@ -83,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.gnk_apply.argtypes = [P, C.POINTER(_Domain), C.c_int, C.c_int, P, C.c_int, P]
     lib.gnk_fbie.argtypes = [P, C.POINTER(_Domain), P, C.c_int, C.POINTER(_Opts), P, P, C.POINTER(Info)]
     lib.gnk_fbie_ad.argtypes = [P, C.POINTER(_Domain), P, C.c_int, C.POINTER(_Opts), P, C.POINTER(Info)]
+    lib.gnk_fbie_batched.argtypes = [P, C.c_int, C.POINTER(_Domain), C.POINTER(P), C.POINTER(C.c_int),
+                                     C.POINTER(_Opts), C.POINTER(P), C.POINTER(P), C.POINTER(Info)]
     for f in EXPORTED:
         if f not in ("gnk_last_error", "gnk_version"):
             getattr(lib, f).restype = C.c_int
@@ -235,3 +238,35 @@ class Context:
         st = self.lib.gnk_fbie_ad(self.h, C.byref(d), g.data_ptr(), nrhs, C.byref(o), mu.data_ptr(), infos)
         self._raise(st)
         return _from_cols(mu, one), [i.as_dict() for i in infos], st
+
+    def fbie_batched(self, doms, gams, restart=25, maxit=40, tol=1e-12, prec=FP64, inner_tol=0.0, want_h=True):
+        """Batched FBIE over several domains. gams[d]: (N_d,) or (N_d, nrhs_d) float64 CUDA.
+        Returns (mus, hs, infos, status) with one entry per domain (infos: list of lists)."""
+        self._bind_stream()
+        nd = len(doms)
+        if nd != len(gams) or nd == 0:
+            raise ValueError("need one gamma per domain")
+        cols, ones = [], []
+        for d, g in zip(doms, gams):
+            gc, k = _check_real(g, d.N, "gam")
+            cols.append((gc, k))
+            ones.append(g.dim() == 1)
+        mus = [torch.empty_like(gc) for gc, _ in cols]
+        hs = [torch.empty_like(gc) for gc, _ in cols] if want_h else None
+        D = (_Domain * nd)(*[d._struct() for d in doms])
+        G = (C.c_void_p * nd)(*[gc.data_ptr() for gc, _ in cols])
+        R = (C.c_int * nd)(*[k for _, k in cols])
+        MU = (C.c_void_p * nd)(*[m.data_ptr() for m in mus])
+        H = (C.c_void_p * nd)(*[h.data_ptr() for h in hs]) if want_h else None
+        ncol = sum(k for _, k in cols)
+        infos = (Info * ncol)()
+        o = self._opts(restart, maxit, tol, prec, inner_tol, 0, None)
+        st = self.lib.gnk_fbie_batched(self.h, nd, D, G, R, C.byref(o), MU, H, infos)
+        self._raise(st)
+        out_i, q = [], 0
+        for _, k in cols:
+            out_i.append([infos[q + j].as_dict() for j in range(k)])
+            q += k
+        mus = [_from_cols(m, one) for m, one in zip(mus, ones)]
+        hs = [_from_cols(h, one) for h, one in zip(hs, ones)] if want_h else None
+        return mus, hs, out_i, st

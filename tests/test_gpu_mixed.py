@@ -63,7 +63,7 @@ def test_fbie_mixed_matches_oracle_reduced(gk, ctx, small_close, nrhs):
     e_mu = orc.rel_linf(mu.cpu().numpy(), mu_o, s)
     e_h = orc.rel_linf(h.cpu().numpy(), h_o, s)
     print(f"[mixed] reduced close: err mu {e_mu:.2e} h {e_h:.2e} infos {infos}", flush=True)
-    assert st == 0 and all(i["refine_steps"] >= 1 for i in infos)
+    assert st == 0 and all(i["mixed_steps"] >= 1 for i in infos)
     assert e_mu < 1e-10 and e_h < 1e-10
 
 

@@ -364,3 +364,39 @@ def config2(n: int = 2048, m1: int = 65, grade: int = 3):
                     meta=dict(kinds=[s.kind for s in shapes], centers=[s.center for s in shapes]))
     gam = (dom.eta ** 2).real
     return dom, gam[:, None]
+
+
+# ----------------------------------------------------------------------------
+# Batched workload: many unbounded domains of uneven size, each with m+1
+# right-hand sides gamma_k = log|eta - alpha_k|, alpha_k inside hole k.
+# ----------------------------------------------------------------------------
+def batch_domain(d: int, m1_range=(2, 40), ns=(256, 512, 1024, 2048), rrange=(0.05, 0.1)):
+    """Domain d of the batched workload (seed [SEED, 3, d])."""
+    rng = np.random.default_rng([SEED, 3, d])
+    m1 = int(rng.integers(m1_range[0], m1_range[1] + 1))
+    n = int(rng.choice(ns))
+    side = 0.5 * np.sqrt(m1)
+    holes = []        # (center, a, b, phi)
+    while len(holes) < m1:
+        r = rng.uniform(*rrange)
+        if rng.uniform() < 0.5:
+            a = b = r
+            phi = 0.0
+        else:
+            a = r
+            b = r * rng.uniform(0.5, 1.0)
+            phi = rng.uniform(0, np.pi)
+        cen = complex(*rng.uniform(-side / 2, side / 2, 2))
+        ok = all(abs(cen - c2) >= a + a2 + 0.5 * max(a, a2) for c2, a2, _, _ in holes)
+        if ok:
+            holes.append((cen, a, b, phi))
+    curves = [(lambda t, h=h: geo.ellipse(t, h[0], h[1], h[2], h[3], ccw=False)) for h in holes]
+    dom = _assemble(curves, n, False, "one", name=f"batch{d}", meta=dict(holes=holes))
+    alphas = [h[0] + 0.3 * h[1] * np.sqrt(rng.uniform()) * np.exp(1j * rng.uniform(0, 2 * np.pi)) for h in holes]
+    gam = np.stack([np.log(np.abs(dom.eta - al)) for al in alphas], axis=1)
+    return dom, gam
+
+
+def config3(ndom: int = 64, **kw):
+    """The batched workload: `ndom` domains (see batch_domain)."""
+    return [batch_domain(d, **kw) for d in range(ndom)]
