@@ -8,12 +8,18 @@ unknowns, A = eta, gamma = -log|eta|): FBIE (right-hand side y, GMRES solve of
 FBIEad (GMRES solve of (diag(e) + B^T + Phat) mu = gamma), all on the GPU with
 the inputs resident in HBM.
 
-value = Cauchy pair evaluations per second over the step (pair x column,
-        counted from the launches the library actually made), in Gpair/s.
-roofline = the dominant kernel (single-column FP64 Cauchy sum), timed with
-        HIP events on the stream it runs on, against the FP64 vector peak.
-cpu_baseline = the CPU oracle's pair evaluation (dense kernel-matrix rows)
-        on a bounded sample of the same workload.
+value        Cauchy pair evaluations (pair x column, counted from the launches
+             the library made) per second over the timed steps, Gpair/s.
+roofline     the dominant kernel (the single-column FP64 pair kernel), timed
+             with HIP events recorded by the library on its own stream during
+             a second pass over the same steps, against the FP64 vector peak.
+cpu_baseline the CPU oracle's pair evaluation (dense kernel-matrix rows) on a
+             bounded sample of the same workload.
+mixed_vs_plain   solve time to the same tolerance on the 65-boundary
+             close-boundary workload (N = 133120), FP64 vs mixed precision.
+batched_vs_plain solve time on the 64-domain workload (1404 right-hand
+             sides): one batched call vs one FP64 call per domain and
+             right-hand side.
 """
 import argparse
 import json
@@ -27,6 +33,10 @@ sys.path.insert(0, ROOT)
 METRIC = "N/M matvec Gpair/s (% FP64 peak) + solve time to 1e-10, mixed/batched vs plain"
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, AMD public figure
 FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1), q (2), complex FMA (8)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(dom, budget_s=10.0):
@@ -51,12 +61,88 @@ def cpu_baseline(dom, budget_s=10.0):
                       f"(K_ij assembly + one product), {dt:.1f} s, NumPy single thread"}
 
 
+def rel(a, b, s):
+    return float((a - b).abs().max()) / max(float(b.abs().max()), s)
+
+
+def mixed_vs_plain(gnk, ctx, torch):
+    import workloads as wl
+    log("mixed vs plain: 65 close boundaries, N = 133120")
+    dom, gam = wl.config2()
+    dd = gnk.DeviceDomain.from_host(dom)
+    g = torch.from_numpy(gam[:, 0].copy()).cuda()
+    kw = dict(restart=256, maxit=8, tol=1e-14)
+    out = {"workload": "unbounded, 65 ellipses and Kress-graded rounded polygons, gaps 1e-3..1e-2 of size, "
+                       "n=2048, N=133120, A=1, gamma=Re(eta^2), GMRES restart 256, tol 1e-14"}
+    ctx.fbie(dd, g, **kw)           # warm-up (workspace, tables)
+    res = {}
+    for name, prec in (("plain", gnk.FP64), ("mixed", gnk.MIXED)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mu, h, inf, st = ctx.fbie(dd, g, prec=prec, **kw)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t, mu, inf[0], st)
+        log(f"  {name}: {res[name][0]:.3f} s, {inf[0]['inner_it']} iterations")
+    s = float(g.abs().max())
+    out.update({"plain_s": round(res["plain"][0], 4), "mixed_s": round(res["mixed"][0], 4),
+                "speedup": round(res["plain"][0] / res["mixed"][0], 3),
+                "iters": {"plain": res["plain"][2]["inner_it"], "mixed": res["mixed"][2]["inner_it"],
+                          "mixed_steps": res["mixed"][2]["mixed_steps"]},
+                "status": [res["plain"][3], res["mixed"][3]],
+                "mixed_vs_plain_rel_linf": rel(res["mixed"][1], res["plain"][1], s)})
+    return out
+
+
+def batched_vs_plain(gnk, ctx, torch):
+    import workloads as wl
+    batch = wl.config3()
+    log(f"batched vs plain: {len(batch)} domains, {sum(g.shape[1] for _, g in batch)} right-hand sides")
+    doms = [gnk.DeviceDomain.from_host(d) for d, _ in batch]
+    gams = [torch.from_numpy(g.copy()).cuda() for _, g in batch]
+    kw = dict(restart=50, maxit=20, tol=1e-12)
+    out = {"workload": "64 unbounded domains, m+1 in 2..40 circles/ellipses, n in 256..2048, m+1 right-hand "
+                       "sides log|eta - alpha_k| each (1404 columns), GMRES restart 50, tol 1e-12"}
+    ctx.fbie_batched(doms, gams, **kw)                       # autotuner + warm-up, both precisions
+    ctx.fbie_batched(doms, gams, prec=gnk.MIXED, **kw)
+    res = {}
+    for name, prec in (("batched_fp64", gnk.FP64), ("batched_mixed", gnk.MIXED)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mus, hs, infos, st = ctx.fbie_batched(doms, gams, prec=prec, **kw)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t, mus, st)
+        log(f"  {name}: {res[name][0]:.3f} s")
+    # plain: one FP64 solve per domain and right-hand side, in sequence
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain = []
+    for dd, g in zip(doms, gams):
+        cols = []
+        for k in range(g.shape[1]):
+            mu, h, inf, st = ctx.fbie(dd, g[:, k].contiguous(), **kw)
+            cols.append(mu)
+        plain.append(torch.stack(cols, dim=1))
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    log(f"  plain sequential: {tp:.3f} s")
+    err = max(rel(m, p, float(g.abs().max())) for m, p, g in zip(res["batched_fp64"][1], plain, gams))
+    errm = max(rel(m, p, float(g.abs().max())) for m, p, g in zip(res["batched_mixed"][1], plain, gams))
+    out.update({"plain_sequential_s": round(tp, 3), "batched_fp64_s": round(res["batched_fp64"][0], 3),
+                "batched_mixed_s": round(res["batched_mixed"][0], 3),
+                "speedup_fp64": round(tp / res["batched_fp64"][0], 3),
+                "speedup_mixed": round(tp / res["batched_mixed"][0], 3),
+                "status": [res["batched_fp64"][2], res["batched_mixed"][2]],
+                "batched_vs_plain_rel_linf": {"fp64": err, "mixed": errm}})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the mixed and batched comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
@@ -80,19 +166,25 @@ def main():
             raise RuntimeError(f"solve did not converge: {inf} {infa}")
         return inf[0], infa[0]
 
+    log(f"warm-up {args.warmup} steps")
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_read(reset=True)
-    # per-phase solve times (one extra pair of solves, outside the timed region)
+    # pass 1: timed steps (graph replay of the Arnoldi steps, no per-kernel events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
-    for _ in range(args.steps):
-        infos.append(step())
+    infos = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"timed {args.steps} steps: {(t1 - t0) * 1e3 / args.steps:.3f} ms/step")
+    # pass 2: the same steps with HIP events around every pair-kernel launch
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     prof = ctx.profile_read(reset=True)
     ctx.profile(False)
 
@@ -105,7 +197,8 @@ def main():
     tc = time.perf_counter()
 
     ms_step = (t1 - t0) * 1e3 / args.steps
-    value = prof["pair_cols"] / (t1 - t0) / 1e9
+    pair_cols_per_step = prof["pair_cols"] / args.steps
+    value = pair_cols_per_step / ((t1 - t0) / args.steps) / 1e9
     pairs1 = prof["pairs1"] / max(1, prof["launches1"])
     avg1_ms = prof["ms1"] / max(1, prof["launches1"])
     achieved = FLOPS_PER_PAIR * pairs1 / (avg1_ms * 1e-3) / 1e12
@@ -126,17 +219,22 @@ def main():
                                "N=17408, A=eta, gamma=-log|eta|; step = FBIE (mu, h) + FBIEad, GMRES "
                                "restart 25, tol 1e-12",
                    "N": dom.N, "m1": dom.m1, "n": dom.n, "precision": "fp64"},
-        "matvec": {"kernel": "k_cauchy_fp64<1>", "avg_ms": round(avg1_ms, 5),
+        "matvec": {"kernel": "k_pairs<1, TPT, false> (FP64, one column)", "avg_ms": round(avg1_ms, 5),
                    "gpair_s": round(pairs1 / (avg1_ms * 1e-3) / 1e9, 2),
                    "frac_fp64_peak": round(achieved / FP64_PEAK_TFLOPS, 4),
-                   "launches_per_step": prof["launches"] / args.steps},
+                   "launches_per_step": prof["launches"] / args.steps,
+                   "ms_per_step_with_events": round((t3 - t2) * 1e3 / args.steps, 4)},
         "solve_ms": {"fbie": round((tb - ta) * 1e3, 3), "fbie_ad": round((tc - tb) * 1e3, 3)},
         "gmres_iters": {"fbie": infos[-1][0]["inner_it"], "fbie_ad": infos[-1][1]["inner_it"]},
         "true_relres": {"fbie": infos[-1][0]["true_relres"], "fbie_ad": infos[-1][1]["true_relres"]},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None},
     }
+    if not args.no_compare:
+        out["mixed_vs_plain"] = mixed_vs_plain(gnk, ctx, torch)
+        out["batched_vs_plain"] = batched_vs_plain(gnk, ctx, torch)
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(dom)
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -134,8 +134,12 @@ typedef struct {
   double true_relres;
 } gnk_info;
 
-/* Context lifetime. device: HIP device ordinal. The default stream is the
- * null stream; gnk_set_stream installs a caller stream (hipStream_t). */
+/* Context lifetime. device: HIP device ordinal. The context owns a blocking
+ * stream of default priority, used unless gnk_set_stream installs a caller
+ * stream (hipStream_t; NULL selects the context's own stream again). The
+ * Arnoldi step of GMRES is captured once per solve into a hipGraph and
+ * replayed (GNK_GRAPH=0 disables this; so does profiling with gnk_profile);
+ * a caller stream must therefore be capturable (not the legacy null stream). */
 GNK_API gnk_status gnk_create(gnk_ctx** ctx, int device);
 GNK_API gnk_status gnk_destroy(gnk_ctx* ctx);
 GNK_API gnk_status gnk_set_stream(gnk_ctx* ctx, void* hip_stream);
@@ -164,7 +168,8 @@ typedef struct {
   double pair_cols_mixed;
 } gnk_prof;
 
-/* enable: 1 starts recording, 0 stops (already recorded launches are kept). */
+/* enable: 1 starts recording, 0 stops (already recorded launches are kept).
+ * While enabled, solves launch every kernel directly (no graph replay). */
 GNK_API gnk_status gnk_profile(gnk_ctx* ctx, int enable);
 /* Waits for the stream, folds the recorded launches into the totals, copies
  * them to *out (may be NULL), and clears them when reset != 0. */

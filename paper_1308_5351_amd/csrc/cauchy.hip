@@ -17,9 +17,9 @@
 //     chunk four ways, then add their sums through LDS in wave order;
 //   * the work is a list of items (domain, target tile, source split, column
 //     group) covering every domain of a batch in one launch per column-group
-//     width; workgroups stride over the list (largest domains first); the
-//     consumer adds the split partial sums in a fixed order, so results are
-//     bitwise reproducible;
+//     width, one workgroup per item (largest domains first); the consumer
+//     adds the split partial sums in a fixed order, so results are bitwise
+//     reproducible;
 //   * 1/|d|^2 comes from v_rcp_f64 refined by one Newton step; two sources
 //     share one reciprocal: 1/a = b/(ab), 1/b = a/(ab) (simultaneous
 //     inversion), which halves the v_rcp_f64 issues;
@@ -36,6 +36,18 @@ namespace gnk {
 
 namespace {
 
+// Pointers into global memory. In the device pass they carry address space 1,
+// so wave-uniform loads through them compile to scalar loads (a generic
+// pointer read from the domain table would give per-lane flat loads). The
+// host pass only parses kernel bodies and keeps plain pointers.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using gptr = T*;
+#endif
+
 // v_rcp_f64 is accurate to about 2^-24 on gfx950; one Newton step brings the
 // reciprocal to about 2^-48 (a few ulp), below the rounding of the sums.
 __device__ __forceinline__ double refine_rcp(double d) {
@@ -51,9 +63,8 @@ struct Acc {
 };
 
 // acc[t] += w * q for NR columns, q = conj(d)/|d|^2 = (qx, qy)
-template <int NR, int TPT>
-__device__ __forceinline__ void accumulate(Acc<NR, TPT>& a, int t, const double2* __restrict__ wj, double qx,
-                                           double qy) {
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void accumulate(Acc<NR, TPT>& a, int t, P wj, double qx, double qy) {
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const double2 w = wj[r];
@@ -66,9 +77,8 @@ __device__ __forceinline__ void accumulate(Acc<NR, TPT>& a, int t, const double2
 
 // two sources a, b (records ra, rb) against every target of the lane
 // ra, rb: source records (eta at [0]); the launch's weight columns start at [wo]
-template <int NR, int TPT>
-__device__ __forceinline__ void pair_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], const double2* __restrict__ ra,
-                                          const double2* __restrict__ rb, int wo) {
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void pair_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], P ra, P rb, int wo) {
   const double2 ea = ra[0], eb = rb[0];
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
@@ -83,9 +93,9 @@ __device__ __forceinline__ void pair_step(Acc<NR, TPT>& acc, const double2 (&tg)
   }
 }
 
-template <int NR, int TPT>
-__device__ __forceinline__ void single_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], const int (&ti)[TPT],
-                                            const double2* __restrict__ rj, int wo, int j, bool masked) {
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void single_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], const int (&ti)[TPT], P rj,
+                                            int wo, int j, bool masked) {
   const double2 e = rj[0];
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
@@ -111,9 +121,8 @@ struct Acc32 {
   float y[TPT][NR];
 };
 
-template <int NR, int TPT>
-__device__ __forceinline__ void accumulate32(Acc32<NR, TPT>& a, int t, const float2* __restrict__ wj, float qx,
-                                             float qy) {
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void accumulate32(Acc32<NR, TPT>& a, int t, P wj, float qx, float qy) {
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const float2 w = wj[r];
@@ -124,9 +133,8 @@ __device__ __forceinline__ void accumulate32(Acc32<NR, TPT>& a, int t, const flo
   }
 }
 
-template <int NR, int TPT>
-__device__ __forceinline__ void pair_step32(Acc32<NR, TPT>& acc, const float2 (&u)[TPT], const float2* __restrict__ ra,
-                                            const float2* __restrict__ rb, int wo) {
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void pair_step32(Acc32<NR, TPT>& acc, const float2 (&u)[TPT], P ra, P rb, int wo) {
   const float2 ea = ra[0], eb = rb[0];
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
@@ -141,153 +149,161 @@ __device__ __forceinline__ void pair_step32(Acc32<NR, TPT>& acc, const float2 (&
   }
 }
 
-// One launch: every item of the list. The four wavefronts of a workgroup share
-// the item's tile of 64*TPT targets and take consecutive quarters of its source
-// chunk; their sums are added through LDS in wave order. MIXED: far source
-// tiles of 64 nodes are summed in FP32 (see above).
+// One work item: the tile of 64*TPT targets starting at `base`, sources
+// [jb0, jb1) of the domain, weight columns wo-1 .. wo-1+NR-1. The four
+// wavefronts of the workgroup take consecutive quarters of the sources; their
+// sums are added through LDS in wave order. MIXED: far source tiles of 64
+// nodes are summed in FP32 (see above). All pointers are restrict-qualified
+// parameters, so after inlining the record loads are known not to alias the
+// partial-sum stores and stay scalar (wave-uniform) loads.
+template <int NR, int TPT, bool MIXED>
+__device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
+                                          gptr<const double4> tb, gptr<double2> part, int N, int stride, int wcols, int wo,
+                                          int base, int tile_idx, int g, int jb0, int jb1, int wchunk, double far2,
+                                          double (&red)[3][TPT][2][64]) {
+  constexpr int kTile = 64 * TPT;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j0 = min(jb1, jb0 + wv * wchunk);
+  const int j1 = min(jb1, j0 + wchunk);
+
+  double2 tg[TPT];
+  int ti[TPT];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    ti[t] = base + t * 64 + lane;
+    tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
+  }
+  Acc<NR, TPT> acc;
+#pragma unroll
+  for (int t = 0; t < TPT; ++t)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) { acc.x[t][r] = 0.0; acc.y[t][r] = 0.0; }
+
+  // sources outside the tile's own window need no j != i test
+  auto plain = [&](int ja, int jb) {
+    int j = ja;
+    for (; j + 3 < jb; j += 4) {
+      gptr<const double2> r = rec + (size_t)j * stride;
+      pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
+      pair_step<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
+    }
+    for (; j + 1 < jb; j += 2) {
+      gptr<const double2> r = rec + (size_t)j * stride;
+      pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
+    }
+    if (j < jb) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, false);
+  };
+  auto fp64_range = [&](int ja, int jb) {
+    plain(ja, min(jb, base));
+    const int ma = max(ja, base), mb = min(jb, base + kTile);
+    for (int j = ma; j < mb; ++j) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
+    plain(max(ja, base + kTile), jb);
+  };
+
+  if (!MIXED) {
+    fp64_range(j0, j1);
+  } else {
+    const double4 tbd = tb[tile_idx];
+    for (int ts = j0; ts < j1; ts += 64) {
+      const int te = min(ts + 64, j1);
+      const double4 sbd = sb[ts >> 6];
+      const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
+      const double rr = tbd.z + sbd.z;
+      if ((dcx * dcx + dcy * dcy) > far2 * rr * rr) {
+        float2 u[TPT];
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) u[t] = make_float2((float)(tg[t].x - sbd.x), (float)(tg[t].y - sbd.y));
+        Acc32<NR, TPT> a32;
+#pragma unroll
+        for (int t = 0; t < TPT; ++t)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) { a32.x[t][r] = 0.f; a32.y[t][r] = 0.f; }
+        int j = ts;
+#pragma unroll 2
+        for (; j + 1 < te; j += 2) {
+          gptr<const float2> r = rec32 + (size_t)j * stride;
+          pair_step32<NR, TPT>(a32, u, r, r + stride, wo);
+        }
+        if (j < te) {
+          gptr<const float2> r = rec32 + (size_t)j * stride;
+          const float2 e = r[0];
+#pragma unroll
+          for (int t = 0; t < TPT; ++t) {
+            const float dx = u[t].x - e.x, dy = u[t].y - e.y;
+            const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
+            accumulate32<NR, TPT>(a32, t, r + wo, dx * q, -dy * q);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < TPT; ++t)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            acc.x[t][r] += (double)a32.x[t][r];
+            acc.y[t][r] += (double)a32.y[t][r];
+          }
+      } else {
+        fp64_range(ts, te);
+      }
+    }
+  }
+
+  // fixed-order reduction over the four wavefronts, one column at a time
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (wv > 0) {
+#pragma unroll
+      for (int t = 0; t < TPT; ++t) {
+        red[wv - 1][t][0][lane] = acc.x[t][r];
+        red[wv - 1][t][1][lane] = acc.y[t][r];
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int t = 0; t < TPT; ++t) {
+        double x = acc.x[t][r], y = acc.y[t][r];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          x += red[q][t][0][lane];
+          y += red[q][t][1][lane];
+        }
+        if (ti[t] < N) part[((size_t)g * wcols + wo - 1 + r) * N + ti[t]] = make_double2(x, y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One launch: one workgroup per item of the list. (A workgroup that looped
+// over several items would store partial sums before loading the next item's
+// records, and the records could then no longer be fetched with scalar loads.)
 template <int NR, int TPT, bool MIXED>
 __global__ __launch_bounds__(256) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
                                                int nitems, int lead, int data, const int* __restrict__ active) {
-  constexpr int kTile = 64 * TPT;
   __shared__ double red[3][TPT][2][64];
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int4 w = items[it];
-    const DomDev& D = doms[w.x];
-    const int N = D.N;
-    const int wcols = lead + data * D.ncols;
-    const int stride = wcols + 1;
-    const double2* __restrict__ rec = D.rec;
-    if (active != nullptr) {
-      bool any = false;
+  const int it = blockIdx.x;
+  if (it >= nitems) return;
+  const int4 w = items[it];
+  const DomDev& D = doms[w.x];
+  const int wcols = lead + data * D.ncols;
+  if (active != nullptr) {
+    bool any = false;
 #pragma unroll
-      for (int q = 0; q < NR; ++q) {
-        const int col = w.w + q - lead;
-        any = any || col < 0 || active[D.c0 + col] != 0;
-      }
-      if (!any) continue;
+    for (int q = 0; q < NR; ++q) {
+      const int col = w.w + q - lead;
+      any = any || col < 0 || active[D.c0 + col] != 0;
     }
-    const int base = w.y * kTile;
-    const int g = w.z;
-    const int chunk = D.chunk;
-    const int jb0 = g * chunk;
-    const int jb1 = min(N, jb0 + chunk);
-    // quarter of the chunk per wave: multiple of 4 (FP64) or whole 64-node tiles (mixed)
-    const int wchunk = MIXED ? (chunk >> 2) : (((chunk + 15) >> 4) << 2);
-    const int j0 = min(jb1, jb0 + wv * wchunk);
-    const int j1 = min(jb1, j0 + wchunk);
-    const int wo = 1 + w.w;
-
-    double2 tg[TPT];
-    int ti[TPT];
-#pragma unroll
-    for (int t = 0; t < TPT; ++t) {
-      ti[t] = base + t * 64 + lane;
-      tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
-    }
-    Acc<NR, TPT> acc;
-#pragma unroll
-    for (int t = 0; t < TPT; ++t)
-#pragma unroll
-      for (int r = 0; r < NR; ++r) { acc.x[t][r] = 0.0; acc.y[t][r] = 0.0; }
-
-    // sources outside the tile's own window need no j != i test
-    auto plain = [&](int ja, int jb) {
-      int j = ja;
-      for (; j + 3 < jb; j += 4) {
-        const double2* r = rec + (size_t)j * stride;
-        pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
-        pair_step<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
-      }
-      for (; j + 1 < jb; j += 2) {
-        const double2* r = rec + (size_t)j * stride;
-        pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
-      }
-      if (j < jb) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, false);
-    };
-    auto fp64_range = [&](int ja, int jb) {
-      plain(ja, min(jb, base));
-      const int ma = max(ja, base), mb = min(jb, base + kTile);
-      for (int j = ma; j < mb; ++j) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
-      plain(max(ja, base + kTile), jb);
-    };
-
-    if (!MIXED) {
-      fp64_range(j0, j1);
-    } else {
-      const double4 tbd = D.tb[w.y];
-      const float2* __restrict__ rec32 = D.rec32;
-      for (int ts = j0; ts < j1; ts += 64) {
-        const int te = min(ts + 64, j1);
-        const double4 sbd = D.sb[ts >> 6];
-        const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
-        const double rr = tbd.z + sbd.z;
-        if ((dcx * dcx + dcy * dcy) > D.far2 * rr * rr) {
-          float2 u[TPT];
-#pragma unroll
-          for (int t = 0; t < TPT; ++t) u[t] = make_float2((float)(tg[t].x - sbd.x), (float)(tg[t].y - sbd.y));
-          Acc32<NR, TPT> a32;
-#pragma unroll
-          for (int t = 0; t < TPT; ++t)
-#pragma unroll
-            for (int r = 0; r < NR; ++r) { a32.x[t][r] = 0.f; a32.y[t][r] = 0.f; }
-          int j = ts;
-#pragma unroll 2
-          for (; j + 1 < te; j += 2) {
-            const float2* r = rec32 + (size_t)j * stride;
-            pair_step32<NR, TPT>(a32, u, r, r + stride, wo);
-          }
-          if (j < te) {
-            const float2* r = rec32 + (size_t)j * stride;
-            const float2 e = r[0];
-#pragma unroll
-            for (int t = 0; t < TPT; ++t) {
-              const float dx = u[t].x - e.x, dy = u[t].y - e.y;
-              const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
-              accumulate32<NR, TPT>(a32, t, r + wo, dx * q, -dy * q);
-            }
-          }
-#pragma unroll
-          for (int t = 0; t < TPT; ++t)
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-              acc.x[t][r] += (double)a32.x[t][r];
-              acc.y[t][r] += (double)a32.y[t][r];
-            }
-        } else {
-          fp64_range(ts, te);
-        }
-      }
-    }
-
-    // fixed-order reduction over the four wavefronts, one column at a time
-    double2* __restrict__ part = D.parts;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (wv > 0) {
-#pragma unroll
-        for (int t = 0; t < TPT; ++t) {
-          red[wv - 1][t][0][lane] = acc.x[t][r];
-          red[wv - 1][t][1][lane] = acc.y[t][r];
-        }
-      }
-      __syncthreads();
-      if (wv == 0) {
-#pragma unroll
-        for (int t = 0; t < TPT; ++t) {
-          double x = acc.x[t][r], y = acc.y[t][r];
-#pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            x += red[q][t][0][lane];
-            y += red[q][t][1][lane];
-          }
-          if (ti[t] < N) part[((size_t)g * wcols + w.w + r) * N + ti[t]] = make_double2(x, y);
-        }
-      }
-      __syncthreads();
-    }
+    if (!any) return;
   }
+  const int chunk = D.chunk;
+  const int jb0 = w.z * chunk;
+  const int jb1 = min(D.N, jb0 + chunk);
+  // quarter of the chunk per wave: multiple of 4 (FP64) or whole 64-node tiles (mixed)
+  const int wchunk = MIXED ? (chunk >> 2) : (((chunk + 15) >> 4) << 2);
+  pair_item<NR, TPT, MIXED>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
+                            (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, wcols + 1, wcols, 1 + w.w, w.y * 64 * TPT,
+                            w.y, w.z, jb0, jb1, wchunk, D.far2, red);
 }
 
 // bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of
@@ -357,9 +373,9 @@ void launch_w(const DomDev* doms, const int4* items, int nitems, int tpt, int le
 }  // namespace
 
 hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
-                        bool mixed, const int* active, int grid, hipStream_t st) {
+                        bool mixed, const int* active, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  if (grid <= 0 || grid > nitems) grid = nitems;
+  const int grid = nitems;
   switch (width) {
     case 8: launch_w<8>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;
     case 4: launch_w<4>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;

@@ -54,11 +54,11 @@ struct ColDev {
 // domain's data columns):
 //   parts_d[(g*wcols_d + q)*N_d + i] = sum_{j in split g, j != i} w_jq / (eta_i - eta_j)
 // items: int4 {d, target tile, split, first weight column}; `width` columns per
-// item (8, 4, 2 or 1). mixed: FP32 for far 64-node source tiles (rec32, sb, tb).
-// active: optional per global column mask; an item whose data columns are all
-// inactive is skipped. grid: number of workgroups (they stride over the items).
+// item (8, 4, 2 or 1), one workgroup per item. mixed: FP32 for far 64-node
+// source tiles (rec32, sb, tb). active: optional per global column mask; an
+// item whose data columns are all inactive is skipped.
 hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
-                        bool mixed, const int* active, int grid, hipStream_t st);
+                        bool mixed, const int* active, hipStream_t st);
 
 // bounding circles of the tiles of `tile` nodes of every domain (source tiles
 // of 64 nodes into sb, target tiles into tb)

@@ -23,6 +23,7 @@ struct GmresState {
   int* kdim;            // Krylov dimension reached in this cycle
   int* inner_it;        // total Arnoldi steps
   int* live;            // number of active columns (single int)
+  int* step;            // current Arnoldi step l of the cycle (single int)
   int ldh;              // restart + 1
   int hstride;          // ldh * restart
 };

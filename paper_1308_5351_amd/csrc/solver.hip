@@ -30,7 +30,9 @@
 
 struct gnk_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // stream of all work (the caller's, or own_stream)
+  hipStream_t own_stream = nullptr;   // blocking, default priority: capturable into graphs
+  bool graphs = true;                 // replay the Arnoldi step from a captured hipGraph
   std::string err;
   int num_cu = 256;
   size_t ws_limit = 0;   // bytes, 0 = unlimited
@@ -57,7 +59,7 @@ struct gnk_ctx {
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
   gnk_prof prof_acc{};
-  // autotuner results: key -> "tpt chunk persistent"
+  // autotuner results: key -> "tpt chunk"
   std::map<std::string, std::string> tune;
   bool tune_loaded = false;
   // host copies of uploaded tables stay alive until the next call
@@ -148,7 +150,6 @@ constexpr int kWidths[4] = {8, 4, 2, 1};
 struct PairShape {
   int tpt = 1;
   int chunk = 0;        // sources per workgroup (0: single-domain plan)
-  int persistent = 0;   // workgroups striding over the items (0: one per item)
 };
 
 struct Batch {
@@ -388,9 +389,8 @@ void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
   }
   for (int k = 0; k < 4; ++k) {
     if (!S.cnt[k]) continue;
-    const int grid = B.shape.persistent > 0 ? std::min(S.cnt[k], B.shape.persistent) : S.cnt[k];
     HIPCHK(c, launch_pairs(B.d_dom, S.d[k], S.cnt[k], kWidths[k], B.shape.tpt, kLead[p], kData[p], mixed, active,
-                           grid, c->stream));
+                           c->stream));
   }
   if (c->prof) {
     HIPCHK(c, hipEventRecord(pr.b, c->stream));
@@ -481,7 +481,9 @@ struct ApplyArgs {
   const double* scale = nullptr;
   double* xout = nullptr;
   const int* active = nullptr;
-  bool mixed = false;      // FP32 far tiles (batch built with mixed records)
+  bool mixed = false;        // FP32 far tiles (batch built with mixed records)
+  const int* step = nullptr; // x = V_l (x, xout advanced by l*stepT), y = V_{l+1}; l read on the device
+  int64_t stepT = 0;
 };
 
 void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const ApplyArgs& a = {}) {
@@ -513,13 +515,13 @@ void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const Ap
   }
   const int M = B.maxm1;
   double* mean = need_mean ? ws<double>(c, "mean", (size_t)B.ncol * M) : nullptr;
-  k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(B.d_dom, B.d_col, cw, x, a.scale,
-                                                                            a.active, a.xout, 0, mean, M);
+  k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
+      B.d_dom, B.d_col, cw, x, a.scale, a.active, a.xout, 0, mean, M, a.step, a.stepT);
   LAUNCHCHK(c);
   const double* xin = a.xout ? a.xout : x;
   pairs(c, B, P_GM, a.mixed, a.active);
   k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, xin, cout, dsel, a0, dsign, cI, cR, mean, M,
-                                                a.active, 0, y);
+                                                a.active, 0, y, a.step, a.stepT);
   LAUNCHCHK(c);
   if (op == GNK_OP_FC || op == GNK_OP_FC_T) circulant(c, B, xin, y, op == GNK_OP_FC ? 1.0 : -1.0);
 }
@@ -556,7 +558,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   st.hstride = st.ldh * restart;
   double* dbl = ws<double>(c, "gmdbl", (size_t)ncol * (4 + st.hstride + 2 * kMaxRestart + (kMaxRestart + 1) +
                                                      kMaxRestart));
-  int* ints = ws<int>(c, "gmint", (size_t)ncol * 5 + 1);
+  int* ints = ws<int>(c, "gmint", (size_t)ncol * 5 + 2);
   {
     double* q = dbl;
     st.bnorm = q; q += ncol;
@@ -574,6 +576,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     st.kdim = r; r += ncol;
     st.inner_it = r; r += ncol;
     st.live = r;
+    st.step = r + 1;
   }
   const unsigned cb = nblocks(ncol, 256);
   k_gmres_init<<<cb, 256, 0, c->stream>>>(ncol, st);
@@ -585,7 +588,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   LAUNCHCHK(c);
 
   auto cycle_start = [&](const double* partial) {
-    k_zero_int<<<1, 1, 0, c->stream>>>(st.live);
+    k_cycle_reset<<<1, 1, 0, c->stream>>>(st);
     LAUNCHCHK(c);
     k_cycle_start<<<cb, 256, 0, c->stream>>>(partial, nblk, ldp, ncol, o.tol, st);
     LAUNCHCHK(c);
@@ -603,6 +606,72 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   }
   LAUNCHCHK(c);
   cycle_start(P1);
+
+  // With relaxed (mixed) products the residual estimate runs slightly ahead
+  // of the true residual, so a mixed cycle aims at half the tolerance; the
+  // convergence test itself always uses the FP64 true residual.
+  const double stop_tol = mixed ? 0.5 * o.tol : o.tol;
+  // One Arnoldi step for every column; the step index l lives on the device
+  // (reset at each cycle start, advanced by the last kernel of the step), so
+  // the same sequence of launches serves every step and can be captured once.
+  auto enqueue_step = [&](bool use_mixed) {
+    ApplyArgs aa;
+    aa.scale = st.invbeta;
+    aa.xout = V;
+    aa.active = st.active;
+    aa.mixed = use_mixed;
+    aa.step = st.step;
+    aa.stepT = T;
+    apply_op(c, B, op, V, V, aa);
+    k_gs_dot<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, st.step, per_blk, st.active, P1, ldp);
+    LAUNCHCHK(c);
+    k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, st.active, P1, P2, ldp, st, 0, 1);
+    LAUNCHCHK(c);
+    k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, st.active, P2, P1, ldp, st, 1, 0);
+    LAUNCHCHK(c);
+    k_arnoldi_finish<<<(unsigned)ncol, 64, 0, c->stream>>>(P1, nblk, ldp, restart, stop_tol, st);
+    LAUNCHCHK(c);
+    k_step_next<<<1, 1, 0, c->stream>>>(st);
+    LAUNCHCHK(c);
+  };
+  // Every buffer the step touches exists before a capture (no allocation,
+  // upload or event record may happen inside it). Profiling times each pair
+  // launch with events and so runs the steps without a graph.
+  build_items(c, B, P_GM);
+  if (op == GNK_OP_GB || op == GNK_OP_GB_T) (void)ws<double>(c, "mean", (size_t)B.ncol * B.maxm1);
+  const bool use_graph = c->graphs && !c->prof;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  struct ExecGuard {
+    hipGraphExec_t* e;
+    ~ExecGuard() {
+      for (int k = 0; k < 2; ++k)
+        if (e[k]) (void)hipGraphExecDestroy(e[k]);
+    }
+  } guard{exec};
+  auto launch_step = [&](bool use_mixed) {
+    if (!use_graph) {
+      enqueue_step(use_mixed);
+      return;
+    }
+    hipGraphExec_t& ge = exec[use_mixed ? 1 : 0];
+    if (!ge) {
+      hipGraph_t graph = nullptr;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+      try {
+        enqueue_step(use_mixed);
+      } catch (...) {
+        hipGraph_t g2 = nullptr;
+        (void)hipStreamEndCapture(c->stream, &g2);
+        if (g2) (void)hipGraphDestroy(g2);
+        throw;
+      }
+      HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+      const hipError_t e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(c, e);
+    }
+    HIPCHK(c, hipGraphLaunch(ge, c->stream));
+  };
 
   std::vector<int> outer(ncol, 0), conv(ncol, 0), mixed_steps(ncol, 0);
   bool mixed_now = false;
@@ -631,27 +700,11 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     // still iterating, so the queue never drains and at most one speculative
     // step runs (fully masked) after the last column stops.
     for (int l = 0; l < restart; ++l) {
-      double* vl = V + (size_t)l * T;
-      double* w = V + (size_t)(l + 1) * T;
-      ApplyArgs aa;
-      aa.scale = st.invbeta;
-      aa.xout = vl;
-      aa.active = st.active;
-      aa.mixed = mixed && mixed_now;
-      if (aa.mixed)
+      const bool use_mixed = mixed && mixed_now;
+      if (use_mixed)
         for (int q = 0; q < ncol; ++q)
           if (!conv[q]) mixed_steps[q] += 1;
-      apply_op(c, B, op, vl, w, aa);
-      k_gs_dot<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, l + 1, w, per_blk, st.active, P1, ldp);
-      LAUNCHCHK(c);
-      k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, l + 1, w, per_blk, st.active, P1, P2, ldp, st,
-                                            l, 0, 1);
-      LAUNCHCHK(c);
-      k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, l + 1, w, per_blk, st.active, P2, P1, ldp, st,
-                                            l, 1, 0);
-      LAUNCHCHK(c);
-      k_arnoldi_finish<<<(unsigned)ncol, 64, 0, c->stream>>>(P1, nblk, ldp, l, restart, o.tol, st);
-      LAUNCHCHK(c);
+      launch_step(use_mixed);
       HIPCHK(c, hipMemcpyAsync(c->pinned + l, st.live, sizeof(int), hipMemcpyDeviceToHost, c->stream));
       if (mixed && !mixed_now)
         HIPCHK(c, hipMemcpyAsync(c->pinned_rel + (size_t)l * ncol, st.relres, sizeof(double) * ncol,
@@ -731,10 +784,10 @@ gnk_opts resolve_opts(gnk_ctx* c, const gnk_opts* o) {
 }
 
 // ------------------------------------------------------------- autotuner
-// Picks the pair-kernel launch shape (targets per lane, sources per workgroup,
-// persistent grid) for a batch by timing the Cauchy sums of one product per
+// Picks the pair-kernel launch shape (targets per lane, sources per
+// workgroup) for a batch by timing the Cauchy sums of one product per
 // candidate; results are cached per batch signature in the context and, with
-// GNK_TUNE_CACHE=path, in a text file ("key tpt chunk persistent" per line).
+// GNK_TUNE_CACHE=path, in a text file ("key tpt chunk" per line).
 std::string tune_key(const gnk_ctx* c, int ndom, const gnk_domain* doms, const int* ncols, bool mixed) {
   std::vector<std::pair<int64_t, int>> v;
   for (int d = 0; d < ndom; ++d) v.push_back({doms[d].m1 * doms[d].n, ncols[d]});
@@ -772,7 +825,6 @@ PairShape tuned_shape(gnk_ctx* c, int ndom, const gnk_domain* doms, const int* n
   PairShape def;
   def.tpt = 1;
   def.chunk = 2048;
-  def.persistent = 0;
   const char* env = getenv("GNK_TUNE");
   if (env && atoi(env) == 0) return def;
   load_tune_cache(c);
@@ -781,13 +833,9 @@ PairShape tuned_shape(gnk_ctx* c, int ndom, const gnk_domain* doms, const int* n
   if (it != c->tune.end()) {
     std::istringstream s(it->second);
     PairShape p;
-    if (s >> p.tpt >> p.chunk >> p.persistent) return p;
+    if (s >> p.tpt >> p.chunk) return p;
   }
-  const int64_t slots = slots_of(c);
-  std::vector<PairShape> cand;
-  for (int tpt : {1, 2})
-    for (int chunk : {1024, 2048, 4096, 8192})
-      for (int pers : {0, (int)(slots / 4)}) cand.push_back(PairShape{tpt, chunk, pers});
+  const std::vector<PairShape> cand = {{1, 512}, {1, 2048}, {2, 1024}, {2, 4096}};
   hipEvent_t a, b;
   HIPCHK(c, hipEventCreate(&a));
   HIPCHK(c, hipEventCreate(&b));
@@ -801,16 +849,17 @@ PairShape tuned_shape(gnk_ctx* c, int ndom, const gnk_domain* doms, const int* n
     k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
     LAUNCHCHK(c);
     k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
-        B.d_dom, B.d_col, C_RHO, x_flat, nullptr, nullptr, nullptr, 0, nullptr, B.maxm1);
+        B.d_dom, B.d_col, C_RHO, x_flat, nullptr, nullptr, nullptr, 0, nullptr, B.maxm1, nullptr, 0);
     LAUNCHCHK(c);
-    pairs(c, B, P_GM, mixed, nullptr);   // warm-up; builds the items
+    build_items(c, B, P_GM);
+    if (&p == &cand[0]) pairs(c, B, P_GM, mixed, nullptr);   // first launch of the kernels
     HIPCHK(c, hipEventRecord(a, c->stream));
     pairs(c, B, P_GM, mixed, nullptr);
     HIPCHK(c, hipEventRecord(b, c->stream));
     HIPCHK(c, hipEventSynchronize(b));
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, a, b));
-    if (c->log) fprintf(stderr, "[gnk] tune tpt %d chunk %d grid %d: %.3f ms\n", p.tpt, p.chunk, p.persistent, ms);
+    if (c->log) fprintf(stderr, "[gnk] tune tpt %d chunk %d: %.3f ms\n", p.tpt, p.chunk, ms);
     if (ms < best) {
       best = ms;
       bestp = p;
@@ -820,7 +869,7 @@ PairShape tuned_shape(gnk_ctx* c, int ndom, const gnk_domain* doms, const int* n
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   std::ostringstream v;
-  v << bestp.tpt << " " << bestp.chunk << " " << bestp.persistent;
+  v << bestp.tpt << " " << bestp.chunk;
   store_tune_cache(c, key, v.str());
   return bestp;
 }
@@ -834,7 +883,7 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
   LAUNCHCHK(c);
   // one launch for E(rho) (leading column) and E(rho gamma) (data columns)
   k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
-      B.d_dom, B.d_col, C_RHO, gam, nullptr, nullptr, nullptr, 1, nullptr, B.maxm1);
+      B.d_dom, B.d_col, C_RHO, gam, nullptr, nullptr, nullptr, 1, nullptr, B.maxm1, nullptr, 0);
   LAUNCHCHK(c);
   pairs(c, B, P_SETUP, false, nullptr);
   k_diag_fbie<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, 1, 1);
@@ -842,7 +891,7 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
   // b = -y = -(D - diag(D1) + Lhat) gamma
   double* b = ws<double>(c, "rhs", T);
   k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_D, 0.0, 1.0, 0.0, 1.0, nullptr, 0,
-                                                nullptr, 1, b);
+                                                nullptr, 1, b, nullptr, 0);
   LAUNCHCHK(c);
   circulant(c, B, gam, b, -1.0);
   // f_B(gamma) from the same sums, for h
@@ -850,7 +899,7 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
   if (h) {
     fbg = ws<double>(c, "fbg", T);
     k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_B, 2.0, 1.0, 1.0, 0.0, nullptr, 0,
-                                                  nullptr, 1, fbg);
+                                                  nullptr, 1, fbg, nullptr, 0);
     LAUNCHCHK(c);
   }
   // (2I + diag(B1) - B) mu = b
@@ -927,6 +976,15 @@ gnk_status gnk_create(gnk_ctx** out, int device) {
     c->num_cu = prop.multiProcessorCount;
   if (const char* s = getenv("GNK_WORKSPACE_MB")) c->ws_limit = (size_t)atoll(s) << 20;
   if (const char* s = getenv("GNK_LOG")) c->log = atoi(s) != 0;
+  if (const char* s = getenv("GNK_GRAPH")) c->graphs = atoi(s) != 0;
+  // a blocking stream of default priority: ordered with the legacy null
+  // stream, and capturable (the null stream cannot be captured)
+  if (hipStreamCreate(&c->own_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return GNK_ERR_HIP;
+  }
+  c->stream = c->own_stream;
   *out = c;
   return GNK_OK;
 }
@@ -934,8 +992,7 @@ gnk_status gnk_create(gnk_ctx** out, int device) {
 gnk_status gnk_destroy(gnk_ctx* c) {
   if (!c) return GNK_ERR_ARG;
   (void)hipSetDevice(c->device);
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  else (void)hipDeviceSynchronize();
+  (void)hipStreamSynchronize(c->stream);
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto e : c->step_ev) (void)hipEventDestroy(e);
@@ -946,13 +1003,14 @@ gnk_status gnk_destroy(gnk_ctx* c) {
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->pinned_rel) (void)hipHostFree(c->pinned_rel);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
   return GNK_OK;
 }
 
 gnk_status gnk_set_stream(gnk_ctx* c, void* s) {
   if (!c) return GNK_ERR_ARG;
-  c->stream = static_cast<hipStream_t>(s);
+  c->stream = s ? static_cast<hipStream_t>(s) : c->own_stream;
   return GNK_OK;
 }
 

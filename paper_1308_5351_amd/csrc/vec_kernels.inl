@@ -133,13 +133,20 @@ __global__ void k_evec(const DomDev* __restrict__ doms) {
 //   v = x * scale[c]                  (optional; written back to xout)
 //   mean[c*M + k] = (1/n) sum_p v_{k n + p}   (optional, component means)
 // grid (max m1, ncol): block (k, c) covers component k of column c.
+// step/stepT: when step is given, x and xout are advanced by (*step) * stepT
+// (the Arnoldi vector of the current step, so one captured graph serves every step).
 __global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
                                                 int csel, const double* __restrict__ x,
                                                 const double* __restrict__ scale, const int* __restrict__ active,
                                                 double* __restrict__ xout, int lead, double* __restrict__ mean,
-                                                int M) {
+                                                int M, const int* __restrict__ step, int64_t stepT) {
   __shared__ double sh[kT / 64];
   const int k = blockIdx.x, c = blockIdx.y;
+  if (step) {
+    const int64_t sh_ = (int64_t)(*step) * stepT;
+    x += sh_;
+    if (xout) xout += sh_;
+  }
   const ColDev C = cols[c];
   const DomDev& D = doms[C.d];
   if (k >= D.m1) return;
@@ -201,8 +208,12 @@ __global__ void k_reduce_parts(const DomDev* __restrict__ doms, double2* __restr
 __global__ void k_epilogue(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
                            const double* __restrict__ x, int csel_out, int dsel, double a0, double dsign, double cI,
                            double cR, const double* __restrict__ mean, int M, const int* __restrict__ active,
-                           int lead, double* __restrict__ y) {
+                           int lead, double* __restrict__ y, const int* __restrict__ step, int64_t stepT) {
   const int c = blockIdx.y;
+  if (step) {   // x = V_l, y = V_{l+1}
+    x += (int64_t)(*step) * stepT;
+    y += (int64_t)(*step + 1) * stepT;
+  }
   const ColDev C = cols[c];
   const DomDev& D = doms[C.d];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -256,13 +267,16 @@ __device__ __forceinline__ void chunk_dots(const double* __restrict__ V, int64_t
   }
 }
 
+// Arnoldi step l = *step: w = V_{l+1}, dots with V_0..V_l
 __global__ __launch_bounds__(kT) void k_gs_dot(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
-                                               const double* __restrict__ V, int64_t T, int nvec,
-                                               const double* __restrict__ w, int per_blk,
+                                               const double* __restrict__ V, int64_t T,
+                                               const int* __restrict__ step, int per_blk,
                                                const int* __restrict__ active, double* __restrict__ partial,
                                                int ldp) {
   const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
   if (!active[c]) return;
+  const int nvec = *step + 1;
+  const double* __restrict__ w = V + (size_t)nvec * T;
   const ColDev C = cols[c];
   const int N = doms[C.d].N;
   double* out = partial + ((size_t)c * nblk + blk) * ldp;
@@ -277,17 +291,20 @@ __global__ __launch_bounds__(kT) void k_gs_dot(const DomDev* __restrict__ doms, 
 // h_l = sum over blocks of pin (fixed order); w -= sum_l h_l V_l on this
 // block's chunk; H[:, col] (+)= h (block 0); then pout = the chunk's dots of
 // the updated w with V_0..V_{nvec-1} (do_dots) or its squared norm (entry 0).
+// Arnoldi step l = *step: w = V_{l+1} against V_0..V_l, Hessenberg column l
 __global__ __launch_bounds__(kT) void k_gs_update(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
-                                                  const double* __restrict__ V, int64_t T, int nvec,
-                                                  double* __restrict__ w, int per_blk,
+                                                  double* __restrict__ V, int64_t T, int per_blk,
                                                   const int* __restrict__ active, const double* __restrict__ pin,
-                                                  double* __restrict__ pout, int ldp, GmresState st, int col,
+                                                  double* __restrict__ pout, int ldp, GmresState st,
                                                   int accumulate_h, int do_dots) {
   __shared__ double h[kMaxRestart + 1];
   __shared__ double sw[kMaxChunk];
   __shared__ double sh[kT / 64];
   const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
   if (!active[c]) return;
+  const int col = *st.step;
+  const int nvec = col + 1;
+  double* __restrict__ w = V + (size_t)nvec * T;
   const ColDev C = cols[c];
   const int N = doms[C.d].N;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -400,18 +417,26 @@ __global__ void k_cycle_start(const double* partial, int nblk, int ldp, int ncol
   }
 }
 
-__global__ void k_zero_int(int* p) { *p = 0; }
+// start of a cycle: no iterating column counted yet, Arnoldi step 0
+__global__ void k_cycle_reset(GmresState st) {
+  *st.live = 0;
+  *st.step = 0;
+}
+
+// end of an Arnoldi step (a separate launch, after every reader of the step)
+__global__ void k_step_next(GmresState st) { *st.step += 1; }
 
 // End of Arnoldi step `col`; one 64-lane block per column c: beta = ||w||
 // from the partials, H(col+1, col) = beta, Givens rotations applied in LDS,
 // residual estimate, stop test for this cycle.
-__global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, int nblk, int ldp, int col,
-                                                       int restart, double tol, GmresState st) {
+__global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, int nblk, int ldp, int restart,
+                                                       double tol, GmresState st) {
   __shared__ double hc[kMaxRestart + 2];
   __shared__ double cs_[kMaxRestart + 1];
   __shared__ double sn_[kMaxRestart + 1];
   const int c = blockIdx.x, lane = threadIdx.x;
   if (!st.active[c]) return;
+  const int col = *st.step;
   double s = 0.0;
   for (int b = lane; b < nblk; b += 64) s += partial[((size_t)c * nblk + b) * ldp];
   s = wave_sum(s);

@@ -161,9 +161,12 @@ class Context:
             pass
 
     def _bind_stream(self):
+        # torch's default stream is the legacy null stream, which cannot be
+        # captured: the context then keeps its own blocking stream (ordered
+        # with the null stream); another current stream is passed through.
         s = torch.cuda.current_stream(self.device).cuda_stream
         if s != self._stream:
-            self.lib.gnk_set_stream(self.h, C.c_void_p(s))
+            self.lib.gnk_set_stream(self.h, C.c_void_p(s) if s else None)
             self._stream = s
 
     def _raise(self, st, allow_not_converged=True):

@@ -78,7 +78,7 @@ def test_batched_tune_cache(gk, monkeypatch, tmp_path):
     m1, _, _, st1 = c1.fbie_batched(doms, gams, want_h=False)
     c1.close()
     lines = path.read_text().strip().splitlines()
-    assert len(lines) == 1 and len(lines[0].split()) == 4
+    assert len(lines) == 1 and len(lines[0].split()) == 3
     c2 = gk.Context(0)
     m2, _, _, st2 = c2.fbie_batched(doms, gams, want_h=False)
     c2.close()
