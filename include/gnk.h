@@ -217,6 +217,56 @@ GNK_API gnk_status gnk_fbie_batched(gnk_ctx* ctx, int ndom, const gnk_domain* do
                                     const int* nrhs, const gnk_opts* opts, double* const* mu, double* const* h,
                                     gnk_info* info);
 
+/* ------------------------------------------------------------------------
+ * Differentiation (reverse mode). L is any real function of the FBIE outputs;
+ * g_mu = dL/dmu and g_h = dL/dh are its cotangents. From
+ *   Aop mu = -Cop gamma,  h = (Cop mu - Aop gamma)/2,
+ *   Aop = 2I + diag(B1) - B (eq. (e:sys)),  Cop = D - diag(D1) + Lhat ((e:y), (e:bh)):
+ *   lam       = Aop^{-T} (Cop^T g_h / 2 + g_mu)            (adjoint GMRES)
+ *   dL/dgamma = -Aop^T g_h / 2 - Cop^T lam
+ *   dL (geometry) = (g_h/2)^T dCop mu - (g_h/2)^T dAop gamma
+ *                   - lam^T dAop mu - lam^T dCop gamma
+ * The transposes use B^T x = (2/n) Im[(eta'/A) E(A x)] (eq. (e:BTx)) and its
+ * real part for D^T, and L^T = -L. Complex gradients follow the convention of
+ * torch.autograd: g = dL/dRe z + i dL/dIm z.
+ * ------------------------------------------------------------------------ */
+
+/* Adjoint solve of FBIE for nrhs columns.
+ *   g_mu, g_h : N x nrhs real cotangents (either may be NULL = zero, not both)
+ *   lam       : N x nrhs real output (the adjoint variable above)
+ *   g_gam     : N x nrhs real output dL/dgamma (may be NULL)
+ *   opts      : GMRES options for the transposed system (opts->x0: initial lam)
+ *   info      : host array of nrhs entries or NULL. */
+GNK_API gnk_status gnk_fbie_adjoint(gnk_ctx* ctx, const gnk_domain* dom, const double* g_mu, const double* g_h,
+                                    int nrhs, const gnk_opts* opts, double* lam, double* g_gam, gnk_info* info);
+
+/* Gradient of s = sum_t coef[t] * u_t^T Op_t v_t with respect to the boundary
+ * data eta, eta', A (the operators' dependence through K_ij =
+ * (2/n)(A_i/A_j) eta'_j/(eta_j - eta_i), eqs. (e:N), (e:M)).
+ *   nterms : 1..64;  ops: host array, each GNK_OP_FB or GNK_OP_FC
+ *   coef   : host array of real factors, or NULL (all 1)
+ *   u, v   : host arrays of nterms device pointers to real N-vectors (terms
+ *            with the same v pointer share work)
+ *   g_eta, g_etap, g_A : N complex outputs (overwritten); any may be NULL,
+ *            not all. FP64, every pair evaluated directly. */
+GNK_API gnk_status gnk_geom_vjp(gnk_ctx* ctx, const gnk_domain* dom, int nterms, const int* ops, const double* coef,
+                                const double* const* u, const double* const* v, void* g_eta, void* g_etap,
+                                void* g_A);
+
+/* Boundary curves given by Fourier series, m1 components of n nodes:
+ *   eta_j(t_p) = sum_{k=kmin}^{kmin+nk-1} c_{j,k} e^{i s k t_p},  t_p = 2 pi p / n,
+ * s = +1 (ccw != 0) or -1, with eta' (factor i s k) and eta'' (factor -k^2).
+ *   coef : m1 x nk complex (component-major);  eta: m1*n complex output;
+ *   etap, etapp: outputs, may be NULL. */
+GNK_API gnk_status gnk_fourier_curve(gnk_ctx* ctx, int64_t m1, int64_t n, int kmin, int nk, int ccw,
+                                     const void* coef, void* eta, void* etap, void* etapp);
+
+/* Reverse mode of gnk_fourier_curve: g_coef[j,k] = sum_p (g_eta + conj(i s k) g_eta'
+ * + conj(-k^2) g_eta'')_p e^{-i s k t_p}; any of g_eta, g_etap, g_etapp may be
+ * NULL (zero), not all. g_coef: m1 x nk complex output. */
+GNK_API gnk_status gnk_fourier_vjp(gnk_ctx* ctx, int64_t m1, int64_t n, int kmin, int nk, int ccw,
+                                   const void* g_eta, const void* g_etap, const void* g_etapp, void* g_coef);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,4 +73,34 @@ hipError_t launch_circulant(const double* x, double* y, const int64_t* offs, int
 hipError_t launch_twiddles(double2* tw, int64_t n, hipStream_t st);
 bool circulant_uses_fft(int64_t n);
 
+// Geometric derivatives of s = sum_t c_t u_t^T Op_t v_t (Op_t = f_B or fC).
+// Terms are grouped by their vector v; z = i c_t (f_B) or c_t (fC).
+struct GeomTerm {
+  const double* u;
+  double2 z;
+};
+struct GeomGroup {
+  const double* v;
+  int t0, t1;        // terms [t0, t1) of the group
+};
+// source records {eta, b V_g (G), b, a U_g (G), a P} with nw = 2G + 2 weights
+hipError_t launch_geom_weights(const double2* eta, const double2* etap, const double2* A, int N,
+                               const GeomTerm* terms, const GeomGroup* groups, int G, int nw, double2* rec,
+                               double2* Ut, double2* P, hipStream_t st);
+// first- and second-order Cauchy sums of the nw weights, per source split
+hipError_t launch_cauchy12(const double2* rec, int nwpad, int N, int nw, int chunk, int splits, double2* parts,
+                           hipStream_t st);
+int geom_width(int nw);
+// gradients with respect to eta, eta', A (any output may be null)
+hipError_t launch_geom_epilogue(const double2* etap, const double2* A, int N, int n, const GeomGroup* groups, int G,
+                                const double2* Ut, const double2* P, const double2* parts, int nw, int splits,
+                                double2* g_eta, double2* g_etap, double2* g_A, hipStream_t st);
+
+// Fourier boundary curves eta_j(t) = sum_k c_{j,k} e^{i sgn k t} at t_p = 2 pi p/n
+// (coef: m1 x nk, component-major) and the chain rule back to the coefficients
+hipError_t launch_fourier_curve(const double2* coef, int m1, int n, int kmin, int nk, int sgn, double2* eta,
+                                double2* etap, double2* etapp, hipStream_t st);
+hipError_t launch_fourier_vjp(const double2* g_eta, const double2* g_etap, const double2* g_etapp, int m1, int n,
+                              int kmin, int nk, int sgn, double2* g_coef, hipStream_t st);
+
 }  // namespace gnk

@@ -947,6 +947,115 @@ void single_batch(gnk_ctx* c, Batch& B, const gnk_domain* d, int nrhs, bool adjo
   build_batch(c, B, 1, d, &nrhs, off, d->m1 * d->n * (int64_t)nrhs, adjoint, mixed, PairShape{});
 }
 
+// ------------------------------------------------------- differentiation
+// Adjoint of FBIE (transpose of eq. (e:sys)):
+//   lam = Aop^{-T} (Cop^T g_h / 2 + g_mu),   g_gam = -Aop^T g_h / 2 - Cop^T lam.
+GmresOut fbie_adjoint_batch(gnk_ctx* c, Batch& B, const double* g_mu, const double* g_h, const gnk_opts& o,
+                            double* lam, double* g_gam) {
+  const int64_t T = B.T;
+  if (g_mu) validate(c, B, g_mu, T);
+  if (g_h) validate(c, B, g_h, T);
+  k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
+  LAUNCHCHK(c);
+  setup_diag(c, B);
+  double* b = ws<double>(c, "adj_rhs", T);
+  if (g_h) {
+    apply_op(c, B, GNK_OP_FC_T, g_h, b);
+    if (g_mu) k_axpby<<<nblocks(T), kT, 0, c->stream>>>(1.0, g_mu, 0.5, b, T);
+    else k_axpby<<<nblocks(T), kT, 0, c->stream>>>(0.0, b, 0.5, b, T);
+    LAUNCHCHK(c);
+  } else {
+    HIPCHK(c, hipMemcpyAsync(b, g_mu, sizeof(double) * T, hipMemcpyDeviceToDevice, c->stream));
+  }
+  GmresOut g = gmres(c, B, GNK_OP_FB_T, b, o, lam, o.prec == GNK_MIXED);
+  if (g_gam) {
+    apply_op(c, B, GNK_OP_FC_T, lam, g_gam);
+    if (g_h) {
+      double* t = ws<double>(c, "adj_tmp", T);
+      apply_op(c, B, GNK_OP_FB_T, g_h, t);
+      k_axpby<<<nblocks(T), kT, 0, c->stream>>>(-0.5, t, -1.0, g_gam, T);
+    } else {
+      k_axpby<<<nblocks(T), kT, 0, c->stream>>>(0.0, g_gam, -1.0, g_gam, T);
+    }
+    LAUNCHCHK(c);
+  }
+  return g;
+}
+
+// Gradient of s = sum_t coef_t u_t^T Op_t v_t with respect to eta, eta', A:
+// weights per source, first- and second-order Cauchy sums, per-node epilogue.
+void geom_vjp(gnk_ctx* c, const gnk_domain* d, int nterms, const int* ops, const double* coef,
+              const double* const* u, const double* const* v, double2* g_eta, double2* g_etap, double2* g_A) {
+  Batch B;
+  single_batch(c, B, d, 1, false, false);
+  const int N = B.dom[0].N;
+  {
+    // finiteness of the domain data and of every term vector
+    int* flags = ws<int>(c, "flags", 1);
+    HIPCHK(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
+    k_validate<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, 0, flags);
+    LAUNCHCHK(c);
+    for (int t = 0; t < nterms; ++t) {
+      k_check_finite<<<nblocks(N), kT, 0, c->stream>>>(u[t], N, flags);
+      k_check_finite<<<nblocks(N), kT, 0, c->stream>>>(v[t], N, flags);
+    }
+    LAUNCHCHK(c);
+    int h = 0;
+    HIPCHK(c, hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h & 1) {
+      set_err(c, "non-finite value in the inputs");
+      throw Fail{GNK_ERR_NONFINITE};
+    }
+    if (h & 2) {
+      set_err(c, "A vanishes at a node");
+      throw Fail{GNK_ERR_ZERO_A};
+    }
+  }
+  // group the terms by their v vector
+  std::vector<const double*> gv;
+  std::vector<std::vector<int>> members;
+  for (int t = 0; t < nterms; ++t) {
+    size_t g = 0;
+    while (g < gv.size() && gv[g] != v[t]) ++g;
+    if (g == gv.size()) {
+      gv.push_back(v[t]);
+      members.emplace_back();
+    }
+    members[g].push_back(t);
+  }
+  std::vector<GeomTerm> terms;
+  std::vector<GeomGroup> groups;
+  for (size_t g = 0; g < gv.size(); ++g) {
+    const int t0 = (int)terms.size();
+    for (int t : members[g]) {
+      const double cf = coef ? coef[t] : 1.0;
+      terms.push_back(GeomTerm{u[t], ops[t] == GNK_OP_FB ? make_double2(0.0, cf) : make_double2(cf, 0.0)});
+    }
+    groups.push_back(GeomGroup{gv[g], t0, (int)terms.size()});
+  }
+  const int G = (int)groups.size();
+  const int nw = 2 * G + 2;
+  // enough workgroups for two rounds of the wave slots, at least 256 sources each
+  const int64_t tiles = (N + 63) / 64;
+  int64_t splits = (2 * slots_of(c) + 4 * tiles - 1) / (4 * tiles);
+  splits = std::max<int64_t>(1, std::min<int64_t>(splits, std::min<int64_t>(64, std::max<int64_t>(1, N / 256))));
+  int64_t chunk = (N + splits - 1) / splits;
+  chunk = (chunk + 3) / 4 * 4;
+  splits = (N + chunk - 1) / chunk;
+  const GeomTerm* dterms = upload(c, "g_terms", terms);
+  const GeomGroup* dgroups = upload(c, "g_groups", groups);
+  double2* rec = ws<double2>(c, "g_rec", (size_t)N * (1 + nw));
+  double2* Ut = ws<double2>(c, "g_U", (size_t)G * N);
+  double2* P = ws<double2>(c, "g_P", N);
+  double2* parts = ws<double2>(c, "g_parts", (size_t)splits * nw * 2 * N);
+  const DomDev& D = B.dom[0];
+  HIPCHK(c, launch_geom_weights(D.eta, D.etap, D.A, N, dterms, dgroups, G, nw, rec, Ut, P, c->stream));
+  HIPCHK(c, launch_cauchy12(rec, nw, N, nw, (int)chunk, (int)splits, parts, c->stream));
+  HIPCHK(c, launch_geom_epilogue(D.etap, D.A, N, D.n, dgroups, G, Ut, P, parts, nw, (int)splits, g_eta, g_etap, g_A,
+                                 c->stream));
+}
+
 }  // namespace
 }  // namespace gnk
 
@@ -1183,6 +1292,87 @@ gnk_status gnk_fbie_batched(gnk_ctx* c, int ndom, const gnk_domain* doms, const 
     if (info)
       for (int q = 0; q < ncol; ++q) info[q] = go.info[q];
     return go.all_converged ? GNK_OK : GNK_NOT_CONVERGED;
+  });
+}
+
+gnk_status gnk_fbie_adjoint(gnk_ctx* c, const gnk_domain* d, const double* g_mu, const double* g_h, int nrhs,
+                            const gnk_opts* opts, double* lam, double* g_gam, gnk_info* info) {
+  return guarded(c, [&]() -> gnk_status {
+    if ((!g_mu && !g_h) || !lam || nrhs < 1 || lam == g_mu || lam == g_h || (g_gam && (g_gam == lam ||
+        g_gam == g_mu || g_gam == g_h))) {
+      set_err(c, "bad arguments to gnk_fbie_adjoint");
+      throw Fail{GNK_ERR_ARG};
+    }
+    gnk_opts o = resolve_opts(c, opts);
+    Batch B;
+    single_batch(c, B, d, nrhs, false, o.prec == GNK_MIXED);
+    GmresOut g = fbie_adjoint_batch(c, B, g_mu, g_h, o, lam, g_gam);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (info)
+      for (int r = 0; r < nrhs; ++r) info[r] = g.info[r];
+    return g.all_converged ? GNK_OK : GNK_NOT_CONVERGED;
+  });
+}
+
+gnk_status gnk_geom_vjp(gnk_ctx* c, const gnk_domain* d, int nterms, const int* ops, const double* coef,
+                        const double* const* u, const double* const* v, void* g_eta, void* g_etap, void* g_A) {
+  return guarded(c, [&]() -> gnk_status {
+    bool ok = nterms >= 1 && nterms <= 64 && ops && u && v && (g_eta || g_etap || g_A);
+    for (int t = 0; ok && t < nterms; ++t)
+      ok = (ops[t] == GNK_OP_FB || ops[t] == GNK_OP_FC) && u[t] && v[t] && (!coef || std::isfinite(coef[t]));
+    if (ok && d) {
+      const void* in[3] = {d->eta, d->etap, d->A};
+      const void* out[3] = {g_eta, g_etap, g_A};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) ok = ok && (!out[b] || out[b] != in[a]);
+    }
+    if (!ok) {
+      set_err(c, "bad arguments to gnk_geom_vjp");
+      throw Fail{GNK_ERR_ARG};
+    }
+    geom_vjp(c, d, nterms, ops, coef, u, v, static_cast<double2*>(g_eta), static_cast<double2*>(g_etap),
+             static_cast<double2*>(g_A));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GNK_OK;
+  });
+}
+
+namespace {
+bool fourier_args_ok(int64_t m1, int64_t n, int kmin, int nk) {
+  return m1 >= 1 && m1 <= 65535 && n >= 1 && m1 * n <= ((int64_t)1 << 30) && nk >= 1 && nk <= 65535 &&
+         kmin >= -(1 << 20) && (int64_t)kmin + nk <= (1 << 20);
+}
+}  // namespace
+
+gnk_status gnk_fourier_curve(gnk_ctx* c, int64_t m1, int64_t n, int kmin, int nk, int ccw, const void* coef,
+                             void* eta, void* etap, void* etapp) {
+  return guarded(c, [&]() -> gnk_status {
+    if (!fourier_args_ok(m1, n, kmin, nk) || !coef || !eta || coef == eta || (etap && (etap == eta || etap == coef)) ||
+        (etapp && (etapp == eta || etapp == coef || etapp == etap))) {
+      set_err(c, "bad arguments to gnk_fourier_curve");
+      throw Fail{GNK_ERR_ARG};
+    }
+    HIPCHK(c, launch_fourier_curve(static_cast<const double2*>(coef), (int)m1, (int)n, kmin, nk, ccw ? 1 : -1,
+                                   static_cast<double2*>(eta), static_cast<double2*>(etap),
+                                   static_cast<double2*>(etapp), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GNK_OK;
+  });
+}
+
+gnk_status gnk_fourier_vjp(gnk_ctx* c, int64_t m1, int64_t n, int kmin, int nk, int ccw, const void* g_eta,
+                           const void* g_etap, const void* g_etapp, void* g_coef) {
+  return guarded(c, [&]() -> gnk_status {
+    if (!fourier_args_ok(m1, n, kmin, nk) || !g_coef || (!g_eta && !g_etap && !g_etapp) || g_coef == g_eta ||
+        g_coef == g_etap || g_coef == g_etapp) {
+      set_err(c, "bad arguments to gnk_fourier_vjp");
+      throw Fail{GNK_ERR_ARG};
+    }
+    HIPCHK(c, launch_fourier_vjp(static_cast<const double2*>(g_eta), static_cast<const double2*>(g_etap),
+                                 static_cast<const double2*>(g_etapp), (int)m1, (int)n, kmin, nk, ccw ? 1 : -1,
+                                 static_cast<double2*>(g_coef), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GNK_OK;
   });
 }
 

@@ -24,7 +24,7 @@ OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT = range(7)
 
 EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
             "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad",
-            "gnk_fbie_batched")
+            "gnk_fbie_batched", "gnk_fbie_adjoint", "gnk_geom_vjp", "gnk_fourier_curve", "gnk_fourier_vjp")
 
 
 class GnkError(RuntimeError):
@@ -86,6 +86,12 @@ def load_library(path: str = LIB_PATH):
     lib.gnk_fbie_ad.argtypes = [P, C.POINTER(_Domain), P, C.c_int, C.POINTER(_Opts), P, C.POINTER(Info)]
     lib.gnk_fbie_batched.argtypes = [P, C.c_int, C.POINTER(_Domain), C.POINTER(P), C.POINTER(C.c_int),
                                      C.POINTER(_Opts), C.POINTER(P), C.POINTER(P), C.POINTER(Info)]
+    lib.gnk_fbie_adjoint.argtypes = [P, C.POINTER(_Domain), P, P, C.c_int, C.POINTER(_Opts), P, P,
+                                     C.POINTER(Info)]
+    lib.gnk_geom_vjp.argtypes = [P, C.POINTER(_Domain), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                 C.POINTER(P), C.POINTER(P), P, P, P]
+    lib.gnk_fourier_curve.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P]
+    lib.gnk_fourier_vjp.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P]
     for f in EXPORTED:
         if f not in ("gnk_last_error", "gnk_version"):
             getattr(lib, f).restype = C.c_int
@@ -273,3 +279,79 @@ class Context:
         mus = [_from_cols(m, one) for m, one in zip(mus, ones)]
         hs = [_from_cols(h, one) for h, one in zip(hs, ones)] if want_h else None
         return mus, hs, out_i, st
+
+    # ------------------------------------------------------- differentiation
+    def fbie_adjoint(self, dom: DeviceDomain, g_mu: Optional[torch.Tensor] = None, g_h: Optional[torch.Tensor] = None,
+                     restart=25, maxit=40, tol=1e-12, prec=FP64, inner_tol=0.0, want_g_gam=True):
+        """Adjoint solve of FBIE: lam = Aop^-T (Cop^T g_h / 2 + g_mu) and
+        dL/dgamma = -Aop^T g_h / 2 - Cop^T lam. Returns (lam, g_gam, infos, status)."""
+        self._bind_stream()
+        ref = g_h if g_h is not None else g_mu
+        if ref is None:
+            raise ValueError("need g_mu or g_h")
+        one = ref.dim() == 1
+        gm = _check_real(g_mu, dom.N, "g_mu") if g_mu is not None else None
+        gh = _check_real(g_h, dom.N, "g_h") if g_h is not None else None
+        nrhs = (gm or gh)[1]
+        if gm is not None and gh is not None and gm[1] != gh[1]:
+            raise ValueError("g_mu and g_h have different column counts")
+        lam = torch.empty((nrhs, dom.N), dtype=torch.float64, device=ref.device)
+        g_gam = torch.empty_like(lam) if want_g_gam else None
+        o = self._opts(restart, maxit, tol, prec, inner_tol, 0, None)
+        infos = (Info * nrhs)()
+        d = dom._struct()
+        st = self.lib.gnk_fbie_adjoint(self.h, C.byref(d), None if gm is None else gm[0].data_ptr(),
+                                       None if gh is None else gh[0].data_ptr(), nrhs, C.byref(o), lam.data_ptr(),
+                                       None if g_gam is None else g_gam.data_ptr(), infos)
+        self._raise(st)
+        return (_from_cols(lam, one), None if g_gam is None else _from_cols(g_gam, one),
+                [i.as_dict() for i in infos], st)
+
+    def geom_vjp(self, dom: DeviceDomain, terms, want=(True, True, True)):
+        """Gradients of s = sum_t c_t u_t^T Op_t v_t with respect to (eta, eta', A).
+        terms: list of (op, c, u, v) with op OP_FB or OP_FC, c a float and u, v
+        contiguous float64 CUDA vectors of length N. Returns three complex128
+        tensors (None where not wanted)."""
+        self._bind_stream()
+        nt = len(terms)
+        for _, _, u, v in terms:
+            for x in (u, v):
+                if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 1 or x.shape[0] != dom.N \
+                        or not x.is_contiguous():
+                    raise ValueError("term vectors must be contiguous float64 CUDA vectors of length N")
+        ops = (C.c_int * nt)(*[int(t[0]) for t in terms])
+        cf = (C.c_double * nt)(*[float(t[1]) for t in terms])
+        U = (C.c_void_p * nt)(*[t[2].data_ptr() for t in terms])
+        V = (C.c_void_p * nt)(*[t[3].data_ptr() for t in terms])
+        outs = [torch.empty(dom.N, dtype=torch.complex128, device=dom.eta.device) if w else None for w in want]
+        d = dom._struct()
+        st = self.lib.gnk_geom_vjp(self.h, C.byref(d), nt, ops, cf, U, V,
+                                   *[None if o is None else o.data_ptr() for o in outs])
+        self._raise(st, False)
+        return tuple(outs)
+
+    def fourier_curve(self, coef: torch.Tensor, kmin: int, n: int, ccw: bool = False):
+        """eta, eta', eta'' (complex128, length m1*n) of the curves
+        eta_j(t) = sum_k coef[j, k - kmin] e^{i s k t}, s = +1 (ccw) or -1, at t_p = 2 pi p / n."""
+        self._bind_stream()
+        if coef.dtype != torch.complex128 or not coef.is_cuda or coef.dim() != 2:
+            raise TypeError("coef must be an (m1, nk) complex128 CUDA tensor")
+        coef = coef.contiguous()
+        m1, nk = coef.shape
+        out = [torch.empty(m1 * n, dtype=torch.complex128, device=coef.device) for _ in range(3)]
+        st = self.lib.gnk_fourier_curve(self.h, m1, n, kmin, nk, 1 if ccw else 0, coef.data_ptr(),
+                                        *[o.data_ptr() for o in out])
+        self._raise(st, False)
+        return tuple(out)
+
+    def fourier_vjp(self, g_eta, g_etap, g_etapp, m1: int, nk: int, kmin: int, n: int, ccw: bool = False):
+        """Reverse mode of fourier_curve: the (m1, nk) complex gradient of the coefficients."""
+        self._bind_stream()
+        ptr = lambda x: None if x is None else x.contiguous().data_ptr()
+        keep = [None if x is None else x.contiguous() for x in (g_eta, g_etap, g_etapp)]
+        ref = next(x for x in keep if x is not None)
+        g = torch.empty((m1, nk), dtype=torch.complex128, device=ref.device)
+        st = self.lib.gnk_fourier_vjp(self.h, m1, n, kmin, nk, 1 if ccw else 0, *[ptr(x) for x in keep],
+                                      g.data_ptr())
+        self._raise(st, False)
+        return g
