@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed and batched comparisons")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with a plain copy of 256 MiB (3 launches), the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
@@ -236,6 +238,14 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(dom)
+    if args.copy_probe:
+        # y = 1.0 * x over 2^25 doubles: 256 MiB read and 256 MiB written per launch
+        x = torch.ones(1 << 25, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = {"read": x.numel() * 8, "write": y.numel() * 8, "launches": 3}
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -74,6 +74,35 @@ __device__ __forceinline__ void pair_step(Acc<NR, TPT>& acc, const double2 (&tg)
   }
 }
 
+// four sources a..d against every target of the lane, one reciprocal for all
+// four: with R = 1/(|da|^2 |db|^2 |dc|^2 |dd|^2), 1/|da|^2 = R |db|^2 (|dc|^2 |dd|^2)
+// and so on (the product stays in range while every distance lies in
+// [1e-38, 1e38])
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void quad_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], P ra, P rb, P rc, P rd,
+                                          int wo) {
+  const double2 ea = ra[0], eb = rb[0], ec = rc[0], ed = rd[0];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const double dxa = tg[t].x - ea.x, dya = tg[t].y - ea.y;
+    const double dxb = tg[t].x - eb.x, dyb = tg[t].y - eb.y;
+    const double dxc = tg[t].x - ec.x, dyc = tg[t].y - ec.y;
+    const double dxd = tg[t].x - ed.x, dyd = tg[t].y - ed.y;
+    const double da = __builtin_fma(dya, dya, dxa * dxa);
+    const double db = __builtin_fma(dyb, dyb, dxb * dxb);
+    const double dc = __builtin_fma(dyc, dyc, dxc * dxc);
+    const double dd = __builtin_fma(dyd, dyd, dxd * dxd);
+    const double ab = da * db, cd = dc * dd;
+    const double R = refine_rcp(ab * cd);
+    const double Rab = R * cd, Rcd = R * ab;
+    const double qa = db * Rab, qb = da * Rab, qc = dd * Rcd, qd = dc * Rcd;
+    accumulate<NR, TPT>(acc, t, ra + wo, dxa * qa, -dya * qa);
+    accumulate<NR, TPT>(acc, t, rb + wo, dxb * qb, -dyb * qb);
+    accumulate<NR, TPT>(acc, t, rc + wo, dxc * qc, -dyc * qc);
+    accumulate<NR, TPT>(acc, t, rd + wo, dxd * qd, -dyd * qd);
+  }
+}
+
 template <int NR, int TPT, class P>
 __device__ __forceinline__ void single_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], const int (&ti)[TPT], P rj,
                                             int wo, int j, bool masked) {
@@ -166,8 +195,13 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
     int j = ja;
     for (; j + 3 < jb; j += 4) {
       gptr<const double2> r = rec + (size_t)j * stride;
-      pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
-      pair_step<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
+      if constexpr (NR <= 2) {
+        quad_step<NR, TPT>(acc, tg, r, r + stride, r + 2 * stride, r + 3 * stride, wo);
+      } else {
+        // four wide records would not fit in scalar registers together
+        pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
+        pair_step<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
+      }
     }
     for (; j + 1 < jb; j += 2) {
       gptr<const double2> r = rec + (size_t)j * stride;
@@ -259,8 +293,10 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 // One launch: one workgroup per item of the list. (A workgroup that looped
 // over several items would store partial sums before loading the next item's
 // records, and the records could then no longer be fetched with scalar loads.)
+// Variants with one or two columns are held to 64 VGPRs (8 waves per SIMD),
+// which they reach without spilling; wider ones keep their registers.
 template <int NR, int TPT, bool MIXED>
-__global__ __launch_bounds__(256) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NR <= 2 ? 8 : 1))) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
                                                int nitems, int lead, int data, const int* __restrict__ active) {
   __shared__ double red[3][TPT][2][64];
   const int it = blockIdx.x;
@@ -351,7 +387,42 @@ void launch_w(const DomDev* doms, const int4* items, int nitems, int tpt, int le
   }
 }
 
+
+template <int NR, int TPT, bool MIXED>
+int occupancy_of() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<NR, TPT, MIXED>, 256, 0) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 8;
+  }
+  return nb;
+}
+
+template <int NR>
+int occupancy_w(int tpt, bool mixed) {
+  if (tpt == 2) return mixed ? occupancy_of<NR, 2, true>() : occupancy_of<NR, 2, false>();
+  return mixed ? occupancy_of<NR, 1, true>() : occupancy_of<NR, 1, false>();
+}
+
 }  // namespace
+
+int pairs_blocks_per_cu(int width, int tpt, bool mixed) {
+  // resident 256-thread workgroups per CU of each pair-kernel variant (register
+  // and LDS limits), cached after the first query
+  static int cache[4][2][2] = {};
+  const int wi = width >= 8 ? 0 : (width >= 4 ? 1 : (width >= 2 ? 2 : 3));
+  const int ti = tpt == 2 ? 1 : 0;
+  int& v = cache[wi][ti][mixed ? 1 : 0];
+  if (v == 0) {
+    switch (wi) {
+      case 0: v = occupancy_w<8>(tpt, mixed); break;
+      case 1: v = occupancy_w<4>(tpt, mixed); break;
+      case 2: v = occupancy_w<2>(tpt, mixed); break;
+      default: v = occupancy_w<1>(tpt, mixed); break;
+    }
+  }
+  return v;
+}
 
 hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
                         bool mixed, const int* active, hipStream_t st) {

@@ -59,6 +59,8 @@ struct ColDev {
 // item whose data columns are all inactive is skipped.
 hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
                         bool mixed, const int* active, hipStream_t st);
+// resident workgroups per CU of the pair-kernel variant (width columns, tpt, mixed)
+int pairs_blocks_per_cu(int width, int tpt, bool mixed);
 
 // bounding circles of the tiles of `tile` nodes of every domain (source tiles
 // of 64 nodes into sb, target tiles into tb)

@@ -24,6 +24,7 @@ struct GmresState {
   int* inner_it;        // total Arnoldi steps
   int* live;            // number of active columns (single int)
   int* step;            // current Arnoldi step l of the cycle (single int)
+  int* done;            // blocks of the step's last kernel that have finished (single int)
   int ldh;              // restart + 1
   int hstride;          // ldh * restart
 };

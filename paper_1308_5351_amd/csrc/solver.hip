@@ -206,12 +206,14 @@ void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint) {
 }
 
 // Single-domain split plan: the split count whose waves fill whole rounds of
-// the wave slots best (fewest splits within 1% of the best), at least 32
-// sources per workgroup, at most 64 splits.
-void plan_single(gnk_ctx* c, int64_t N, int align, int* tpt, int* chunk, int* splits) {
-  const int64_t slots = slots_of(c);
-  int t = ((N + 127) / 128) * 64 >= slots ? 2 : 1;
+// the wave slots of the pair-kernel variant best (fewest splits within 1% of
+// the best), at least 32 sources per workgroup, at most 64 splits.
+void plan_single(gnk_ctx* c, int64_t N, int align, int width, bool mixed, int* tpt, int* chunk, int* splits) {
+  int t = ((N + 127) / 128) * 64 >= slots_of(c) ? 2 : 1;
   if (const char* s = getenv("GNK_CAUCHY_TPT")) t = atoi(s) == 2 ? 2 : 1;
+  // wave slots of the variant that runs the products (its register use sets
+  // how many workgroups fit on a CU)
+  const int64_t slots = (int64_t)c->num_cu * 4 * pairs_blocks_per_cu(width, t, mixed);
   const int64_t tiles = (N + 64 * t - 1) / (64 * t);
   const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, N / 32));
   std::vector<double> score((size_t)max_s + 1, 0.0);
@@ -265,7 +267,8 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     c0 += ncols[d];
     if (ndom == 1 && shape.chunk == 0) {
       int t, ch, sp;
-      plan_single(c, D.N, align, &t, &ch, &sp);
+      const int width = ncols[d] >= 8 ? 8 : (ncols[d] >= 4 ? 4 : (ncols[d] >= 2 ? 2 : 1));
+      plan_single(c, D.N, align, width, mixed, &t, &ch, &sp);
       B.shape.tpt = t;
       D.chunk = ch;
       D.splits = sp;
@@ -484,6 +487,10 @@ struct ApplyArgs {
   bool mixed = false;        // FP32 far tiles (batch built with mixed records)
   const int* step = nullptr; // x = V_l (x, xout advanced by l*stepT), y = V_{l+1}; l read on the device
   int64_t stepT = 0;
+  // inside an Arnoldi step: the epilogue also takes the first Gram-Schmidt
+  // pass (dots of V_{l+1} with V_0..V_l per block of per_blk elements)
+  double* dots = nullptr;
+  int per_blk = 0, nblk = 0, ldp = 0;
 };
 
 void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const ApplyArgs& a = {}) {
@@ -520,6 +527,17 @@ void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const Ap
   LAUNCHCHK(c);
   const double* xin = a.xout ? a.xout : x;
   pairs(c, B, P_GM, a.mixed, a.active);
+  if (a.dots) {
+    if (!a.step || x != y || op == GNK_OP_FC || op == GNK_OP_FC_T) {
+      set_err(c, "internal: fused Gram-Schmidt epilogue needs an Arnoldi step of FB, FB_T, GB or GB_T");
+      throw Fail{GNK_ERR_ARG};
+    }
+    k_epilogue_dots<<<dim3((unsigned)a.nblk, (unsigned)B.ncol), kT, 0, c->stream>>>(
+        B.d_dom, B.d_col, y, a.stepT, cout, dsel, a0, dsign, cI, cR, mean, M, a.active, a.step, a.per_blk, a.dots,
+        a.ldp);
+    LAUNCHCHK(c);
+    return;
+  }
   k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, xin, cout, dsel, a0, dsign, cI, cR, mean, M,
                                                 a.active, 0, y, a.step, a.stepT);
   LAUNCHCHK(c);
@@ -558,7 +576,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   st.hstride = st.ldh * restart;
   double* dbl = ws<double>(c, "gmdbl", (size_t)ncol * (4 + st.hstride + 2 * kMaxRestart + (kMaxRestart + 1) +
                                                      kMaxRestart));
-  int* ints = ws<int>(c, "gmint", (size_t)ncol * 5 + 2);
+  int* ints = ws<int>(c, "gmint", (size_t)ncol * 5 + 3);
   {
     double* q = dbl;
     st.bnorm = q; q += ncol;
@@ -577,6 +595,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     st.inner_it = r; r += ncol;
     st.live = r;
     st.step = r + 1;
+    st.done = r + 2;
   }
   const unsigned cb = nblocks(ncol, 256);
   k_gmres_init<<<cb, 256, 0, c->stream>>>(ncol, st);
@@ -607,6 +626,20 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   LAUNCHCHK(c);
   cycle_start(P1);
 
+  // host-mapped memory that the last kernel of every Arnoldi step writes: the
+  // number of iterating columns and (mixed solves) the residual estimates
+  if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(int) * (kMaxRestart + 1), 0));
+  if (c->pinned_rel_n < (size_t)ncol * kMaxRestart) {
+    if (c->pinned_rel) HIPCHK(c, hipHostFree(c->pinned_rel));
+    c->pinned_rel = nullptr;
+    HIPCHK(c, hipHostMalloc((void**)&c->pinned_rel, sizeof(double) * ncol * kMaxRestart, 0));
+    c->pinned_rel_n = (size_t)ncol * kMaxRestart;
+  }
+  int* host_live = nullptr;
+  double* host_rel = nullptr;
+  HIPCHK(c, hipHostGetDevicePointer((void**)&host_live, c->pinned, 0));
+  HIPCHK(c, hipHostGetDevicePointer((void**)&host_rel, c->pinned_rel, 0));
+
   // With relaxed (mixed) products the residual estimate runs slightly ahead
   // of the true residual, so a mixed cycle aims at half the tolerance; the
   // convergence test itself always uses the FP64 true residual.
@@ -622,16 +655,17 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     aa.mixed = use_mixed;
     aa.step = st.step;
     aa.stepT = T;
+    aa.dots = P1;
+    aa.per_blk = per_blk;
+    aa.nblk = nblk;
+    aa.ldp = ldp;
     apply_op(c, B, op, V, V, aa);
-    k_gs_dot<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, st.step, per_blk, st.active, P1, ldp);
-    LAUNCHCHK(c);
     k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, st.active, P1, P2, ldp, st, 0, 1);
     LAUNCHCHK(c);
     k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, st.active, P2, P1, ldp, st, 1, 0);
     LAUNCHCHK(c);
-    k_arnoldi_finish<<<(unsigned)ncol, 64, 0, c->stream>>>(P1, nblk, ldp, restart, stop_tol, st);
-    LAUNCHCHK(c);
-    k_step_next<<<1, 1, 0, c->stream>>>(st);
+    k_arnoldi_finish<<<(unsigned)ncol, 64, 0, c->stream>>>(P1, nblk, ldp, restart, stop_tol, st, host_live,
+                                                           mixed ? host_rel : nullptr, ncol);
     LAUNCHCHK(c);
   };
   // Every buffer the step touches exists before a capture (no allocation,
@@ -675,13 +709,6 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
 
   std::vector<int> outer(ncol, 0), conv(ncol, 0), mixed_steps(ncol, 0);
   bool mixed_now = false;
-  if (!c->pinned) HIPCHK(c, hipHostMalloc((void**)&c->pinned, sizeof(int) * (kMaxRestart + 1), 0));
-  if (c->pinned_rel_n < (size_t)ncol * kMaxRestart) {
-    if (c->pinned_rel) HIPCHK(c, hipHostFree(c->pinned_rel));
-    c->pinned_rel = nullptr;
-    HIPCHK(c, hipHostMalloc((void**)&c->pinned_rel, sizeof(double) * ncol * kMaxRestart, 0));
-    c->pinned_rel_n = (size_t)ncol * kMaxRestart;
-  }
   while ((int)c->step_ev.size() < kMaxRestart) {
     hipEvent_t e;
     HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -705,10 +732,6 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
         for (int q = 0; q < ncol; ++q)
           if (!conv[q]) mixed_steps[q] += 1;
       launch_step(use_mixed);
-      HIPCHK(c, hipMemcpyAsync(c->pinned + l, st.live, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      if (mixed && !mixed_now)
-        HIPCHK(c, hipMemcpyAsync(c->pinned_rel + (size_t)l * ncol, st.relres, sizeof(double) * ncol,
-                                 hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipEventRecord(c->step_ev[l], c->stream));
       if (l >= 1) {
         HIPCHK(c, hipEventSynchronize(c->step_ev[l - 1]));

@@ -267,25 +267,45 @@ __device__ __forceinline__ void chunk_dots(const double* __restrict__ V, int64_t
   }
 }
 
-// Arnoldi step l = *step: w = V_{l+1}, dots with V_0..V_l
-__global__ __launch_bounds__(kT) void k_gs_dot(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
-                                               const double* __restrict__ V, int64_t T,
-                                               const int* __restrict__ step, int per_blk,
-                                               const int* __restrict__ active, double* __restrict__ partial,
-                                               int ldp) {
+// The epilogue of the operator inside an Arnoldi step l = *step, fused with
+// the first Gram-Schmidt pass: w = V_{l+1} = op(V_l) on this block's chunk of
+// per_blk elements (grid (nblk, ncol)), then the chunk's dots of w with
+// V_0..V_l into partial (c*nblk + blk)*ldp. V is the basis (vector q at V + q*T).
+__global__ __launch_bounds__(kT) void k_epilogue_dots(const DomDev* __restrict__ doms,
+                                                      const ColDev* __restrict__ cols, double* __restrict__ V,
+                                                      int64_t T, int csel_out, int dsel, double a0, double dsign,
+                                                      double cI, double cR, const double* __restrict__ mean, int M,
+                                                      const int* __restrict__ active, const int* __restrict__ step,
+                                                      int per_blk, double* __restrict__ partial, int ldp) {
+  __shared__ double sw[kMaxChunk];
   const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
   if (!active[c]) return;
-  const int nvec = *step + 1;
-  const double* __restrict__ w = V + (size_t)nvec * T;
+  const int l = *step;
+  const int nvec = l + 1;
+  const double* __restrict__ xl = V + (size_t)l * T;
+  double* __restrict__ w = V + (size_t)nvec * T;
   const ColDev C = cols[c];
-  const int N = doms[C.d].N;
+  const DomDev& D = doms[C.d];
+  const int N = D.N;
   double* out = partial + ((size_t)c * nblk + blk) * ldp;
   const int i0 = blk * per_blk, i1 = min(N, i0 + per_blk);
   if (i0 >= N) {
-    for (int l = threadIdx.x; l < nvec; l += blockDim.x) out[l] = 0.0;
+    for (int q = threadIdx.x; q < nvec; q += blockDim.x) out[q] = 0.0;
     return;
   }
-  chunk_dots(V, T, C.off, nvec, w + C.off + i0, i0, i1, out);
+  const double two_n = 2.0 / (double)D.n;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double2 s = reduce_parts(D, D.ncols, C.r, i);
+    const double2 cs = cmul(coef(D, csel_out, i), s);
+    const double xv = xl[C.off + i];
+    double v = a0 * xv + two_n * (cI * cs.y + cR * cs.x);
+    if (dsel != D_NONE) v += dsign * diagv(D, dsel, i) * xv;
+    if (mean) v += mean[(size_t)c * M + i / D.n];
+    w[C.off + i] = v;
+    sw[i - i0] = v;
+  }
+  __syncthreads();
+  chunk_dots(V, T, C.off, nvec, sw, i0, i1, out);
 }
 
 // h_l = sum over blocks of pin (fixed order); w -= sum_l h_l V_l on this
@@ -421,22 +441,19 @@ __global__ void k_cycle_start(const double* partial, int nblk, int ldp, int ncol
 __global__ void k_cycle_reset(GmresState st) {
   *st.live = 0;
   *st.step = 0;
+  *st.done = 0;
 }
-
-// end of an Arnoldi step (a separate launch, after every reader of the step)
-__global__ void k_step_next(GmresState st) { *st.step += 1; }
 
 // End of Arnoldi step `col`; one 64-lane block per column c: beta = ||w||
 // from the partials, H(col+1, col) = beta, Givens rotations applied in LDS,
-// residual estimate, stop test for this cycle.
-__global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, int nblk, int ldp, int restart,
-                                                       double tol, GmresState st) {
-  __shared__ double hc[kMaxRestart + 2];
-  __shared__ double cs_[kMaxRestart + 1];
-  __shared__ double sn_[kMaxRestart + 1];
-  const int c = blockIdx.x, lane = threadIdx.x;
-  if (!st.active[c]) return;
-  const int col = *st.step;
+// residual estimate, stop test for this cycle. The block that finishes last
+// (counted in *st.done after a device-scope fence) publishes the number of
+// iterating columns to host_live[col] and, when given, the residual estimates
+// to host_rel[col*ncol ..] (host-mapped memory the host reads after an event),
+// then advances the step counter: every block of the launch has read it.
+__device__ void arnoldi_column(const double* partial, int nblk, int ldp, int restart, double tol, GmresState st,
+                               int c, int col, double* hc, double* cs_, double* sn_) {
+  const int lane = threadIdx.x;
   double s = 0.0;
   for (int b = lane; b < nblk; b += 64) s += partial[((size_t)c * nblk + b) * ldp];
   s = wave_sum(s);
@@ -485,6 +502,33 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, in
   }
   __syncthreads();
   for (int k = lane; k <= col + 1; k += 64) Hc[k] = hc[k];
+}
+
+__global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, int nblk, int ldp, int restart,
+                                                       double tol, GmresState st, int* host_live, double* host_rel,
+                                                       int ncol) {
+  __shared__ double hc[kMaxRestart + 2];
+  __shared__ double cs_[kMaxRestart + 1];
+  __shared__ double sn_[kMaxRestart + 1];
+  __shared__ int last;
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int col = *st.step;
+  if (st.active[c]) arnoldi_column(partial, nblk, ldp, restart, tol, st, c, col, hc, cs_, sn_);
+  __syncthreads();
+  if (lane == 0) {
+    __threadfence();
+    last = atomicAdd(st.done, 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (host_rel)
+    for (int q = lane; q < ncol; q += 64) host_rel[(size_t)col * ncol + q] = st.relres[q];
+  if (lane == 0) {
+    host_live[col] = atomicAdd(st.live, 0);
+    *st.done = 0;
+    *st.step = col + 1;
+  }
 }
 
 // Back substitution H y = g (upper triangular kdim x kdim after the Givens
