@@ -159,6 +159,132 @@ __device__ __forceinline__ void pair_step32(Acc32<NR, TPT>& acc, const float2 (&
   }
 }
 
+// Far tiles on the matrix cores (4 and 8 columns). For a group of 16 targets
+// and four sources j..j+3, two v_mfma_f32_16x16x4f32 form
+//   D[i][2c + 0] += sum_k Qr_ik Wr_kc,  D[i][2c + 1] += sum_k Qr_ik Wi_kc   (A = Re Q)
+//   D[i][2c + 0] -= sum_k Qi_ik Wi_kc,  D[i][2c + 1] += sum_k Qi_ik Wr_kc   (A = Im Q)
+// (Q = 1/(u_i - v_k), W the weights, c < 8 complex columns), so each lane
+// forms one whole reciprocal (target i = l % 16, source k = l / 16) and uses
+// both its parts. Lane l supplies A[i = l%16][k = l/16] and B[k = l/16][n = l%16];
+// the result D[i][n] sits in register i%4 of lane n + 16(i/4). The 16
+// K-steps of a 64-node tile accumulate in FP32, then the tile's sums are
+// added to FP64 accumulators kept in the same layout (FarAcc).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int TPT>
+struct FarAcc {
+  double v[4 * TPT][4];
+};
+
+// Records of one far tile are staged in the wave's LDS area (lane k copies
+// source ts + k: eta offset and the item's NR weights), so the K-steps read
+// LDS instead of waiting on L2 at every step.
+template <int NR>
+constexpr int stage_stride() { return NR + 1; }   // float2 per staged source
+
+template <int NR, int TPT, bool FULL>
+__device__ __forceinline__ void far_ksteps(f32x4 (&accR)[4 * TPT], f32x4 (&accI)[4 * TPT],
+                                           const float (&ux)[4 * TPT], const float (&uy)[4 * TPT],
+                                           const float2* stg, int len) {
+  constexpr int G = 4 * TPT;
+  constexpr int SW = stage_stride<NR>();
+  const int lane = threadIdx.x & 63;
+  const int k = lane >> 4, n = lane & 15;
+  const bool im_col = (n & 1) != 0;
+  const int c = n >> 1;
+  const bool cvalid = c < NR;
+  const int cc = cvalid ? c : 0;
+  auto kstep = [&](int p) {     // sources 4p .. 4p + 3 of the tile
+    const int jl = 4 * p + k;
+    const bool ok = FULL || jl < len;
+    const int js = ok ? jl : 0;
+    const float2 v = stg[js * SW];
+    const float2 w = stg[js * SW + 1 + cc];
+    float b1 = im_col ? w.y : w.x;    // with A = Re Q
+    float b2 = im_col ? w.x : -w.y;   // with A = Im Q
+    if (!FULL || NR < 8) {
+      b1 = (ok && cvalid) ? b1 : 0.f;
+      b2 = (ok && cvalid) ? b2 : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const float dx = ux[q] - v.x, dy = uy[q] - v.y;
+      const float m = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
+      float qr = dx * m, qi = -dy * m;
+      if (!FULL) {
+        qr = ok ? qr : 0.f;
+        qi = ok ? qi : 0.f;
+      }
+      accR[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(qr, b1, accR[q], 0, 0, 0);
+      accI[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(qi, b2, accI[q], 0, 0, 0);
+    }
+  };
+  if constexpr (FULL) {
+#pragma unroll 4
+    for (int p = 0; p < 16; ++p) kstep(p);
+  } else {
+    for (int p = 0; p < ((len + 3) >> 2); ++p) kstep(p);
+  }
+}
+
+template <int NR, int TPT>
+__device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg)[TPT], double cx, double cy,
+                                              gptr<const float2> rec32, int stride, int wo, int ts, int te,
+                                              float2* stg) {
+  constexpr int G = 4 * TPT;
+  constexpr int SW = stage_stride<NR>();
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15;
+  const int len = te - ts;
+  if (lane < len) {
+    gptr<const float2> r = rec32 + (size_t)(ts + lane) * stride;
+    stg[lane * SW] = r[0];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) stg[lane * SW + 1 + q] = r[wo + q];
+  }
+  // targets of group g in the A layout: lane n + 16 * (g % 4) of slot g / 4
+  float ux[G], uy[G];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const float fx = (float)(tg[t].x - cx), fy = (float)(tg[t].y - cy);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      ux[4 * t + b] = __shfl(fx, 16 * b + n, 64);
+      uy[4 * t + b] = __shfl(fy, 16 * b + n, 64);
+    }
+  }
+  f32x4 accR[G], accI[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    accR[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    accI[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (len == 64) far_ksteps<NR, TPT, true>(accR, accI, ux, uy, stg, len);
+  else far_ksteps<NR, TPT, false>(accR, accI, ux, uy, stg, len);
+  // the next tile's staging overwrites stg
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int q = 0; q < G; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) F.v[q][e] += (double)(accR[q][e] + accI[q][e]);
+}
+
+// Launch modes of the pair kernel:
+//   M_FP64  every pair in FP64;
+//   M_MIXED near tiles FP64, far tiles FP32 on the VALU (1-2 columns);
+//   M_NEAR  near tiles only, FP64 (4-8 columns of a mixed product);
+// and k_far (below) takes the far tiles of an M_NEAR launch's items on the
+// matrix cores, adding to the partial sums that the M_NEAR launch wrote just
+// before. Splitting a mixed product in two keeps each kernel's register
+// footprint small (the FP64 loops and the MFMA accumulators do not share a
+// register file).
+enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2 };
+
 // One work item: the tile of 64*TPT targets starting at `base`, sources
 // [jb0, jb1) of the domain, weight columns wo-1 .. wo-1+NR-1. The four
 // wavefronts of the workgroup take consecutive quarters of the sources; their
@@ -166,12 +292,13 @@ __device__ __forceinline__ void pair_step32(Acc32<NR, TPT>& acc, const float2 (&
 // nodes are summed in FP32 (see above). All pointers are restrict-qualified
 // parameters, so after inlining the record loads are known not to alias the
 // partial-sum stores and stay scalar (wave-uniform) loads.
-template <int NR, int TPT, bool MIXED>
+template <int NR, int TPT, int MODE>
 __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
                                           gptr<const double4> tb, gptr<double2> part, int N, int stride, int wcols, int wo,
                                           int base, int tile_idx, int g, int jb0, int jb1, int wchunk, double far2,
                                           double (&red)[3][TPT][2][64]) {
   constexpr int kTile = 64 * TPT;
+  constexpr bool MIXED = MODE != M_FP64;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j0 = min(jb1, jb0 + wv * wchunk);
@@ -225,7 +352,10 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
       const double4 sbd = sb[ts >> 6];
       const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
       const double rr = tbd.z + sbd.z;
-      if ((dcx * dcx + dcy * dcy) > far2 * rr * rr) {
+      const bool far = (dcx * dcx + dcy * dcy) > far2 * rr * rr;
+      if constexpr (MODE == M_NEAR) {
+        if (!far) fp64_range(ts, te);
+      } else if (far) {
         float2 u[TPT];
 #pragma unroll
         for (int t = 0; t < TPT; ++t) u[t] = make_float2((float)(tg[t].x - sbd.x), (float)(tg[t].y - sbd.y));
@@ -293,12 +423,13 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 // One launch: one workgroup per item of the list. (A workgroup that looped
 // over several items would store partial sums before loading the next item's
 // records, and the records could then no longer be fetched with scalar loads.)
-// Variants with one or two columns are held to 64 VGPRs (8 waves per SIMD),
-// which they reach without spilling; wider ones keep their registers.
-template <int NR, int TPT, bool MIXED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NR <= 2 ? 8 : 1))) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+// FP64 variants with one or two columns are held to 64 VGPRs (8 waves per
+// SIMD), which they reach without spilling; the others keep their registers.
+template <int NR, int TPT, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 && MODE == M_FP64) ? 8 : 1))) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
                                                int nitems, int lead, int data, const int* __restrict__ active) {
   __shared__ double red[3][TPT][2][64];
+  constexpr bool MIXED = MODE != M_FP64;
   const int it = blockIdx.x;
   if (it >= nitems) return;
   const int4 w = items[it];
@@ -318,9 +449,102 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NR <= 2 ? 8
   const int jb1 = min(D.N, jb0 + chunk);
   // quarter of the chunk per wave: multiple of 4 (FP64) or whole 64-node tiles (mixed)
   const int wchunk = MIXED ? (chunk >> 2) : (((chunk + 15) >> 4) << 2);
-  pair_item<NR, TPT, MIXED>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
+  pair_item<NR, TPT, MODE>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
                             (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, wcols + 1, wcols, 1 + w.w, w.y * 64 * TPT,
                             w.y, w.z, jb0, jb1, wchunk, D.far2, red);
+}
+
+// Far tiles of one item (the items of an M_NEAR launch, 4 or 8 columns) on
+// the matrix cores, one slot of 64 targets at a time (an item of 64 TPT
+// targets takes TPT passes over its sources, so the register footprint is
+// that of 64 targets). Each wave keeps its sums in the MFMA output layout in
+// FP64 (FarAcc); at the end of a slot the four waves' sums meet in LDS and
+// each thread adds, in wave order, its complex outputs to the partial sums
+// the M_NEAR launch wrote for the same item.
+template <int NR, int TPT>
+__device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
+                                         gptr<const double4> tb, gptr<double2> part, int N, int stride, int wcols,
+                                         int wo, int base, int tile_idx, int g, int jb0, int jb1, int wchunk,
+                                         double far2, double (*fl)[64][17], float2* stg) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j0 = min(jb1, jb0 + wv * wchunk);
+  const int j1 = min(jb1, j0 + wchunk);
+  const double4 tbd = tb[tile_idx];
+  const int n = lane & 15, kq = lane >> 4;
+  for (int t = 0; t < TPT; ++t) {
+    const double2 tg[1] = {rec[(size_t)min(base + t * 64 + lane, N - 1) * stride]};
+    FarAcc<1> F;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) F.v[q][e] = 0.0;
+    for (int ts = j0; ts < j1; ts += 64) {
+      const int te = min(ts + 64, j1);
+      const double4 sbd = sb[ts >> 6];
+      const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
+      const double rr = tbd.z + sbd.z;
+      if ((dcx * dcx + dcy * dcy) > far2 * rr * rr)
+        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, rec32, stride, wo, ts, te, stg);
+    }
+    __syncthreads();   // fl shares its LDS with the staging areas
+    // group b holds rows i (targets 16b + i) in register i % 4 of lane n + 16 (i / 4), column n
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) fl[wv][16 * b + 4 * kq + e][n] = F.v[b][e];
+    __syncthreads();
+    // 64 targets x NR complex columns; thread k takes (target k % 64, columns k / 64 + 4 m)
+    const int tgt = threadIdx.x & 63;
+    const int ti = base + t * 64 + tgt;
+#pragma unroll
+    for (int m = 0; m < (NR + 3) / 4; ++m) {
+      const int cc = (threadIdx.x >> 6) + 4 * m;
+      if (cc < NR && ti < N) {
+        double x = 0.0, y = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          x += fl[q][tgt][2 * cc];
+          y += fl[q][tgt][2 * cc + 1];
+        }
+        const size_t o = ((size_t)g * wcols + wo - 1 + cc) * N + ti;
+        const double2 p = part[o];
+        part[o] = make_double2(p.x + x, p.y + y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int NR, int TPT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_far(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+                                             int nitems, int lead, int data, const int* __restrict__ active) {
+  // the final reduction tile (4 x 64 x 17 doubles) and, before it, the four
+  // waves' staging areas (64 sources x (NR + 1) float2 each) share one buffer
+  __shared__ double smem[4 * 64 * 17];
+  static_assert(4 * 64 * (NR + 1) * 2 <= 4 * 64 * 17 * 2, "staging exceeds the shared buffer");
+  double(*fl)[64][17] = reinterpret_cast<double(*)[64][17]>(smem);
+  float2* stg = reinterpret_cast<float2*>(smem) + (threadIdx.x >> 6) * 64 * (NR + 1);
+  const int it = blockIdx.x;
+  if (it >= nitems) return;
+  const int4 w = items[it];
+  const DomDev& D = doms[w.x];
+  const int wcols = lead + data * D.ncols;
+  if (active != nullptr) {
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int col = w.w + q - lead;
+      any = any || col < 0 || active[D.c0 + col] != 0;
+    }
+    if (!any) return;
+  }
+  const int chunk = D.chunk;
+  const int jb0 = w.z * chunk;
+  const int jb1 = min(D.N, jb0 + chunk);
+  far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
+                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, wcols + 1, wcols, 1 + w.w,
+                    w.y * 64 * TPT, w.y, w.z, jb0, jb1, chunk >> 2, D.far2, fl, stg);
 }
 
 // bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of
@@ -369,39 +593,54 @@ __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data)
   for (int q = 1; q < stride; ++q) o[q] = make_float2((float)r[q].x, (float)r[q].y);
 }
 
-template <int NR, int TPT, bool MIXED>
+template <int NR, int TPT, int MODE>
 void launch_k(const DomDev* doms, const int4* items, int nitems, int lead, int data, const int* active, int grid,
               hipStream_t st) {
-  k_pairs<NR, TPT, MIXED><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
+  k_pairs<NR, TPT, MODE><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
+}
+
+// FP64: one launch. Mixed: 1-2 columns in one M_MIXED launch; 4-8 columns as
+// M_NEAR then k_far over the same items (the second adds to the first's sums).
+template <int NR, int TPT>
+void launch_t(const DomDev* doms, const int4* items, int nitems, int lead, int data, bool mixed, const int* active,
+              int grid, hipStream_t st) {
+  if (!mixed) {
+    launch_k<NR, TPT, M_FP64>(doms, items, nitems, lead, data, active, grid, st);
+  } else if constexpr (NR >= 4) {
+    launch_k<NR, TPT, M_NEAR>(doms, items, nitems, lead, data, active, grid, st);
+    k_far<NR, TPT><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
+  } else {
+    launch_k<NR, TPT, M_MIXED>(doms, items, nitems, lead, data, active, grid, st);
+  }
 }
 
 template <int NR>
 void launch_w(const DomDev* doms, const int4* items, int nitems, int tpt, int lead, int data, bool mixed,
               const int* active, int grid, hipStream_t st) {
-  if (tpt == 2) {
-    if (mixed) launch_k<NR, 2, true>(doms, items, nitems, lead, data, active, grid, st);
-    else launch_k<NR, 2, false>(doms, items, nitems, lead, data, active, grid, st);
-  } else {
-    if (mixed) launch_k<NR, 1, true>(doms, items, nitems, lead, data, active, grid, st);
-    else launch_k<NR, 1, false>(doms, items, nitems, lead, data, active, grid, st);
-  }
+  if (tpt == 2) launch_t<NR, 2>(doms, items, nitems, lead, data, mixed, active, grid, st);
+  else launch_t<NR, 1>(doms, items, nitems, lead, data, mixed, active, grid, st);
 }
 
-
-template <int NR, int TPT, bool MIXED>
+template <int NR, int TPT, int MODE>
 int occupancy_of() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<NR, TPT, MIXED>, 256, 0) != hipSuccess || nb < 1) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs<NR, TPT, MODE>, 256, 0) != hipSuccess || nb < 1) {
     (void)hipGetLastError();
     nb = 8;
   }
   return nb;
 }
 
+template <int NR, int TPT>
+int occupancy_t(bool mixed) {
+  if (!mixed) return occupancy_of<NR, TPT, M_FP64>();
+  if constexpr (NR >= 4) return occupancy_of<NR, TPT, M_NEAR>();
+  return occupancy_of<NR, TPT, M_MIXED>();
+}
+
 template <int NR>
 int occupancy_w(int tpt, bool mixed) {
-  if (tpt == 2) return mixed ? occupancy_of<NR, 2, true>() : occupancy_of<NR, 2, false>();
-  return mixed ? occupancy_of<NR, 1, true>() : occupancy_of<NR, 1, false>();
+  return tpt == 2 ? occupancy_t<NR, 2>(mixed) : occupancy_t<NR, 1>(mixed);
 }
 
 }  // namespace
