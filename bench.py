@@ -12,7 +12,9 @@ value        Cauchy pair evaluations (pair x column, counted from the launches
              the library made) per second over the timed steps, Gpair/s.
 roofline     the dominant kernel (the single-column FP64 pair kernel), timed
              with HIP events recorded by the library on its own stream during
-             a second pass over the same steps, against the FP64 vector peak.
+             a second pass over the same steps, against the FP64 vector peak;
+             traffic = its HBM bytes per launch from hardware counters (null
+             once the kernel sources differ from those the counters were taken on).
 cpu_baseline the CPU oracle's pair evaluation (dense kernel-matrix rows) on a
              bounded sample of the same workload.
 mixed_vs_plain   solve time to the same tolerance on the 65-boundary
@@ -33,6 +35,23 @@ sys.path.insert(0, ROOT)
 METRIC = "N/M matvec Gpair/s (% FP64 peak) + solve time to 1e-10, mixed/batched vs plain"
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector, AMD public figure
 FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1), q (2), complex FMA (8)
+
+# HBM bytes per launch of the single-column FP64 pair kernel at N = 17408, from
+# two rocprofv3 --pmc runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 KiB, the
+# factors from a 256 MiB copy of known size; profiles/k_pairs_fp64_N17408_hbm_counters.md).
+# Valid only for the kernel sources they were taken on (hash below), else null.
+PAIR_TRAFFIC = {"sources": ("cauchy.hip", "gnk_device.h", "gnk_internal.h"),
+                "sha256": "d545474a0613ef9c021d9ee4a74a524f1bb9a8de8fd7c8845fa3a58407083939",
+                "bytes_per_launch": 8613414}
+
+
+def pair_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PAIR_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_1308_5351_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return PAIR_TRAFFIC["bytes_per_launch"] if h.hexdigest() == PAIR_TRAFFIC["sha256"] else None
 
 
 def log(msg):
@@ -143,6 +162,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed and batched comparisons")
+    ap.add_argument("--batched-mixed-only", action="store_true",
+                    help="run only the 64-domain batched solve in mixed precision (warm-up + one timed call)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain copy of 256 MiB (3 launches), the reference for HBM counters")
     args = ap.parse_args()
@@ -154,6 +175,22 @@ def main():
     import torch
     import workloads as wl
     from paper_1308_5351_amd import gnk
+
+    if args.batched_mixed_only:
+        ctx = gnk.Context(0)
+        batch = wl.config3()
+        doms = [gnk.DeviceDomain.from_host(d) for d, _ in batch]
+        gams = [torch.from_numpy(g.copy()).cuda() for _, g in batch]
+        kw = dict(restart=50, maxit=20, tol=1e-12, prec=gnk.MIXED)
+        ctx.fbie_batched(doms, gams, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, infos, st = ctx.fbie_batched(doms, gams, **kw)
+        torch.cuda.synchronize()
+        print(json.dumps({"batched_mixed_s": round(time.perf_counter() - t, 3), "status": st,
+                          "max_iters": max(i["inner_it"] for inf in infos for i in inf)}), flush=True)
+        ctx.close()
+        return
 
     dom, gam = wl.config1()
     ctx = gnk.Context(0)
@@ -221,7 +258,7 @@ def main():
                                "N=17408, A=eta, gamma=-log|eta|; step = FBIE (mu, h) + FBIEad, GMRES "
                                "restart 25, tol 1e-12",
                    "N": dom.N, "m1": dom.m1, "n": dom.n, "precision": "fp64"},
-        "matvec": {"kernel": "k_pairs<1, TPT, false> (FP64, one column)", "avg_ms": round(avg1_ms, 5),
+        "matvec": {"kernel": "k_pairs<1, TPT, M_FP64> (FP64, one column)", "avg_ms": round(avg1_ms, 5),
                    "gpair_s": round(pairs1 / (avg1_ms * 1e-3) / 1e9, 2),
                    "frac_fp64_peak": round(achieved / FP64_PEAK_TFLOPS, 4),
                    "launches_per_step": prof["launches"] / args.steps,
@@ -230,7 +267,7 @@ def main():
         "gmres_iters": {"fbie": infos[-1][0]["inner_it"], "fbie_ad": infos[-1][1]["inner_it"]},
         "true_relres": {"fbie": infos[-1][0]["true_relres"], "fbie_ad": infos[-1][1]["true_relres"]},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None},
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": pair_traffic()},
     }
     if not args.no_compare:
         out["mixed_vs_plain"] = mixed_vs_plain(gnk, ctx, torch)

@@ -50,6 +50,51 @@ def test_mixed_products_close_to_fp64(gk, ctx, small_close):
         assert 1e-12 < err < 1e-5
 
 
+@pytest.mark.parametrize("nrhs", [4, 8, 13])
+def test_mixed_products_matrix_cores(gk, ctx, small_close, nrhs):
+    """Products with 4-8 column groups take their far tiles on the matrix cores
+    (13 columns = groups of 8, 4 and 1): every column against the FP64
+    product, and against the oracle's kernel rows on sampled targets."""
+    dom, _ = small_close
+    dd = gk.DeviceDomain.from_host(dom)
+    rng = np.random.default_rng([5, nrhs])
+    x = rng.normal(size=(dom.N, nrhs))
+    xd = _cuda(x)
+    for op in (gk.OP_FB, gk.OP_FC_T):
+        y64 = ctx.apply(dd, op, xd).cpu().numpy()
+        y32 = ctx.apply(dd, op, xd, prec=gk.MIXED).cpu().numpy()
+        err = np.max(np.abs(y32 - y64), axis=0) / np.max(np.abs(y64), axis=0)
+        print(f"[mixed] nrhs {nrhs} op {op} per-column rel err max {err.max():.2e} min {err.min():.2e}", flush=True)
+        assert np.all(err < 1e-6) and np.all(err > 1e-13)
+    # FB on sampled rows from the kernel definition: y = 2x + diag(B1)x - Bx
+    rows = slice(0, dom.N, 37)
+    K = orc.kernel_rows(dom.eta, dom.etap, dom.A, dom.n, rows)
+    idx = np.arange(dom.N)[rows]
+    B = K.imag
+    ref = 2.0 * x[idx] + B.sum(axis=1)[:, None] * x[idx] - B @ x
+    y32 = ctx.apply(dd, gk.OP_FB, xd, prec=gk.MIXED).cpu().numpy()[idx]
+    assert np.max(np.abs(y32 - ref)) / np.max(np.abs(ref)) < 1e-6
+
+
+def test_batched_mixed_matrix_cores_matches_oracle(gk, ctx):
+    """Batched mixed solve of domains with 8-13 right-hand sides (matrix-core far
+    tiles) against the dense oracle, 1e-10 relative L-infinity."""
+    batch = [wl.batch_domain(d, m1_range=(8, 13), ns=(128, 256)) for d in range(3)]
+    doms = [gk.DeviceDomain.from_host(d) for d, _ in batch]
+    gams = [_cuda(g) for _, g in batch]
+    print(f"[mixed] batched sizes {[(d.m1, d.n) for d, _ in batch]}", flush=True)
+    mus, hs, infos, st = ctx.fbie_batched(doms, gams, tol=1e-13, prec=gk.MIXED, restart=50)
+    assert st == 0
+    assert max(i["mixed_steps"] for inf in infos for i in inf) >= 1
+    worst = 0.0
+    for (dom, gam), mu, h in zip(batch, mus, hs):
+        mu_o, h_o = orc.fbie(dom.eta, dom.etap, dom.A, gam, dom.n)
+        s = np.max(np.abs(gam))
+        worst = max(worst, orc.rel_linf(mu.cpu().numpy(), mu_o, s), orc.rel_linf(h.cpu().numpy(), h_o, s))
+    print(f"  worst rel err {worst:.2e}", flush=True)
+    assert worst < 1e-10
+
+
 @pytest.mark.parametrize("nrhs", [1, 2])
 def test_fbie_mixed_matches_oracle_reduced(gk, ctx, small_close, nrhs):
     """9 close boundaries (3 graded polygons), n = 256: mixed + refinement vs the dense oracle."""
