@@ -6,11 +6,12 @@
 // (eq. (e:BTx)); w = eta' gives the vector e (eq. (e:bve)).
 //
 // Mapping (VALU-bound, no matrix cores: every pair needs its own reciprocal):
-//   * sources are packed records {eta_j, w_j,0 .. w_j,ncols-1} (16 B each
-//     field); the source loop index is wave-uniform, so whole records arrive
-//     with wide scalar loads into SGPRs and are broadcast to all lanes (no LDS
-//     traffic, no bank conflicts); four sources are fetched per iteration so
-//     one wait covers four reciprocals;
+//   * sources are packed records {eta_j, eta'_j, w_j,q.., b_j,q..} (16 B each
+//     field; eta' = eta - centre of the node's 64-node tile, b = w conj(eta'));
+//     the source loop index is wave-uniform, so whole records arrive with wide
+//     scalar loads into SGPRs and are broadcast to all lanes (no LDS traffic,
+//     no bank conflicts); four sources are fetched per iteration so one wait
+//     covers four reciprocals;
 //   * each lane owns TPT target nodes (a tile of TPT*64 consecutive targets),
 //     which reuses every fetched source TPT times and gives independent chains;
 //   * the four wavefronts of a workgroup share the tile and split its source
@@ -100,6 +101,56 @@ __device__ __forceinline__ void quad_step(Acc<NR, TPT>& acc, const double2 (&tg)
     accumulate<NR, TPT>(acc, t, rb + wo, dxb * qb, -dyb * qb);
     accumulate<NR, TPT>(acc, t, rc + wo, dxc * qc, -dyc * qc);
     accumulate<NR, TPT>(acc, t, rd + wo, dxd * qd, -dyd * qd);
+  }
+}
+
+// Far source tiles in FP64, one column. With z' = z_i - c and
+// eta'_j = eta_j - c (c the source tile's centre) and m = 1/|z' - eta'_j|^2,
+//   S_i = sum_j w_j conj(z' - eta'_j) m = conj(z') sum_j w_j m - sum_j b_j m,
+// b_j = w_j conj(eta'_j) taken from the record: per pair two FMAs per part
+// and no product for q. The tile pair is far, so |eta'_j| <= r_s < |z' - eta'_j|
+// and the two sums do not cancel.
+template <int NR, int TPT>
+struct AccAB {
+  double ax[TPT][NR], ay[TPT][NR], bx[TPT][NR], by[TPT][NR];
+};
+
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void accumulate_ab(AccAB<NR, TPT>& a, int t, P r, int wo, int wb, double m) {
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const double2 w = r[wo + q], b = r[wb + q];
+    a.ax[t][q] = __builtin_fma(w.x, m, a.ax[t][q]);
+    a.ay[t][q] = __builtin_fma(w.y, m, a.ay[t][q]);
+    a.bx[t][q] = __builtin_fma(b.x, m, a.bx[t][q]);
+    a.by[t][q] = __builtin_fma(b.y, m, a.by[t][q]);
+  }
+}
+
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void pair_step_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT], const double (&zy)[TPT],
+                                              P ra, P rb, int wo, int wb) {
+  const double2 ea = ra[1], eb = rb[1];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const double dxa = zx[t] - ea.x, dya = zy[t] - ea.y;
+    const double dxb = zx[t] - eb.x, dyb = zy[t] - eb.y;
+    const double da = __builtin_fma(dya, dya, dxa * dxa);
+    const double db = __builtin_fma(dyb, dyb, dxb * dxb);
+    const double R = refine_rcp(da * db);
+    accumulate_ab<NR, TPT>(acc, t, ra, wo, wb, db * R);
+    accumulate_ab<NR, TPT>(acc, t, rb, wo, wb, da * R);
+  }
+}
+
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void single_step_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT],
+                                                const double (&zy)[TPT], P r, int wo, int wb) {
+  const double2 e = r[1];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const double dx = zx[t] - e.x, dy = zy[t] - e.y;
+    accumulate_ab<NR, TPT>(acc, t, r, wo, wb, refine_rcp(__builtin_fma(dy, dy, dx * dx)));
   }
 }
 
@@ -286,7 +337,7 @@ __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg
 enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2 };
 
 // One work item: the tile of 64*TPT targets starting at `base`, sources
-// [jb0, jb1) of the domain, weight columns wo-1 .. wo-1+NR-1. The four
+// [jb0, jb1) of the domain, weight columns col0 .. col0+NR-1. The four
 // wavefronts of the workgroup take consecutive quarters of the sources; their
 // sums are added through LDS in wave order. MIXED: far source tiles of 64
 // nodes are summed in FP32 (see above). All pointers are restrict-qualified
@@ -294,10 +345,13 @@ enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2 };
 // partial-sum stores and stay scalar (wave-uniform) loads.
 template <int NR, int TPT, int MODE>
 __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
-                                          gptr<const double4> tb, gptr<double2> part, int N, int stride, int wcols, int wo,
-                                          int base, int tile_idx, int g, int jb0, int jb1, int wchunk, double far2,
-                                          double (&red)[3][TPT][2][64]) {
+                                          gptr<const double4> tb, gptr<double2> part, int N, int stride, int stride32,
+                                          int wcols, int col0, int base, int tile_idx, int g, int jb0, int jb1,
+                                          int wchunk, double far2, double (&red)[3][TPT][2][64]) {
   constexpr int kTile = 64 * TPT;
+  const int wo = 2 + col0;            // FP64 record: weights of the item's first column
+  const int wb = 2 + wcols + col0;    // FP64 record: its b = w conj(eta')
+  const int wo32 = 1 + col0;          // FP32 record: weights
   constexpr bool MIXED = MODE != M_FP64;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -343,7 +397,46 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
     plain(max(ja, base + kTile), jb);
   };
 
-  if (!MIXED) {
+  if constexpr (!MIXED && NR == 1) {
+    // 64-node source tiles (segments of them at the range ends): far ones by
+    // the A/B form on coordinates relative to the tile centre, the rest as above
+    const double4 tbd = tb[tile_idx];
+    for (int ts = j0; ts < j1;) {
+      const int te = min(((ts >> 6) + 1) << 6, j1);
+      const double4 sbd = sb[ts >> 6];
+      const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
+      const double rr = tbd.z + sbd.z;
+      if ((dcx * dcx + dcy * dcy) > far2 * rr * rr) {
+        double zx[TPT], zy[TPT];
+        AccAB<NR, TPT> ab;
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) {
+          zx[t] = tg[t].x - sbd.x;
+          zy[t] = tg[t].y - sbd.y;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) ab.ax[t][r] = ab.ay[t][r] = ab.bx[t][r] = ab.by[t][r] = 0.0;
+        }
+        int j = ts;
+        // two sources per reciprocal: four records with three fields each would
+        // not fit in scalar registers beside the loop state
+        for (; j + 1 < te; j += 2) {
+          gptr<const double2> r = rec + (size_t)j * stride;
+          pair_step_far<NR, TPT>(ab, zx, zy, r, r + stride, wo, wb);
+        }
+        for (; j < te; ++j) single_step_far<NR, TPT>(ab, zx, zy, rec + (size_t)j * stride, wo, wb);
+#pragma unroll
+        for (int t = 0; t < TPT; ++t)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            acc.x[t][r] += __builtin_fma(zx[t], ab.ax[t][r], zy[t] * ab.ay[t][r]) - ab.bx[t][r];
+            acc.y[t][r] += __builtin_fma(zx[t], ab.ay[t][r], -zy[t] * ab.ax[t][r]) - ab.by[t][r];
+          }
+      } else {
+        fp64_range(ts, te);
+      }
+      ts = te;
+    }
+  } else if (!MIXED) {
     fp64_range(j0, j1);
   } else {
     const double4 tbd = tb[tile_idx];
@@ -367,17 +460,17 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
         int j = ts;
 #pragma unroll 2
         for (; j + 1 < te; j += 2) {
-          gptr<const float2> r = rec32 + (size_t)j * stride;
-          pair_step32<NR, TPT>(a32, u, r, r + stride, wo);
+          gptr<const float2> r = rec32 + (size_t)j * stride32;
+          pair_step32<NR, TPT>(a32, u, r, r + stride32, wo32);
         }
         if (j < te) {
-          gptr<const float2> r = rec32 + (size_t)j * stride;
+          gptr<const float2> r = rec32 + (size_t)j * stride32;
           const float2 e = r[0];
 #pragma unroll
           for (int t = 0; t < TPT; ++t) {
             const float dx = u[t].x - e.x, dy = u[t].y - e.y;
             const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
-            accumulate32<NR, TPT>(a32, t, r + wo, dx * q, -dy * q);
+            accumulate32<NR, TPT>(a32, t, r + wo32, dx * q, -dy * q);
           }
         }
 #pragma unroll
@@ -413,7 +506,7 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
           x += red[q][t][0][lane];
           y += red[q][t][1][lane];
         }
-        if (ti[t] < N) part[((size_t)g * wcols + wo - 1 + r) * N + ti[t]] = make_double2(x, y);
+        if (ti[t] < N) part[((size_t)g * wcols + col0 + r) * N + ti[t]] = make_double2(x, y);
       }
     }
     __syncthreads();
@@ -450,8 +543,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
   // quarter of the chunk per wave: multiple of 4 (FP64) or whole 64-node tiles (mixed)
   const int wchunk = MIXED ? (chunk >> 2) : (((chunk + 15) >> 4) << 2);
   pair_item<NR, TPT, MODE>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
-                            (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, wcols + 1, wcols, 1 + w.w, w.y * 64 * TPT,
-                            w.y, w.z, jb0, jb1, wchunk, D.far2, red);
+                            (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, 2 + 2 * wcols, 1 + wcols, wcols,
+                            w.w, w.y * 64 * TPT, w.y, w.z, jb0, jb1, wchunk, D.far2, red);
 }
 
 // Far tiles of one item (the items of an M_NEAR launch, 4 or 8 columns) on
@@ -463,8 +556,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
 // the M_NEAR launch wrote for the same item.
 template <int NR, int TPT>
 __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
-                                         gptr<const double4> tb, gptr<double2> part, int N, int stride, int wcols,
-                                         int wo, int base, int tile_idx, int g, int jb0, int jb1, int wchunk,
+                                         gptr<const double4> tb, gptr<double2> part, int N, int stride, int stride32,
+                                         int wcols, int col0, int base, int tile_idx, int g, int jb0, int jb1, int wchunk,
                                          double far2, double (*fl)[64][17], float2* stg) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -485,7 +578,7 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
       const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
       const double rr = tbd.z + sbd.z;
       if ((dcx * dcx + dcy * dcy) > far2 * rr * rr)
-        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, rec32, stride, wo, ts, te, stg);
+        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, rec32, stride32, 1 + col0, ts, te, stg);
     }
     __syncthreads();   // fl shares its LDS with the staging areas
     // group b holds rows i (targets 16b + i) in register i % 4 of lane n + 16 (i / 4), column n
@@ -507,7 +600,7 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
           x += fl[q][tgt][2 * cc];
           y += fl[q][tgt][2 * cc + 1];
         }
-        const size_t o = ((size_t)g * wcols + wo - 1 + cc) * N + ti;
+        const size_t o = ((size_t)g * wcols + col0 + cc) * N + ti;
         const double2 p = part[o];
         part[o] = make_double2(p.x + x, p.y + y);
       }
@@ -543,8 +636,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int jb0 = w.z * chunk;
   const int jb1 = min(D.N, jb0 + chunk);
   far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
-                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, wcols + 1, wcols, 1 + w.w,
-                    w.y * 64 * TPT, w.y, w.z, jb0, jb1, chunk >> 2, D.far2, fl, stg);
+                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, 2 + 2 * wcols, 1 + wcols, wcols,
+                    w.w, w.y * 64 * TPT, w.y, w.z, jb0, jb1, chunk >> 2, D.far2, fl, stg);
 }
 
 // bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of
@@ -580,17 +673,17 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ d
   if (lane == 0) (target ? D.tb : D.sb)[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
 }
 
-// FP32 records: v_j = eta_j - c_{tile(j)}, then the weights rounded to FP32
+// FP32 records {v_j = eta_j - c_tile(j), w_j,q..} (stride 1 + wcols) from the
+// FP64 records {eta, eta', w.., b..} (stride 2 + 2 wcols)
 __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data) {
   const DomDev& D = doms[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= D.N) return;
-  const int stride = lead + data * D.ncols + 1;
-  const double2* r = D.rec + (size_t)j * stride;
-  float2* o = D.rec32 + (size_t)j * stride;
-  const double4 c = D.sb[j >> 6];
-  o[0] = make_float2((float)(r[0].x - c.x), (float)(r[0].y - c.y));
-  for (int q = 1; q < stride; ++q) o[q] = make_float2((float)r[q].x, (float)r[q].y);
+  const int wcols = lead + data * D.ncols;
+  const double2* r = D.rec + (size_t)j * (2 + 2 * wcols);
+  float2* o = D.rec32 + (size_t)j * (1 + wcols);
+  o[0] = make_float2((float)r[1].x, (float)r[1].y);
+  for (int q = 0; q < wcols; ++q) o[1 + q] = make_float2((float)r[2 + q].x, (float)r[2 + q].y);
 }
 
 template <int NR, int TPT, int MODE>

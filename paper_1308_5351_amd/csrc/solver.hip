@@ -246,7 +246,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   B.adjoint = adjoint;
   B.shape = shape;
   const int align = mixed ? 256 : 16;
-  int64_t Ntot = 0, rec_total = 0, part_total = 0, sb_total = 0, tb_total = 0;
+  int64_t Ntot = 0, rec_total = 0, rec32_total = 0, part_total = 0, sb_total = 0, tb_total = 0;
   B.dom.resize(ndom);
   int c0 = 0;
   for (int d = 0; d < ndom; ++d) {
@@ -283,7 +283,8 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     B.maxN = std::max(B.maxN, D.N);
     B.maxm1 = std::max(B.maxm1, D.m1);
     Ntot += D.N;
-    rec_total += (int64_t)D.N * (D.ncols + 2);
+    rec_total += (int64_t)D.N * (2 * D.ncols + 4);   // {eta, eta', w.., b..} with a lead column
+    rec32_total += (int64_t)D.N * (D.ncols + 2);
     part_total += (int64_t)D.splits * (D.ncols + 1) * D.N;
     sb_total += (D.N + 63) / 64;
     tb_total += (D.N + 63) / 64;
@@ -294,13 +295,14 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   double* dD = ws<double>(c, "b_dD", Ntot);
   double* ev = adjoint ? ws<double>(c, "b_e", Ntot) : nullptr;
   double2* rec = ws<double2>(c, "b_rec", rec_total);
-  float2* rec32 = mixed ? ws<float2>(c, "b_rec32", rec_total) : nullptr;
+  float2* rec32 = mixed ? ws<float2>(c, "b_rec32", rec32_total) : nullptr;
   double2* parts = ws<double2>(c, "b_parts", part_total);
-  double4* sb = mixed ? ws<double4>(c, "b_sb", sb_total) : nullptr;
-  double4* tb = mixed ? ws<double4>(c, "b_tb", tb_total) : nullptr;
+  // tile bounds: far-tile classification (both precisions) and tile-relative records
+  double4* sb = ws<double4>(c, "b_sb", sb_total);
+  double4* tb = ws<double4>(c, "b_tb", tb_total);
   double theta = 1.0;
   if (const char* e = getenv("GNK_MIXED_THETA")) theta = atof(e);
-  int64_t on = 0, orc = 0, op = 0, osb = 0, otb = 0;
+  int64_t on = 0, orc = 0, orc32 = 0, op = 0, osb = 0, otb = 0;
   for (int d = 0; d < ndom; ++d) {
     DomDev& D = B.dom[d];
     D.rho = rho + on;
@@ -308,13 +310,14 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     D.dD = dD + on;
     D.e = ev ? ev + on : nullptr;
     D.rec = rec + orc;
-    D.rec32 = rec32 ? rec32 + orc : nullptr;
+    D.rec32 = rec32 ? rec32 + orc32 : nullptr;
     D.parts = parts + op;
     D.sb = sb ? sb + osb : nullptr;
     D.tb = tb ? tb + otb : nullptr;
     D.far2 = (1.0 + theta) * (1.0 + theta);
     on += D.N;
-    orc += (int64_t)D.N * (D.ncols + 2);
+    orc += (int64_t)D.N * (2 * D.ncols + 4);
+    orc32 += (int64_t)D.N * (D.ncols + 2);
     op += (int64_t)D.splits * (D.ncols + 1) * D.N;
     osb += (D.N + 63) / 64;
     otb += (D.N + 63) / 64;
@@ -322,10 +325,8 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   }
   B.d_dom = upload(c, "b_dom", B.dom);
   B.d_col = upload(c, "b_col", B.col);
-  if (mixed) {
-    HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64, false, c->stream));
-    HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64 * B.shape.tpt, true, c->stream));
-  }
+  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64, false, c->stream));
+  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64 * B.shape.tpt, true, c->stream));
 }
 
 // Work items of a pattern: every domain (largest first), column group, target
@@ -1199,8 +1200,7 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
     Batch B;
     std::vector<int64_t> off{0};
     build_batch(c, B, 1, &d, &nrhs, off, N * (int64_t)nrhs, false, false, PairShape{}, N);
-    k_pack_records<<<nblocks(N), kT, 0, c->stream>>>(static_cast<const double2*>(eta),
-                                                      static_cast<const double2*>(w), (int)N, nrhs, B.dom[0].rec);
+    k_pack_records<<<nblocks(N), kT, 0, c->stream>>>(B.d_dom, static_cast<const double2*>(w), nrhs);
     LAUNCHCHK(c);
     pairs(c, B, P_GM, false, nullptr);
     k_reduce_parts<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(B.d_dom, static_cast<double2*>(S));

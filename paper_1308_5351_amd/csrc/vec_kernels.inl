@@ -48,6 +48,16 @@ enum DSel : int { D_NONE = 0, D_B = 1, D_D = 2, D_E = 3 };
 __device__ __forceinline__ double2 coef(const DomDev& D, int sel, int i) {
   return sel == C_RHO ? D.rho[i] : (sel == C_A ? D.A[i] : D.etap[i]);
 }
+// eta_j relative to the centre of its 64-node tile (the pair kernels' far form)
+__device__ __forceinline__ double2 eta_rel(const DomDev& D, int j) {
+  const double2 e = D.eta[j];
+  const double4 c = D.sb[j >> 6];
+  return make_double2(e.x - c.x, e.y - c.y);
+}
+// a * conj(b)
+__device__ __forceinline__ double2 cmul_conj(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
 __device__ __forceinline__ double diagv(const DomDev& D, int sel, int i) {
   return sel == D_B ? D.dB[i] : (sel == D_D ? D.dD[i] : (sel == D_E ? D.e[i] : 0.0));
 }
@@ -128,8 +138,11 @@ __global__ void k_evec(const DomDev* __restrict__ doms) {
 }
 
 // ----------------------------------------------- source records and means
-// Records rec_d[j*stride]: eta_j; field 1 = C_j when lead; fields 1+lead+r =
-// C_j * v_j for the domain's column r, with
+// FP64 records rec_d[j*stride], stride = 2 + 2 wcols (wcols = lead + ncols):
+//   [0] eta_j, [1] eta'_j = eta_j - c (c the centre of j's 64-node tile),
+//   [2 + q] w_q, [2 + wcols + q] b_q = w_q conj(eta'_j),
+// with weight column q = 0 the leading coefficient C_j when lead, and
+// q = lead + r the value C_j * v_j of the domain's column r, where
 //   v = x * scale[c]                  (optional; written back to xout)
 //   mean[c*M + k] = (1/n) sum_p v_{k n + p}   (optional, component means)
 // grid (max m1, ncol): block (k, c) covers component k of column c.
@@ -152,7 +165,8 @@ __global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms,
   if (k >= D.m1) return;
   if (active && !active[c]) return;
   const double s = scale ? scale[c] : 1.0;
-  const int stride = lead + D.ncols + 1;
+  const int wcols = lead + D.ncols;
+  const int stride = 2 + 2 * wcols;
   const double* xr = x + C.off + (size_t)k * D.n;
   double acc = 0.0;
   for (int p = threadIdx.x; p < D.n; p += blockDim.x) {
@@ -160,11 +174,18 @@ __global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms,
     const double v = xr[p] * s;
     if (xout) xout[C.off + j] = v;
     const double2 cf = coef(D, csel, j);
+    const double2 ep = eta_rel(D, j);
     double2* rj = D.rec + (size_t)j * stride;
-    rj[1 + lead + C.r] = make_double2(cf.x * v, cf.y * v);
+    const double2 w = make_double2(cf.x * v, cf.y * v);
+    rj[2 + lead + C.r] = w;
+    rj[2 + wcols + lead + C.r] = cmul_conj(w, ep);
     if (C.r == 0) {
       rj[0] = D.eta[j];
-      if (lead) rj[1] = cf;
+      rj[1] = ep;
+      if (lead) {
+        rj[2] = cf;
+        rj[2 + wcols] = cmul_conj(cf, ep);
+      }
     }
     acc += v;
   }
@@ -174,23 +195,34 @@ __global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms,
   }
 }
 
-// records holding only the leading column: rec_d[j*2] = eta_j, rec_d[j*2+1] = C_j
+// records holding only the leading column (stride 4): eta, eta', C_j, C_j conj(eta')
 __global__ void k_lead_records(const DomDev* __restrict__ doms, int csel) {
   const DomDev& D = doms[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= D.N) return;
-  D.rec[(size_t)j * 2] = D.eta[j];
-  D.rec[(size_t)j * 2 + 1] = coef(D, csel, j);
+  const double2 ep = eta_rel(D, j);
+  const double2 cf = coef(D, csel, j);
+  double2* rj = D.rec + (size_t)j * 4;
+  rj[0] = D.eta[j];
+  rj[1] = ep;
+  rj[2] = cf;
+  rj[3] = cmul_conj(cf, ep);
 }
 
-// records from eta and column-major complex weights w (N x ncols), one domain
-__global__ void k_pack_records(const double2* __restrict__ eta, const double2* __restrict__ w, int N, int ncols,
-                               double2* __restrict__ rec) {
+// records of one domain from column-major complex weights w (N x ncols)
+__global__ void k_pack_records(const DomDev* __restrict__ doms, const double2* __restrict__ w, int ncols) {
+  const DomDev& D = doms[0];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  double2* rj = rec + (size_t)j * (ncols + 1);
-  rj[0] = eta[j];
-  for (int r = 0; r < ncols; ++r) rj[1 + r] = w[(size_t)r * N + j];
+  if (j >= D.N) return;
+  const double2 ep = eta_rel(D, j);
+  double2* rj = D.rec + (size_t)j * (2 + 2 * ncols);
+  rj[0] = D.eta[j];
+  rj[1] = ep;
+  for (int r = 0; r < ncols; ++r) {
+    const double2 v = w[(size_t)r * D.N + j];
+    rj[2 + r] = v;
+    rj[2 + ncols + r] = cmul_conj(v, ep);
+  }
 }
 
 // S[r*N + i] = sum over the splits of column r (one domain, no lead column)
