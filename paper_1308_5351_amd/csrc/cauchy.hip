@@ -328,12 +328,12 @@ __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg
 // Launch modes of the pair kernel:
 //   M_FP64  every pair in FP64;
 //   M_MIXED near tiles FP64, far tiles FP32 on the VALU (1-2 columns);
-//   M_NEAR  near tiles only, FP64 (4-8 columns of a mixed product);
-// and k_far (below) takes the far tiles of an M_NEAR launch's items on the
-// matrix cores, adding to the partial sums that the M_NEAR launch wrote just
-// before. Splitting a mixed product in two keeps each kernel's register
-// footprint small (the FP64 loops and the MFMA accumulators do not share a
-// register file).
+//   M_NEAR  near tiles only, FP64 (4-8 columns of a mixed product), added to
+//           the partial sums that k_far (below) wrote for the same items just
+//           before; items without a near tile store nothing.
+// k_far takes the far tiles on the matrix cores. Splitting a mixed product in
+// two keeps each kernel's register footprint small (the FP64 loops and the
+// MFMA accumulators do not share a register file).
 enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2 };
 
 // One work item: the tile of 64*TPT targets starting at `base`, sources
@@ -397,6 +397,7 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
     plain(max(ja, base + kTile), jb);
   };
 
+  bool any_near = false;
   if constexpr (!MIXED && NR == 1) {
     // 64-node source tiles (segments of them at the range ends): far ones by
     // the A/B form on coordinates relative to the tile centre, the rest as above
@@ -447,7 +448,10 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
       const double rr = tbd.z + sbd.z;
       const bool far = (dcx * dcx + dcy * dcy) > far2 * rr * rr;
       if constexpr (MODE == M_NEAR) {
-        if (!far) fp64_range(ts, te);
+        if (!far) {
+          fp64_range(ts, te);
+          any_near = true;
+        }
       } else if (far) {
         float2 u[TPT];
 #pragma unroll
@@ -486,6 +490,9 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
     }
   }
 
+  if constexpr (MODE == M_NEAR) {
+    if (!__syncthreads_or(any_near ? 1 : 0)) return;   // k_far's sums are complete
+  }
   // fixed-order reduction over the four wavefronts, one column at a time
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -506,7 +513,15 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
           x += red[q][t][0][lane];
           y += red[q][t][1][lane];
         }
-        if (ti[t] < N) part[((size_t)g * wcols + col0 + r) * N + ti[t]] = make_double2(x, y);
+        if (ti[t] < N) {
+          const size_t o = ((size_t)g * wcols + col0 + r) * N + ti[t];
+          if constexpr (MODE == M_NEAR) {
+            const double2 p = part[o];
+            x += p.x;
+            y += p.y;
+          }
+          part[o] = make_double2(x, y);
+        }
       }
     }
     __syncthreads();
@@ -552,8 +567,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
 // targets takes TPT passes over its sources, so the register footprint is
 // that of 64 targets). Each wave keeps its sums in the MFMA output layout in
 // FP64 (FarAcc); at the end of a slot the four waves' sums meet in LDS and
-// each thread adds, in wave order, its complex outputs to the partial sums
-// the M_NEAR launch wrote for the same item.
+// each thread writes, in wave order, its complex outputs to the partial sums
+// (the M_NEAR launch that follows adds the near tiles).
 template <int NR, int TPT>
 __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
                                          gptr<const double4> tb, gptr<double2> part, int N, int stride, int stride32,
@@ -600,9 +615,7 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
           x += fl[q][tgt][2 * cc];
           y += fl[q][tgt][2 * cc + 1];
         }
-        const size_t o = ((size_t)g * wcols + col0 + cc) * N + ti;
-        const double2 p = part[o];
-        part[o] = make_double2(p.x + x, p.y + y);
+        part[((size_t)g * wcols + col0 + cc) * N + ti] = make_double2(x, y);
       }
     }
     __syncthreads();
@@ -693,15 +706,15 @@ void launch_k(const DomDev* doms, const int4* items, int nitems, int lead, int d
 }
 
 // FP64: one launch. Mixed: 1-2 columns in one M_MIXED launch; 4-8 columns as
-// M_NEAR then k_far over the same items (the second adds to the first's sums).
+// k_far then M_NEAR over the same items (the second adds to the first's sums).
 template <int NR, int TPT>
 void launch_t(const DomDev* doms, const int4* items, int nitems, int lead, int data, bool mixed, const int* active,
               int grid, hipStream_t st) {
   if (!mixed) {
     launch_k<NR, TPT, M_FP64>(doms, items, nitems, lead, data, active, grid, st);
   } else if constexpr (NR >= 4) {
-    launch_k<NR, TPT, M_NEAR>(doms, items, nitems, lead, data, active, grid, st);
     k_far<NR, TPT><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
+    launch_k<NR, TPT, M_NEAR>(doms, items, nitems, lead, data, active, grid, st);
   } else {
     launch_k<NR, TPT, M_MIXED>(doms, items, nitems, lead, data, active, grid, st);
   }

@@ -33,6 +33,10 @@ struct gnk_ctx {
   hipStream_t stream = nullptr;       // stream of all work (the caller's, or own_stream)
   hipStream_t own_stream = nullptr;   // blocking, default priority: capturable into graphs
   bool graphs = true;                 // replay the Arnoldi step from a captured hipGraph
+  // instantiated Arnoldi-step graphs (FP64, mixed), kept across solves: each
+  // solve captures its step and refreshes these with hipGraphExecUpdate, which
+  // avoids a new instantiation when only kernel arguments changed
+  hipGraphExec_t step_exec[2] = {nullptr, nullptr};
   std::string err;
   int num_cu = 256;
   size_t ws_limit = 0;   // bytes, 0 = unlimited
@@ -64,6 +68,12 @@ struct gnk_ctx {
   bool tune_loaded = false;
   // host copies of uploaded tables stay alive until the next call
   std::vector<std::vector<char>> host_keep;
+  // last contents uploaded to each named table: an unchanged table is not copied again
+  std::map<std::string, std::pair<void*, std::vector<char>>> up_last;
+  // host-mapped pinned memory that small kernels fill with results the host
+  // reads after a stream synchronisation (flags, live count, per-column info)
+  char* hostio = nullptr;
+  size_t hostio_bytes = 0;
 };
 
 namespace gnk {
@@ -128,13 +138,41 @@ template <class T>
 T* upload(gnk_ctx* c, const std::string& name, const std::vector<T>& v) {
   T* d = ws<T>(c, name, std::max<size_t>(v.size(), 1));
   if (!v.empty()) {
+    auto& last = c->up_last[name];
+    const size_t nb = sizeof(T) * v.size();
+    if (last.first == (void*)d && last.second.size() == nb && memcmp(last.second.data(), v.data(), nb) == 0)
+      return d;   // the device table already holds these contents
+    last.first = nullptr;   // set again once the copy is enqueued
     std::vector<char> keep(sizeof(T) * v.size());
     memcpy(keep.data(), v.data(), keep.size());
     c->host_keep.push_back(std::move(keep));
     HIPCHK(c, hipMemcpyAsync(d, c->host_keep.back().data(), sizeof(T) * v.size(), hipMemcpyHostToDevice,
                              c->stream));
+    last.first = d;
+    last.second.assign(reinterpret_cast<const char*>(v.data()), reinterpret_cast<const char*>(v.data()) + nb);
   }
   return d;
+}
+
+// host-mapped pinned buffer of at least `bytes` (host pointer; the device
+// pointer comes from hostio_dev). Grown only between uses: every call ends
+// synchronised, and each use waits for its kernel before reading.
+char* hostio(gnk_ctx* c, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 4096);
+  if (c->hostio_bytes < bytes) {
+    if (c->hostio) HIPCHK(c, hipHostFree(c->hostio));
+    c->hostio = nullptr;
+    c->hostio_bytes = 0;
+    HIPCHK(c, hipHostMalloc((void**)&c->hostio, bytes, 0));
+    c->hostio_bytes = bytes;
+  }
+  return c->hostio;
+}
+template <class T>
+T* hostio_dev(gnk_ctx* c, T* host) {
+  void* d = nullptr;
+  HIPCHK(c, hipHostGetDevicePointer(&d, host, 0));
+  return static_cast<T*>(d);
 }
 
 unsigned nblocks(int64_t n, int t = kT) { return (unsigned)((n + t - 1) / t); }
@@ -441,9 +479,11 @@ void validate(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
     k_check_finite<<<nblocks(len), kT, 0, c->stream>>>(x, len, flags);
     LAUNCHCHK(c);
   }
-  int h = 0;
-  HIPCHK(c, hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  int* hf = reinterpret_cast<int*>(hostio(c, sizeof(int)));
+  k_publish_ints<<<1, 64, 0, c->stream>>>(flags, 1, hostio_dev(c, hf));
+  LAUNCHCHK(c);
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int h = hf[0];
   if (h & 1) {
     set_err(c, "non-finite value in the inputs");
     throw Fail{GNK_ERR_NONFINITE};
@@ -675,21 +715,15 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   build_items(c, B, P_GM);
   if (op == GNK_OP_GB || op == GNK_OP_GB_T) (void)ws<double>(c, "mean", (size_t)B.ncol * B.maxm1);
   const bool use_graph = c->graphs && !c->prof;
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
-  struct ExecGuard {
-    hipGraphExec_t* e;
-    ~ExecGuard() {
-      for (int k = 0; k < 2; ++k)
-        if (e[k]) (void)hipGraphExecDestroy(e[k]);
-    }
-  } guard{exec};
+  bool fresh[2] = {false, false};   // cached graph matches this solve's step
   auto launch_step = [&](bool use_mixed) {
     if (!use_graph) {
       enqueue_step(use_mixed);
       return;
     }
-    hipGraphExec_t& ge = exec[use_mixed ? 1 : 0];
-    if (!ge) {
+    const int m = use_mixed ? 1 : 0;
+    hipGraphExec_t& ge = c->step_exec[m];
+    if (!fresh[m]) {
       hipGraph_t graph = nullptr;
       HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
       try {
@@ -701,9 +735,23 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
         throw;
       }
       HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
-      const hipError_t e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+      bool updated = false;
+      if (ge) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        updated = hipGraphExecUpdate(ge, graph, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+          (void)hipGetLastError();
+          (void)hipGraphExecDestroy(ge);
+          ge = nullptr;
+        }
+      }
+      hipError_t e = hipSuccess;
+      if (!updated) e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) ge = nullptr;
       HIPCHK(c, e);
+      fresh[m] = true;
     }
     HIPCHK(c, hipGraphLaunch(ge, c->stream));
   };
@@ -715,12 +763,28 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     c->step_ev.push_back(e);
   }
+  // per-column results read back through host-mapped memory: [live, converged..]
+  // at each cycle start; converged, inner_it, relres, true_relres at the end
+  char* hio = hostio(c, (sizeof(int) * 2 + sizeof(double) * 2) * (ncol + 1));
+  int* hi = reinterpret_cast<int*>(hio);
+  double* hd = reinterpret_cast<double*>(hio + sizeof(int) * 2 * (ncol + 1));
+  int* hi_dev = hostio_dev(c, hi);
+  double* hd_dev = hostio_dev(c, hd);
   for (int cyc = 0; cyc < o.maxit; ++cyc) {
-    int live = 0;
-    HIPCHK(c, hipMemcpyAsync(&live, st.live, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(conv.data(), st.converged, sizeof(int) * ncol, hipMemcpyDeviceToHost, c->stream));
+    k_publish_cycle<<<nblocks(ncol + 1), kT, 0, c->stream>>>(st, ncol, hi_dev, hd_dev);
+    LAUNCHCHK(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int live = hi[0];
+    for (int q = 0; q < ncol; ++q) conv[q] = hi[1 + q];
     if (live == 0) break;
+    // a cycle whose starting (FP64) residual is already below inner_tol
+    // takes mixed products from its first step
+    if (mixed && !mixed_now) {
+      double mx = 0.0;
+      for (int q = 0; q < ncol; ++q)
+        if (!conv[q]) mx = std::max(mx, hd[q]);
+      if (mx <= o.inner_tol) mixed_now = true;
+    }
     for (int q = 0; q < ncol; ++q)
       if (!conv[q]) outer[q] += 1;
     // Arnoldi steps. The host looks one step behind the device: before
@@ -767,11 +831,15 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   out.info.resize(ncol);
   std::vector<double> rel(ncol), trel(ncol);
   std::vector<int> inner(ncol);
-  HIPCHK(c, hipMemcpyAsync(conv.data(), st.converged, sizeof(int) * ncol, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(rel.data(), st.relres, sizeof(double) * ncol, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(trel.data(), st.true_relres, sizeof(double) * ncol, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(inner.data(), st.inner_it, sizeof(int) * ncol, hipMemcpyDeviceToHost, c->stream));
+  k_publish_info<<<nblocks(ncol), kT, 0, c->stream>>>(st, ncol, hi_dev, hd_dev);
+  LAUNCHCHK(c);
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int q = 0; q < ncol; ++q) {
+    conv[q] = hi[q];
+    inner[q] = hi[ncol + q];
+    rel[q] = hd[q];
+    trel[q] = hd[ncol + q];
+  }
   out.all_converged = true;
   for (int q = 0; q < ncol; ++q) {
     gnk_info& I = out.info[q];
@@ -1129,6 +1197,8 @@ gnk_status gnk_destroy(gnk_ctx* c) {
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto e : c->step_ev) (void)hipEventDestroy(e);
+  for (auto& g : c->step_exec)
+    if (g) (void)hipGraphExecDestroy(g);
   for (auto& r : c->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -1136,6 +1206,7 @@ gnk_status gnk_destroy(gnk_ctx* c) {
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->pinned_rel) (void)hipHostFree(c->pinned_rel);
+  if (c->hostio) (void)hipHostFree(c->hostio);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
   return GNK_OK;

@@ -600,6 +600,35 @@ __global__ void k_xupdate(const DomDev* __restrict__ doms, const ColDev* __restr
   x[C.off + i] = v;
 }
 
+// copies of small device results into host-mapped memory (read by the host
+// after a stream synchronisation)
+__global__ void k_publish_ints(const int* __restrict__ src, int n, int* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// cycle start: dst[0] = iterating columns, dst[1 + c] = converged flags,
+// rel[c] = true relative residual
+__global__ void k_publish_cycle(GmresState st, int ncol, int* __restrict__ dst, double* __restrict__ rel) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) dst[0] = *st.live;
+  if (i < ncol) {
+    dst[1 + i] = st.converged[i];
+    rel[i] = st.true_relres[i];
+  }
+}
+
+// end of a solve: converged and inner iterations (ints), residual estimate and
+// true relative residual (doubles), each ncol long
+__global__ void k_publish_info(GmresState st, int ncol, int* __restrict__ di, double* __restrict__ dd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncol) return;
+  di[i] = st.converged[i];
+  di[ncol + i] = st.inner_it[i];
+  dd[i] = st.relres[i];
+  dd[ncol + i] = st.true_relres[i];
+}
+
 // inner_it counters etc. to zero
 __global__ void k_gmres_init(int ncol, GmresState st) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;

@@ -76,16 +76,22 @@ def test_mixed_products_matrix_cores(gk, ctx, small_close, nrhs):
     assert np.max(np.abs(y32 - ref)) / np.max(np.abs(ref)) < 1e-6
 
 
-def test_batched_mixed_matrix_cores_matches_oracle(gk, ctx):
+@pytest.mark.parametrize("restart,inner_tol", [(50, 0.0), (10, 1.0)])
+def test_batched_mixed_matrix_cores_matches_oracle(gk, ctx, restart, inner_tol):
     """Batched mixed solve of domains with 8-13 right-hand sides (matrix-core far
-    tiles) against the dense oracle, 1e-10 relative L-infinity."""
+    tiles) against the dense oracle, 1e-10 relative L-infinity: relaxed
+    switching (inner_tol default) and outer refinement (every product mixed,
+    FP64 residual at each restart of 10)."""
     batch = [wl.batch_domain(d, m1_range=(8, 13), ns=(128, 256)) for d in range(3)]
     doms = [gk.DeviceDomain.from_host(d) for d, _ in batch]
     gams = [_cuda(g) for _, g in batch]
-    print(f"[mixed] batched sizes {[(d.m1, d.n) for d, _ in batch]}", flush=True)
-    mus, hs, infos, st = ctx.fbie_batched(doms, gams, tol=1e-13, prec=gk.MIXED, restart=50)
+    print(f"[mixed] batched sizes {[(d.m1, d.n) for d, _ in batch]} restart {restart}", flush=True)
+    mus, hs, infos, st = ctx.fbie_batched(doms, gams, tol=1e-13, prec=gk.MIXED, restart=restart,
+                                          inner_tol=inner_tol)
     assert st == 0
     assert max(i["mixed_steps"] for inf in infos for i in inf) >= 1
+    if inner_tol >= 1.0:   # every Arnoldi step mixed
+        assert all(i["mixed_steps"] == i["inner_it"] for inf in infos for i in inf)
     worst = 0.0
     for (dom, gam), mu, h in zip(batch, mus, hs):
         mu_o, h_o = orc.fbie(dom.eta, dom.etap, dom.A, gam, dom.n)
