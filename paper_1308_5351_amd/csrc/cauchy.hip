@@ -236,14 +236,14 @@ constexpr int stage_stride() { return NR + 1; }   // float2 per staged source
 template <int NR, int TPT, bool FULL>
 __device__ __forceinline__ void far_ksteps(f32x4 (&accR)[4 * TPT], f32x4 (&accI)[4 * TPT],
                                            const float (&ux)[4 * TPT], const float (&uy)[4 * TPT],
-                                           const float2* stg, int len) {
+                                           const float2* stg, int len, int width) {
   constexpr int G = 4 * TPT;
   constexpr int SW = stage_stride<NR>();
   const int lane = threadIdx.x & 63;
   const int k = lane >> 4, n = lane & 15;
   const bool im_col = (n & 1) != 0;
   const int c = n >> 1;
-  const bool cvalid = c < NR;
+  const bool cvalid = c < width;
   const int cc = cvalid ? c : 0;
   auto kstep = [&](int p) {     // sources 4p .. 4p + 3 of the tile
     const int jl = 4 * p + k;
@@ -253,7 +253,7 @@ __device__ __forceinline__ void far_ksteps(f32x4 (&accR)[4 * TPT], f32x4 (&accI)
     const float2 w = stg[js * SW + 1 + cc];
     float b1 = im_col ? w.y : w.x;    // with A = Re Q
     float b2 = im_col ? w.x : -w.y;   // with A = Im Q
-    if (!FULL || NR < 8) {
+    if (!FULL || width < 8) {
       b1 = (ok && cvalid) ? b1 : 0.f;
       b2 = (ok && cvalid) ? b2 : 0.f;
     }
@@ -281,7 +281,7 @@ __device__ __forceinline__ void far_ksteps(f32x4 (&accR)[4 * TPT], f32x4 (&accI)
 template <int NR, int TPT>
 __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg)[TPT], double cx, double cy,
                                               gptr<const float2> rec32, int stride, int wo, int ts, int te,
-                                              float2* stg) {
+                                              float2* stg, int width) {
   constexpr int G = 4 * TPT;
   constexpr int SW = stage_stride<NR>();
   const int lane = threadIdx.x & 63;
@@ -291,7 +291,11 @@ __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg
     gptr<const float2> r = rec32 + (size_t)(ts + lane) * stride;
     stg[lane * SW] = r[0];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) stg[lane * SW + 1 + q] = r[wo + q];
+    for (int q = 0; q < NR; ++q) {
+      float2 v = make_float2(0.f, 0.f);
+      if (q < width) v = r[wo + q];
+      stg[lane * SW + 1 + q] = v;
+    }
   }
   // targets of group g in the A layout: lane n + 16 * (g % 4) of slot g / 4
   float ux[G], uy[G];
@@ -313,8 +317,8 @@ __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (len == 64) far_ksteps<NR, TPT, true>(accR, accI, ux, uy, stg, len);
-  else far_ksteps<NR, TPT, false>(accR, accI, ux, uy, stg, len);
+  if (len == 64) far_ksteps<NR, TPT, true>(accR, accI, ux, uy, stg, len, width);
+  else far_ksteps<NR, TPT, false>(accR, accI, ux, uy, stg, len, width);
   // the next tile's staging overwrites stg
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -346,8 +350,8 @@ enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2 };
 template <int NR, int TPT, int MODE>
 __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
                                           gptr<const double4> tb, gptr<double2> part, int N, int stride, int stride32,
-                                          int wcols, int col0, int base, int tile_idx, int g, int jb0, int jb1,
-                                          int wchunk, double far2, double (&red)[3][TPT][2][64]) {
+                                          int wcols, int col0, int width, int base, int tile_idx, int g, int jb0,
+                                          int jb1, int wchunk, double far2, double (&red)[3][TPT][2][64]) {
   constexpr int kTile = 64 * TPT;
   const int wo = 2 + col0;            // FP64 record: weights of the item's first column
   const int wb = 2 + wcols + col0;    // FP64 record: its b = w conj(eta')
@@ -513,7 +517,7 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
           x += red[q][t][0][lane];
           y += red[q][t][1][lane];
         }
-        if (ti[t] < N) {
+        if (ti[t] < N && r < width) {
           const size_t o = ((size_t)g * wcols + col0 + r) * N + ti[t];
           if constexpr (MODE == M_NEAR) {
             const double2 p = part[o];
@@ -543,12 +547,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
   const int4 w = items[it];
   const DomDev& D = doms[w.x];
   const int wcols = lead + data * D.ncols;
+  // first column, and the group's width (an 8-column group padded from fewer
+  // columns carries its width in bits 20 and up)
+  const int col0 = w.w & 0xFFFFF;
+  const int width = (w.w >> 20) ? (w.w >> 20) : NR;
   if (active != nullptr) {
     bool any = false;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      const int col = w.w + q - lead;
-      any = any || col < 0 || active[D.c0 + col] != 0;
+      const int col = col0 + q - lead;
+      any = any || (q < width && (col < 0 || active[D.c0 + col] != 0));
     }
     if (!any) return;
   }
@@ -559,7 +567,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
   const int wchunk = MIXED ? (chunk >> 2) : (((chunk + 15) >> 4) << 2);
   pair_item<NR, TPT, MODE>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
                             (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, 2 + 2 * wcols, 1 + wcols, wcols,
-                            w.w, w.y * 64 * TPT, w.y, w.z, jb0, jb1, wchunk, D.far2, red);
+                            col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, wchunk, D.far2, red);
 }
 
 // Far tiles of one item (the items of an M_NEAR launch, 4 or 8 columns) on
@@ -572,7 +580,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
 template <int NR, int TPT>
 __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
                                          gptr<const double4> tb, gptr<double2> part, int N, int stride, int stride32,
-                                         int wcols, int col0, int base, int tile_idx, int g, int jb0, int jb1, int wchunk,
+                                         int wcols, int col0, int width, int base, int tile_idx, int g, int jb0,
+                                         int jb1, int wchunk,
                                          double far2, double (*fl)[64][17], float2* stg) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -593,7 +602,7 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
       const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
       const double rr = tbd.z + sbd.z;
       if ((dcx * dcx + dcy * dcy) > far2 * rr * rr)
-        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, rec32, stride32, 1 + col0, ts, te, stg);
+        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, rec32, stride32, 1 + col0, ts, te, stg, width);
     }
     __syncthreads();   // fl shares its LDS with the staging areas
     // group b holds rows i (targets 16b + i) in register i % 4 of lane n + 16 (i / 4), column n
@@ -608,7 +617,7 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
 #pragma unroll
     for (int m = 0; m < (NR + 3) / 4; ++m) {
       const int cc = (threadIdx.x >> 6) + 4 * m;
-      if (cc < NR && ti < N) {
+      if (cc < width && ti < N) {
         double x = 0.0, y = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -636,12 +645,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int4 w = items[it];
   const DomDev& D = doms[w.x];
   const int wcols = lead + data * D.ncols;
+  // first column, and the group's width (an 8-column group padded from fewer
+  // columns carries its width in bits 20 and up)
+  const int col0 = w.w & 0xFFFFF;
+  const int width = (w.w >> 20) ? (w.w >> 20) : NR;
   if (active != nullptr) {
     bool any = false;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      const int col = w.w + q - lead;
-      any = any || col < 0 || active[D.c0 + col] != 0;
+      const int col = col0 + q - lead;
+      any = any || (q < width && (col < 0 || active[D.c0 + col] != 0));
     }
     if (!any) return;
   }
@@ -650,7 +663,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int jb1 = min(D.N, jb0 + chunk);
   far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
                     (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, 2 + 2 * wcols, 1 + wcols, wcols,
-                    w.w, w.y * 64 * TPT, w.y, w.z, jb0, jb1, chunk >> 2, D.far2, fl, stg);
+                    col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, chunk >> 2, D.far2, fl, stg);
 }
 
 // bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of

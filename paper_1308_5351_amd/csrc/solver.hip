@@ -180,9 +180,11 @@ unsigned nblocks(int64_t n, int t = kT) { return (unsigned)((n + t - 1) / t); }
 int64_t slots_of(const gnk_ctx* c) { return (int64_t)c->num_cu * 4 * 8; }   // 4 SIMDs x 8 waves
 
 // ------------------------------------------------------------------ batches
-enum Pattern { P_GM = 0, P_SETUP = 1, P_LEAD = 2 };   // (lead, data) = (0,1), (1,1), (1,0)
-constexpr int kLead[3] = {0, 1, 1};
-constexpr int kData[3] = {1, 1, 0};
+// (lead, data) = (0,1), (1,1), (1,0); P_GM_MIXED: the P_GM columns grouped for
+// mixed products (remainders of 3-7 columns padded to an 8-column group)
+enum Pattern { P_GM = 0, P_SETUP = 1, P_LEAD = 2, P_GM_MIXED = 3 };
+constexpr int kLead[4] = {0, 1, 1, 0};
+constexpr int kData[4] = {1, 1, 0, 1};
 constexpr int kWidths[4] = {8, 4, 2, 1};
 
 struct PairShape {
@@ -205,7 +207,7 @@ struct Batch {
     int cnt[4] = {0, 0, 0, 0};
     double pair_cols = 0, flops = 0, pairs1 = 0;
     bool built = false;
-  } sets[3];
+  } sets[4];
   struct Circ {
     int64_t n;
     int64_t* offs;
@@ -395,9 +397,17 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
           wi = k;
           break;
         }
+      int w = kWidths[wi];
+      int code = r0;
+      if (p == P_GM_MIXED && wcols - r0 >= 3 && wcols - r0 < 8) {
+        // padded 8-column group of the remaining columns (width in bits 20..)
+        wi = 0;
+        w = wcols - r0;
+        code = r0 | (w << 20);
+      }
       for (int t = 0; t < tiles; ++t)
-        for (int g = 0; g < D.splits; ++g) lists[wi].push_back(make_int4(d, t, g, r0));
-      r0 += kWidths[wi];
+        for (int g = 0; g < D.splits; ++g) lists[wi].push_back(make_int4(d, t, g, code));
+      r0 += w;
     }
   }
   for (int k = 0; k < 4; ++k) {
@@ -420,6 +430,7 @@ hipEvent_t pool_event(gnk_ctx* c) {
 
 // All Cauchy sums of a pattern for the batch (one launch per column-group width).
 void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
+  if (mixed && p == P_GM) p = P_GM_MIXED;
   build_items(c, B, p);
   auto& S = B.sets[p];
   if (mixed) HIPCHK(c, launch_records32(B.d_dom, B.ndom, B.maxN, kLead[p], kData[p], c->stream));
@@ -713,6 +724,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   // upload or event record may happen inside it). Profiling times each pair
   // launch with events and so runs the steps without a graph.
   build_items(c, B, P_GM);
+  if (mixed) build_items(c, B, P_GM_MIXED);
   if (op == GNK_OP_GB || op == GNK_OP_GB_T) (void)ws<double>(c, "mean", (size_t)B.ncol * B.maxm1);
   const bool use_graph = c->graphs && !c->prof;
   bool fresh[2] = {false, false};   // cached graph matches this solve's step
