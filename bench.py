@@ -41,8 +41,8 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # factors from a 256 MiB copy of known size; profiles/k_pairs_fp64_N17408_hbm_counters.md).
 # Valid only for the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "d545474a0613ef9c021d9ee4a74a524f1bb9a8de8fd7c8845fa3a58407083939",
-                "bytes_per_launch": 8613414}
+                "sha256": "cade3ea6d6d7d5f599cb44c5fbbc106893fd6553dfa50f2e80cd9c6da329fbd1",
+                "bytes_per_launch": 13098270}
 
 
 def pair_traffic():
@@ -61,7 +61,9 @@ def log(msg):
 def cpu_baseline(dom, budget_s=10.0):
     """Oracle kernel-matrix rows (complex FP64, NumPy) of the same workload."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import nystrom as orc
+    limiter = threadpool_limits(1)     # one core: NumPy's BLAS held to a single thread
     rng = np.random.default_rng(0)
     x = rng.normal(size=dom.N)
     block = 512
@@ -75,6 +77,7 @@ def cpu_baseline(dom, budget_s=10.0):
         pairs += K.shape[0] * dom.N
         rows_done += K.shape[0]
     dt = time.perf_counter() - t0
+    limiter.unregister()
     return {"value": round(pairs / dt / 1e9, 5), "unit": "Gpair/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle kernel rows 0..{rows_done} x {dom.N} sources of the N={dom.N} workload "
                       f"(K_ij assembly + one product), {dt:.1f} s, NumPy single thread"}
