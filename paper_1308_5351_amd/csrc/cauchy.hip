@@ -349,9 +349,10 @@ enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2 };
 // partial-sum stores and stay scalar (wave-uniform) loads.
 template <int NR, int TPT, int MODE>
 __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
-                                          gptr<const double4> tb, gptr<double2> part, int N, int stride, int stride32,
-                                          int wcols, int col0, int width, int base, int tile_idx, int g, int jb0,
-                                          int jb1, int wchunk, double far2, double (&red)[3][TPT][2][64]) {
+                                          gptr<const double4> sbf, gptr<const double4> tb, gptr<double2> part, int N,
+                                          int stride, int stride32, int wcols, int col0, int width, int base,
+                                          int tile_idx, int g, int jb0, int jb1, int wchunk, double far2,
+                                          double (&red)[3][TPT][2][64]) {
   constexpr int kTile = 64 * TPT;
   const int wo = 2 + col0;            // FP64 record: weights of the item's first column
   const int wb = 2 + wcols + col0;    // FP64 record: its b = w conj(eta')
@@ -403,12 +404,13 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 
   bool any_near = false;
   if constexpr (!MIXED && NR == 1) {
-    // 64-node source tiles (segments of them at the range ends): far ones by
-    // the A/B form on coordinates relative to the tile centre, the rest as above
+    // source tiles of kFarTile nodes (segments of them at the range ends): far
+    // ones by the A/B form on coordinates relative to the tile centre, the
+    // rest as above
     const double4 tbd = tb[tile_idx];
     for (int ts = j0; ts < j1;) {
-      const int te = min(((ts >> 6) + 1) << 6, j1);
-      const double4 sbd = sb[ts >> 6];
+      const int te = min(((ts >> kFarTileLog2) + 1) << kFarTileLog2, j1);
+      const double4 sbd = sbf[ts >> kFarTileLog2];
       const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
       const double rr = tbd.z + sbd.z;
       if ((dcx * dcx + dcy * dcy) > far2 * rr * rr) {
@@ -566,8 +568,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
   // quarter of the chunk per wave: multiple of 4 (FP64) or whole 64-node tiles (mixed)
   const int wchunk = MIXED ? (chunk >> 2) : (((chunk + 15) >> 4) << 2);
   pair_item<NR, TPT, MODE>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
-                            (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, 2 + 2 * wcols, 1 + wcols, wcols,
-                            col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, wchunk, D.far2, red);
+                            (gptr<const double4>)D.sbf, (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N,
+                            2 + 2 * wcols, 1 + wcols, wcols, col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, wchunk,
+                            D.far2, red);
 }
 
 // Far tiles of one item (the items of an M_NEAR launch, 4 or 8 columns) on
@@ -668,7 +671,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
 // bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of
 // `tile` consecutive nodes; one wavefront per (tile, domain)
-__global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ doms, int tile, int target) {
+__global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ doms, int tile, int which) {
   const DomDev& D = doms[blockIdx.y];
   const int b = blockIdx.x, lane = threadIdx.x;
   const int i0 = b * tile;
@@ -696,11 +699,12 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ d
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
   // widen by a relative margin so rounding of the centre cannot hide a node
-  if (lane == 0) (target ? D.tb : D.sb)[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
+  double4* out = which == 1 ? D.tb : (which == 2 ? D.sbf : D.sb);
+  if (lane == 0) out[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
 }
 
-// FP32 records {v_j = eta_j - c_tile(j), w_j,q..} (stride 1 + wcols) from the
-// FP64 records {eta, eta', w.., b..} (stride 2 + 2 wcols)
+// FP32 records {v_j = eta_j - c_tile(j) (64-node tile), w_j,q..} (stride 1 + wcols)
+// from the FP64 records {eta, eta', w.., b..} (stride 2 + 2 wcols)
 __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data) {
   const DomDev& D = doms[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -708,7 +712,8 @@ __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data)
   const int wcols = lead + data * D.ncols;
   const double2* r = D.rec + (size_t)j * (2 + 2 * wcols);
   float2* o = D.rec32 + (size_t)j * (1 + wcols);
-  o[0] = make_float2((float)r[1].x, (float)r[1].y);
+  const double4 c = D.sb[j >> 6];
+  o[0] = make_float2((float)(r[0].x - c.x), (float)(r[0].y - c.y));
   for (int q = 0; q < wcols; ++q) o[1 + q] = make_float2((float)r[2 + q].x, (float)r[2 + q].y);
 }
 
@@ -795,9 +800,9 @@ hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int w
   return hipGetLastError();
 }
 
-hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, bool target, hipStream_t st) {
+hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, int which, hipStream_t st) {
   dim3 grid((unsigned)((maxN + tile - 1) / tile), (unsigned)ndom);
-  k_tile_bounds<<<grid, 64, 0, st>>>(doms, tile, target ? 1 : 0);
+  k_tile_bounds<<<grid, 64, 0, st>>>(doms, tile, which);
   return hipGetLastError();
 }
 

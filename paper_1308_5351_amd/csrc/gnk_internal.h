@@ -16,6 +16,14 @@
 
 namespace gnk {
 
+// Source tiles of the FP64 single-column far form: records hold eta and b
+// relative to the centre of the node's tile of this size.
+#ifndef GNK_FAR_TILE_LOG2
+#define GNK_FAR_TILE_LOG2 8
+#endif
+constexpr int kFarTileLog2 = GNK_FAR_TILE_LOG2;
+constexpr int kFarTile = 1 << kFarTileLog2;
+
 struct DomDev {
   // boundary data (caller-owned)
   const double2* eta;
@@ -33,6 +41,7 @@ struct DomDev {
   float2* rec32;     // FP32 records (tile-local eta offsets, weights)
   double2* parts;    // partial sums [splits][wcols][N]
   double4* sb;       // bounds of the 64-node source tiles {cx, cy, r, 0}
+  double4* sbf;      // bounds of the FP64 far-form source tiles (kFarTile nodes)
   double4* tb;       // bounds of the 64*tpt-node target tiles
   double far2;       // mixed precision: far when |c_t - c_s|^2 > far2 (r_t + r_s)^2
   int N, n, m1;
@@ -64,7 +73,8 @@ int pairs_blocks_per_cu(int width, int tpt, bool mixed);
 
 // bounding circles of the tiles of `tile` nodes of every domain (source tiles
 // of 64 nodes into sb, target tiles into tb)
-hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, bool target, hipStream_t st);
+// which: 0 source tiles (sb), 1 target tiles (tb), 2 far-form source tiles (sbf)
+hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, int which, hipStream_t st);
 // FP32 records from the FP64 records of every domain
 hipError_t launch_records32(const DomDev* doms, int ndom, int maxN, int lead, int data, hipStream_t st);
 

@@ -286,7 +286,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   B.adjoint = adjoint;
   B.shape = shape;
   const int align = mixed ? 256 : 16;
-  int64_t Ntot = 0, rec_total = 0, rec32_total = 0, part_total = 0, sb_total = 0, tb_total = 0;
+  int64_t Ntot = 0, rec_total = 0, rec32_total = 0, part_total = 0, sb_total = 0, tb_total = 0, sbf_total = 0;
   B.dom.resize(ndom);
   int c0 = 0;
   for (int d = 0; d < ndom; ++d) {
@@ -328,6 +328,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     part_total += (int64_t)D.splits * (D.ncols + 1) * D.N;
     sb_total += (D.N + 63) / 64;
     tb_total += (D.N + 63) / 64;
+    sbf_total += (D.N + kFarTile - 1) / kFarTile;
   }
   B.ncol = c0;
   double2* rho = ws<double2>(c, "b_rho", Ntot);
@@ -340,9 +341,10 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   // tile bounds: far-tile classification (both precisions) and tile-relative records
   double4* sb = ws<double4>(c, "b_sb", sb_total);
   double4* tb = ws<double4>(c, "b_tb", tb_total);
+  double4* sbf = ws<double4>(c, "b_sbf", sbf_total);
   double theta = 1.0;
   if (const char* e = getenv("GNK_MIXED_THETA")) theta = atof(e);
-  int64_t on = 0, orc = 0, orc32 = 0, op = 0, osb = 0, otb = 0;
+  int64_t on = 0, orc = 0, orc32 = 0, op = 0, osb = 0, otb = 0, osbf = 0;
   for (int d = 0; d < ndom; ++d) {
     DomDev& D = B.dom[d];
     D.rho = rho + on;
@@ -354,6 +356,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     D.parts = parts + op;
     D.sb = sb ? sb + osb : nullptr;
     D.tb = tb ? tb + otb : nullptr;
+    D.sbf = sbf + osbf;
     D.far2 = (1.0 + theta) * (1.0 + theta);
     on += D.N;
     orc += (int64_t)D.N * (2 * D.ncols + 4);
@@ -361,12 +364,14 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     op += (int64_t)D.splits * (D.ncols + 1) * D.N;
     osb += (D.N + 63) / 64;
     otb += (D.N + 63) / 64;
+    osbf += (D.N + kFarTile - 1) / kFarTile;
     for (int r = 0; r < D.ncols; ++r) B.col.push_back(ColDev{d, r, col_off[d] + (int64_t)r * D.N});
   }
   B.d_dom = upload(c, "b_dom", B.dom);
   B.d_col = upload(c, "b_col", B.col);
-  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64, false, c->stream));
-  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64 * B.shape.tpt, true, c->stream));
+  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64, 0, c->stream));
+  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64 * B.shape.tpt, 1, c->stream));
+  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, kFarTile, 2, c->stream));
 }
 
 // Work items of a pattern: every domain (largest first), column group, target

@@ -48,10 +48,10 @@ enum DSel : int { D_NONE = 0, D_B = 1, D_D = 2, D_E = 3 };
 __device__ __forceinline__ double2 coef(const DomDev& D, int sel, int i) {
   return sel == C_RHO ? D.rho[i] : (sel == C_A ? D.A[i] : D.etap[i]);
 }
-// eta_j relative to the centre of its 64-node tile (the pair kernels' far form)
+// eta_j relative to the centre of its far-form tile (the pair kernels' far form)
 __device__ __forceinline__ double2 eta_rel(const DomDev& D, int j) {
   const double2 e = D.eta[j];
-  const double4 c = D.sb[j >> 6];
+  const double4 c = D.sbf[j >> kFarTileLog2];
   return make_double2(e.x - c.x, e.y - c.y);
 }
 // a * conj(b)
@@ -139,7 +139,7 @@ __global__ void k_evec(const DomDev* __restrict__ doms) {
 
 // ----------------------------------------------- source records and means
 // FP64 records rec_d[j*stride], stride = 2 + 2 wcols (wcols = lead + ncols):
-//   [0] eta_j, [1] eta'_j = eta_j - c (c the centre of j's 64-node tile),
+//   [0] eta_j, [1] eta'_j = eta_j - c (c the centre of j's far-form tile of kFarTile nodes),
 //   [2 + q] w_q, [2 + wcols + q] b_q = w_q conj(eta'_j),
 // with weight column q = 0 the leading coefficient C_j when lead, and
 // q = lead + r the value C_j * v_j of the domain's column r, where
