@@ -41,8 +41,8 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # factors from a 256 MiB copy of known size; profiles/k_pairs_fp64_N17408_hbm_counters.md).
 # Valid only for the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "cade3ea6d6d7d5f599cb44c5fbbc106893fd6553dfa50f2e80cd9c6da329fbd1",
-                "bytes_per_launch": 13098270}
+                "sha256": "dbaa957a2b1e00a55fe899cdd126806001fcfc8a443ce8700333449f9f351c8e",
+                "bytes_per_launch": 13010211}
 
 
 def pair_traffic():
