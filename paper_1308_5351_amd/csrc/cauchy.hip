@@ -108,8 +108,11 @@ __device__ __forceinline__ void quad_step(Acc<NR, TPT>& acc, const double2 (&tg)
 // eta'_j = eta_j - c (c the source tile's centre) and m = 1/|z' - eta'_j|^2,
 //   S_i = sum_j w_j conj(z' - eta'_j) m = conj(z') sum_j w_j m - sum_j b_j m,
 // b_j = w_j conj(eta'_j) taken from the record: per pair two FMAs per part
-// and no product for q. The tile pair is far, so |eta'_j| <= r_s < |z' - eta'_j|
-// and the two sums do not cancel.
+// and no product for q. The squared distance comes from the record's
+// u_j = -2 eta'_j and a_j = |eta'_j|^2 and the target's |z'|^2 as
+// a_j + |z'|^2 + u_j . z' (one add, two FMAs). The tile pair is far, so
+// |z'| > 2 |eta'_j|: the sums do not cancel, and |z' - eta'_j|^2 is at least a
+// fifth of a_j + |z'|^2, so the distance keeps all but a few bits.
 template <int NR, int TPT>
 struct AccAB {
   double ax[TPT][NR], ay[TPT][NR], bx[TPT][NR], by[TPT][NR];
@@ -127,16 +130,41 @@ __device__ __forceinline__ void accumulate_ab(AccAB<NR, TPT>& a, int t, P r, int
   }
 }
 
+// |z' - eta'_j|^2 from the record head (u_j at [1], a_j at [2].x) and the
+// target (z', |z'|^2)
+template <class P>
+__device__ __forceinline__ double far_dist2(P r, double zx, double zy, double zz) {
+  const double2 u = r[1];
+  return __builtin_fma(u.x, zx, __builtin_fma(u.y, zy, r[2].x + zz));
+}
+
+// four sources per reciprocal (as in quad_step)
 template <int NR, int TPT, class P>
-__device__ __forceinline__ void pair_step_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT], const double (&zy)[TPT],
-                                              P ra, P rb, int wo, int wb) {
-  const double2 ea = ra[1], eb = rb[1];
+__device__ __forceinline__ void quad_step_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT], const double (&zy)[TPT],
+                                              const double (&zz)[TPT], P ra, P rb, P rc, P rd, int wo, int wb) {
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
-    const double dxa = zx[t] - ea.x, dya = zy[t] - ea.y;
-    const double dxb = zx[t] - eb.x, dyb = zy[t] - eb.y;
-    const double da = __builtin_fma(dya, dya, dxa * dxa);
-    const double db = __builtin_fma(dyb, dyb, dxb * dxb);
+    const double da = far_dist2(ra, zx[t], zy[t], zz[t]);
+    const double db = far_dist2(rb, zx[t], zy[t], zz[t]);
+    const double dc = far_dist2(rc, zx[t], zy[t], zz[t]);
+    const double dd = far_dist2(rd, zx[t], zy[t], zz[t]);
+    const double ab = da * db, cd = dc * dd;
+    const double R = refine_rcp(ab * cd);
+    const double Rab = R * cd, Rcd = R * ab;
+    accumulate_ab<NR, TPT>(acc, t, ra, wo, wb, db * Rab);
+    accumulate_ab<NR, TPT>(acc, t, rb, wo, wb, da * Rab);
+    accumulate_ab<NR, TPT>(acc, t, rc, wo, wb, dd * Rcd);
+    accumulate_ab<NR, TPT>(acc, t, rd, wo, wb, dc * Rcd);
+  }
+}
+
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void pair_step_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT], const double (&zy)[TPT],
+                                              const double (&zz)[TPT], P ra, P rb, int wo, int wb) {
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const double da = far_dist2(ra, zx[t], zy[t], zz[t]);
+    const double db = far_dist2(rb, zx[t], zy[t], zz[t]);
     const double R = refine_rcp(da * db);
     accumulate_ab<NR, TPT>(acc, t, ra, wo, wb, db * R);
     accumulate_ab<NR, TPT>(acc, t, rb, wo, wb, da * R);
@@ -145,13 +173,11 @@ __device__ __forceinline__ void pair_step_far(AccAB<NR, TPT>& acc, const double 
 
 template <int NR, int TPT, class P>
 __device__ __forceinline__ void single_step_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT],
-                                                const double (&zy)[TPT], P r, int wo, int wb) {
-  const double2 e = r[1];
+                                                const double (&zy)[TPT], const double (&zz)[TPT], P r, int wo,
+                                                int wb) {
 #pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    const double dx = zx[t] - e.x, dy = zy[t] - e.y;
-    accumulate_ab<NR, TPT>(acc, t, r, wo, wb, refine_rcp(__builtin_fma(dy, dy, dx * dx)));
-  }
+  for (int t = 0; t < TPT; ++t)
+    accumulate_ab<NR, TPT>(acc, t, r, wo, wb, refine_rcp(far_dist2(r, zx[t], zy[t], zz[t])));
 }
 
 template <int NR, int TPT, class P>
@@ -354,8 +380,8 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
                                           int tile_idx, int g, int jb0, int jb1, int wchunk, double far2,
                                           double (&red)[3][TPT][2][64]) {
   constexpr int kTile = 64 * TPT;
-  const int wo = 2 + col0;            // FP64 record: weights of the item's first column
-  const int wb = 2 + wcols + col0;    // FP64 record: its b = w conj(eta')
+  const int wo = kRecHead + col0;            // FP64 record: weights of the item's first column
+  const int wb = kRecHead + wcols + col0;    // FP64 record: its b = w conj(eta')
   const int wo32 = 1 + col0;          // FP32 record: weights
   constexpr bool MIXED = MODE != M_FP64;
   const int lane = threadIdx.x & 63;
@@ -414,23 +440,28 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
       const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
       const double rr = tbd.z + sbd.z;
       if ((dcx * dcx + dcy * dcy) > far2 * rr * rr) {
-        double zx[TPT], zy[TPT];
+        double zx[TPT], zy[TPT], zz[TPT];
         AccAB<NR, TPT> ab;
 #pragma unroll
         for (int t = 0; t < TPT; ++t) {
           zx[t] = tg[t].x - sbd.x;
           zy[t] = tg[t].y - sbd.y;
+          zz[t] = __builtin_fma(zy[t], zy[t], zx[t] * zx[t]);
 #pragma unroll
           for (int r = 0; r < NR; ++r) ab.ax[t][r] = ab.ay[t][r] = ab.bx[t][r] = ab.by[t][r] = 0.0;
         }
         int j = ts;
-        // two sources per reciprocal: four records with three fields each would
-        // not fit in scalar registers beside the loop state
+#if GNK_FAR_QUAD
+        for (; j + 3 < te; j += 4) {
+          gptr<const double2> r = rec + (size_t)j * stride;
+          quad_step_far<NR, TPT>(ab, zx, zy, zz, r, r + stride, r + 2 * stride, r + 3 * stride, wo, wb);
+        }
+#endif
         for (; j + 1 < te; j += 2) {
           gptr<const double2> r = rec + (size_t)j * stride;
-          pair_step_far<NR, TPT>(ab, zx, zy, r, r + stride, wo, wb);
+          pair_step_far<NR, TPT>(ab, zx, zy, zz, r, r + stride, wo, wb);
         }
-        for (; j < te; ++j) single_step_far<NR, TPT>(ab, zx, zy, rec + (size_t)j * stride, wo, wb);
+        for (; j < te; ++j) single_step_far<NR, TPT>(ab, zx, zy, zz, rec + (size_t)j * stride, wo, wb);
 #pragma unroll
         for (int t = 0; t < TPT; ++t)
 #pragma unroll
@@ -569,7 +600,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
   const int wchunk = MIXED ? (chunk >> 2) : (((chunk + 15) >> 4) << 2);
   pair_item<NR, TPT, MODE>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
                             (gptr<const double4>)D.sbf, (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N,
-                            2 + 2 * wcols, 1 + wcols, wcols, col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, wchunk,
+                            rec_stride(wcols), 1 + wcols, wcols, col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, wchunk,
                             D.far2, red);
 }
 
@@ -665,7 +696,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int jb0 = w.z * chunk;
   const int jb1 = min(D.N, jb0 + chunk);
   far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
-                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, 2 + 2 * wcols, 1 + wcols, wcols,
+                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), 1 + wcols, wcols,
                     col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, chunk >> 2, D.far2, fl, stg);
 }
 
@@ -704,17 +735,17 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ d
 }
 
 // FP32 records {v_j = eta_j - c_tile(j) (64-node tile), w_j,q..} (stride 1 + wcols)
-// from the FP64 records {eta, eta', w.., b..} (stride 2 + 2 wcols)
+// from the FP64 records (head, w.., b..)
 __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data) {
   const DomDev& D = doms[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= D.N) return;
   const int wcols = lead + data * D.ncols;
-  const double2* r = D.rec + (size_t)j * (2 + 2 * wcols);
+  const double2* r = D.rec + (size_t)j * rec_stride(wcols);
   float2* o = D.rec32 + (size_t)j * (1 + wcols);
   const double4 c = D.sb[j >> 6];
   o[0] = make_float2((float)(r[0].x - c.x), (float)(r[0].y - c.y));
-  for (int q = 0; q < wcols; ++q) o[1 + q] = make_float2((float)r[2 + q].x, (float)r[2 + q].y);
+  for (int q = 0; q < wcols; ++q) o[1 + q] = make_float2((float)r[kRecHead + q].x, (float)r[kRecHead + q].y);
 }
 
 template <int NR, int TPT, int MODE>

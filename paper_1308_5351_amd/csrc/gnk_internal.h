@@ -24,6 +24,12 @@ namespace gnk {
 constexpr int kFarTileLog2 = GNK_FAR_TILE_LOG2;
 constexpr int kFarTile = 1 << kFarTileLog2;
 
+// FP64 source records (double2 fields): a head {eta, u = -2 eta', (|eta'|^2, 0)}
+// (eta' = eta - centre of the node's far-form tile), then wcols weights w_q,
+// then wcols products b_q = w_q conj(eta')
+constexpr int kRecHead = 3;
+__host__ __device__ constexpr int rec_stride(int wcols) { return kRecHead + 2 * wcols; }
+
 struct DomDev {
   // boundary data (caller-owned)
   const double2* eta;

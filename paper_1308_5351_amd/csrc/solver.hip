@@ -323,7 +323,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     B.maxN = std::max(B.maxN, D.N);
     B.maxm1 = std::max(B.maxm1, D.m1);
     Ntot += D.N;
-    rec_total += (int64_t)D.N * (2 * D.ncols + 4);   // {eta, eta', w.., b..} with a lead column
+    rec_total += (int64_t)D.N * rec_stride(D.ncols + 1);   // head, w.., b.. with a lead column
     rec32_total += (int64_t)D.N * (D.ncols + 2);
     part_total += (int64_t)D.splits * (D.ncols + 1) * D.N;
     sb_total += (D.N + 63) / 64;
@@ -359,7 +359,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     D.sbf = sbf + osbf;
     D.far2 = (1.0 + theta) * (1.0 + theta);
     on += D.N;
-    orc += (int64_t)D.N * (2 * D.ncols + 4);
+    orc += (int64_t)D.N * rec_stride(D.ncols + 1);
     orc32 += (int64_t)D.N * (D.ncols + 2);
     op += (int64_t)D.splits * (D.ncols + 1) * D.N;
     osb += (D.N + 63) / 64;

@@ -54,6 +54,12 @@ __device__ __forceinline__ double2 eta_rel(const DomDev& D, int j) {
   const double4 c = D.sbf[j >> kFarTileLog2];
   return make_double2(e.x - c.x, e.y - c.y);
 }
+// record head {eta, u = -2 eta', (|eta'|^2, 0)}
+__device__ __forceinline__ void record_head(double2* rj, double2 eta, double2 ep) {
+  rj[0] = eta;
+  rj[1] = make_double2(-2.0 * ep.x, -2.0 * ep.y);
+  rj[2] = make_double2(__builtin_fma(ep.y, ep.y, ep.x * ep.x), 0.0);
+}
 // a * conj(b)
 __device__ __forceinline__ double2 cmul_conj(double2 a, double2 b) {
   return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
@@ -138,9 +144,10 @@ __global__ void k_evec(const DomDev* __restrict__ doms) {
 }
 
 // ----------------------------------------------- source records and means
-// FP64 records rec_d[j*stride], stride = 2 + 2 wcols (wcols = lead + ncols):
-//   [0] eta_j, [1] eta'_j = eta_j - c (c the centre of j's far-form tile of kFarTile nodes),
-//   [2 + q] w_q, [2 + wcols + q] b_q = w_q conj(eta'_j),
+// FP64 records rec_d[j*stride], stride = 3 + 2 wcols (wcols = lead + ncols):
+//   [0] eta_j, [1] u_j = -2 eta'_j, [2] (|eta'_j|^2, 0), with eta'_j = eta_j - c
+//   (c the centre of j's far-form tile of kFarTile nodes),
+//   [3 + q] w_q, [3 + wcols + q] b_q = w_q conj(eta'_j),
 // with weight column q = 0 the leading coefficient C_j when lead, and
 // q = lead + r the value C_j * v_j of the domain's column r, where
 //   v = x * scale[c]                  (optional; written back to xout)
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms,
   if (active && !active[c]) return;
   const double s = scale ? scale[c] : 1.0;
   const int wcols = lead + D.ncols;
-  const int stride = 2 + 2 * wcols;
+  const int stride = rec_stride(wcols);
   const double* xr = x + C.off + (size_t)k * D.n;
   double acc = 0.0;
   for (int p = threadIdx.x; p < D.n; p += blockDim.x) {
@@ -177,14 +184,13 @@ __global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms,
     const double2 ep = eta_rel(D, j);
     double2* rj = D.rec + (size_t)j * stride;
     const double2 w = make_double2(cf.x * v, cf.y * v);
-    rj[2 + lead + C.r] = w;
-    rj[2 + wcols + lead + C.r] = cmul_conj(w, ep);
+    rj[kRecHead + lead + C.r] = w;
+    rj[kRecHead + wcols + lead + C.r] = cmul_conj(w, ep);
     if (C.r == 0) {
-      rj[0] = D.eta[j];
-      rj[1] = ep;
+      record_head(rj, D.eta[j], ep);
       if (lead) {
-        rj[2] = cf;
-        rj[2 + wcols] = cmul_conj(cf, ep);
+        rj[kRecHead] = cf;
+        rj[kRecHead + wcols] = cmul_conj(cf, ep);
       }
     }
     acc += v;
@@ -195,18 +201,17 @@ __global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms,
   }
 }
 
-// records holding only the leading column (stride 4): eta, eta', C_j, C_j conj(eta')
+// records holding only the leading column (wcols = 1): head, C_j, C_j conj(eta')
 __global__ void k_lead_records(const DomDev* __restrict__ doms, int csel) {
   const DomDev& D = doms[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= D.N) return;
   const double2 ep = eta_rel(D, j);
   const double2 cf = coef(D, csel, j);
-  double2* rj = D.rec + (size_t)j * 4;
-  rj[0] = D.eta[j];
-  rj[1] = ep;
-  rj[2] = cf;
-  rj[3] = cmul_conj(cf, ep);
+  double2* rj = D.rec + (size_t)j * rec_stride(1);
+  record_head(rj, D.eta[j], ep);
+  rj[kRecHead] = cf;
+  rj[kRecHead + 1] = cmul_conj(cf, ep);
 }
 
 // records of one domain from column-major complex weights w (N x ncols)
@@ -215,13 +220,12 @@ __global__ void k_pack_records(const DomDev* __restrict__ doms, const double2* _
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= D.N) return;
   const double2 ep = eta_rel(D, j);
-  double2* rj = D.rec + (size_t)j * (2 + 2 * ncols);
-  rj[0] = D.eta[j];
-  rj[1] = ep;
+  double2* rj = D.rec + (size_t)j * rec_stride(ncols);
+  record_head(rj, D.eta[j], ep);
   for (int r = 0; r < ncols; ++r) {
     const double2 v = w[(size_t)r * D.N + j];
-    rj[2 + r] = v;
-    rj[2 + ncols + r] = cmul_conj(v, ep);
+    rj[kRecHead + r] = v;
+    rj[kRecHead + ncols + r] = cmul_conj(v, ep);
   }
 }
 
