@@ -138,26 +138,6 @@ __device__ __forceinline__ double far_dist2(P r, double zx, double zy, double zz
   return __builtin_fma(u.x, zx, __builtin_fma(u.y, zy, r[2].x + zz));
 }
 
-// four sources per reciprocal (as in quad_step)
-template <int NR, int TPT, class P>
-__device__ __forceinline__ void quad_step_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT], const double (&zy)[TPT],
-                                              const double (&zz)[TPT], P ra, P rb, P rc, P rd, int wo, int wb) {
-#pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    const double da = far_dist2(ra, zx[t], zy[t], zz[t]);
-    const double db = far_dist2(rb, zx[t], zy[t], zz[t]);
-    const double dc = far_dist2(rc, zx[t], zy[t], zz[t]);
-    const double dd = far_dist2(rd, zx[t], zy[t], zz[t]);
-    const double ab = da * db, cd = dc * dd;
-    const double R = refine_rcp(ab * cd);
-    const double Rab = R * cd, Rcd = R * ab;
-    accumulate_ab<NR, TPT>(acc, t, ra, wo, wb, db * Rab);
-    accumulate_ab<NR, TPT>(acc, t, rb, wo, wb, da * Rab);
-    accumulate_ab<NR, TPT>(acc, t, rc, wo, wb, dd * Rcd);
-    accumulate_ab<NR, TPT>(acc, t, rd, wo, wb, dc * Rcd);
-  }
-}
-
 template <int NR, int TPT, class P>
 __device__ __forceinline__ void pair_step_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT], const double (&zy)[TPT],
                                               const double (&zz)[TPT], P ra, P rb, int wo, int wb) {
@@ -366,10 +346,10 @@ __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg
 // MFMA accumulators do not share a register file).
 enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2 };
 
-// One work item: the tile of 64*TPT targets starting at `base`, sources
-// [jb0, jb1) of the domain, weight columns col0 .. col0+NR-1. The four
-// wavefronts of the workgroup take consecutive quarters of the sources; their
-// sums are added through LDS in wave order. MIXED: far source tiles of 64
+// One work item: the tile of 64*TPT targets starting at `base`, a range of
+// sources of the domain, weight columns col0 .. col0+NR-1. The four
+// wavefronts of the workgroup take consecutive parts [j0, j1) of the range;
+// their sums are added through LDS in wave order. MIXED: far source tiles of 64
 // nodes are summed in FP32 (see above). All pointers are restrict-qualified
 // parameters, so after inlining the record loads are known not to alias the
 // partial-sum stores and stay scalar (wave-uniform) loads.
@@ -377,7 +357,7 @@ template <int NR, int TPT, int MODE>
 __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
                                           gptr<const double4> sbf, gptr<const double4> tb, gptr<double2> part, int N,
                                           int stride, int stride32, int wcols, int col0, int width, int base,
-                                          int tile_idx, int g, int jb0, int jb1, int wchunk, double far2,
+                                          int tile_idx, int g, int j0, int j1, double far2,
                                           double (&red)[3][TPT][2][64]) {
   constexpr int kTile = 64 * TPT;
   const int wo = kRecHead + col0;            // FP64 record: weights of the item's first column
@@ -386,8 +366,6 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
   constexpr bool MIXED = MODE != M_FP64;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int j0 = min(jb1, jb0 + wv * wchunk);
-  const int j1 = min(jb1, j0 + wchunk);
 
   double2 tg[TPT];
   int ti[TPT];
@@ -451,12 +429,8 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
           for (int r = 0; r < NR; ++r) ab.ax[t][r] = ab.ay[t][r] = ab.bx[t][r] = ab.by[t][r] = 0.0;
         }
         int j = ts;
-#if GNK_FAR_QUAD
-        for (; j + 3 < te; j += 4) {
-          gptr<const double2> r = rec + (size_t)j * stride;
-          quad_step_far<NR, TPT>(ab, zx, zy, zz, r, r + stride, r + 2 * stride, r + 3 * stride, wo, wb);
-        }
-#endif
+        // two sources per reciprocal: four records (u, a, w, b each) would not
+        // fit in the scalar registers of an 8-wave launch
         for (; j + 1 < te; j += 2) {
           gptr<const double2> r = rec + (size_t)j * stride;
           pair_step_far<NR, TPT>(ab, zx, zy, zz, r, r + stride, wo, wb);
@@ -593,14 +567,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
     }
     if (!any) return;
   }
+  // the wave's sources: a quarter of the item's chunk (a multiple of 4 in
+  // FP64, whole 64-node tiles in mixed precision)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int chunk = D.chunk;
   const int jb0 = w.z * chunk;
   const int jb1 = min(D.N, jb0 + chunk);
-  // quarter of the chunk per wave: multiple of 4 (FP64) or whole 64-node tiles (mixed)
   const int wchunk = MIXED ? (chunk >> 2) : (((chunk + 15) >> 4) << 2);
+  const int j0 = min(jb1, jb0 + wv * wchunk);
+  const int j1 = min(jb1, j0 + wchunk);
   pair_item<NR, TPT, MODE>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
                             (gptr<const double4>)D.sbf, (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N,
-                            rec_stride(wcols), 1 + wcols, wcols, col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, wchunk,
+                            rec_stride(wcols), 1 + wcols, wcols, col0, width, w.y * 64 * TPT, w.y, w.z, j0, j1,
                             D.far2, red);
 }
 

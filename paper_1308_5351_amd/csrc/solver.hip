@@ -245,9 +245,16 @@ void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint) {
   }
 }
 
-// Single-domain split plan: the split count whose waves fill whole rounds of
-// the wave slots of the pair-kernel variant best (fewest splits within 1% of
-// the best), at least 32 sources per workgroup, at most 64 splits.
+// Single-domain split plan: among the split counts whose waves fill whole
+// rounds of the wave slots of the pair-kernel variant best (within 1% of the
+// best fill), the fewest that give two rounds, else the most rounds; at least
+// 128 sources per workgroup, at most 64 splits. Workgroups take unequal times
+// (near source tiles cost more than far ones) and a second round lets the
+// dispatcher even that out; more rounds shorten the products a little more
+// but every split adds partial sums that the consumer has to read (measured
+// at N = 17408: 123 us per product at 15 splits, 118 us at 30, 115 us at 45,
+// with the reading growing by about 0.3 us per split).
+int64_t single_max_splits(int64_t N) { return std::max<int64_t>(1, std::min<int64_t>(64, N / 128)); }
 void plan_single(gnk_ctx* c, int64_t N, int align, int width, bool mixed, int* tpt, int* chunk, int* splits) {
   int t = ((N + 127) / 128) * 64 >= slots_of(c) ? 2 : 1;
   if (const char* s = getenv("GNK_CAUCHY_TPT")) t = atoi(s) == 2 ? 2 : 1;
@@ -255,16 +262,19 @@ void plan_single(gnk_ctx* c, int64_t N, int align, int width, bool mixed, int* t
   // how many workgroups fit on a CU)
   const int64_t slots = (int64_t)c->num_cu * 4 * pairs_blocks_per_cu(width, t, mixed);
   const int64_t tiles = (N + 64 * t - 1) / (64 * t);
-  const int64_t max_s = std::max<int64_t>(1, std::min<int64_t>(64, N / 32));
-  std::vector<double> score((size_t)max_s + 1, 0.0);
+  const int64_t max_s = single_max_splits(N);
+  std::vector<double> score((size_t)max_s + 1, 0.0), rounds((size_t)max_s + 1, 0.0);
   double best = 0.0;
   for (int64_t s = 1; s <= max_s; ++s) {
-    const double rounds = (double)(tiles * s * 4) / (double)slots;
-    score[s] = rounds / std::ceil(rounds) * std::min(1.0, rounds);
+    rounds[s] = (double)(tiles * s * 4) / (double)slots;
+    score[s] = rounds[s] / std::ceil(rounds[s]) * std::min(1.0, rounds[s]);
     best = std::max(best, score[s]);
   }
-  int64_t bs = 1;
-  while (bs < max_s && score[bs] < best - 0.01) ++bs;
+  int64_t bs = 0;
+  for (int64_t s = 1; s <= max_s && !bs; ++s)
+    if (score[s] >= best - 0.01 && rounds[s] >= 1.9) bs = s;
+  for (int64_t s = max_s; s >= 1 && !bs; --s)
+    if (score[s] >= best - 0.01) bs = s;
   if (const char* s = getenv("GNK_CAUCHY_SPLITS")) bs = std::max(1, atoi(s));
   int64_t ch = (N + bs - 1) / bs;
   ch = (ch + align - 1) / align * align;
@@ -410,8 +420,18 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
         w = wcols - r0;
         code = r0 | (w << 20);
       }
-      for (int t = 0; t < tiles; ++t)
-        for (int g = 0; g < D.splits; ++g) lists[wi].push_back(make_int4(d, t, g, code));
+      // Records larger than half an XCD's L2 (4 MB): split-major, so the
+      // workgroups resident together read one source range (measured at
+      // N = 133120: 28% shorter products than tile-major). Smaller ones stay
+      // in L2 either way and go tile-major, whose last round is cheaper
+      // (3% at N = 17408).
+      if ((int64_t)D.N * rec_stride(wcols) * (int64_t)sizeof(double2) > (int64_t)2 << 20) {
+        for (int g = 0; g < D.splits; ++g)
+          for (int t = 0; t < tiles; ++t) lists[wi].push_back(make_int4(d, t, g, code));
+      } else {
+        for (int t = 0; t < tiles; ++t)
+          for (int g = 0; g < D.splits; ++g) lists[wi].push_back(make_int4(d, t, g, code));
+      }
       r0 += w;
     }
   }

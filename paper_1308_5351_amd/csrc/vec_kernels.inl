@@ -7,6 +7,7 @@
 // repeated runs are bitwise identical.
 // Included by solver.hip (one translation unit with the host driver).
 #pragma once
+#include "gnk_device.h"
 #include "gnk_vec.h"
 
 namespace gnk {
@@ -102,13 +103,25 @@ __global__ void k_rho(const DomDev* __restrict__ doms) {
   D.rho[i] = make_double2((p.x * a.x + p.y * a.y) / d, (p.y * a.x - p.x * a.y) / d);
 }
 
-// sum over the splits of weight column q (of wcols) of a domain's partial sums
+// sum over the splits of weight column q (of wcols) of a domain's partial
+// sums, added in split order; the loads go out eight at a time
 __device__ __forceinline__ double2 reduce_parts(const DomDev& D, int wcols, int q, int i) {
+  constexpr int kG = 8;
+  const gptr<const double2> p = (gptr<const double2>)D.parts + (size_t)q * D.N + i;
+  const size_t gs = (size_t)wcols * D.N;
+  const int splits = D.splits;
   double2 s = make_double2(0.0, 0.0);
-  for (int g = 0; g < D.splits; ++g) {
-    const double2 v = D.parts[((size_t)g * wcols + q) * D.N + i];
-    s.x += v.x;
-    s.y += v.y;
+  for (int g = 0; g < splits; g += kG) {
+    double2 v[kG];
+#pragma unroll
+    for (int k = 0; k < kG; ++k)
+      if (g + k < splits) v[k] = p[(size_t)(g + k) * gs];
+#pragma unroll
+    for (int k = 0; k < kG; ++k)
+      if (g + k < splits) {
+        s.x += v[k].x;
+        s.y += v[k].y;
+      }
   }
   return s;
 }
