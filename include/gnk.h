@@ -184,6 +184,28 @@ GNK_API gnk_status gnk_profile_read(gnk_ctx* ctx, gnk_prof* out, int reset);
 GNK_API gnk_status gnk_cauchy_sum(gnk_ctx* ctx, int64_t N, const void* eta, const void* w, int nrhs,
                           void* S);
 
+/* Cauchy integral formula at interior points (Sec. 7, eqs. (e:cauchy5) and
+ * (e:cauchy6)): the values f(z_i) at nz points of G of a function analytic in G,
+ * from its values at the N = m1 n boundary nodes, by the subtracted form
+ *   bounded G:    f(z) = P_f / P_1
+ *   unbounded G:  f(z) = (f(inf) - P_f/(n i)) / (1 - P_1/(n i))
+ * with P_f = sum_j f_j eta'_j / (z - eta_j) and P_1 = sum_j eta'_j / (z - eta_j)
+ * summed directly in FP64 over every node (no far-field approximation).
+ *   eta, etap : N complex (device), nodes and derivatives, component-major
+ *   f         : N x nrhs complex (device), boundary values, leading dim N
+ *   z         : nz complex (device), the points (in G; any layout of them)
+ *   finf      : NULL for bounded G; for unbounded G, a HOST array of nrhs
+ *               complex values f(infinity)
+ *   fz        : nz x nrhs complex (device, output, leading dim nz); must not
+ *               alias f, z, eta or etap.
+ * n is the number of nodes per boundary component (the weight 2 pi/n); it need
+ * not be even here. A point equal to a node gets that node's value (the limit
+ * of the ratio); points outside G give the formula's value there (not f).
+ * Errors: GNK_ERR_ARG for sizes outside 1..2^30 (N, nz), nrhs outside 1..4096,
+ * NULL or aliased pointers; nothing is written then. */
+GNK_API gnk_status gnk_fcau(gnk_ctx* ctx, int64_t m1, int64_t n, const void* eta, const void* etap,
+                            const void* f, int nrhs, const void* z, int64_t nz, const void* finf, void* fz);
+
 /* Operator application y = op(x) for one domain (see gnk_op). x and y are
  * real N x nrhs and must not alias. GB and GB_T need etapp, Ap and c.
  * prec: GNK_FP64, or GNK_MIXED (Cauchy sums over well-separated 64-node tiles

@@ -344,7 +344,7 @@ __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg
 // k_far takes the far tiles on the matrix cores. Splitting a mixed product in
 // two keeps each kernel's register footprint small (the FP64 loops and the
 // MFMA accumulators do not share a register file).
-enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2 };
+enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2, M_EXT = 3 };
 
 // One work item: the tile of 64*TPT targets starting at `base`, a range of
 // sources of the domain, weight columns col0 .. col0+NR-1. The four
@@ -356,14 +356,17 @@ enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2 };
 template <int NR, int TPT, int MODE>
 __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
                                           gptr<const double4> sbf, gptr<const double4> tb, gptr<double2> part, int N,
-                                          int stride, int stride32, int wcols, int col0, int width, int base,
-                                          int tile_idx, int g, int j0, int j1, double far2,
-                                          double (&red)[3][TPT][2][64]) {
+                                          gptr<const double2> tz, int Nt, int stride, int stride32, int wcols,
+                                          int col0, int width, int base, int tile_idx, int g, int j0, int j1,
+                                          double far2, double (&red)[3][TPT][2][64]) {
   constexpr int kTile = 64 * TPT;
   const int wo = kRecHead + col0;            // FP64 record: weights of the item's first column
   const int wb = kRecHead + wcols + col0;    // FP64 record: its b = w conj(eta')
   const int wo32 = 1 + col0;          // FP32 record: weights
-  constexpr bool MIXED = MODE != M_FP64;
+  constexpr bool MIXED = MODE == M_MIXED || MODE == M_NEAR;
+  // M_EXT: FP64 with targets tz[0..Nt) that are not nodes (no j != i window)
+  constexpr bool EXT = MODE == M_EXT;
+  const int NT = EXT ? Nt : N;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
@@ -372,7 +375,8 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
     ti[t] = base + t * 64 + lane;
-    tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
+    if constexpr (EXT) tg[t] = tz[min(ti[t], NT - 1)];
+    else tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
   }
   Acc<NR, TPT> acc;
 #pragma unroll
@@ -400,6 +404,10 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
     if (j < jb) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, false);
   };
   auto fp64_range = [&](int ja, int jb) {
+    if constexpr (EXT) {
+      plain(ja, jb);
+      return;
+    }
     plain(ja, min(jb, base));
     const int ma = max(ja, base), mb = min(jb, base + kTile);
     for (int j = ma; j < mb; ++j) single_step<NR, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
@@ -524,8 +532,8 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
           x += red[q][t][0][lane];
           y += red[q][t][1][lane];
         }
-        if (ti[t] < N && r < width) {
-          const size_t o = ((size_t)g * wcols + col0 + r) * N + ti[t];
+        if (ti[t] < NT && r < width) {
+          const size_t o = ((size_t)g * wcols + col0 + r) * NT + ti[t];
           if constexpr (MODE == M_NEAR) {
             const double2 p = part[o];
             x += p.x;
@@ -545,10 +553,10 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 // FP64 variants with one or two columns are held to 64 VGPRs (8 waves per
 // SIMD), which they reach without spilling; the others keep their registers.
 template <int NR, int TPT, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 && MODE == M_FP64) ? 8 : 1))) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 && (MODE == M_FP64 || MODE == M_EXT)) ? 8 : 1))) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
                                                int nitems, int lead, int data, const int* __restrict__ active) {
   __shared__ double red[3][TPT][2][64];
-  constexpr bool MIXED = MODE != M_FP64;
+  constexpr bool MIXED = MODE == M_MIXED || MODE == M_NEAR;
   const int it = blockIdx.x;
   if (it >= nitems) return;
   const int4 w = items[it];
@@ -578,8 +586,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
   const int j1 = min(jb1, j0 + wchunk);
   pair_item<NR, TPT, MODE>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
                             (gptr<const double4>)D.sbf, (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N,
-                            rec_stride(wcols), 1 + wcols, wcols, col0, width, w.y * 64 * TPT, w.y, w.z, j0, j1,
-                            D.far2, red);
+                            (gptr<const double2>)D.tz, D.Nt, rec_stride(wcols), 1 + wcols, wcols, col0, width,
+                            w.y * 64 * TPT, w.y, w.z, j0, j1, D.far2, red);
 }
 
 // Far tiles of one item (the items of an M_NEAR launch, 4 or 8 columns) on
@@ -683,12 +691,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ doms, int tile, int which) {
   const DomDev& D = doms[blockIdx.y];
   const int b = blockIdx.x, lane = threadIdx.x;
+  const double2* pts = which == 3 ? D.tz : D.eta;
+  const int np = which == 3 ? D.Nt : D.N;
   const int i0 = b * tile;
-  if (i0 >= D.N) return;
-  const int i1 = min(D.N, i0 + tile);
+  if (i0 >= np) return;
+  const int i1 = min(np, i0 + tile);
   double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
   for (int i = i0 + lane; i < i1; i += 64) {
-    const double2 e = D.eta[i];
+    const double2 e = pts[i];
     xmin = fmin(xmin, e.x); xmax = fmax(xmax, e.x);
     ymin = fmin(ymin, e.y); ymax = fmax(ymax, e.y);
   }
@@ -702,13 +712,13 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ d
   const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax);
   double r = 0.0;
   for (int i = i0 + lane; i < i1; i += 64) {
-    const double2 e = D.eta[i];
+    const double2 e = pts[i];
     r = fmax(r, sqrt((e.x - cx) * (e.x - cx) + (e.y - cy) * (e.y - cy)));
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
   // widen by a relative margin so rounding of the centre cannot hide a node
-  double4* out = which == 1 ? D.tb : (which == 2 ? D.sbf : D.sb);
+  double4* out = (which == 1 || which == 3) ? D.tb : (which == 2 ? D.sbf : D.sb);
   if (lane == 0) out[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
 }
 
@@ -735,9 +745,11 @@ void launch_k(const DomDev* doms, const int4* items, int nitems, int lead, int d
 // FP64: one launch. Mixed: 1-2 columns in one M_MIXED launch; 4-8 columns as
 // k_far then M_NEAR over the same items (the second adds to the first's sums).
 template <int NR, int TPT>
-void launch_t(const DomDev* doms, const int4* items, int nitems, int lead, int data, bool mixed, const int* active,
-              int grid, hipStream_t st) {
-  if (!mixed) {
+void launch_t(const DomDev* doms, const int4* items, int nitems, int lead, int data, bool mixed, bool ext,
+              const int* active, int grid, hipStream_t st) {
+  if (ext) {
+    launch_k<NR, TPT, M_EXT>(doms, items, nitems, lead, data, active, grid, st);
+  } else if (!mixed) {
     launch_k<NR, TPT, M_FP64>(doms, items, nitems, lead, data, active, grid, st);
   } else if constexpr (NR >= 4) {
     k_far<NR, TPT><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
@@ -748,10 +760,10 @@ void launch_t(const DomDev* doms, const int4* items, int nitems, int lead, int d
 }
 
 template <int NR>
-void launch_w(const DomDev* doms, const int4* items, int nitems, int tpt, int lead, int data, bool mixed,
+void launch_w(const DomDev* doms, const int4* items, int nitems, int tpt, int lead, int data, bool mixed, bool ext,
               const int* active, int grid, hipStream_t st) {
-  if (tpt == 2) launch_t<NR, 2>(doms, items, nitems, lead, data, mixed, active, grid, st);
-  else launch_t<NR, 1>(doms, items, nitems, lead, data, mixed, active, grid, st);
+  if (tpt == 2) launch_t<NR, 2>(doms, items, nitems, lead, data, mixed, ext, active, grid, st);
+  else launch_t<NR, 1>(doms, items, nitems, lead, data, mixed, ext, active, grid, st);
 }
 
 template <int NR, int TPT, int MODE>
@@ -797,14 +809,15 @@ int pairs_blocks_per_cu(int width, int tpt, bool mixed) {
 }
 
 hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
-                        bool mixed, const int* active, hipStream_t st) {
+                        bool mixed, bool ext, const int* active, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
+  if (ext && mixed) return hipErrorInvalidValue;
   const int grid = nitems;
   switch (width) {
-    case 8: launch_w<8>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;
-    case 4: launch_w<4>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;
-    case 2: launch_w<2>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;
-    default: launch_w<1>(doms, items, nitems, tpt, lead, data, mixed, active, grid, st); break;
+    case 8: launch_w<8>(doms, items, nitems, tpt, lead, data, mixed, ext, active, grid, st); break;
+    case 4: launch_w<4>(doms, items, nitems, tpt, lead, data, mixed, ext, active, grid, st); break;
+    case 2: launch_w<2>(doms, items, nitems, tpt, lead, data, mixed, ext, active, grid, st); break;
+    default: launch_w<1>(doms, items, nitems, tpt, lead, data, mixed, ext, active, grid, st); break;
   }
   return hipGetLastError();
 }

@@ -49,6 +49,9 @@ struct DomDev {
   double4* sb;       // bounds of the 64-node source tiles {cx, cy, r, 0}
   double4* sbf;      // bounds of the FP64 far-form source tiles (kFarTile nodes)
   double4* tb;       // bounds of the 64*tpt-node target tiles
+  const double2* tz; // targets other than the nodes (Cauchy integral at interior
+                     // points), or null: the targets are the nodes themselves
+  int Nt;            // number of those targets
   double far2;       // mixed precision: far when |c_t - c_s|^2 > far2 (r_t + r_s)^2
   int N, n, m1;
   int ncols;         // real columns of the domain
@@ -72,14 +75,16 @@ struct ColDev {
 // item (8, 4, 2 or 1), one workgroup per item. mixed: FP32 for far 64-node
 // source tiles (rec32, sb, tb). active: optional per global column mask; an
 // item whose data columns are all inactive is skipped.
+// ext: the single domain's targets are doms[0].tz (FP64 only)
 hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
-                        bool mixed, const int* active, hipStream_t st);
+                        bool mixed, bool ext, const int* active, hipStream_t st);
 // resident workgroups per CU of the pair-kernel variant (width columns, tpt, mixed)
 int pairs_blocks_per_cu(int width, int tpt, bool mixed);
 
 // bounding circles of the tiles of `tile` nodes of every domain (source tiles
 // of 64 nodes into sb, target tiles into tb)
-// which: 0 source tiles (sb), 1 target tiles (tb), 2 far-form source tiles (sbf)
+// which: 0 source tiles (sb), 1 target tiles (tb), 2 far-form source tiles (sbf),
+// 3 target tiles of the separate targets tz (tb)
 hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, int which, hipStream_t st);
 // FP32 records from the FP64 records of every domain
 hipError_t launch_records32(const DomDev* doms, int ndom, int maxN, int lead, int data, hipStream_t st);

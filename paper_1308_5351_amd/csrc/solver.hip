@@ -255,14 +255,17 @@ void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint) {
 // at N = 17408: 123 us per product at 15 splits, 118 us at 30, 115 us at 45,
 // with the reading growing by about 0.3 us per split).
 int64_t single_max_splits(int64_t N) { return std::max<int64_t>(1, std::min<int64_t>(64, N / 128)); }
-void plan_single(gnk_ctx* c, int64_t N, int align, int width, bool mixed, int* tpt, int* chunk, int* splits) {
-  int t = ((N + 127) / 128) * 64 >= slots_of(c) ? 2 : 1;
+// Nt targets against Ns sources (the nodes, or separate points for the Cauchy
+// integral at interior points)
+void plan_pairs(gnk_ctx* c, int64_t Nt, int64_t Ns, int align, int width, bool mixed, int* tpt, int* chunk,
+                int* splits) {
+  int t = ((Nt + 127) / 128) * 64 >= slots_of(c) ? 2 : 1;
   if (const char* s = getenv("GNK_CAUCHY_TPT")) t = atoi(s) == 2 ? 2 : 1;
   // wave slots of the variant that runs the products (its register use sets
   // how many workgroups fit on a CU)
   const int64_t slots = (int64_t)c->num_cu * 4 * pairs_blocks_per_cu(width, t, mixed);
-  const int64_t tiles = (N + 64 * t - 1) / (64 * t);
-  const int64_t max_s = single_max_splits(N);
+  const int64_t tiles = (Nt + 64 * t - 1) / (64 * t);
+  const int64_t max_s = single_max_splits(Ns);
   std::vector<double> score((size_t)max_s + 1, 0.0), rounds((size_t)max_s + 1, 0.0);
   double best = 0.0;
   for (int64_t s = 1; s <= max_s; ++s) {
@@ -276,11 +279,14 @@ void plan_single(gnk_ctx* c, int64_t N, int align, int width, bool mixed, int* t
   for (int64_t s = max_s; s >= 1 && !bs; --s)
     if (score[s] >= best - 0.01) bs = s;
   if (const char* s = getenv("GNK_CAUCHY_SPLITS")) bs = std::max(1, atoi(s));
-  int64_t ch = (N + bs - 1) / bs;
+  int64_t ch = (Ns + bs - 1) / bs;
   ch = (ch + align - 1) / align * align;
   *tpt = t;
   *chunk = (int)ch;
-  *splits = (int)((N + ch - 1) / ch);
+  *splits = (int)((Ns + ch - 1) / ch);
+}
+void plan_single(gnk_ctx* c, int64_t N, int align, int width, bool mixed, int* tpt, int* chunk, int* splits) {
+  plan_pairs(c, N, N, align, width, mixed, tpt, chunk, splits);
 }
 
 // Builds the batch tables and workspace. doms: host array; ncols: columns per
@@ -399,8 +405,9 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
     const DomDev& D = B.dom[d];
     const int wcols = lead + data * D.ncols;
     const int tile = 64 * B.shape.tpt;
-    const int tiles = (D.N + tile - 1) / tile;
-    const double pairs = (double)D.N * (double)(D.N - 1);
+    const int NT = D.tz ? D.Nt : D.N;   // targets: separate points, or the nodes
+    const int tiles = (NT + tile - 1) / tile;
+    const double pairs = D.tz ? (double)NT * (double)D.N : (double)D.N * (double)(D.N - 1);
     S.pair_cols += pairs * wcols;
     S.flops += pairs * (16.0 + 8.0 * (wcols - 1));
     if (wcols == 1) S.pairs1 += pairs;
@@ -467,8 +474,8 @@ void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
   }
   for (int k = 0; k < 4; ++k) {
     if (!S.cnt[k]) continue;
-    HIPCHK(c, launch_pairs(B.d_dom, S.d[k], S.cnt[k], kWidths[k], B.shape.tpt, kLead[p], kData[p], mixed, active,
-                           c->stream));
+    HIPCHK(c, launch_pairs(B.d_dom, S.d[k], S.cnt[k], kWidths[k], B.shape.tpt, kLead[p], kData[p], mixed,
+                           B.dom[0].tz != nullptr, active, c->stream));
   }
   if (c->prof) {
     HIPCHK(c, hipEventRecord(pr.b, c->stream));
@@ -1312,6 +1319,52 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
     LAUNCHCHK(c);
     pairs(c, B, P_GM, false, nullptr);
     k_reduce_parts<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(B.d_dom, static_cast<double2*>(S));
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GNK_OK;
+  });
+}
+
+gnk_status gnk_fcau(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const void* etap, const void* f, int nrhs,
+                    const void* z, int64_t nz, const void* finf, void* fz) {
+  return guarded(c, [&]() -> gnk_status {
+    const int64_t N = m1 * n;
+    if (m1 < 1 || n < 1 || N > ((int64_t)1 << 30) || nz < 1 || nz > ((int64_t)1 << 30) || nrhs < 1 ||
+        nrhs > 4096 || !eta || !etap || !f || !z || !fz || fz == f || fz == z || fz == eta || fz == etap) {
+      set_err(c, "bad arguments to gnk_fcau");
+      throw Fail{GNK_ERR_ARG};
+    }
+    // a pseudo-domain of one component holding the N nodes (the even mesh
+    // size only passes the domain check; the node count is N)
+    gnk_domain d{};
+    d.m1 = 1;
+    d.n = N + (N & 1);
+    d.eta = eta;
+    d.etap = d.A = etap;
+    const int wcols = 1 + nrhs;
+    const int width = wcols >= 8 ? 8 : (wcols >= 4 ? 4 : (wcols >= 2 ? 2 : 1));
+    int t, ch, sp;
+    plan_pairs(c, nz, N, 16, width, false, &t, &ch, &sp);
+    Batch B;
+    std::vector<int64_t> off{0};
+    build_batch(c, B, 1, &d, &nrhs, off, N * (int64_t)nrhs, false, false, PairShape{t, ch}, N);
+    DomDev& D = B.dom[0];
+    D.tz = static_cast<const double2*>(z);
+    D.Nt = (int)nz;
+    D.parts = ws<double2>(c, "f_parts", (size_t)D.splits * wcols * nz);
+    D.tb = ws<double4>(c, "f_tb", (size_t)((nz + 63) / 64));
+    B.d_dom = upload(c, "b_dom", B.dom);
+    HIPCHK(c, launch_tile_bounds(B.d_dom, 1, (int)nz, 64 * B.shape.tpt, 3, c->stream));
+    k_fcau_records<<<nblocks(N), kT, 0, c->stream>>>(B.d_dom, static_cast<const double2*>(f), nrhs);
+    LAUNCHCHK(c);
+    pairs(c, B, P_SETUP, false, nullptr);
+    const double2* fi = nullptr;
+    if (finf) {
+      const double2* h = static_cast<const double2*>(finf);
+      fi = upload(c, "f_finf", std::vector<double2>(h, h + nrhs));
+    }
+    k_fcau_epilogue<<<dim3(nblocks(nz), (unsigned)nrhs), kT, 0, c->stream>>>(
+        B.d_dom, static_cast<const double2*>(f), nrhs, fi, (double)n, static_cast<double2*>(fz));
     LAUNCHCHK(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GNK_OK;

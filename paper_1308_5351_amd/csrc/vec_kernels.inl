@@ -242,6 +242,81 @@ __global__ void k_pack_records(const DomDev* __restrict__ doms, const double2* _
   }
 }
 
+// ------------------------------------------ Cauchy integral at interior points
+// Records of the nodes for F[eta'] and F[f_q eta'] (Sec. 7, eqs. (e:cauchy5),
+// (e:cauchy6)): weight column 0 is eta'_j, column 1 + q is f_{j,q} eta'_j
+// (f: N x nrhs complex, column-major).
+__global__ void k_fcau_records(const DomDev* __restrict__ doms, const double2* __restrict__ f, int nrhs) {
+  const DomDev& D = doms[0];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= D.N) return;
+  const int wcols = 1 + nrhs;
+  const double2 ep = eta_rel(D, j);
+  const double2 p = D.etap[j];
+  double2* rj = D.rec + (size_t)j * rec_stride(wcols);
+  record_head(rj, D.eta[j], ep);
+  rj[kRecHead] = p;
+  rj[kRecHead + wcols] = cmul_conj(p, ep);
+  for (int q = 0; q < nrhs; ++q) {
+    const double2 w = cmul(f[(size_t)q * D.N + j], p);
+    rj[kRecHead + 1 + q] = w;
+    rj[kRecHead + wcols + 1 + q] = cmul_conj(w, ep);
+  }
+}
+
+// a / b without overflow of |b|^2 (scaled division)
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  const double r = b.x / b.y, d = b.y + b.x * r;
+  return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+
+// f(z_i) for column q (grid (blocks over Nt, nrhs)) from the split partial
+// sums of P_1 = F[eta'] (weight column 0) and P_f = F[f_q eta'] (column 1 + q):
+//   bounded:   P_f / P_1                                   (e:cauchy6-b)
+//   unbounded: (f(inf) - P_f/(n i)) / (1 - P_1/(n i))      (e:cauchy6-u)
+// finf: nrhs values, or null for bounded G. A target on a node makes both
+// sums infinite; it takes that node's value (the limit of the ratio).
+__global__ void k_fcau_epilogue(const DomDev* __restrict__ doms, const double2* __restrict__ f, int nrhs,
+                                const double2* __restrict__ finf, double n, double2* __restrict__ fz) {
+  const DomDev& D = doms[0];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, q = blockIdx.y;
+  const int Nt = D.Nt;
+  if (i >= Nt) return;
+  const int wcols = 1 + nrhs;
+  double2 p1 = make_double2(0.0, 0.0), pf = make_double2(0.0, 0.0);
+  for (int g = 0; g < D.splits; ++g) {
+    const double2 a = D.parts[((size_t)g * wcols) * Nt + i];
+    const double2 b = D.parts[((size_t)g * wcols + 1 + q) * Nt + i];
+    p1.x += a.x;
+    p1.y += a.y;
+    pf.x += b.x;
+    pf.y += b.y;
+  }
+  double2 r;
+  if (finf == nullptr) {
+    r = cdiv(pf, p1);
+  } else {
+    // P/(n i) = (Im P, -Re P)/n
+    const double2 fi = finf[q];
+    r = cdiv(make_double2(fi.x - pf.y / n, fi.y + pf.x / n), make_double2(1.0 - p1.y / n, p1.x / n));
+  }
+  if (!isfinite(r.x) || !isfinite(r.y)) {
+    const double2 zi = D.tz[i];
+    for (int j = 0; j < D.N; ++j) {
+      const double2 e = D.eta[j];
+      if (e.x == zi.x && e.y == zi.y) {
+        r = f[(size_t)q * D.N + j];
+        break;
+      }
+    }
+  }
+  fz[(size_t)q * Nt + i] = r;
+}
+
 // S[r*N + i] = sum over the splits of column r (one domain, no lead column)
 __global__ void k_reduce_parts(const DomDev* __restrict__ doms, double2* __restrict__ S) {
   const DomDev& D = doms[0];

@@ -24,7 +24,8 @@ OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT = range(7)
 
 EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
             "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad",
-            "gnk_fbie_batched", "gnk_fbie_adjoint", "gnk_geom_vjp", "gnk_fourier_curve", "gnk_fourier_vjp")
+            "gnk_fbie_batched", "gnk_fbie_adjoint", "gnk_geom_vjp", "gnk_fourier_curve", "gnk_fourier_vjp",
+            "gnk_fcau")
 
 
 class GnkError(RuntimeError):
@@ -92,6 +93,7 @@ def load_library(path: str = LIB_PATH):
                                  C.POINTER(P), C.POINTER(P), P, P, P]
     lib.gnk_fourier_curve.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P]
     lib.gnk_fourier_vjp.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P]
+    lib.gnk_fcau.argtypes = [P, C.c_int64, C.c_int64, P, P, P, C.c_int, P, C.c_int64, P, P]
     for f in EXPORTED:
         if f not in ("gnk_last_error", "gnk_version"):
             getattr(lib, f).restype = C.c_int
@@ -200,6 +202,35 @@ class Context:
         st = self.lib.gnk_cauchy_sum(self.h, N, eta.data_ptr(), wc.data_ptr(), wc.shape[0], S.data_ptr())
         self._raise(st, False)
         return _from_cols(S, one)
+
+    def fcau(self, eta: torch.Tensor, etap: torch.Tensor, f: torch.Tensor, z: torch.Tensor, m1: int, n: int,
+             finf=None) -> torch.Tensor:
+        """f at the points z of G by the Cauchy integral formula (Sec. 7): eta, etap (N,) and f (N,) or
+        (N, nrhs) complex128 on the device, N = m1 n; z (nz,) complex128. finf: None for bounded G, else
+        f(infinity) (a number or nrhs numbers) for unbounded G. Returns (nz,) or (nz, nrhs)."""
+        self._bind_stream()
+        N = m1 * n
+        for name, t in (("eta", eta), ("etap", etap)):
+            if t.dtype != torch.complex128 or t.shape != (N,) or not t.is_cuda:
+                raise ValueError(f"{name} must be a complex128 CUDA tensor of shape ({N},)")
+        if f.dtype != torch.complex128 or f.shape[0] != N or f.dim() > 2 or not f.is_cuda:
+            raise ValueError(f"f must be complex128 of shape ({N},) or ({N}, nrhs) on the GPU")
+        if z.dtype != torch.complex128 or z.dim() != 1 or not z.is_cuda:
+            raise ValueError("z must be a 1-D complex128 CUDA tensor")
+        one = f.dim() == 1
+        fc = (f.unsqueeze(1) if one else f).t().contiguous()
+        nrhs = fc.shape[0]
+        zc = z.contiguous()
+        out = torch.empty((nrhs, zc.shape[0]), dtype=torch.complex128, device=z.device)
+        fin = None
+        if finf is not None:
+            v = np.broadcast_to(np.asarray(finf, np.complex128), (nrhs,))
+            fin = np.ascontiguousarray(v).view(np.float64)
+        ec, pc = eta.contiguous(), etap.contiguous()
+        st = self.lib.gnk_fcau(self.h, m1, n, ec.data_ptr(), pc.data_ptr(), fc.data_ptr(), nrhs, zc.data_ptr(),
+                               zc.shape[0], None if fin is None else fin.ctypes.data, out.data_ptr())
+        self._raise(st, False)
+        return _from_cols(out, one)
 
     def apply(self, dom: DeviceDomain, op: int, x: torch.Tensor, prec: int = FP64) -> torch.Tensor:
         self._bind_stream()

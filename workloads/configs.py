@@ -400,3 +400,76 @@ def batch_domain(d: int, m1_range=(2, 40), ns=(256, 512, 1024, 2048), rrange=(0.
 def config3(ndom: int = 64, **kw):
     """The batched workload: `ndom` domains (see batch_domain)."""
     return [batch_domain(d, **kw) for d in range(ndom)]
+
+
+# ----------------------------------------------------------------------------
+# Points of G for the Cauchy integral formula at interior points.
+def _near_factor(rng, k):
+    return np.exp(rng.uniform(np.log(1e-4), np.log(1e-2), k))
+
+
+def interior_points_config1(dom: Domain, nz: int, seed, near: float = 0.25):
+    """nz seeded points of a config-1 domain (inside the unit circle, outside
+    every ellipse): uniform in the disk by rejection, and a fraction `near` of
+    them next to a random node, 1e-4..1e-2 of its curve's size inside G."""
+    rng = np.random.default_rng(seed)
+    ell = dom.meta["ellipses"]
+
+    def inside_G(z):
+        ok = np.abs(z) < 1.0
+        for c, a, b, phi in ell:
+            w = (z - c) * np.exp(-1j * phi)
+            ok &= (w.real / a) ** 2 + (w.imag / b) ** 2 > 1.0
+        return ok
+
+    out = []
+    n_near = int(round(near * nz))
+    while len(out) < n_near:
+        j = rng.integers(0, dom.eta.shape[0], 64)
+        k = j // dom.n
+        d = _near_factor(rng, j.shape[0])
+        z = np.where(k == 0, dom.eta[j] * (1.0 - d), 0j)
+        for e, (c, _, _, _) in enumerate(ell):
+            m = k == e + 1
+            z[m] = c + (dom.eta[j[m]] - c) * (1.0 + d[m])
+        out.extend(z[inside_G(z)].tolist())
+    out = out[:n_near]
+    while len(out) < nz:
+        z = np.sqrt(rng.uniform(0, 1, 256)) * np.exp(2j * np.pi * rng.uniform(0, 1, 256))
+        out.extend(z[inside_G(z)].tolist())
+    z = np.array(out[:nz], np.complex128)
+    return z[rng.permutation(nz)]
+
+
+def exterior_points_fourier(dom: Domain, nz: int, seed, near: float = 0.25, margin: float = 1.0):
+    """nz seeded points outside every perturbed circle of a Fourier domain
+    (config 4): uniform in the bounding square grown by `margin` by rejection
+    (at least 1.5 r_j from centre j), and a fraction `near` next to a random
+    node, its radius from its curve's centre grown by 1e-4..1e-2."""
+    rng = np.random.default_rng(seed)
+    coeffs, kmin = dom.meta["coeffs"], dom.meta["kmin"]
+    cen = coeffs[:, -kmin]
+    rad = np.abs(coeffs[:, 1 - kmin])
+
+    def outside_all(z, skip=None):
+        ok = np.ones(z.shape, bool)
+        for q in range(cen.shape[0]):
+            far = np.abs(z - cen[q]) > 1.5 * rad[q]
+            ok &= far if skip is None else (far | (skip == q))
+        return ok
+
+    out = []
+    n_near = int(round(near * nz))
+    while len(out) < n_near:
+        j = rng.integers(0, dom.eta.shape[0], 64)
+        k = j // dom.n
+        z = cen[k] + (dom.eta[j] - cen[k]) * (1.0 + _near_factor(rng, j.shape[0]))
+        out.extend(z[outside_all(z, skip=k)].tolist())
+    out = out[:n_near]
+    lo = min(cen.real.min(), cen.imag.min()) - margin
+    hi = max(cen.real.max(), cen.imag.max()) + margin
+    while len(out) < nz:
+        z = rng.uniform(lo, hi, 512) + 1j * rng.uniform(lo, hi, 512)
+        out.extend(z[outside_all(z)].tolist())
+    z = np.array(out[:nz], np.complex128)
+    return z[rng.permutation(nz)]
