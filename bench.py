@@ -115,6 +115,34 @@ def mixed_vs_plain(gnk, ctx, torch):
     return out
 
 
+def fcau_rate(gnk, ctx, torch, reps=10):
+    """Cauchy integral formula at 65536 interior points of the 17-component
+    domain (one column f): pairs per second of its two direct sums."""
+    import numpy as np
+    import workloads as wl
+    log("Cauchy integral at interior points: N = 17408, 65536 points")
+    dom, _ = wl.config1()
+    z = wl.interior_points_config1(dom, 65536, [wl.SEED, 90])
+    cen = [c for c, _, _, _ in dom.meta["ellipses"]]
+    fb = dom.eta ** 2 + sum(1.0 / (dom.eta - c) for c in cen)
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    eta, etap, f, zz = cu(dom.eta), cu(dom.etap), cu(fb), cu(z)
+    for _ in range(2):
+        ctx.fcau(eta, etap, f, zz, dom.m1, dom.n)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        ctx.fcau(eta, etap, f, zz, dom.m1, dom.n)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    pairs = float(z.shape[0]) * dom.eta.shape[0]
+    flops = pairs * (16.0 + 8.0)      # two weight columns share each reciprocal
+    return {"workload": "17-component bounded domain (N = 17408), 65536 seeded interior points (a quarter "
+                        "1e-4..1e-2 from the boundary), one column; F[eta'] and F[f eta'] in one launch",
+            "ms_per_call": round(dt * 1e3, 4), "gpair_s": round(pairs / dt / 1e9, 2),
+            "frac_fp64_peak": round(flops / dt / 1e12 / FP64_PEAK_TFLOPS, 4)}
+
+
 def batched_vs_plain(gnk, ctx, torch):
     import workloads as wl
     batch = wl.config3()
@@ -279,6 +307,7 @@ def main():
     if not args.no_compare:
         out["mixed_vs_plain"] = mixed_vs_plain(gnk, ctx, torch)
         out["batched_vs_plain"] = batched_vs_plain(gnk, ctx, torch)
+        out["fcau"] = fcau_rate(gnk, ctx, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(dom)
