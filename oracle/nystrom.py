@@ -21,6 +21,9 @@ factored Cauchy-matrix form the GPU path uses), solved by LAPACK LU.
   * fbiead_e           -- the vector e of eq. (e:ei) with r(t_i) from (e:ri) and the
                           kernel N_g of (e:Ng), (e:Ng-tt) (direct form, not (e:bve)).
   * fbiead             -- (diag(e) + B^T + Phat) mu = gamma, eq. (e:sys*).
+  * n_diagonal, fbie_unsubtracted, fbiead_unsubtracted
+                       -- the same equations without singularity subtraction
+                          (Example 2): the kernel N with its diagonal limit (e:N-tt).
 
 Arrays: complex128 / float64 vectors of length N = (m+1) n in component-major
 order (node i = k n + p, eq. (e:ti-skp)).
@@ -166,6 +169,41 @@ def fbiead(eta, etap, etapp, A, Ap, gam, n, c, return_op=False):
     if return_op:
         return mu, G
     return mu
+
+
+def n_diagonal(etap, etapp, A, Ap, n):
+    """(2 pi/n) N(t_i, t_i) from the diagonal limit (e:N-tt):
+    (2 pi/n)(1/pi)(1/2 Im(eta''/eta') - Im(A'/A))."""
+    return (2.0 / n) * (0.5 * (etapp / etap).imag - (Ap / A).imag)
+
+
+def fbie_unsubtracted(eta, etap, etapp, A, Ap, gam, n):
+    """FBIE without singularity subtraction (Example 2's comparison): the
+    trapezoidal rule for the continuous kernel N with its diagonal limit,
+    (I - N_n) mu = -y, N_n = B + diag((2 pi/n) N(t_i, t_i)), instead of
+    2I + diag(B1) - B. The right-hand side y and h use the discretization of M of
+    eq. (e:y) in both variants (its other form, eq. (e:phi-kp), gives the same
+    vector to rounding), so the two differ only in the treatment of N:
+    h = [(D - diag(D1) + Lhat) mu - (I - N_n) gamma] / 2."""
+    N = eta.shape[0]
+    _, Cop = fbie_operators(eta, etap, A, n)
+    B = kernel_matrix(eta, etap, A, n).imag
+    Aop = np.eye(N) - B - np.diag(n_diagonal(etap, etapp, A, Ap, n))
+    mu = sla.lu_solve(sla.lu_factor(Aop), -(Cop @ gam))
+    h = (Cop @ mu - Aop @ gam) / 2.0
+    return mu, h
+
+
+def fbiead_unsubtracted(eta, etap, etapp, A, Ap, gam, n):
+    """FBIEad without singularity subtraction: (I + N*_n + J) mu = gamma with
+    (N*_n)_ij = (2 pi/n) N(t_j, t_i) (= B^T off the diagonal, the limit (e:N-tt)
+    on it) and J = Phat, instead of diag(e) + B^T + Phat of eq. (e:sys*)."""
+    N = eta.shape[0]
+    m1 = N // n
+    B = kernel_matrix(eta, etap, A, n).imag
+    G = np.eye(N) + B.T + np.diag(n_diagonal(etap, etapp, A, Ap, n)) + \
+        block_diag_repeat(np.full((n, n), 1.0 / n), m1)
+    return sla.lu_solve(sla.lu_factor(G), gam)
 
 
 def component_means(x, n):
