@@ -71,7 +71,12 @@ typedef enum {
   GNK_OP_FB_T = 3,  /* (2I + diag(B1) - B)^T x                  transpose of FB      */
   GNK_OP_FC_T = 4,  /* (D - diag(D1) + Lhat)^T x = (D^T - diag(D1) - Lhat) x         */
   GNK_OP_GB_T = 5,  /* (diag(e) + B + Phat) x                   transpose of GB      */
-  GNK_OP_LHAT = 6   /* Lhat x, the circulant blocks alone       eq. (e:L-bs)         */
+  GNK_OP_LHAT = 6,  /* Lhat x, the circulant blocks alone       eq. (e:L-bs)         */
+  /* the same equations without singularity subtraction (Example 2's comparison):
+   * the kernel N by the trapezoidal rule with its diagonal limit (e:N-tt),
+   * Nd_i = (2 pi/n) N(t_i, t_i); need etapp and Ap */
+  GNK_OP_FB_U = 7,  /* (I - B - diag(Nd)) x                     (I - N) x, no subtraction   */
+  GNK_OP_GB_U = 8   /* (I + B^T + diag(Nd) + Phat) x            (I + N* + J) x, likewise    */
 } gnk_op;
 
 /* Boundary data of an (m+1)-connected domain (Sec. 2.1-2.2).
@@ -79,8 +84,9 @@ typedef enum {
  *   A         : N complex, nonzero; eq. (e:A) gives the admissible choices
  *               e^{i(pi/2-theta)}(eta-alpha) (bounded) and e^{i(pi/2-theta)}
  *               (unbounded); any nonzero values are accepted.
- *   etapp, Ap : N complex, eta'' and A'; used only by the adjoint equation
- *               (may be NULL for the FBIE entry points).
+ *   etapp, Ap : N complex, eta'' and A'; used by the adjoint equation and by
+ *               the variants without singularity subtraction (may be NULL
+ *               for the FBIE entry points otherwise).
  *   c         : +1 bounded, -1 unbounded (eq. (e:c)); adjoint equation only. */
 typedef struct {
   int64_t m1;        /* number of boundary components m+1 (>= 1) */
@@ -108,7 +114,11 @@ typedef struct {
  *   inner_tol  : GNK_MIXED switch level (0: min(1e-4, tol * 1e8), since the
  *                mixed products have a relative error below 1e-8)
  *   max_refine : reserved (0)
- *   x0         : optional device initial guess (N x nrhs) or NULL for zero */
+ *   x0         : optional device initial guess (N x nrhs) or NULL for zero
+ *   no_subtraction : 0 (the paper's method); 1 solves gnk_fbie / gnk_fbie_ad
+ *                without singularity subtraction (GNK_OP_FB_U / GNK_OP_GB_U,
+ *                the comparison of Example 2; needs etapp and Ap); the
+ *                right-hand side and h use M as in the paper's method */
 typedef struct {
   int restart;
   int maxit;
@@ -117,6 +127,7 @@ typedef struct {
   double inner_tol;
   int max_refine;
   const double* x0;
+  int no_subtraction;
 } gnk_opts;
 
 /* Per right-hand side outcome (host memory, one entry per column).

@@ -42,6 +42,7 @@ struct DomDev {
   double* dB;        // diag(B1)
   double* dD;        // diag(D1)
   double* e;         // vector e of the adjoint equation
+  double* bu;        // (2 pi/n) N(t_i, t_i), the diagonal limit (e:N-tt)
   // Cauchy-sum workspace: records rec[j*stride + f], f = 0: eta_j, f = 1 + q: weight column q
   double2* rec;
   float2* rec32;     // FP32 records (tile-local eta offsets, weights)

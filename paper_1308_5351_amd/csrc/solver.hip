@@ -202,6 +202,7 @@ struct Batch {
   PairShape shape;
   bool mixed = false;
   bool adjoint = false;
+  bool second = false;   // eta'' and A' present (adjoint or no-subtraction operators)
   struct ItemSet {
     int4* d[4] = {nullptr, nullptr, nullptr, nullptr};
     int cnt[4] = {0, 0, 0, 0};
@@ -218,7 +219,7 @@ struct Batch {
   bool circ_built = false;
 };
 
-void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint) {
+void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint, bool second = false) {
   if (!d) {
     set_err(c, "domain is NULL");
     throw Fail{GNK_ERR_ARG};
@@ -241,6 +242,10 @@ void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint) {
   }
   if (adjoint && (!d->etapp || !d->Ap || (d->c != 1 && d->c != -1))) {
     set_err(c, "the adjoint equation needs etapp, Ap and c = +1 or -1");
+    throw Fail{GNK_ERR_ARG};
+  }
+  if (second && (!d->etapp || !d->Ap)) {
+    set_err(c, "the equations without singularity subtraction need etapp and Ap");
     throw Fail{GNK_ERR_ARG};
   }
 }
@@ -351,6 +356,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   double* dB = ws<double>(c, "b_dB", Ntot);
   double* dD = ws<double>(c, "b_dD", Ntot);
   double* ev = adjoint ? ws<double>(c, "b_e", Ntot) : nullptr;
+  double* bu = ws<double>(c, "b_bu", Ntot);
   double2* rec = ws<double2>(c, "b_rec", rec_total);
   float2* rec32 = mixed ? ws<float2>(c, "b_rec32", rec32_total) : nullptr;
   double2* parts = ws<double2>(c, "b_parts", part_total);
@@ -367,6 +373,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     D.dB = dB + on;
     D.dD = dD + on;
     D.e = ev ? ev + on : nullptr;
+    D.bu = bu + on;
     D.rec = rec + orc;
     D.rec32 = rec32 ? rec32 + orc32 : nullptr;
     D.parts = parts + op;
@@ -516,7 +523,7 @@ dim3 col_grid(const Batch& B) { return dim3(nblocks(B.maxN), (unsigned)B.ncol); 
 void validate(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
   int* flags = ws<int>(c, "flags", 1);
   HIPCHK(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
-  k_validate<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, B.adjoint ? 1 : 0, flags);
+  k_validate<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, (B.adjoint || B.second) ? 1 : 0, flags);
   LAUNCHCHK(c);
   if (x && len > 0) {
     k_check_finite<<<nblocks(len), kT, 0, c->stream>>>(x, len, flags);
@@ -542,6 +549,12 @@ void validate(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
 }
 
 // rho, and diag(B1), diag(D1) from S = E(rho) (leading column only)
+// the diagonal limit of N for the operators without singularity subtraction
+void setup_ndiag(gnk_ctx* c, Batch& B) {
+  k_ndiag<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
+  LAUNCHCHK(c);
+}
+
 void setup_diag(gnk_ctx* c, Batch& B) {
   k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
   LAUNCHCHK(c);
@@ -584,7 +597,7 @@ void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const Ap
     circulant(c, B, x, y, 1.0);
     return;
   }
-  const bool need_mean = (op == GNK_OP_GB || op == GNK_OP_GB_T);
+  const bool need_mean = (op == GNK_OP_GB || op == GNK_OP_GB_T || op == GNK_OP_GB_U);
   int cw = C_RHO, cout = C_A, dsel = D_NONE;
   double a0 = 0.0, dsign = 0.0, cI = 0.0, cR = 0.0;
   switch (op) {
@@ -600,6 +613,10 @@ void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const Ap
       cw = C_A; cout = C_RHO; dsel = D_D; dsign = -1.0; cR = 1.0; break;
     case GNK_OP_GB_T: // e x + B x + Phat x
       cw = C_RHO; cout = C_A; dsel = D_E; dsign = 1.0; cI = -1.0; break;
+    case GNK_OP_FB_U: // x - B x - Nd x  (no subtraction)
+      cw = C_RHO; cout = C_A; a0 = 1.0; dsel = D_BU; dsign = -1.0; cI = 1.0; break;
+    case GNK_OP_GB_U: // x + B^T x + Nd x + Phat x  (no subtraction)
+      cw = C_A; cout = C_RHO; a0 = 1.0; dsel = D_BU; dsign = 1.0; cI = 1.0; break;
     default:
       set_err(c, "unknown operator %d", op);
       throw Fail{GNK_ERR_ARG};
@@ -612,7 +629,7 @@ void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const Ap
   const double* xin = a.xout ? a.xout : x;
   pairs(c, B, P_GM, a.mixed, a.active);
   if (a.dots) {
-    if (!a.step || x != y || op == GNK_OP_FC || op == GNK_OP_FC_T) {
+    if (!a.step || x != y || op == GNK_OP_FC || op == GNK_OP_FC_T || op == GNK_OP_LHAT) {
       set_err(c, "internal: fused Gram-Schmidt epilogue needs an Arnoldi step of FB, FB_T, GB or GB_T");
       throw Fail{GNK_ERR_ARG};
     }
@@ -908,7 +925,7 @@ gnk_opts resolve_opts(gnk_ctx* c, const gnk_opts* o) {
   r.x0 = nullptr;
   if (o) r = *o;
   if (r.restart < 1 || r.restart > kMaxRestart || r.maxit < 1 || !(r.tol > 0.0) || r.tol >= 1.0 ||
-      (r.prec != GNK_FP64 && r.prec != GNK_MIXED)) {
+      (r.prec != GNK_FP64 && r.prec != GNK_MIXED) || (r.no_subtraction != 0 && r.no_subtraction != 1)) {
     set_err(c, "bad options: restart %d (1..%d), maxit %d (>=1), tol %g (0..1), prec %d", r.restart, kMaxRestart,
             r.maxit, r.tol, r.prec);
     throw Fail{GNK_ERR_ARG};
@@ -1030,16 +1047,23 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
                                                 nullptr, 1, b, nullptr, 0);
   LAUNCHCHK(c);
   circulant(c, B, gam, b, -1.0);
-  // f_B(gamma) from the same sums, for h
+  // f_B(gamma) from the same sums, for h; without singularity subtraction the
+  // operator is I - B - diag(Nd) (Nd the diagonal limit (e:N-tt))
+  const bool unsub = o.no_subtraction != 0;
+  if (unsub) setup_ndiag(c, B);
   double* fbg = nullptr;
   if (h) {
     fbg = ws<double>(c, "fbg", T);
-    k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_B, 2.0, 1.0, 1.0, 0.0, nullptr, 0,
-                                                  nullptr, 1, fbg, nullptr, 0);
+    if (unsub)
+      k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_BU, 1.0, -1.0, 1.0, 0.0, nullptr,
+                                                    0, nullptr, 1, fbg, nullptr, 0);
+    else
+      k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_B, 2.0, 1.0, 1.0, 0.0, nullptr, 0,
+                                                    nullptr, 1, fbg, nullptr, 0);
     LAUNCHCHK(c);
   }
-  // (2I + diag(B1) - B) mu = b
-  GmresOut g = gmres(c, B, GNK_OP_FB, b, o, mu, o.prec == GNK_MIXED);
+  // (2I + diag(B1) - B) mu = b, or (I - B - diag(Nd)) mu = b
+  GmresOut g = gmres(c, B, unsub ? GNK_OP_FB_U : GNK_OP_FB, b, o, mu, o.prec == GNK_MIXED);
   if (h) {
     // h = [(D - diag(D1) + Lhat) mu - (2I + diag(B1) - B) gamma] / 2
     apply_op(c, B, GNK_OP_FC, mu, h);
@@ -1054,6 +1078,10 @@ GmresOut fbiead_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o
   k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
   LAUNCHCHK(c);
   setup_evec(c, B);
+  if (o.no_subtraction) {
+    setup_ndiag(c, B);
+    return gmres(c, B, GNK_OP_GB_U, gam, o, mu, o.prec == GNK_MIXED);
+  }
   return gmres(c, B, GNK_OP_GB, gam, o, mu, o.prec == GNK_MIXED);
 }
 
@@ -1077,11 +1105,14 @@ gnk_status guarded(gnk_ctx* c, F&& f) {
 }
 
 // Batch of one domain whose flat vectors are the caller's N x nrhs arrays.
-void single_batch(gnk_ctx* c, Batch& B, const gnk_domain* d, int nrhs, bool adjoint, bool mixed) {
-  check_domain(c, d, adjoint);
+void single_batch(gnk_ctx* c, Batch& B, const gnk_domain* d, int nrhs, bool adjoint, bool mixed,
+                  bool second = false) {
+  check_domain(c, d, adjoint, second);
   std::vector<int64_t> off{0};
   build_batch(c, B, 1, d, &nrhs, off, d->m1 * d->n * (int64_t)nrhs, adjoint, mixed, PairShape{});
+  B.second = second || adjoint;
 }
+
 
 // ------------------------------------------------------- differentiation
 // Adjoint of FBIE (transpose of eq. (e:sys)):
@@ -1374,17 +1405,19 @@ gnk_status gnk_fcau(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const vo
 gnk_status gnk_apply(gnk_ctx* c, const gnk_domain* d, int op, int prec, const double* x, int nrhs, double* y) {
   return guarded(c, [&]() -> gnk_status {
     const bool adj = (op == GNK_OP_GB || op == GNK_OP_GB_T);
-    if (!x || !y || x == y || nrhs < 1 || op < 0 || op > GNK_OP_LHAT || (prec != GNK_FP64 && prec != GNK_MIXED)) {
+    const bool unsub = (op == GNK_OP_FB_U || op == GNK_OP_GB_U);
+    if (!x || !y || x == y || nrhs < 1 || op < 0 || op > GNK_OP_GB_U || (prec != GNK_FP64 && prec != GNK_MIXED)) {
       set_err(c, "bad arguments to gnk_apply");
       throw Fail{GNK_ERR_ARG};
     }
     Batch B;
     const bool mixed = prec == GNK_MIXED && op != GNK_OP_LHAT;
-    single_batch(c, B, d, nrhs, adj, mixed);
+    single_batch(c, B, d, nrhs, adj, mixed, unsub);
     validate(c, B, x, B.T);
     if (op != GNK_OP_LHAT) {
       setup_diag(c, B);
       if (adj) setup_evec(c, B);
+      if (unsub) setup_ndiag(c, B);
     }
     ApplyArgs a;
     a.mixed = mixed;
@@ -1403,7 +1436,7 @@ gnk_status gnk_fbie(gnk_ctx* c, const gnk_domain* d, const double* gam, int nrhs
     }
     gnk_opts o = resolve_opts(c, opts);
     Batch B;
-    single_batch(c, B, d, nrhs, false, o.prec == GNK_MIXED);
+    single_batch(c, B, d, nrhs, false, o.prec == GNK_MIXED, o.no_subtraction != 0);
     GmresOut g = fbie_batch(c, B, gam, o, mu, h);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (info)
@@ -1438,6 +1471,10 @@ gnk_status gnk_fbie_batched(gnk_ctx* c, int ndom, const gnk_domain* doms, const 
       throw Fail{GNK_ERR_ARG};
     }
     gnk_opts o = resolve_opts(c, opts);
+    if (o.no_subtraction) {
+      set_err(c, "no_subtraction is available for gnk_fbie and gnk_fbie_ad only");
+      throw Fail{GNK_ERR_ARG};
+    }
     if (o.x0) {
       set_err(c, "gnk_fbie_batched takes no initial guess");
       throw Fail{GNK_ERR_ARG};
@@ -1488,6 +1525,10 @@ gnk_status gnk_fbie_adjoint(gnk_ctx* c, const gnk_domain* d, const double* g_mu,
       throw Fail{GNK_ERR_ARG};
     }
     gnk_opts o = resolve_opts(c, opts);
+    if (o.no_subtraction) {
+      set_err(c, "no_subtraction is available for gnk_fbie and gnk_fbie_ad only");
+      throw Fail{GNK_ERR_ARG};
+    }
     Batch B;
     single_batch(c, B, d, nrhs, false, o.prec == GNK_MIXED);
     GmresOut g = fbie_adjoint_batch(c, B, g_mu, g_h, o, lam, g_gam);

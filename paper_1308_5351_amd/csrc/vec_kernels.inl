@@ -44,7 +44,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 
 // per-node coefficient selectors of the records and epilogues
 enum CSel : int { C_RHO = 0, C_A = 1, C_ETAP = 2 };
-enum DSel : int { D_NONE = 0, D_B = 1, D_D = 2, D_E = 3 };
+enum DSel : int { D_NONE = 0, D_B = 1, D_D = 2, D_E = 3, D_BU = 4 };
 
 __device__ __forceinline__ double2 coef(const DomDev& D, int sel, int i) {
   return sel == C_RHO ? D.rho[i] : (sel == C_A ? D.A[i] : D.etap[i]);
@@ -66,7 +66,7 @@ __device__ __forceinline__ double2 cmul_conj(double2 a, double2 b) {
   return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 __device__ __forceinline__ double diagv(const DomDev& D, int sel, int i) {
-  return sel == D_B ? D.dB[i] : (sel == D_D ? D.dD[i] : (sel == D_E ? D.e[i] : 0.0));
+  return sel == D_B ? D.dB[i] : (sel == D_D ? D.dD[i] : (sel == D_E ? D.e[i] : (sel == D_BU ? D.bu[i] : 0.0)));
 }
 
 // ---------------------------------------------------------------- validation
@@ -139,6 +139,19 @@ __global__ void k_diag_fbie(const DomDev* __restrict__ doms, int lead, int data)
   const double two_n = 2.0 / (double)D.n;
   D.dB[i] = -two_n * as.y;
   D.dD[i] = -two_n * as.x;
+}
+
+// (2 pi/n) N(t_i, t_i) = (2/n) (1/2 Im(eta''/eta') - Im(A'/A))   (eq. (e:N-tt)),
+// the diagonal of the kernel N for the equations without singularity subtraction
+__global__ void k_ndiag(const DomDev* __restrict__ doms) {
+  const DomDev& D = doms[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.N) return;
+  const double2 p = D.etap[i], pp = D.etapp[i], a = D.A[i], ap = D.Ap[i];
+  const double dp = p.x * p.x + p.y * p.y, da = a.x * a.x + a.y * a.y;
+  const double im1 = (pp.y * p.x - pp.x * p.y) / dp;   // Im(eta''/eta')
+  const double im2 = (ap.y * a.x - ap.x * a.y) / da;   // Im(A'/A)
+  D.bu[i] = (2.0 / (double)D.n) * (0.5 * im1 - im2);
 }
 
 // From S = E eta' (weight column 0 of wcols = 1):

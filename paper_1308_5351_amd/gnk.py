@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgnk.so")
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_ODD_N, ERR_ZERO_A, ERR_ZERO_ETAP, ERR_NONFINITE, ERR_HIP, ERR_OOM = -1, -2, -3, -4, -5, -10, -11
 FP64, MIXED = 0, 1
-OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT = range(7)
+OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT, OP_FB_U, OP_GB_U = range(9)
 
 EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
             "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad",
@@ -41,7 +41,8 @@ class _Domain(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double), ("prec", C.c_int),
-                ("inner_tol", C.c_double), ("max_refine", C.c_int), ("x0", C.c_void_p)]
+                ("inner_tol", C.c_double), ("max_refine", C.c_int), ("x0", C.c_void_p),
+                ("no_subtraction", C.c_int)]
 
 
 class Info(C.Structure):
@@ -243,19 +244,21 @@ class Context:
         return _from_cols(y, one)
 
     @staticmethod
-    def _opts(restart, maxit, tol, prec, inner_tol, max_refine, x0):
-        return _Opts(restart, maxit, tol, prec, inner_tol, max_refine, None if x0 is None else x0.data_ptr())
+    def _opts(restart, maxit, tol, prec, inner_tol, max_refine, x0, subtract=True):
+        return _Opts(restart, maxit, tol, prec, inner_tol, max_refine, None if x0 is None else x0.data_ptr(),
+                     0 if subtract else 1)
 
     def fbie(self, dom: DeviceDomain, gam: torch.Tensor, restart=25, maxit=40, tol=1e-12, prec=FP64,
-             inner_tol=0.0, max_refine=0, x0=None, want_h=True):
-        """Solve (I - N) mu = -M gamma and h = [M mu - (I - N) gamma]/2. Returns (mu, h, infos, status)."""
+             inner_tol=0.0, max_refine=0, x0=None, want_h=True, subtract=True):
+        """Solve (I - N) mu = -M gamma and h = [M mu - (I - N) gamma]/2. Returns (mu, h, infos, status).
+        subtract=False: without singularity subtraction (Example 2's comparison; needs etapp, Ap)."""
         self._bind_stream()
         one = gam.dim() == 1
         g, nrhs = _check_real(gam, dom.N, "gam")
         mu = torch.empty_like(g)
         h = torch.empty_like(g) if want_h else None
         x0c = None if x0 is None else _check_real(x0, dom.N, "x0")[0]
-        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c)
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract)
         infos = (Info * nrhs)()
         d = dom._struct()
         st = self.lib.gnk_fbie(self.h, C.byref(d), g.data_ptr(), nrhs, C.byref(o), mu.data_ptr(),
@@ -265,21 +268,23 @@ class Context:
                 [i.as_dict() for i in infos], st)
 
     def fbie_ad(self, dom: DeviceDomain, gam: torch.Tensor, restart=25, maxit=40, tol=1e-12, prec=FP64,
-                inner_tol=0.0, max_refine=0, x0=None):
-        """Solve (I + N* + J) mu = gamma. Returns (mu, infos, status)."""
+                inner_tol=0.0, max_refine=0, x0=None, subtract=True):
+        """Solve (I + N* + J) mu = gamma. Returns (mu, infos, status).
+        subtract=False: without singularity subtraction (Example 2's comparison)."""
         self._bind_stream()
         one = gam.dim() == 1
         g, nrhs = _check_real(gam, dom.N, "gam")
         mu = torch.empty_like(g)
         x0c = None if x0 is None else _check_real(x0, dom.N, "x0")[0]
-        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c)
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract)
         infos = (Info * nrhs)()
         d = dom._struct()
         st = self.lib.gnk_fbie_ad(self.h, C.byref(d), g.data_ptr(), nrhs, C.byref(o), mu.data_ptr(), infos)
         self._raise(st)
         return _from_cols(mu, one), [i.as_dict() for i in infos], st
 
-    def fbie_batched(self, doms, gams, restart=25, maxit=40, tol=1e-12, prec=FP64, inner_tol=0.0, want_h=True):
+    def fbie_batched(self, doms, gams, restart=25, maxit=40, tol=1e-12, prec=FP64, inner_tol=0.0, want_h=True,
+                     subtract=True):
         """Batched FBIE over several domains. gams[d]: (N_d,) or (N_d, nrhs_d) float64 CUDA.
         Returns (mus, hs, infos, status) with one entry per domain (infos: list of lists)."""
         self._bind_stream()
@@ -300,7 +305,7 @@ class Context:
         H = (C.c_void_p * nd)(*[h.data_ptr() for h in hs]) if want_h else None
         ncol = sum(k for _, k in cols)
         infos = (Info * ncol)()
-        o = self._opts(restart, maxit, tol, prec, inner_tol, 0, None)
+        o = self._opts(restart, maxit, tol, prec, inner_tol, 0, None, subtract)
         st = self.lib.gnk_fbie_batched(self.h, nd, D, G, R, C.byref(o), MU, H, infos)
         self._raise(st)
         out_i, q = [], 0
