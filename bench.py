@@ -41,8 +41,8 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # factors from a 256 MiB copy of known size; profiles/k_pairs_fp64_N17408_hbm_counters.md).
 # Valid only for the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "3a18c19ef36612ff246ce9e26988b584c84abfa6c090c8bc1d2448713c5c7ccb",
-                "bytes_per_launch": 21999465}
+                "sha256": "1ec3c893d0a33d6a042f9f7c45f524442e3f9882c9bfdc32d01318a7c0ae3074",
+                "bytes_per_launch": 21994713}
 
 
 def pair_traffic():
