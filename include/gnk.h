@@ -118,7 +118,12 @@ typedef struct {
  *   no_subtraction : 0 (the paper's method); 1 solves gnk_fbie / gnk_fbie_ad
  *                without singularity subtraction (GNK_OP_FB_U / GNK_OP_GB_U,
  *                the comparison of Example 2; needs etapp and Ap); the
- *                right-hand side and h use M as in the paper's method */
+ *                right-hand side and h use M as in the paper's method
+ *   far_tol    : 0 (every pair summed directly); > 0: the Cauchy sums take
+ *                their far field from multipole expansions of boxes of
+ *                consecutive nodes (a treecode; the paper uses the FMM), each
+ *                truncated where (r_box / distance)^p <= far_tol; FP64 only
+ *                (prec GNK_FP64), gnk_fbie and gnk_fbie_ad only; 1e-15..0.1 */
 typedef struct {
   int restart;
   int maxit;
@@ -128,6 +133,7 @@ typedef struct {
   int max_refine;
   const double* x0;
   int no_subtraction;
+  double far_tol;
 } gnk_opts;
 
 /* Per right-hand side outcome (host memory, one entry per column).
@@ -216,6 +222,14 @@ GNK_API gnk_status gnk_cauchy_sum(gnk_ctx* ctx, int64_t N, const void* eta, cons
  * NULL or aliased pointers; nothing is written then. */
 GNK_API gnk_status gnk_fcau(gnk_ctx* ctx, int64_t m1, int64_t n, const void* eta, const void* etap,
                             const void* f, int nrhs, const void* z, int64_t nz, const void* finf, void* fz);
+
+/* gnk_cauchy_sum with the far field from the treecode (see gnk_opts.far_tol):
+ * S_i = sum_{j != i} w_j / (eta_i - eta_j), near pairs summed directly, far
+ * boxes by p-term expansions with (r/R)^p <= far_tol (1e-15..0.1). Same
+ * arguments and layout as gnk_cauchy_sum; GNK_ERR_ARG for far_tol outside
+ * that range. */
+GNK_API gnk_status gnk_cauchy_sum_tree(gnk_ctx* ctx, int64_t N, const void* eta, const void* w, int nrhs,
+                                       double far_tol, void* S);
 
 /* Operator application y = op(x) for one domain (see gnk_op). x and y are
  * real N x nrhs and must not alias. GB and GB_T need etapp, Ap and c.

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgnk.so")
-SOURCES = ["cauchy.hip", "circulant.hip", "geom.hip", "solver.hip"]
+SOURCES = ["cauchy.hip", "circulant.hip", "geom.hip", "solver.hip", "tree.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -38,71 +38,7 @@ namespace gnk {
 
 namespace {
 
-template <int NR, int TPT>
-struct Acc {
-  double x[TPT][NR];
-  double y[TPT][NR];
-};
-
-// acc[t] += w * q for NR columns, q = conj(d)/|d|^2 = (qx, qy)
-template <int NR, int TPT, class P>
-__device__ __forceinline__ void accumulate(Acc<NR, TPT>& a, int t, P wj, double qx, double qy) {
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const double2 w = wj[r];
-    a.x[t][r] = __builtin_fma(w.x, qx, a.x[t][r]);
-    a.x[t][r] = __builtin_fma(-w.y, qy, a.x[t][r]);
-    a.y[t][r] = __builtin_fma(w.x, qy, a.y[t][r]);
-    a.y[t][r] = __builtin_fma(w.y, qx, a.y[t][r]);
-  }
-}
-
-// two sources a, b (records ra, rb) against every target of the lane
-// ra, rb: source records (eta at [0]); the launch's weight columns start at [wo]
-template <int NR, int TPT, class P>
-__device__ __forceinline__ void pair_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], P ra, P rb, int wo) {
-  const double2 ea = ra[0], eb = rb[0];
-#pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    const double dxa = tg[t].x - ea.x, dya = tg[t].y - ea.y;
-    const double dxb = tg[t].x - eb.x, dyb = tg[t].y - eb.y;
-    const double da = __builtin_fma(dya, dya, dxa * dxa);
-    const double db = __builtin_fma(dyb, dyb, dxb * dxb);
-    const double R = refine_rcp(da * db);
-    const double qa = db * R, qb = da * R;
-    accumulate<NR, TPT>(acc, t, ra + wo, dxa * qa, -dya * qa);
-    accumulate<NR, TPT>(acc, t, rb + wo, dxb * qb, -dyb * qb);
-  }
-}
-
-// four sources a..d against every target of the lane, one reciprocal for all
-// four: with R = 1/(|da|^2 |db|^2 |dc|^2 |dd|^2), 1/|da|^2 = R |db|^2 (|dc|^2 |dd|^2)
-// and so on (the product stays in range while every distance lies in
-// [1e-38, 1e38])
-template <int NR, int TPT, class P>
-__device__ __forceinline__ void quad_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], P ra, P rb, P rc, P rd,
-                                          int wo) {
-  const double2 ea = ra[0], eb = rb[0], ec = rc[0], ed = rd[0];
-#pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    const double dxa = tg[t].x - ea.x, dya = tg[t].y - ea.y;
-    const double dxb = tg[t].x - eb.x, dyb = tg[t].y - eb.y;
-    const double dxc = tg[t].x - ec.x, dyc = tg[t].y - ec.y;
-    const double dxd = tg[t].x - ed.x, dyd = tg[t].y - ed.y;
-    const double da = __builtin_fma(dya, dya, dxa * dxa);
-    const double db = __builtin_fma(dyb, dyb, dxb * dxb);
-    const double dc = __builtin_fma(dyc, dyc, dxc * dxc);
-    const double dd = __builtin_fma(dyd, dyd, dxd * dxd);
-    const double ab = da * db, cd = dc * dd;
-    const double R = refine_rcp(ab * cd);
-    const double Rab = R * cd, Rcd = R * ab;
-    const double qa = db * Rab, qb = da * Rab, qc = dd * Rcd, qd = dc * Rcd;
-    accumulate<NR, TPT>(acc, t, ra + wo, dxa * qa, -dya * qa);
-    accumulate<NR, TPT>(acc, t, rb + wo, dxb * qb, -dyb * qb);
-    accumulate<NR, TPT>(acc, t, rc + wo, dxc * qc, -dyc * qc);
-    accumulate<NR, TPT>(acc, t, rd + wo, dxd * qd, -dyd * qd);
-  }
-}
+#include "pair_steps.inl"
 
 // Far source tiles in FP64, one column. With z' = z_i - c and
 // eta'_j = eta_j - c (c the source tile's centre) and m = 1/|z' - eta'_j|^2,
@@ -160,18 +96,6 @@ __device__ __forceinline__ void single_step_far(AccAB<NR, TPT>& acc, const doubl
     accumulate_ab<NR, TPT>(acc, t, r, wo, wb, refine_rcp(far_dist2(r, zx[t], zy[t], zz[t])));
 }
 
-template <int NR, int TPT, class P>
-__device__ __forceinline__ void single_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], const int (&ti)[TPT], P rj,
-                                            int wo, int j, bool masked) {
-  const double2 e = rj[0];
-#pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    const double dx = tg[t].x - e.x, dy = tg[t].y - e.y;
-    double r = refine_rcp(__builtin_fma(dy, dy, dx * dx));
-    if (masked) r = (j == ti[t]) ? 0.0 : r;
-    accumulate<NR, TPT>(acc, t, rj + wo, dx * r, -dy * r);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Mixed precision: well-separated source tiles in FP32, the rest in FP64.

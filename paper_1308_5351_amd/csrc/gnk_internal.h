@@ -87,6 +87,21 @@ int pairs_blocks_per_cu(int width, int tpt, bool mixed);
 // which: 0 source tiles (sb), 1 target tiles (tb), 2 far-form source tiles (sbf),
 // 3 target tiles of the separate targets tz (tb)
 hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, int which, hipStream_t st);
+// Treecode (csrc/tree.hip): boxes of kLeaf << l consecutive nodes at level l
+constexpr int kLeaf = 256;
+constexpr int kTreeMaxP = 48;
+// bounding circles of the boxes of `tile` nodes of eta (N nodes) into out
+hipError_t launch_box_bounds(const double2* eta, int N, int tile, double4* out, hipStream_t st);
+// multipole moments (p per box) of record weight field wo: leaves directly,
+// then every level from its children; level_off/level_nb: host arrays
+hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, const double4* bounds,
+                               const int* level_off, const int* level_nb, int levels, int p, double2* mom,
+                               hipStream_t st);
+// far boxes by their moments, near 64-node blocks directly, for weight column
+// col of doms[0]; seg: per target tile, 4 splits + 1 bounds into list
+hipError_t launch_tree_eval(const DomDev* doms, int tiles, int tpt, const int* seg, const int* list,
+                            const double4* bounds, const double2* mom, int p, int splits, int col, int wcols,
+                            const int* active, int lead, hipStream_t st);
 // FP32 records from the FP64 records of every domain
 hipError_t launch_records32(const DomDev* doms, int ndom, int maxN, int lead, int data, hipStream_t st);
 

@@ -217,6 +217,17 @@ struct Batch {
   };
   std::vector<Circ> circ;
   bool circ_built = false;
+  // treecode far field (one domain, FP64), see build_tree
+  struct Tree {
+    bool on = false;
+    int p = 0, levels = 0, nbox = 0, splits = 0, tiles = 0;
+    std::vector<int> off, nb;
+    double4* bounds = nullptr;
+    double2* mom = nullptr;
+    int* seg = nullptr;
+    int* list = nullptr;
+    size_t list_len = 0;
+  } tree;
 };
 
 void check_domain(gnk_ctx* c, const gnk_domain* d, bool adjoint, bool second = false) {
@@ -467,8 +478,140 @@ hipEvent_t pool_event(gnk_ctx* c) {
   return e;
 }
 
+// ----------------------------------------------------------------- treecode
+// Far-field compression for one domain (the treecode of csrc/tree.hip): box
+// bounds on the device, then on the host one depth-first pass per target
+// tile over the box hierarchy: a box whose bounding circle is separated from
+// the tile's by (1 + theta)(r_t + r_b) is far (its expansion), a leaf that is
+// not is near (its four 64-node blocks, summed directly); each tile's list is
+// cut into 4 splits ranges of about equal estimated cost (far box 4p + 24,
+// near source 13 per target, the tile's own window 16). theta = 1.5 bounds
+// r_b/|z - c_b| by 0.4, so p = log(far_tol)/log(0.4) terms meet far_tol.
+constexpr double kTreeTheta = 1.5;
+
+int tree_terms(double far_tol) {
+  const double rho = 1.0 / (1.0 + kTreeTheta);
+  const int p = (int)std::ceil(std::log(far_tol) / std::log(rho));
+  return std::max(4, std::min(kTreeMaxP, p));
+}
+
+void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
+  if (B.ndom != 1 || B.mixed) {
+    set_err(c, "the treecode takes one domain in FP64");
+    throw Fail{GNK_ERR_ARG};
+  }
+  DomDev& D = B.dom[0];
+  auto& T = B.tree;
+  const int N = D.N, tpt = B.shape.tpt, kt = 64 * tpt;
+  T = Batch::Tree{};
+  T.p = tree_terms(far_tol);
+  int total = 0;
+  for (int nb = (N + kLeaf - 1) / kLeaf;; nb = (nb + 1) / 2) {
+    T.off.push_back(total);
+    T.nb.push_back(nb);
+    total += nb;
+    if (nb == 1) break;
+  }
+  T.levels = (int)T.nb.size();
+  T.nbox = total;
+  T.bounds = ws<double4>(c, "t_bounds", total);
+  T.mom = ws<double2>(c, "t_mom", (size_t)total * T.p);
+  for (int l = 0; l < T.levels; ++l)
+    HIPCHK(c, launch_box_bounds(D.eta, N, (int)std::min<int64_t>((int64_t)kLeaf << l, (int64_t)1 << 30),
+                                T.bounds + T.off[l], c->stream));
+  T.tiles = (N + kt - 1) / kt;
+  std::vector<double4> hb(total), ht(T.tiles);
+  HIPCHK(c, hipMemcpyAsync(hb.data(), T.bounds, sizeof(double4) * total, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(ht.data(), D.tb, sizeof(double4) * T.tiles, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // about two rounds of resident workgroups
+  const int64_t resident = (int64_t)c->num_cu * 5;
+  int S = (int)std::max<int64_t>(1, std::min<int64_t>(16, (2 * resident + T.tiles - 1) / T.tiles));
+  if (const char* e = getenv("GNK_TREE_SPLITS")) S = std::max(1, atoi(e));
+  T.splits = S;
+  const double f2 = (1.0 + kTreeTheta) * (1.0 + kTreeTheta);
+  const double cfar = 4.0 * T.p + 24.0, cnear = 13.0, cself = 16.0;
+  std::vector<int> list, seg((size_t)T.tiles * (4 * S + 1));
+  std::vector<int> ent;
+  std::vector<double> cost;
+  std::vector<std::pair<int, int>> stack;
+  for (int t = 0; t < T.tiles; ++t) {
+    ent.clear();
+    cost.clear();
+    const double4 tt = ht[t];
+    const int base = t * kt, top = T.levels - 1;
+    for (int b = 0; b < T.nb[top]; ++b) stack.push_back({top, b});
+    while (!stack.empty()) {
+      const auto [l, b] = stack.back();
+      stack.pop_back();
+      const double4 bb = hb[T.off[l] + b];
+      const double dx = tt.x - bb.x, dy = tt.y - bb.y, rr = tt.z + bb.z;
+      if (dx * dx + dy * dy > f2 * rr * rr) {
+        ent.push_back(T.off[l] + b);
+        cost.push_back(cfar);
+      } else if (l == 0) {
+        for (int k = 0; k < kLeaf / 64; ++k) {
+          const int j0 = b * kLeaf + k * 64;
+          if (j0 >= N) break;
+          const int j1 = std::min(N, j0 + 64);
+          const int ov = std::max(0, std::min(j1, base + kt) - std::max(j0, base));
+          ent.push_back(~(j0 / 64));
+          cost.push_back(cnear * (j1 - j0 - ov) + cself * ov);
+        }
+      } else {
+        // children pushed in reverse so that the list keeps node order
+        if (2 * b + 1 < T.nb[l - 1]) stack.push_back({l - 1, 2 * b + 1});
+        stack.push_back({l - 1, 2 * b});
+      }
+    }
+    double tot = 0.0;
+    for (double x : cost) tot += x;
+    int* sg = seg.data() + (size_t)t * (4 * S + 1);
+    const int start = (int)list.size();
+    sg[0] = start;
+    double acc = 0.0;
+    size_t e = 0;
+    for (int k = 1; k < 4 * S; ++k) {
+      const double target = tot * k / (4.0 * S);
+      while (e < ent.size() && acc + 0.5 * cost[e] < target) acc += cost[e++];
+      sg[k] = start + (int)e;
+    }
+    sg[4 * S] = start + (int)ent.size();
+    list.insert(list.end(), ent.begin(), ent.end());
+    if (list.size() > (size_t)INT32_MAX / 2) {
+      set_err(c, "treecode interaction lists too long");
+      throw Fail{GNK_ERR_OOM};
+    }
+  }
+  T.list_len = list.size();
+  T.list = upload(c, "t_list", list);
+  T.seg = upload(c, "t_seg", seg);
+  D.splits = S;
+  D.chunk = N;
+  D.parts = ws<double2>(c, "t_parts", (size_t)S * (D.ncols + 1) * N);
+  B.d_dom = upload(c, "b_dom", B.dom);
+  T.on = true;
+}
+
+// the Cauchy sums of one pattern by the treecode, one weight column at a time
+void tree_pairs(gnk_ctx* c, Batch& B, int p, const int* active) {
+  auto& T = B.tree;
+  const DomDev& D = B.dom[0];
+  const int lead = kLead[p], wcols = lead + kData[p] * D.ncols;
+  for (int col = 0; col < wcols; ++col) {
+    HIPCHK(c, launch_tree_moments(D.rec, rec_stride(wcols), kRecHead + col, D.N, T.bounds, T.off.data(),
+                                  T.nb.data(), T.levels, T.p, T.mom, c->stream));
+    HIPCHK(c, launch_tree_eval(B.d_dom, T.tiles, B.shape.tpt, T.seg, T.list, T.bounds, T.mom, T.p, T.splits, col,
+                               wcols, active, lead, c->stream));
+  }
+}
+
 // All Cauchy sums of a pattern for the batch (one launch per column-group width).
 void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
+  if (B.tree.on && !mixed) {
+    tree_pairs(c, B, p, active);
+    return;
+  }
   if (mixed && p == P_GM) p = P_GM_MIXED;
   build_items(c, B, p);
   auto& S = B.sets[p];
@@ -925,9 +1068,11 @@ gnk_opts resolve_opts(gnk_ctx* c, const gnk_opts* o) {
   r.x0 = nullptr;
   if (o) r = *o;
   if (r.restart < 1 || r.restart > kMaxRestart || r.maxit < 1 || !(r.tol > 0.0) || r.tol >= 1.0 ||
-      (r.prec != GNK_FP64 && r.prec != GNK_MIXED) || (r.no_subtraction != 0 && r.no_subtraction != 1)) {
-    set_err(c, "bad options: restart %d (1..%d), maxit %d (>=1), tol %g (0..1), prec %d", r.restart, kMaxRestart,
-            r.maxit, r.tol, r.prec);
+      (r.prec != GNK_FP64 && r.prec != GNK_MIXED) || (r.no_subtraction != 0 && r.no_subtraction != 1) ||
+      !(r.far_tol >= 0.0) || (r.far_tol > 0.0 && (r.far_tol < 1e-15 || r.far_tol > 0.1 || r.prec != GNK_FP64))) {
+    set_err(c, "bad options: restart %d (1..%d), maxit %d (>=1), tol %g (0..1), prec %d, no_subtraction %d, "
+            "far_tol %g (0, or 1e-15..0.1 with GNK_FP64)", r.restart, kMaxRestart, r.maxit, r.tol, r.prec,
+            r.no_subtraction, r.far_tol);
     throw Fail{GNK_ERR_ARG};
   }
   // mixed products once the residual estimate is below tol / 1e-8 (their
@@ -1356,6 +1501,32 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
   });
 }
 
+gnk_status gnk_cauchy_sum_tree(gnk_ctx* c, int64_t N, const void* eta, const void* w, int nrhs, double far_tol,
+                               void* S) {
+  return guarded(c, [&]() -> gnk_status {
+    if (N < 1 || N > ((int64_t)1 << 30) || nrhs < 1 || !eta || !w || !S || w == S || !(far_tol >= 1e-15) ||
+        far_tol > 0.1) {
+      set_err(c, "bad arguments to gnk_cauchy_sum_tree");
+      throw Fail{GNK_ERR_ARG};
+    }
+    gnk_domain d{};
+    d.m1 = 1;
+    d.n = N + (N & 1);
+    d.eta = d.etap = d.A = eta;
+    Batch B;
+    std::vector<int64_t> off{0};
+    build_batch(c, B, 1, &d, &nrhs, off, N * (int64_t)nrhs, false, false, PairShape{}, N);
+    build_tree(c, B, far_tol);
+    k_pack_records<<<nblocks(N), kT, 0, c->stream>>>(B.d_dom, static_cast<const double2*>(w), nrhs);
+    LAUNCHCHK(c);
+    pairs(c, B, P_GM, false, nullptr);
+    k_reduce_parts<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(B.d_dom, static_cast<double2*>(S));
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GNK_OK;
+  });
+}
+
 gnk_status gnk_fcau(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const void* etap, const void* f, int nrhs,
                     const void* z, int64_t nz, const void* finf, void* fz) {
   return guarded(c, [&]() -> gnk_status {
@@ -1437,6 +1608,7 @@ gnk_status gnk_fbie(gnk_ctx* c, const gnk_domain* d, const double* gam, int nrhs
     gnk_opts o = resolve_opts(c, opts);
     Batch B;
     single_batch(c, B, d, nrhs, false, o.prec == GNK_MIXED, o.no_subtraction != 0);
+    if (o.far_tol > 0.0) build_tree(c, B, o.far_tol);
     GmresOut g = fbie_batch(c, B, gam, o, mu, h);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (info)
@@ -1455,6 +1627,7 @@ gnk_status gnk_fbie_ad(gnk_ctx* c, const gnk_domain* d, const double* gam, int n
     gnk_opts o = resolve_opts(c, opts);
     Batch B;
     single_batch(c, B, d, nrhs, true, o.prec == GNK_MIXED);
+    if (o.far_tol > 0.0) build_tree(c, B, o.far_tol);
     GmresOut g = fbiead_batch(c, B, gam, o, mu);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (info)
@@ -1471,8 +1644,8 @@ gnk_status gnk_fbie_batched(gnk_ctx* c, int ndom, const gnk_domain* doms, const 
       throw Fail{GNK_ERR_ARG};
     }
     gnk_opts o = resolve_opts(c, opts);
-    if (o.no_subtraction) {
-      set_err(c, "no_subtraction is available for gnk_fbie and gnk_fbie_ad only");
+    if (o.no_subtraction || o.far_tol > 0.0) {
+      set_err(c, "no_subtraction and far_tol are available for gnk_fbie and gnk_fbie_ad only");
       throw Fail{GNK_ERR_ARG};
     }
     if (o.x0) {
@@ -1525,8 +1698,8 @@ gnk_status gnk_fbie_adjoint(gnk_ctx* c, const gnk_domain* d, const double* g_mu,
       throw Fail{GNK_ERR_ARG};
     }
     gnk_opts o = resolve_opts(c, opts);
-    if (o.no_subtraction) {
-      set_err(c, "no_subtraction is available for gnk_fbie and gnk_fbie_ad only");
+    if (o.no_subtraction || o.far_tol > 0.0) {
+      set_err(c, "no_subtraction and far_tol are available for gnk_fbie and gnk_fbie_ad only");
       throw Fail{GNK_ERR_ARG};
     }
     Batch B;

@@ -1,0 +1,280 @@
+// Far-field compression of the Cauchy sums S_i = sum_{j != i} w_j/(eta_i - eta_j)
+// for large N (the paper evaluates these sums with a fast multipole method;
+// this is a treecode on the GPU, FP64 throughout):
+//   * boxes: level 0 holds the leaves of kLeaf = 256 consecutive nodes (the
+//     node order follows the boundary curves, so a range of nodes is compact),
+//     level l + 1 pairs the boxes of level l; each box has a bounding circle;
+//   * multipole moments of box b about its centre c_b, for one weight column:
+//     a_k = sum_{j in b} w_j (eta_j - c_b)^k, k < p; leaves from their nodes,
+//     parents from their children by the binomial shift;
+//   * a far box contributes sum_{k<p} a_k u^{k+1}, u = 1/(z - c_b), to a
+//     target z: the expansion of 1/(z - eta_j) in powers of (eta_j - c_b)/(z - c_b),
+//     truncated with error below (r_b/|z - c_b|)^p times sum |w_j|/(|z - c_b| - r_b);
+//   * every other source is summed directly, in blocks of 64 nodes, by the
+//     FP64 pair loops (j != i excluded);
+//   * the interaction lists (far boxes and near blocks per target tile) come
+//     from the host; each (target tile, split) workgroup takes four
+//     cost-balanced ranges of its tile's list, one per wavefront, and writes
+//     one partial sum, which the consumer adds in split order like those of
+//     the direct kernels.
+#include <algorithm>
+#include <cmath>
+
+#include "gnk_device.h"
+#include "gnk_internal.h"
+
+namespace gnk {
+
+namespace {
+
+#include "pair_steps.inl"
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// bounding circle {cx, cy, r, 0} (centre of the bounding box) of the nodes
+// [b tile, (b + 1) tile) of eta; one wavefront per box
+__global__ __launch_bounds__(64) void k_box_bounds(const double2* __restrict__ eta, int N, int tile,
+                                                   double4* __restrict__ out) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int i0 = b * tile;
+  if (i0 >= N) return;
+  const int i1 = min(N, i0 + tile);
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+  for (int i = i0 + lane; i < i1; i += 64) {
+    const double2 e = eta[i];
+    xmin = fmin(xmin, e.x);
+    xmax = fmax(xmax, e.x);
+    ymin = fmin(ymin, e.y);
+    ymax = fmax(ymax, e.y);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    xmin = fmin(xmin, __shfl_xor(xmin, off, 64));
+    xmax = fmax(xmax, __shfl_xor(xmax, off, 64));
+    ymin = fmin(ymin, __shfl_xor(ymin, off, 64));
+    ymax = fmax(ymax, __shfl_xor(ymax, off, 64));
+  }
+  const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax);
+  double r = 0.0;
+  for (int i = i0 + lane; i < i1; i += 64) {
+    const double2 e = eta[i];
+    r = fmax(r, sqrt((e.x - cx) * (e.x - cx) + (e.y - cy) * (e.y - cy)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
+  if (lane == 0) out[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
+}
+
+// Leaf moments of weight column wo (record field) about the leaf centres:
+// one wavefront per leaf, each lane holding up to four nodes; moment k is
+// the wave sum of w_j (eta_j - c)^k, the powers advanced one k at a time.
+__global__ __launch_bounds__(64) void k_leaf_moments(const double2* __restrict__ rec, int stride, int wo, int N,
+                                                     const double4* __restrict__ bounds, int p,
+                                                     double2* __restrict__ mom) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const double4 c = bounds[b];
+  double dx[kLeaf / 64], dy[kLeaf / 64], tx[kLeaf / 64], ty[kLeaf / 64];
+#pragma unroll
+  for (int m = 0; m < kLeaf / 64; ++m) {
+    const int j = b * kLeaf + m * 64 + lane;
+    if (j < N) {
+      const double2 e = rec[(size_t)j * stride], w = rec[(size_t)j * stride + wo];
+      dx[m] = e.x - c.x;
+      dy[m] = e.y - c.y;
+      tx[m] = w.x;
+      ty[m] = w.y;
+    } else {
+      dx[m] = dy[m] = tx[m] = ty[m] = 0.0;
+    }
+  }
+  for (int k = 0; k < p; ++k) {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int m = 0; m < kLeaf / 64; ++m) {
+      sx += tx[m];
+      sy += ty[m];
+      const double nx = tx[m] * dx[m] - ty[m] * dy[m];
+      ty[m] = tx[m] * dy[m] + ty[m] * dx[m];
+      tx[m] = nx;
+    }
+    sx = wave_sum64(sx);
+    sy = wave_sum64(sy);
+    if (lane == 0) mom[(size_t)b * p + k] = make_double2(sx, sy);
+  }
+}
+
+// Moments of the parents (level l + 1, boxes par0 .. par0 + npar - 1 of the
+// global numbering) from their children (level l, from child0, nchild of
+// them): a_k(parent) = sum over children sum_{q <= k} C(k, q) a_q(child) d^(k-q),
+// d = c_child - c_parent. One thread per (parent, k).
+__global__ void k_m2m(const double4* __restrict__ bounds, int child0, int nchild, int par0, int npar, int p,
+                      double2* __restrict__ mom) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= npar * p) return;
+  const int b = tid / p, k = tid - b * p;
+  const double4 cp = bounds[par0 + b];
+  double ax = 0.0, ay = 0.0;
+  for (int ch = 2 * b; ch < min(2 * b + 2, nchild); ++ch) {
+    const double4 cc = bounds[child0 + ch];
+    const double ddx = cc.x - cp.x, ddy = cc.y - cp.y;
+    const double2* a = mom + (size_t)(child0 + ch) * p;
+    // sum over q = k down to 0 of C(k, q) a_q d^(k - q)
+    double px = 1.0, py = 0.0, binom = 1.0;
+    for (int q = k; q >= 0; --q) {
+      const double2 aq = a[q];
+      const double tx = aq.x * px - aq.y * py, ty = aq.x * py + aq.y * px;
+      ax = __builtin_fma(binom, tx, ax);
+      ay = __builtin_fma(binom, ty, ay);
+      const double nx = px * ddx - py * ddy;
+      py = px * ddy + py * ddx;
+      px = nx;
+      binom = binom * (double)q / (double)(k - q + 1);   // C(k, q - 1) from C(k, q)
+    }
+  }
+  mom[(size_t)(par0 + b) * p + k] = make_double2(ax, ay);
+}
+
+// One workgroup per (target tile, split): wave wv takes the entries
+// [seg[4 split + wv], seg[4 split + wv + 1]) of its tile's list. Entries >= 0
+// are far boxes (global index), entries < 0 are near blocks ~blk of 64 nodes.
+// Partial sums of weight column col go to slot split, like the direct kernels'.
+template <int TPT>
+__global__ __launch_bounds__(256) void k_tree(const DomDev* __restrict__ doms, const int* __restrict__ seg,
+                                              const int* __restrict__ list, const double4* __restrict__ bounds,
+                                              const double2* __restrict__ mom, int p, int splits, int col, int wcols,
+                                              const int* __restrict__ active, int lead) {
+  __shared__ double red[3][TPT][2][64];
+  constexpr int kTile = 64 * TPT;
+  const DomDev& D = doms[0];
+  if (active != nullptr && col >= lead && active[D.c0 + col - lead] == 0) return;
+  const int N = D.N;
+  const int tile = blockIdx.x / splits, g = blockIdx.x - tile * splits;
+  const int base = tile * kTile;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int stride = rec_stride(wcols);
+  const int wo = kRecHead + col;
+  const gptr<const double2> rec = (gptr<const double2>)D.rec;
+  const gptr<const int> sg = (gptr<const int>)seg + (size_t)tile * (4 * splits + 1) + 4 * g + wv;
+  const int e0 = __builtin_amdgcn_readfirstlane(sg[0]);
+  const int e1 = __builtin_amdgcn_readfirstlane(sg[1]);
+
+  double2 tg[TPT];
+  int ti[TPT];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    ti[t] = base + t * 64 + lane;
+    tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
+  }
+  Acc<1, TPT> acc;
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) acc.x[t][0] = acc.y[t][0] = 0.0;
+
+  auto plain = [&](int ja, int jb) {
+    int j = ja;
+    for (; j + 3 < jb; j += 4) {
+      gptr<const double2> r = rec + (size_t)j * stride;
+      quad_step<1, TPT>(acc, tg, r, r + stride, r + 2 * stride, r + 3 * stride, wo);
+    }
+    for (; j + 1 < jb; j += 2) {
+      gptr<const double2> r = rec + (size_t)j * stride;
+      pair_step<1, TPT>(acc, tg, r, r + stride, wo);
+    }
+    if (j < jb) single_step<1, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, false);
+  };
+
+  const gptr<const int> ls = (gptr<const int>)list;
+  const gptr<const double4> bd = (gptr<const double4>)bounds;
+  const gptr<const double2> mm = (gptr<const double2>)mom;
+  for (int e = e0; e < e1; ++e) {
+    const int ent = ls[e];
+    if (ent >= 0) {
+      const double4 c = bd[ent];
+      const gptr<const double2> a = mm + (size_t)ent * p;
+#pragma unroll
+      for (int t = 0; t < TPT; ++t) {
+        const double dx = tg[t].x - c.x, dy = tg[t].y - c.y;
+        const double inv = refine_rcp(__builtin_fma(dy, dy, dx * dx));
+        const double ux = dx * inv, uy = -dy * inv;
+        double sx = 0.0, sy = 0.0;
+        for (int k = p - 1; k >= 0; --k) {
+          const double2 ak = a[k];
+          const double nx = __builtin_fma(ux, sx, __builtin_fma(-uy, sy, ak.x));
+          sy = __builtin_fma(ux, sy, __builtin_fma(uy, sx, ak.y));
+          sx = nx;
+        }
+        acc.x[t][0] += ux * sx - uy * sy;
+        acc.y[t][0] += ux * sy + uy * sx;
+      }
+    } else {
+      const int ja = (~ent) * 64, jb = min(N, ja + 64);
+      plain(ja, min(jb, base));
+      const int ma = max(ja, base), mb = min(jb, base + kTile);
+      for (int j = ma; j < mb; ++j) single_step<1, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
+      plain(max(ja, base + kTile), jb);
+    }
+  }
+
+  // fixed-order reduction over the four wavefronts
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+      red[wv - 1][t][0][lane] = acc.x[t][0];
+      red[wv - 1][t][1][lane] = acc.y[t][0];
+    }
+  }
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+      double x = acc.x[t][0], y = acc.y[t][0];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        x += red[q][t][0][lane];
+        y += red[q][t][1][lane];
+      }
+      if (ti[t] < N) D.parts[((size_t)g * wcols + col) * N + ti[t]] = make_double2(x, y);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_box_bounds(const double2* eta, int N, int tile, double4* out, hipStream_t st) {
+  const int nb = (N + tile - 1) / tile;
+  k_box_bounds<<<nb, 64, 0, st>>>(eta, N, tile, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, const double4* bounds,
+                               const int* level_off, const int* level_nb, int levels, int p, double2* mom,
+                               hipStream_t st) {
+  k_leaf_moments<<<level_nb[0], 64, 0, st>>>(rec, stride, wo, N, bounds, p, mom);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int l = 0; l + 1 < levels; ++l) {
+    const int npar = level_nb[l + 1];
+    const int threads = npar * p;
+    k_m2m<<<(threads + 255) / 256, 256, 0, st>>>(bounds, level_off[l], level_nb[l], level_off[l + 1], npar, p, mom);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_tree_eval(const DomDev* doms, int tiles, int tpt, const int* seg, const int* list,
+                            const double4* bounds, const double2* mom, int p, int splits, int col, int wcols,
+                            const int* active, int lead, hipStream_t st) {
+  const unsigned grid = (unsigned)tiles * (unsigned)splits;
+  if (tpt == 2)
+    k_tree<2><<<grid, 256, 0, st>>>(doms, seg, list, bounds, mom, p, splits, col, wcols, active, lead);
+  else
+    k_tree<1><<<grid, 256, 0, st>>>(doms, seg, list, bounds, mom, p, splits, col, wcols, active, lead);
+  return hipGetLastError();
+}
+
+}  // namespace gnk

@@ -25,7 +25,7 @@ OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT, OP_FB_U, OP_GB_U = rang
 EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
             "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad",
             "gnk_fbie_batched", "gnk_fbie_adjoint", "gnk_geom_vjp", "gnk_fourier_curve", "gnk_fourier_vjp",
-            "gnk_fcau")
+            "gnk_fcau", "gnk_cauchy_sum_tree")
 
 
 class GnkError(RuntimeError):
@@ -42,7 +42,7 @@ class _Domain(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double), ("prec", C.c_int),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int), ("x0", C.c_void_p),
-                ("no_subtraction", C.c_int)]
+                ("no_subtraction", C.c_int), ("far_tol", C.c_double)]
 
 
 class Info(C.Structure):
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     lib.gnk_fourier_curve.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P]
     lib.gnk_fourier_vjp.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P]
     lib.gnk_fcau.argtypes = [P, C.c_int64, C.c_int64, P, P, P, C.c_int, P, C.c_int64, P, P]
+    lib.gnk_cauchy_sum_tree.argtypes = [P, C.c_int64, P, P, C.c_int, C.c_double, P]
     for f in EXPORTED:
         if f not in ("gnk_last_error", "gnk_version"):
             getattr(lib, f).restype = C.c_int
@@ -193,13 +194,19 @@ class Context:
         self._raise(self.lib.gnk_profile_read(self.h, C.byref(p), 1 if reset else 0), False)
         return p.as_dict()
 
-    def cauchy_sum(self, eta: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
-        """S = E w, S_i = sum_{j != i} w_j / (eta_i - eta_j); w: (N,) or (N, nrhs) complex128."""
+    def cauchy_sum(self, eta: torch.Tensor, w: torch.Tensor, far_tol: float = 0.0) -> torch.Tensor:
+        """S = E w, S_i = sum_{j != i} w_j / (eta_i - eta_j); w: (N,) or (N, nrhs) complex128.
+        far_tol > 0: the far field from the treecode's expansions (gnk_cauchy_sum_tree)."""
         self._bind_stream()
         N = eta.shape[0]
         one = w.dim() == 1
         wc = (w.unsqueeze(1) if one else w).t().contiguous()
         S = torch.empty_like(wc)
+        if far_tol > 0:
+            st = self.lib.gnk_cauchy_sum_tree(self.h, N, eta.data_ptr(), wc.data_ptr(), wc.shape[0], far_tol,
+                                              S.data_ptr())
+            self._raise(st, False)
+            return _from_cols(S, one)
         st = self.lib.gnk_cauchy_sum(self.h, N, eta.data_ptr(), wc.data_ptr(), wc.shape[0], S.data_ptr())
         self._raise(st, False)
         return _from_cols(S, one)
@@ -244,12 +251,12 @@ class Context:
         return _from_cols(y, one)
 
     @staticmethod
-    def _opts(restart, maxit, tol, prec, inner_tol, max_refine, x0, subtract=True):
+    def _opts(restart, maxit, tol, prec, inner_tol, max_refine, x0, subtract=True, far_tol=0.0):
         return _Opts(restart, maxit, tol, prec, inner_tol, max_refine, None if x0 is None else x0.data_ptr(),
-                     0 if subtract else 1)
+                     0 if subtract else 1, far_tol)
 
     def fbie(self, dom: DeviceDomain, gam: torch.Tensor, restart=25, maxit=40, tol=1e-12, prec=FP64,
-             inner_tol=0.0, max_refine=0, x0=None, want_h=True, subtract=True):
+             inner_tol=0.0, max_refine=0, x0=None, want_h=True, subtract=True, far_tol=0.0):
         """Solve (I - N) mu = -M gamma and h = [M mu - (I - N) gamma]/2. Returns (mu, h, infos, status).
         subtract=False: without singularity subtraction (Example 2's comparison; needs etapp, Ap)."""
         self._bind_stream()
@@ -258,7 +265,7 @@ class Context:
         mu = torch.empty_like(g)
         h = torch.empty_like(g) if want_h else None
         x0c = None if x0 is None else _check_real(x0, dom.N, "x0")[0]
-        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract)
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract, far_tol)
         infos = (Info * nrhs)()
         d = dom._struct()
         st = self.lib.gnk_fbie(self.h, C.byref(d), g.data_ptr(), nrhs, C.byref(o), mu.data_ptr(),
@@ -268,7 +275,7 @@ class Context:
                 [i.as_dict() for i in infos], st)
 
     def fbie_ad(self, dom: DeviceDomain, gam: torch.Tensor, restart=25, maxit=40, tol=1e-12, prec=FP64,
-                inner_tol=0.0, max_refine=0, x0=None, subtract=True):
+                inner_tol=0.0, max_refine=0, x0=None, subtract=True, far_tol=0.0):
         """Solve (I + N* + J) mu = gamma. Returns (mu, infos, status).
         subtract=False: without singularity subtraction (Example 2's comparison)."""
         self._bind_stream()
@@ -276,7 +283,7 @@ class Context:
         g, nrhs = _check_real(gam, dom.N, "gam")
         mu = torch.empty_like(g)
         x0c = None if x0 is None else _check_real(x0, dom.N, "x0")[0]
-        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract)
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract, far_tol)
         infos = (Info * nrhs)()
         d = dom._struct()
         st = self.lib.gnk_fbie_ad(self.h, C.byref(d), g.data_ptr(), nrhs, C.byref(o), mu.data_ptr(), infos)
