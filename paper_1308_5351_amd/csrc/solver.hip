@@ -598,11 +598,23 @@ void tree_pairs(gnk_ctx* c, Batch& B, int p, const int* active) {
   auto& T = B.tree;
   const DomDev& D = B.dom[0];
   const int lead = kLead[p], wcols = lead + kData[p] * D.ncols;
+  gnk_ctx::ProfRec pr{};
+  if (c->prof) {
+    // counted as the pairs the direct sum would take
+    const double pairs = (double)D.N * (double)(D.N - 1);
+    pr = gnk_ctx::ProfRec{pool_event(c), pool_event(c), pairs * wcols, pairs * (16.0 + 8.0 * (wcols - 1)),
+                          wcols == 1 ? pairs : 0.0, false, wcols == 1};
+    HIPCHK(c, hipEventRecord(pr.a, c->stream));
+  }
   for (int col = 0; col < wcols; ++col) {
     HIPCHK(c, launch_tree_moments(D.rec, rec_stride(wcols), kRecHead + col, D.N, T.bounds, T.off.data(),
                                   T.nb.data(), T.levels, T.p, T.mom, c->stream));
     HIPCHK(c, launch_tree_eval(B.d_dom, T.tiles, B.shape.tpt, T.seg, T.list, T.bounds, T.mom, T.p, T.splits, col,
                                wcols, active, lead, c->stream));
+  }
+  if (c->prof) {
+    HIPCHK(c, hipEventRecord(pr.b, c->stream));
+    c->prof_pending.push_back(pr);
   }
 }
 
