@@ -223,6 +223,25 @@ GNK_API gnk_status gnk_cauchy_sum(gnk_ctx* ctx, int64_t N, const void* eta, cons
 GNK_API gnk_status gnk_fcau(gnk_ctx* ctx, int64_t m1, int64_t n, const void* eta, const void* etap,
                             const void* f, int nrhs, const void* z, int64_t nz, const void* finf, void* fz);
 
+/* Conformal map of a bounded (m+1)-connected domain onto the unit disc with
+ * m circular slits (Example 3, theta = pi/2), from one FBIE solve: with
+ * A = eta - alpha and gamma = -log|eta - alpha| (alpha in G), the boundary
+ * values are f(eta) = exp(-h_0) (eta - alpha) exp(gamma + h + i mu) and the
+ * slit radii R_j = exp(h_j - h_0) (h_j the mean of FBIE's h over component j;
+ * R_0 = 1), so f(alpha) = 0 and f'(alpha) > 0.
+ *   eta, etap : N complex (device), component-major, outer boundary first (ccw),
+ *               inner boundaries clockwise
+ *   alpha     : host, 2 doubles {Re, Im}, a point of G
+ *   opts      : as for gnk_fbie (NULL: defaults); far_tol allowed
+ *   f         : N complex (device, output): boundary values of the map
+ *   radii     : host array of m1 doubles (output) or NULL
+ *   info      : host, one entry (the FBIE solve) or NULL
+ * Interior values follow from gnk_fcau with these boundary values.
+ * Errors: GNK_ERR_ARG for NULL or aliased pointers, sizes, no_subtraction. */
+GNK_API gnk_status gnk_circular_slit_map(gnk_ctx* ctx, int64_t m1, int64_t n, const void* eta, const void* etap,
+                                         const double* alpha, const gnk_opts* opts, void* f, double* radii,
+                                         gnk_info* info);
+
 /* gnk_cauchy_sum with the far field from the treecode (see gnk_opts.far_tol):
  * S_i = sum_{j != i} w_j / (eta_i - eta_j), near pairs summed directly, far
  * boxes by p-term expansions with (r/R)^p <= far_tol (1e-15..0.1). Same

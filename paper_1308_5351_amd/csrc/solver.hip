@@ -1513,6 +1513,54 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
   });
 }
 
+gnk_status gnk_circular_slit_map(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const void* etap,
+                                 const double* alpha, const gnk_opts* opts, void* f, double* radii, gnk_info* info) {
+  return guarded(c, [&]() -> gnk_status {
+    if (!eta || !etap || !alpha || !f || f == eta || f == etap || m1 < 1 || n < 2) {
+      set_err(c, "bad arguments to gnk_circular_slit_map");
+      throw Fail{GNK_ERR_ARG};
+    }
+    gnk_opts o = resolve_opts(c, opts);
+    if (o.no_subtraction) {
+      set_err(c, "the map takes the paper's method (no_subtraction = 0)");
+      throw Fail{GNK_ERR_ARG};
+    }
+    const int64_t N = m1 * n;
+    if (N > ((int64_t)1 << 30)) {
+      set_err(c, "N = (m+1) n = %lld exceeds 2^30", (long long)N);
+      throw Fail{GNK_ERR_ARG};
+    }
+    double2* A = ws<double2>(c, "s_A", N);
+    double* gam = ws<double>(c, "s_gam", N);
+    double* mu = ws<double>(c, "s_mu", N);
+    double* h = ws<double>(c, "s_h", N);
+    double* hbar = ws<double>(c, "s_hbar", m1);
+    k_slit_setup<<<nblocks(N), kT, 0, c->stream>>>(static_cast<const double2*>(eta), N, alpha[0], alpha[1], A, gam);
+    LAUNCHCHK(c);
+    gnk_domain d{};
+    d.m1 = m1;
+    d.n = n;
+    d.eta = eta;
+    d.etap = etap;
+    d.A = A;
+    Batch B;
+    single_batch(c, B, &d, 1, false, o.prec == GNK_MIXED);
+    if (o.far_tol > 0.0) build_tree(c, B, o.far_tol);
+    GmresOut g = fbie_batch(c, B, gam, o, mu, h);
+    k_comp_means<<<(unsigned)m1, kT, 0, c->stream>>>(h, (int)n, hbar);
+    LAUNCHCHK(c);
+    k_slit_map<<<nblocks(N), kT, 0, c->stream>>>(A, gam, mu, hbar, N, (int)n, static_cast<double2*>(f));
+    LAUNCHCHK(c);
+    std::vector<double> hb((size_t)m1);
+    HIPCHK(c, hipMemcpyAsync(hb.data(), hbar, sizeof(double) * m1, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (radii)
+      for (int64_t k = 0; k < m1; ++k) radii[k] = std::exp(hb[k] - hb[0]);
+    if (info) info[0] = g.info[0];
+    return g.all_converged ? GNK_OK : GNK_NOT_CONVERGED;
+  });
+}
+
 gnk_status gnk_cauchy_sum_tree(gnk_ctx* c, int64_t N, const void* eta, const void* w, int nrhs, double far_tol,
                                void* S) {
   return guarded(c, [&]() -> gnk_status {

@@ -255,6 +255,42 @@ __global__ void k_pack_records(const DomDev* __restrict__ doms, const double2* _
   }
 }
 
+// ---------------------------------------- conformal map onto the circular-slit disc
+// A = eta - alpha and gamma = -log|eta - alpha| of the Riemann-Hilbert problem
+// whose solution gives the map (theta = pi/2 in eq. (e:A))
+__global__ void k_slit_setup(const double2* __restrict__ eta, int64_t N, double ax, double ay,
+                             double2* __restrict__ A, double* __restrict__ gam) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double2 e = eta[i];
+  const double dx = e.x - ax, dy = e.y - ay;
+  A[i] = make_double2(dx, dy);
+  gam[i] = -0.5 * log(dx * dx + dy * dy);
+}
+
+// hbar[k] = (1/n) sum over component k of h (fixed-order block reduction)
+__global__ __launch_bounds__(kT) void k_comp_means(const double* __restrict__ h, int n, double* __restrict__ hbar) {
+  __shared__ double sh[kT / 64];
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) acc += h[(size_t)k * n + p];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) hbar[k] = t / (double)n;
+}
+
+// f(eta_i) = exp(-hbar_0) (eta_i - alpha) exp(gamma_i + hbar_k(i) + i mu_i)
+__global__ void k_slit_map(const double2* __restrict__ A, const double* __restrict__ gam,
+                           const double* __restrict__ mu, const double* __restrict__ hbar, int64_t N, int n,
+                           double2* __restrict__ f) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double mag = exp(gam[i] + hbar[i / n] - hbar[0]);
+  double s, c;
+  sincos(mu[i], &s, &c);
+  const double2 a = A[i];
+  f[i] = make_double2(mag * (a.x * c - a.y * s), mag * (a.x * s + a.y * c));
+}
+
 // ------------------------------------------ Cauchy integral at interior points
 // Records of the nodes for F[eta'] and F[f_q eta'] (Sec. 7, eqs. (e:cauchy5),
 // (e:cauchy6)): weight column 0 is eta'_j, column 1 + q is f_{j,q} eta'_j

@@ -25,7 +25,7 @@ OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT, OP_FB_U, OP_GB_U = rang
 EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
             "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad",
             "gnk_fbie_batched", "gnk_fbie_adjoint", "gnk_geom_vjp", "gnk_fourier_curve", "gnk_fourier_vjp",
-            "gnk_fcau", "gnk_cauchy_sum_tree")
+            "gnk_fcau", "gnk_cauchy_sum_tree", "gnk_circular_slit_map")
 
 
 class GnkError(RuntimeError):
@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH):
     lib.gnk_fourier_vjp.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P]
     lib.gnk_fcau.argtypes = [P, C.c_int64, C.c_int64, P, P, P, C.c_int, P, C.c_int64, P, P]
     lib.gnk_cauchy_sum_tree.argtypes = [P, C.c_int64, P, P, C.c_int, C.c_double, P]
+    lib.gnk_circular_slit_map.argtypes = [P, C.c_int64, C.c_int64, P, P, C.POINTER(C.c_double), C.POINTER(_Opts), P,
+                                          C.POINTER(C.c_double), C.POINTER(Info)]
     for f in EXPORTED:
         if f not in ("gnk_last_error", "gnk_version"):
             getattr(lib, f).restype = C.c_int
@@ -239,6 +241,26 @@ class Context:
                                zc.shape[0], None if fin is None else fin.ctypes.data, out.data_ptr())
         self._raise(st, False)
         return _from_cols(out, one)
+
+    def circular_slit_map(self, eta: torch.Tensor, etap: torch.Tensor, m1: int, n: int, alpha: complex,
+                          restart=25, maxit=40, tol=1e-12, far_tol=0.0):
+        """Boundary values f (N,) complex128 of the map of a bounded domain onto the unit disc with circular
+        slits (f(alpha) = 0, f'(alpha) > 0) and the slit radii (m1,) (R_0 = 1). Returns (f, radii, info, status)."""
+        self._bind_stream()
+        N = m1 * n
+        for name, t in (("eta", eta), ("etap", etap)):
+            if t.dtype != torch.complex128 or t.shape != (N,) or not t.is_cuda:
+                raise ValueError(f"{name} must be a complex128 CUDA tensor of shape ({N},)")
+        ec, pc = eta.contiguous(), etap.contiguous()
+        f = torch.empty(N, dtype=torch.complex128, device=eta.device)
+        al = (C.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+        radii = (C.c_double * m1)()
+        info = (Info * 1)()
+        o = self._opts(restart, maxit, tol, FP64, 0.0, 0, None, True, far_tol)
+        st = self.lib.gnk_circular_slit_map(self.h, m1, n, ec.data_ptr(), pc.data_ptr(), al, C.byref(o),
+                                            f.data_ptr(), radii, info)
+        self._raise(st)
+        return f, np.array(radii[:]), info[0].as_dict(), st
 
     def apply(self, dom: DeviceDomain, op: int, x: torch.Tensor, prec: int = FP64) -> torch.Tensor:
         self._bind_stream()
