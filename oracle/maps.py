@@ -21,6 +21,28 @@ constant with Re[A g] = gamma + h; mu = Im[A g] on the boundary):
 
 The discrete h is only approximately constant on each component; the map
 takes h_j as its mean over component j (the reading used for h_k elsewhere).
+
+The disc with circular and radial slits (Example 3, theta = (pi/2, 0, pi/2, 0,
+pi/2)) follows the same way with a piecewise constant theta, theta_0 = pi/2:
+write rot = exp(i (pi/2 - theta)), so A = rot (eta - alpha) (eq. (e:A)), and
+ask Re[rot log f] to be constant on each Gamma_j. With
+f = c (z - alpha) exp((z - alpha) g) that is Re[A g] = gamma + h_j with
+
+    gamma = -Re[rot log(eta - alpha)],
+
+log(eta - alpha) taken continuous along each component (alpha lies in G, so
+its argument returns to its start around every inner component and gains 2 pi
+around Gamma_0). Then (eta - alpha) g = (gamma + h + i mu) / rot,
+
+    f(eta) = exp(-h_0) (eta - alpha) exp((gamma + h + i mu) / rot),
+
+and Re[rot log f] = h_j - h_0 sin(theta_j) =: level_j on Gamma_j. For
+theta_j = pi/2 that is log R_j (a circular slit of radius R_j); for
+theta_j = 0 it is -arg f (a radial slit at angle -level_j); any other constant
+gives an arc of a logarithmic spiral. The integral identity behind the
+discrete FBIE (eq. (e:NM-const)) holds for piecewise constant theta as well:
+the contribution of a component other than the one holding s cancels by
+residues, whatever its phase.
 """
 from __future__ import annotations
 
@@ -45,3 +67,25 @@ def circular_slit_map(eta, etap, alpha, n):
     f = np.exp(-hbar[0]) * (eta - alpha) * np.exp(gam + hn + 1j * mu)
     R = np.exp(hbar - hbar[0])
     return f, R, mu, h
+
+
+def slit_map(eta, etap, alpha, theta, n):
+    """Boundary values of the map onto the unit disc with slits on the curves
+    Re[exp(i (pi/2 - theta_j)) log w] = level_j (circular for theta_j = pi/2,
+    radial for theta_j = 0); f(alpha) = 0, f'(alpha) > 0, theta_0 = pi/2.
+
+    theta: (m1,) real. Returns (f, level, mu, h); level_0 = 0."""
+    eta = np.asarray(eta, np.complex128)
+    etap = np.asarray(etap, np.complex128)
+    theta = np.asarray(theta, np.float64)
+    m1 = eta.shape[0] // n
+    d = eta - alpha
+    arg = np.concatenate([np.unwrap(np.angle(d[k * n:(k + 1) * n])) for k in range(m1)])
+    rot = np.repeat(np.exp(1j * (np.pi / 2 - theta)), n)
+    A = rot * d
+    gam = -np.real(rot * (np.log(np.abs(d)) + 1j * arg))
+    mu, h = orc.fbie(eta, etap, A, gam, n)
+    hbar = orc.component_means(h, n)
+    f = np.exp(-hbar[0]) * d * np.exp((gam + np.repeat(hbar, n) + 1j * mu) / rot)
+    level = hbar - hbar[0] * np.sin(theta)
+    return f, level, mu, h
