@@ -43,6 +43,17 @@ gives an arc of a logarithmic spiral. The integral identity behind the
 discrete FBIE (eq. (e:NM-const)) holds for piecewise constant theta as well:
 the contribution of a component other than the one holding s cancels by
 residues, whatever its phase.
+
+Unbounded G (Example 4): A = rot (eq. (e:A)) and the solution of the
+Riemann-Hilbert problem vanishes at infinity. Write the map onto the extended
+plane with slits as F(z) = (z - alpha) exp(g(z)), g analytic in G with
+g(infinity) = 0, so F(alpha) = 0 and F(z) = z + O(1) at infinity; then
+Re[rot g] = gamma + h_j with the same gamma (alpha lies outside every hole,
+so log(eta - alpha) is continuous along every component), and
+
+    F(eta) = (eta - alpha) exp((gamma + h + i mu) / rot),  level_j = h_j.
+
+Every component becomes a slit; theta_0 is free.
 """
 from __future__ import annotations
 
@@ -69,12 +80,14 @@ def circular_slit_map(eta, etap, alpha, n):
     return f, R, mu, h
 
 
-def slit_map(eta, etap, alpha, theta, n):
-    """Boundary values of the map onto the unit disc with slits on the curves
+def slit_map(eta, etap, alpha, theta, n, bounded=True):
+    """Boundary values of the map onto the unit disc (bounded G; theta_0 = pi/2,
+    f(alpha) = 0, f'(alpha) > 0) or the extended plane (unbounded G; F(alpha) = 0,
+    F(z) = z + O(1) at infinity) with slits on the curves
     Re[exp(i (pi/2 - theta_j)) log w] = level_j (circular for theta_j = pi/2,
-    radial for theta_j = 0); f(alpha) = 0, f'(alpha) > 0, theta_0 = pi/2.
+    radial for theta_j = 0).
 
-    theta: (m1,) real. Returns (f, level, mu, h); level_0 = 0."""
+    theta: (m1,) real. Returns (f, level, mu, h); level_0 = 0 for bounded G."""
     eta = np.asarray(eta, np.complex128)
     etap = np.asarray(etap, np.complex128)
     theta = np.asarray(theta, np.float64)
@@ -82,10 +95,12 @@ def slit_map(eta, etap, alpha, theta, n):
     d = eta - alpha
     arg = np.concatenate([np.unwrap(np.angle(d[k * n:(k + 1) * n])) for k in range(m1)])
     rot = np.repeat(np.exp(1j * (np.pi / 2 - theta)), n)
-    A = rot * d
+    A = rot * d if bounded else rot
     gam = -np.real(rot * (np.log(np.abs(d)) + 1j * arg))
     mu, h = orc.fbie(eta, etap, A, gam, n)
     hbar = orc.component_means(h, n)
+    if not bounded:
+        return d * np.exp((gam + np.repeat(hbar, n) + 1j * mu) / rot), hbar, mu, h
     f = np.exp(-hbar[0]) * d * np.exp((gam + np.repeat(hbar, n) + 1j * mu) / rot)
     level = hbar - hbar[0] * np.sin(theta)
     return f, level, mu, h

@@ -7,6 +7,7 @@ Cauchy integral formula of Sec. 7 (an independent oracle) recovers from the
 boundary values alone; h must be constant on each component; and the domain's
 symmetry under z -> i z gives the four slits one radius."""
 import numpy as np
+import pytest
 
 import workloads as wl
 from oracle import nystrom as orc
@@ -148,3 +149,93 @@ def test_theta_pi_over_2_is_the_circular_slit_map():
     f, level, _, _ = slit_map(d.eta, d.etap, 0.0, np.full(5, np.pi / 2), n)
     fc, R, _, _ = circular_slit_map(d.eta, d.etap, 0.0, n)
     assert np.max(np.abs(f - fc)) < 1e-14 and np.max(np.abs(np.exp(level) - R)) < 1e-14
+
+
+# ------------------------------------------------------------ closed forms, one circle
+def _circle_nodes(n, ccw):
+    t = 2 * np.pi * np.arange(n) / n
+    e = np.exp(1j * t) if ccw else np.exp(-1j * t)
+    return e, (1j if ccw else -1j) * e
+
+
+def test_disc_map_is_the_moebius_map():
+    # the unit disc: f(z) = (z - alpha) / (1 - conj(alpha) z) (f(alpha) = 0, f'(alpha) > 0)
+    n = 128
+    eta, etap = _circle_nodes(n, True)
+    for alpha in (0.0, 0.3 + 0.4j, -0.6j):
+        f, level, _, _ = slit_map(eta, etap, alpha, np.array([np.pi / 2]), n)
+        assert np.max(np.abs(f - (eta - alpha) / (1 - np.conj(alpha) * eta))) < 1e-12
+        assert level[0] == 0.0
+
+
+@pytest.mark.parametrize("alpha", [2.0, 1.5 - 0.7j, -3.0j])
+def test_exterior_of_the_circle_closed_forms(alpha):
+    # |z| > 1 onto the plane with one slit, F(alpha) = 0, F(z) = z + O(1):
+    #   circular slit: F = z (z - alpha) / (z - 1/conj(alpha)), radius |alpha|
+    #   radial slit:   F = z + e^{2 i phi} / z - e^{i phi} (|alpha| + 1/|alpha|), alpha = |alpha| e^{i phi}
+    #                  (a Joukowski map), on the ray at angle phi + pi
+    n = 256
+    eta, etap = _circle_nodes(n, False)
+    F, level, _, _ = slit_map(eta, etap, alpha, np.array([np.pi / 2]), n, bounded=False)
+    assert np.max(np.abs(F - eta * (eta - alpha) / (eta - 1 / np.conj(alpha)))) < 1e-11
+    assert abs(level[0] - np.log(abs(alpha))) < 1e-12
+    F, level, _, _ = slit_map(eta, etap, alpha, np.array([0.0]), n, bounded=False)
+    ph = np.angle(alpha)
+    ex = eta + np.exp(2j * ph) / eta - np.exp(1j * ph) * (abs(alpha) + 1 / abs(alpha))
+    assert np.max(np.abs(F - ex)) < 1e-11
+    assert abs(np.angle(np.exp(-1j * level[0]) * np.exp(-1j * (ph + np.pi)))) < 1e-12
+
+
+# ------------------------------------------------------------ Example 4 (unbounded)
+EX4_CENTRES = np.array([0.0, 1 + 1j, -1 + 1j, -1 - 1j, 1 - 1j])
+
+
+def _hole_sums(d, F, z):
+    # (1/2 pi i) int_Gamma (F - eta)/(eta - z) d eta at points z inside the holes: for F - z
+    # analytic in the unbounded G (bounded at infinity) this is -(F - z)(infinity), one
+    # constant for every hole
+    return -cauchy_sums(d.eta, (F - d.eta) * d.etap, z) / (d.n * 1j)
+
+
+def test_example4_map_is_analytic_with_zero_at_alpha():
+    n = 256
+    d = wl.example4_circles(n, 0.1)
+    alpha = 2.0 + 2.0j
+    F, level, mu, h = slit_map(d.eta, d.etap, alpha, THETA_EX3, n, bounded=False)
+    P = _hole_sums(d, F, EX4_CENTRES + 0.05)
+    assert np.max(np.abs(P - P[0])) < 1e-10
+    # Cauchy's formula at alpha with (F - z)(infinity) = -P: F(alpha) = 0
+    Fa = alpha - P[0] - cauchy_sums(d.eta, (F - d.eta) * d.etap, np.array([alpha]))[0] / (n * 1j)
+    assert abs(Fa) < 1e-10
+    # the slit conditions, and h constant on every component
+    for k in range(5):
+        seg = F[k * n:(k + 1) * n]
+        if THETA_EX3[k] == 0.0:
+            assert np.max(np.abs(np.angle(seg * np.exp(1j * level[k])))) < 1e-10
+        else:
+            assert np.max(np.abs(np.log(np.abs(seg)) - level[k])) < 1e-10
+    assert np.max(np.abs(h - np.repeat(orc.component_means(h, n), n))) < 1e-9
+    # multiplying by rot instead of dividing breaks analyticity
+    rot = np.repeat(np.exp(1j * (np.pi / 2 - THETA_EX3)), n)
+    dz = d.eta - alpha
+    arg = np.concatenate([np.unwrap(np.angle(dz[k * n:(k + 1) * n])) for k in range(5)])
+    gam = -np.real(rot * (np.log(np.abs(dz)) + 1j * arg))
+    G = dz * np.exp((gam + np.repeat(orc.component_means(h, n), n) + 1j * mu) * rot)
+    Q = _hole_sums(d, G, EX4_CENTRES + 0.05)
+    assert np.max(np.abs(Q - Q[0])) > 1e-3
+
+
+def test_example4_symmetry():
+    # z -> i conj(z) fixes alpha = 2 + 2i, the domain and this theta, and F(z) = z + O(1):
+    # so F(i conj z) = i conj F(z): the radial slits of the circles on y = x lie on that
+    # line, and the circular slits of -1 + i and 1 - i share one radius. With
+    # theta = pi/2 everywhere and alpha = 2 (fixed by z -> conj z), conjugate circles
+    # share a radius.
+    n = 256
+    d = wl.example4_circles(n, 0.1)
+    F, level, _, _ = slit_map(d.eta, d.etap, 2.0 + 2.0j, THETA_EX3, n, bounded=False)
+    assert abs(level[2] - level[4]) < 1e-10
+    for k in (1, 3):
+        assert abs(np.exp(-2j * level[k]) - 1j) < 1e-10      # 2 arg F = pi/2 (mod 2 pi)
+    F, level, _, _ = slit_map(d.eta, d.etap, 2.0, np.full(5, np.pi / 2), n, bounded=False)
+    assert abs(level[1] - level[4]) < 1e-10 and abs(level[2] - level[3]) < 1e-10
