@@ -484,9 +484,11 @@ hipEvent_t pool_event(gnk_ctx* c) {
 // tile over the box hierarchy: a box whose bounding circle is separated from
 // the tile's by (1 + theta)(r_t + r_b) is far (its expansion), a leaf that is
 // not is near (its four 64-node blocks, summed directly); each tile's list is
-// cut into 4 splits ranges of about equal estimated cost (far box 4p + 24,
+// cut into 4 splits ranges of about equal estimated cost (far box 4p_e + 24,
 // near source 13 per target, the tile's own window 16). theta = 1.5 bounds
-// r_b/|z - c_b| by 0.4, so p = log(far_tol)/log(0.4) terms meet far_tol.
+// r_b/|z - c_b| by 0.4, so p = log(far_tol)/log(0.4) terms meet far_tol for
+// every far box; each (tile, box) entry takes the p_e its own ratio
+// rho_e = r_b/(|c_t - c_b| - r_t) >= r_b/|z - c_b| needs, which keeps the bound.
 constexpr double kTreeTheta = 1.5;
 
 int tree_terms(double far_tol) {
@@ -506,6 +508,11 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   T = Batch::Tree{};
   T.p = tree_terms(far_tol);
   int total = 0;
+  // far entries carry the box index in 24 bits
+  if ((int64_t)2 * ((N + kLeaf - 1) / kLeaf) + 64 >= ((int64_t)1 << 24)) {
+    set_err(c, "the treecode takes at most about 2^31 nodes");
+    throw Fail{GNK_ERR_ARG};
+  }
   for (int nb = (N + kLeaf - 1) / kLeaf;; nb = (nb + 1) / 2) {
     T.off.push_back(total);
     T.nb.push_back(nb);
@@ -530,7 +537,8 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   if (const char* e = getenv("GNK_TREE_SPLITS")) S = std::max(1, atoi(e));
   T.splits = S;
   const double f2 = (1.0 + kTreeTheta) * (1.0 + kTreeTheta);
-  const double cfar = 4.0 * T.p + 24.0, cnear = 13.0, cself = 16.0;
+  const double cnear = 13.0, cself = 16.0;
+  const double ltol = std::log(far_tol);
   std::vector<int> list, seg((size_t)T.tiles * (4 * S + 1));
   std::vector<int> ent;
   std::vector<double> cost;
@@ -547,8 +555,10 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
       const double4 bb = hb[T.off[l] + b];
       const double dx = tt.x - bb.x, dy = tt.y - bb.y, rr = tt.z + bb.z;
       if (dx * dx + dy * dy > f2 * rr * rr) {
-        ent.push_back(T.off[l] + b);
-        cost.push_back(cfar);
+        const double rho = bb.z / (std::sqrt(dx * dx + dy * dy) - tt.z);
+        const int pe = std::max(2, std::min(T.p, (int)std::ceil(ltol / std::log(rho))));
+        ent.push_back((pe << 24) | (T.off[l] + b));
+        cost.push_back(4.0 * pe + 24.0);
       } else if (l == 0) {
         for (int k = 0; k < kLeaf / 64; ++k) {
           const int j0 = b * kLeaf + k * 64;

@@ -140,10 +140,12 @@ __global__ void k_m2m(const double4* __restrict__ bounds, int child0, int nchild
 
 // One workgroup per (target tile, split): wave wv takes the entries
 // [seg[4 split + wv], seg[4 split + wv + 1]) of its tile's list. Entries >= 0
-// are far boxes (global index), entries < 0 are near blocks ~blk of 64 nodes.
+// are far boxes: global index in bits 0..23, the number of terms this box
+// needs for this tile in bits 24..29; entries < 0 are near blocks ~blk of 64
+// nodes.
 // Partial sums of weight column col go to slot split, like the direct kernels'.
 template <int TPT>
-__global__ __launch_bounds__(256) void k_tree(const DomDev* __restrict__ doms, const int* __restrict__ seg,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_tree(const DomDev* __restrict__ doms, const int* __restrict__ seg,
                                               const int* __restrict__ list, const double4* __restrict__ bounds,
                                               const double2* __restrict__ mom, int p, int splits, int col, int wcols,
                                               const int* __restrict__ active, int lead) {
@@ -193,15 +195,16 @@ __global__ __launch_bounds__(256) void k_tree(const DomDev* __restrict__ doms, c
   for (int e = e0; e < e1; ++e) {
     const int ent = ls[e];
     if (ent >= 0) {
-      const double4 c = bd[ent];
-      const gptr<const double2> a = mm + (size_t)ent * p;
+      const int box = ent & 0xFFFFFF, pe = ent >> 24;
+      const double4 c = bd[box];
+      const gptr<const double2> a = mm + (size_t)box * p;
 #pragma unroll
       for (int t = 0; t < TPT; ++t) {
         const double dx = tg[t].x - c.x, dy = tg[t].y - c.y;
         const double inv = refine_rcp(__builtin_fma(dy, dy, dx * dx));
         const double ux = dx * inv, uy = -dy * inv;
         double sx = 0.0, sy = 0.0;
-        for (int k = p - 1; k >= 0; --k) {
+        for (int k = pe - 1; k >= 0; --k) {
           const double2 ak = a[k];
           const double nx = __builtin_fma(ux, sx, __builtin_fma(-uy, sy, ak.x));
           sy = __builtin_fma(ux, sy, __builtin_fma(uy, sx, ak.y));
