@@ -237,10 +237,48 @@ GNK_API gnk_status gnk_fcau(gnk_ctx* ctx, int64_t m1, int64_t n, const void* eta
  *   radii     : host array of m1 doubles (output) or NULL
  *   info      : host, one entry (the FBIE solve) or NULL
  * Interior values follow from gnk_fcau with these boundary values.
- * Errors: GNK_ERR_ARG for NULL or aliased pointers, sizes, no_subtraction. */
+ * Errors: GNK_ERR_ARG for NULL or aliased pointers, sizes, no_subtraction, and
+ * alpha outside G (as for gnk_slit_map, which this is with bounded = 1 and
+ * theta = pi/2). */
 GNK_API gnk_status gnk_circular_slit_map(gnk_ctx* ctx, int64_t m1, int64_t n, const void* eta, const void* etap,
                                          const double* alpha, const gnk_opts* opts, void* f, double* radii,
                                          gnk_info* info);
+
+/* Conformal map of an (m+1)-connected domain onto a canonical domain with
+ * slits, from one FBIE solve with the piecewise constant theta of eq. (e:A):
+ * circular slits for theta_j = pi/2, radial slits for theta_j = 0 (Examples 3
+ * and 4), arcs of logarithmic spirals for other values. With
+ * rot_j = exp(i (pi/2 - theta_j)), gamma = -Re[rot_j log(eta - alpha)] (the
+ * logarithm continued along each component) and h_j the mean of FBIE's h over
+ * component j:
+ *   bounded G:   A = rot_j (eta - alpha), theta_0 = pi/2,
+ *                f(eta) = exp(-h_0) (eta - alpha) exp((gamma + h_j + i mu) / rot_j):
+ *                the unit disc with slits, f(alpha) = 0, f'(alpha) > 0,
+ *                level_j = h_j - h_0 sin(theta_j) (level_0 = 0);
+ *   unbounded G: A = rot_j,
+ *                f(eta) = (eta - alpha) exp((gamma + h_j + i mu) / rot_j):
+ *                the extended plane with m + 1 slits, f(alpha) = 0,
+ *                f(z) = z + O(1) at infinity, level_j = h_j.
+ * On Gamma_j, Re[rot_j log f] = level_j: a circle of radius exp(level_j) for
+ * theta_j = pi/2, a radial slit at angle -level_j for theta_j = 0.
+ *   eta, etap : N complex (device), component-major; bounded: outer boundary
+ *               first (ccw), the others clockwise; unbounded: all clockwise
+ *   bounded   : 1 for a bounded G, 0 for an unbounded one
+ *   alpha     : host, 2 doubles {Re, Im}, a point of G
+ *   theta     : host, m1 doubles (theta[0] = pi/2 when bounded); NULL = pi/2 everywhere
+ *   opts      : as for gnk_fbie (NULL: defaults); far_tol allowed
+ *   f         : N complex (device, output): boundary values of the map
+ *   level     : host array of m1 doubles (output) or NULL
+ *   info      : host, one entry (the FBIE solve) or NULL
+ * Interior values follow from gnk_fcau with these boundary values (for an
+ * unbounded G, from those of f(z) - z, whose value at infinity is finite).
+ * Errors: GNK_ERR_ARG for NULL or aliased pointers, sizes, bounded not 0 or 1,
+ * no_subtraction, theta[0] != pi/2 (bounded) or a non-finite theta, and alpha
+ * outside G (found from the winding of each component around alpha: 1 for the
+ * outer boundary of a bounded G, 0 for every other component). */
+GNK_API gnk_status gnk_slit_map(gnk_ctx* ctx, int64_t m1, int64_t n, const void* eta, const void* etap, int bounded,
+                                const double* alpha, const double* theta, const gnk_opts* opts, void* f,
+                                double* level, gnk_info* info);
 
 /* gnk_cauchy_sum with the far field from the treecode (see gnk_opts.far_tol):
  * S_i = sum_{j != i} w_j / (eta_i - eta_j), near pairs summed directly, far

@@ -1523,51 +1523,105 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
   });
 }
 
+// Boundary values of the map onto the unit disc (bounded G) or the extended plane
+// (unbounded G) with slits, from one FBIE solve (theta == NULL: pi/2 on every
+// component). level[k] = hbar_k - hbar_0 sin(theta_k) (bounded), hbar_k (unbounded).
+static gnk_status slit_map(gnk_ctx* c, const char* name, int64_t m1, int64_t n, const void* eta, const void* etap,
+                           int bounded, const double* alpha, const double* theta, const gnk_opts* opts, void* f,
+                           double* level, gnk_info* info) {
+  if (!eta || !etap || !alpha || !f || f == eta || f == etap || m1 < 1 || n < 2 || (bounded != 0 && bounded != 1) ||
+      !std::isfinite(alpha[0]) || !std::isfinite(alpha[1])) {
+    set_err(c, "bad arguments to %s", name);
+    throw Fail{GNK_ERR_ARG};
+  }
+  gnk_opts o = resolve_opts(c, opts);
+  if (o.no_subtraction) {
+    set_err(c, "the map takes the paper's method (no_subtraction = 0)");
+    throw Fail{GNK_ERR_ARG};
+  }
+  const int64_t N = m1 * n;
+  if (N > ((int64_t)1 << 30)) {
+    set_err(c, "N = (m+1) n = %lld exceeds 2^30", (long long)N);
+    throw Fail{GNK_ERR_ARG};
+  }
+  // rot_k = exp(i (pi/2 - theta_k)) = (sin theta_k, cos theta_k)
+  std::vector<double2> rot((size_t)m1, make_double2(1.0, 0.0));
+  if (theta) {
+    if (bounded && std::fabs(theta[0] - 0.5 * M_PI) > 1e-12) {
+      set_err(c, "theta_0 must be pi/2 (the outer boundary maps onto the unit circle)");
+      throw Fail{GNK_ERR_ARG};
+    }
+    for (int64_t k = bounded; k < m1; ++k) {
+      if (!std::isfinite(theta[k])) {
+        set_err(c, "theta[%lld] is not finite", (long long)k);
+        throw Fail{GNK_ERR_ARG};
+      }
+      rot[k] = make_double2(std::cos(0.5 * M_PI - theta[k]), std::sin(0.5 * M_PI - theta[k]));
+    }
+  }
+  double2* A = ws<double2>(c, "s_A", N);
+  double* gam = ws<double>(c, "s_gam", N);
+  double* mu = ws<double>(c, "s_mu", N);
+  double* h = ws<double>(c, "s_h", N);
+  double* hbar = ws<double>(c, "s_hbar", m1);
+  double* wind = ws<double>(c, "s_wind", m1);
+  double2* rot_d = ws<double2>(c, "s_rot", m1);
+  HIPCHK(c, hipMemcpyAsync(rot_d, rot.data(), sizeof(double2) * m1, hipMemcpyHostToDevice, c->stream));
+  k_slit_setup<<<(unsigned)m1, kT, 0, c->stream>>>(static_cast<const double2*>(eta), (int)n, bounded, alpha[0],
+                                                    alpha[1], rot_d, A, gam, wind);
+  LAUNCHCHK(c);
+  std::vector<double> w((size_t)m1);
+  HIPCHK(c, hipMemcpyAsync(w.data(), wind, sizeof(double) * m1, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int64_t k = 0; k < m1; ++k) {
+    const int want = (k == 0 && bounded) ? 1 : 0;
+    if (!(std::fabs(w[k] - 2.0 * M_PI * want) < 1.0)) {
+      set_err(c, "alpha is not in G: the boundary component %lld winds %.3g times around it (expected %d)",
+              (long long)k, w[k] / (2.0 * M_PI), want);
+      throw Fail{GNK_ERR_ARG};
+    }
+  }
+  gnk_domain d{};
+  d.m1 = m1;
+  d.n = n;
+  d.eta = eta;
+  d.etap = etap;
+  d.A = A;
+  Batch B;
+  single_batch(c, B, &d, 1, false, o.prec == GNK_MIXED);
+  if (o.far_tol > 0.0) build_tree(c, B, o.far_tol);
+  GmresOut g = fbie_batch(c, B, gam, o, mu, h);
+  k_comp_means<<<(unsigned)m1, kT, 0, c->stream>>>(h, (int)n, hbar);
+  LAUNCHCHK(c);
+  k_slit_map<<<nblocks(N), kT, 0, c->stream>>>(static_cast<const double2*>(eta), bounded, alpha[0], alpha[1], rot_d,
+                                               gam, mu, hbar, N, (int)n, static_cast<double2*>(f));
+  LAUNCHCHK(c);
+  std::vector<double> hb((size_t)m1);
+  HIPCHK(c, hipMemcpyAsync(hb.data(), hbar, sizeof(double) * m1, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (level)
+    for (int64_t k = 0; k < m1; ++k) level[k] = bounded ? hb[k] - hb[0] * rot[k].x : hb[k];
+  if (info) info[0] = g.info[0];
+  return g.all_converged ? GNK_OK : GNK_NOT_CONVERGED;
+}
+
 gnk_status gnk_circular_slit_map(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const void* etap,
                                  const double* alpha, const gnk_opts* opts, void* f, double* radii, gnk_info* info) {
   return guarded(c, [&]() -> gnk_status {
-    if (!eta || !etap || !alpha || !f || f == eta || f == etap || m1 < 1 || n < 2) {
-      set_err(c, "bad arguments to gnk_circular_slit_map");
-      throw Fail{GNK_ERR_ARG};
-    }
-    gnk_opts o = resolve_opts(c, opts);
-    if (o.no_subtraction) {
-      set_err(c, "the map takes the paper's method (no_subtraction = 0)");
-      throw Fail{GNK_ERR_ARG};
-    }
-    const int64_t N = m1 * n;
-    if (N > ((int64_t)1 << 30)) {
-      set_err(c, "N = (m+1) n = %lld exceeds 2^30", (long long)N);
-      throw Fail{GNK_ERR_ARG};
-    }
-    double2* A = ws<double2>(c, "s_A", N);
-    double* gam = ws<double>(c, "s_gam", N);
-    double* mu = ws<double>(c, "s_mu", N);
-    double* h = ws<double>(c, "s_h", N);
-    double* hbar = ws<double>(c, "s_hbar", m1);
-    k_slit_setup<<<nblocks(N), kT, 0, c->stream>>>(static_cast<const double2*>(eta), N, alpha[0], alpha[1], A, gam);
-    LAUNCHCHK(c);
-    gnk_domain d{};
-    d.m1 = m1;
-    d.n = n;
-    d.eta = eta;
-    d.etap = etap;
-    d.A = A;
-    Batch B;
-    single_batch(c, B, &d, 1, false, o.prec == GNK_MIXED);
-    if (o.far_tol > 0.0) build_tree(c, B, o.far_tol);
-    GmresOut g = fbie_batch(c, B, gam, o, mu, h);
-    k_comp_means<<<(unsigned)m1, kT, 0, c->stream>>>(h, (int)n, hbar);
-    LAUNCHCHK(c);
-    k_slit_map<<<nblocks(N), kT, 0, c->stream>>>(A, gam, mu, hbar, N, (int)n, static_cast<double2*>(f));
-    LAUNCHCHK(c);
-    std::vector<double> hb((size_t)m1);
-    HIPCHK(c, hipMemcpyAsync(hb.data(), hbar, sizeof(double) * m1, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> level((size_t)std::max<int64_t>(m1, 1));
+    const gnk_status st =
+        slit_map(c, "gnk_circular_slit_map", m1, n, eta, etap, 1, alpha, nullptr, opts, f, level.data(), info);
     if (radii)
-      for (int64_t k = 0; k < m1; ++k) radii[k] = std::exp(hb[k] - hb[0]);
-    if (info) info[0] = g.info[0];
-    return g.all_converged ? GNK_OK : GNK_NOT_CONVERGED;
+      for (int64_t k = 0; k < m1; ++k) radii[k] = std::exp(level[k]);
+    return st;
+  });
+}
+
+gnk_status gnk_slit_map(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const void* etap, int bounded,
+                        const double* alpha, const double* theta, const gnk_opts* opts, void* f, double* level,
+                        gnk_info* info) {
+  return guarded(c, [&]() -> gnk_status {
+    return slit_map(c, "gnk_slit_map", m1, n, eta, etap, bounded, alpha, theta, opts, f, level, info);
   });
 }
 

@@ -255,17 +255,64 @@ __global__ void k_pack_records(const DomDev* __restrict__ doms, const double2* _
   }
 }
 
-// ---------------------------------------- conformal map onto the circular-slit disc
-// A = eta - alpha and gamma = -log|eta - alpha| of the Riemann-Hilbert problem
-// whose solution gives the map (theta = pi/2 in eq. (e:A))
-__global__ void k_slit_setup(const double2* __restrict__ eta, int64_t N, double ax, double ay,
-                             double2* __restrict__ A, double* __restrict__ gam) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double2 e = eta[i];
-  const double dx = e.x - ax, dy = e.y - ay;
-  A[i] = make_double2(dx, dy);
-  gam[i] = -0.5 * log(dx * dx + dy * dy);
+// ------------------------------- conformal maps onto the disc with slits
+// One block per component k: d = eta - alpha, its argument continued along the
+// component from the principal value at the first node (sums of the angles
+// arg(d_p / d_{p-1}) between neighbours: one contiguous chunk per thread, then
+// an exclusive scan of the chunk sums), and with rot_k = exp(i (pi/2 - theta_k))
+//   A = rot_k d (bounded G) or rot_k (unbounded G)   (eq. (e:A))
+//   gamma = -Re[rot_k log d]         (Re[rot log f] constant on each component).
+// wind[k] = the argument's total change around the closed component: 2 pi for
+// the outer boundary of a bounded G and 0 for a hole when alpha lies in G.
+__global__ __launch_bounds__(kT) void k_slit_setup(const double2* __restrict__ eta, int n, int bounded, double ax,
+                                                   double ay, const double2* __restrict__ rot,
+                                                   double2* __restrict__ A, double* __restrict__ gam,
+                                                   double* __restrict__ wind) {
+  __shared__ double sc[kT];
+  const int k = blockIdx.x, t = threadIdx.x;
+  const int chunk = (n + kT - 1) / kT;
+  const int p0 = min(n, t * chunk), p1 = min(n, p0 + chunk);
+  const double2* e = eta + (size_t)k * n;
+  auto dz = [&](int p) {
+    const double2 v = e[p];
+    return make_double2(v.x - ax, v.y - ay);
+  };
+  auto turn = [](double2 a, double2 b) { return atan2(a.x * b.y - a.y * b.x, a.x * b.x + a.y * b.y); };
+  double s = 0.0;
+  if (p0 < p1) {
+    double2 prev = dz(p0 > 0 ? p0 - 1 : 0);
+    for (int p = p0; p < p1; ++p) {
+      const double2 cur = dz(p);
+      if (p > 0) s += turn(prev, cur);
+      prev = cur;
+    }
+  }
+  sc[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    double run = 0.0;
+    for (int q = 0; q < kT; ++q) {
+      const double v = sc[q];
+      sc[q] = run;
+      run += v;
+    }
+    wind[k] = run + turn(dz(n - 1), dz(0));
+  }
+  __syncthreads();
+  const double2 r = rot[k];
+  const double2 d0 = dz(0);
+  double arg = atan2(d0.y, d0.x) + sc[t];
+  if (p0 < p1) {
+    double2 prev = dz(p0 > 0 ? p0 - 1 : 0);
+    for (int p = p0; p < p1; ++p) {
+      const double2 d = dz(p);
+      if (p > 0) arg += turn(prev, d);
+      prev = d;
+      const size_t i = (size_t)k * n + p;
+      A[i] = bounded ? make_double2(r.x * d.x - r.y * d.y, r.x * d.y + r.y * d.x) : r;
+      gam[i] = -r.x * (0.5 * log(d.x * d.x + d.y * d.y)) + r.y * arg;
+    }
+  }
 }
 
 // hbar[k] = (1/n) sum over component k of h (fixed-order block reduction)
@@ -278,17 +325,24 @@ __global__ __launch_bounds__(kT) void k_comp_means(const double* __restrict__ h,
   if (threadIdx.x == 0) hbar[k] = t / (double)n;
 }
 
-// f(eta_i) = exp(-hbar_0) (eta_i - alpha) exp(gamma_i + hbar_k(i) + i mu_i)
-__global__ void k_slit_map(const double2* __restrict__ A, const double* __restrict__ gam,
+// f(eta_i) = exp(-shift) d_i exp((gamma_i + hbar_k + i mu_i) / rot_k), d = eta - alpha,
+// shift = hbar_0 for a bounded G (|f| = 1 on the outer boundary), 0 for an unbounded
+// one (f(z) = z + O(1)); |rot_k| = 1, so the division is a product with its conjugate
+__global__ void k_slit_map(const double2* __restrict__ eta, int bounded, double ax, double ay,
+                           const double2* __restrict__ rot, const double* __restrict__ gam,
                            const double* __restrict__ mu, const double* __restrict__ hbar, int64_t N, int n,
                            double2* __restrict__ f) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const double mag = exp(gam[i] + hbar[i / n] - hbar[0]);
+  const int64_t k = i / n;
+  const double2 r = rot[k];
+  const double a = gam[i] + hbar[k], b = mu[i];
+  const double mag = exp((a * r.x + b * r.y) - (bounded ? hbar[0] : 0.0));
   double s, c;
-  sincos(mu[i], &s, &c);
-  const double2 a = A[i];
-  f[i] = make_double2(mag * (a.x * c - a.y * s), mag * (a.x * s + a.y * c));
+  sincos(b * r.x - a * r.y, &s, &c);
+  const double2 e = eta[i];
+  const double dx = e.x - ax, dy = e.y - ay;
+  f[i] = make_double2(mag * (dx * c - dy * s), mag * (dx * s + dy * c));
 }
 
 // ------------------------------------------ Cauchy integral at interior points

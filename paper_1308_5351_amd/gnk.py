@@ -25,7 +25,7 @@ OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT, OP_FB_U, OP_GB_U = rang
 EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
             "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad",
             "gnk_fbie_batched", "gnk_fbie_adjoint", "gnk_geom_vjp", "gnk_fourier_curve", "gnk_fourier_vjp",
-            "gnk_fcau", "gnk_cauchy_sum_tree", "gnk_circular_slit_map")
+            "gnk_fcau", "gnk_cauchy_sum_tree", "gnk_circular_slit_map", "gnk_slit_map")
 
 
 class GnkError(RuntimeError):
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH):
     lib.gnk_cauchy_sum_tree.argtypes = [P, C.c_int64, P, P, C.c_int, C.c_double, P]
     lib.gnk_circular_slit_map.argtypes = [P, C.c_int64, C.c_int64, P, P, C.POINTER(C.c_double), C.POINTER(_Opts), P,
                                           C.POINTER(C.c_double), C.POINTER(Info)]
+    lib.gnk_slit_map.argtypes = [P, C.c_int64, C.c_int64, P, P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(_Opts), P, C.POINTER(C.c_double), C.POINTER(Info)]
     for f in EXPORTED:
         if f not in ("gnk_last_error", "gnk_version"):
             getattr(lib, f).restype = C.c_int
@@ -261,6 +263,32 @@ class Context:
                                             f.data_ptr(), radii, info)
         self._raise(st)
         return f, np.array(radii[:]), info[0].as_dict(), st
+
+    def slit_map(self, eta: torch.Tensor, etap: torch.Tensor, m1: int, n: int, alpha: complex, theta,
+                 restart=25, maxit=40, tol=1e-12, far_tol=0.0, bounded=True):
+        """Boundary values f (N,) complex128 of the map of a bounded domain onto the unit disc (theta[0] = pi/2)
+        or of an unbounded one onto the extended plane (f(z) = z + O(1)) with slits on
+        Re[exp(i (pi/2 - theta_j)) log w] = level_j (circular for theta_j = pi/2, radial at angle -level_j for
+        theta_j = 0); theta: m1 reals. Returns (f, level, info, status)."""
+        self._bind_stream()
+        N = m1 * n
+        for name, t in (("eta", eta), ("etap", etap)):
+            if t.dtype != torch.complex128 or t.shape != (N,) or not t.is_cuda:
+                raise ValueError(f"{name} must be a complex128 CUDA tensor of shape ({N},)")
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        if th.shape != (m1,):
+            raise ValueError(f"theta must hold {m1} values")
+        ec, pc = eta.contiguous(), etap.contiguous()
+        f = torch.empty(N, dtype=torch.complex128, device=eta.device)
+        al = (C.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+        tha = (C.c_double * m1)(*th.tolist())
+        level = (C.c_double * m1)()
+        info = (Info * 1)()
+        o = self._opts(restart, maxit, tol, FP64, 0.0, 0, None, True, far_tol)
+        st = self.lib.gnk_slit_map(self.h, m1, n, ec.data_ptr(), pc.data_ptr(), int(bool(bounded)), al, tha, C.byref(o),
+                                   f.data_ptr(), level, info)
+        self._raise(st)
+        return f, np.array(level[:]), info[0].as_dict(), st
 
     def apply(self, dom: DeviceDomain, op: int, x: torch.Tensor, prec: int = FP64) -> torch.Tensor:
         self._bind_stream()
