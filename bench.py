@@ -40,9 +40,9 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # two rocprofv3 --pmc runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 KiB, the
 # factors from a 256 MiB copy of known size; profiles/k_pairs_fp64_N17408_hbm_counters.md).
 # Valid only for the kernel sources they were taken on (hash below), else null.
-PAIR_TRAFFIC = {"sources": ("cauchy.hip", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "1ec3c893d0a33d6a042f9f7c45f524442e3f9882c9bfdc32d01318a7c0ae3074",
-                "bytes_per_launch": 21994713}
+PAIR_TRAFFIC = {"sources": ("cauchy.hip", "pair_steps.inl", "gnk_device.h", "gnk_internal.h"),
+                "sha256": "8fcb7a33e4cc17354f6d6851b8eb81224657a6ccdb3e4a096bed36f432a1ede0",
+                "bytes_per_launch": 21997911}
 
 
 def pair_traffic():
@@ -173,6 +173,49 @@ def subtraction_ablation(gnk, ctx, torch, n=512):
             "rows": rows}
 
 
+def slit_maps(gnk, ctx, torch, n=4096):
+    """Examples 3 and 4: the maps onto slit domains from FBIE (restart 25, tol
+    1e-12, maxit 40, n = 4096 per circle) at separations 1e-1..1e-4, with
+    theta = pi/2 everywhere and theta = (pi/2, 0, pi/2, 0, pi/2). The domains'
+    symmetries fix the directions of the radial slits (pi/4 and -3 pi/4 on
+    Example 2's domain with alpha = 0; the line y = x on Example 4's with
+    alpha = 2 + 2i): the miss measures FBIE's accuracy with non-constant theta,
+    and on the bounded domain the radial slits must stay inside the unit disc."""
+    import numpy as np
+    import workloads as wl
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    thetas = (("circular", np.full(5, np.pi / 2)), ("circular+radial", np.array([np.pi / 2, 0.0, np.pi / 2, 0.0, np.pi / 2])))
+    log("slit maps: Examples 3 and 4")
+    rows = []
+    for eps in (1e-1, 1e-2, 1e-3, 1e-4):
+        for ex, dom, bounded, alpha in (("ex3", wl.example2_circles(n, eps), True, 0.0),
+                                        ("ex4", wl.example4_circles(n, eps), False, 2.0 + 2.0j)):
+            e, p = cu(dom.eta), cu(dom.etap)
+            for tname, th in thetas:
+                kw = dict(restart=25, maxit=40, tol=1e-12, bounded=bounded)
+                ctx.slit_map(e, p, dom.m1, n, alpha, th, **kw)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                f, lev, info, st = ctx.slit_map(e, p, dom.m1, n, alpha, th, **kw)
+                torch.cuda.synchronize()
+                row = {"example": ex, "eps": eps, "theta": tname, "ms": round((time.perf_counter() - t) * 1e3, 3),
+                       "iters": info["inner_it"], "status": st}
+                if tname == "circular+radial":
+                    if bounded:
+                        miss = [np.angle(np.exp(-1j * lev[1]) * np.exp(-1j * np.pi / 4)),
+                                np.angle(np.exp(-1j * lev[3]) * np.exp(3j * np.pi / 4))]
+                        fh = f.cpu().numpy()
+                        row["max_abs_f_on_radial_slits"] = float(max(np.abs(fh[n:2 * n]).max(),
+                                                                     np.abs(fh[3 * n:4 * n]).max()))
+                    else:
+                        miss = [0.5 * np.angle(np.exp(-2j * lev[k]) * -1j) for k in (1, 3)]
+                    row["radial_angle_miss"] = float(max(abs(m) for m in miss))
+                rows.append(row)
+    return {"workload": "Example 3: unit circle and four circles at separation eps (alpha = 0); Example 4: five "
+                        "circles at separation eps, unbounded (alpha = 2 + 2i); n = 4096 per circle (N = 20480), "
+                        "FBIE restart 25, tol 1e-12, maxit 40", "rows": rows}
+
+
 def far_field(gnk, ctx, torch):
     """The treecode far field (gnk_opts.far_tol) against the direct sums: FBIE
     on the 129 perturbed circles (N = 264192), then a treecode-only solve at
@@ -272,6 +315,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed and batched comparisons")
     ap.add_argument("--batched-mixed-only", action="store_true",
                     help="run only the 64-domain batched solve in mixed precision (warm-up + one timed call)")
+    ap.add_argument("--far-field-only", action="store_true",
+                    help="run only the treecode comparison (for kernel traces of the treecode)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain copy of 256 MiB (3 launches), the reference for HBM counters")
     args = ap.parse_args()
@@ -297,6 +342,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"batched_mixed_s": round(time.perf_counter() - t, 3), "status": st,
                           "max_iters": max(i["inner_it"] for inf in infos for i in inf)}), flush=True)
+        ctx.close()
+        return
+
+    if args.far_field_only:
+        ctx = gnk.Context(0)
+        print(json.dumps({"far_field": far_field(gnk, ctx, torch)}), flush=True)
         ctx.close()
         return
 
@@ -383,6 +434,7 @@ def main():
         out["fcau"] = fcau_rate(gnk, ctx, torch)
         out["subtraction_ablation"] = subtraction_ablation(gnk, ctx, torch)
         out["far_field"] = far_field(gnk, ctx, torch)
+        out["slit_maps"] = slit_maps(gnk, ctx, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(dom)

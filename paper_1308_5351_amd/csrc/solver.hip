@@ -23,6 +23,7 @@
 #include <memory>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "gnk_internal.h"
@@ -539,59 +540,102 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   const double f2 = (1.0 + kTreeTheta) * (1.0 + kTreeTheta);
   const double cnear = 13.0, cself = 16.0;
   const double ltol = std::log(far_tol);
-  std::vector<int> list, seg((size_t)T.tiles * (4 * S + 1));
-  std::vector<int> ent;
-  std::vector<double> cost;
-  std::vector<std::pair<int, int>> stack;
-  for (int t = 0; t < T.tiles; ++t) {
-    ent.clear();
-    cost.clear();
-    const double4 tt = ht[t];
-    const int base = t * kt, top = T.levels - 1;
-    for (int b = 0; b < T.nb[top]; ++b) stack.push_back({top, b});
-    while (!stack.empty()) {
-      const auto [l, b] = stack.back();
-      stack.pop_back();
-      const double4 bb = hb[T.off[l] + b];
-      const double dx = tt.x - bb.x, dy = tt.y - bb.y, rr = tt.z + bb.z;
-      if (dx * dx + dy * dy > f2 * rr * rr) {
-        const double rho = bb.z / (std::sqrt(dx * dx + dy * dy) - tt.z);
-        const int pe = std::max(2, std::min(T.p, (int)std::ceil(ltol / std::log(rho))));
-        ent.push_back((pe << 24) | (T.off[l] + b));
-        cost.push_back(4.0 * pe + 24.0);
-      } else if (l == 0) {
-        for (int k = 0; k < kLeaf / 64; ++k) {
-          const int j0 = b * kLeaf + k * 64;
-          if (j0 >= N) break;
-          const int j1 = std::min(N, j0 + 64);
-          const int ov = std::max(0, std::min(j1, base + kt) - std::max(j0, base));
-          ent.push_back(~(j0 / 64));
-          cost.push_back(cnear * (j1 - j0 - ov) + cself * ov);
+  std::vector<int> seg((size_t)T.tiles * (4 * S + 1));
+  // the tiles' lists are independent: contiguous tile ranges on a few host
+  // threads, each list local to its thread, then joined in tile order
+  const int nth = std::max(1, std::min({16, (int)std::thread::hardware_concurrency(), (T.tiles + 63) / 64}));
+  std::vector<std::vector<int>> part((size_t)nth);
+  std::vector<char> failed((size_t)nth, 0);
+  auto lists_for = [&](int th) {
+    const int t0 = (int)((int64_t)T.tiles * th / nth), t1 = (int)((int64_t)T.tiles * (th + 1) / nth);
+    std::vector<int>& lst = part[(size_t)th];
+    try {
+      std::vector<int> ent;
+      std::vector<double> cost;
+      std::vector<std::pair<int, int>> stack;
+      for (int t = t0; t < t1; ++t) {
+        ent.clear();
+        cost.clear();
+        const double4 tt = ht[t];
+        const int base = t * kt, top = T.levels - 1;
+        for (int b = 0; b < T.nb[top]; ++b) stack.push_back({top, b});
+        while (!stack.empty()) {
+          const auto [l, b] = stack.back();
+          stack.pop_back();
+          const double4 bb = hb[T.off[l] + b];
+          const double dx = tt.x - bb.x, dy = tt.y - bb.y, rr = tt.z + bb.z;
+          if (dx * dx + dy * dy > f2 * rr * rr) {
+            const double rho = bb.z / (std::sqrt(dx * dx + dy * dy) - tt.z);
+            const int pe = std::max(2, std::min(T.p, (int)std::ceil(ltol / std::log(rho))));
+            ent.push_back((pe << 24) | (T.off[l] + b));
+            cost.push_back(4.0 * pe + 24.0);
+          } else if (l == 0) {
+            for (int k = 0; k < kLeaf / 64; ++k) {
+              const int j0 = b * kLeaf + k * 64;
+              if (j0 >= N) break;
+              const int j1 = std::min(N, j0 + 64);
+              const int ov = std::max(0, std::min(j1, base + kt) - std::max(j0, base));
+              ent.push_back(~(j0 / 64));
+              cost.push_back(cnear * (j1 - j0 - ov) + cself * ov);
+            }
+          } else {
+            // children pushed in reverse so that the list keeps node order
+            if (2 * b + 1 < T.nb[l - 1]) stack.push_back({l - 1, 2 * b + 1});
+            stack.push_back({l - 1, 2 * b});
+          }
         }
-      } else {
-        // children pushed in reverse so that the list keeps node order
-        if (2 * b + 1 < T.nb[l - 1]) stack.push_back({l - 1, 2 * b + 1});
-        stack.push_back({l - 1, 2 * b});
+        double tot = 0.0;
+        for (double x : cost) tot += x;
+        int* sg = seg.data() + (size_t)t * (4 * S + 1);
+        const int64_t start = (int64_t)lst.size();
+        sg[0] = (int)start;
+        double acc = 0.0;
+        size_t e = 0;
+        for (int k = 1; k < 4 * S; ++k) {
+          const double target = tot * k / (4.0 * S);
+          while (e < ent.size() && acc + 0.5 * cost[e] < target) acc += cost[e++];
+          sg[k] = (int)(start + (int64_t)e);
+        }
+        sg[4 * S] = (int)(start + (int64_t)ent.size());
+        if (lst.size() + ent.size() > (size_t)INT32_MAX / 2) {
+          failed[(size_t)th] = 1;   // reported after the join
+          return;
+        }
+        lst.insert(lst.end(), ent.begin(), ent.end());
       }
+    } catch (...) {
+      failed[(size_t)th] = 1;
     }
-    double tot = 0.0;
-    for (double x : cost) tot += x;
-    int* sg = seg.data() + (size_t)t * (4 * S + 1);
-    const int start = (int)list.size();
-    sg[0] = start;
-    double acc = 0.0;
-    size_t e = 0;
-    for (int k = 1; k < 4 * S; ++k) {
-      const double target = tot * k / (4.0 * S);
-      while (e < ent.size() && acc + 0.5 * cost[e] < target) acc += cost[e++];
-      sg[k] = start + (int)e;
+  };
+  {
+    std::vector<std::thread> pool;
+    int spawned = 1;
+    try {
+      for (; spawned < nth; ++spawned) pool.emplace_back(lists_for, spawned);
+    } catch (...) {
     }
-    sg[4 * S] = start + (int)ent.size();
-    list.insert(list.end(), ent.begin(), ent.end());
-    if (list.size() > (size_t)INT32_MAX / 2) {
-      set_err(c, "treecode interaction lists too long");
-      throw Fail{GNK_ERR_OOM};
-    }
+    for (int th = spawned; th < nth; ++th) lists_for(th);   // ranges that got no thread
+    lists_for(0);
+    for (auto& t : pool) t.join();
+  }
+  size_t len = 0;
+  bool cut = false;
+  for (int th = 0; th < nth; ++th) {
+    len += part[(size_t)th].size();
+    cut = cut || failed[(size_t)th];
+  }
+  if (cut || len > (size_t)INT32_MAX / 2) {
+    set_err(c, "treecode interaction lists too long");
+    throw Fail{GNK_ERR_OOM};
+  }
+  std::vector<int> list;
+  list.reserve(len);
+  for (int th = 0; th < nth; ++th) {
+    const int t0 = (int)((int64_t)T.tiles * th / nth), t1 = (int)((int64_t)T.tiles * (th + 1) / nth);
+    const int off = (int)list.size();
+    for (int t = t0; t < t1; ++t)
+      for (int k = 0; k <= 4 * S; ++k) seg[(size_t)t * (4 * S + 1) + k] += off;
+    list.insert(list.end(), part[(size_t)th].begin(), part[(size_t)th].end());
   }
   T.list_len = list.size();
   T.list = upload(c, "t_list", list);
