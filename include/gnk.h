@@ -171,7 +171,12 @@ GNK_API const char* gnk_version(void);
  *   flops             : N(N-1) * (16 + 8 (columns - 1)) summed (16 flops per
  *                       pair and column 1, 8 per further column sharing it)
  *   launches1, ms1, pairs1 : the single-column FP64 launches alone
- *   *_mixed           : the mixed-precision launches (also in the totals) */
+ *   *_mixed           : the mixed-precision launches (also in the totals)
+ *   *_tree            : the treecode products (also in the totals; their flops
+ *                       field counts the direct sum they replace): launches,
+ *                       time, and the work their interaction lists imply,
+ *                       8 p_e + 8 flops per target and far box (a p_e-term
+ *                       expansion), 16 per near pair, for each column */
 typedef struct {
   int64_t launches;
   double ms;
@@ -183,6 +188,9 @@ typedef struct {
   int64_t launches_mixed;   /* mixed-precision launches (any column count) */
   double ms_mixed;
   double pair_cols_mixed;
+  int64_t launches_tree;    /* treecode products (any column count) */
+  double ms_tree;
+  double flops_tree;
 } gnk_prof;
 
 /* enable: 1 starts recording, 0 stops (already recorded launches are kept).

@@ -90,8 +90,11 @@ hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, 
 // Treecode (csrc/tree.hip): boxes of kLeaf << l consecutive nodes at level l
 constexpr int kLeaf = 256;
 constexpr int kTreeMaxP = 48;
-// bounding circles of the boxes of `tile` nodes of eta (N nodes) into out
-hipError_t launch_box_bounds(const double2* eta, int N, int tile, double4* out, hipStream_t st);
+// bounding circles of the boxes of every level (level l: boxes of kLeaf << l
+// consecutive nodes of eta, at out + level_off[l]); bbox and rbits: scratch of
+// one entry per box
+hipError_t launch_box_bounds(const double2* eta, int N, const int* level_off, const int* level_nb, int levels,
+                             double4* bbox, unsigned long long* rbits, double4* out, hipStream_t st);
 // multipole moments (p per box) of record weight field wo: leaves directly,
 // then every level from its children; level_off/level_nb: host arrays
 hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, const double4* bounds,

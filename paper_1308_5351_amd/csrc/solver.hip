@@ -60,6 +60,8 @@ struct gnk_ctx {
     hipEvent_t a, b;
     double pair_cols, flops, pairs1;
     bool mixed, single;
+    double tree_flops = 0.0;   // treecode products: the work of their lists
+    bool tree = false;
   };
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -228,6 +230,7 @@ struct Batch {
     int* seg = nullptr;
     int* list = nullptr;
     size_t list_len = 0;
+    double flops = 0.0;   // per column: 8 p_e + 8 per (target, far box), 16 per near pair
   } tree;
 };
 
@@ -524,9 +527,9 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   T.nbox = total;
   T.bounds = ws<double4>(c, "t_bounds", total);
   T.mom = ws<double2>(c, "t_mom", (size_t)total * T.p);
-  for (int l = 0; l < T.levels; ++l)
-    HIPCHK(c, launch_box_bounds(D.eta, N, (int)std::min<int64_t>((int64_t)kLeaf << l, (int64_t)1 << 30),
-                                T.bounds + T.off[l], c->stream));
+  double4* bbox = ws<double4>(c, "t_bbox", total);
+  unsigned long long* rbits = ws<unsigned long long>(c, "t_rbits", total);
+  HIPCHK(c, launch_box_bounds(D.eta, N, T.off.data(), T.nb.data(), T.levels, bbox, rbits, T.bounds, c->stream));
   T.tiles = (N + kt - 1) / kt;
   std::vector<double4> hb(total), ht(T.tiles);
   HIPCHK(c, hipMemcpyAsync(hb.data(), T.bounds, sizeof(double4) * total, hipMemcpyDeviceToHost, c->stream));
@@ -546,6 +549,7 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   const int nth = std::max(1, std::min({16, (int)std::thread::hardware_concurrency(), (T.tiles + 63) / 64}));
   std::vector<std::vector<int>> part((size_t)nth);
   std::vector<char> failed((size_t)nth, 0);
+  std::vector<double> work((size_t)nth, 0.0);
   auto lists_for = [&](int th) {
     const int t0 = (int)((int64_t)T.tiles * th / nth), t1 = (int)((int64_t)T.tiles * (th + 1) / nth);
     std::vector<int>& lst = part[(size_t)th];
@@ -558,6 +562,7 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
         cost.clear();
         const double4 tt = ht[t];
         const int base = t * kt, top = T.levels - 1;
+        const double nt = (double)std::min(kt, N - base);
         for (int b = 0; b < T.nb[top]; ++b) stack.push_back({top, b});
         while (!stack.empty()) {
           const auto [l, b] = stack.back();
@@ -569,6 +574,7 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
             const int pe = std::max(2, std::min(T.p, (int)std::ceil(ltol / std::log(rho))));
             ent.push_back((pe << 24) | (T.off[l] + b));
             cost.push_back(4.0 * pe + 24.0);
+            work[(size_t)th] += nt * (8.0 * pe + 8.0);
           } else if (l == 0) {
             for (int k = 0; k < kLeaf / 64; ++k) {
               const int j0 = b * kLeaf + k * 64;
@@ -577,6 +583,7 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
               const int ov = std::max(0, std::min(j1, base + kt) - std::max(j0, base));
               ent.push_back(~(j0 / 64));
               cost.push_back(cnear * (j1 - j0 - ov) + cself * ov);
+              work[(size_t)th] += 16.0 * (nt * (j1 - j0) - ov);
             }
           } else {
             // children pushed in reverse so that the list keeps node order
@@ -620,7 +627,9 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   }
   size_t len = 0;
   bool cut = false;
+  T.flops = 0.0;
   for (int th = 0; th < nth; ++th) {
+    T.flops += work[(size_t)th];
     len += part[(size_t)th].size();
     cut = cut || failed[(size_t)th];
   }
@@ -657,7 +666,7 @@ void tree_pairs(gnk_ctx* c, Batch& B, int p, const int* active) {
     // counted as the pairs the direct sum would take
     const double pairs = (double)D.N * (double)(D.N - 1);
     pr = gnk_ctx::ProfRec{pool_event(c), pool_event(c), pairs * wcols, pairs * (16.0 + 8.0 * (wcols - 1)),
-                          wcols == 1 ? pairs : 0.0, false, wcols == 1};
+                          wcols == 1 ? pairs : 0.0, false, wcols == 1, T.flops * wcols, true};
     HIPCHK(c, hipEventRecord(pr.a, c->stream));
   }
   for (int col = 0; col < wcols; ++col) {
@@ -1523,6 +1532,11 @@ gnk_status gnk_profile_read(gnk_ctx* c, gnk_prof* out, int reset) {
       A.ms += ms;
       A.pair_cols += r.pair_cols;
       A.flops += r.flops;
+      if (r.tree) {
+        A.launches_tree += 1;
+        A.ms_tree += ms;
+        A.flops_tree += r.tree_flops;
+      }
       if (r.mixed) {
         A.launches_mixed += 1;
         A.ms_mixed += ms;

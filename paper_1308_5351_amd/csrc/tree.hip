@@ -35,14 +35,19 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-// bounding circle {cx, cy, r, 0} (centre of the bounding box) of the nodes
-// [b tile, (b + 1) tile) of eta; one wavefront per box
-__global__ __launch_bounds__(64) void k_box_bounds(const double2* __restrict__ eta, int N, int tile,
-                                                   double4* __restrict__ out) {
+// Bounding circles {cx, cy, r, 0} of the boxes of every level: the centre of
+// the box's bounding box and the largest distance of its nodes from it. Leaf
+// bounding boxes come from their nodes (one wavefront per leaf), a parent's
+// from its two children (exact: min and max), and the radii of all levels from
+// one pass over the nodes (one 256-thread block per leaf, whose nodes lie in a
+// single box of every level; a block maximum, then an atomic maximum on the
+// radius's bit pattern, which orders non-negative doubles as unsigned integers).
+__global__ __launch_bounds__(64) void k_leaf_bbox(const double2* __restrict__ eta, int N,
+                                                  double4* __restrict__ bbox) {
   const int b = blockIdx.x, lane = threadIdx.x;
-  const int i0 = b * tile;
+  const int i0 = b * kLeaf;
   if (i0 >= N) return;
-  const int i1 = min(N, i0 + tile);
+  const int i1 = min(N, i0 + kLeaf);
   double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
   for (int i = i0 + lane; i < i1; i += 64) {
     const double2 e = eta[i];
@@ -58,15 +63,62 @@ __global__ __launch_bounds__(64) void k_box_bounds(const double2* __restrict__ e
     ymin = fmin(ymin, __shfl_xor(ymin, off, 64));
     ymax = fmax(ymax, __shfl_xor(ymax, off, 64));
   }
-  const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax);
-  double r = 0.0;
-  for (int i = i0 + lane; i < i1; i += 64) {
-    const double2 e = eta[i];
-    r = fmax(r, sqrt((e.x - cx) * (e.x - cx) + (e.y - cy) * (e.y - cy)));
+  if (lane == 0) bbox[b] = make_double4(xmin, xmax, ymin, ymax);
+}
+
+__global__ void k_bbox_merge(const double4* __restrict__ child, int nchild, double4* __restrict__ parent, int npar) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= npar) return;
+  double4 v = child[2 * b];
+  if (2 * b + 1 < nchild) {
+    const double4 u = child[2 * b + 1];
+    v = make_double4(fmin(v.x, u.x), fmax(v.y, u.y), fmin(v.z, u.z), fmax(v.w, u.w));
   }
+  parent[b] = v;
+}
+
+// centres of all boxes; radii (as bits) cleared for the maximum that follows
+__global__ void k_box_centres(const double4* __restrict__ bbox, int nbox, double4* __restrict__ out,
+                              unsigned long long* __restrict__ rbits) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbox) return;
+  const double4 v = bbox[b];
+  out[b] = make_double4(0.5 * (v.x + v.y), 0.5 * (v.z + v.w), 0.0, 0.0);
+  rbits[b] = 0ull;
+}
+
+struct LevelTable {
+  int off[32];
+};
+
+__global__ __launch_bounds__(256) void k_box_radii(const double2* __restrict__ eta, int N, LevelTable lv, int levels,
+                                                   const double4* __restrict__ out,
+                                                   unsigned long long* __restrict__ rbits) {
+  __shared__ double sh[4];
+  const int leaf = blockIdx.x, t = threadIdx.x;
+  const int i = leaf * kLeaf + t;
+  const bool in = i < N;
+  const double2 e = in ? eta[i] : make_double2(0.0, 0.0);
+  for (int l = 0; l < levels; ++l) {
+    const int box = lv.off[l] + (leaf >> l);
+    const double4 c = out[box];
+    double r = in ? sqrt((e.x - c.x) * (e.x - c.x) + (e.y - c.y) * (e.y - c.y)) : 0.0;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
-  if (lane == 0) out[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
+    for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off, 64));
+    if ((t & 63) == 0) sh[t >> 6] = r;
+    __syncthreads();
+    if (t == 0)
+      atomicMax(rbits + box, (unsigned long long)__double_as_longlong(fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]))));
+    __syncthreads();
+  }
+}
+
+// widen by a relative margin so rounding of the centre cannot hide a node
+__global__ void k_box_finish(const unsigned long long* __restrict__ rbits, int nbox, double4* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbox) return;
+  const double r = __longlong_as_double((long long)rbits[b]);
+  out[b].z = r * (1.0 + 1e-12) + 1e-300;
 }
 
 // Leaf moments of weight column wo (record field) about the leaf centres:
@@ -247,9 +299,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 
 }  // namespace
 
-hipError_t launch_box_bounds(const double2* eta, int N, int tile, double4* out, hipStream_t st) {
-  const int nb = (N + tile - 1) / tile;
-  k_box_bounds<<<nb, 64, 0, st>>>(eta, N, tile, out);
+hipError_t launch_box_bounds(const double2* eta, int N, const int* level_off, const int* level_nb, int levels,
+                             double4* bbox, unsigned long long* rbits, double4* out, hipStream_t st) {
+  if (levels < 1 || levels > 32) return hipErrorInvalidValue;
+  k_leaf_bbox<<<level_nb[0], 64, 0, st>>>(eta, N, bbox);
+  hipError_t e = hipGetLastError();
+  for (int l = 0; l + 1 < levels && e == hipSuccess; ++l) {
+    const int npar = level_nb[l + 1];
+    k_bbox_merge<<<(npar + 255) / 256, 256, 0, st>>>(bbox + level_off[l], level_nb[l], bbox + level_off[l + 1], npar);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  const int nbox = level_off[levels - 1] + level_nb[levels - 1];
+  k_box_centres<<<(nbox + 255) / 256, 256, 0, st>>>(bbox, nbox, out, rbits);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  LevelTable lv{};
+  for (int l = 0; l < levels; ++l) lv.off[l] = level_off[l];
+  k_box_radii<<<level_nb[0], 256, 0, st>>>(eta, N, lv, levels, out, rbits);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_box_finish<<<(nbox + 255) / 256, 256, 0, st>>>(rbits, nbox, out);
   return hipGetLastError();
 }
 
