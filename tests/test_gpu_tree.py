@@ -134,3 +134,24 @@ def test_tree_argument_errors(gk, ctx):
     assert e.value.status == gk.ERR_ARG
     mu, h, infos, st = ctx.fbie(dd, _cuda(gam))
     assert st == gk.OK
+
+
+def test_tree_profile_counts(gk, ctx):
+    # the profile separates the treecode products and counts the work of their lists:
+    # at most the direct sum's 16 N(N-1) flops per column, and well below it for large N
+    dom, _ = wl.config4()
+    N = dom.eta.shape[0]
+    w = np.cos(3 * np.angle(dom.eta)) * dom.etap
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    ctx.cauchy_sum(_cuda(dom.eta), _cuda(w), far_tol=1e-12)
+    p = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    assert p["launches_tree"] == 1 and p["ms_tree"] > 0.0
+    direct = 16.0 * N * (N - 1)
+    assert 0.0 < p["flops_tree"] < 0.2 * direct
+    ctx.profile(True)
+    ctx.cauchy_sum(_cuda(dom.eta[:20000]), _cuda(w[:20000]))
+    p = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    assert p["launches_tree"] == 0 and p["flops_tree"] == 0.0 and p["launches"] >= 1
