@@ -269,6 +269,33 @@ def far_field(gnk, ctx, torch):
     return out
 
 
+def circulant_rate(gnk, ctx, torch):
+    """The circulant products L-hat x (eq. (e:L-bs), by FFT) of the batched workload:
+    every (component, right-hand side) of the 64 domains, one launch per block length,
+    timed by the library's events inside a batched FBIE call (right-hand side y and h);
+    one GMRES step (restart 1, maxit 1) keeps the call short."""
+    import workloads as wl
+    batch = wl.config3()
+    doms = [gnk.DeviceDomain.from_host(d) for d, _ in batch]
+    gams = [torch.from_numpy(g.copy()).cuda() for _, g in batch]
+    kw = dict(restart=1, maxit=1, tol=1e-12)
+    log("circulant products: batched workload")
+    ctx.fbie_batched(doms, gams, **kw)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    ctx.fbie_batched(doms, gams, **kw)
+    p = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    units = sum(d.N * g.shape[1] for d, g in batch)
+    gbs = p["bytes_fft"] / (p["ms_fft"] * 1e-3) / 1e9
+    return {"workload": "64 unbounded domains, m+1 in 2..40, n in 256..2048, m+1 right-hand sides each: "
+                        f"{units} unknown-columns per product, block lengths 256..2048, one launch per length",
+            "calls": p["launches_fft"], "ms_per_call": round(p["ms_fft"] / max(1, p["launches_fft"]), 4),
+            "bytes_per_call": p["bytes_fft"] / max(1, p["launches_fft"]),
+            "gb_s": round(gbs, 1), "frac_hbm_peak": round(gbs / 8000.0, 4)}
+
+
 def batched_vs_plain(gnk, ctx, torch):
     import workloads as wl
     batch = wl.config3()
@@ -325,6 +352,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed and batched comparisons")
     ap.add_argument("--batched-mixed-only", action="store_true",
                     help="run only the 64-domain batched solve in mixed precision (warm-up + one timed call)")
+    ap.add_argument("--circulant-only", action="store_true",
+                    help="run only the circulant-product measurement (for kernel traces of the FFT)")
     ap.add_argument("--far-field-only", action="store_true",
                     help="run only the treecode comparison (for kernel traces of the treecode)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -352,6 +381,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"batched_mixed_s": round(time.perf_counter() - t, 3), "status": st,
                           "max_iters": max(i["inner_it"] for inf in infos for i in inf)}), flush=True)
+        ctx.close()
+        return
+
+    if args.circulant_only:
+        ctx = gnk.Context(0)
+        print(json.dumps({"circulant": circulant_rate(gnk, ctx, torch)}), flush=True)
         ctx.close()
         return
 
@@ -445,6 +480,7 @@ def main():
         out["subtraction_ablation"] = subtraction_ablation(gnk, ctx, torch)
         out["far_field"] = far_field(gnk, ctx, torch)
         out["slit_maps"] = slit_maps(gnk, ctx, torch)
+        out["circulant"] = circulant_rate(gnk, ctx, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(dom)

@@ -176,7 +176,11 @@ GNK_API const char* gnk_version(void);
  *                       field counts the direct sum they replace): launches,
  *                       time, and the work their interaction lists imply,
  *                       8 p_e + 8 flops per target and far box (a p_e-term
- *                       expansion), 16 per near pair, for each column */
+ *                       expansion), 16 per near pair, for each column
+ *   *_fft             : the circulant products L-hat x (not in the totals):
+ *                       launches (one per call, all block lengths), time, and
+ *                       algorithmic bytes, 24 per unknown and column (read x,
+ *                       read and write y) */
 typedef struct {
   int64_t launches;
   double ms;
@@ -191,6 +195,9 @@ typedef struct {
   int64_t launches_tree;    /* treecode products (any column count) */
   double ms_tree;
   double flops_tree;
+  int64_t launches_fft;     /* circulant products */
+  double ms_fft;
+  double bytes_fft;
 } gnk_prof;
 
 /* enable: 1 starts recording, 0 stops (already recorded launches are kept).

@@ -5,13 +5,17 @@
 // first column; fft(b)_k equals 2 i k / n for the signed frequency |k| < n/2
 // and 0 at k = n/2, so the symbol is applied in closed form.
 //
-// gfx950 mapping: one workgroup per PAIR of real length-n columns (two
-// components, or two right-hand sides): because L is a real matrix,
+// gfx950 mapping: each complex vector carries a PAIR of real length-n columns
+// (two components, or two right-hand sides): because L is a real matrix,
 // L (x_a + i x_b) = L x_a + i L x_b, so one complex FFT carries two real
-// columns with no post-processing. The transform runs in LDS:
-// a radix-2 decimation-in-frequency pass (natural order in, bit-reversed out),
-// the symbol multiply in bit-reversed order, then a decimation-in-time inverse
-// pass (bit-reversed in, natural out), so no permutation pass is needed.
+// columns with no post-processing. A workgroup holds 2048 complex elements
+// (2048 / n vectors, one for longer n) in LDS: a decimation-in-frequency
+// transform (natural order in, bit-reversed out), the symbol multiply in
+// bit-reversed order, then a decimation-in-time inverse (bit-reversed in,
+// natural out), so no permutation pass is needed. The radix-2 stages run
+// three at a time on eight register-resident elements per thread, so a
+// length-2048 product takes 7 trips through LDS instead of 24; the first pass
+// reads x and the last adds into y directly.
 // Global traffic is one read of x and one read-modify-write of y per element.
 // The vectors are given as a list of flat offsets, so one launch covers every
 // component of every column (and of every domain with this n).
@@ -56,67 +60,158 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {   // a * conj(b
   return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
-// vectors: offs[v] is the flat offset of length-n vector v; block b takes v = 2b, 2b+1
-__global__ __launch_bounds__(kFftThreads) void k_circulant_fft(const double* __restrict__ x, double* __restrict__ y,
-                                                               const int64_t* __restrict__ offs, int n, int logn,
-                                                               int V, double sign, const double2* __restrict__ tw) {
-  extern __shared__ double2 z[];
-  const int va = 2 * blockIdx.x;
-  const int vb = va + 1;
-  const bool hasb = vb < V;
-  const int64_t oa = offs[va];
-  const int64_t ob = hasb ? offs[vb] : 0;
-  const double* xa = x + oa;
-  const double* xb = x + ob;
-  for (int p = threadIdx.x; p < n; p += blockDim.x) z[p] = make_double2(xa[p], hasb ? xb[p] : 0.0);
+// Radix-2 stages fused F at a time: a group of 2^F elements at stride q,
+// i0 + m q (m < 2^F), held in registers while the F stages act on it. DIF
+// stages run with spans q 2^(F-1) .. q, DIT stages with spans q .. q 2^(F-1);
+// each butterfly is the radix-2 one of its stage (twiddle index (i mod span)
+// * n / (2 span)), so the transform and its bit-reversed middle order are
+// those of the plain radix-2 passes.
+template <int F>
+__device__ __forceinline__ void dif_group(double2 (&v)[1 << F], int j, int q, int half,
+                                          const double2* __restrict__ tw) {
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    const int h = 1 << (F - 1 - f);
+    const int ts = half / (q * h);
+#pragma unroll
+    for (int m = 0; m < (1 << F); ++m) {
+      if (m & h) continue;
+      const double2 u = v[m], w = v[m + h];
+      v[m] = make_double2(u.x + w.x, u.y + w.y);
+      v[m + h] = cmul(make_double2(u.x - w.x, u.y - w.y), tw[(j + (m & (h - 1)) * q) * ts]);
+    }
+  }
+}
 
-  const int half = n >> 1;
-  // forward DIF: span = n/2 .. 1
-  for (int ls = logn - 1; ls >= 0; --ls) {
-    __syncthreads();
-    const int span = 1 << ls;
-    const int tstride = half >> ls;   // n / (2 span)
-    for (int b = threadIdx.x; b < half; b += blockDim.x) {
-      const int j = b & (span - 1);
-      const int i0 = ((b >> ls) << (ls + 1)) + j;
-      const int i1 = i0 + span;
-      const double2 u = z[i0], v = z[i1];
-      z[i0] = make_double2(u.x + v.x, u.y + v.y);
-      z[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), tw[j * tstride]);
+template <int F>
+__device__ __forceinline__ void dit_group(double2 (&v)[1 << F], int j, int q, int half,
+                                          const double2* __restrict__ tw) {
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    const int h = 1 << f;
+    const int ts = half / (q * h);
+#pragma unroll
+    for (int m = 0; m < (1 << F); ++m) {
+      if (m & h) continue;
+      const double2 u = v[m];
+      const double2 w = cmulc(v[m + h], tw[(j + (m & (h - 1)) * q) * ts]);
+      v[m] = make_double2(u.x + w.x, u.y + w.y);
+      v[m + h] = make_double2(u.x - w.x, u.y - w.y);
     }
   }
-  __syncthreads();
-  // symbol (2 i k / n) with the 1/n of the inverse folded in; k = bitrev(pos)
-  const double scale = 2.0 / ((double)n * (double)n);
-  for (int pos = threadIdx.x; pos < n; pos += blockDim.x) {
-    const int k = (int)(__brev((unsigned)pos) >> (32 - logn));
-    const int ks = (k < half) ? k : ((k == half) ? 0 : k - n);
-    const double c = scale * (double)ks;
-    const double2 v = z[pos];
-    z[pos] = make_double2(-c * v.y, c * v.x);
-  }
-  // inverse DIT: span = 1 .. n/2, conjugate twiddles
-  for (int ls = 0; ls < logn; ++ls) {
-    __syncthreads();
-    const int span = 1 << ls;
-    const int tstride = half >> ls;
-    for (int b = threadIdx.x; b < half; b += blockDim.x) {
-      const int j = b & (span - 1);
-      const int i0 = ((b >> ls) << (ls + 1)) + j;
-      const int i1 = i0 + span;
-      const double2 u = z[i0];
-      const double2 v = cmulc(z[i1], tw[j * tstride]);
-      z[i0] = make_double2(u.x + v.x, u.y + v.y);
-      z[i1] = make_double2(u.x - v.x, u.y - v.y);
+}
+
+// Complex elements per workgroup: P = kFftElems / n vectors of length n (one
+// for n >= kFftElems), each carrying two real columns.
+constexpr int kFftElems = 2048;
+
+struct FftArgs {
+  const double* x;
+  double* y;
+  const int64_t* offs;
+  int n, logn, V, P;
+  double sign;
+  const double2* tw;
+};
+
+// One pass of F fused stages over every group of the workgroup's P vectors.
+// FIRST: the elements come from x (global), not LDS. SYMBOL: after the last
+// DIF stage, multiply by the symbol (2 i k / n, with the 1/n of the inverse),
+// k the bit reversal of the position. LAST: the results go to y (global,
+// y += sign * result) instead of LDS.
+template <int F, bool DIF, bool FIRST, bool SYMBOL, bool LAST>
+__device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q) {
+  const int n = A.n, half = n >> 1;
+  const int per = n >> F;   // groups per vector
+  for (int g = threadIdx.x; g < A.P * per; g += blockDim.x) {
+    const int vl = g / per, gg = g - vl * per;
+    const int blk = gg / q, j = gg - blk * q;
+    const int i0 = (blk << F) * q + j;
+    double2* zv = z + (size_t)vl * n;
+    const int va = 2 * (blockIdx.x * A.P + vl);
+    double2 v[1 << F];
+    if constexpr (FIRST) {
+      const bool hasa = va < A.V, hasb = va + 1 < A.V;
+      const double* xa = A.x + (hasa ? A.offs[va] : 0);
+      const double* xb = A.x + (hasb ? A.offs[va + 1] : 0);
+#pragma unroll
+      for (int m = 0; m < (1 << F); ++m) {
+        const int p = i0 + m * q;
+        v[m] = make_double2(hasa ? xa[p] : 0.0, hasb ? xb[p] : 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < (1 << F); ++m) v[m] = zv[i0 + m * q];
+    }
+    if constexpr (DIF) dif_group<F>(v, j, q, half, A.tw);
+    else dit_group<F>(v, j, q, half, A.tw);
+    if constexpr (SYMBOL) {
+      const double scale = 2.0 / ((double)n * (double)n);
+#pragma unroll
+      for (int m = 0; m < (1 << F); ++m) {
+        const int pos = i0 + m * q;
+        const int k = (int)(__brev((unsigned)pos) >> (32 - A.logn));
+        const int ks = (k < half) ? k : ((k == half) ? 0 : k - n);
+        const double c = scale * (double)ks;
+        v[m] = make_double2(-c * v[m].y, c * v[m].x);
+      }
+    }
+    if constexpr (LAST) {
+      const bool hasa = va < A.V, hasb = va + 1 < A.V;
+      double* ya = A.y + (hasa ? A.offs[va] : 0);
+      double* yb = A.y + (hasb ? A.offs[va + 1] : 0);
+#pragma unroll
+      for (int m = 0; m < (1 << F); ++m) {
+        const int p = i0 + m * q;
+        if (hasa) ya[p] += A.sign * v[m].x;
+        if (hasb) yb[p] += A.sign * v[m].y;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < (1 << F); ++m) zv[i0 + m * q] = v[m];
     }
   }
-  __syncthreads();
-  double* ya = y + oa;
-  double* yb = y + ob;
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    const double2 v = z[p];
-    ya[p] += sign * v.x;
-    if (hasb) yb[p] += sign * v.y;
+}
+
+template <bool DIF, bool FIRST, bool SYMBOL, bool LAST>
+__device__ __forceinline__ void fft_pass_f(int F, const FftArgs& A, double2* z, int q) {
+  if (F == 3) fft_pass<3, DIF, FIRST, SYMBOL, LAST>(A, z, q);
+  else if (F == 2) fft_pass<2, DIF, FIRST, SYMBOL, LAST>(A, z, q);
+  else fft_pass<1, DIF, FIRST, SYMBOL, LAST>(A, z, q);
+}
+
+// y_k += sign * L x_k for the vectors listed in offs (V of them, length n, a
+// power of two): workgroup b takes the complex vectors b P .. b P + P - 1,
+// vector c carrying the real columns 2c and 2c + 1. Forward DIF (natural ->
+// bit-reversed) in passes of up to three fused stages, the first reading x,
+// the last applying the symbol; inverse DIT (bit-reversed -> natural), the
+// last pass adding into y. Between passes the vectors sit in LDS.
+__global__ __launch_bounds__(kFftThreads) void k_circulant_fft(FftArgs A) {
+  extern __shared__ double2 z[];
+  const int L = A.logn;
+  const int np = (L + 2) / 3;   // passes per direction; all of 3 stages but the last (L - 3 (np - 1))
+  // forward: pass t covers stages with spans n/2 >> 3t .. ; its smallest span is q
+  int top = L;                  // stages above this pass
+  for (int t = 0; t < np; ++t) {
+    const int F = (t + 1 < np) ? 3 : L - 3 * (np - 1);
+    const int q = 1 << (top - F);
+    if (t > 0) __syncthreads();
+    const bool first = t == 0, last = t + 1 == np;
+    if (first && last) fft_pass_f<true, true, true, false>(F, A, z, q);
+    else if (first) fft_pass_f<true, true, false, false>(F, A, z, q);
+    else if (last) fft_pass_f<true, false, true, false>(F, A, z, q);
+    else fft_pass_f<true, false, false, false>(F, A, z, q);
+    top -= F;
+  }
+  // inverse: the short pass first (smallest spans), then passes of three
+  int bottom = 0;
+  for (int t = 0; t < np; ++t) {
+    const int F = (t == 0) ? L - 3 * (np - 1) : 3;
+    const int q = 1 << bottom;
+    __syncthreads();
+    if (t + 1 == np) fft_pass_f<false, false, false, true>(F, A, z, q);
+    else fft_pass_f<false, false, false, false>(F, A, z, q);
+    bottom += F;
   }
 }
 
@@ -162,9 +257,12 @@ hipError_t launch_circulant(const double* x, double* y, const int64_t* offs, int
                             const double2* twiddle, hipStream_t st) {
   if (nvec <= 0) return hipSuccess;
   if (circulant_uses_fft(n)) {
-    const unsigned pairs = (unsigned)((nvec + 1) / 2);
-    const size_t lds = (size_t)n * sizeof(double2);
-    k_circulant_fft<<<pairs, kFftThreads, lds, st>>>(x, y, offs, (int)n, ilog2(n), nvec, sign, twiddle);
+    const int P = (int)std::max<int64_t>(1, kFftElems / n);
+    const int64_t cvec = (nvec + 1) / 2;
+    const unsigned blocks = (unsigned)((cvec + P - 1) / P);
+    const size_t lds = (size_t)P * n * sizeof(double2);
+    FftArgs A{x, y, offs, (int)n, ilog2(n), nvec, P, sign, twiddle};
+    k_circulant_fft<<<blocks, kFftThreads, lds, st>>>(A);
   } else {
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)nvec);
     k_circulant_direct<<<grid, 256, 0, st>>>(x, y, offs, (int)n, sign, reinterpret_cast<const double*>(twiddle));

@@ -62,6 +62,8 @@ struct gnk_ctx {
     bool mixed, single;
     double tree_flops = 0.0;   // treecode products: the work of their lists
     bool tree = false;
+    double fft_bytes = 0.0;    // circulant products (kept out of the pair totals)
+    bool fft = false;
   };
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -732,7 +734,18 @@ void build_circ(gnk_ctx* c, Batch& B) {
 
 void circulant(gnk_ctx* c, Batch& B, const double* x, double* y, double sign) {
   build_circ(c, B);
+  gnk_ctx::ProfRec pr{};
+  if (c->prof) {
+    double units = 0.0;
+    for (auto& ci : B.circ) units += (double)ci.nvec * (double)ci.n;
+    pr = gnk_ctx::ProfRec{pool_event(c), pool_event(c), 0.0, 0.0, 0.0, false, false, 0.0, false, 24.0 * units, true};
+    HIPCHK(c, hipEventRecord(pr.a, c->stream));
+  }
   for (auto& ci : B.circ) HIPCHK(c, launch_circulant(x, y, ci.offs, ci.nvec, ci.n, sign, ci.tw, c->stream));
+  if (c->prof) {
+    HIPCHK(c, hipEventRecord(pr.b, c->stream));
+    c->prof_pending.push_back(pr);
+  }
 }
 
 dim3 node_grid(const Batch& B) { return dim3(nblocks(B.maxN), (unsigned)B.ndom); }
@@ -1528,6 +1541,14 @@ gnk_status gnk_profile_read(gnk_ctx* c, gnk_prof* out, int reset) {
       float ms = 0.f;
       HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
       gnk_prof& A = c->prof_acc;
+      c->ev_pool.push_back(r.a);
+      c->ev_pool.push_back(r.b);
+      if (r.fft) {
+        A.launches_fft += 1;
+        A.ms_fft += ms;
+        A.bytes_fft += r.fft_bytes;
+        continue;
+      }
       A.launches += 1;
       A.ms += ms;
       A.pair_cols += r.pair_cols;
@@ -1546,8 +1567,6 @@ gnk_status gnk_profile_read(gnk_ctx* c, gnk_prof* out, int reset) {
         A.ms1 += ms;
         A.pairs1 += r.pairs1;
       }
-      c->ev_pool.push_back(r.a);
-      c->ev_pool.push_back(r.b);
     }
     c->prof_pending.clear();
     if (out) *out = c->prof_acc;

@@ -57,7 +57,8 @@ class Prof(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("pair_cols", C.c_double), ("flops", C.c_double),
                 ("launches1", C.c_int64), ("ms1", C.c_double), ("pairs1", C.c_double),
                 ("launches_mixed", C.c_int64), ("ms_mixed", C.c_double), ("pair_cols_mixed", C.c_double),
-                ("launches_tree", C.c_int64), ("ms_tree", C.c_double), ("flops_tree", C.c_double)]
+                ("launches_tree", C.c_int64), ("ms_tree", C.c_double), ("flops_tree", C.c_double),
+                ("launches_fft", C.c_int64), ("ms_fft", C.c_double), ("bytes_fft", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -290,3 +290,26 @@ def test_workspace_cap(gk, monkeypatch):
         c.fbie(dd, _cuda(gam[:, 0]))
     assert e.value.status == gk.ERR_OOM
     c.close()
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 64, 256, 512, 1024, 2048, 4096])
+def test_circulant_every_fft_length(gk, ctx, n):
+    # L-hat by FFT against the dense circulant blocks L_pq = (-1)^(p-q) (1/n) cot((p-q) pi/n):
+    # an odd number of real columns (m1 * nrhs), several vectors per workgroup for short n and
+    # a partly filled last workgroup
+    m1 = 1 if n == 2 else 3
+    nrhs = 7 if n <= 256 else 3
+    centres = [0j, 3.0 + 0.5j, -2.5 + 2.0j][:m1]
+    dom = wl.circles_unbounded(n, centres, [1.0, 0.7, 0.5][:m1])
+    print(f"[circulant] n={n} m1={m1} nrhs={nrhs}", flush=True)
+    dd = gk.DeviceDomain.from_host(dom)
+    rng = np.random.default_rng([wl.SEED, 62, n])
+    x = rng.normal(size=(dom.N, nrhs))
+    y = ctx.apply(dd, gk.OP_LHAT, _cuda(x)).cpu().numpy()
+    L = orc.circulant_L(n)
+    for k in range(m1):
+        blk = slice(k * n, (k + 1) * n)
+        ref = L @ x[blk]
+        # (for n = 2, L = 0 exactly; the dense form holds cot(pi/2) rounded, 6e-17)
+        scale = max((np.abs(L) @ np.abs(x[blk])).max(), np.abs(x[blk]).max() / n)
+        assert np.max(np.abs(y[blk] - ref)) / scale < 1e-13, k
