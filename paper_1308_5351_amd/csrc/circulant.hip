@@ -8,8 +8,9 @@
 // gfx950 mapping: each complex vector carries a PAIR of real length-n columns
 // (two components, or two right-hand sides): because L is a real matrix,
 // L (x_a + i x_b) = L x_a + i L x_b, so one complex FFT carries two real
-// columns with no post-processing. A workgroup holds 2048 complex elements
-// (2048 / n vectors, one for longer n) in LDS: a decimation-in-frequency
+// columns with no post-processing. A workgroup holds up to 2048 complex
+// elements (whole vectors; fewer when that leaves the chip short of
+// workgroups) in LDS: a decimation-in-frequency
 // transform (natural order in, bit-reversed out), the symbol multiply in
 // bit-reversed order, then a decimation-in-time inverse (bit-reversed in,
 // natural out), so no permutation pass is needed. The radix-2 stages run
@@ -65,39 +66,52 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {   // a * conj(b
 // stages run with spans q 2^(F-1) .. q, DIT stages with spans q .. q 2^(F-1);
 // each butterfly is the radix-2 one of its stage (twiddle index (i mod span)
 // * n / (2 span)), so the transform and its bit-reversed middle order are
-// those of the plain radix-2 passes.
-template <int F>
-__device__ __forceinline__ void dif_group(double2 (&v)[1 << F], int j, int q, int half,
-                                          const double2* __restrict__ tw) {
-#pragma unroll
-  for (int f = 0; f < F; ++f) {
-    const int h = 1 << (F - 1 - f);
-    const int ts = half / (q * h);
-#pragma unroll
-    for (int m = 0; m < (1 << F); ++m) {
-      if (m & h) continue;
-      const double2 u = v[m], w = v[m + h];
-      v[m] = make_double2(u.x + w.x, u.y + w.y);
-      v[m + h] = cmul(make_double2(u.x - w.x, u.y - w.y), tw[(j + (m & (h - 1)) * q) * ts]);
-    }
+// those of the plain radix-2 passes. In a stage whose partners are h apart,
+// the twiddles of the group are w_r = tw[j ts] exp(-i pi r / h), r < h <= 4:
+// one table load per stage, the rest constant rotations.
+template <int R, int H>
+__device__ __forceinline__ double2 rotate(double2 b) {
+  static_assert(R < H && H <= 4, "rotations for radix up to 8");
+  if constexpr (R == 0) {
+    return b;
+  } else if constexpr (2 * R == H) {
+    return make_double2(b.y, -b.x);                        // * (-i)
+  } else {
+    constexpr double c = 0.70710678118654752440;           // cos(pi/4)
+    constexpr double sr = (R == 1) ? c : -c;               // real part of exp(-i pi R/4)
+    return make_double2(sr * b.x + c * b.y, sr * b.y - c * b.x);   // * (sr - i c)
   }
 }
 
-template <int F>
-__device__ __forceinline__ void dit_group(double2 (&v)[1 << F], int j, int q, int half,
-                                          const double2* __restrict__ tw) {
-#pragma unroll
-  for (int f = 0; f < F; ++f) {
-    const int h = 1 << f;
-    const int ts = half / (q * h);
-#pragma unroll
-    for (int m = 0; m < (1 << F); ++m) {
-      if (m & h) continue;
-      const double2 u = v[m];
-      const double2 w = cmulc(v[m + h], tw[(j + (m & (h - 1)) * q) * ts]);
-      v[m] = make_double2(u.x + w.x, u.y + w.y);
-      v[m + h] = make_double2(u.x - w.x, u.y - w.y);
+template <int F, int f, bool DIF, int M = 0>
+__device__ __forceinline__ void stage(double2 (&v)[1 << F], double2 base) {
+  if constexpr (M < (1 << F)) {
+    constexpr int h = DIF ? (1 << (F - 1 - f)) : (1 << f);
+    if constexpr ((M & h) == 0) {
+      const double2 w = rotate<(M & (h - 1)), h>(base);
+      const double2 u = v[M];
+      if constexpr (DIF) {
+        const double2 t = v[M + h];
+        v[M] = make_double2(u.x + t.x, u.y + t.y);
+        v[M + h] = cmul(make_double2(u.x - t.x, u.y - t.y), w);
+      } else {
+        const double2 t = cmulc(v[M + h], w);
+        v[M] = make_double2(u.x + t.x, u.y + t.y);
+        v[M + h] = make_double2(u.x - t.x, u.y - t.y);
+      }
     }
+    stage<F, f, DIF, M + 1>(v, base);
+  }
+}
+
+template <int F, bool DIF, int f = 0>
+__device__ __forceinline__ void group_stages(double2 (&v)[1 << F], int j, int q, int half,
+                                             const double2* __restrict__ tw) {
+  if constexpr (f < F) {
+    constexpr int h = DIF ? (1 << (F - 1 - f)) : (1 << f);
+    const double2 base = tw[j * (half / (q * h))];
+    stage<F, f, DIF>(v, base);
+    group_stages<F, DIF, f + 1>(v, j, q, half, tw);
   }
 }
 
@@ -143,8 +157,7 @@ __device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q) {
 #pragma unroll
       for (int m = 0; m < (1 << F); ++m) v[m] = zv[i0 + m * q];
     }
-    if constexpr (DIF) dif_group<F>(v, j, q, half, A.tw);
-    else dit_group<F>(v, j, q, half, A.tw);
+    group_stages<F, DIF>(v, j, q, half, A.tw);
     if constexpr (SYMBOL) {
       const double scale = 2.0 / ((double)n * (double)n);
 #pragma unroll
@@ -257,12 +270,18 @@ hipError_t launch_circulant(const double* x, double* y, const int64_t* offs, int
                             const double2* twiddle, hipStream_t st) {
   if (nvec <= 0) return hipSuccess;
   if (circulant_uses_fft(n)) {
-    const int P = (int)std::max<int64_t>(1, kFftElems / n);
+    // complex elements per workgroup: kFftElems, halved (down to max(n, 512))
+    // while the launch would have fewer than 2048 workgroups; one thread per
+    // group of eight elements
     const int64_t cvec = (nvec + 1) / 2;
+    int64_t E = kFftElems;
+    while (E / 2 >= std::max<int64_t>(n, 512) && cvec * n / E < 2048) E /= 2;
+    const int P = (int)std::max<int64_t>(1, E / n);
     const unsigned blocks = (unsigned)((cvec + P - 1) / P);
+    const int threads = (int)std::min<int64_t>(kFftThreads, std::max<int64_t>(64, (int64_t)P * n / 8));
     const size_t lds = (size_t)P * n * sizeof(double2);
     FftArgs A{x, y, offs, (int)n, ilog2(n), nvec, P, sign, twiddle};
-    k_circulant_fft<<<blocks, kFftThreads, lds, st>>>(A);
+    k_circulant_fft<<<blocks, threads, lds, st>>>(A);
   } else {
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)nvec);
     k_circulant_direct<<<grid, 256, 0, st>>>(x, y, offs, (int)n, sign, reinterpret_cast<const double*>(twiddle));
