@@ -250,20 +250,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       const int box = ent & 0xFFFFFF, pe = ent >> 24;
       const double4 c = bd[box];
       const gptr<const double2> a = mm + (size_t)box * p;
+      // Horner in u = 1/(z - c) for every target at once: each moment is loaded
+      // once for the TPT targets, four at a time
+      double ux[TPT], uy[TPT], sx[TPT], sy[TPT];
 #pragma unroll
       for (int t = 0; t < TPT; ++t) {
         const double dx = tg[t].x - c.x, dy = tg[t].y - c.y;
         const double inv = refine_rcp(__builtin_fma(dy, dy, dx * dx));
-        const double ux = dx * inv, uy = -dy * inv;
-        double sx = 0.0, sy = 0.0;
-        for (int k = pe - 1; k >= 0; --k) {
-          const double2 ak = a[k];
-          const double nx = __builtin_fma(ux, sx, __builtin_fma(-uy, sy, ak.x));
-          sy = __builtin_fma(ux, sy, __builtin_fma(uy, sx, ak.y));
-          sx = nx;
+        ux[t] = dx * inv;
+        uy[t] = -dy * inv;
+        sx[t] = 0.0;
+        sy[t] = 0.0;
+      }
+      auto horner = [&](double2 ak) {
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) {
+          const double nx = __builtin_fma(ux[t], sx[t], __builtin_fma(-uy[t], sy[t], ak.x));
+          sy[t] = __builtin_fma(ux[t], sy[t], __builtin_fma(uy[t], sx[t], ak.y));
+          sx[t] = nx;
         }
-        acc.x[t][0] += ux * sx - uy * sy;
-        acc.y[t][0] += ux * sy + uy * sx;
+      };
+      int k = pe - 1;
+      for (; k >= 3; k -= 4) {
+        const double2 a0 = a[k], a1 = a[k - 1], a2 = a[k - 2], a3 = a[k - 3];
+        horner(a0);
+        horner(a1);
+        horner(a2);
+        horner(a3);
+      }
+      for (; k >= 0; --k) horner(a[k]);
+#pragma unroll
+      for (int t = 0; t < TPT; ++t) {
+        acc.x[t][0] += ux[t] * sx[t] - uy[t] * sy[t];
+        acc.y[t][0] += ux[t] * sy[t] + uy[t] * sx[t];
       }
     } else {
       const int ja = (~ent) * 64, jb = min(N, ja + 64);
