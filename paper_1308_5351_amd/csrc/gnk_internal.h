@@ -90,14 +90,18 @@ hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, 
 // Treecode (csrc/tree.hip): boxes of kLeaf << l consecutive nodes at level l
 constexpr int kLeaf = 256;
 constexpr int kTreeMaxP = 48;
-// bounding circles of the boxes of every level (level l: boxes of kLeaf << l
-// consecutive nodes of eta, at out + level_off[l]); bbox and rbits: scratch of
-// one entry per box
+// bounding circles of the boxes of every level (at out + level_off[l]): level
+// 0 holds the leaves in slot order (perm: slot -> leaf, invp: leaf -> slot),
+// box b of level l the slots [b 2^l, (b + 1) 2^l); leafbox: the leaves'
+// bounding boxes; bbox and rbits: scratch of one entry per box
 hipError_t launch_box_bounds(const double2* eta, int N, const int* level_off, const int* level_nb, int levels,
-                             double4* bbox, unsigned long long* rbits, double4* out, hipStream_t st);
+                             const double4* leafbox, const int* perm, const int* invp, double4* bbox,
+                             unsigned long long* rbits, double4* out, hipStream_t st);
+// bounding boxes {xmin, xmax, ymin, ymax} of the leaves (kLeaf consecutive nodes)
+hipError_t launch_leaf_boxes(const double2* eta, int N, int nleaf, double4* leafbox, hipStream_t st);
 // multipole moments (p per box) of record weight field wo: leaves directly,
 // then every level from its children; level_off/level_nb: host arrays
-hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, const double4* bounds,
+hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, const double4* bounds, const int* perm,
                                const int* level_off, const int* level_nb, int levels, int p, double2* mom,
                                hipStream_t st);
 // far boxes by their moments, near 64-node blocks directly, for weight column

@@ -233,6 +233,8 @@ struct Batch {
     int* list = nullptr;
     size_t list_len = 0;
     double flops = 0.0;   // per column: 8 p_e + 8 per (target, far box), 16 per near pair
+    int* perm = nullptr;  // level-0 slot -> leaf (device), and leaf -> slot
+    int* invp = nullptr;
   } tree;
 };
 
@@ -531,7 +533,46 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   T.mom = ws<double2>(c, "t_mom", (size_t)total * T.p);
   double4* bbox = ws<double4>(c, "t_bbox", total);
   unsigned long long* rbits = ws<unsigned long long>(c, "t_rbits", total);
-  HIPCHK(c, launch_box_bounds(D.eta, N, T.off.data(), T.nb.data(), T.levels, bbox, rbits, T.bounds, c->stream));
+  // The leaves take the level-0 slots in the Morton order of their centres, so
+  // that a box of 2^l slots is a compact cluster of the plane (in node order a
+  // box could join boundary pieces far apart, and few boxes would be far).
+  const int nleaf = T.nb[0];
+  double4* lbox = ws<double4>(c, "t_lbox", nleaf);
+  HIPCHK(c, launch_leaf_boxes(D.eta, N, nleaf, lbox, c->stream));
+  std::vector<double4> hl((size_t)nleaf);
+  HIPCHK(c, hipMemcpyAsync(hl.data(), lbox, sizeof(double4) * nleaf, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<int> perm((size_t)nleaf), invp((size_t)nleaf);
+  {
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    for (const auto& b : hl) {
+      const double cx = 0.5 * (b.x + b.y), cy = 0.5 * (b.z + b.w);
+      x0 = std::min(x0, cx), x1 = std::max(x1, cx), y0 = std::min(y0, cy), y1 = std::max(y1, cy);
+    }
+    const double span = std::max(x1 - x0, y1 - y0);
+    const double sc = span > 0.0 ? 65535.0 / span : 0.0;
+    auto spread = [](uint64_t v) {   // bits of v at the even positions
+      v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
+      v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
+      v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
+      v = (v | (v << 2)) & 0x3333333333333333ull;
+      return (v | (v << 1)) & 0x5555555555555555ull;
+    };
+    std::vector<uint64_t> code((size_t)nleaf);
+    for (int b = 0; b < nleaf; ++b) {
+      const double cx = 0.5 * (hl[b].x + hl[b].y), cy = 0.5 * (hl[b].z + hl[b].w);
+      const uint64_t qx = (uint64_t)std::min(65535.0, std::max(0.0, (cx - x0) * sc));
+      const uint64_t qy = (uint64_t)std::min(65535.0, std::max(0.0, (cy - y0) * sc));
+      code[b] = (spread(qx) << 1) | spread(qy);
+      perm[b] = b;
+    }
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return code[a] < code[b]; });
+    for (int s2 = 0; s2 < nleaf; ++s2) invp[perm[s2]] = s2;
+  }
+  T.perm = upload(c, "t_perm", perm);
+  T.invp = upload(c, "t_invp", invp);
+  HIPCHK(c, launch_box_bounds(D.eta, N, T.off.data(), T.nb.data(), T.levels, lbox, T.perm, T.invp, bbox, rbits,
+                              T.bounds, c->stream));
   T.tiles = (N + kt - 1) / kt;
   std::vector<double4> hb(total), ht(T.tiles);
   HIPCHK(c, hipMemcpyAsync(hb.data(), T.bounds, sizeof(double4) * total, hipMemcpyDeviceToHost, c->stream));
@@ -544,7 +585,10 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   T.splits = S;
   const double f2 = (1.0 + kTreeTheta) * (1.0 + kTreeTheta);
   const double cnear = 13.0, cself = 16.0;
-  const double ltol = std::log(far_tol);
+  // rho^k <= far_tol exactly when rho <= far_tol^(1/k): the order p_e of a far
+  // entry is the least k >= 2 (at most p) whose threshold rho meets
+  std::vector<double> thr((size_t)T.p + 1, 0.0);
+  for (int k = 1; k <= T.p; ++k) thr[k] = std::pow(far_tol, 1.0 / k);
   std::vector<int> seg((size_t)T.tiles * (4 * S + 1));
   // the tiles' lists are independent: contiguous tile ranges on a few host
   // threads, each list local to its thread, then joined in tile order
@@ -558,28 +602,35 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
     try {
       std::vector<int> ent;
       std::vector<double> cost;
-      std::vector<std::pair<int, int>> stack;
+      int stack[2 * 34][2];   // depth-first: at most one pending sibling per level
       for (int t = t0; t < t1; ++t) {
         ent.clear();
         cost.clear();
         const double4 tt = ht[t];
         const int base = t * kt, top = T.levels - 1;
         const double nt = (double)std::min(kt, N - base);
-        for (int b = 0; b < T.nb[top]; ++b) stack.push_back({top, b});
-        while (!stack.empty()) {
-          const auto [l, b] = stack.back();
-          stack.pop_back();
+        int sp = 0;
+        for (int b = T.nb[top] - 1; b >= 0; --b) {
+          stack[sp][0] = top;
+          stack[sp][1] = b;
+          ++sp;
+        }
+        while (sp > 0) {
+          --sp;
+          const int l = stack[sp][0], b = stack[sp][1];
           const double4 bb = hb[T.off[l] + b];
           const double dx = tt.x - bb.x, dy = tt.y - bb.y, rr = tt.z + bb.z;
-          if (dx * dx + dy * dy > f2 * rr * rr) {
-            const double rho = bb.z / (std::sqrt(dx * dx + dy * dy) - tt.z);
-            const int pe = std::max(2, std::min(T.p, (int)std::ceil(ltol / std::log(rho))));
+          const double d2 = dx * dx + dy * dy;
+          if (d2 > f2 * rr * rr) {
+            const double rho = bb.z / (std::sqrt(d2) - tt.z);
+            int pe = 2;
+            while (pe < T.p && rho > thr[pe]) ++pe;
             ent.push_back((pe << 24) | (T.off[l] + b));
             cost.push_back(4.0 * pe + 24.0);
             work[(size_t)th] += nt * (8.0 * pe + 8.0);
           } else if (l == 0) {
             for (int k = 0; k < kLeaf / 64; ++k) {
-              const int j0 = b * kLeaf + k * 64;
+              const int j0 = perm[b] * kLeaf + k * 64;
               if (j0 >= N) break;
               const int j1 = std::min(N, j0 + 64);
               const int ov = std::max(0, std::min(j1, base + kt) - std::max(j0, base));
@@ -588,9 +639,15 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
               work[(size_t)th] += 16.0 * (nt * (j1 - j0) - ov);
             }
           } else {
-            // children pushed in reverse so that the list keeps node order
-            if (2 * b + 1 < T.nb[l - 1]) stack.push_back({l - 1, 2 * b + 1});
-            stack.push_back({l - 1, 2 * b});
+            // children pushed in reverse so that the list keeps slot order
+            if (2 * b + 1 < T.nb[l - 1]) {
+              stack[sp][0] = l - 1;
+              stack[sp][1] = 2 * b + 1;
+              ++sp;
+            }
+            stack[sp][0] = l - 1;
+            stack[sp][1] = 2 * b;
+            ++sp;
           }
         }
         double tot = 0.0;
@@ -672,7 +729,7 @@ void tree_pairs(gnk_ctx* c, Batch& B, int p, const int* active) {
     HIPCHK(c, hipEventRecord(pr.a, c->stream));
   }
   for (int col = 0; col < wcols; ++col) {
-    HIPCHK(c, launch_tree_moments(D.rec, rec_stride(wcols), kRecHead + col, D.N, T.bounds, T.off.data(),
+    HIPCHK(c, launch_tree_moments(D.rec, rec_stride(wcols), kRecHead + col, D.N, T.bounds, T.perm, T.off.data(),
                                   T.nb.data(), T.levels, T.p, T.mom, c->stream));
     HIPCHK(c, launch_tree_eval(B.d_dom, T.tiles, B.shape.tpt, T.seg, T.list, T.bounds, T.mom, T.p, T.splits, col,
                                wcols, active, lead, c->stream));

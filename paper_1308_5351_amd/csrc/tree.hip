@@ -36,12 +36,15 @@ __device__ __forceinline__ double wave_sum64(double v) {
 }
 
 // Bounding circles {cx, cy, r, 0} of the boxes of every level: the centre of
-// the box's bounding box and the largest distance of its nodes from it. Leaf
-// bounding boxes come from their nodes (one wavefront per leaf), a parent's
-// from its two children (exact: min and max), and the radii of all levels from
-// one pass over the nodes (one 256-thread block per leaf, whose nodes lie in a
-// single box of every level; a block maximum, then an atomic maximum on the
-// radius's bit pattern, which orders non-negative doubles as unsigned integers).
+// the box's bounding box and the largest distance of its nodes from it. The
+// leaves (256 consecutive nodes) take the slots of level 0 in an order chosen
+// on the host (perm: slot -> leaf, invp: leaf -> slot); the box of slots
+// [b 2^l, (b + 1) 2^l) is box b of level l. Leaf bounding boxes come from
+// their nodes (one wavefront per leaf), a parent's from its two children
+// (exact: min and max), and the radii of all levels from one pass over the
+// nodes (one 256-thread block per leaf, whose nodes lie in a single box of
+// every level; a block maximum, then an atomic maximum on the radius's bit
+// pattern, which orders non-negative doubles as unsigned integers).
 __global__ __launch_bounds__(64) void k_leaf_bbox(const double2* __restrict__ eta, int N,
                                                   double4* __restrict__ bbox) {
   const int b = blockIdx.x, lane = threadIdx.x;
@@ -64,6 +67,12 @@ __global__ __launch_bounds__(64) void k_leaf_bbox(const double2* __restrict__ et
     ymax = fmax(ymax, __shfl_xor(ymax, off, 64));
   }
   if (lane == 0) bbox[b] = make_double4(xmin, xmax, ymin, ymax);
+}
+
+__global__ void k_bbox_gather(const double4* __restrict__ leafbox, const int* __restrict__ perm, int nleaf,
+                              double4* __restrict__ slotbox) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nleaf) slotbox[s] = leafbox[perm[s]];
 }
 
 __global__ void k_bbox_merge(const double4* __restrict__ child, int nchild, double4* __restrict__ parent, int npar) {
@@ -92,15 +101,16 @@ struct LevelTable {
 };
 
 __global__ __launch_bounds__(256) void k_box_radii(const double2* __restrict__ eta, int N, LevelTable lv, int levels,
-                                                   const double4* __restrict__ out,
+                                                   const int* __restrict__ invp, const double4* __restrict__ out,
                                                    unsigned long long* __restrict__ rbits) {
   __shared__ double sh[4];
   const int leaf = blockIdx.x, t = threadIdx.x;
+  const int slot = invp[leaf];
   const int i = leaf * kLeaf + t;
   const bool in = i < N;
   const double2 e = in ? eta[i] : make_double2(0.0, 0.0);
   for (int l = 0; l < levels; ++l) {
-    const int box = lv.off[l] + (leaf >> l);
+    const int box = lv.off[l] + (slot >> l);
     const double4 c = out[box];
     double r = in ? sqrt((e.x - c.x) * (e.x - c.x) + (e.y - c.y) * (e.y - c.y)) : 0.0;
 #pragma unroll
@@ -122,17 +132,18 @@ __global__ void k_box_finish(const unsigned long long* __restrict__ rbits, int n
 }
 
 // Leaf moments of weight column wo (record field) about the leaf centres:
-// one wavefront per leaf, each lane holding up to four nodes; moment k is
+// one wavefront per level-0 slot (leaf perm[slot]), each lane holding up to four nodes; moment k is
 // the wave sum of w_j (eta_j - c)^k, the powers advanced one k at a time.
 __global__ __launch_bounds__(64) void k_leaf_moments(const double2* __restrict__ rec, int stride, int wo, int N,
-                                                     const double4* __restrict__ bounds, int p,
-                                                     double2* __restrict__ mom) {
+                                                     const double4* __restrict__ bounds, const int* __restrict__ perm,
+                                                     int p, double2* __restrict__ mom) {
   const int b = blockIdx.x, lane = threadIdx.x;
+  const int leaf = perm[b];
   const double4 c = bounds[b];
   double dx[kLeaf / 64], dy[kLeaf / 64], tx[kLeaf / 64], ty[kLeaf / 64];
 #pragma unroll
   for (int m = 0; m < kLeaf / 64; ++m) {
-    const int j = b * kLeaf + m * 64 + lane;
+    const int j = leaf * kLeaf + m * 64 + lane;
     if (j < N) {
       const double2 e = rec[(size_t)j * stride], w = rec[(size_t)j * stride + wo];
       dx[m] = e.x - c.x;
@@ -318,10 +329,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 
 }  // namespace
 
+hipError_t launch_leaf_boxes(const double2* eta, int N, int nleaf, double4* leafbox, hipStream_t st) {
+  k_leaf_bbox<<<nleaf, 64, 0, st>>>(eta, N, leafbox);
+  return hipGetLastError();
+}
+
 hipError_t launch_box_bounds(const double2* eta, int N, const int* level_off, const int* level_nb, int levels,
-                             double4* bbox, unsigned long long* rbits, double4* out, hipStream_t st) {
+                             const double4* leafbox, const int* perm, const int* invp, double4* bbox,
+                             unsigned long long* rbits, double4* out, hipStream_t st) {
   if (levels < 1 || levels > 32) return hipErrorInvalidValue;
-  k_leaf_bbox<<<level_nb[0], 64, 0, st>>>(eta, N, bbox);
+  k_bbox_gather<<<(level_nb[0] + 255) / 256, 256, 0, st>>>(leafbox, perm, level_nb[0], bbox);
   hipError_t e = hipGetLastError();
   for (int l = 0; l + 1 < levels && e == hipSuccess; ++l) {
     const int npar = level_nb[l + 1];
@@ -334,16 +351,16 @@ hipError_t launch_box_bounds(const double2* eta, int N, const int* level_off, co
   if ((e = hipGetLastError()) != hipSuccess) return e;
   LevelTable lv{};
   for (int l = 0; l < levels; ++l) lv.off[l] = level_off[l];
-  k_box_radii<<<level_nb[0], 256, 0, st>>>(eta, N, lv, levels, out, rbits);
+  k_box_radii<<<level_nb[0], 256, 0, st>>>(eta, N, lv, levels, invp, out, rbits);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_box_finish<<<(nbox + 255) / 256, 256, 0, st>>>(rbits, nbox, out);
   return hipGetLastError();
 }
 
-hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, const double4* bounds,
+hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, const double4* bounds, const int* perm,
                                const int* level_off, const int* level_nb, int levels, int p, double2* mom,
                                hipStream_t st) {
-  k_leaf_moments<<<level_nb[0], 64, 0, st>>>(rec, stride, wo, N, bounds, p, mom);
+  k_leaf_moments<<<level_nb[0], 64, 0, st>>>(rec, stride, wo, N, bounds, perm, p, mom);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int l = 0; l + 1 < levels; ++l) {
