@@ -41,7 +41,7 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # factors from a 256 MiB copy of known size; profiles/k_pairs_fp64_N17408_hbm_counters.md).
 # Valid only for the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "pair_steps.inl", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "e0d4c5903468c5191b7b98d935e7a00df5e2d432f78cd83cc753c091830832bd",
+                "sha256": "d1688a6df37db5637d8548f48e1aeba5242b4499d9b18f1e4b95d2470bb702db",
                 "bytes_per_launch": 21997911}
 
 
