@@ -41,7 +41,7 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # factors from a 256 MiB copy of known size; profiles/k_pairs_fp64_N17408_hbm_counters.md).
 # Valid only for the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "pair_steps.inl", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "d1688a6df37db5637d8548f48e1aeba5242b4499d9b18f1e4b95d2470bb702db",
+                "sha256": "6494a48ae8ba113f994434185c75f0c48ad2995097671da4c9323293ffec5644",
                 "bytes_per_launch": 21997911}
 
 
@@ -266,6 +266,33 @@ def far_field(gnk, ctx, torch):
     out["large"] = {"workload": "1089 seeded perturbed circles x 4096 nodes (N = 4460544, the paper's largest "
                                 "size), gamma = Re(eta^2), FBIE restart 25 tol 1e-12, far_tol 1e-13 (solve time "
                                 "includes building the tree)", **tb}
+    # the Cauchy integral at exterior points of the same domain: treecode sums for all
+    # points, direct sums for the first 16384 (time and agreement)
+    log("far field: Cauchy integral at 262144 points around 4460544 nodes")
+    z = wl.exterior_points_fourier(big, 262144, [wl.SEED, 98], near=0.05)
+    cen = big.meta["coeffs"][:, -big.meta["kmin"]]
+    fv = 1.0 / (big.eta - cen[0]) + 3.0
+    eb, pb, fb, zb = cu(big.eta), cu(big.etap), cu(fv), cu(z)
+    zs = zb[:16384].contiguous()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+    ft, t_tree = timed(lambda: ctx.fcau(eb, pb, fb, zb, big.m1, big.n, finf=3.0, far_tol=1e-13))
+    fd, t_dir = timed(lambda: ctx.fcau(eb, pb, fb, zs, big.m1, big.n, finf=3.0))
+    ex = 1.0 / (z - cen[0]) + 3.0
+    out["fcau_large"] = {
+        "workload": "f = 1/(z - c_0) + 3 on the 4460544-node domain, 262144 seeded exterior points (5% 1e-4..1e-2 "
+                    "from a curve), f(inf) = 3; treecode far_tol 1e-13 (time includes building the tree) for all "
+                    "points, direct sums for the first 16384",
+        "tree_ms": round(t_tree, 2), "direct_ms_16384_points": round(t_dir, 2),
+        "direct_ms_all_points_est": round(t_dir * 262144 / 16384, 1),
+        "tree_vs_direct_rel": float((ft[:16384] - fd).abs().max() / fd.abs().max()),
+        "tree_vs_exact_rel": float(np.max(np.abs(ft.cpu().numpy() - ex)) / np.max(np.abs(ex)))}
     return out
 
 

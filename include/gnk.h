@@ -259,6 +259,16 @@ GNK_API gnk_status gnk_circular_slit_map(gnk_ctx* ctx, int64_t m1, int64_t n, co
                                          const double* alpha, const gnk_opts* opts, void* f, double* radii,
                                          gnk_info* info);
 
+/* gnk_fcau with the two Cauchy sums from the treecode (see gnk_opts.far_tol):
+ * the nodes' box tree, target tiles of 128 points, far boxes by p_e-term
+ * expansions with (r/R)^p_e <= far_tol, near 64-node blocks summed directly.
+ * Same arguments, layout and results as gnk_fcau, plus far_tol (1e-15..0.1);
+ * GNK_ERR_ARG for far_tol outside that range. For many points around a large
+ * boundary (N in the millions), where the direct sums take N nz pairs. */
+GNK_API gnk_status gnk_fcau_tree(gnk_ctx* ctx, int64_t m1, int64_t n, const void* eta, const void* etap,
+                                 const void* f, int nrhs, const void* z, int64_t nz, const void* finf,
+                                 double far_tol, void* fz);
+
 /* Conformal map of an (m+1)-connected domain onto a canonical domain with
  * slits, from one FBIE solve with the piecewise constant theta of eq. (e:A):
  * circular slits for theta_j = pi/2, radial slits for theta_j = 0 (Examples 3

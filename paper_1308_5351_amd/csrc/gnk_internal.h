@@ -108,7 +108,7 @@ hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, co
 // col of doms[0]; seg: per target tile, 4 splits + 1 bounds into list
 hipError_t launch_tree_eval(const DomDev* doms, int tiles, int tpt, const int* seg, const int* list,
                             const double4* bounds, const double2* mom, int p, int splits, int col, int wcols,
-                            const int* active, int lead, hipStream_t st);
+                            const int* active, int lead, bool ext, hipStream_t st);
 // FP32 records from the FP64 records of every domain
 hipError_t launch_records32(const DomDev* doms, int ndom, int maxN, int lead, int data, hipStream_t st);
 

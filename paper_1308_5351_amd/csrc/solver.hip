@@ -235,6 +235,7 @@ struct Batch {
     double flops = 0.0;   // per column: 8 p_e + 8 per (target, far box), 16 per near pair
     int* perm = nullptr;  // level-0 slot -> leaf (device), and leaf -> slot
     int* invp = nullptr;
+    bool ext = false;     // targets are the points tz (no j != i window), not the nodes
   } tree;
 };
 
@@ -505,7 +506,46 @@ int tree_terms(double far_tol) {
   return std::max(4, std::min(kTreeMaxP, p));
 }
 
-void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
+// perm: the indices of pts in the order of their positions along a Hilbert
+// curve (16 bits per coordinate over the points' bounding square; ties keep
+// index order). The curve has no jumps, so any run of consecutive indices
+// lies in a compact region of the plane.
+void hilbert_order(const std::vector<double2>& pts, std::vector<int>& perm) {
+  const size_t n = pts.size();
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (const auto& p : pts) {
+    x0 = std::min(x0, p.x), x1 = std::max(x1, p.x), y0 = std::min(y0, p.y), y1 = std::max(y1, p.y);
+  }
+  const double span = std::max(x1 - x0, y1 - y0);
+  const double sc = span > 0.0 ? 65535.0 / span : 0.0;
+  constexpr uint32_t side = 1u << 16;
+  auto distance = [](uint32_t x, uint32_t y) {   // position along the curve of cell (x, y)
+    uint64_t d = 0;
+    for (uint32_t h = side / 2; h > 0; h /= 2) {
+      const uint32_t rx = (x & h) ? 1u : 0u, ry = (y & h) ? 1u : 0u;
+      d += (uint64_t)h * h * ((3u * rx) ^ ry);
+      if (ry == 0) {   // rotate the quadrant
+        if (rx == 1) {
+          x = side - 1 - x;
+          y = side - 1 - y;
+        }
+        std::swap(x, y);
+      }
+    }
+    return d;
+  };
+  std::vector<uint64_t> code(n);
+  perm.resize(n);
+  for (size_t b = 0; b < n; ++b) {
+    const uint32_t qx = (uint32_t)std::min(65535.0, std::max(0.0, (pts[b].x - x0) * sc));
+    const uint32_t qy = (uint32_t)std::min(65535.0, std::max(0.0, (pts[b].y - y0) * sc));
+    code[b] = distance(qx, qy);
+    perm[b] = (int)b;
+  }
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return code[a] < code[b]; });
+}
+
+void build_tree(gnk_ctx* c, Batch& B, double far_tol, bool ext = false) {
   if (B.ndom != 1 || B.mixed) {
     set_err(c, "the treecode takes one domain in FP64");
     throw Fail{GNK_ERR_ARG};
@@ -513,7 +553,9 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   DomDev& D = B.dom[0];
   auto& T = B.tree;
   const int N = D.N, tpt = B.shape.tpt, kt = 64 * tpt;
+  const int NT = ext ? D.Nt : N;   // targets
   T = Batch::Tree{};
+  T.ext = ext;
   T.p = tree_terms(far_tol);
   int total = 0;
   // far entries carry the box index in 24 bits
@@ -533,7 +575,7 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   T.mom = ws<double2>(c, "t_mom", (size_t)total * T.p);
   double4* bbox = ws<double4>(c, "t_bbox", total);
   unsigned long long* rbits = ws<unsigned long long>(c, "t_rbits", total);
-  // The leaves take the level-0 slots in the Morton order of their centres, so
+  // The leaves take the level-0 slots in the Hilbert order of their centres, so
   // that a box of 2^l slots is a compact cluster of the plane (in node order a
   // box could join boundary pieces far apart, and few boxes would be far).
   const int nleaf = T.nb[0];
@@ -542,38 +584,16 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   std::vector<double4> hl((size_t)nleaf);
   HIPCHK(c, hipMemcpyAsync(hl.data(), lbox, sizeof(double4) * nleaf, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  std::vector<int> perm((size_t)nleaf), invp((size_t)nleaf);
-  {
-    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
-    for (const auto& b : hl) {
-      const double cx = 0.5 * (b.x + b.y), cy = 0.5 * (b.z + b.w);
-      x0 = std::min(x0, cx), x1 = std::max(x1, cx), y0 = std::min(y0, cy), y1 = std::max(y1, cy);
-    }
-    const double span = std::max(x1 - x0, y1 - y0);
-    const double sc = span > 0.0 ? 65535.0 / span : 0.0;
-    auto spread = [](uint64_t v) {   // bits of v at the even positions
-      v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
-      v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
-      v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
-      v = (v | (v << 2)) & 0x3333333333333333ull;
-      return (v | (v << 1)) & 0x5555555555555555ull;
-    };
-    std::vector<uint64_t> code((size_t)nleaf);
-    for (int b = 0; b < nleaf; ++b) {
-      const double cx = 0.5 * (hl[b].x + hl[b].y), cy = 0.5 * (hl[b].z + hl[b].w);
-      const uint64_t qx = (uint64_t)std::min(65535.0, std::max(0.0, (cx - x0) * sc));
-      const uint64_t qy = (uint64_t)std::min(65535.0, std::max(0.0, (cy - y0) * sc));
-      code[b] = (spread(qx) << 1) | spread(qy);
-      perm[b] = b;
-    }
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return code[a] < code[b]; });
-    for (int s2 = 0; s2 < nleaf; ++s2) invp[perm[s2]] = s2;
-  }
+  std::vector<double2> centre((size_t)nleaf);
+  for (int b = 0; b < nleaf; ++b) centre[b] = make_double2(0.5 * (hl[b].x + hl[b].y), 0.5 * (hl[b].z + hl[b].w));
+  std::vector<int> perm, invp((size_t)nleaf);
+  hilbert_order(centre, perm);
+  for (int s2 = 0; s2 < nleaf; ++s2) invp[perm[s2]] = s2;
   T.perm = upload(c, "t_perm", perm);
   T.invp = upload(c, "t_invp", invp);
   HIPCHK(c, launch_box_bounds(D.eta, N, T.off.data(), T.nb.data(), T.levels, lbox, T.perm, T.invp, bbox, rbits,
                               T.bounds, c->stream));
-  T.tiles = (N + kt - 1) / kt;
+  T.tiles = (NT + kt - 1) / kt;
   std::vector<double4> hb(total), ht(T.tiles);
   HIPCHK(c, hipMemcpyAsync(hb.data(), T.bounds, sizeof(double4) * total, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(ht.data(), D.tb, sizeof(double4) * T.tiles, hipMemcpyDeviceToHost, c->stream));
@@ -608,7 +628,7 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
         cost.clear();
         const double4 tt = ht[t];
         const int base = t * kt, top = T.levels - 1;
-        const double nt = (double)std::min(kt, N - base);
+        const double nt = (double)std::min(kt, NT - base);
         int sp = 0;
         for (int b = T.nb[top] - 1; b >= 0; --b) {
           stack[sp][0] = top;
@@ -633,7 +653,7 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
               const int j0 = perm[b] * kLeaf + k * 64;
               if (j0 >= N) break;
               const int j1 = std::min(N, j0 + 64);
-              const int ov = std::max(0, std::min(j1, base + kt) - std::max(j0, base));
+              const int ov = ext ? 0 : std::max(0, std::min(j1, base + kt) - std::max(j0, base));
               ent.push_back(~(j0 / 64));
               cost.push_back(cnear * (j1 - j0 - ov) + cself * ov);
               work[(size_t)th] += 16.0 * (nt * (j1 - j0) - ov);
@@ -710,7 +730,7 @@ void build_tree(gnk_ctx* c, Batch& B, double far_tol) {
   T.seg = upload(c, "t_seg", seg);
   D.splits = S;
   D.chunk = N;
-  D.parts = ws<double2>(c, "t_parts", (size_t)S * (D.ncols + 1) * N);
+  D.parts = ws<double2>(c, "t_parts", (size_t)S * (D.ncols + 1) * NT);
   B.d_dom = upload(c, "b_dom", B.dom);
   T.on = true;
 }
@@ -723,7 +743,7 @@ void tree_pairs(gnk_ctx* c, Batch& B, int p, const int* active) {
   gnk_ctx::ProfRec pr{};
   if (c->prof) {
     // counted as the pairs the direct sum would take
-    const double pairs = (double)D.N * (double)(D.N - 1);
+    const double pairs = T.ext ? (double)D.N * (double)D.Nt : (double)D.N * (double)(D.N - 1);
     pr = gnk_ctx::ProfRec{pool_event(c), pool_event(c), pairs * wcols, pairs * (16.0 + 8.0 * (wcols - 1)),
                           wcols == 1 ? pairs : 0.0, false, wcols == 1, T.flops * wcols, true};
     HIPCHK(c, hipEventRecord(pr.a, c->stream));
@@ -732,7 +752,7 @@ void tree_pairs(gnk_ctx* c, Batch& B, int p, const int* active) {
     HIPCHK(c, launch_tree_moments(D.rec, rec_stride(wcols), kRecHead + col, D.N, T.bounds, T.perm, T.off.data(),
                                   T.nb.data(), T.levels, T.p, T.mom, c->stream));
     HIPCHK(c, launch_tree_eval(B.d_dom, T.tiles, B.shape.tpt, T.seg, T.list, T.bounds, T.mom, T.p, T.splits, col,
-                               wcols, active, lead, c->stream));
+                               wcols, active, lead, T.ext, c->stream));
   }
   if (c->prof) {
     HIPCHK(c, hipEventRecord(pr.b, c->stream));
@@ -1785,13 +1805,17 @@ gnk_status gnk_cauchy_sum_tree(gnk_ctx* c, int64_t N, const void* eta, const voi
   });
 }
 
-gnk_status gnk_fcau(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const void* etap, const void* f, int nrhs,
-                    const void* z, int64_t nz, const void* finf, void* fz) {
-  return guarded(c, [&]() -> gnk_status {
+// The Cauchy integral at interior points; far_tol > 0: the sums by the treecode
+// (the node tree as for gnk_cauchy_sum_tree, target tiles of the points)
+static gnk_status fcau(gnk_ctx* c, const char* name, int64_t m1, int64_t n, const void* eta, const void* etap,
+                       const void* f, int nrhs, const void* z, int64_t nz, const void* finf, double far_tol,
+                       void* fz) {
+  {
     const int64_t N = m1 * n;
     if (m1 < 1 || n < 1 || N > ((int64_t)1 << 30) || nz < 1 || nz > ((int64_t)1 << 30) || nrhs < 1 ||
-        nrhs > 4096 || !eta || !etap || !f || !z || !fz || fz == f || fz == z || fz == eta || fz == etap) {
-      set_err(c, "bad arguments to gnk_fcau");
+        nrhs > 4096 || !eta || !etap || !f || !z || !fz || fz == f || fz == z || fz == eta || fz == etap ||
+        (far_tol != 0.0 && !(far_tol >= 1e-15 && far_tol <= 0.1))) {
+      set_err(c, "bad arguments to %s", name);
       throw Fail{GNK_ERR_ARG};
     }
     // a pseudo-domain of one component holding the N nodes (the even mesh
@@ -1811,12 +1835,29 @@ gnk_status gnk_fcau(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const vo
     DomDev& D = B.dom[0];
     D.tz = static_cast<const double2*>(z);
     D.Nt = (int)nz;
+    // treecode: the points in the Hilbert order of their positions, so that a
+    // tile of consecutive targets is a compact cluster (results go back to the
+    // caller's order in the epilogue)
+    const int* tperm = nullptr;
+    if (far_tol > 0.0) {
+      std::vector<double2> hz((size_t)nz);
+      HIPCHK(c, hipMemcpyAsync(hz.data(), z, sizeof(double2) * nz, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      std::vector<int> perm;
+      hilbert_order(hz, perm);
+      tperm = upload(c, "f_tperm", perm);
+      double2* zp = ws<double2>(c, "f_zp", (size_t)nz);
+      k_gather_points<<<nblocks(nz), kT, 0, c->stream>>>(static_cast<const double2*>(z), tperm, nz, zp);
+      LAUNCHCHK(c);
+      D.tz = zp;
+    }
     D.parts = ws<double2>(c, "f_parts", (size_t)D.splits * wcols * nz);
     D.tb = ws<double4>(c, "f_tb", (size_t)((nz + 63) / 64));
     B.d_dom = upload(c, "b_dom", B.dom);
     HIPCHK(c, launch_tile_bounds(B.d_dom, 1, (int)nz, 64 * B.shape.tpt, 3, c->stream));
     k_fcau_records<<<nblocks(N), kT, 0, c->stream>>>(B.d_dom, static_cast<const double2*>(f), nrhs);
     LAUNCHCHK(c);
+    if (far_tol > 0.0) build_tree(c, B, far_tol, true);
     pairs(c, B, P_SETUP, false, nullptr);
     const double2* fi = nullptr;
     if (finf) {
@@ -1824,10 +1865,28 @@ gnk_status gnk_fcau(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const vo
       fi = upload(c, "f_finf", std::vector<double2>(h, h + nrhs));
     }
     k_fcau_epilogue<<<dim3(nblocks(nz), (unsigned)nrhs), kT, 0, c->stream>>>(
-        B.d_dom, static_cast<const double2*>(f), nrhs, fi, (double)n, static_cast<double2*>(fz));
+        B.d_dom, static_cast<const double2*>(f), nrhs, fi, (double)n, tperm, static_cast<double2*>(fz));
     LAUNCHCHK(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GNK_OK;
+  }
+}
+
+gnk_status gnk_fcau(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const void* etap, const void* f, int nrhs,
+                    const void* z, int64_t nz, const void* finf, void* fz) {
+  return guarded(c, [&]() -> gnk_status {
+    return fcau(c, "gnk_fcau", m1, n, eta, etap, f, nrhs, z, nz, finf, 0.0, fz);
+  });
+}
+
+gnk_status gnk_fcau_tree(gnk_ctx* c, int64_t m1, int64_t n, const void* eta, const void* etap, const void* f,
+                         int nrhs, const void* z, int64_t nz, const void* finf, double far_tol, void* fz) {
+  return guarded(c, [&]() -> gnk_status {
+    if (far_tol == 0.0) {
+      set_err(c, "gnk_fcau_tree takes far_tol in 1e-15..0.1");
+      throw Fail{GNK_ERR_ARG};
+    }
+    return fcau(c, "gnk_fcau_tree", m1, n, eta, etap, f, nrhs, z, nz, finf, far_tol, fz);
   });
 }
 

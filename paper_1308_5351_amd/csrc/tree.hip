@@ -211,12 +211,13 @@ template <int TPT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_tree(const DomDev* __restrict__ doms, const int* __restrict__ seg,
                                               const int* __restrict__ list, const double4* __restrict__ bounds,
                                               const double2* __restrict__ mom, int p, int splits, int col, int wcols,
-                                              const int* __restrict__ active, int lead) {
+                                              const int* __restrict__ active, int lead, int ext) {
   __shared__ double red[3][TPT][2][64];
   constexpr int kTile = 64 * TPT;
   const DomDev& D = doms[0];
   if (active != nullptr && col >= lead && active[D.c0 + col - lead] == 0) return;
   const int N = D.N;
+  const int NT = ext ? D.Nt : N;   // targets: the points tz (ext) or the nodes
   const int tile = blockIdx.x / splits, g = blockIdx.x - tile * splits;
   const int base = tile * kTile;
   const int lane = threadIdx.x & 63;
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
     ti[t] = base + t * 64 + lane;
-    tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
+    tg[t] = ext ? D.tz[min(ti[t], NT - 1)] : rec[(size_t)min(ti[t], N - 1) * stride];
   }
   Acc<1, TPT> acc;
 #pragma unroll
@@ -297,6 +298,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       }
     } else {
       const int ja = (~ent) * 64, jb = min(N, ja + 64);
+      if (ext) {
+        plain(ja, jb);
+        continue;
+      }
       plain(ja, min(jb, base));
       const int ma = max(ja, base), mb = min(jb, base + kTile);
       for (int j = ma; j < mb; ++j) single_step<1, TPT>(acc, tg, ti, rec + (size_t)j * stride, wo, j, true);
@@ -322,7 +327,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         x += red[q][t][0][lane];
         y += red[q][t][1][lane];
       }
-      if (ti[t] < N) D.parts[((size_t)g * wcols + col) * N + ti[t]] = make_double2(x, y);
+      if (ti[t] < NT) D.parts[((size_t)g * wcols + col) * NT + ti[t]] = make_double2(x, y);
     }
   }
 }
@@ -375,12 +380,13 @@ hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, co
 
 hipError_t launch_tree_eval(const DomDev* doms, int tiles, int tpt, const int* seg, const int* list,
                             const double4* bounds, const double2* mom, int p, int splits, int col, int wcols,
-                            const int* active, int lead, hipStream_t st) {
+                            const int* active, int lead, bool ext, hipStream_t st) {
   const unsigned grid = (unsigned)tiles * (unsigned)splits;
+  const int e = ext ? 1 : 0;
   if (tpt == 2)
-    k_tree<2><<<grid, 256, 0, st>>>(doms, seg, list, bounds, mom, p, splits, col, wcols, active, lead);
+    k_tree<2><<<grid, 256, 0, st>>>(doms, seg, list, bounds, mom, p, splits, col, wcols, active, lead, e);
   else
-    k_tree<1><<<grid, 256, 0, st>>>(doms, seg, list, bounds, mom, p, splits, col, wcols, active, lead);
+    k_tree<1><<<grid, 256, 0, st>>>(doms, seg, list, bounds, mom, p, splits, col, wcols, active, lead, e);
   return hipGetLastError();
 }
 

@@ -383,8 +383,10 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 //   unbounded: (f(inf) - P_f/(n i)) / (1 - P_1/(n i))      (e:cauchy6-u)
 // finf: nrhs values, or null for bounded G. A target on a node makes both
 // sums infinite; it takes that node's value (the limit of the ratio).
+// tperm (or null): target i is the caller's point tperm[i], where it is written.
 __global__ void k_fcau_epilogue(const DomDev* __restrict__ doms, const double2* __restrict__ f, int nrhs,
-                                const double2* __restrict__ finf, double n, double2* __restrict__ fz) {
+                                const double2* __restrict__ finf, double n, const int* __restrict__ tperm,
+                                double2* __restrict__ fz) {
   const DomDev& D = doms[0];
   const int i = blockIdx.x * blockDim.x + threadIdx.x, q = blockIdx.y;
   const int Nt = D.Nt;
@@ -417,7 +419,14 @@ __global__ void k_fcau_epilogue(const DomDev* __restrict__ doms, const double2* 
       }
     }
   }
-  fz[(size_t)q * Nt + i] = r;
+  fz[(size_t)q * Nt + (tperm ? tperm[i] : i)] = r;
+}
+
+// zp[i] = z[perm[i]]
+__global__ void k_gather_points(const double2* __restrict__ z, const int* __restrict__ perm, int64_t nz,
+                                double2* __restrict__ zp) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nz) zp[i] = z[perm[i]];
 }
 
 // S[r*N + i] = sum over the splits of column r (one domain, no lead column)

@@ -25,7 +25,7 @@ OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT, OP_FB_U, OP_GB_U = rang
 EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
             "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad",
             "gnk_fbie_batched", "gnk_fbie_adjoint", "gnk_geom_vjp", "gnk_fourier_curve", "gnk_fourier_vjp",
-            "gnk_fcau", "gnk_cauchy_sum_tree", "gnk_circular_slit_map", "gnk_slit_map")
+            "gnk_fcau", "gnk_cauchy_sum_tree", "gnk_circular_slit_map", "gnk_slit_map", "gnk_fcau_tree")
 
 
 class GnkError(RuntimeError):
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
     lib.gnk_fourier_vjp.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, P, P, P, P]
     lib.gnk_fcau.argtypes = [P, C.c_int64, C.c_int64, P, P, P, C.c_int, P, C.c_int64, P, P]
     lib.gnk_cauchy_sum_tree.argtypes = [P, C.c_int64, P, P, C.c_int, C.c_double, P]
+    lib.gnk_fcau_tree.argtypes = [P, C.c_int64, C.c_int64, P, P, P, C.c_int, P, C.c_int64, P, C.c_double, P]
     lib.gnk_circular_slit_map.argtypes = [P, C.c_int64, C.c_int64, P, P, C.POINTER(C.c_double), C.POINTER(_Opts), P,
                                           C.POINTER(C.c_double), C.POINTER(Info)]
     lib.gnk_slit_map.argtypes = [P, C.c_int64, C.c_int64, P, P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -218,10 +219,11 @@ class Context:
         return _from_cols(S, one)
 
     def fcau(self, eta: torch.Tensor, etap: torch.Tensor, f: torch.Tensor, z: torch.Tensor, m1: int, n: int,
-             finf=None) -> torch.Tensor:
+             finf=None, far_tol: float = 0.0) -> torch.Tensor:
         """f at the points z of G by the Cauchy integral formula (Sec. 7): eta, etap (N,) and f (N,) or
         (N, nrhs) complex128 on the device, N = m1 n; z (nz,) complex128. finf: None for bounded G, else
-        f(infinity) (a number or nrhs numbers) for unbounded G. Returns (nz,) or (nz, nrhs)."""
+        f(infinity) (a number or nrhs numbers) for unbounded G. far_tol > 0: the sums by the treecode
+        (gnk_fcau_tree). Returns (nz,) or (nz, nrhs)."""
         self._bind_stream()
         N = m1 * n
         for name, t in (("eta", eta), ("etap", etap)):
@@ -241,8 +243,13 @@ class Context:
             v = np.broadcast_to(np.asarray(finf, np.complex128), (nrhs,))
             fin = np.ascontiguousarray(v).view(np.float64)
         ec, pc = eta.contiguous(), etap.contiguous()
-        st = self.lib.gnk_fcau(self.h, m1, n, ec.data_ptr(), pc.data_ptr(), fc.data_ptr(), nrhs, zc.data_ptr(),
-                               zc.shape[0], None if fin is None else fin.ctypes.data, out.data_ptr())
+        fptr = None if fin is None else fin.ctypes.data
+        if far_tol > 0.0:
+            st = self.lib.gnk_fcau_tree(self.h, m1, n, ec.data_ptr(), pc.data_ptr(), fc.data_ptr(), nrhs,
+                                        zc.data_ptr(), zc.shape[0], fptr, far_tol, out.data_ptr())
+        else:
+            st = self.lib.gnk_fcau(self.h, m1, n, ec.data_ptr(), pc.data_ptr(), fc.data_ptr(), nrhs,
+                                   zc.data_ptr(), zc.shape[0], fptr, out.data_ptr())
         self._raise(st, False)
         return _from_cols(out, one)
 

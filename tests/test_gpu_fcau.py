@@ -183,3 +183,63 @@ def test_fcau_argument_errors(gk, ctx):
     assert lib.gnk_fcau(ctx.h, 1, 8, p(eta), None, p(eta), 1, p(z), 4, None, p(out)) == gk.ERR_ARG
     # a valid call still works after the errors
     assert lib.gnk_fcau(ctx.h, 1, 8, p(eta), p(eta), p(eta), 1, p(z), 4, None, p(out)) == gk.OK
+
+
+# ------------------------------------------------------------------ treecode sums (gnk_fcau_tree)
+def test_fcau_tree_config1_matches_oracle_and_direct(ctx):
+    dom, _ = wl.config1()
+    z = wl.interior_points_config1(dom, 3001, [wl.SEED, 71])
+    fs = _cfg1_functions(dom)
+    F = np.stack([f(dom.eta) for f in fs], axis=1)
+    print(f"[fcau-tree] config1 N={dom.eta.shape[0]} nz={z.shape[0]}", flush=True)
+    e, p, Fc, zc = _cuda(dom.eta), _cuda(dom.etap), _cuda(F), _cuda(z)
+    got = ctx.fcau(e, p, Fc, zc, dom.m1, dom.n, far_tol=1e-13).cpu().numpy()
+    direct = ctx.fcau(e, p, Fc, zc, dom.m1, dom.n).cpu().numpy()
+    ref = fcau_ref(dom.eta, dom.etap, F, z, dom.n)
+    for q in range(3):
+        assert _rel(got[:, q], ref[:, q]) < TOL, q
+        assert _rel(got[:, q], direct[:, q]) < TOL, q
+
+
+def test_fcau_tree_large_sampled(ctx):
+    # 264192 nodes, 100003 exterior points, f(inf) given; a sample against the oracle
+    dom, _ = wl.config4()
+    z = wl.exterior_points_fourier(dom, 100003, [wl.SEED, 74])
+    cen = dom.meta["coeffs"][:, -dom.meta["kmin"]]
+    f = lambda w: 1.0 / (w - cen[0]) + 1.0 / (w - cen[64]) ** 2 + 3.0
+    print(f"[fcau-tree] config4 N={dom.eta.shape[0]} nz={z.shape[0]}", flush=True)
+    got = ctx.fcau(_cuda(dom.eta), _cuda(dom.etap), _cuda(f(dom.eta)), _cuda(z), dom.m1, dom.n, finf=3.0,
+                   far_tol=1e-12).cpu().numpy()
+    rng = np.random.default_rng([wl.SEED, 76])
+    sample = np.concatenate([rng.choice(z.shape[0] - 1, 47, replace=False), [z.shape[0] - 1]])
+    ref = fcau_ref(dom.eta, dom.etap, f(dom.eta), z[sample], dom.n, finf=3.0)
+    assert _rel(got[sample], ref) < TOL
+    assert _rel(got, f(z)) < 1e-8
+
+
+def test_fcau_tree_node_hits_and_tiny(ctx):
+    dom, _ = wl.config1(n=256)
+    Fv = np.exp(dom.eta)
+    idx = np.array([0, 5, 255, 256, 1000, dom.eta.shape[0] - 1])
+    z = np.concatenate([dom.eta[idx], [0.1 + 0.1j, -0.2j]])
+    got = ctx.fcau(_cuda(dom.eta), _cuda(dom.etap), _cuda(Fv), _cuda(z), dom.m1, dom.n, far_tol=1e-13).cpu().numpy()
+    assert np.array_equal(got[:idx.shape[0]], Fv[idx])
+    assert np.max(np.abs(got[idx.shape[0]:] - np.exp(z[idx.shape[0]:]))) < 1e-12
+    for n, nz in ((8, 1), (6, 129)):
+        eta, etap = _domain([(0.0, 1.0, True)], n)
+        rng = np.random.default_rng([wl.SEED, 77, n, nz])
+        zz = 0.5 * (rng.uniform(-1, 1, nz) + 1j * rng.uniform(-1, 1, nz))
+        fv = eta ** 2 + 0.5
+        g = ctx.fcau(_cuda(eta), _cuda(etap), _cuda(fv), _cuda(zz), 1, n, far_tol=1e-13).cpu().numpy()
+        assert _rel(g, fcau_ref(eta, etap, fv, zz, n)) < TOL
+
+
+def test_fcau_tree_argument_errors(gk, ctx):
+    lib = gk.load_library()
+    eta = _cuda(np.exp(1j * np.linspace(0, 6, 8)))
+    out = torch.empty(4, dtype=torch.complex128, device="cuda")
+    z = _cuda(np.array([0.1j, 0.2, 0.3, 0.0]))
+    p = lambda t: t.data_ptr()
+    for ft in (0.0, 0.5, 1e-17):
+        assert lib.gnk_fcau_tree(ctx.h, 1, 8, p(eta), p(eta), p(eta), 1, p(z), 4, None, ft, p(out)) == gk.ERR_ARG
+    assert lib.gnk_fcau_tree(ctx.h, 1, 8, p(eta), p(eta), p(eta), 1, p(z), 4, None, 1e-12, p(out)) == gk.OK
