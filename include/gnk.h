@@ -201,7 +201,9 @@ typedef struct {
 } gnk_prof;
 
 /* enable: 1 starts recording, 0 stops (already recorded launches are kept).
- * While enabled, solves launch every kernel directly (no graph replay). */
+ * While enabled, solves launch every kernel directly (no graph replay), and
+ * the fully masked speculative Arnoldi steps that GMRES runs after its last
+ * column stops (they do no work) are left out of the totals. */
 GNK_API gnk_status gnk_profile(gnk_ctx* ctx, int enable);
 /* Waits for the stream, folds the recorded launches into the totals, copies
  * them to *out (may be NULL), and clears them when reset != 0. */

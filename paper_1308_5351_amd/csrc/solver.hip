@@ -37,7 +37,7 @@ struct gnk_ctx {
   // instantiated Arnoldi-step graphs (FP64, mixed), kept across solves: each
   // solve captures its step and refreshes these with hipGraphExecUpdate, which
   // avoids a new instantiation when only kernel arguments changed
-  hipGraphExec_t step_exec[2] = {nullptr, nullptr};
+  hipGraphExec_t step_exec[4] = {nullptr, nullptr, nullptr, nullptr};   // [mixed + 2 (steps - 1)]
   std::string err;
   int num_cu = 256;
   size_t ws_limit = 0;   // bytes, 0 = unlimited
@@ -64,6 +64,7 @@ struct gnk_ctx {
     bool tree = false;
     double fft_bytes = 0.0;    // circulant products (kept out of the pair totals)
     bool fft = false;
+    bool spec = false;         // a fully masked speculative Arnoldi step: no work, not counted
   };
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -1084,19 +1085,29 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   if (mixed) build_items(c, B, P_GM_MIXED);
   if (op == GNK_OP_GB || op == GNK_OP_GB_T) (void)ws<double>(c, "mean", (size_t)B.ncol * B.maxm1);
   const bool use_graph = c->graphs && !c->prof;
-  bool fresh[2] = {false, false};   // cached graph matches this solve's step
-  auto launch_step = [&](bool use_mixed) {
+  bool fresh[4] = {false, false, false, false};   // cached graph matches this solve's step
+  // k (1 or 2) consecutive Arnoldi steps in one launch: the step index lives on
+  // the device, and inside a graph the kernels follow each other with no gap,
+  // while each graph launch costs a gap of about 13 us
+  // profiling: the pair records of each step of the cycle, so that those of the
+  // fully masked speculative steps can be left out of the totals
+  std::vector<std::pair<size_t, size_t>> step_recs;
+  auto launch_step = [&](bool use_mixed, int k) {
     if (!use_graph) {
-      enqueue_step(use_mixed);
+      for (int i = 0; i < k; ++i) {
+        const size_t r0 = c->prof_pending.size();
+        enqueue_step(use_mixed);
+        step_recs.emplace_back(r0, c->prof_pending.size());
+      }
       return;
     }
-    const int m = use_mixed ? 1 : 0;
+    const int m = (use_mixed ? 1 : 0) + 2 * (k - 1);
     hipGraphExec_t& ge = c->step_exec[m];
     if (!fresh[m]) {
       hipGraph_t graph = nullptr;
       HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
       try {
-        enqueue_step(use_mixed);
+        for (int i = 0; i < k; ++i) enqueue_step(use_mixed);
       } catch (...) {
         hipGraph_t g2 = nullptr;
         (void)hipStreamEndCapture(c->stream, &g2);
@@ -1156,26 +1167,41 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     }
     for (int q = 0; q < ncol; ++q)
       if (!conv[q]) outer[q] += 1;
-    // Arnoldi steps. The host looks one step behind the device: before
-    // enqueuing step l+1 it waits for step l-1 and reads how many columns are
-    // still iterating, so the queue never drains and at most one speculative
-    // step runs (fully masked) after the last column stops.
-    for (int l = 0; l < restart; ++l) {
+    // Arnoldi steps, two per launch while two remain in the cycle. The host
+    // looks one launch behind the device: before enqueuing the next launch it
+    // waits for the last step of the one before the current and reads how
+    // many columns are still iterating, so the queue never drains and at most
+    // three speculative steps run (fully masked) after the last column stops.
+    step_recs.clear();
+    for (int l = 0; l < restart;) {
       const bool use_mixed = mixed && mixed_now;
+      const int k = (l + 2 <= restart) ? 2 : 1;
       if (use_mixed)
         for (int q = 0; q < ncol; ++q)
-          if (!conv[q]) mixed_steps[q] += 1;
-      launch_step(use_mixed);
-      HIPCHK(c, hipEventRecord(c->step_ev[l], c->stream));
-      if (l >= 1) {
-        HIPCHK(c, hipEventSynchronize(c->step_ev[l - 1]));
-        if (c->pinned[l - 1] == 0) break;
+          if (!conv[q]) mixed_steps[q] += k;
+      launch_step(use_mixed, k);
+      HIPCHK(c, hipEventRecord(c->step_ev[l + k - 1], c->stream));
+      const int prev = l - 1;   // last step of the previous launch
+      l += k;
+      if (prev >= 0) {
+        HIPCHK(c, hipEventSynchronize(c->step_ev[prev]));
+        if (c->pinned[prev] == 0) break;
         if (mixed && !mixed_now) {
           double mx = 0.0;
-          for (int q = 0; q < ncol; ++q) mx = std::max(mx, c->pinned_rel[(size_t)(l - 1) * ncol + q]);
+          for (int q = 0; q < ncol; ++q) mx = std::max(mx, c->pinned_rel[(size_t)prev * ncol + q]);
           if (mx <= o.inner_tol) mixed_now = true;
         }
       }
+    }
+    if (c->prof && !step_recs.empty()) {
+      // steps after the first one that left no column iterating did no work
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      int dead = -1;
+      for (int t = 0; t < (int)step_recs.size() && dead < 0; ++t)
+        if (c->pinned[t] == 0) dead = t;
+      if (dead >= 0)
+        for (int t = dead + 1; t < (int)step_recs.size(); ++t)
+          for (size_t r = step_recs[t].first; r < step_recs[t].second; ++r) c->prof_pending[r].spec = true;
     }
     k_backsolve<<<(unsigned)ncol, 64, 0, c->stream>>>(st);
     LAUNCHCHK(c);
@@ -1620,6 +1646,7 @@ gnk_status gnk_profile_read(gnk_ctx* c, gnk_prof* out, int reset) {
       gnk_prof& A = c->prof_acc;
       c->ev_pool.push_back(r.a);
       c->ev_pool.push_back(r.b);
+      if (r.spec) continue;
       if (r.fft) {
         A.launches_fft += 1;
         A.ms_fft += ms;

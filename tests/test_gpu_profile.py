@@ -43,3 +43,22 @@ def test_profile_separates_circulant_products(gk, ctx):
     ctx.profile(False)
     assert p["launches_fft"] == 0 and p["launches"] >= 1
     assert p["pair_cols"] == float(N) * (N - 1)
+
+
+def test_profile_leaves_out_speculative_steps(gk, ctx):
+    # GMRES runs a few fully masked steps after its column stops (two steps per graph
+    # launch, one launch ahead); the profile counts only the products that do work, so
+    # products minus Arnoldi steps is the same for solves of different lengths
+    dom, gam = wl.config1(n=256)
+    dd = gk.DeviceDomain.from_host(dom)
+    g = torch.from_numpy(gam[:, 0].copy()).cuda()
+    extra = []
+    for tol in (1e-6, 1e-9, 1e-12):
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        mu, h, infos, st = ctx.fbie(dd, g, restart=40, tol=tol)
+        p = ctx.profile_read(reset=True)
+        ctx.profile(False)
+        assert st == gk.OK
+        extra.append(p["launches1"] - infos[0]["inner_it"])
+    assert len(set(extra)) == 1, extra
