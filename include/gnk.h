@@ -141,7 +141,9 @@ typedef struct {
  *   outer_it    : restart cycles used;  inner_it: total Arnoldi steps
  *   relres      : GMRES residual estimate at exit
  *   true_relres : ||b - A x|| / ||b|| recomputed with an FP64 product
- *   mixed_steps : Arnoldi steps whose product used FP32 far tiles (GNK_MIXED) */
+ *   mixed_steps : Arnoldi steps whose product used FP32 far tiles (GNK_MIXED); at most
+ *                 inner_it, and in a solve that switches to mixed products part-way it
+ *                 may include up to three speculative steps after the column stopped */
 typedef struct {
   int flag;
   int outer_it;

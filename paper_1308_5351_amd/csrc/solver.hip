@@ -1241,7 +1241,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     I.flag = conv[q] ? 0 : 1;
     I.outer_it = outer[q];
     I.inner_it = inner[q];
-    I.mixed_steps = mixed_steps[q];
+    I.mixed_steps = std::min(mixed_steps[q], I.inner_it);   // the host count includes speculative steps
     I.relres = rel[q];
     I.true_relres = trel[q];
     if (!conv[q]) out.all_converged = false;
