@@ -147,32 +147,42 @@ def fcau_rate(gnk, ctx, torch, reps=10):
 
 
 def subtraction_ablation(gnk, ctx, torch, n=512):
-    """Example 2's comparison: FBIE with and without singularity subtraction on
-    the unit circle with four inner circles at separation eps, against the exact
-    mu of gamma = Re[A f] (f = 1/(z - 2) + sin z)."""
+    """Example 2's comparison: FBIE and FBIEad with and without singularity
+    subtraction on the unit circle with four inner circles at separation eps,
+    theta constant (pi/2) and non-constant (pi/2, 0, pi/2, 0, pi/2). FBIE: error
+    of mu against the exact mu of gamma = Re[A f] (f = 1/(z - 2) + sin z).
+    FBIEad: (I + N* + J) phi = 1 and E_n = |(2 pi/n) sum gamma phi|, which
+    vanishes for the exact phi (Example 1)."""
     import numpy as np
     import workloads as wl
     log("subtraction ablation: Example 2 circles")
     f = lambda z: 1.0 / (z - 2.0) + np.sin(z)
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    kw = dict(restart=40, maxit=40, tol=1e-13)
     rows = []
-    for eps in (1e-1, 1e-2, 1e-3):
-        dom = wl.example2_circles(n, eps)
-        gam, mu_ex = wl.closed_form_rhs(dom, f)
-        dd = gnk.DeviceDomain.from_host(dom)
-        g = torch.from_numpy(gam.copy()).cuda()
-        row = {"eps": eps}
-        for name, sub in (("subtracted", True), ("unsubtracted", False)):
-            ctx.fbie(dd, g, restart=40, maxit=40, tol=1e-13, subtract=sub)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            mu, h, inf, st = ctx.fbie(dd, g, restart=40, maxit=40, tol=1e-13, subtract=sub)
-            torch.cuda.synchronize()
-            row[name] = {"err_mu_inf": float(np.max(np.abs(mu.cpu().numpy() - mu_ex))),
-                         "iters": inf[0]["inner_it"], "ms": round((time.perf_counter() - t) * 1e3, 3),
-                         "status": st}
-        rows.append(row)
+    for tname, theta in (("constant", None), ("non-constant", np.array([np.pi / 2, 0.0, np.pi / 2, 0.0, np.pi / 2]))):
+        for eps in (1e-1, 1e-2, 1e-3):
+            dom = wl.example2_circles(n, eps, theta=theta)
+            gam, mu_ex = wl.closed_form_rhs(dom, f)
+            dd = gnk.DeviceDomain.from_host(dom)
+            g, one = cu(gam), cu(np.ones(dom.N))
+            row = {"theta": tname, "eps": eps, "fbie": {}, "fbiead": {}}
+            for name, sub in (("subtracted", True), ("unsubtracted", False)):
+                ctx.fbie(dd, g, subtract=sub, **kw)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                mu, h, inf, st = ctx.fbie(dd, g, subtract=sub, **kw)
+                torch.cuda.synchronize()
+                row["fbie"][name] = {"err_mu_inf": float(np.max(np.abs(mu.cpu().numpy() - mu_ex))),
+                                     "iters": inf[0]["inner_it"], "ms": round((time.perf_counter() - t) * 1e3, 3),
+                                     "status": st}
+                phi, infa, sta = ctx.fbie_ad(dd, one, subtract=sub, **kw)
+                row["fbiead"][name] = {"E_n": float(abs(2 * np.pi / n * np.dot(gam, phi.cpu().numpy()))),
+                                       "iters": infa[0]["inner_it"], "status": sta}
+            rows.append(row)
     return {"workload": f"Example 2: unit circle and four circles at separation eps, n = {n} per circle "
-                        f"(N = {5 * n}), A = eta, gamma = Re[A f], f = 1/(z - 2) + sin z, GMRES tol 1e-13",
+                        f"(N = {5 * n}), A = exp(i(pi/2 - theta)) eta, gamma = Re[A f], f = 1/(z - 2) + sin z, "
+                        "GMRES restart 40, tol 1e-13",
             "rows": rows}
 
 
