@@ -186,6 +186,54 @@ def subtraction_ablation(gnk, ctx, torch, n=512):
             "rows": rows}
 
 
+def example1_convergence(gnk, ctx, torch):
+    """Example 1 on the unbounded 1089-component stand-in (the 1089 seeded
+    perturbed circles of the far-field block) with n = 64 .. 4096 nodes per
+    component: theta_j = 2 j pi / m, A = exp(i (pi/2 - theta_j)), f(z) = 1/w -
+    sin(1/w), w = z - c with c the centre of the circle nearest 0 (inside a
+    hole, so f is analytic in G with f(inf) = 0), gamma = Re[A f], exact
+    mu = Im[A f] and h = 0; FBIE (restart 10, maxit 10, tol 1e-12, the paper's)
+    and FBIEad on phi = 1 (E_n = |(2 pi/n) sum gamma phi|), both with the
+    treecode (far_tol 1e-13)."""
+    import numpy as np
+    import workloads as wl
+    log("Example 1: 1089 components, n = 64 .. 4096")
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    coeffs, kmin = wl.fourier_perturbed_circles(1089, 4096, [wl.SEED, 99], side=40.0)
+    cen = coeffs[:, -kmin]
+    c0 = cen[np.argmin(np.abs(cen))]
+    f = lambda z: 1.0 / (z - c0) - np.sin(1.0 / (z - c0))
+    rows = []
+    for n in (64, 256, 1024, 4096):
+        dom = wl.domain_from_fourier(coeffs, kmin, n)
+        m = dom.m1 - 1
+        rot = np.repeat(np.exp(1j * (np.pi / 2 - 2 * np.pi * np.arange(dom.m1) / m)), n)
+        fv = f(dom.eta)
+        gam, mu_ex = (rot * fv).real, (rot * fv).imag
+        dd = gnk.DeviceDomain(dom.m1, n, cu(dom.eta), cu(dom.etap), cu(rot), cu(dom.etapp),
+                              cu(np.zeros(dom.N, np.complex128)), dom.c)
+        g = cu(gam)
+        kw = dict(restart=10, maxit=10, tol=1e-12, far_tol=1e-13)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mu, h, inf, st = ctx.fbie(dd, g, **kw)
+        torch.cuda.synchronize()
+        t_fbie = (time.perf_counter() - t) * 1e3
+        t = time.perf_counter()
+        phi, infa, sta = ctx.fbie_ad(dd, cu(np.ones(dom.N)), **kw)
+        torch.cuda.synchronize()
+        t_ad = (time.perf_counter() - t) * 1e3
+        rows.append({"n": n, "N": dom.N, "err_mu_inf": float(np.max(np.abs(mu.cpu().numpy() - mu_ex))),
+                     "err_h_inf": float(np.max(np.abs(h.cpu().numpy()))),
+                     "E_n": float(abs(2 * np.pi / n * np.dot(gam, phi.cpu().numpy()))),
+                     "iters": {"fbie": inf[0]["inner_it"], "fbiead": infa[0]["inner_it"]},
+                     "ms": {"fbie": round(t_fbie, 1), "fbiead": round(t_ad, 1)}, "status": [st, sta]})
+    return {"workload": "1089 seeded perturbed circles (16 Fourier terms each) in a 40 x 40 square, unbounded, "
+                        "theta_j = 2 j pi/m, f = 1/w - sin(1/w); FBIE restart 10 maxit 10 tol 1e-12 and FBIEad "
+                        "with the treecode (far_tol 1e-13), times include building the tree",
+            "rows": rows}
+
+
 def slit_maps(gnk, ctx, torch, n=4096):
     """Examples 3 and 4: the maps onto slit domains from FBIE (restart 25, tol
     1e-12, maxit 40, n = 4096 per circle) at separations 1e-1..1e-4, with
@@ -518,6 +566,7 @@ def main():
         out["far_field"] = far_field(gnk, ctx, torch)
         out["slit_maps"] = slit_maps(gnk, ctx, torch)
         out["circulant"] = circulant_rate(gnk, ctx, torch)
+        out["example1"] = example1_convergence(gnk, ctx, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(dom)
