@@ -199,3 +199,17 @@ def test_slit_map_unbounded_argument_errors(gk, ctx):
     F, lev, info, st = ctx.slit_map(e, p, d.m1, d.n, 2.0 + 2.0j, [0.0, 0.0, np.pi / 2, 0.0, np.pi / 2],
                                     bounded=False)
     assert st == gk.OK
+
+
+def test_slit_map_unbounded_treecode(gk, ctx):
+    # Example 4's domain at n = 1024 (N = 5120): the treecode solve gives the direct one's map
+    d = wl.example4_circles(1024, 0.1)
+    e, p = _cuda(d.eta), _cuda(d.etap)
+    print(f"[map] example4 treecode N={d.eta.shape[0]}", flush=True)
+    F, lev, info, st = ctx.slit_map(e, p, d.m1, d.n, 2.0 + 2.0j, THETA_EX3, bounded=False, tol=1e-13, restart=40)
+    Ft, levt, infot, stt = ctx.slit_map(e, p, d.m1, d.n, 2.0 + 2.0j, THETA_EX3, bounded=False, tol=1e-13,
+                                       restart=40, far_tol=1e-13)
+    assert st == gk.OK and stt == gk.OK
+    Fh = F.cpu().numpy()
+    assert np.max(np.abs(Ft.cpu().numpy() - Fh)) / np.max(np.abs(Fh)) < 1e-10
+    assert np.max(np.abs(levt - lev)) < 1e-10
