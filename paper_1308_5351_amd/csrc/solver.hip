@@ -897,6 +897,9 @@ struct ApplyArgs {
   // pass (dots of V_{l+1} with V_0..V_l per block of per_blk elements)
   double* dots = nullptr;
   int per_blk = 0, nblk = 0, ldp = 0;
+  // the partial sums of E(w x) from the last pair launch are those this
+  // operator needs (same weights and x): apply only the epilogue
+  bool reuse_sums = false;
 };
 
 void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const ApplyArgs& a = {}) {
@@ -932,11 +935,17 @@ void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const Ap
   }
   const int M = B.maxm1;
   double* mean = need_mean ? ws<double>(c, "mean", (size_t)B.ncol * M) : nullptr;
-  k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
-      B.d_dom, B.d_col, cw, x, a.scale, a.active, a.xout, 0, mean, M, a.step, a.stepT);
-  LAUNCHCHK(c);
+  if (a.reuse_sums && (need_mean || a.dots || a.xout || a.step || a.scale)) {
+    set_err(c, "internal: reused sums need a plain product of x");
+    throw Fail{GNK_ERR_ARG};
+  }
+  if (!a.reuse_sums) {
+    k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
+        B.d_dom, B.d_col, cw, x, a.scale, a.active, a.xout, 0, mean, M, a.step, a.stepT);
+    LAUNCHCHK(c);
+  }
   const double* xin = a.xout ? a.xout : x;
-  pairs(c, B, P_GM, a.mixed, a.active);
+  if (!a.reuse_sums) pairs(c, B, P_GM, a.mixed, a.active);
   if (a.dots) {
     if (!a.step || x != y || op == GNK_OP_FC || op == GNK_OP_FC_T || op == GNK_OP_LHAT) {
       set_err(c, "internal: fused Gram-Schmidt epilogue needs an Arnoldi step of FB, FB_T, GB or GB_T");
@@ -958,6 +967,9 @@ void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const Ap
 struct GmresOut {
   std::vector<gnk_info> info;
   bool all_converged = false;
+  // the last pair launch was the FP64 residual product of the returned x for
+  // every column, with the weights rho x (FB, FB_U): D.parts hold E(rho x)
+  bool sums_of_x = false;
 };
 
 // Restarted GMRES on every column of the batch (x, b: flat). With `mixed`,
@@ -1137,6 +1149,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   };
 
   std::vector<int> outer(ncol, 0), conv(ncol, 0), mixed_steps(ncol, 0);
+  bool sums_of_x = false;
   bool mixed_now = false;
   while ((int)c->step_ev.size() < kMaxRestart) {
     hipEvent_t e;
@@ -1209,6 +1222,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     LAUNCHCHK(c);
     // true residual of the new iterate (FP64 product) and the next cycle's start
     apply_op(c, B, op, x, V, am);
+    sums_of_x = (op == GNK_OP_FB || op == GNK_OP_FB_U);
     k_residual<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, b, V, per_blk, P1, ldp);
     LAUNCHCHK(c);
     cycle_start(P1);
@@ -1223,6 +1237,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     }
   }
   GmresOut out;
+  out.sums_of_x = sums_of_x;
   out.info.resize(ncol);
   std::vector<double> rel(ncol), trel(ncol);
   std::vector<int> inner(ncol);
@@ -1401,8 +1416,11 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
   // (2I + diag(B1) - B) mu = b, or (I - B - diag(Nd)) mu = b
   GmresOut g = gmres(c, B, unsub ? GNK_OP_FB_U : GNK_OP_FB, b, o, mu, o.prec == GNK_MIXED);
   if (h) {
-    // h = [(D - diag(D1) + Lhat) mu - (2I + diag(B1) - B) gamma] / 2
-    apply_op(c, B, GNK_OP_FC, mu, h);
+    // h = [(D - diag(D1) + Lhat) mu - (2I + diag(B1) - B) gamma] / 2; D mu from
+    // the sums of GMRES's last (FP64) residual product of mu when it left them
+    ApplyArgs ah;
+    ah.reuse_sums = g.sums_of_x;
+    apply_op(c, B, GNK_OP_FC, mu, h, ah);
     k_axpby<<<nblocks(T), kT, 0, c->stream>>>(-0.5, fbg, 0.5, h, T);
     LAUNCHCHK(c);
   }
