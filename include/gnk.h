@@ -159,6 +159,19 @@ typedef struct {
  * Arnoldi step of GMRES is captured once per solve into a hipGraph and
  * replayed (GNK_GRAPH=0 disables this; so does profiling with gnk_profile);
  * a caller stream must therefore be capturable (not the legacy null stream). */
+/* Environment (all optional):
+ *   GNK_WORKSPACE_MB=m   cap the context's workspace at m MiB (GNK_ERR_OOM beyond)
+ *   GNK_GRAPH=0          launch every kernel directly instead of replaying graphs
+ *   GNK_LOG=1            print each GMRES cycle's true residual to stderr
+ *   GNK_TUNE, GNK_TUNE_CACHE   the batched autotuner (see gnk_fbie_batched)
+ *   GNK_CAUCHY_TPT=1|2, GNK_CAUCHY_SPLITS=s   override the pair kernels' targets
+ *                        per lane and source splits (the planner's choice otherwise)
+ *   GNK_MIXED_THETA=t    separation factor of the far-tile test (default 1): a
+ *                        source tile is far from a target tile when their
+ *                        bounding circles are (1 + t)(r_t + r_s) apart
+ *   GNK_TREE_SPLITS=s    override the treecode's splits per target tile
+ * The overrides change launch shapes and the near/far split (in mixed precision,
+ * which pairs are summed in FP32), never which pairs are summed. */
 GNK_API gnk_status gnk_create(gnk_ctx** ctx, int device);
 GNK_API gnk_status gnk_destroy(gnk_ctx* ctx);
 GNK_API gnk_status gnk_set_stream(gnk_ctx* ctx, void* hip_stream);
