@@ -1104,15 +1104,8 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   // profiling: the pair records of each step of the cycle, so that those of the
   // fully masked speculative steps can be left out of the totals
   std::vector<std::pair<size_t, size_t>> step_recs;
-  auto launch_step = [&](bool use_mixed, int k) {
-    if (!use_graph) {
-      for (int i = 0; i < k; ++i) {
-        const size_t r0 = c->prof_pending.size();
-        enqueue_step(use_mixed);
-        step_recs.emplace_back(r0, c->prof_pending.size());
-      }
-      return;
-    }
+  // capture (or update the cached executable of) the graph of k steps
+  auto prepare_step = [&](bool use_mixed, int k) {
     const int m = (use_mixed ? 1 : 0) + 2 * (k - 1);
     hipGraphExec_t& ge = c->step_exec[m];
     if (!fresh[m]) {
@@ -1145,8 +1138,26 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
       HIPCHK(c, e);
       fresh[m] = true;
     }
-    HIPCHK(c, hipGraphLaunch(ge, c->stream));
+    return ge;
   };
+  auto launch_step = [&](bool use_mixed, int k) {
+    if (!use_graph) {
+      for (int i = 0; i < k; ++i) {
+        const size_t r0 = c->prof_pending.size();
+        enqueue_step(use_mixed);
+        step_recs.emplace_back(r0, c->prof_pending.size());
+      }
+      return;
+    }
+    HIPCHK(c, hipGraphLaunch(prepare_step(use_mixed, k), c->stream));
+  };
+  // The first launch's graph is prepared before the host first waits on the
+  // stream, so that the capture overlaps the kernels still queued (right-hand
+  // side, initial residual) instead of leaving the GPU idle at the cycle
+  // start. A mixed solve from a zero start takes mixed steps at once when
+  // inner_tol >= 1 (its starting relative residual is 1); a wrong guess only
+  // costs a capture.
+  if (use_graph) (void)prepare_step(mixed && !o.x0 && o.inner_tol >= 1.0, restart >= 2 ? 2 : 1);
 
   std::vector<int> outer(ncol, 0), conv(ncol, 0), mixed_steps(ncol, 0);
   bool sums_of_x = false;
