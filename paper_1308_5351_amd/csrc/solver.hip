@@ -54,6 +54,8 @@ struct gnk_ctx {
   double* pinned_rel = nullptr;          // host-pinned residual estimates (mixed switch)
   size_t pinned_rel_n = 0;
   std::vector<hipEvent_t> step_ev;       // one event per Arnoldi step
+  int* vflags = nullptr;                 // host-pinned input-check flags
+  hipEvent_t val_ev = nullptr;           // recorded after the input checks
   // optional timing of the Cauchy-sum launches (HIP events on the context stream)
   bool prof = false;
   struct ProfRec {
@@ -829,7 +831,14 @@ void circulant(gnk_ctx* c, Batch& B, const double* x, double* y, double sign) {
 dim3 node_grid(const Batch& B) { return dim3(nblocks(B.maxN), (unsigned)B.ndom); }
 dim3 col_grid(const Batch& B) { return dim3(nblocks(B.maxN), (unsigned)B.ncol); }
 
-void validate(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
+// Input checks on the device (finite values, A and, where the operator needs
+// it, eta' nonzero). validate_enqueue queues them and the copy of their flags
+// to host-pinned memory; validate_finish waits for that copy alone and throws
+// on a failed check. Between the two a caller may queue work that writes only
+// the library's workspace (the right-hand side product, diagonals), so that
+// the wait overlaps it; nothing the caller owns is written before the finish,
+// and an error return synchronises the stream first.
+void validate_enqueue(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
   int* flags = ws<int>(c, "flags", 1);
   HIPCHK(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
   k_validate<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, (B.adjoint || B.second) ? 1 : 0, flags);
@@ -838,11 +847,16 @@ void validate(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
     k_check_finite<<<nblocks(len), kT, 0, c->stream>>>(x, len, flags);
     LAUNCHCHK(c);
   }
-  int* hf = reinterpret_cast<int*>(hostio(c, sizeof(int)));
-  k_publish_ints<<<1, 64, 0, c->stream>>>(flags, 1, hostio_dev(c, hf));
+  if (!c->vflags) HIPCHK(c, hipHostMalloc((void**)&c->vflags, sizeof(int), 0));
+  if (!c->val_ev) HIPCHK(c, hipEventCreateWithFlags(&c->val_ev, hipEventDisableTiming));
+  k_publish_ints<<<1, 64, 0, c->stream>>>(flags, 1, hostio_dev(c, c->vflags));
   LAUNCHCHK(c);
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  const int h = hf[0];
+  HIPCHK(c, hipEventRecord(c->val_ev, c->stream));
+}
+
+void validate_finish(gnk_ctx* c) {
+  HIPCHK(c, hipEventSynchronize(c->val_ev));
+  const int h = *reinterpret_cast<volatile int*>(c->vflags);
   if (h & 1) {
     set_err(c, "non-finite value in the inputs");
     throw Fail{GNK_ERR_NONFINITE};
@@ -855,6 +869,11 @@ void validate(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
     set_err(c, "eta' vanishes at a node (the adjoint equation divides by eta')");
     throw Fail{GNK_ERR_ZERO_ETAP};
   }
+}
+
+void validate(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
+  validate_enqueue(c, B, x, len);
+  validate_finish(c);
 }
 
 // rho, and diag(B1), diag(D1) from S = E(rho) (leading column only)
@@ -1393,7 +1412,7 @@ PairShape tuned_shape(gnk_ctx* c, int ndom, const gnk_domain* doms, const int* n
 // gam, mu, h: flat vectors of the batch (h may be null).
 GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, double* mu, double* h) {
   const int64_t T = B.T;
-  validate(c, B, gam, T);
+  validate_enqueue(c, B, gam, T);
   k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
   LAUNCHCHK(c);
   // one launch for E(rho) (leading column) and E(rho gamma) (data columns)
@@ -1424,6 +1443,7 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
                                                     nullptr, 1, fbg, nullptr, 0);
     LAUNCHCHK(c);
   }
+  validate_finish(c);
   // (2I + diag(B1) - B) mu = b, or (I - B - diag(Nd)) mu = b
   GmresOut g = gmres(c, B, unsub ? GNK_OP_FB_U : GNK_OP_FB, b, o, mu, o.prec == GNK_MIXED);
   if (h) {
@@ -1439,10 +1459,11 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
 }
 
 GmresOut fbiead_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, double* mu) {
-  validate(c, B, gam, B.T);
+  validate_enqueue(c, B, gam, B.T);
   k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
   LAUNCHCHK(c);
   setup_evec(c, B);
+  validate_finish(c);
   if (o.no_subtraction) {
     setup_ndiag(c, B);
     return gmres(c, B, GNK_OP_GB_U, gam, o, mu, o.prec == GNK_MIXED);
@@ -1644,6 +1665,8 @@ gnk_status gnk_destroy(gnk_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->val_ev) (void)hipEventDestroy(c->val_ev);
+  if (c->vflags) (void)hipHostFree(c->vflags);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->pinned_rel) (void)hipHostFree(c->pinned_rel);
   if (c->hostio) (void)hipHostFree(c->hostio);
