@@ -1186,20 +1186,24 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     c->step_ev.push_back(e);
   }
-  // per-column results read back through host-mapped memory: [live, converged..]
-  // at each cycle start; converged, inner_it, relres, true_relres at the end
+  // per-column results read back through host-mapped memory at each cycle
+  // start: [live, converged.., inner_it..] and [true_relres.., relres..]
   char* hio = hostio(c, (sizeof(int) * 2 + sizeof(double) * 2) * (ncol + 1));
   int* hi = reinterpret_cast<int*>(hio);
   double* hd = reinterpret_cast<double*>(hio + sizeof(int) * 2 * (ncol + 1));
   int* hi_dev = hostio_dev(c, hi);
   double* hd_dev = hostio_dev(c, hd);
+  bool published = false;   // the host copy holds the final state
   for (int cyc = 0; cyc < o.maxit; ++cyc) {
     k_publish_cycle<<<nblocks(ncol + 1), kT, 0, c->stream>>>(st, ncol, hi_dev, hd_dev);
     LAUNCHCHK(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int live = hi[0];
     for (int q = 0; q < ncol; ++q) conv[q] = hi[1 + q];
-    if (live == 0) break;
+    if (live == 0) {
+      published = true;
+      break;
+    }
     // a cycle whose starting (FP64) residual is already below inner_tol
     // takes mixed products from its first step
     if (mixed && !mixed_now) {
@@ -1271,14 +1275,16 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   out.info.resize(ncol);
   std::vector<double> rel(ncol), trel(ncol);
   std::vector<int> inner(ncol);
-  k_publish_info<<<nblocks(ncol), kT, 0, c->stream>>>(st, ncol, hi_dev, hd_dev);
-  LAUNCHCHK(c);
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!published) {   // maxit cycles ran: publish the state after the last cycle start
+    k_publish_cycle<<<nblocks(ncol + 1), kT, 0, c->stream>>>(st, ncol, hi_dev, hd_dev);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   for (int q = 0; q < ncol; ++q) {
-    conv[q] = hi[q];
-    inner[q] = hi[ncol + q];
-    rel[q] = hd[q];
-    trel[q] = hd[ncol + q];
+    conv[q] = hi[1 + q];
+    inner[q] = hi[1 + ncol + q];
+    trel[q] = hd[q];
+    rel[q] = hd[ncol + q];
   }
   out.all_converged = true;
   for (int q = 0; q < ncol; ++q) {

@@ -811,26 +811,18 @@ __global__ void k_publish_ints(const int* __restrict__ src, int n, int* __restri
   if (i < n) dst[i] = src[i];
 }
 
-// cycle start: dst[0] = iterating columns, dst[1 + c] = converged flags,
-// rel[c] = true relative residual
+// cycle start (and end of a solve): dst[0] = iterating columns, dst[1 + c] =
+// converged flags, dst[1 + ncol + c] = inner iterations, rel[c] = true
+// relative residual, rel[ncol + c] = residual estimate
 __global__ void k_publish_cycle(GmresState st, int ncol, int* __restrict__ dst, double* __restrict__ rel) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) dst[0] = *st.live;
   if (i < ncol) {
     dst[1 + i] = st.converged[i];
+    dst[1 + ncol + i] = st.inner_it[i];
     rel[i] = st.true_relres[i];
+    rel[ncol + i] = st.relres[i];
   }
-}
-
-// end of a solve: converged and inner iterations (ints), residual estimate and
-// true relative residual (doubles), each ncol long
-__global__ void k_publish_info(GmresState st, int ncol, int* __restrict__ di, double* __restrict__ dd) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ncol) return;
-  di[i] = st.converged[i];
-  di[ncol + i] = st.inner_it[i];
-  dd[i] = st.relres[i];
-  dd[ncol + i] = st.true_relres[i];
 }
 
 // inner_it counters etc. to zero

@@ -275,6 +275,17 @@ def test_error_paths(gk, ctx):
     mu, h, infos, st = ctx.fbie(dd, g, restart=1, maxit=1)
     assert st == gk.NOT_CONVERGED and infos[0]["flag"] == 1
     assert torch.isfinite(mu).all()
+    # the state after the last cycle: one cycle of one step; from a zero start
+    # one step cannot raise the residual, and at a restart the Givens estimate
+    # equals the true residual up to rounding
+    inf = infos[0]
+    assert inf["outer_it"] == 1 and inf["inner_it"] == 1
+    assert 0.0 < inf["true_relres"] <= 1.0
+    assert abs(inf["relres"] - inf["true_relres"]) <= 1e-8 * inf["true_relres"]
+    # two cycles of one step: the counts follow the cycles
+    _, _, infos2, st2 = ctx.fbie(dd, g, restart=1, maxit=2)
+    assert st2 == gk.NOT_CONVERGED and infos2[0]["outer_it"] == 2 and infos2[0]["inner_it"] == 2
+    assert infos2[0]["true_relres"] <= inf["true_relres"] * (1 + 1e-12)
     # bad options
     with pytest.raises(gk.GnkError) as e:
         ctx.fbie(dd, g, restart=0)
