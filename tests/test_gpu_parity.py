@@ -168,6 +168,35 @@ def test_fbie_config0(gk, ctx, kind):
     assert e_mu < 1e-10 and e_h < 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fbie_initial_guess(gk, ctx, prec):
+    """The options' initial guess x0. Started at the oracle's mu the solve stops at
+    the first cycle start; started at a perturbed mu it reaches the oracle's mu and
+    h in fewer Arnoldi steps than from zero. In mixed precision a start from x0
+    first prepares FP64 steps, and the cycle start (residual below inner_tol)
+    switches to mixed ones."""
+    dom, gam = wl.config0("eta-alpha")
+    dd = gk.DeviceDomain.from_host(dom)
+    g = _cuda(gam)
+    mu_o, h_o = orc.fbie(dom.eta, dom.etap, dom.A, gam, dom.n)
+    gs = np.max(np.abs(gam))
+    p = gk.MIXED if prec == "mixed" else gk.FP64
+    _, _, inf0, st0 = ctx.fbie(dd, g, prec=p)
+    assert st0 == 0
+    mu, h, inf1, st1 = ctx.fbie(dd, g, prec=p, x0=_cuda(mu_o))
+    print(f"[x0] {prec}: from zero {inf0[0]}, from the solution {inf1[0]}", flush=True)
+    assert st1 == 0 and inf1[0]["inner_it"] <= 1
+    assert _rel(mu.cpu().numpy(), mu_o, gs) < 1e-10 and _rel(h.cpu().numpy(), h_o, gs) < 1e-10
+    rng = np.random.default_rng(17)
+    x0 = mu_o + 1e-6 * gs * rng.standard_normal(mu_o.shape)
+    mu, h, inf2, st2 = ctx.fbie(dd, g, prec=p, x0=_cuda(x0))
+    print(f"[x0] {prec}: from a perturbed solution {inf2[0]}", flush=True)
+    assert st2 == 0 and inf2[0]["inner_it"] < inf0[0]["inner_it"]
+    if prec == "mixed":
+        assert inf2[0]["mixed_steps"] >= 1
+    assert _rel(mu.cpu().numpy(), mu_o, gs) < 1e-10 and _rel(h.cpu().numpy(), h_o, gs) < 1e-10
+
+
 def test_fbie_multi_rhs_ragged(gk, ctx):
     """Several right-hand sides at once on a ragged mesh equal the oracle column by column."""
     dom = wl.circles_unbounded(70, [0j, 1.6 + 0.3j, -1.2 + 1.0j], [0.5, 0.4, 0.45])
