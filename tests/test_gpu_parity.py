@@ -197,6 +197,33 @@ def test_fbie_initial_guess(gk, ctx, prec):
     assert _rel(mu.cpu().numpy(), mu_o, gs) < 1e-10 and _rel(h.cpu().numpy(), h_o, gs) < 1e-10
 
 
+def test_solves_follow_the_current_stream(gk, ctx):
+    """A solve issued while a side torch stream is current is enqueued on that
+    stream (its Arnoldi steps captured there) and equals the solve on the
+    default stream; back on the default stream the context follows again."""
+    dom = wl.example4_circles(128, 1e-1)
+    gam = (dom.eta ** 2).real
+    dd = gk.DeviceDomain.from_host(dom)
+    g = _cuda(gam)
+    mu0, h0, _, st0 = ctx.fbie(dd, g)
+    ad0, _, sa0 = ctx.fbie_ad(dd, g)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        mu1, h1, _, st1 = ctx.fbie(dd, g)
+        ad1, _, sa1 = ctx.fbie_ad(dd, g)
+        done = torch.cuda.Event()
+        done.record(side)
+    torch.cuda.current_stream().wait_stream(side)
+    mu2, h2, _, st2 = ctx.fbie(dd, g)
+    torch.cuda.synchronize()
+    assert done.query()
+    assert st0 == st1 == st2 == 0 and sa0 == sa1 == 0
+    s = np.max(np.abs(gam))
+    for a, b in ((mu1, mu0), (h1, h0), (mu2, mu0), (h2, h0), (ad1, ad0)):
+        assert _rel(a.cpu().numpy(), b.cpu().numpy(), s) < 1e-13
+
+
 def test_fbie_multi_rhs_ragged(gk, ctx):
     """Several right-hand sides at once on a ragged mesh equal the oracle column by column."""
     dom = wl.circles_unbounded(70, [0j, 1.6 + 0.3j, -1.2 + 1.0j], [0.5, 0.4, 0.45])
