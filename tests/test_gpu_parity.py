@@ -348,6 +348,33 @@ def test_error_paths(gk, ctx):
     assert e.value.status == gk.ERR_ARG
 
 
+def test_failed_checks_write_nothing(gk, ctx):
+    """Through the C ABI: a call whose inputs fail the device checks (a
+    non-finite gamma, A = 0 at a node) returns the error and leaves the
+    caller's mu and h as they were, although the checks' result is read only
+    after the right-hand side product has been queued."""
+    import ctypes as C
+    dom, gam = wl.config0("eta-alpha")
+    dd = gk.DeviceDomain.from_host(dom)
+    ctx._bind_stream()
+    o = ctx._opts(25, 40, 1e-12, gk.FP64, 0.0, 0, None)
+    g_bad = _cuda(gam[:, 0].copy())
+    g_bad[7] = float("nan")
+    A0 = dd.A.clone()
+    A0[3] = 0
+    cases = [(dd, g_bad, gk.ERR_NONFINITE),
+             (gk.DeviceDomain(dom.m1, dom.n, dd.eta, dd.etap, A0), _cuda(gam[:, 0].copy()), gk.ERR_ZERO_A)]
+    for dom_dev, g, want in cases:
+        mu = torch.full((dom.N,), 123.0, dtype=torch.float64, device="cuda")
+        h = torch.full((dom.N,), -7.0, dtype=torch.float64, device="cuda")
+        infos = (gk.Info * 1)()
+        d = dom_dev._struct()
+        st = ctx.lib.gnk_fbie(ctx.h, C.byref(d), g.data_ptr(), 1, C.byref(o), mu.data_ptr(), h.data_ptr(), infos)
+        torch.cuda.synchronize()
+        assert st == want
+        assert bool((mu == 123.0).all()) and bool((h == -7.0).all())
+
+
 def test_workspace_cap(gk, monkeypatch):
     monkeypatch.setenv("GNK_WORKSPACE_MB", "1")
     c = gk.Context(0)
