@@ -373,6 +373,16 @@ def test_failed_checks_write_nothing(gk, ctx):
         torch.cuda.synchronize()
         assert st == want
         assert bool((mu == 123.0).all()) and bool((h == -7.0).all())
+    # FBIEad: eta' = 0 at a node
+    ep0 = dd.etap.clone()
+    ep0[5] = 0
+    d = gk.DeviceDomain(dom.m1, dom.n, dd.eta, ep0, dd.A, dd.etapp, dd.Ap, dom.c)._struct()
+    mu = torch.full((dom.N,), 123.0, dtype=torch.float64, device="cuda")
+    infos = (gk.Info * 1)()
+    g = _cuda(gam[:, 0].copy())
+    st = ctx.lib.gnk_fbie_ad(ctx.h, C.byref(d), g.data_ptr(), 1, C.byref(o), mu.data_ptr(), infos)
+    torch.cuda.synchronize()
+    assert st == gk.ERR_ZERO_ETAP and bool((mu == 123.0).all())
 
 
 def test_workspace_cap(gk, monkeypatch):
