@@ -1044,13 +1044,13 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   dim3 gv((unsigned)nblk, (unsigned)ncol);
   k_norm_partial<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, b, per_blk, P1, ldp);
   LAUNCHCHK(c);
-  k_bnorm<<<cb, 256, 0, c->stream>>>(P1, nblk, ldp, ncol, st);
+  k_bnorm<<<(unsigned)ncol, 64, 0, c->stream>>>(P1, nblk, ldp, st);
   LAUNCHCHK(c);
 
   auto cycle_start = [&](const double* partial) {
     k_cycle_reset<<<1, 1, 0, c->stream>>>(st);
     LAUNCHCHK(c);
-    k_cycle_start<<<cb, 256, 0, c->stream>>>(partial, nblk, ldp, ncol, o.tol, st);
+    k_cycle_start<<<(unsigned)ncol, 64, 0, c->stream>>>(partial, nblk, ldp, o.tol, st);
     LAUNCHCHK(c);
   };
   // r0 = b - A x0 into V_0

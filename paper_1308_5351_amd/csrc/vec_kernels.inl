@@ -635,23 +635,29 @@ __global__ __launch_bounds__(kT) void k_residual(const DomDev* __restrict__ doms
   if (threadIdx.x == 0) partial[((size_t)c * nblk + blk) * ldp] = s;
 }
 
-// One thread per column: ||b|| from partials.
-__global__ void k_bnorm(const double* partial, int nblk, int ldp, int ncol, GmresState st) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncol) return;
+// Sum of column c's nblk block partials, one 64-lane block per column (the
+// lanes' loads are in flight together; the order is fixed).
+__device__ __forceinline__ double column_partials(const double* partial, int nblk, int ldp, int c) {
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[((size_t)c * nblk + b) * ldp];
-  st.bnorm[c] = sqrt(s);
+  for (int b = threadIdx.x; b < nblk; b += 64) s += partial[((size_t)c * nblk + b) * ldp];
+  return wave_sum(s);
 }
 
-// Start of a restart cycle, one thread per column: beta0 = ||r|| from the
-// partials, true relative residual, convergence test, g = beta0 e_1. The
+// ||b|| of column c = blockIdx.x from the partials (64 threads per block)
+__global__ __launch_bounds__(64) void k_bnorm(const double* partial, int nblk, int ldp, GmresState st) {
+  const int c = blockIdx.x;
+  const double s = column_partials(partial, nblk, ldp, c);
+  if (threadIdx.x == 0) st.bnorm[c] = sqrt(s);
+}
+
+// Start of a restart cycle, one 64-lane block per column: beta0 = ||r|| from
+// the partials, true relative residual, convergence test, g = beta0 e_1. The
 // number of iterating columns is accumulated in *st.live (zeroed before).
-__global__ void k_cycle_start(const double* partial, int nblk, int ldp, int ncol, double tol, GmresState st) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncol) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[((size_t)c * nblk + b) * ldp];
+__global__ __launch_bounds__(64) void k_cycle_start(const double* partial, int nblk, int ldp, double tol,
+                                                    GmresState st) {
+  const int c = blockIdx.x;
+  const double s = column_partials(partial, nblk, ldp, c);
+  if (threadIdx.x != 0) return;
   const double beta = sqrt(s);
   const double bn = st.bnorm[c];
   const double rel = bn > 0.0 ? beta / bn : 0.0;
