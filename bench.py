@@ -588,6 +588,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the mixed and batched comparisons")
     ap.add_argument("--batched-mixed-only", action="store_true",
                     help="run only the 64-domain batched solve in mixed precision (warm-up + one timed call)")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="run only the close-boundary FP64 vs mixed comparison")
     ap.add_argument("--circulant-only", action="store_true",
                     help="run only the circulant-product measurement (for kernel traces of the FFT)")
     ap.add_argument("--far-field-only", action="store_true",
@@ -617,6 +619,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"batched_mixed_s": round(time.perf_counter() - t, 3), "status": st,
                           "max_iters": max(i["inner_it"] for inf in infos for i in inf)}), flush=True)
+        ctx.close()
+        return
+
+    if args.mixed_only:
+        ctx = gnk.Context(0)
+        print(json.dumps({"mixed_vs_plain": mixed_vs_plain(gnk, ctx, torch)}), flush=True)
         ctx.close()
         return
 

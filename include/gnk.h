@@ -113,7 +113,10 @@ typedef struct {
  *                is reached
  *   inner_tol  : GNK_MIXED switch level (0: min(1e-4, tol * 1e8), since the
  *                mixed products have a relative error below 1e-8)
- *   max_refine : reserved (0)
+ *   max_refine : GNK_MIXED: at most this many restart cycles take mixed
+ *                products (each is followed by the cycle's FP64 residual, one
+ *                step of iterative refinement); the cycles after them take
+ *                FP64 products. 0: no limit. Ignored for GNK_FP64.
  *   x0         : optional device initial guess (N x nrhs) or NULL for zero
  *   no_subtraction : 0 (the paper's method); 1 solves gnk_fbie / gnk_fbie_ad
  *                without singularity subtraction (GNK_OP_FB_U / GNK_OP_GB_U,
@@ -123,7 +126,17 @@ typedef struct {
  *                their far field from multipole expansions of boxes of
  *                consecutive nodes (a treecode; the paper uses the FMM), each
  *                truncated where (r_box / distance)^p <= far_tol; FP64 only
- *                (prec GNK_FP64), gnk_fbie and gnk_fbie_ad only; 1e-15..0.1 */
+ *                (prec GNK_FP64), gnk_fbie and gnk_fbie_ad only; 1e-15..0.1
+ *   hist, hist_len : optional residual history (the paper reports GMRES's
+ *                convergence, Sec. 7): HOST array of hist_len doubles per
+ *                right-hand side (column r at hist + r * hist_len, in the order
+ *                of the info entries), caller-owned. Per column it receives the
+ *                relative true residual (FP64 product) at the start of each
+ *                restart cycle, each followed by the relative residual estimate
+ *                after each Arnoldi step of that cycle, and finally the true
+ *                residual that ended the solve; gnk_info.hist_count entries are
+ *                written, the rest are left untouched. hist_len 0 (hist NULL):
+ *                no history; hist_len > 0 needs hist. */
 typedef struct {
   int restart;
   int maxit;
@@ -134,6 +147,8 @@ typedef struct {
   const double* x0;
   int no_subtraction;
   double far_tol;
+  double* hist;
+  int hist_len;
 } gnk_opts;
 
 /* Per right-hand side outcome (host memory, one entry per column).
@@ -143,7 +158,10 @@ typedef struct {
  *   true_relres : ||b - A x|| / ||b|| recomputed with an FP64 product
  *   mixed_steps : Arnoldi steps whose product used FP32 far tiles (GNK_MIXED); at most
  *                 inner_it, and in a solve that switches to mixed products part-way it
- *                 may include up to three speculative steps after the column stopped */
+ *                 may include up to three speculative steps after the column stopped
+ *   refine_steps: GNK_MIXED: restart cycles of this column that took mixed products,
+ *                 each followed by an FP64 residual (refinement steps); 0 for GNK_FP64
+ *   hist_count  : entries written to this column's residual history (0 without one) */
 typedef struct {
   int flag;
   int outer_it;
@@ -151,6 +169,8 @@ typedef struct {
   int mixed_steps;
   double relres;
   double true_relres;
+  int refine_steps;
+  int hist_count;
 } gnk_info;
 
 /* Context lifetime. device: HIP device ordinal. The context owns a blocking

@@ -74,7 +74,7 @@ class FBIESolve(torch.autograd.Function):
         dom, opts, gctx = ctx.dom, ctx.opts, ctx.gctx
         if g_mu is None and g_h is None:
             return (None,) * 8
-        o = {k: v for k, v in opts.items() if k in ("restart", "maxit", "tol", "prec", "inner_tol")}
+        o = dict(opts)
         lam, g_gam, infos, st = gctx.fbie_adjoint(dom, g_mu, g_h, **o)
         if st != gnk.OK:
             raise gnk.GnkError(st, f"adjoint GMRES did not converge: {infos}")
@@ -99,7 +99,18 @@ def fourier_curve(coef: torch.Tensor, kmin: int, n: int, ccw: bool = False, cont
     return FourierCurve.apply(coef, kmin, n, ccw, gctx)
 
 
+_SOLVE_OPTS = ("restart", "maxit", "tol", "prec", "inner_tol", "max_refine")
+
+
 def fbie(eta, etap, A, gam, m1: int, n: int, context: Optional[gnk.Context] = None, **opts):
-    """Differentiable FBIE; opts: restart, maxit, tol, prec, inner_tol (as Context.fbie)."""
+    """Differentiable FBIE; opts: restart, maxit, tol, prec, inner_tol, max_refine
+    (as Context.fbie). The forward and the adjoint solve use the same options.
+    Options that change the discrete map (far_tol > 0: the treecode's truncated
+    sums; subtract=False: the equation without singularity subtraction) have no
+    matching adjoint and are rejected."""
+    bad = sorted(k for k in opts if k not in _SOLVE_OPTS)
+    if bad:
+        raise ValueError(f"autograd.fbie does not take {bad}: only {list(_SOLVE_OPTS)} (the adjoint solve "
+                         "differentiates the FBIE map with directly summed products and singularity subtraction)")
     gctx = context or default_context(eta.device.index)
     return FBIESolve.apply(eta, etap, A, gam, m1, n, opts, gctx)

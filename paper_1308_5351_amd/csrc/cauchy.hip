@@ -101,42 +101,75 @@ __device__ __forceinline__ void single_step_far(AccAB<NR, TPT>& acc, const doubl
 // Mixed precision: well-separated source tiles in FP32, the rest in FP64.
 // A source tile is 64 consecutive nodes with bounding circle (c_s, r_s); the
 // workgroup's target tile has (c_t, r_t). The tile pair is far when
-// |c_t - c_s| > (1 + theta)(r_t + r_s). For a far tile every lane forms
-// u = (eta_i - c_s) in FP64 and rounds it to FP32; the records hold
-// v_j = (eta_j - c_s) in FP32, so d = u - v keeps a relative error of a few
-// FP32 ulps however far the tiles are from the origin. The tile's 64 terms
-// are summed in FP32 and added to the FP64 accumulators.
+// |c_t - c_s| > (1 + theta)(r_t + r_s). The FP32 records hold
+// v_j = eta_j - c_s (formed in FP64, then rounded), a_j = |v_j|^2, the weights
+// w_j and b_j = w_j conj(v_j); every lane forms z' = z_i - c_s in FP64 and
+// rounds it. As in the FP64 far form,
+//   S_i = conj(z') sum_j w_j m_j - sum_j b_j m_j,  m_j = 1/|z' - v_j|^2,
+//   |z' - v_j|^2 = a_j + |z'|^2 - 2 v_j . z'   (one add, two FMAs),
+// with one FP32 reciprocal per pair (|z' - v_j|^2 itself stays within the
+// FP32 range for distances between 1e-19 and 1e19, whatever the scale of the
+// domain) and four FMAs per column. The tile's 64 terms are summed in FP32;
+// the combination with conj(z') is made in FP64 and added to the FP64
+// accumulators. The pair is far, so |z'| > 2 |v_j| and the distance keeps all
+// but a few bits (it is at least a fifth of a_j + |z'|^2).
 template <int NR, int TPT>
-struct Acc32 {
-  float x[TPT][NR];
-  float y[TPT][NR];
+struct AccAB32 {
+  float ax[TPT][NR], ay[TPT][NR], bx[TPT][NR], by[TPT][NR];
 };
 
-template <int NR, int TPT, class P>
-__device__ __forceinline__ void accumulate32(Acc32<NR, TPT>& a, int t, P wj, float qx, float qy) {
+// one source (record fields already loaded) against the lane's TPT targets
+template <int NR, int TPT>
+__device__ __forceinline__ void step_far32(AccAB32<NR, TPT>& a, const float (&m2x)[TPT], const float (&m2y)[TPT],
+                                           const float (&zz)[TPT], float2 v, float av, const float2 (&w)[NR],
+                                           const float2 (&b)[NR]) {
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const float2 w = wj[r];
-    a.x[t][r] = __builtin_fmaf(w.x, qx, a.x[t][r]);
-    a.x[t][r] = __builtin_fmaf(-w.y, qy, a.x[t][r]);
-    a.y[t][r] = __builtin_fmaf(w.x, qy, a.y[t][r]);
-    a.y[t][r] = __builtin_fmaf(w.y, qx, a.y[t][r]);
+  for (int t = 0; t < TPT; ++t) {
+    const float m = __builtin_amdgcn_rcpf(__builtin_fmaf(v.x, m2x[t], __builtin_fmaf(v.y, m2y[t], av + zz[t])));
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      a.ax[t][q] = __builtin_fmaf(w[q].x, m, a.ax[t][q]);
+      a.ay[t][q] = __builtin_fmaf(w[q].y, m, a.ay[t][q]);
+      a.bx[t][q] = __builtin_fmaf(b[q].x, m, a.bx[t][q]);
+      a.by[t][q] = __builtin_fmaf(b[q].y, m, a.by[t][q]);
+    }
   }
 }
 
+// the sources [ts, te) of one far tile: four records fetched (wave-uniform
+// scalar loads) before their arithmetic, so one wait covers four sources
 template <int NR, int TPT, class P>
-__device__ __forceinline__ void pair_step32(Acc32<NR, TPT>& acc, const float2 (&u)[TPT], P ra, P rb, int wo) {
-  const float2 ea = ra[0], eb = rb[0];
+__device__ __forceinline__ void tile_far32(AccAB32<NR, TPT>& a, const float (&m2x)[TPT], const float (&m2y)[TPT],
+                                           const float (&zz)[TPT], P rec32, int stride32, int wo, int wb, int ts,
+                                           int te) {
+  int j = ts;
+  for (; j + 3 < te; j += 4) {
+    P r = rec32 + (size_t)j * stride32;
+    float2 v[4], w[4][NR], b[4][NR];
+    float av[4];
 #pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    const float dxa = u[t].x - ea.x, dya = u[t].y - ea.y;
-    const float dxb = u[t].x - eb.x, dyb = u[t].y - eb.y;
-    const float da = __builtin_fmaf(dya, dya, dxa * dxa);
-    const float db = __builtin_fmaf(dyb, dyb, dxb * dxb);
-    const float R = __builtin_amdgcn_rcpf(da * db);
-    const float qa = db * R, qb = da * R;
-    accumulate32<NR, TPT>(acc, t, ra + wo, dxa * qa, -dya * qa);
-    accumulate32<NR, TPT>(acc, t, rb + wo, dxb * qb, -dyb * qb);
+    for (int k = 0; k < 4; ++k) {
+      P rk = r + k * stride32;
+      v[k] = rk[0];
+      av[k] = rk[1].x;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        w[k][q] = rk[wo + q];
+        b[k][q] = rk[wb + q];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) step_far32<NR, TPT>(a, m2x, m2y, zz, v[k], av[k], w[k], b[k]);
+  }
+  for (; j < te; ++j) {
+    P r = rec32 + (size_t)j * stride32;
+    float2 w[NR], b[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      w[q] = r[wo + q];
+      b[q] = r[wb + q];
+    }
+    step_far32<NR, TPT>(a, m2x, m2y, zz, r[0], r[1].x, w, b);
   }
 }
 
@@ -286,7 +319,8 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
   constexpr int kTile = 64 * TPT;
   const int wo = kRecHead + col0;            // FP64 record: weights of the item's first column
   const int wb = kRecHead + wcols + col0;    // FP64 record: its b = w conj(eta')
-  const int wo32 = 1 + col0;          // FP32 record: weights
+  const int wo32 = 2 + col0;          // FP32 record: weights of the item's first column
+  const int wb32 = 2 + wcols + col0;  // FP32 record: its b = w conj(v)
   constexpr bool MIXED = MODE == M_MIXED || MODE == M_NEAR;
   // M_EXT: FP64 with targets tz[0..Nt) that are not nodes (no j != i window)
   constexpr bool EXT = MODE == M_EXT;
@@ -396,36 +430,28 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
           any_near = true;
         }
       } else if (far) {
-        float2 u[TPT];
+        double zx[TPT], zy[TPT];
+        float m2x[TPT], m2y[TPT], zz[TPT];
+        AccAB32<NR, TPT> a32;
 #pragma unroll
-        for (int t = 0; t < TPT; ++t) u[t] = make_float2((float)(tg[t].x - sbd.x), (float)(tg[t].y - sbd.y));
-        Acc32<NR, TPT> a32;
+        for (int t = 0; t < TPT; ++t) {
+          zx[t] = tg[t].x - sbd.x;
+          zy[t] = tg[t].y - sbd.y;
+          const float fx = (float)zx[t], fy = (float)zy[t];
+          m2x[t] = -2.f * fx;
+          m2y[t] = -2.f * fy;
+          zz[t] = __builtin_fmaf(fy, fy, fx * fx);
 #pragma unroll
-        for (int t = 0; t < TPT; ++t)
-#pragma unroll
-          for (int r = 0; r < NR; ++r) { a32.x[t][r] = 0.f; a32.y[t][r] = 0.f; }
-        int j = ts;
-#pragma unroll 2
-        for (; j + 1 < te; j += 2) {
-          gptr<const float2> r = rec32 + (size_t)j * stride32;
-          pair_step32<NR, TPT>(a32, u, r, r + stride32, wo32);
+          for (int r = 0; r < NR; ++r) a32.ax[t][r] = a32.ay[t][r] = a32.bx[t][r] = a32.by[t][r] = 0.f;
         }
-        if (j < te) {
-          gptr<const float2> r = rec32 + (size_t)j * stride32;
-          const float2 e = r[0];
-#pragma unroll
-          for (int t = 0; t < TPT; ++t) {
-            const float dx = u[t].x - e.x, dy = u[t].y - e.y;
-            const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
-            accumulate32<NR, TPT>(a32, t, r + wo32, dx * q, -dy * q);
-          }
-        }
+        tile_far32<NR, TPT>(a32, m2x, m2y, zz, rec32, stride32, wo32, wb32, ts, te);
 #pragma unroll
         for (int t = 0; t < TPT; ++t)
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
-            acc.x[t][r] += (double)a32.x[t][r];
-            acc.y[t][r] += (double)a32.y[t][r];
+            const double ax = a32.ax[t][r], ay = a32.ay[t][r];
+            acc.x[t][r] += __builtin_fma(zx[t], ax, zy[t] * ay) - (double)a32.bx[t][r];
+            acc.y[t][r] += __builtin_fma(zx[t], ay, -zy[t] * ax) - (double)a32.by[t][r];
           }
       } else {
         fp64_range(ts, te);
@@ -477,7 +503,7 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 // FP64 variants with one or two columns are held to 64 VGPRs (8 waves per
 // SIMD), which they reach without spilling; the others keep their registers.
 template <int NR, int TPT, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 && (MODE == M_FP64 || MODE == M_EXT)) ? 8 : 1))) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((NR <= 2 && (MODE == M_FP64 || MODE == M_EXT)) || (NR == 1 && MODE == M_MIXED)) ? 8 : 1))) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
                                                int nitems, int lead, int data, const int* __restrict__ active) {
   __shared__ double red[3][TPT][2][64];
   constexpr bool MIXED = MODE == M_MIXED || MODE == M_NEAR;
@@ -510,7 +536,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NR <= 2 &&
   const int j1 = min(jb1, j0 + wchunk);
   pair_item<NR, TPT, MODE>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
                             (gptr<const double4>)D.sbf, (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N,
-                            (gptr<const double2>)D.tz, D.Nt, rec_stride(wcols), 1 + wcols, wcols, col0, width,
+                            (gptr<const double2>)D.tz, D.Nt, rec_stride(wcols), rec32_stride(wcols), wcols, col0,
+                            width,
                             w.y * 64 * TPT, w.y, w.z, j0, j1, D.far2, red);
 }
 
@@ -546,7 +573,7 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
       const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
       const double rr = tbd.z + sbd.z;
       if ((dcx * dcx + dcy * dcy) > far2 * rr * rr)
-        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, rec32, stride32, 1 + col0, ts, te, stg, width);
+        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, rec32, stride32, 2 + col0, ts, te, stg, width);
     }
     __syncthreads();   // fl shares its LDS with the staging areas
     // group b holds rows i (targets 16b + i) in register i % 4 of lane n + 16 (i / 4), column n
@@ -606,7 +633,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int jb0 = w.z * chunk;
   const int jb1 = min(D.N, jb0 + chunk);
   far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
-                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), 1 + wcols, wcols,
+                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), rec32_stride(wcols), wcols,
                     col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, chunk >> 2, D.far2, fl, stg);
 }
 
@@ -646,18 +673,25 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ d
   if (lane == 0) out[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
 }
 
-// FP32 records {v_j = eta_j - c_tile(j) (64-node tile), w_j,q..} (stride 1 + wcols)
-// from the FP64 records (head, w.., b..)
+// FP32 records {v_j = eta_j - c_tile(j) (64-node tile), (|v_j|^2, 0), w_j,q.., b_j,q = w_j,q conj(v_j)..}
+// (stride 2 + 2 wcols) from the FP64 records (head, w.., b..)
 __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data) {
   const DomDev& D = doms[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= D.N) return;
   const int wcols = lead + data * D.ncols;
   const double2* r = D.rec + (size_t)j * rec_stride(wcols);
-  float2* o = D.rec32 + (size_t)j * (1 + wcols);
+  float2* o = D.rec32 + (size_t)j * rec32_stride(wcols);
   const double4 c = D.sb[j >> 6];
-  o[0] = make_float2((float)(r[0].x - c.x), (float)(r[0].y - c.y));
-  for (int q = 0; q < wcols; ++q) o[1 + q] = make_float2((float)r[kRecHead + q].x, (float)r[kRecHead + q].y);
+  const float2 v = make_float2((float)(r[0].x - c.x), (float)(r[0].y - c.y));
+  const double vx = v.x, vy = v.y;
+  o[0] = v;
+  o[1] = make_float2((float)(vx * vx + vy * vy), 0.f);
+  for (int q = 0; q < wcols; ++q) {
+    const double2 w = r[kRecHead + q];
+    o[2 + q] = make_float2((float)w.x, (float)w.y);
+    o[2 + wcols + q] = make_float2((float)(w.x * vx + w.y * vy), (float)(w.y * vx - w.x * vy));
+  }
 }
 
 template <int NR, int TPT, int MODE>

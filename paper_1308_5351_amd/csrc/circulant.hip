@@ -128,13 +128,22 @@ struct FftArgs {
   const double2* tw;
 };
 
+// Every block length of one product in one launch: workgroups first[c] ..
+// first[c + 1] - 1 take class c (the classes' vector lists, lengths, twiddles).
+constexpr int kMaxCirc = 12;   // powers of two 2 .. 4096
+struct FftMulti {
+  FftArgs a[kMaxCirc];
+  int first[kMaxCirc + 1];
+  int nc;
+};
+
 // One pass of F fused stages over every group of the workgroup's P vectors.
 // FIRST: the elements come from x (global), not LDS. SYMBOL: after the last
 // DIF stage, multiply by the symbol (2 i k / n, with the 1/n of the inverse),
 // k the bit reversal of the position. LAST: the results go to y (global,
 // y += sign * result) instead of LDS.
 template <int F, bool DIF, bool FIRST, bool SYMBOL, bool LAST>
-__device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q) {
+__device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q, int wg) {
   const int n = A.n, half = n >> 1;
   const int per = n >> F;   // groups per vector
   for (int g = threadIdx.x; g < A.P * per; g += blockDim.x) {
@@ -142,8 +151,21 @@ __device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q) {
     const int blk = gg / q, j = gg - blk * q;
     const int i0 = (blk << F) * q + j;
     double2* zv = z + (size_t)vl * n;
-    const int va = 2 * (blockIdx.x * A.P + vl);
+    const int va = 2 * (wg * A.P + vl);
     double2 v[1 << F];
+    // LAST: the y values to add to are fetched before the LDS reads and the
+    // butterflies, so their latency overlaps that work
+    double2 yv[LAST ? (1 << F) : 1];
+    if constexpr (LAST) {
+      const bool hasa = va < A.V, hasb = va + 1 < A.V;
+      const double* ya = A.y + (hasa ? A.offs[va] : 0);
+      const double* yb = A.y + (hasb ? A.offs[va + 1] : 0);
+#pragma unroll
+      for (int m = 0; m < (1 << F); ++m) {
+        const int p = i0 + m * q;
+        yv[m] = make_double2(hasa ? ya[p] : 0.0, hasb ? yb[p] : 0.0);
+      }
+    }
     if constexpr (FIRST) {
       const bool hasa = va < A.V, hasb = va + 1 < A.V;
       const double* xa = A.x + (hasa ? A.offs[va] : 0);
@@ -176,8 +198,8 @@ __device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q) {
 #pragma unroll
       for (int m = 0; m < (1 << F); ++m) {
         const int p = i0 + m * q;
-        if (hasa) ya[p] += A.sign * v[m].x;
-        if (hasb) yb[p] += A.sign * v[m].y;
+        if (hasa) ya[p] = __builtin_fma(A.sign, v[m].x, yv[m].x);
+        if (hasb) yb[p] = __builtin_fma(A.sign, v[m].y, yv[m].y);
       }
     } else {
 #pragma unroll
@@ -187,20 +209,25 @@ __device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q) {
 }
 
 template <bool DIF, bool FIRST, bool SYMBOL, bool LAST>
-__device__ __forceinline__ void fft_pass_f(int F, const FftArgs& A, double2* z, int q) {
-  if (F == 3) fft_pass<3, DIF, FIRST, SYMBOL, LAST>(A, z, q);
-  else if (F == 2) fft_pass<2, DIF, FIRST, SYMBOL, LAST>(A, z, q);
-  else fft_pass<1, DIF, FIRST, SYMBOL, LAST>(A, z, q);
+__device__ __forceinline__ void fft_pass_f(int F, const FftArgs& A, double2* z, int q, int wg) {
+  if (F == 3) fft_pass<3, DIF, FIRST, SYMBOL, LAST>(A, z, q, wg);
+  else if (F == 2) fft_pass<2, DIF, FIRST, SYMBOL, LAST>(A, z, q, wg);
+  else fft_pass<1, DIF, FIRST, SYMBOL, LAST>(A, z, q, wg);
 }
 
 // y_k += sign * L x_k for the vectors listed in offs (V of them, length n, a
-// power of two): workgroup b takes the complex vectors b P .. b P + P - 1,
-// vector c carrying the real columns 2c and 2c + 1. Forward DIF (natural ->
-// bit-reversed) in passes of up to three fused stages, the first reading x,
-// the last applying the symbol; inverse DIT (bit-reversed -> natural), the
-// last pass adding into y. Between passes the vectors sit in LDS.
-__global__ __launch_bounds__(kFftThreads) void k_circulant_fft(FftArgs A) {
+// power of two) of every class: workgroup b of a class takes its complex
+// vectors b P .. b P + P - 1, vector c carrying the real columns 2c and 2c + 1.
+// Forward DIF (natural -> bit-reversed) in passes of up to three fused stages,
+// the first reading x, the last applying the symbol; inverse DIT
+// (bit-reversed -> natural), the last pass adding into y. Between passes the
+// vectors sit in LDS.
+__global__ __launch_bounds__(kFftThreads) void k_circulant_fft(FftMulti M) {
   extern __shared__ double2 z[];
+  int c = 0;
+  while (c + 1 < M.nc && (int)blockIdx.x >= M.first[c + 1]) ++c;
+  const FftArgs A = M.a[c];
+  const int wg = (int)blockIdx.x - M.first[c];
   const int L = A.logn;
   const int np = (L + 2) / 3;   // passes per direction; all of 3 stages but the last (L - 3 (np - 1))
   // forward: pass t covers stages with spans n/2 >> 3t .. ; its smallest span is q
@@ -210,10 +237,10 @@ __global__ __launch_bounds__(kFftThreads) void k_circulant_fft(FftArgs A) {
     const int q = 1 << (top - F);
     if (t > 0) __syncthreads();
     const bool first = t == 0, last = t + 1 == np;
-    if (first && last) fft_pass_f<true, true, true, false>(F, A, z, q);
-    else if (first) fft_pass_f<true, true, false, false>(F, A, z, q);
-    else if (last) fft_pass_f<true, false, true, false>(F, A, z, q);
-    else fft_pass_f<true, false, false, false>(F, A, z, q);
+    if (first && last) fft_pass_f<true, true, true, false>(F, A, z, q, wg);
+    else if (first) fft_pass_f<true, true, false, false>(F, A, z, q, wg);
+    else if (last) fft_pass_f<true, false, true, false>(F, A, z, q, wg);
+    else fft_pass_f<true, false, false, false>(F, A, z, q, wg);
     top -= F;
   }
   // inverse: the short pass first (smallest spans), then passes of three
@@ -222,8 +249,8 @@ __global__ __launch_bounds__(kFftThreads) void k_circulant_fft(FftArgs A) {
     const int F = (t == 0) ? L - 3 * (np - 1) : 3;
     const int q = 1 << bottom;
     __syncthreads();
-    if (t + 1 == np) fft_pass_f<false, false, false, true>(F, A, z, q);
-    else fft_pass_f<false, false, false, false>(F, A, z, q);
+    if (t + 1 == np) fft_pass_f<false, false, false, true>(F, A, z, q, wg);
+    else fft_pass_f<false, false, false, false>(F, A, z, q, wg);
     bottom += F;
   }
 }
@@ -266,27 +293,45 @@ hipError_t launch_twiddles(double2* tw, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_circulant(const double* x, double* y, const int64_t* offs, int nvec, int64_t n, double sign,
-                            const double2* twiddle, hipStream_t st) {
-  if (nvec <= 0) return hipSuccess;
-  if (circulant_uses_fft(n)) {
-    // complex elements per workgroup: kFftElems, halved (down to max(n, 512))
-    // while the launch would have fewer than 2048 workgroups; one thread per
-    // group of eight elements
-    const int64_t cvec = (nvec + 1) / 2;
-    int64_t E = kFftElems;
-    while (E / 2 >= std::max<int64_t>(n, 512) && cvec * n / E < 2048) E /= 2;
-    const int P = (int)std::max<int64_t>(1, E / n);
-    const unsigned blocks = (unsigned)((cvec + P - 1) / P);
-    const int threads = (int)std::min<int64_t>(kFftThreads, std::max<int64_t>(64, (int64_t)P * n / 8));
-    const size_t lds = (size_t)P * n * sizeof(double2);
-    FftArgs A{x, y, offs, (int)n, ilog2(n), nvec, P, sign, twiddle};
-    k_circulant_fft<<<blocks, threads, lds, st>>>(A);
-  } else {
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)nvec);
-    k_circulant_direct<<<grid, 256, 0, st>>>(x, y, offs, (int)n, sign, reinterpret_cast<const double*>(twiddle));
+hipError_t launch_circulant(const double* x, double* y, const CircClass* cls, int ncls, double sign, hipStream_t st) {
+  // power-of-two lengths: one launch for all of them (chunks of kMaxCirc
+  // classes), 2048 complex elements (P = 2048 / n whole vectors, one for
+  // n >= 2048) per workgroup of 256 threads; other lengths: the direct product
+  FftMulti M{};
+  size_t lds = 0;
+  int wgs = 0;
+  auto flush = [&]() -> hipError_t {
+    if (M.nc == 0) return hipSuccess;
+    M.first[M.nc] = wgs;
+    k_circulant_fft<<<(unsigned)wgs, kFftThreads, lds, st>>>(M);
+    M = FftMulti{};
+    lds = 0;
+    wgs = 0;
+    return hipGetLastError();
+  };
+  for (int k = 0; k < ncls; ++k) {
+    const CircClass& C = cls[k];
+    if (C.nvec <= 0) continue;
+    if (circulant_uses_fft(C.n)) {
+      const int64_t cvec = (C.nvec + 1) / 2;
+      const int P = (int)std::max<int64_t>(1, kFftElems / C.n);
+      M.a[M.nc] = FftArgs{x, y, C.offs, (int)C.n, ilog2(C.n), C.nvec, P, sign, C.tw};
+      M.first[M.nc] = wgs;
+      wgs += (int)((cvec + P - 1) / P);
+      lds = std::max(lds, (size_t)P * C.n * sizeof(double2));
+      if (++M.nc == kMaxCirc) {
+        const hipError_t e = flush();
+        if (e != hipSuccess) return e;
+      }
+    } else {
+      dim3 grid((unsigned)((C.n + 255) / 256), (unsigned)C.nvec);
+      k_circulant_direct<<<grid, 256, 0, st>>>(x, y, C.offs, (int)C.n, sign,
+                                               reinterpret_cast<const double*>(C.tw));
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
-  return hipGetLastError();
+  return flush();
 }
 
 }  // namespace gnk

@@ -29,6 +29,8 @@ constexpr int kFarTile = 1 << kFarTileLog2;
 // then wcols products b_q = w_q conj(eta')
 constexpr int kRecHead = 3;
 __host__ __device__ constexpr int rec_stride(int wcols) { return kRecHead + 2 * wcols; }
+// FP32 records of mixed products: {v, (|v|^2, 0), w.., b..} (float2 fields)
+__host__ __device__ constexpr int rec32_stride(int wcols) { return 2 + 2 * wcols; }
 
 struct DomDev {
   // boundary data (caller-owned)
@@ -45,7 +47,7 @@ struct DomDev {
   double* bu;        // (2 pi/n) N(t_i, t_i), the diagonal limit (e:N-tt)
   // Cauchy-sum workspace: records rec[j*stride + f], f = 0: eta_j, f = 1 + q: weight column q
   double2* rec;
-  float2* rec32;     // FP32 records (tile-local eta offsets, weights)
+  float2* rec32;     // FP32 records (tile-local eta offsets, |v|^2, weights, b = w conj(v))
   double2* parts;    // partial sums [splits][wcols][N]
   double4* sb;       // bounds of the 64-node source tiles {cx, cy, r, 0}
   double4* sbf;      // bounds of the FP64 far-form source tiles (kFarTile nodes)
@@ -112,10 +114,17 @@ hipError_t launch_tree_eval(const DomDev* doms, int tiles, int tpt, const int* s
 // FP32 records from the FP64 records of every domain
 hipError_t launch_records32(const DomDev* doms, int ndom, int maxN, int lead, int data, hipStream_t st);
 
-// y_k += sign * L x_k for a list of length-n vectors at the given flat offsets
-// (the circulant blocks of Sec. 3.3); twiddle: the table for this n.
-hipError_t launch_circulant(const double* x, double* y, const int64_t* offs, int nvec, int64_t n, double sign,
-                            const double2* twiddle, hipStream_t st);
+// One block length of a circulant product: nvec length-n vectors at the flat
+// offsets offs; tw the twiddle table of n (or the direct product's column).
+struct CircClass {
+  const int64_t* offs;
+  int nvec;
+  int64_t n;
+  const double2* tw;
+};
+// y_k += sign * L x_k for every vector of every class (the circulant blocks of
+// Sec. 3.3); all power-of-two lengths in one launch.
+hipError_t launch_circulant(const double* x, double* y, const CircClass* cls, int ncls, double sign, hipStream_t st);
 hipError_t launch_twiddles(double2* tw, int64_t n, hipStream_t st);
 bool circulant_uses_fft(int64_t n);
 

@@ -368,7 +368,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     B.maxm1 = std::max(B.maxm1, D.m1);
     Ntot += D.N;
     rec_total += (int64_t)D.N * rec_stride(D.ncols + 1);   // head, w.., b.. with a lead column
-    rec32_total += (int64_t)D.N * (D.ncols + 2);
+    rec32_total += (int64_t)D.N * rec32_stride(D.ncols + 1);
     part_total += (int64_t)D.splits * (D.ncols + 1) * D.N;
     sb_total += (D.N + 63) / 64;
     tb_total += (D.N + 63) / 64;
@@ -406,7 +406,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     D.far2 = (1.0 + theta) * (1.0 + theta);
     on += D.N;
     orc += (int64_t)D.N * rec_stride(D.ncols + 1);
-    orc32 += (int64_t)D.N * (D.ncols + 2);
+    orc32 += (int64_t)D.N * rec32_stride(D.ncols + 1);
     op += (int64_t)D.splits * (D.ncols + 1) * D.N;
     osb += (D.N + 63) / 64;
     otb += (D.N + 63) / 64;
@@ -821,7 +821,9 @@ void circulant(gnk_ctx* c, Batch& B, const double* x, double* y, double sign) {
     pr = gnk_ctx::ProfRec{pool_event(c), pool_event(c), 0.0, 0.0, 0.0, false, false, 0.0, false, 24.0 * units, true};
     HIPCHK(c, hipEventRecord(pr.a, c->stream));
   }
-  for (auto& ci : B.circ) HIPCHK(c, launch_circulant(x, y, ci.offs, ci.nvec, ci.n, sign, ci.tw, c->stream));
+  std::vector<CircClass> cls;
+  for (auto& ci : B.circ) cls.push_back(CircClass{ci.offs, ci.nvec, ci.n, ci.tw});
+  HIPCHK(c, launch_circulant(x, y, cls.data(), (int)cls.size(), sign, c->stream));
   if (c->prof) {
     HIPCHK(c, hipEventRecord(pr.b, c->stream));
     c->prof_pending.push_back(pr);
@@ -1081,6 +1083,9 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   HIPCHK(c, hipHostGetDevicePointer((void**)&host_live, c->pinned, 0));
   HIPCHK(c, hipHostGetDevicePointer((void**)&host_rel, c->pinned_rel, 0));
 
+  // optional residual history: per column, the true residual at each cycle
+  // start followed by the estimate after each of the cycle's Arnoldi steps
+  const bool want_hist = o.hist && o.hist_len > 0;
   // With relaxed (mixed) products the residual estimate runs slightly ahead
   // of the true residual, so a mixed cycle aims at half the tolerance; the
   // convergence test itself always uses the FP64 true residual.
@@ -1106,7 +1111,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, st.active, P2, P1, ldp, st, 1, 0);
     LAUNCHCHK(c);
     k_arnoldi_finish<<<(unsigned)ncol, 64, 0, c->stream>>>(P1, nblk, ldp, restart, stop_tol, st, host_live,
-                                                           mixed ? host_rel : nullptr, ncol);
+                                                           (mixed || want_hist) ? host_rel : nullptr, ncol);
     LAUNCHCHK(c);
   };
   // Every buffer the step touches exists before a capture (no allocation,
@@ -1178,9 +1183,12 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   // costs a capture.
   if (use_graph) (void)prepare_step(mixed && !o.x0 && o.inner_tol >= 1.0, restart >= 2 ? 2 : 1);
 
-  std::vector<int> outer(ncol, 0), conv(ncol, 0), mixed_steps(ncol, 0);
+  std::vector<int> outer(ncol, 0), conv(ncol, 0), mixed_steps(ncol, 0), refine(ncol, 0);
+  std::vector<int> hist_cnt(ncol, 0), prev_inner(ncol, 0);
   bool sums_of_x = false;
   bool mixed_now = false;
+  bool refine_capped = false;   // max_refine cycles with mixed products done: FP64 from here on
+  int mixed_cycles = 0;
   while ((int)c->step_ev.size() < kMaxRestart) {
     hipEvent_t e;
     HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1194,10 +1202,25 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   int* hi_dev = hostio_dev(c, hi);
   double* hd_dev = hostio_dev(c, hd);
   bool published = false;   // the host copy holds the final state
+  // after each publish: the history entries of the cycle that just ended (its
+  // steps' estimates, then the true residual that starts the next cycle)
+  auto record_hist = [&](bool first) {
+    if (!want_hist) return;
+    for (int q = 0; q < ncol; ++q) {
+      const int inner_q = hi[1 + ncol + q];
+      const int steps = inner_q - prev_inner[q];
+      if (!first && steps <= 0) continue;
+      double* hq = o.hist + (size_t)q * o.hist_len;
+      for (int t = 0; t < steps && hist_cnt[q] < o.hist_len; ++t) hq[hist_cnt[q]++] = c->pinned_rel[(size_t)t * ncol + q];
+      if (hist_cnt[q] < o.hist_len) hq[hist_cnt[q]++] = hd[q];
+      prev_inner[q] = inner_q;
+    }
+  };
   for (int cyc = 0; cyc < o.maxit; ++cyc) {
     k_publish_cycle<<<nblocks(ncol + 1), kT, 0, c->stream>>>(st, ncol, hi_dev, hd_dev);
     LAUNCHCHK(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    record_hist(cyc == 0);
     const int live = hi[0];
     for (int q = 0; q < ncol; ++q) conv[q] = hi[1 + q];
     if (live == 0) {
@@ -1206,7 +1229,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     }
     // a cycle whose starting (FP64) residual is already below inner_tol
     // takes mixed products from its first step
-    if (mixed && !mixed_now) {
+    if (mixed && !mixed_now && !refine_capped) {
       double mx = 0.0;
       for (int q = 0; q < ncol; ++q)
         if (!conv[q]) mx = std::max(mx, hd[q]);
@@ -1220,8 +1243,10 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     // many columns are still iterating, so the queue never drains and at most
     // three speculative steps run (fully masked) after the last column stops.
     step_recs.clear();
+    bool cycle_mixed = false;
     for (int l = 0; l < restart;) {
       const bool use_mixed = mixed && mixed_now;
+      cycle_mixed = cycle_mixed || use_mixed;
       const int k = (l + 2 <= restart) ? 2 : 1;
       if (use_mixed)
         for (int q = 0; q < ncol; ++q)
@@ -1233,7 +1258,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
       if (prev >= 0) {
         HIPCHK(c, hipEventSynchronize(c->step_ev[prev]));
         if (c->pinned[prev] == 0) break;
-        if (mixed && !mixed_now) {
+        if (mixed && !mixed_now && !refine_capped) {
           double mx = 0.0;
           for (int q = 0; q < ncol; ++q) mx = std::max(mx, c->pinned_rel[(size_t)prev * ncol + q]);
           if (mx <= o.inner_tol) mixed_now = true;
@@ -1260,6 +1285,16 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     k_residual<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, b, V, per_blk, P1, ldp);
     LAUNCHCHK(c);
     cycle_start(P1);
+    // a cycle with mixed products followed by this FP64 residual is one step of
+    // iterative refinement; after max_refine of them the cycles stay FP64
+    if (cycle_mixed) {
+      for (int q = 0; q < ncol; ++q)
+        if (!conv[q]) refine[q] += 1;
+      if (o.max_refine > 0 && ++mixed_cycles >= o.max_refine) {
+        refine_capped = true;
+        mixed_now = false;
+      }
+    }
     if (c->log) {
       std::vector<double> tr(ncol);
       HIPCHK(c, hipMemcpyAsync(tr.data(), st.true_relres, sizeof(double) * ncol, hipMemcpyDeviceToHost, c->stream));
@@ -1279,6 +1314,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     k_publish_cycle<<<nblocks(ncol + 1), kT, 0, c->stream>>>(st, ncol, hi_dev, hd_dev);
     LAUNCHCHK(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    record_hist(false);
   }
   for (int q = 0; q < ncol; ++q) {
     conv[q] = hi[1 + q];
@@ -1295,6 +1331,8 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     I.mixed_steps = std::min(mixed_steps[q], I.inner_it);   // the host count includes speculative steps
     I.relres = rel[q];
     I.true_relres = trel[q];
+    I.refine_steps = refine[q];
+    I.hist_count = hist_cnt[q];
     if (!conv[q]) out.all_converged = false;
   }
   return out;
@@ -1311,10 +1349,12 @@ gnk_opts resolve_opts(gnk_ctx* c, const gnk_opts* o) {
   if (o) r = *o;
   if (r.restart < 1 || r.restart > kMaxRestart || r.maxit < 1 || !(r.tol > 0.0) || r.tol >= 1.0 ||
       (r.prec != GNK_FP64 && r.prec != GNK_MIXED) || (r.no_subtraction != 0 && r.no_subtraction != 1) ||
+      r.max_refine < 0 || r.hist_len < 0 || (r.hist_len > 0 && !r.hist) ||
       !(r.far_tol >= 0.0) || (r.far_tol > 0.0 && (r.far_tol < 1e-15 || r.far_tol > 0.1 || r.prec != GNK_FP64))) {
     set_err(c, "bad options: restart %d (1..%d), maxit %d (>=1), tol %g (0..1), prec %d, no_subtraction %d, "
-            "far_tol %g (0, or 1e-15..0.1 with GNK_FP64)", r.restart, kMaxRestart, r.maxit, r.tol, r.prec,
-            r.no_subtraction, r.far_tol);
+            "far_tol %g (0, or 1e-15..0.1 with GNK_FP64), max_refine %d (>=0), hist_len %d (>=0, hist set "
+            "when > 0)", r.restart, kMaxRestart, r.maxit, r.tol, r.prec, r.no_subtraction, r.far_tol,
+            r.max_refine, r.hist_len);
     throw Fail{GNK_ERR_ARG};
   }
   // mixed products once the residual estimate is below tol / 1e-8 (their
@@ -1615,6 +1655,29 @@ void geom_vjp(gnk_ctx* c, const gnk_domain* d, int nterms, const int* ops, const
                                  c->stream));
 }
 
+// S = E w for gnk_cauchy_sum
+void cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w, int nrhs, void* S) {
+  if (N < 1 || N > ((int64_t)1 << 30) || nrhs < 1 || !eta || !w || !S || w == S) {
+    set_err(c, "bad arguments to gnk_cauchy_sum");
+    throw Fail{GNK_ERR_ARG};
+  }
+  // a pseudo-domain of one component holding the N nodes (the even mesh
+  // size only passes the domain check; the node count is N)
+  gnk_domain d{};
+  d.m1 = 1;
+  d.n = N + (N & 1);
+  d.eta = d.etap = d.A = eta;
+  Batch B;
+  std::vector<int64_t> off{0};
+  build_batch(c, B, 1, &d, &nrhs, off, N * (int64_t)nrhs, false, false, PairShape{}, N);
+  k_pack_records<<<nblocks(N), kT, 0, c->stream>>>(B.d_dom, static_cast<const double2*>(w), nrhs);
+  LAUNCHCHK(c);
+  pairs(c, B, P_GM, false, nullptr);
+  k_reduce_parts<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(B.d_dom, static_cast<double2*>(S));
+  LAUNCHCHK(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+}
+
 }  // namespace
 }  // namespace gnk
 
@@ -1739,25 +1802,7 @@ gnk_status gnk_profile_read(gnk_ctx* c, gnk_prof* out, int reset) {
 
 gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w, int nrhs, void* S) {
   return guarded(c, [&]() -> gnk_status {
-    if (N < 1 || N > ((int64_t)1 << 30) || nrhs < 1 || !eta || !w || !S || w == S) {
-      set_err(c, "bad arguments to gnk_cauchy_sum");
-      throw Fail{GNK_ERR_ARG};
-    }
-    // a pseudo-domain of one component holding the N nodes (the even mesh
-    // size only passes the domain check; the node count is N)
-    gnk_domain d{};
-    d.m1 = 1;
-    d.n = N + (N & 1);
-    d.eta = d.etap = d.A = eta;
-    Batch B;
-    std::vector<int64_t> off{0};
-    build_batch(c, B, 1, &d, &nrhs, off, N * (int64_t)nrhs, false, false, PairShape{}, N);
-    k_pack_records<<<nblocks(N), kT, 0, c->stream>>>(B.d_dom, static_cast<const double2*>(w), nrhs);
-    LAUNCHCHK(c);
-    pairs(c, B, P_GM, false, nullptr);
-    k_reduce_parts<<<dim3(nblocks(N), (unsigned)nrhs), kT, 0, c->stream>>>(B.d_dom, static_cast<double2*>(S));
-    LAUNCHCHK(c);
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    cauchy_sum(c, N, eta, w, nrhs, S);
     return GNK_OK;
   });
 }

@@ -42,12 +42,14 @@ class _Domain(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double), ("prec", C.c_int),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int), ("x0", C.c_void_p),
-                ("no_subtraction", C.c_int), ("far_tol", C.c_double)]
+                ("no_subtraction", C.c_int), ("far_tol", C.c_double), ("hist", C.c_void_p),
+                ("hist_len", C.c_int)]
 
 
 class Info(C.Structure):
     _fields_ = [("flag", C.c_int), ("outer_it", C.c_int), ("inner_it", C.c_int), ("mixed_steps", C.c_int),
-                ("relres", C.c_double), ("true_relres", C.c_double)]
+                ("relres", C.c_double), ("true_relres", C.c_double), ("refine_steps", C.c_int),
+                ("hist_count", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -310,31 +312,49 @@ class Context:
         return _from_cols(y, one)
 
     @staticmethod
-    def _opts(restart, maxit, tol, prec, inner_tol, max_refine, x0, subtract=True, far_tol=0.0):
+    def _opts(restart, maxit, tol, prec, inner_tol, max_refine, x0, subtract=True, far_tol=0.0, hist=None):
+        hl = 0 if hist is None else hist[1]
         return _Opts(restart, maxit, tol, prec, inner_tol, max_refine, None if x0 is None else x0.data_ptr(),
-                     0 if subtract else 1, far_tol)
+                     0 if subtract else 1, far_tol, None if hist is None else C.addressof(hist[0]), hl)
+
+    @staticmethod
+    def _hist(ncol, hist_len):
+        """(host buffer, hist_len) for the residual history of ncol columns, or None."""
+        if not hist_len:
+            return None
+        return (C.c_double * (ncol * hist_len))(), int(hist_len)
+
+    @staticmethod
+    def _infos(infos, hist):
+        out = [i.as_dict() for i in infos]
+        if hist is not None:
+            buf, hl = hist
+            for q, d in enumerate(out):
+                d["hist"] = list(buf[q * hl:q * hl + d["hist_count"]])
+        return out
 
     def fbie(self, dom: DeviceDomain, gam: torch.Tensor, restart=25, maxit=40, tol=1e-12, prec=FP64,
-             inner_tol=0.0, max_refine=0, x0=None, want_h=True, subtract=True, far_tol=0.0):
+             inner_tol=0.0, max_refine=0, x0=None, want_h=True, subtract=True, far_tol=0.0, hist_len=0):
         """Solve (I - N) mu = -M gamma and h = [M mu - (I - N) gamma]/2. Returns (mu, h, infos, status).
-        subtract=False: without singularity subtraction (Example 2's comparison; needs etapp, Ap)."""
+        subtract=False: without singularity subtraction (Example 2's comparison; needs etapp, Ap).
+        hist_len > 0: each info also holds "hist", the column's residual history."""
         self._bind_stream()
         one = gam.dim() == 1
         g, nrhs = _check_real(gam, dom.N, "gam")
         mu = torch.empty_like(g)
         h = torch.empty_like(g) if want_h else None
         x0c = None if x0 is None else _check_real(x0, dom.N, "x0")[0]
-        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract, far_tol)
+        hist = self._hist(nrhs, hist_len)
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract, far_tol, hist)
         infos = (Info * nrhs)()
         d = dom._struct()
         st = self.lib.gnk_fbie(self.h, C.byref(d), g.data_ptr(), nrhs, C.byref(o), mu.data_ptr(),
                                None if h is None else h.data_ptr(), infos)
         self._raise(st)
-        return (_from_cols(mu, one), None if h is None else _from_cols(h, one),
-                [i.as_dict() for i in infos], st)
+        return (_from_cols(mu, one), None if h is None else _from_cols(h, one), self._infos(infos, hist), st)
 
     def fbie_ad(self, dom: DeviceDomain, gam: torch.Tensor, restart=25, maxit=40, tol=1e-12, prec=FP64,
-                inner_tol=0.0, max_refine=0, x0=None, subtract=True, far_tol=0.0):
+                inner_tol=0.0, max_refine=0, x0=None, subtract=True, far_tol=0.0, hist_len=0):
         """Solve (I + N* + J) mu = gamma. Returns (mu, infos, status).
         subtract=False: without singularity subtraction (Example 2's comparison)."""
         self._bind_stream()
@@ -342,15 +362,16 @@ class Context:
         g, nrhs = _check_real(gam, dom.N, "gam")
         mu = torch.empty_like(g)
         x0c = None if x0 is None else _check_real(x0, dom.N, "x0")[0]
-        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract, far_tol)
+        hist = self._hist(nrhs, hist_len)
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, x0c, subtract, far_tol, hist)
         infos = (Info * nrhs)()
         d = dom._struct()
         st = self.lib.gnk_fbie_ad(self.h, C.byref(d), g.data_ptr(), nrhs, C.byref(o), mu.data_ptr(), infos)
         self._raise(st)
-        return _from_cols(mu, one), [i.as_dict() for i in infos], st
+        return _from_cols(mu, one), self._infos(infos, hist), st
 
     def fbie_batched(self, doms, gams, restart=25, maxit=40, tol=1e-12, prec=FP64, inner_tol=0.0, want_h=True,
-                     subtract=True):
+                     subtract=True, max_refine=0, hist_len=0):
         """Batched FBIE over several domains. gams[d]: (N_d,) or (N_d, nrhs_d) float64 CUDA.
         Returns (mus, hs, infos, status) with one entry per domain (infos: list of lists)."""
         self._bind_stream()
@@ -371,12 +392,14 @@ class Context:
         H = (C.c_void_p * nd)(*[h.data_ptr() for h in hs]) if want_h else None
         ncol = sum(k for _, k in cols)
         infos = (Info * ncol)()
-        o = self._opts(restart, maxit, tol, prec, inner_tol, 0, None, subtract)
+        hist = self._hist(ncol, hist_len)
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, None, subtract, 0.0, hist)
         st = self.lib.gnk_fbie_batched(self.h, nd, D, G, R, C.byref(o), MU, H, infos)
         self._raise(st)
+        flat = self._infos(infos, hist)
         out_i, q = [], 0
         for _, k in cols:
-            out_i.append([infos[q + j].as_dict() for j in range(k)])
+            out_i.append(flat[q:q + k])
             q += k
         mus = [_from_cols(m, one) for m, one in zip(mus, ones)]
         hs = [_from_cols(h, one) for h, one in zip(hs, ones)] if want_h else None
@@ -384,7 +407,8 @@ class Context:
 
     # ------------------------------------------------------- differentiation
     def fbie_adjoint(self, dom: DeviceDomain, g_mu: Optional[torch.Tensor] = None, g_h: Optional[torch.Tensor] = None,
-                     restart=25, maxit=40, tol=1e-12, prec=FP64, inner_tol=0.0, want_g_gam=True):
+                     restart=25, maxit=40, tol=1e-12, prec=FP64, inner_tol=0.0, want_g_gam=True, max_refine=0,
+                     hist_len=0):
         """Adjoint solve of FBIE: lam = Aop^-T (Cop^T g_h / 2 + g_mu) and
         dL/dgamma = -Aop^T g_h / 2 - Cop^T lam. Returns (lam, g_gam, infos, status)."""
         self._bind_stream()
@@ -399,7 +423,8 @@ class Context:
             raise ValueError("g_mu and g_h have different column counts")
         lam = torch.empty((nrhs, dom.N), dtype=torch.float64, device=ref.device)
         g_gam = torch.empty_like(lam) if want_g_gam else None
-        o = self._opts(restart, maxit, tol, prec, inner_tol, 0, None)
+        hist = self._hist(nrhs, hist_len)
+        o = self._opts(restart, maxit, tol, prec, inner_tol, max_refine, None, True, 0.0, hist)
         infos = (Info * nrhs)()
         d = dom._struct()
         st = self.lib.gnk_fbie_adjoint(self.h, C.byref(d), None if gm is None else gm[0].data_ptr(),
@@ -407,7 +432,7 @@ class Context:
                                        None if g_gam is None else g_gam.data_ptr(), infos)
         self._raise(st)
         return (_from_cols(lam, one), None if g_gam is None else _from_cols(g_gam, one),
-                [i.as_dict() for i in infos], st)
+                self._infos(infos, hist), st)
 
     def geom_vjp(self, dom: DeviceDomain, terms, want=(True, True, True)):
         """Gradients of s = sum_t c_t u_t^T Op_t v_t with respect to (eta, eta', A).

@@ -269,7 +269,6 @@ def test_config0_as_stated_is_nonsingular():
     uniquely solvable and the row sums of B tend to +1 instead of -1."""
     d, gam = wl.config0("one")
     Aop, Cop = orc.fbie_operators(d.eta, d.etap, d.A, d.n)
-    B1 = (2.0 * np.eye(d.N) - Aop).sum(axis=1) * 0  # placeholder keeps shapes
     K = orc.kernel_matrix(d.eta, d.etap, d.A, d.n)
     rs = K.imag.sum(axis=1) + (1.0 / d.n) * (d.etapp / d.etap).imag
     assert np.max(np.abs(rs - 1.0)) < 1e-8
