@@ -253,6 +253,22 @@ GNK_API gnk_status gnk_profile_read(gnk_ctx* ctx, gnk_prof* out, int reset);
 GNK_API gnk_status gnk_cauchy_sum(gnk_ctx* ctx, int64_t N, const void* eta, const void* w, int nrhs,
                           void* S);
 
+/* gnk_cauchy_sum for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, layout and results, but the call allocates nothing. Its
+ * workspace (node records, split partial sums, tile bounds, work lists) lives
+ * in a fixed 64 MiB device array that the library holds on each GPU it runs on
+ * until the process ends. That limits the size: the call needs about
+ *   N * (40 + 16 (3 + 2 (nrhs + 1)) + 16 s (nrhs + 1)) bytes plus small tables,
+ * s being the planner's source splits (1..64, fewer for larger N; the split
+ * partial sums dominate): N = 65536 with nrhs = 1 fits, N = 264192 does not.
+ * Larger inputs return GNK_ERR_ARG with a message naming the buffer that did
+ * not fit, and nothing is written. Every call on one GPU shares that GPU's
+ * array and overwrites it: calls that overlap on one GPU (several host threads
+ * or contexts) race and must be serialised by the caller. */
+GNK_API gnk_status gnk_cauchy_sum_noalloc(gnk_ctx* ctx, int64_t N, const void* eta, const void* w, int nrhs,
+                                          void* S);
+
 /* Cauchy integral formula at interior points (Sec. 7, eqs. (e:cauchy5) and
  * (e:cauchy6)): the values f(z_i) at nz points of G of a function analytic in G,
  * from its values at the N = m1 n boundary nodes, by the subtracted form

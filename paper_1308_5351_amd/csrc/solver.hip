@@ -21,6 +21,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -28,6 +29,14 @@
 
 #include "gnk_internal.h"
 #include "vec_kernels.inl"
+
+// Scratch of gnk_cauchy_sum_noalloc: that entry point's workspace lives in
+// this fixed device array (one copy per GPU, held until the process ends)
+// instead of allocations. Host code uses only the address from
+// hipGetSymbolAddress (gnk_ctx::scratch, taken once per device at
+// gnk_create), never the array's name.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 struct gnk_ctx {
   int device = 0;
@@ -82,6 +91,11 @@ struct gnk_ctx {
   // reads after a stream synchronisation (flags, live count, per-column info)
   char* hostio = nullptr;
   size_t hostio_bytes = 0;
+  // device address of this device's scratch array (gnk_cauchy_sum_noalloc), or null
+  char* scratch = nullptr;
+  // while set, ws() carves buffers from this region instead of allocating
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
 };
 
 namespace gnk {
@@ -115,6 +129,16 @@ void set_err(gnk_ctx* c, const char* fmt, ...) {
 template <class T>
 T* ws(gnk_ctx* c, const std::string& name, size_t count) {
   const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  if (c->arena) {   // an entry point that allocates nothing: bump allocation in its scratch
+    const size_t off = (c->arena_used + 255) & ~(size_t)255;
+    if (off + bytes > c->arena_cap) {
+      set_err(c, "input too large for the fixed scratch of %zu bytes: buffer '%s' needs %zu bytes at offset %zu "
+              "(use the allocating entry point for this size)", c->arena_cap, name.c_str(), bytes, off);
+      throw Fail{GNK_ERR_ARG};
+    }
+    c->arena_used = off + bytes;
+    return reinterpret_cast<T*>(c->arena + off);
+  }
   auto& b = c->bufs[name];
   if (b.bytes >= bytes) return static_cast<T*>(b.p);
   if (b.p) {
@@ -145,6 +169,14 @@ T* ws(gnk_ctx* c, const std::string& name, size_t count) {
 template <class T>
 T* upload(gnk_ctx* c, const std::string& name, const std::vector<T>& v) {
   T* d = ws<T>(c, name, std::max<size_t>(v.size(), 1));
+  if (!v.empty() && c->arena) {   // scratch contents belong to no call: always copy
+    std::vector<char> keep(sizeof(T) * v.size());
+    memcpy(keep.data(), v.data(), keep.size());
+    c->host_keep.push_back(std::move(keep));
+    HIPCHK(c, hipMemcpyAsync(d, c->host_keep.back().data(), sizeof(T) * v.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    return d;
+  }
   if (!v.empty()) {
     auto& last = c->up_last[name];
     const size_t nb = sizeof(T) * v.size();
@@ -1655,7 +1687,39 @@ void geom_vjp(gnk_ctx* c, const gnk_domain* d, int nterms, const int* ops, const
                                  c->stream));
 }
 
-// S = E w for gnk_cauchy_sum
+std::mutex scratch_mu;
+std::map<int, char*> scratch_addr;   // device -> address of its scratch array
+
+// the current device's scratch address (nullptr if the runtime cannot give it)
+char* scratch_of_device(int device) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  auto it = scratch_addr.find(device);
+  if (it != scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  scratch_addr[device] = static_cast<char*>(p);
+  return static_cast<char*>(p);
+}
+
+// While alive, ws() of this context carves buffers from [base, base + cap).
+struct ArenaScope {
+  gnk_ctx* c;
+  ArenaScope(gnk_ctx* c_, char* base, size_t cap) : c(c_) {
+    c->arena = base;
+    c->arena_cap = cap;
+    c->arena_used = 0;
+  }
+  ~ArenaScope() {
+    c->arena = nullptr;
+    c->arena_cap = 0;
+    c->arena_used = 0;
+  }
+};
+
+// S = E w for gnk_cauchy_sum and gnk_cauchy_sum_noalloc
 void cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w, int nrhs, void* S) {
   if (N < 1 || N > ((int64_t)1 << 30) || nrhs < 1 || !eta || !w || !S || w == S) {
     set_err(c, "bad arguments to gnk_cauchy_sum");
@@ -1716,6 +1780,7 @@ gnk_status gnk_create(gnk_ctx** out, int device) {
     return GNK_ERR_HIP;
   }
   c->stream = c->own_stream;
+  c->scratch = scratch_of_device(device);
   *out = c;
   return GNK_OK;
 }
@@ -1806,6 +1871,19 @@ gnk_status gnk_cauchy_sum(gnk_ctx* c, int64_t N, const void* eta, const void* w,
     return GNK_OK;
   });
 }
+
+gnk_status gnk_cauchy_sum_noalloc(gnk_ctx* c, int64_t N, const void* eta, const void* w, int nrhs, void* S) {
+  return guarded(c, [&]() -> gnk_status {
+    if (!c->scratch) {
+      set_err(c, "gnk_cauchy_sum_noalloc: the scratch array's address on device %d is unknown", c->device);
+      throw Fail{GNK_ERR_HIP};
+    }
+    ArenaScope scope(c, c->scratch, kScratchBytes);
+    cauchy_sum(c, N, eta, w, nrhs, S);
+    return GNK_OK;
+  });
+}
+
 
 // Boundary values of the map onto the unit disc (bounded G) or the extended plane
 // (unbounded G) with slits, from one FBIE solve (theta == NULL: pi/2 on every

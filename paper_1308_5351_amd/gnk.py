@@ -25,7 +25,8 @@ OP_FB, OP_FC, OP_GB, OP_FB_T, OP_FC_T, OP_GB_T, OP_LHAT, OP_FB_U, OP_GB_U = rang
 EXPORTED = ("gnk_create", "gnk_destroy", "gnk_set_stream", "gnk_last_error", "gnk_version",
             "gnk_profile", "gnk_profile_read", "gnk_cauchy_sum", "gnk_apply", "gnk_fbie", "gnk_fbie_ad",
             "gnk_fbie_batched", "gnk_fbie_adjoint", "gnk_geom_vjp", "gnk_fourier_curve", "gnk_fourier_vjp",
-            "gnk_fcau", "gnk_cauchy_sum_tree", "gnk_circular_slit_map", "gnk_slit_map", "gnk_fcau_tree")
+            "gnk_fcau", "gnk_cauchy_sum_tree", "gnk_circular_slit_map", "gnk_slit_map", "gnk_fcau_tree",
+            "gnk_cauchy_sum_noalloc")
 
 
 class GnkError(RuntimeError):
@@ -87,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     lib.gnk_profile.argtypes = [P, C.c_int]
     lib.gnk_profile_read.argtypes = [P, C.POINTER(Prof), C.c_int]
     lib.gnk_cauchy_sum.argtypes = [P, C.c_int64, P, P, C.c_int, P]
+    lib.gnk_cauchy_sum_noalloc.argtypes = [P, C.c_int64, P, P, C.c_int, P]
     lib.gnk_apply.argtypes = [P, C.POINTER(_Domain), C.c_int, C.c_int, P, C.c_int, P]
     lib.gnk_fbie.argtypes = [P, C.POINTER(_Domain), P, C.c_int, C.POINTER(_Opts), P, P, C.POINTER(Info)]
     lib.gnk_fbie_ad.argtypes = [P, C.POINTER(_Domain), P, C.c_int, C.POINTER(_Opts), P, C.POINTER(Info)]
