@@ -111,8 +111,9 @@ typedef struct {
  *                each restart cycle is recomputed with FP64 products, so
  *                restarts act as FP64 iterative refinement and the same tol
  *                is reached
- *   inner_tol  : GNK_MIXED switch level (0: min(1e-4, tol * 1e8), since the
- *                mixed products have a relative error below 1e-8)
+ *   inner_tol  : GNK_MIXED switch level (0: min(1e-4, 5e6 tol): the mixed
+ *                products' relative error, about 1e-8, then adds at most about
+ *                tol/2 to the final residual, so no extra restart is needed)
  *   max_refine : GNK_MIXED: at most this many restart cycles take mixed
  *                products (each is followed by the cycle's FP64 residual, one
  *                step of iterative refinement); the cycles after them take
