@@ -22,6 +22,9 @@
 // component of every column (and of every domain with this n).
 // Powers of two up to 4096 use the FFT; other even n use a direct O(n^2)
 // circulant product with the closed-form first column.
+#include <algorithm>
+#include <vector>
+
 #include "gnk_internal.h"
 
 namespace gnk {
@@ -309,7 +312,12 @@ hipError_t launch_circulant(const double* x, double* y, const CircClass* cls, in
     wgs = 0;
     return hipGetLastError();
   };
-  for (int k = 0; k < ncls; ++k) {
+  // longest vectors first: their workgroups take longest, so the short ones
+  // fill the tail of the launch
+  std::vector<int> order(ncls);
+  for (int k = 0; k < ncls; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cls[a].n > cls[b].n; });
+  for (int k : order) {
     const CircClass& C = cls[k];
     if (C.nvec <= 0) continue;
     if (circulant_uses_fft(C.n)) {
