@@ -30,6 +30,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 #include <omp.h>
 
 enum { RB = 16 };   /* rows per block for products with several columns */
@@ -50,6 +51,17 @@ static void kernel_row(int64_t N, int n, int64_t i, const double* er, const doub
         kr[j] = (nr * cr + ni * ci) * s;
         ki[j] = (ni * cr - nr * ci) * s;
     }
+}
+
+enum { SB = 256 };   /* block length of the sums of the one-column product */
+
+/* Neumaier's compensated addition: s + c holds the running sum to about twice
+   the working precision */
+static inline void csum(double* s, double* c, double y)
+{
+    const double t = *s + y;
+    *c += (fabs(*s) >= fabs(y)) ? ((*s - t) + y) : ((y - t) + *s);
+    *s = t;
 }
 
 static double total(int64_t N, const double* a)
@@ -157,8 +169,42 @@ int gnk_oracle_fbie_rows(int64_t N, int n, int64_t i0, int64_t i1, const double*
         }
 #pragma omp for schedule(dynamic, 16)
         for (int64_t i = i0; i < (cols > 1 && !trans ? i0 : i1); ++i) {
+            if (cols == 1 && !trans) {
+                /* one column: the same entries, used in the loop that forms them; each of
+                   the four sums over j is taken in blocks of SB terms whose partial sums are
+                   added with compensation (Neumaier), so that the rounding of the sum grows
+                   with the block length, not with N */
+                const double w = 2.0 / n;
+                const double eir = er[i], eii = ei[i], air = ar[i], aii = ai[i];
+                double t1 = 0.0, e1 = 0.0, t2 = 0.0, e2 = 0.0, t3 = 0.0, e3 = 0.0, t4 = 0.0, e4 = 0.0;
+                for (int64_t j0 = 0; j0 < N; j0 += SB) {
+                    const int64_t j1 = (j0 + SB < N) ? j0 + SB : N;
+                    double b1 = 0.0, d1 = 0.0, bx = 0.0, dx = 0.0;
+#pragma omp simd reduction(+ : b1, d1, bx, dx)
+                    for (int64_t j = j0; j < j1; ++j) {
+                        double dr = er[j] - eir, di = ei[j] - eii;
+                        double nr = air * pr[j] - aii * pi[j], ni = air * pi[j] + aii * pr[j];
+                        double cr = ar[j] * dr - ai[j] * di, ci = ar[j] * di + ai[j] * dr;
+                        double q = (j == i) ? 0.0 : w / (cr * cr + ci * ci);   /* K_ii = 0 */
+                        double kre = (nr * cr + ni * ci) * q, kim = (ni * cr - nr * ci) * q;
+                        b1 += kim;
+                        d1 += kre;
+                        bx += kim * x[j];            /* (B x)_i */
+                        dx += kre * x[j];            /* (D x)_i */
+                    }
+                    csum(&t1, &e1, b1);
+                    csum(&t2, &e2, d1);
+                    csum(&t3, &e3, bx);
+                    csum(&t4, &e4, dx);
+                }
+                rowB[i] = t1 + e1;
+                rowD[i] = t2 + e2;
+                ya[i] = t3 + e3;
+                yc[i] = t4 + e4;
+                continue;
+            }
             if (cols == 1) {
-                /* one column: the same entries, used in the loop that forms them */
+                /* one column, transposed: the same entries, scattered in the loop that forms them */
                 const double w = 2.0 / n;
                 const double eir = er[i], eii = ei[i], air = ar[i], aii = ai[i], xi = x[i];
                 double b1 = 0.0, d1 = 0.0, bx = 0.0, dx = 0.0;
