@@ -136,19 +136,23 @@ __device__ __forceinline__ void step_far32(AccAB32<NR, TPT>& a, const float (&m2
   }
 }
 
-// the sources [ts, te) of one far tile: four records fetched (wave-uniform
-// scalar loads) before their arithmetic, so one wait covers four sources
+// the sources [ts, te) of one far tile: FB32 records fetched (wave-uniform
+// scalar loads) before their arithmetic, so one wait covers them; two rather
+// than four leave fewer scalar registers to spill into vector lanes (46
+// against 69 in the one-column variant; the close-boundary mixed solve
+// 1.47 s against 1.51 s)
+constexpr int FB32 = 2;
 template <int NR, int TPT, class P>
 __device__ __forceinline__ void tile_far32(AccAB32<NR, TPT>& a, const float (&m2x)[TPT], const float (&m2y)[TPT],
                                            const float (&zz)[TPT], P rec32, int stride32, int wo, int wb, int ts,
                                            int te) {
   int j = ts;
-  for (; j + 3 < te; j += 4) {
+  for (; j + FB32 - 1 < te; j += FB32) {
     P r = rec32 + (size_t)j * stride32;
-    float2 v[4], w[4][NR], b[4][NR];
-    float av[4];
+    float2 v[FB32], w[FB32][NR], b[FB32][NR];
+    float av[FB32];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < FB32; ++k) {
       P rk = r + k * stride32;
       v[k] = rk[0];
       av[k] = rk[1].x;
@@ -159,7 +163,7 @@ __device__ __forceinline__ void tile_far32(AccAB32<NR, TPT>& a, const float (&m2
       }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) step_far32<NR, TPT>(a, m2x, m2y, zz, v[k], av[k], w[k], b[k]);
+    for (int k = 0; k < FB32; ++k) step_far32<NR, TPT>(a, m2x, m2y, zz, v[k], av[k], w[k], b[k]);
   }
   for (; j < te; ++j) {
     P r = rec32 + (size_t)j * stride32;
