@@ -195,46 +195,32 @@ struct FarAcc {
 };
 
 // Records of one far tile are staged in the wave's LDS area (lane k copies
-// source ts + k: eta offset and the item's NR weights), so the K-steps read
-// LDS instead of waiting on L2 at every step.
-template <int NR>
-constexpr int stage_stride() { return NR + 1; }   // float2 per staged source
+// source ts + k), so the K-steps read LDS instead of waiting on L2 at every
+// step. A staged source holds its offset v and the B operands of both MFMAs
+// already arranged per output lane n (real part of column n/2 for even n,
+// imaginary for odd n): B1[n] = (Re w, Im w) and B2[n] = (-Im w, Re w) of column
+// n/2, zero for columns beyond the item's width and for rows beyond the tile,
+// so a K-step needs no selects or masks.
+constexpr int kFarStage = 36;   // floats per staged source: v.x, v.y, 2 pad, B1[16], B2[16]
 
-template <int NR, int TPT, bool FULL>
+template <int TPT, bool FULL>
 __device__ __forceinline__ void far_ksteps(f32x4 (&accR)[4 * TPT], f32x4 (&accI)[4 * TPT],
                                            const float (&ux)[4 * TPT], const float (&uy)[4 * TPT],
-                                           const float2* stg, int len, int width) {
+                                           const float* stg, int len) {
   constexpr int G = 4 * TPT;
-  constexpr int SW = stage_stride<NR>();
   const int lane = threadIdx.x & 63;
   const int k = lane >> 4, n = lane & 15;
-  const bool im_col = (n & 1) != 0;
-  const int c = n >> 1;
-  const bool cvalid = c < width;
-  const int cc = cvalid ? c : 0;
-  auto kstep = [&](int p) {     // sources 4p .. 4p + 3 of the tile
-    const int jl = 4 * p + k;
-    const bool ok = FULL || jl < len;
-    const int js = ok ? jl : 0;
-    const float2 v = stg[js * SW];
-    const float2 w = stg[js * SW + 1 + cc];
-    float b1 = im_col ? w.y : w.x;    // with A = Re Q
-    float b2 = im_col ? w.x : -w.y;   // with A = Im Q
-    if (!FULL || width < 8) {
-      b1 = (ok && cvalid) ? b1 : 0.f;
-      b2 = (ok && cvalid) ? b2 : 0.f;
-    }
+  auto kstep = [&](int p) {     // sources 4p .. 4p + 3 of the tile (zero rows past its end)
+    const float* r = stg + (4 * p + k) * kFarStage;
+    const float2 v = *reinterpret_cast<const float2*>(r);
+    const float b1 = r[4 + n];    // with A = Re Q
+    const float b2 = r[20 + n];   // with A = Im Q
 #pragma unroll
     for (int q = 0; q < G; ++q) {
       const float dx = ux[q] - v.x, dy = uy[q] - v.y;
       const float m = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
-      float qr = dx * m, qi = -dy * m;
-      if (!FULL) {
-        qr = ok ? qr : 0.f;
-        qi = ok ? qi : 0.f;
-      }
-      accR[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(qr, b1, accR[q], 0, 0, 0);
-      accI[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(qi, b2, accI[q], 0, 0, 0);
+      accR[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(dx * m, b1, accR[q], 0, 0, 0);
+      accI[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-dy * m, b2, accI[q], 0, 0, 0);
     }
   };
   if constexpr (FULL) {
@@ -248,20 +234,29 @@ __device__ __forceinline__ void far_ksteps(f32x4 (&accR)[4 * TPT], f32x4 (&accI)
 template <int NR, int TPT>
 __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg)[TPT], double cx, double cy,
                                               gptr<const float2> rec32, int stride, int wo, int ts, int te,
-                                              float2* stg, int width) {
+                                              float* stg, int width) {
   constexpr int G = 4 * TPT;
-  constexpr int SW = stage_stride<NR>();
   const int lane = threadIdx.x & 63;
   const int n = lane & 15;
   const int len = te - ts;
-  if (lane < len) {
-    gptr<const float2> r = rec32 + (size_t)(ts + lane) * stride;
-    stg[lane * SW] = r[0];
+  {
+    float2 v = make_float2(0.f, 0.f);
+    float2 w[8];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      float2 v = make_float2(0.f, 0.f);
-      if (q < width) v = r[wo + q];
-      stg[lane * SW + 1 + q] = v;
+    for (int q = 0; q < 8; ++q) w[q] = make_float2(0.f, 0.f);
+    if (lane < len) {
+      gptr<const float2> r = rec32 + (size_t)(ts + lane) * stride;
+      v = r[0];
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (q < width) w[q] = r[wo + q];
+    }
+    float* o = stg + lane * kFarStage;
+    *reinterpret_cast<f32x4*>(o) = f32x4{v.x, v.y, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+      *reinterpret_cast<f32x4*>(o + 4 + 2 * q) = f32x4{w[q].x, w[q].y, w[q + 1].x, w[q + 1].y};
+      *reinterpret_cast<f32x4*>(o + 20 + 2 * q) = f32x4{-w[q].y, w[q].x, -w[q + 1].y, w[q + 1].x};
     }
   }
   // targets of group g in the A layout: lane n + 16 * (g % 4) of slot g / 4
@@ -284,8 +279,8 @@ __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (len == 64) far_ksteps<NR, TPT, true>(accR, accI, ux, uy, stg, len, width);
-  else far_ksteps<NR, TPT, false>(accR, accI, ux, uy, stg, len, width);
+  if (len == 64) far_ksteps<TPT, true>(accR, accI, ux, uy, stg, len);
+  else far_ksteps<TPT, false>(accR, accI, ux, uy, stg, len);
   // the next tile's staging overwrites stg
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -557,7 +552,7 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
                                          gptr<const double4> tb, gptr<double2> part, int N, int stride, int stride32,
                                          int wcols, int col0, int width, int base, int tile_idx, int g, int jb0,
                                          int jb1, int wchunk,
-                                         double far2, double (*fl)[64][17], float2* stg) {
+                                         double far2, double (*fl)[64][17], float* stg) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j0 = min(jb1, jb0 + wv * wchunk);
@@ -610,11 +605,11 @@ template <int NR, int TPT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_far(const DomDev* __restrict__ doms, const int4* __restrict__ items,
                                              int nitems, int lead, int data, const int* __restrict__ active) {
   // the final reduction tile (4 x 64 x 17 doubles) and, before it, the four
-  // waves' staging areas (64 sources x (NR + 1) float2 each) share one buffer
-  __shared__ double smem[4 * 64 * 17];
-  static_assert(4 * 64 * (NR + 1) * 2 <= 4 * 64 * 17 * 2, "staging exceeds the shared buffer");
+  // waves' staging areas (64 sources x kFarStage floats each) share one buffer
+  __shared__ double smem[4 * 64 * kFarStage / 2];
+  static_assert(kFarStage / 2 >= 17, "the reduction tile exceeds the shared buffer");
   double(*fl)[64][17] = reinterpret_cast<double(*)[64][17]>(smem);
-  float2* stg = reinterpret_cast<float2*>(smem) + (threadIdx.x >> 6) * 64 * (NR + 1);
+  float* stg = reinterpret_cast<float*>(smem) + (threadIdx.x >> 6) * 64 * kFarStage;
   const int it = blockIdx.x;
   if (it >= nitems) return;
   const int4 w = items[it];
