@@ -177,16 +177,22 @@ __device__ __forceinline__ void tile_far32(AccAB32<NR, TPT>& a, const float (&m2
   }
 }
 
-// Far tiles on the matrix cores (4 and 8 columns). For a group of 16 targets
-// and four sources j..j+3, two v_mfma_f32_16x16x4f32 form
-//   D[i][2c + 0] += sum_k Qr_ik Wr_kc,  D[i][2c + 1] += sum_k Qr_ik Wi_kc   (A = Re Q)
-//   D[i][2c + 0] -= sum_k Qi_ik Wi_kc,  D[i][2c + 1] += sum_k Qi_ik Wr_kc   (A = Im Q)
-// (Q = 1/(u_i - v_k), W the weights, c < 8 complex columns), so each lane
-// forms one whole reciprocal (target i = l % 16, source k = l / 16) and uses
-// both its parts. Lane l supplies A[i = l%16][k = l/16] and B[k = l/16][n = l%16];
-// the result D[i][n] sits in register i%4 of lane n + 16(i/4). The 16
-// K-steps of a 64-node tile accumulate in FP32, then the tile's sums are
-// added to FP64 accumulators kept in the same layout (FarAcc).
+// Far tiles on the matrix cores (4 and 8 columns), in the A/B form of the
+// FP32 far tiles above: with u the target and v_k the source offsets from the
+// source tile's centre and m_ik = 1/|u_i - v_k|^2,
+//   sum_k w_k / (u_i - v_k) = conj(u_i) sum_k m_ik w_k - sum_k m_ik b_k,
+// b_k = w_k conj(v_k) (both in the FP32 records). For 16 targets and four
+// sources two v_mfma_f32_16x16x4f32 form W[n][i] = sum_k w[n][k] m[k][i] and
+// B[n][i] = sum_k b[n][k] m[k][i], where n < 16 runs over (Re, Im) of the 8
+// columns: the weights are the A operand (lane l supplies A[n = l%16][k = l/16])
+// and the one real factor m of the pair (target i = l%16, source k = l/16) is
+// the B operand of both, so a pair costs two subtractions, a multiply-add and a
+// reciprocal on the VALU. The result D[n][i] sits in register n%4 of lane
+// i + 16(n/4): the real and imaginary parts of a column are neighbouring
+// registers of the lane that holds the target, which combines them with its own
+// u after the tile's 16 K-steps (FP32) and adds the result to FP64 accumulators
+// kept in the same layout (FarAcc). For targets of a far tile |v_k| is well
+// below |u_i|, so the two terms do not cancel.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int TPT>
@@ -196,15 +202,14 @@ struct FarAcc {
 
 // Records of one far tile are staged in the wave's LDS area (lane k copies
 // source ts + k), so the K-steps read LDS instead of waiting on L2 at every
-// step. A staged source holds its offset v and the B operands of both MFMAs
-// already arranged per output lane n (real part of column n/2 for even n,
-// imaginary for odd n): B1[n] = (Re w, Im w) and B2[n] = (-Im w, Re w) of column
-// n/2, zero for columns beyond the item's width and for rows beyond the tile,
-// so a K-step needs no selects or masks.
-constexpr int kFarStage = 36;   // floats per staged source: v.x, v.y, 2 pad, B1[16], B2[16]
+// step. A staged source holds its offset v and both A operands arranged per
+// row n (real part of column n/2 for even n, imaginary for odd n): the weights
+// w and the products b = w conj(v), zero for columns beyond the item's width
+// and for rows beyond the tile, so a K-step needs no selects or masks.
+constexpr int kFarStage = 36;   // floats per staged source: v.x, v.y, 2 pad, w[16], b[16]
 
 template <int TPT, bool FULL>
-__device__ __forceinline__ void far_ksteps(f32x4 (&accR)[4 * TPT], f32x4 (&accI)[4 * TPT],
+__device__ __forceinline__ void far_ksteps(f32x4 (&accW)[4 * TPT], f32x4 (&accB)[4 * TPT],
                                            const float (&ux)[4 * TPT], const float (&uy)[4 * TPT],
                                            const float* stg, int len) {
   constexpr int G = 4 * TPT;
@@ -213,14 +218,23 @@ __device__ __forceinline__ void far_ksteps(f32x4 (&accR)[4 * TPT], f32x4 (&accI)
   auto kstep = [&](int p) {     // sources 4p .. 4p + 3 of the tile (zero rows past its end)
     const float* r = stg + (4 * p + k) * kFarStage;
     const float2 v = *reinterpret_cast<const float2*>(r);
-    const float b1 = r[4 + n];    // with A = Re Q
-    const float b2 = r[20 + n];   // with A = Im Q
+    const float aw = r[4 + n];
+    const float ab = r[20 + n];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
       const float dx = ux[q] - v.x, dy = uy[q] - v.y;
       const float m = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
-      accR[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(dx * m, b1, accR[q], 0, 0, 0);
-      accI[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-dy * m, b2, accI[q], 0, 0, 0);
+      accW[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, m, accW[q], 0, 0, 0);
+      accB[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, m, accB[q], 0, 0, 0);
+    }
+    // keep VALU work between the MFMAs (both of a pair read the same m and
+    // would otherwise issue back to back, the wave stalling on the second)
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
     }
   };
   if constexpr (FULL) {
@@ -233,33 +247,34 @@ __device__ __forceinline__ void far_ksteps(f32x4 (&accR)[4 * TPT], f32x4 (&accI)
 
 template <int NR, int TPT>
 __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg)[TPT], double cx, double cy,
-                                              gptr<const float2> rec32, int stride, int wo, int ts, int te,
-                                              float* stg, int width) {
+                                              gptr<const float2> far, int len, float* stg, int width) {
   constexpr int G = 4 * TPT;
   const int lane = threadIdx.x & 63;
   const int n = lane & 15;
-  const int len = te - ts;
   {
     float2 v = make_float2(0.f, 0.f);
-    float2 w[8];
+    float2 w[8], b[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) w[q] = make_float2(0.f, 0.f);
     if (lane < len) {
-      gptr<const float2> r = rec32 + (size_t)(ts + lane) * stride;
+      gptr<const float2> r = far + lane;
       v = r[0];
 #pragma unroll
       for (int q = 0; q < NR; ++q)
-        if (q < width) w[q] = r[wo + q];
+        if (q < width) w[q] = r[64 * (1 + q)];
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      b[q] = make_float2(__builtin_fmaf(w[q].x, v.x, w[q].y * v.y), __builtin_fmaf(w[q].y, v.x, -w[q].x * v.y));
     float* o = stg + lane * kFarStage;
     *reinterpret_cast<f32x4*>(o) = f32x4{v.x, v.y, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < 8; q += 2) {
       *reinterpret_cast<f32x4*>(o + 4 + 2 * q) = f32x4{w[q].x, w[q].y, w[q + 1].x, w[q + 1].y};
-      *reinterpret_cast<f32x4*>(o + 20 + 2 * q) = f32x4{-w[q].y, w[q].x, -w[q + 1].y, w[q + 1].x};
+      *reinterpret_cast<f32x4*>(o + 20 + 2 * q) = f32x4{b[q].x, b[q].y, b[q + 1].x, b[q + 1].y};
     }
   }
-  // targets of group g in the A layout: lane n + 16 * (g % 4) of slot g / 4
+  // target of group g: 16 * (g % 4) + n of slot g / 4, held by every lane with l % 16 = n
   float ux[G], uy[G];
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
@@ -270,25 +285,30 @@ __device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg
       uy[4 * t + b] = __shfl(fy, 16 * b + n, 64);
     }
   }
-  f32x4 accR[G], accI[G];
+  f32x4 accW[G], accB[G];
 #pragma unroll
   for (int q = 0; q < G; ++q) {
-    accR[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    accI[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    accW[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    accB[q] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (len == 64) far_ksteps<TPT, true>(accR, accI, ux, uy, stg, len);
-  else far_ksteps<TPT, false>(accR, accI, ux, uy, stg, len);
+  if (len == 64) far_ksteps<TPT, true>(accW, accB, ux, uy, stg, len);
+  else far_ksteps<TPT, false>(accW, accB, ux, uy, stg, len);
   // the next tile's staging overwrites stg
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // registers (e, e + 1) hold (Re, Im) of one column: conj(u) W - B
 #pragma unroll
   for (int q = 0; q < G; ++q)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) F.v[q][e] += (double)(accR[q][e] + accI[q][e]);
+    for (int e = 0; e < 4; e += 2) {
+      const float wr = accW[q][e], wi = accW[q][e + 1];
+      F.v[q][e] += (double)(__builtin_fmaf(ux[q], wr, __builtin_fmaf(uy[q], wi, -accB[q][e])));
+      F.v[q][e + 1] += (double)(__builtin_fmaf(ux[q], wi, __builtin_fmaf(-uy[q], wr, -accB[q][e + 1])));
+    }
 }
 
 // Launch modes of the pair kernel:
@@ -548,17 +568,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((NR <= 2 &
 // each thread writes, in wave order, its complex outputs to the partial sums
 // (the M_NEAR launch that follows adds the near tiles).
 template <int NR, int TPT>
-__device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
-                                         gptr<const double4> tb, gptr<double2> part, int N, int stride, int stride32,
+__device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const float2> far32, gptr<const double4> sb,
+                                         gptr<const double4> tb, gptr<double2> part, int N, int stride,
                                          int wcols, int col0, int width, int base, int tile_idx, int g, int jb0,
-                                         int jb1, int wchunk,
-                                         double far2, double (*fl)[64][17], float* stg) {
+                                         int jb1, double far2, double (*fl)[64][17], float* stg) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int j0 = min(jb1, jb0 + wv * wchunk);
-  const int j1 = min(jb1, j0 + wchunk);
   const double4 tbd = tb[tile_idx];
   const int n = lane & 15, kq = lane >> 4;
+  // the item's 8-column block of the far-tile sources (col0 is a multiple of 8)
+  const gptr<const float2> blk = far32 + (size_t)(col0 >> 3) * ((N + 63) / 64) * (kFar32Fields * 64);
   for (int t = 0; t < TPT; ++t) {
     const double2 tg[1] = {rec[(size_t)min(base + t * 64 + lane, N - 1) * stride]};
     FarAcc<1> F;
@@ -566,20 +585,24 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int e = 0; e < 4; ++e) F.v[q][e] = 0.0;
-    for (int ts = j0; ts < j1; ts += 64) {
-      const int te = min(ts + 64, j1);
+    // the waves take the range's 64-node tiles in turn: near tiles (left to
+    // the M_NEAR launch) come in runs, and contiguous quarters of the range
+    // would leave some waves idle at the barrier below
+    for (int ts = jb0 + 64 * wv; ts < jb1; ts += 256) {
+      const int te = min(ts + 64, jb1);
       const double4 sbd = sb[ts >> 6];
       const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
       const double rr = tbd.z + sbd.z;
       if ((dcx * dcx + dcy * dcy) > far2 * rr * rr)
-        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, rec32, stride32, 2 + col0, ts, te, stg, width);
+        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, blk + (size_t)(ts >> 6) * (kFar32Fields * 64), te - ts, stg,
+                             width);
     }
     __syncthreads();   // fl shares its LDS with the staging areas
-    // group b holds rows i (targets 16b + i) in register i % 4 of lane n + 16 (i / 4), column n
+    // group b holds target 16b + n in lane n + 16 kq, its (Re, Im) rows 4 kq + e in register e
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) fl[wv][16 * b + 4 * kq + e][n] = F.v[b][e];
+      for (int e = 0; e < 4; ++e) fl[wv][16 * b + n][4 * kq + e] = F.v[b][e];
     __syncthreads();
     // 64 targets x NR complex columns; thread k takes (target k % 64, columns k / 64 + 4 m)
     const int tgt = threadIdx.x & 63;
@@ -631,9 +654,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int chunk = D.chunk;
   const int jb0 = w.z * chunk;
   const int jb1 = min(D.N, jb0 + chunk);
-  far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
-                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), rec32_stride(wcols), wcols,
-                    col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, chunk >> 2, D.far2, fl, stg);
+  far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.far32, (gptr<const double4>)D.sb,
+                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), wcols,
+                    col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, fl, stg);
 }
 
 // bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of
@@ -673,7 +696,8 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ d
 }
 
 // FP32 records {v_j = eta_j - c_tile(j) (64-node tile), (|v_j|^2, 0), w_j,q.., b_j,q = w_j,q conj(v_j)..}
-// (stride 2 + 2 wcols) from the FP64 records (head, w.., b..)
+// (stride 2 + 2 wcols) from the FP64 records (head, w.., b..), and the far-tile
+// sources of the matrix cores (v_j and the weights by 8-column block)
 __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data) {
   const DomDev& D = doms[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -690,6 +714,20 @@ __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data)
     const double2 w = r[kRecHead + q];
     o[2 + q] = make_float2((float)w.x, (float)w.y);
     o[2 + wcols + q] = make_float2((float)(w.x * vx + w.y * vy), (float)(w.y * vx - w.x * vy));
+  }
+  if (D.far32 != nullptr) {
+    const int ntl = (D.N + 63) / 64;
+    for (int gb = 0; gb < (wcols + 7) / 8; ++gb) {
+      float2* f = D.far32 + ((size_t)(gb * ntl + (j >> 6)) * kFar32Fields) * 64 + (j & 63);
+      f[0] = v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int col = 8 * gb + q;
+        float2 w = make_float2(0.f, 0.f);
+        if (col < wcols) w = make_float2((float)r[kRecHead + col].x, (float)r[kRecHead + col].y);
+        f[64 * (1 + q)] = w;
+      }
+    }
   }
 }
 

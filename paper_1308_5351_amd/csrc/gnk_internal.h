@@ -31,6 +31,14 @@ constexpr int kRecHead = 3;
 __host__ __device__ constexpr int rec_stride(int wcols) { return kRecHead + 2 * wcols; }
 // FP32 records of mixed products: {v, (|v|^2, 0), w.., b..} (float2 fields)
 __host__ __device__ constexpr int rec32_stride(int wcols) { return 2 + 2 * wcols; }
+// FP32 sources of the matrix-core far tiles, per block of 8 weight columns and
+// 64-node source tile: 9 fields (v, then w of the block's columns 0..7, zero
+// past the last column), each 64 float2 (one per node), so that a wave reads
+// every field of a tile in one coalesced load
+constexpr int kFar32Fields = 9;
+__host__ __device__ constexpr int64_t far32_size(int N, int wcols) {
+  return (int64_t)((wcols + 7) / 8) * ((N + 63) / 64) * kFar32Fields * 64;
+}
 
 struct DomDev {
   // boundary data (caller-owned)
@@ -48,6 +56,7 @@ struct DomDev {
   // Cauchy-sum workspace: records rec[j*stride + f], f = 0: eta_j, f = 1 + q: weight column q
   double2* rec;
   float2* rec32;     // FP32 records (tile-local eta offsets, |v|^2, weights, b = w conj(v))
+  float2* far32;     // FP32 far-tile sources [8-column block][64-node tile][field][node] (see far32_size)
   double2* parts;    // partial sums [splits][wcols][N]
   double4* sb;       // bounds of the 64-node source tiles {cx, cy, r, 0}
   double4* sbf;      // bounds of the FP64 far-form source tiles (kFarTile nodes)

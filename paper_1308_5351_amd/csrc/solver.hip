@@ -362,7 +362,8 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   B.adjoint = adjoint;
   B.shape = shape;
   const int align = mixed ? 256 : 16;
-  int64_t Ntot = 0, rec_total = 0, rec32_total = 0, part_total = 0, sb_total = 0, tb_total = 0, sbf_total = 0;
+  int64_t Ntot = 0, rec_total = 0, rec32_total = 0, far32_total = 0, part_total = 0, sb_total = 0, tb_total = 0,
+          sbf_total = 0;
   B.dom.resize(ndom);
   int c0 = 0;
   for (int d = 0; d < ndom; ++d) {
@@ -401,6 +402,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     Ntot += D.N;
     rec_total += (int64_t)D.N * rec_stride(D.ncols + 1);   // head, w.., b.. with a lead column
     rec32_total += (int64_t)D.N * rec32_stride(D.ncols + 1);
+    far32_total += far32_size(D.N, D.ncols + 1);
     part_total += (int64_t)D.splits * (D.ncols + 1) * D.N;
     sb_total += (D.N + 63) / 64;
     tb_total += (D.N + 63) / 64;
@@ -414,6 +416,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   double* bu = ws<double>(c, "b_bu", Ntot);
   double2* rec = ws<double2>(c, "b_rec", rec_total);
   float2* rec32 = mixed ? ws<float2>(c, "b_rec32", rec32_total) : nullptr;
+  float2* far32 = mixed ? ws<float2>(c, "b_far32", far32_total) : nullptr;
   double2* parts = ws<double2>(c, "b_parts", part_total);
   // tile bounds: far-tile classification (both precisions) and tile-relative records
   double4* sb = ws<double4>(c, "b_sb", sb_total);
@@ -421,7 +424,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   double4* sbf = ws<double4>(c, "b_sbf", sbf_total);
   double theta = 1.0;
   if (const char* e = getenv("GNK_MIXED_THETA")) theta = atof(e);
-  int64_t on = 0, orc = 0, orc32 = 0, op = 0, osb = 0, otb = 0, osbf = 0;
+  int64_t on = 0, orc = 0, orc32 = 0, ofar = 0, op = 0, osb = 0, otb = 0, osbf = 0;
   for (int d = 0; d < ndom; ++d) {
     DomDev& D = B.dom[d];
     D.rho = rho + on;
@@ -431,6 +434,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     D.bu = bu + on;
     D.rec = rec + orc;
     D.rec32 = rec32 ? rec32 + orc32 : nullptr;
+    D.far32 = far32 ? far32 + ofar : nullptr;
     D.parts = parts + op;
     D.sb = sb ? sb + osb : nullptr;
     D.tb = tb ? tb + otb : nullptr;
@@ -439,6 +443,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     on += D.N;
     orc += (int64_t)D.N * rec_stride(D.ncols + 1);
     orc32 += (int64_t)D.N * rec32_stride(D.ncols + 1);
+    ofar += far32_size(D.N, D.ncols + 1);
     op += (int64_t)D.splits * (D.ncols + 1) * D.N;
     osb += (D.N + 63) / 64;
     otb += (D.N + 63) / 64;
