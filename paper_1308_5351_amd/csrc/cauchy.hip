@@ -178,137 +178,98 @@ __device__ __forceinline__ void tile_far32(AccAB32<NR, TPT>& a, const float (&m2
 }
 
 // Far tiles on the matrix cores (4 and 8 columns), in the A/B form of the
-// FP32 far tiles above: with u the target and v_k the source offsets from the
-// source tile's centre and m_ik = 1/|u_i - v_k|^2,
+// FP32 far tiles above, with every offset taken from the centre of the target
+// tile and divided by its radius r_t: for targets u_i and sources v_k so
+// scaled and m_ik = 1/|u_i - v_k|^2,
 //   sum_k w_k / (u_i - v_k) = conj(u_i) sum_k m_ik w_k - sum_k m_ik b_k,
-// b_k = w_k conj(v_k) (both in the FP32 records). For 16 targets and four
-// sources two v_mfma_f32_16x16x4f32 form W[n][i] = sum_k w[n][k] m[k][i] and
-// B[n][i] = sum_k b[n][k] m[k][i], where n < 16 runs over (Re, Im) of the 8
-// columns: the weights are the A operand (lane l supplies A[n = l%16][k = l/16])
-// and the one real factor m of the pair (target i = l%16, source k = l/16) is
-// the B operand of both, so a pair costs two subtractions, a multiply-add and a
-// reciprocal on the VALU. The result D[n][i] sits in register n%4 of lane
-// i + 16(n/4): the real and imaginary parts of a column are neighbouring
-// registers of the lane that holds the target, which combines them with its own
-// u after the tile's 16 K-steps (FP32) and adds the result to FP64 accumulators
-// kept in the same layout (FarAcc). For targets of a far tile |v_k| is well
-// below |u_i|, so the two terms do not cancel.
+// b_k = w_k conj(v_k), and the sum for the unscaled offsets is this one
+// divided by r_t. One v_mfma_f32_32x32x2f32 per 32 targets and two sources
+// forms both sums: its A operand holds 32 rows, the (Re, Im) components of
+// the 8 columns' weights (rows 0-15) and of their b (rows 16-31), lane l
+// supplying A[row = l%32][k = l/32]; its B operand is the one real factor m of
+// the pair (target l%32, source l/32). Each lane so forms one m per MFMA, and
+// the two target groups of a wave share one reciprocal (m_0 = a_1/(a_0 a_1),
+// m_1 = a_0/(a_0 a_1), the scaled squared distances lying between about 1 and
+// the square of the domain's size in tile radii). The FP32 matrix cores and
+// the VALU do not overlap on this chip, so the pair's VALU work is what the
+// MFMAs cannot hide. Row 8(r/4) + 4(l/32) + r%4 of the result sits in
+// register r of lane l (column l%32): a lane holds W and B of the same
+// components eight registers apart, Re and Im side by side, and combines them
+// with its target's u once the wave's far tiles for the slot are summed. Every
+// source of a far tile is further from each target than the target's own
+// offset |u_i|, so conj(u_i) W never dominates B and the difference does not
+// cancel.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-template <int TPT>
-struct FarAcc {
-  double v[4 * TPT][4];
-};
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Records of one far tile are staged in the wave's LDS area (lane k copies
-// source ts + k), so the K-steps read LDS instead of waiting on L2 at every
-// step. A staged source holds its offset v and both A operands arranged per
-// row n (real part of column n/2 for even n, imaginary for odd n): the weights
-// w and the products b = w conj(v), zero for columns beyond the item's width
-// and for rows beyond the tile, so a K-step needs no selects or masks.
+// source ts + k): its scaled offset v, the 16 weight components and the 16
+// components of b = w conj(v), zero for columns beyond the item's width and
+// for rows beyond the tile, so a K-step reads its A operand directly.
 constexpr int kFarStage = 36;   // floats per staged source: v.x, v.y, 2 pad, w[16], b[16]
 
-template <int TPT, bool FULL>
-__device__ __forceinline__ void far_ksteps(f32x4 (&accW)[4 * TPT], f32x4 (&accB)[4 * TPT],
-                                           const float (&ux)[4 * TPT], const float (&uy)[4 * TPT],
-                                           const float* stg, int len) {
-  constexpr int G = 4 * TPT;
+// The 32 K-steps (two sources each) of one staged tile for two groups of 32
+// targets. Rows past a short tile's end hold zero weights.
+__device__ __forceinline__ void far_ksteps(f32x16 (&acc)[2], const float (&ux)[2], const float (&uy)[2],
+                                           const float* stg) {
   const int lane = threadIdx.x & 63;
-  const int k = lane >> 4, n = lane & 15;
-  auto kstep = [&](int p) {     // sources 4p .. 4p + 3 of the tile (zero rows past its end)
-    const float* r = stg + (4 * p + k) * kFarStage;
-    const float2 v = *reinterpret_cast<const float2*>(r);
-    const float aw = r[4 + n];
-    const float ab = r[20 + n];
-#pragma unroll
-    for (int q = 0; q < G; ++q) {
-      const float dx = ux[q] - v.x, dy = uy[q] - v.y;
-      const float m = __builtin_amdgcn_rcpf(__builtin_fmaf(dy, dy, dx * dx));
-      accW[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(aw, m, accW[q], 0, 0, 0);
-      accB[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, m, accB[q], 0, 0, 0);
-    }
-    // keep VALU work between the MFMAs (both of a pair read the same m and
-    // would otherwise issue back to back, the wave stalling on the second)
-#pragma unroll
-    for (int q = 0; q < G; ++q) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
-    }
-  };
-  if constexpr (FULL) {
+  const int k = lane >> 5, i = lane & 31;
 #pragma unroll 4
-    for (int p = 0; p < 16; ++p) kstep(p);
-  } else {
-    for (int p = 0; p < ((len + 3) >> 2); ++p) kstep(p);
+  for (int p = 0; p < 32; ++p) {
+    const float* r = stg + (2 * p + k) * kFarStage;
+    const float2 v = *reinterpret_cast<const float2*>(r);
+    const float a = r[4 + i];
+    const float dx0 = ux[0] - v.x, dy0 = uy[0] - v.y;
+    const float dx1 = ux[1] - v.x, dy1 = uy[1] - v.y;
+    const float s0 = __builtin_fmaf(dy0, dy0, dx0 * dx0);
+    const float s1 = __builtin_fmaf(dy1, dy1, dx1 * dx1);
+    const float rr = __builtin_amdgcn_rcpf(s0 * s1);
+    acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, s1 * rr, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, s0 * rr, acc[1], 0, 0, 0);
   }
 }
 
-template <int NR, int TPT>
-__device__ __forceinline__ void far_tile_mfma(FarAcc<TPT>& F, const double2 (&tg)[TPT], double cx, double cy,
-                                              gptr<const float2> far, int len, float* stg, int width) {
-  constexpr int G = 4 * TPT;
+// One far source tile: stage it (offsets from the target tile's centre,
+// scaled: (v_s + c_s - c_t) / r_t, the stored v_s being relative to the
+// source tile's centre c_s) and run its K-steps. Rows past the tile's end get
+// the source tile's centre and zero weights, which keeps m finite.
+template <int NR>
+__device__ __forceinline__ void far_tile_mfma(f32x16 (&acc)[2], const float (&ux)[2], const float (&uy)[2], float dcx,
+                                              float dcy, float sc, gptr<const float2> far, int len, float* stg,
+                                              int width) {
   const int lane = threadIdx.x & 63;
-  const int n = lane & 15;
   {
-    float2 v = make_float2(0.f, 0.f);
-    float2 w[8], b[8];
+    float2 v = make_float2(dcx * sc, dcy * sc);
+    float2 w[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) w[q] = make_float2(0.f, 0.f);
     if (lane < len) {
       gptr<const float2> r = far + lane;
-      v = r[0];
+      const float2 vs = r[0];
+      v = make_float2((vs.x + dcx) * sc, (vs.y + dcy) * sc);
 #pragma unroll
       for (int q = 0; q < NR; ++q)
         if (q < width) w[q] = r[64 * (1 + q)];
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      b[q] = make_float2(__builtin_fmaf(w[q].x, v.x, w[q].y * v.y), __builtin_fmaf(w[q].y, v.x, -w[q].x * v.y));
     float* o = stg + lane * kFarStage;
     *reinterpret_cast<f32x4*>(o) = f32x4{v.x, v.y, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < 8; q += 2) {
+      const float2 b0 = make_float2(__builtin_fmaf(w[q].x, v.x, w[q].y * v.y), __builtin_fmaf(w[q].y, v.x, -w[q].x * v.y));
+      const float2 b1 = make_float2(__builtin_fmaf(w[q + 1].x, v.x, w[q + 1].y * v.y),
+                                    __builtin_fmaf(w[q + 1].y, v.x, -w[q + 1].x * v.y));
       *reinterpret_cast<f32x4*>(o + 4 + 2 * q) = f32x4{w[q].x, w[q].y, w[q + 1].x, w[q + 1].y};
-      *reinterpret_cast<f32x4*>(o + 20 + 2 * q) = f32x4{b[q].x, b[q].y, b[q + 1].x, b[q + 1].y};
+      *reinterpret_cast<f32x4*>(o + 20 + 2 * q) = f32x4{b0.x, b0.y, b1.x, b1.y};
     }
-  }
-  // target of group g: 16 * (g % 4) + n of slot g / 4, held by every lane with l % 16 = n
-  float ux[G], uy[G];
-#pragma unroll
-  for (int t = 0; t < TPT; ++t) {
-    const float fx = (float)(tg[t].x - cx), fy = (float)(tg[t].y - cy);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      ux[4 * t + b] = __shfl(fx, 16 * b + n, 64);
-      uy[4 * t + b] = __shfl(fy, 16 * b + n, 64);
-    }
-  }
-  f32x4 accW[G], accB[G];
-#pragma unroll
-  for (int q = 0; q < G; ++q) {
-    accW[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    accB[q] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (len == 64) far_ksteps<TPT, true>(accW, accB, ux, uy, stg, len);
-  else far_ksteps<TPT, false>(accW, accB, ux, uy, stg, len);
+  far_ksteps(acc, ux, uy, stg);
   // the next tile's staging overwrites stg
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // registers (e, e + 1) hold (Re, Im) of one column: conj(u) W - B
-#pragma unroll
-  for (int q = 0; q < G; ++q)
-#pragma unroll
-    for (int e = 0; e < 4; e += 2) {
-      const float wr = accW[q][e], wi = accW[q][e + 1];
-      F.v[q][e] += (double)(__builtin_fmaf(ux[q], wr, __builtin_fmaf(uy[q], wi, -accB[q][e])));
-      F.v[q][e + 1] += (double)(__builtin_fmaf(ux[q], wi, __builtin_fmaf(-uy[q], wr, -accB[q][e + 1])));
-    }
 }
 
 // Launch modes of the pair kernel:
@@ -562,11 +523,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((NR <= 2 &
 
 // Far tiles of one item (the items of an M_NEAR launch, 4 or 8 columns) on
 // the matrix cores, one slot of 64 targets at a time (an item of 64 TPT
-// targets takes TPT passes over its sources, so the register footprint is
-// that of 64 targets). Each wave keeps its sums in the MFMA output layout in
-// FP64 (FarAcc); at the end of a slot the four waves' sums meet in LDS and
-// each thread writes, in wave order, its complex outputs to the partial sums
-// (the M_NEAR launch that follows adds the near tiles).
+// targets takes TPT passes over its sources). Each wave keeps W and B in the
+// MFMA output layout over its far tiles; at the end of a slot it forms
+// conj(u) W - B in FP32, the four waves' results meet in LDS in FP64 and the
+// threads write the complex outputs to the partial sums (the M_NEAR launch
+// that follows adds the near tiles).
 template <int NR, int TPT>
 __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const float2> far32, gptr<const double4> sb,
                                          gptr<const double4> tb, gptr<double2> part, int N, int stride,
@@ -575,34 +536,85 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const double4 tbd = tb[tile_idx];
-  const int n = lane & 15, kq = lane >> 4;
+  const double inv_r = 1.0 / tbd.z;
+  const float sc = (float)inv_r;
+  const int j = lane & 31, h = lane >> 5;
   // the item's 8-column block of the far-tile sources (col0 is a multiple of 8)
   const gptr<const float2> blk = far32 + (size_t)(col0 >> 3) * ((N + 63) / 64) * (kFar32Fields * 64);
   for (int t = 0; t < TPT; ++t) {
-    const double2 tg[1] = {rec[(size_t)min(base + t * 64 + lane, N - 1) * stride]};
-    FarAcc<1> F;
+    // targets relative to the target tile's centre, over its radius; target
+    // 32q + j of the slot is held by the lanes j and j + 32
+    float ux[2], uy[2];
+    {
+      const double2 tg = rec[(size_t)min(base + t * 64 + lane, N - 1) * stride];
+      const float fx = (float)((tg.x - tbd.x) * inv_r), fy = (float)((tg.y - tbd.y) * inv_r);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 2; ++q) {
+        ux[q] = __shfl(fx, 32 * q + j, 64);
+        uy[q] = __shfl(fy, 32 * q + j, 64);
+      }
+    }
+    f32x16 acc[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) F.v[q][e] = 0.0;
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[q][e] = 0.f;
     // the waves take the range's 64-node tiles in turn: near tiles (left to
     // the M_NEAR launch) come in runs, and contiguous quarters of the range
     // would leave some waves idle at the barrier below
     for (int ts = jb0 + 64 * wv; ts < jb1; ts += 256) {
       const int te = min(ts + 64, jb1);
       const double4 sbd = sb[ts >> 6];
-      const double dcx = tbd.x - sbd.x, dcy = tbd.y - sbd.y;
+      const double dcx = sbd.x - tbd.x, dcy = sbd.y - tbd.y;
       const double rr = tbd.z + sbd.z;
       if ((dcx * dcx + dcy * dcy) > far2 * rr * rr)
-        far_tile_mfma<NR, 1>(F, tg, sbd.x, sbd.y, blk + (size_t)(ts >> 6) * (kFar32Fields * 64), te - ts, stg,
-                             width);
+        far_tile_mfma<NR>(acc, ux, uy, (float)dcx, (float)dcy, sc, blk + (size_t)(ts >> 6) * (kFar32Fields * 64),
+                          te - ts, stg, width);
     }
-    __syncthreads();   // fl shares its LDS with the staging areas
-    // group b holds target 16b + n in lane n + 16 kq, its (Re, Im) rows 4 kq + e in register e
+    // Register e (< 8) holds W and register e + 8 B of component
+    // 8(e/4) + 4h + e%4; e even: Re, e + 1: Im of column 4(e/4) + 2h + (e%4)/2.
+    // Multiplied by 1/r_t, conj(u) W - B is the sum for the unscaled offsets.
+    double F[2][8];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) fl[wv][16 * b + n][4 * kq + e] = F.v[b][e];
+      for (int e = 0; e < 8; e += 2) {
+        const float wr = acc[q][e], wi = acc[q][e + 1];
+        F[q][e] = (double)__builtin_fmaf(ux[q], wr, __builtin_fmaf(uy[q], wi, -acc[q][e + 8])) * inv_r;
+        F[q][e + 1] = (double)__builtin_fmaf(ux[q], wi, __builtin_fmaf(-uy[q], wr, -acc[q][e + 9])) * inv_r;
+      }
+    // The four waves' sums meet in two rounds through a tile of two waves'
+    // sums, which shares its LDS with the staging areas: (w0 + w2) + (w1 + w3).
+    // Lane l holds target 32q + j, components 8(e/4) + 4h + e%4 in F[q][e].
+    auto slot = [&](int q, int e) -> double& { return fl[0][32 * q + j][8 * (e >> 2) + 4 * h + (e & 3)]; };
+    __syncthreads();
+    if (wv >= 2) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) (&slot(q, e))[(wv - 2) * 64 * 17] = F[q][e];
+    }
+    __syncthreads();
+    if (wv < 2) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) F[q][e] += (&slot(q, e))[wv * 64 * 17];
+    }
+    __syncthreads();
+    if (wv == 1) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) (&slot(q, e))[64 * 17] = F[q][e];
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) slot(q, e) = F[q][e] + (&slot(q, e))[64 * 17];
+    }
     __syncthreads();
     // 64 targets x NR complex columns; thread k takes (target k % 64, columns k / 64 + 4 m)
     const int tgt = threadIdx.x & 63;
@@ -610,27 +622,19 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
 #pragma unroll
     for (int m = 0; m < (NR + 3) / 4; ++m) {
       const int cc = (threadIdx.x >> 6) + 4 * m;
-      if (cc < width && ti < N) {
-        double x = 0.0, y = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          x += fl[q][tgt][2 * cc];
-          y += fl[q][tgt][2 * cc + 1];
-        }
-        part[((size_t)g * wcols + col0 + cc) * N + ti] = make_double2(x, y);
-      }
+      if (cc < width && ti < N) part[((size_t)g * wcols + col0 + cc) * N + ti] = make_double2(fl[0][tgt][2 * cc], fl[0][tgt][2 * cc + 1]);
     }
     __syncthreads();
   }
 }
 
 template <int NR, int TPT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_far(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+__global__ __launch_bounds__(256) void k_far(const DomDev* __restrict__ doms, const int4* __restrict__ items,
                                              int nitems, int lead, int data, const int* __restrict__ active) {
-  // the final reduction tile (4 x 64 x 17 doubles) and, before it, the four
-  // waves' staging areas (64 sources x kFarStage floats each) share one buffer
+  // the four waves' staging areas (64 sources x kFarStage floats each) and,
+  // after them, the reduction tile (2 x 64 x 17 doubles) share one buffer
   __shared__ double smem[4 * 64 * kFarStage / 2];
-  static_assert(kFarStage / 2 >= 17, "the reduction tile exceeds the shared buffer");
+  static_assert(2 * 64 * 17 <= 4 * 64 * kFarStage / 2, "the reduction tile exceeds the shared buffer");
   double(*fl)[64][17] = reinterpret_cast<double(*)[64][17]>(smem);
   float* stg = reinterpret_cast<float*>(smem) + (threadIdx.x >> 6) * 64 * kFarStage;
   const int it = blockIdx.x;
