@@ -526,7 +526,7 @@ def circulant_rate(gnk, ctx, torch):
     units = sum(d.N * g.shape[1] for d, g in batch)
     gbs = p["bytes_fft"] / (p["ms_fft"] * 1e-3) / 1e9
     return {"workload": "64 unbounded domains, m+1 in 2..40, n in 256..2048, m+1 right-hand sides each: "
-                        f"{units} unknown-columns per product, block lengths 256..2048, one launch per length",
+                        f"{units} unknown-columns per product, block lengths 256..2048, one launch for every length",
             "calls": p["launches_fft"], "ms_per_call": round(p["ms_fft"] / max(1, p["launches_fft"]), 4),
             "bytes_per_call": p["bytes_fft"] / max(1, p["launches_fft"]),
             "gb_s": round(gbs, 1), "frac_hbm_peak": round(gbs / 8000.0, 4)}

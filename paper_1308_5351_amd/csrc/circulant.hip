@@ -144,9 +144,13 @@ struct FftMulti {
 // FIRST: the elements come from x (global), not LDS. SYMBOL: after the last
 // DIF stage, multiply by the symbol (2 i k / n, with the 1/n of the inverse),
 // k the bit reversal of the position. LAST: the results go to y (global,
-// y += sign * result) instead of LDS.
-template <int F, bool DIF, bool FIRST, bool SYMBOL, bool LAST>
-__device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q, int wg) {
+// y += sign * result) instead of LDS. KEEPY (with FIRST, F = 3): also fetch
+// the y values of the group into yk; HAVEY (with LAST, F = 3): add to those
+// instead of fetching them. For n <= 2048 the first and the last pass both
+// give each thread one group of eight elements at stride n/8, the same ones.
+template <int F, bool DIF, bool FIRST, bool SYMBOL, bool LAST, bool KEEPY = false, bool HAVEY = false>
+__device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q, int wg, double2 (&yk)[8]) {
+  static_assert(!(KEEPY || HAVEY) || F == 3, "y is kept for passes of eight elements");
   const int n = A.n, half = n >> 1;
   const int per = n >> F;   // groups per vector
   for (int g = threadIdx.x; g < A.P * per; g += blockDim.x) {
@@ -159,14 +163,17 @@ __device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q, in
     // LAST: the y values to add to are fetched before the LDS reads and the
     // butterflies, so their latency overlaps that work
     double2 yv[LAST ? (1 << F) : 1];
-    if constexpr (LAST) {
+    if constexpr (LAST && HAVEY) {
+#pragma unroll
+      for (int m = 0; m < (1 << F); ++m) yv[m] = yk[m];
+    } else if constexpr (LAST) {
       const bool hasa = va < A.V, hasb = va + 1 < A.V;
       const double* ya = A.y + (hasa ? A.offs[va] : 0);
       const double* yb = A.y + (hasb ? A.offs[va + 1] : 0);
 #pragma unroll
       for (int m = 0; m < (1 << F); ++m) {
         const int p = i0 + m * q;
-        yv[m] = make_double2(hasa ? ya[p] : 0.0, hasb ? yb[p] : 0.0);
+        yv[m] = make_double2(hasa ? __builtin_nontemporal_load(ya + p) : 0.0, hasb ? __builtin_nontemporal_load(yb + p) : 0.0);
       }
     }
     if constexpr (FIRST) {
@@ -176,7 +183,16 @@ __device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q, in
 #pragma unroll
       for (int m = 0; m < (1 << F); ++m) {
         const int p = i0 + m * q;
-        v[m] = make_double2(hasa ? xa[p] : 0.0, hasb ? xb[p] : 0.0);
+        v[m] = make_double2(hasa ? __builtin_nontemporal_load(xa + p) : 0.0, hasb ? __builtin_nontemporal_load(xb + p) : 0.0);
+      }
+      if constexpr (KEEPY) {
+        const double* ya = A.y + (hasa ? A.offs[va] : 0);
+        const double* yb = A.y + (hasb ? A.offs[va + 1] : 0);
+#pragma unroll
+        for (int m = 0; m < (1 << F); ++m) {
+          const int p = i0 + m * q;
+          yk[m] = make_double2(hasa ? __builtin_nontemporal_load(ya + p) : 0.0, hasb ? __builtin_nontemporal_load(yb + p) : 0.0);
+        }
       }
     } else {
 #pragma unroll
@@ -201,8 +217,8 @@ __device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q, in
 #pragma unroll
       for (int m = 0; m < (1 << F); ++m) {
         const int p = i0 + m * q;
-        if (hasa) ya[p] = __builtin_fma(A.sign, v[m].x, yv[m].x);
-        if (hasb) yb[p] = __builtin_fma(A.sign, v[m].y, yv[m].y);
+        if (hasa) __builtin_nontemporal_store(__builtin_fma(A.sign, v[m].x, yv[m].x), ya + p);
+        if (hasb) __builtin_nontemporal_store(__builtin_fma(A.sign, v[m].y, yv[m].y), yb + p);
       }
     } else {
 #pragma unroll
@@ -212,10 +228,10 @@ __device__ __forceinline__ void fft_pass(const FftArgs& A, double2* z, int q, in
 }
 
 template <bool DIF, bool FIRST, bool SYMBOL, bool LAST>
-__device__ __forceinline__ void fft_pass_f(int F, const FftArgs& A, double2* z, int q, int wg) {
-  if (F == 3) fft_pass<3, DIF, FIRST, SYMBOL, LAST>(A, z, q, wg);
-  else if (F == 2) fft_pass<2, DIF, FIRST, SYMBOL, LAST>(A, z, q, wg);
-  else fft_pass<1, DIF, FIRST, SYMBOL, LAST>(A, z, q, wg);
+__device__ __forceinline__ void fft_pass_f(int F, const FftArgs& A, double2* z, int q, int wg, double2 (&yk)[8]) {
+  if (F == 3) fft_pass<3, DIF, FIRST, SYMBOL, LAST>(A, z, q, wg, yk);
+  else if (F == 2) fft_pass<2, DIF, FIRST, SYMBOL, LAST>(A, z, q, wg, yk);
+  else fft_pass<1, DIF, FIRST, SYMBOL, LAST>(A, z, q, wg, yk);
 }
 
 // y_k += sign * L x_k for the vectors listed in offs (V of them, length n, a
@@ -233,6 +249,10 @@ __global__ __launch_bounds__(kFftThreads) void k_circulant_fft(FftMulti M) {
   const int wg = (int)blockIdx.x - M.first[c];
   const int L = A.logn;
   const int np = (L + 2) / 3;   // passes per direction; all of 3 stages but the last (L - 3 (np - 1))
+  // y fetched with x in the first pass (one group of eight per thread, n <= 2048,
+  // at least two passes), so both reads are in flight together
+  const bool early = np >= 2 && A.P * (A.n >> 3) <= (int)blockDim.x;
+  double2 yk[8];
   // forward: pass t covers stages with spans n/2 >> 3t .. ; its smallest span is q
   int top = L;                  // stages above this pass
   for (int t = 0; t < np; ++t) {
@@ -240,10 +260,11 @@ __global__ __launch_bounds__(kFftThreads) void k_circulant_fft(FftMulti M) {
     const int q = 1 << (top - F);
     if (t > 0) __syncthreads();
     const bool first = t == 0, last = t + 1 == np;
-    if (first && last) fft_pass_f<true, true, true, false>(F, A, z, q, wg);
-    else if (first) fft_pass_f<true, true, false, false>(F, A, z, q, wg);
-    else if (last) fft_pass_f<true, false, true, false>(F, A, z, q, wg);
-    else fft_pass_f<true, false, false, false>(F, A, z, q, wg);
+    if (first && early) fft_pass<3, true, true, false, false, true>(A, z, q, wg, yk);
+    else if (first && last) fft_pass_f<true, true, true, false>(F, A, z, q, wg, yk);
+    else if (first) fft_pass_f<true, true, false, false>(F, A, z, q, wg, yk);
+    else if (last) fft_pass_f<true, false, true, false>(F, A, z, q, wg, yk);
+    else fft_pass_f<true, false, false, false>(F, A, z, q, wg, yk);
     top -= F;
   }
   // inverse: the short pass first (smallest spans), then passes of three
@@ -252,8 +273,9 @@ __global__ __launch_bounds__(kFftThreads) void k_circulant_fft(FftMulti M) {
     const int F = (t == 0) ? L - 3 * (np - 1) : 3;
     const int q = 1 << bottom;
     __syncthreads();
-    if (t + 1 == np) fft_pass_f<false, false, false, true>(F, A, z, q, wg);
-    else fft_pass_f<false, false, false, false>(F, A, z, q, wg);
+    if (t + 1 == np && early) fft_pass<3, false, false, false, true, false, true>(A, z, q, wg, yk);
+    else if (t + 1 == np) fft_pass_f<false, false, false, true>(F, A, z, q, wg, yk);
+    else fft_pass_f<false, false, false, false>(F, A, z, q, wg, yk);
     bottom += F;
   }
 }
