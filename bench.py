@@ -594,6 +594,8 @@ def main():
                     help="run only the circulant-product measurement (for kernel traces of the FFT)")
     ap.add_argument("--far-field-only", action="store_true",
                     help="run only the treecode comparison (for kernel traces of the treecode)")
+    ap.add_argument("--config1-only", action="store_true",
+                    help="run only the 17-component step (FBIE + FBIEad, for kernel traces of the GMRES step)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain copy of 256 MiB (3 launches), the reference for HBM counters")
     args = ap.parse_args()
@@ -631,6 +633,13 @@ def main():
     if args.circulant_only:
         ctx = gnk.Context(0)
         print(json.dumps({"circulant": circulant_rate(gnk, ctx, torch)}), flush=True)
+        ctx.close()
+        return
+
+    if args.config1_only:
+        ctx = gnk.Context(0)
+        print(json.dumps({"config1_step": config1_step(gnk, ctx, torch, steps=args.steps, warmup=args.warmup)}),
+              flush=True)
         ctx.close()
         return
 

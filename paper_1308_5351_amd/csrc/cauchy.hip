@@ -101,18 +101,21 @@ __device__ __forceinline__ void single_step_far(AccAB<NR, TPT>& acc, const doubl
 // Mixed precision: well-separated source tiles in FP32, the rest in FP64.
 // A source tile is 64 consecutive nodes with bounding circle (c_s, r_s); the
 // workgroup's target tile has (c_t, r_t). The tile pair is far when
-// |c_t - c_s| > (1 + theta)(r_t + r_s). The FP32 records hold
-// v_j = eta_j - c_s (formed in FP64, then rounded), a_j = |v_j|^2, the weights
-// w_j and b_j = w_j conj(v_j); every lane forms z' = z_i - c_s in FP64 and
-// rounds it. As in the FP64 far form,
-//   S_i = conj(z') sum_j w_j m_j - sum_j b_j m_j,  m_j = 1/|z' - v_j|^2,
+// |c_t - c_s| > (1 + theta)(r_t + r_s). The FP32 records hold the offsets in
+// units of the tile radius, v_j = (eta_j - c_s)/r_s (formed in FP64, then
+// rounded), a_j = |v_j|^2, the weights w_j and b_j = w_j conj(v_j); every
+// lane forms z' = (z_i - c_s)/r_s in FP64 and rounds it. As in the FP64 far
+// form,
+//   r_s S_i = conj(z') sum_j w_j m_j - sum_j b_j m_j,  m_j = 1/|z' - v_j|^2,
 //   |z' - v_j|^2 = a_j + |z'|^2 - 2 v_j . z'   (one add, two FMAs),
-// with one FP32 reciprocal per pair (|z' - v_j|^2 itself stays within the
-// FP32 range for distances between 1e-19 and 1e19, whatever the scale of the
-// domain) and four FMAs per column. The tile's 64 terms are summed in FP32;
-// the combination with conj(z') is made in FP64 and added to the FP64
-// accumulators. The pair is far, so |z'| > 2 |v_j| and the distance keeps all
-// but a few bits (it is at least a fifth of a_j + |z'|^2).
+// with one FP32 reciprocal for two sources (m_a = d_b/(d_a d_b)): in tile
+// radii the squared distances lie between about 1 and the square of the
+// domain's size in tile radii, so their product stays within the FP32 range
+// whatever the scale of the domain. Four FMAs per column and pair. The tile's
+// 64 terms are summed in FP32; the combination with conj(z') and the factor
+// 1/r_s are applied in FP64 and added to the FP64 accumulators. The pair is
+// far, so |z'| > 2 |v_j| and the distance keeps all but a few bits (it is at
+// least a fifth of a_j + |z'|^2).
 template <int NR, int TPT>
 struct AccAB32 {
   float ax[TPT][NR], ay[TPT][NR], bx[TPT][NR], by[TPT][NR];
@@ -136,12 +139,36 @@ __device__ __forceinline__ void step_far32(AccAB32<NR, TPT>& a, const float (&m2
   }
 }
 
+// two sources (record fields already loaded), one reciprocal
+template <int NR, int TPT>
+__device__ __forceinline__ void pair_step_far32(AccAB32<NR, TPT>& a, const float (&m2x)[TPT],
+                                                const float (&m2y)[TPT], const float (&zz)[TPT], const float2 (&v)[2],
+                                                const float (&av)[2], const float2 (&w)[2][NR],
+                                                const float2 (&b)[2][NR]) {
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const float da = __builtin_fmaf(v[0].x, m2x[t], __builtin_fmaf(v[0].y, m2y[t], av[0] + zz[t]));
+    const float db = __builtin_fmaf(v[1].x, m2x[t], __builtin_fmaf(v[1].y, m2y[t], av[1] + zz[t]));
+    const float r = __builtin_amdgcn_rcpf(da * db);
+    const float m[2] = {db * r, da * r};
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        a.ax[t][q] = __builtin_fmaf(w[k][q].x, m[k], a.ax[t][q]);
+        a.ay[t][q] = __builtin_fmaf(w[k][q].y, m[k], a.ay[t][q]);
+        a.bx[t][q] = __builtin_fmaf(b[k][q].x, m[k], a.bx[t][q]);
+        a.by[t][q] = __builtin_fmaf(b[k][q].y, m[k], a.by[t][q]);
+      }
+  }
+}
+
 // the sources [ts, te) of one far tile: FB32 records fetched (wave-uniform
 // scalar loads) before their arithmetic, so one wait covers them; two rather
 // than four leave fewer scalar registers to spill into vector lanes (46
 // against 69 in the one-column variant; the close-boundary mixed solve
 // 1.47 s against 1.51 s)
-constexpr int FB32 = 2;
+constexpr int FB32 = 2;   // a pair: one reciprocal
 template <int NR, int TPT, class P>
 __device__ __forceinline__ void tile_far32(AccAB32<NR, TPT>& a, const float (&m2x)[TPT], const float (&m2y)[TPT],
                                            const float (&zz)[TPT], P rec32, int stride32, int wo, int wb, int ts,
@@ -162,8 +189,7 @@ __device__ __forceinline__ void tile_far32(AccAB32<NR, TPT>& a, const float (&m2
         b[k][q] = rk[wb + q];
       }
     }
-#pragma unroll
-    for (int k = 0; k < FB32; ++k) step_far32<NR, TPT>(a, m2x, m2y, zz, v[k], av[k], w[k], b[k]);
+    pair_step_far32<NR, TPT>(a, m2x, m2y, zz, v, av, w, b);
   }
   for (; j < te; ++j) {
     P r = rec32 + (size_t)j * stride32;
@@ -413,10 +439,11 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
         double zx[TPT], zy[TPT];
         float m2x[TPT], m2y[TPT], zz[TPT];
         AccAB32<NR, TPT> a32;
+        const double inv_r = 1.0 / sbd.z;
 #pragma unroll
         for (int t = 0; t < TPT; ++t) {
-          zx[t] = tg[t].x - sbd.x;
-          zy[t] = tg[t].y - sbd.y;
+          zx[t] = (tg[t].x - sbd.x) * inv_r;
+          zy[t] = (tg[t].y - sbd.y) * inv_r;
           const float fx = (float)zx[t], fy = (float)zy[t];
           m2x[t] = -2.f * fx;
           m2y[t] = -2.f * fy;
@@ -430,8 +457,8 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
             const double ax = a32.ax[t][r], ay = a32.ay[t][r];
-            acc.x[t][r] += __builtin_fma(zx[t], ax, zy[t] * ay) - (double)a32.bx[t][r];
-            acc.y[t][r] += __builtin_fma(zx[t], ay, -zy[t] * ax) - (double)a32.by[t][r];
+            acc.x[t][r] += (__builtin_fma(zx[t], ax, zy[t] * ay) - (double)a32.bx[t][r]) * inv_r;
+            acc.y[t][r] += (__builtin_fma(zx[t], ay, -zy[t] * ax) - (double)a32.by[t][r]) * inv_r;
           }
       } else {
         fp64_range(ts, te);
@@ -699,9 +726,10 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ d
   if (lane == 0) out[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
 }
 
-// FP32 records {v_j = eta_j - c_tile(j) (64-node tile), (|v_j|^2, 0), w_j,q.., b_j,q = w_j,q conj(v_j)..}
-// (stride 2 + 2 wcols) from the FP64 records (head, w.., b..), and the far-tile
-// sources of the matrix cores (v_j and the weights by 8-column block)
+// FP32 records {v_j = (eta_j - c_s)/r_s ((c_s, r_s) the node's 64-node tile),
+// (|v_j|^2, 0), w_j,q.., b_j,q = w_j,q conj(v_j)..} (stride 2 + 2 wcols) from
+// the FP64 records (head, w.., b..), and the far-tile sources of the matrix
+// cores (eta_j - c_s unscaled, and the weights by 8-column block)
 __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data) {
   const DomDev& D = doms[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -711,8 +739,10 @@ __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data)
   float2* o = D.rec32 + (size_t)j * rec32_stride(wcols);
   const double4 c = D.sb[j >> 6];
   const float2 v = make_float2((float)(r[0].x - c.x), (float)(r[0].y - c.y));
-  const double vx = v.x, vy = v.y;
-  o[0] = v;
+  const double inv_r = 1.0 / c.z;
+  const float2 vs = make_float2((float)((r[0].x - c.x) * inv_r), (float)((r[0].y - c.y) * inv_r));
+  const double vx = vs.x, vy = vs.y;
+  o[0] = vs;
   o[1] = make_float2((float)(vx * vx + vy * vy), 0.f);
   for (int q = 0; q < wcols; ++q) {
     const double2 w = r[kRecHead + q];

@@ -29,7 +29,8 @@ constexpr int kFarTile = 1 << kFarTileLog2;
 // then wcols products b_q = w_q conj(eta')
 constexpr int kRecHead = 3;
 __host__ __device__ constexpr int rec_stride(int wcols) { return kRecHead + 2 * wcols; }
-// FP32 records of mixed products: {v, (|v|^2, 0), w.., b..} (float2 fields)
+// FP32 records of mixed products: {v, (|v|^2, 0), w.., b..} (float2 fields;
+// v the offset from the node's 64-node tile centre in units of its radius)
 __host__ __device__ constexpr int rec32_stride(int wcols) { return 2 + 2 * wcols; }
 // FP32 sources of the matrix-core far tiles, per block of 8 weight columns and
 // 64-node source tile: 9 fields (v, then w of the block's columns 0..7, zero
@@ -55,7 +56,7 @@ struct DomDev {
   double* bu;        // (2 pi/n) N(t_i, t_i), the diagonal limit (e:N-tt)
   // Cauchy-sum workspace: records rec[j*stride + f], f = 0: eta_j, f = 1 + q: weight column q
   double2* rec;
-  float2* rec32;     // FP32 records (tile-local eta offsets, |v|^2, weights, b = w conj(v))
+  float2* rec32;     // FP32 records (tile-local eta offsets over the tile radius, |v|^2, weights, b = w conj(v))
   float2* far32;     // FP32 far-tile sources [8-column block][64-node tile][field][node] (see far32_size)
   double2* parts;    // partial sums [splits][wcols][N]
   double4* sb;       // bounds of the 64-node source tiles {cx, cy, r, 0}
