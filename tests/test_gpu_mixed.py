@@ -76,6 +76,40 @@ def test_mixed_products_matrix_cores(gk, ctx, small_close, nrhs):
     assert np.max(np.abs(y32 - ref)) / np.max(np.abs(ref)) < 1e-6
 
 
+@pytest.mark.parametrize("nrhs", [8, 13])
+def test_mixed_matrix_cores_short_tiles(gk, ctx, nrhs):
+    """n = 100 (N = 100 (m+1), not a multiple of 64): the last source and target
+    tiles of the domain are short, so the matrix-core far kernel stages zero
+    weights past their end. Products against the FP64 ones and the oracle's
+    kernel rows; a mixed solve with every Arnoldi product mixed against the
+    dense oracle at 1e-10."""
+    dom, gam = wl.batch_domain(7, m1_range=(nrhs, nrhs), ns=(100,))
+    assert dom.N % 64 != 0 and gam.shape[1] == nrhs
+    dd = gk.DeviceDomain.from_host(dom)
+    rng = np.random.default_rng([8, nrhs])
+    x = rng.normal(size=(dom.N, nrhs))
+    xd = _cuda(x)
+    print(f"[mixed] short tiles: N = {dom.N}, nrhs {nrhs}", flush=True)
+    y64 = ctx.apply(dd, gk.OP_FB, xd).cpu().numpy()
+    y32 = ctx.apply(dd, gk.OP_FB, xd, prec=gk.MIXED).cpu().numpy()
+    err = np.max(np.abs(y32 - y64), axis=0) / np.max(np.abs(y64), axis=0)
+    print(f"  per-column rel err max {err.max():.2e} min {err.min():.2e}", flush=True)
+    assert np.all(err < 1e-6) and np.all(err > 1e-13)
+    K = orc.kernel_rows(dom.eta, dom.etap, dom.A, dom.n, slice(dom.N - 70, dom.N))
+    idx = np.arange(dom.N - 70, dom.N)
+    B = K.imag
+    ref = 2.0 * x[idx] + B.sum(axis=1)[:, None] * x[idx] - B @ x
+    assert np.max(np.abs(y32[idx] - ref)) / np.max(np.abs(ref)) < 1e-6
+    mu, h, infos, st = ctx.fbie(dd, _cuda(gam), tol=1e-13, restart=10, maxit=40, prec=gk.MIXED, inner_tol=1.0)
+    mu_o, h_o = orc.fbie(dom.eta, dom.etap, dom.A, gam, dom.n)
+    s = np.max(np.abs(gam))
+    e_mu = orc.rel_linf(mu.cpu().numpy(), mu_o, s)
+    e_h = orc.rel_linf(h.cpu().numpy(), h_o, s)
+    print(f"  solve: err mu {e_mu:.2e} h {e_h:.2e} mixed steps {[i['mixed_steps'] for i in infos]}", flush=True)
+    assert st == 0 and all(i["mixed_steps"] >= 1 for i in infos)
+    assert e_mu < 1e-10 and e_h < 1e-10
+
+
 @pytest.mark.parametrize("restart,inner_tol", [(50, 0.0), (10, 1.0)])
 def test_batched_mixed_matrix_cores_matches_oracle(gk, ctx, restart, inner_tol):
     """Batched mixed solve of domains with 8-13 right-hand sides (matrix-core far
