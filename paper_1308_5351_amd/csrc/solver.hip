@@ -243,9 +243,12 @@ struct Batch {
   bool mixed = false;
   bool adjoint = false;
   bool second = false;   // eta'' and A' present (adjoint or no-subtraction operators)
+  // item lists by column-group width 8, 4, 2, 1; mixed Arnoldi products also
+  // 16 (index 4: their far tiles) with the 8-column halves of those items
+  // (index 5: their near tiles)
   struct ItemSet {
-    int4* d[4] = {nullptr, nullptr, nullptr, nullptr};
-    int cnt[4] = {0, 0, 0, 0};
+    int4* d[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int cnt[6] = {0, 0, 0, 0, 0, 0};
     double pair_cols = 0, flops = 0, pairs1 = 0;
     bool built = false;
   } sets[4];
@@ -466,7 +469,7 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
   std::vector<int> order(B.ndom);
   for (int d = 0; d < B.ndom; ++d) order[d] = d;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.dom[a].N > B.dom[b].N; });
-  std::vector<int4> lists[4];
+  std::vector<int4> lists[6];
   S.pair_cols = S.flops = S.pairs1 = 0;
   for (int d : order) {
     const DomDev& D = B.dom[d];
@@ -478,7 +481,26 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
     S.pair_cols += pairs * wcols;
     S.flops += pairs * (16.0 + 8.0 * (wcols - 1));
     if (wcols == 1) S.pairs1 += pairs;
+    const bool split_major = (int64_t)D.N * rec_stride(wcols) * (int64_t)sizeof(double2) > (int64_t)2 << 20;
     int r0 = 0;
+    // mixed Arnoldi products: 16-column groups first; k_far takes their far
+    // tiles with each pair's factor shared by four MFMAs, the near-only launch
+    // takes the two 8-column halves
+    while (p == P_GM_MIXED && wcols - r0 >= 16) {
+      auto push = [&](int t, int g) {
+        lists[4].push_back(make_int4(d, t, g, r0));
+        lists[5].push_back(make_int4(d, t, g, r0));
+        lists[5].push_back(make_int4(d, t, g, r0 + 8));
+      };
+      if (split_major) {
+        for (int g = 0; g < D.splits; ++g)
+          for (int t = 0; t < tiles; ++t) push(t, g);
+      } else {
+        for (int t = 0; t < tiles; ++t)
+          for (int g = 0; g < D.splits; ++g) push(t, g);
+      }
+      r0 += 16;
+    }
     while (r0 < wcols) {
       int wi = 3;
       for (int k = 0; k < 4; ++k)
@@ -499,7 +521,7 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
       // N = 133120: 28% shorter products than tile-major). Smaller ones stay
       // in L2 either way and go tile-major, whose last round is cheaper
       // (3% at N = 17408).
-      if ((int64_t)D.N * rec_stride(wcols) * (int64_t)sizeof(double2) > (int64_t)2 << 20) {
+      if (split_major) {
         for (int g = 0; g < D.splits; ++g)
           for (int t = 0; t < tiles; ++t) lists[wi].push_back(make_int4(d, t, g, code));
       } else {
@@ -509,7 +531,7 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
       r0 += w;
     }
   }
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 6; ++k) {
     S.cnt[k] = (int)lists[k].size();
     S.d[k] = upload(c, "b_items" + std::to_string(p) + "_" + std::to_string(k), lists[k]);
   }
@@ -816,6 +838,9 @@ void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
                           S.pairs1 > 0 && S.pairs1 == S.pair_cols};
     HIPCHK(c, hipEventRecord(pr.a, c->stream));
   }
+  if (S.cnt[4])
+    HIPCHK(c, launch_far16(B.d_dom, S.d[4], S.cnt[4], S.d[5], S.cnt[5], B.shape.tpt, kLead[p], kData[p], active,
+                           c->stream));
   for (int k = 0; k < 4; ++k) {
     if (!S.cnt[k]) continue;
     HIPCHK(c, launch_pairs(B.d_dom, S.d[k], S.cnt[k], kWidths[k], B.shape.tpt, kLead[p], kData[p], mixed,

@@ -50,11 +50,12 @@ def test_mixed_products_close_to_fp64(gk, ctx, small_close):
         assert 1e-12 < err < 1e-5
 
 
-@pytest.mark.parametrize("nrhs", [4, 8, 13])
+@pytest.mark.parametrize("nrhs", [4, 8, 13, 21])
 def test_mixed_products_matrix_cores(gk, ctx, small_close, nrhs):
-    """Products with 4-8 column groups take their far tiles on the matrix cores
-    (13 columns = groups of 8, 4 and 1): every column against the FP64
-    product, and against the oracle's kernel rows on sampled targets."""
+    """Products with 4-16 column groups take their far tiles on the matrix cores
+    (13 columns = groups of 8, 4 and 1; 21 = 16 and a padded group of 5):
+    every column against the FP64 product, and against the oracle's kernel
+    rows on sampled targets."""
     dom, _ = small_close
     dd = gk.DeviceDomain.from_host(dom)
     rng = np.random.default_rng([5, nrhs])
@@ -76,7 +77,7 @@ def test_mixed_products_matrix_cores(gk, ctx, small_close, nrhs):
     assert np.max(np.abs(y32 - ref)) / np.max(np.abs(ref)) < 1e-6
 
 
-@pytest.mark.parametrize("nrhs", [8, 13])
+@pytest.mark.parametrize("nrhs", [8, 13, 20])
 def test_mixed_matrix_cores_short_tiles(gk, ctx, nrhs):
     """n = 100 (N = 100 (m+1), not a multiple of 64): the last source and target
     tiles of the domain are short, so the matrix-core far kernel stages zero
