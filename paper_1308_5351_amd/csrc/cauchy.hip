@@ -732,6 +732,44 @@ __global__ __launch_bounds__(256) void k_far(const DomDev* __restrict__ doms, co
                     col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, smem, stg);
 }
 
+// The far tiles of a mixed Arnoldi product in one launch: items of 16 columns
+// (width 16 in bits 20 and up) and of up to 8 (padded groups carry their
+// width there too) share it, each workgroup taking the path of its item, so
+// the smaller items fill the tail of the larger ones.
+template <int TPT>
+__global__ __launch_bounds__(256) void k_far_mix(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+                                                 int nitems, int lead, int data, const int* __restrict__ active) {
+  __shared__ double smem[4 * 64 * kFarStage / 2];
+  static_assert(2 * 64 * 33 <= 4 * 64 * kFarStage / 2, "the reduction tile exceeds the shared buffer");
+  float* stg = reinterpret_cast<float*>(smem) + (threadIdx.x >> 6) * 64 * kFarStage;
+  const int it = blockIdx.x;
+  if (it >= nitems) return;
+  const int4 w = items[it];
+  const DomDev& D = doms[w.x];
+  const int wcols = lead + data * D.ncols;
+  const int col0 = w.w & 0xFFFFF;
+  const int width = (w.w >> 20) ? (w.w >> 20) : 8;
+  if (active != nullptr) {
+    bool any = false;
+    for (int q = 0; q < width; ++q) {
+      const int col = col0 + q - lead;
+      any = any || col < 0 || active[D.c0 + col] != 0;
+    }
+    if (!any) return;
+  }
+  const int chunk = D.chunk;
+  const int jb0 = w.z * chunk;
+  const int jb1 = min(D.N, jb0 + chunk);
+  if (width > 8)
+    far_item<16, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.far32, (gptr<const double4>)D.sb,
+                      (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), wcols,
+                      col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, smem, stg);
+  else
+    far_item<8, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.far32, (gptr<const double4>)D.sb,
+                     (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), wcols,
+                     col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, smem, stg);
+}
+
 // bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of
 // `tile` consecutive nodes; one wavefront per (tile, domain)
 __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ doms, int tile, int which) {
@@ -893,14 +931,14 @@ hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int w
   return hipGetLastError();
 }
 
-hipError_t launch_far16(const DomDev* doms, const int4* items, int nitems, const int4* near_items, int nnear,
-                        int tpt, int lead, int data, const int* active, hipStream_t st) {
+hipError_t launch_far_mixed(const DomDev* doms, const int4* items, int nitems, const int4* near_items, int nnear,
+                            int tpt, int lead, int data, const int* active, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   if (tpt == 2) {
-    k_far<16, 2><<<nitems, 256, 0, st>>>(doms, items, nitems, lead, data, active);
+    k_far_mix<2><<<nitems, 256, 0, st>>>(doms, items, nitems, lead, data, active);
     launch_k<8, 2, M_NEAR>(doms, near_items, nnear, lead, data, active, nnear, st);
   } else {
-    k_far<16, 1><<<nitems, 256, 0, st>>>(doms, items, nitems, lead, data, active);
+    k_far_mix<1><<<nitems, 256, 0, st>>>(doms, items, nitems, lead, data, active);
     launch_k<8, 1, M_NEAR>(doms, near_items, nnear, lead, data, active, nnear, st);
   }
   return hipGetLastError();

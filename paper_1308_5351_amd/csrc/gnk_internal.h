@@ -91,12 +91,14 @@ struct ColDev {
 // ext: the single domain's targets are doms[0].tz (FP64 only)
 hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
                         bool mixed, bool ext, const int* active, hipStream_t st);
-// Mixed products of 16-column groups: the far tiles of the 16-column items on
-// the matrix cores, then the near-only FP64 launch over near_items, the items'
-// 8-column halves (the same domain, target tile and split; first columns col0
-// and col0 + 8), which adds to the partial sums the first launch wrote.
-hipError_t launch_far16(const DomDev* doms, const int4* items, int nitems, const int4* near_items, int nnear,
-                        int tpt, int lead, int data, const int* active, hipStream_t st);
+// Mixed Arnoldi products of groups of 3 to 16 columns: the far tiles of every
+// item on the matrix cores in one launch (items of 16 columns carry width 16
+// in bits 20 and up, padded groups their width), then the near-only FP64
+// launch over near_items, the items' 8-column parts (the same domain, target
+// tile and split; a 16-column item's halves start at col0 and col0 + 8), which
+// adds to the partial sums the first launch wrote.
+hipError_t launch_far_mixed(const DomDev* doms, const int4* items, int nitems, const int4* near_items, int nnear,
+                            int tpt, int lead, int data, const int* active, hipStream_t st);
 // resident workgroups per CU of the pair-kernel variant (width columns, tpt, mixed)
 int pairs_blocks_per_cu(int width, int tpt, bool mixed);
 

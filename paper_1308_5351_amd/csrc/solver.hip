@@ -243,9 +243,9 @@ struct Batch {
   bool mixed = false;
   bool adjoint = false;
   bool second = false;   // eta'' and A' present (adjoint or no-subtraction operators)
-  // item lists by column-group width 8, 4, 2, 1; mixed Arnoldi products also
-  // 16 (index 4: their far tiles) with the 8-column halves of those items
-  // (index 5: their near tiles)
+  // item lists by column-group width 8, 4, 2, 1; mixed Arnoldi products put
+  // their groups of 3 to 16 columns in index 4 (the far tiles, one launch) and
+  // the 8-column parts of those items in index 5 (their near tiles)
   struct ItemSet {
     int4* d[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int cnt[6] = {0, 0, 0, 0, 0, 0};
@@ -481,14 +481,19 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
     S.pair_cols += pairs * wcols;
     S.flops += pairs * (16.0 + 8.0 * (wcols - 1));
     if (wcols == 1) S.pairs1 += pairs;
+    // Records larger than half an XCD's L2 (4 MB): split-major, so the
+    // workgroups resident together read one source range (measured at
+    // N = 133120: 28% shorter products than tile-major). Smaller ones stay
+    // in L2 either way and go tile-major, whose last round is cheaper
+    // (3% at N = 17408).
     const bool split_major = (int64_t)D.N * rec_stride(wcols) * (int64_t)sizeof(double2) > (int64_t)2 << 20;
     int r0 = 0;
-    // mixed Arnoldi products: 16-column groups first; k_far takes their far
-    // tiles with each pair's factor shared by four MFMAs, the near-only launch
-    // takes the two 8-column halves
+    // mixed Arnoldi products: 16-column groups first (the far kernel shares
+    // each pair's factor between four MFMAs), listed with the 8-column groups
+    // below for one far launch; the near-only launch takes 8-column parts
     while (p == P_GM_MIXED && wcols - r0 >= 16) {
       auto push = [&](int t, int g) {
-        lists[4].push_back(make_int4(d, t, g, r0));
+        lists[4].push_back(make_int4(d, t, g, r0 | (16 << 20)));
         lists[5].push_back(make_int4(d, t, g, r0));
         lists[5].push_back(make_int4(d, t, g, r0 + 8));
       };
@@ -516,17 +521,22 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
         w = wcols - r0;
         code = r0 | (w << 20);
       }
-      // Records larger than half an XCD's L2 (4 MB): split-major, so the
-      // workgroups resident together read one source range (measured at
-      // N = 133120: 28% shorter products than tile-major). Smaller ones stay
-      // in L2 either way and go tile-major, whose last round is cheaper
-      // (3% at N = 17408).
+      // mixed Arnoldi products: groups of 3 to 8 columns join the far launch
+      const bool far_mix = p == P_GM_MIXED && wi == 0;
+      auto push = [&](int t, int g) {
+        if (far_mix) {
+          lists[4].push_back(make_int4(d, t, g, code));
+          lists[5].push_back(make_int4(d, t, g, code));
+        } else {
+          lists[wi].push_back(make_int4(d, t, g, code));
+        }
+      };
       if (split_major) {
         for (int g = 0; g < D.splits; ++g)
-          for (int t = 0; t < tiles; ++t) lists[wi].push_back(make_int4(d, t, g, code));
+          for (int t = 0; t < tiles; ++t) push(t, g);
       } else {
         for (int t = 0; t < tiles; ++t)
-          for (int g = 0; g < D.splits; ++g) lists[wi].push_back(make_int4(d, t, g, code));
+          for (int g = 0; g < D.splits; ++g) push(t, g);
       }
       r0 += w;
     }
@@ -839,8 +849,8 @@ void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
     HIPCHK(c, hipEventRecord(pr.a, c->stream));
   }
   if (S.cnt[4])
-    HIPCHK(c, launch_far16(B.d_dom, S.d[4], S.cnt[4], S.d[5], S.cnt[5], B.shape.tpt, kLead[p], kData[p], active,
-                           c->stream));
+    HIPCHK(c, launch_far_mixed(B.d_dom, S.d[4], S.cnt[4], S.d[5], S.cnt[5], B.shape.tpt, kLead[p], kData[p],
+                               active, c->stream));
   for (int k = 0; k < 4; ++k) {
     if (!S.cnt[k]) continue;
     HIPCHK(c, launch_pairs(B.d_dom, S.d[k], S.cnt[k], kWidths[k], B.shape.tpt, kLead[p], kData[p], mixed,
