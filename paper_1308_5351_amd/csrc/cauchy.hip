@@ -333,11 +333,12 @@ __device__ __forceinline__ void far_tile_mfma(f32x16 (&acc)[2][(NR + 7) / 8], co
 // Launch modes of the pair kernel:
 //   M_FP64  every pair in FP64;
 //   M_MIXED near tiles FP64, far tiles FP32 on the VALU (1-2 columns);
-//   M_NEAR  near tiles only, FP64 (4-8 columns of a mixed product), added to
-//           the partial sums that k_far (below) wrote for the same items just
-//           before; items without a near tile store nothing.
-// k_far takes the far tiles on the matrix cores. Splitting a mixed product in
-// two keeps each kernel's register footprint small (the FP64 loops and the
+//   M_NEAR  near tiles only, FP64 (the 8-column parts of the groups of 3 to
+//           16 columns of a mixed product), added to the partial sums that
+//           k_far_mix (below) wrote for the same (tile, split) just before;
+//           items without a near tile store nothing.
+// k_far_mix takes the far tiles on the matrix cores. Splitting a mixed product
+// in two keeps each kernel's register footprint small (the FP64 loops and the
 // MFMA accumulators do not share a register file).
 enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2, M_EXT = 3 };
 
@@ -499,7 +500,7 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
   }
 
   if constexpr (MODE == M_NEAR) {
-    if (!__syncthreads_or(any_near ? 1 : 0)) return;   // k_far's sums are complete
+    if (!__syncthreads_or(any_near ? 1 : 0)) return;   // the far launch's sums are complete
   }
   // fixed-order reduction over the four wavefronts, one column at a time
 #pragma unroll
@@ -697,41 +698,6 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
   }
 }
 
-template <int NR, int TPT>
-__global__ __launch_bounds__(256) void k_far(const DomDev* __restrict__ doms, const int4* __restrict__ items,
-                                             int nitems, int lead, int data, const int* __restrict__ active) {
-  // the four waves' staging areas (64 sources x kFarStage floats each) and,
-  // after them, the reduction tile (2 x 64 x (16 NB + 1) doubles) share one buffer
-  constexpr int NB = (NR + 7) / 8;
-  __shared__ double smem[4 * 64 * kFarStage / 2];
-  static_assert(2 * 64 * (16 * NB + 1) <= 4 * 64 * kFarStage / 2, "the reduction tile exceeds the shared buffer");
-  float* stg = reinterpret_cast<float*>(smem) + (threadIdx.x >> 6) * 64 * kFarStage;
-  const int it = blockIdx.x;
-  if (it >= nitems) return;
-  const int4 w = items[it];
-  const DomDev& D = doms[w.x];
-  const int wcols = lead + data * D.ncols;
-  // first column, and the group's width (an 8-column group padded from fewer
-  // columns carries its width in bits 20 and up)
-  const int col0 = w.w & 0xFFFFF;
-  const int width = (w.w >> 20) ? (w.w >> 20) : NR;
-  if (active != nullptr) {
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const int col = col0 + q - lead;
-      any = any || (q < width && (col < 0 || active[D.c0 + col] != 0));
-    }
-    if (!any) return;
-  }
-  const int chunk = D.chunk;
-  const int jb0 = w.z * chunk;
-  const int jb1 = min(D.N, jb0 + chunk);
-  far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.far32, (gptr<const double4>)D.sb,
-                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), wcols,
-                    col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, smem, stg);
-}
-
 // The far tiles of a mixed Arnoldi product in one launch: items of 16 columns
 // (width 16 in bits 20 and up) and of up to 8 (padded groups carry their
 // width there too) share it, each workgroup taking the path of its item, so
@@ -851,8 +817,8 @@ void launch_k(const DomDev* doms, const int4* items, int nitems, int lead, int d
   k_pairs<NR, TPT, MODE><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
 }
 
-// FP64: one launch. Mixed: 1-2 columns in one M_MIXED launch; 4-8 columns as
-// k_far then M_NEAR over the same items (the second adds to the first's sums).
+// FP64: one launch. Mixed: 1-2 columns in one M_MIXED launch (groups of 3 or
+// more columns go through launch_far_mixed; launch_pairs rejects them).
 template <int NR, int TPT>
 void launch_t(const DomDev* doms, const int4* items, int nitems, int lead, int data, bool mixed, bool ext,
               const int* active, int grid, hipStream_t st) {
@@ -860,10 +826,7 @@ void launch_t(const DomDev* doms, const int4* items, int nitems, int lead, int d
     launch_k<NR, TPT, M_EXT>(doms, items, nitems, lead, data, active, grid, st);
   } else if (!mixed) {
     launch_k<NR, TPT, M_FP64>(doms, items, nitems, lead, data, active, grid, st);
-  } else if constexpr (NR >= 4) {
-    k_far<NR, TPT><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
-    launch_k<NR, TPT, M_NEAR>(doms, items, nitems, lead, data, active, grid, st);
-  } else {
+  } else if constexpr (NR <= 2) {
     launch_k<NR, TPT, M_MIXED>(doms, items, nitems, lead, data, active, grid, st);
   }
 }
@@ -921,6 +884,7 @@ hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int w
                         bool mixed, bool ext, const int* active, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   if (ext && mixed) return hipErrorInvalidValue;
+  if (mixed && width >= 4) return hipErrorInvalidValue;   // launch_far_mixed takes these
   const int grid = nitems;
   switch (width) {
     case 8: launch_w<8>(doms, items, nitems, tpt, lead, data, mixed, ext, active, grid, st); break;

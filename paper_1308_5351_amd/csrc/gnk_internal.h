@@ -85,9 +85,10 @@ struct ColDev {
 // domain's data columns):
 //   parts_d[(g*wcols_d + q)*N_d + i] = sum_{j in split g, j != i} w_jq / (eta_i - eta_j)
 // items: int4 {d, target tile, split, first weight column}; `width` columns per
-// item (8, 4, 2 or 1), one workgroup per item. mixed: FP32 for far 64-node
-// source tiles (rec32, sb, tb). active: optional per global column mask; an
-// item whose data columns are all inactive is skipped.
+// item (8, 4, 2 or 1), one workgroup per item. mixed (1 or 2 columns; wider
+// groups go through launch_far_mixed): FP32 for far 64-node source tiles
+// (rec32, sb, tb). active: optional per global column mask; an item whose data
+// columns are all inactive is skipped.
 // ext: the single domain's targets are doms[0].tz (FP64 only)
 hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
                         bool mixed, bool ext, const int* active, hipStream_t st);
