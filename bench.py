@@ -46,8 +46,8 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # KiB, the factors from a 256 MiB copy of known size; profiles/*_hbm_counters.md).
 # Valid only for that N and the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "pair_steps.inl", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "c2ff4e148afcf8f4e738efc2cdcac1e50a74b540fe8c48c4327f362419e8b700",
-                "N": 264192, "bytes_per_launch": 859097822}
+                "sha256": "a709a43dc4b42f7093773224564bd8bc9b202b23753ee411a183fa5fd9fb4828",
+                "N": 264192, "bytes_per_launch": 872212486}
 
 
 def pair_traffic(N):

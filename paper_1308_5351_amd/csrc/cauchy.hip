@@ -224,60 +224,34 @@ __device__ __forceinline__ void tile_far32(AccAB32<NR, TPT>& a, const float (&m2
 // with its target's u once the wave's far tiles for the slot are summed. Every
 // source of a far tile is further from each target than the target's own
 // offset |u_i|, so conj(u_i) W never dominates B and the difference does not
-// cancel. Items of 16 columns (two blocks of 8) take two MFMAs per target
-// group and K-step with the same m, so the pair's VALU work is shared by four
-// MFMAs instead of two.
+// cancel.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Records of one far tile are staged in the wave's LDS area (lane k copies
-// source ts + k): its scaled offset v and 32 floats of A operands, zero for
-// columns beyond the item's width and for rows beyond the tile. One block of
-// 8 columns: the 16 weight components and the 16 components of b = w conj(v),
-// so a K-step reads its A operand directly. Two blocks: the 32 weight
-// components; a lane forms its b component from the weight component and its
-// partner (Re b = wr vx + wi vy, Im b = wi vx - wr vy).
-constexpr int kFarStage = 36;   // floats per staged source: v.x, v.y, 2 pad, 32 A-operand floats
+// source ts + k): its scaled offset v, the 16 weight components and the 16
+// components of b = w conj(v), zero for columns beyond the item's width and
+// for rows beyond the tile, so a K-step reads its A operand directly.
+constexpr int kFarStage = 36;   // floats per staged source: v.x, v.y, 2 pad, w[16], b[16]
 
 // The 32 K-steps (two sources each) of one staged tile for two groups of 32
-// targets and NB blocks of 8 columns. Rows past a short tile's end hold zero
-// weights.
-template <int NB>
-__device__ __forceinline__ void far_ksteps(f32x16 (&acc)[2][NB], const float (&ux)[2], const float (&uy)[2],
+// targets. Rows past a short tile's end hold zero weights.
+__device__ __forceinline__ void far_ksteps(f32x16 (&acc)[2], const float (&ux)[2], const float (&uy)[2],
                                            const float* stg) {
   const int lane = threadIdx.x & 63;
   const int k = lane >> 5, i = lane & 31;
-  // two blocks: rows i < 16 take the weight component w_c, rows i >= 16 the
-  // component of b, w_c vx + s w_{c^1} vy (s = +1 for Re, -1 for Im): one form
-  // for every lane, w_c cx + w_{c^1} cy, with lane constants in cx and cy
-  const bool brow = i >= 16;
-  const float sgn = (i & 1) ? -1.f : 1.f;
-  const int ca = i & 15, cp = (i & 15) ^ 1;
 #pragma unroll 4
   for (int p = 0; p < 32; ++p) {
     const float* r = stg + (2 * p + k) * kFarStage;
     const float2 v = *reinterpret_cast<const float2*>(r);
-    float a[NB];
-    if constexpr (NB == 1) {
-      a[0] = r[4 + i];
-    } else {
-      const float cx = brow ? v.x : 1.f;
-      const float cy = brow ? sgn * v.y : 0.f;
-#pragma unroll
-      for (int blk = 0; blk < NB; ++blk)
-        a[blk] = __builtin_fmaf(r[4 + 16 * blk + ca], cx, r[4 + 16 * blk + cp] * cy);
-    }
+    const float a = r[4 + i];
     const float dx0 = ux[0] - v.x, dy0 = uy[0] - v.y;
     const float dx1 = ux[1] - v.x, dy1 = uy[1] - v.y;
     const float s0 = __builtin_fmaf(dy0, dy0, dx0 * dx0);
     const float s1 = __builtin_fmaf(dy1, dy1, dx1 * dx1);
     const float rr = __builtin_amdgcn_rcpf(s0 * s1);
-    const float m0 = s1 * rr, m1 = s0 * rr;
-#pragma unroll
-    for (int blk = 0; blk < NB; ++blk) {
-      acc[0][blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[blk], m0, acc[0][blk], 0, 0, 0);
-      acc[1][blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[blk], m1, acc[1][blk], 0, 0, 0);
-    }
+    acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, s1 * rr, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, s0 * rr, acc[1], 0, 0, 0);
   }
 }
 
@@ -286,44 +260,38 @@ __device__ __forceinline__ void far_ksteps(f32x16 (&acc)[2][NB], const float (&u
 // source tile's centre c_s) and run its K-steps. Rows past the tile's end get
 // the source tile's centre and zero weights, which keeps m finite.
 template <int NR>
-__device__ __forceinline__ void far_tile_mfma(f32x16 (&acc)[2][(NR + 7) / 8], const float (&ux)[2],
-                                              const float (&uy)[2], float dcx, float dcy, float sc,
-                                              gptr<const float2> far, size_t blk_stride, int len, float* stg,
+__device__ __forceinline__ void far_tile_mfma(f32x16 (&acc)[2], const float (&ux)[2], const float (&uy)[2], float dcx,
+                                              float dcy, float sc, gptr<const float2> far, int len, float* stg,
                                               int width) {
-  constexpr int NB = (NR + 7) / 8;
   const int lane = threadIdx.x & 63;
   {
     float2 v = make_float2(dcx * sc, dcy * sc);
-    float2 w[8 * NB];
+    float2 w[8];
 #pragma unroll
-    for (int q = 0; q < 8 * NB; ++q) w[q] = make_float2(0.f, 0.f);
+    for (int q = 0; q < 8; ++q) w[q] = make_float2(0.f, 0.f);
     if (lane < len) {
       gptr<const float2> r = far + lane;
       const float2 vs = r[0];
       v = make_float2((vs.x + dcx) * sc, (vs.y + dcy) * sc);
 #pragma unroll
       for (int q = 0; q < NR; ++q)
-        if (q < width) w[q] = r[(size_t)(q >> 3) * blk_stride + 64 * (1 + (q & 7))];
+        if (q < width) w[q] = r[64 * (1 + q)];
     }
     float* o = stg + lane * kFarStage;
     *reinterpret_cast<f32x4*>(o) = f32x4{v.x, v.y, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < 8 * NB; q += 2)
+    for (int q = 0; q < 8; q += 2) {
+      const float2 b0 = make_float2(__builtin_fmaf(w[q].x, v.x, w[q].y * v.y), __builtin_fmaf(w[q].y, v.x, -w[q].x * v.y));
+      const float2 b1 = make_float2(__builtin_fmaf(w[q + 1].x, v.x, w[q + 1].y * v.y),
+                                    __builtin_fmaf(w[q + 1].y, v.x, -w[q + 1].x * v.y));
       *reinterpret_cast<f32x4*>(o + 4 + 2 * q) = f32x4{w[q].x, w[q].y, w[q + 1].x, w[q + 1].y};
-    if constexpr (NB == 1) {
-#pragma unroll
-      for (int q = 0; q < 8; q += 2) {
-        const float2 b0 = make_float2(__builtin_fmaf(w[q].x, v.x, w[q].y * v.y), __builtin_fmaf(w[q].y, v.x, -w[q].x * v.y));
-        const float2 b1 = make_float2(__builtin_fmaf(w[q + 1].x, v.x, w[q + 1].y * v.y),
-                                      __builtin_fmaf(w[q + 1].y, v.x, -w[q + 1].x * v.y));
-        *reinterpret_cast<f32x4*>(o + 20 + 2 * q) = f32x4{b0.x, b0.y, b1.x, b1.y};
-      }
+      *reinterpret_cast<f32x4*>(o + 20 + 2 * q) = f32x4{b0.x, b0.y, b1.x, b1.y};
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  far_ksteps<NB>(acc, ux, uy, stg);
+  far_ksteps(acc, ux, uy, stg);
   // the next tile's staging overwrites stg
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -333,12 +301,11 @@ __device__ __forceinline__ void far_tile_mfma(f32x16 (&acc)[2][(NR + 7) / 8], co
 // Launch modes of the pair kernel:
 //   M_FP64  every pair in FP64;
 //   M_MIXED near tiles FP64, far tiles FP32 on the VALU (1-2 columns);
-//   M_NEAR  near tiles only, FP64 (the 8-column parts of the groups of 3 to
-//           16 columns of a mixed product), added to the partial sums that
-//           k_far_mix (below) wrote for the same (tile, split) just before;
-//           items without a near tile store nothing.
-// k_far_mix takes the far tiles on the matrix cores. Splitting a mixed product
-// in two keeps each kernel's register footprint small (the FP64 loops and the
+//   M_NEAR  near tiles only, FP64 (4-8 columns of a mixed product), added to
+//           the partial sums that k_far (below) wrote for the same items just
+//           before; items without a near tile store nothing.
+// k_far takes the far tiles on the matrix cores. Splitting a mixed product in
+// two keeps each kernel's register footprint small (the FP64 loops and the
 // MFMA accumulators do not share a register file).
 enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2, M_EXT = 3 };
 
@@ -500,7 +467,7 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
   }
 
   if constexpr (MODE == M_NEAR) {
-    if (!__syncthreads_or(any_near ? 1 : 0)) return;   // the far launch's sums are complete
+    if (!__syncthreads_or(any_near ? 1 : 0)) return;   // k_far's sums are complete
   }
   // fixed-order reduction over the four wavefronts, one column at a time
 #pragma unroll
@@ -592,19 +559,15 @@ template <int NR, int TPT>
 __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const float2> far32, gptr<const double4> sb,
                                          gptr<const double4> tb, gptr<double2> part, int N, int stride,
                                          int wcols, int col0, int width, int base, int tile_idx, int g, int jb0,
-                                         int jb1, double far2, double* fl, float* stg) {
-  constexpr int NB = (NR + 7) / 8;
-  constexpr int FL = 16 * NB + 1;   // doubles per target in the reduction tile
+                                         int jb1, double far2, double (*fl)[64][17], float* stg) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const double4 tbd = tb[tile_idx];
   const double inv_r = 1.0 / tbd.z;
   const float sc = (float)inv_r;
   const int j = lane & 31, h = lane >> 5;
-  // the item's first 8-column block of the far-tile sources (col0 is a
-  // multiple of 8), and the distance to the next block
-  const size_t blk_stride = (size_t)((N + 63) / 64) * (kFar32Fields * 64);
-  const gptr<const float2> blk = far32 + (size_t)(col0 >> 3) * blk_stride;
+  // the item's 8-column block of the far-tile sources (col0 is a multiple of 8)
+  const gptr<const float2> blk = far32 + (size_t)(col0 >> 3) * ((N + 63) / 64) * (kFar32Fields * 64);
   for (int t = 0; t < TPT; ++t) {
     // targets relative to the target tile's centre, over its radius; target
     // 32q + j of the slot is held by the lanes j and j + 32
@@ -618,13 +581,11 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
         uy[q] = __shfl(fy, 32 * q + j, 64);
       }
     }
-    f32x16 acc[2][NB];
+    f32x16 acc[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[q][b][e] = 0.f;
+      for (int e = 0; e < 16; ++e) acc[q][e] = 0.f;
     // the waves take the range's 64-node tiles in turn: near tiles (left to
     // the M_NEAR launch) come in runs, and contiguous quarters of the range
     // would leave some waves idle at the barrier below
@@ -635,53 +596,51 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
       const double rr = tbd.z + sbd.z;
       if ((dcx * dcx + dcy * dcy) > far2 * rr * rr)
         far_tile_mfma<NR>(acc, ux, uy, (float)dcx, (float)dcy, sc, blk + (size_t)(ts >> 6) * (kFar32Fields * 64),
-                          blk_stride, te - ts, stg, width);
+                          te - ts, stg, width);
     }
     // Register e (< 8) holds W and register e + 8 B of component
-    // 8(e/4) + 4h + e%4 of its block; e even: Re, e + 1: Im of column
-    // 8 blk + 4(e/4) + 2h + (e%4)/2. Multiplied by 1/r_t, conj(u) W - B is the
-    // sum for the unscaled offsets (res, formed when it is stored).
-    auto res = [&](int q, int b, int e) -> double {
-      const int e0 = e & ~1;
-      const float wr = acc[q][b][e0], wi = acc[q][b][e0 + 1];
-      const float v = (e & 1) ? __builtin_fmaf(ux[q], wi, __builtin_fmaf(-uy[q], wr, -acc[q][b][e0 + 9]))
-                              : __builtin_fmaf(ux[q], wr, __builtin_fmaf(uy[q], wi, -acc[q][b][e0 + 8]));
-      return (double)v * inv_r;
-    };
-    // The four waves' sums meet in LDS, in a tile of two waves' sums
-    // (fl[w][target][component], FL doubles per target) that shares its LDS
-    // with the staging areas: waves 2 and 3 store theirs, waves 0 and 1 add
-    // theirs to them, wave 0 adds the two: (w0 + w2) + (w1 + w3). Lane l holds
-    // target 32q + j, components 16 blk + 8(e/4) + 4h + e%4.
-    auto slot = [&](int w, int q, int b, int e) -> double& {
-      return fl[((size_t)w * 64 + 32 * q + j) * FL + 16 * b + 8 * (e >> 2) + 4 * h + (e & 3)];
-    };
+    // 8(e/4) + 4h + e%4; e even: Re, e + 1: Im of column 4(e/4) + 2h + (e%4)/2.
+    // Multiplied by 1/r_t, conj(u) W - B is the sum for the unscaled offsets.
+    double F[2][8];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const float wr = acc[q][e], wi = acc[q][e + 1];
+        F[q][e] = (double)__builtin_fmaf(ux[q], wr, __builtin_fmaf(uy[q], wi, -acc[q][e + 8])) * inv_r;
+        F[q][e + 1] = (double)__builtin_fmaf(ux[q], wi, __builtin_fmaf(-uy[q], wr, -acc[q][e + 9])) * inv_r;
+      }
+    // The four waves' sums meet in two rounds through a tile of two waves'
+    // sums, which shares its LDS with the staging areas: (w0 + w2) + (w1 + w3).
+    // Lane l holds target 32q + j, components 8(e/4) + 4h + e%4 in F[q][e].
+    auto slot = [&](int q, int e) -> double& { return fl[0][32 * q + j][8 * (e >> 2) + 4 * h + (e & 3)]; };
     __syncthreads();
     if (wv >= 2) {
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) slot(wv - 2, q, b, e) = res(q, b, e);
+        for (int e = 0; e < 8; ++e) (&slot(q, e))[(wv - 2) * 64 * 17] = F[q][e];
     }
     __syncthreads();
     if (wv < 2) {
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+        for (int e = 0; e < 8; ++e) F[q][e] += (&slot(q, e))[wv * 64 * 17];
+    }
+    __syncthreads();
+    if (wv == 1) {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) slot(wv, q, b, e) = res(q, b, e) + slot(wv, q, b, e);
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) (&slot(q, e))[64 * 17] = F[q][e];
     }
     __syncthreads();
     if (wv == 0) {
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) slot(0, q, b, e) += slot(1, q, b, e);
+        for (int e = 0; e < 8; ++e) slot(q, e) = F[q][e] + (&slot(q, e))[64 * 17];
     }
     __syncthreads();
     // 64 targets x NR complex columns; thread k takes (target k % 64, columns k / 64 + 4 m)
@@ -690,50 +649,45 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
 #pragma unroll
     for (int m = 0; m < (NR + 3) / 4; ++m) {
       const int cc = (threadIdx.x >> 6) + 4 * m;
-      if (cc < width && ti < N)
-        part[((size_t)g * wcols + col0 + cc) * N + ti] =
-            make_double2(fl[(size_t)tgt * FL + 2 * cc], fl[(size_t)tgt * FL + 2 * cc + 1]);
+      if (cc < width && ti < N) part[((size_t)g * wcols + col0 + cc) * N + ti] = make_double2(fl[0][tgt][2 * cc], fl[0][tgt][2 * cc + 1]);
     }
     __syncthreads();
   }
 }
 
-// The far tiles of a mixed Arnoldi product in one launch: items of 16 columns
-// (width 16 in bits 20 and up) and of up to 8 (padded groups carry their
-// width there too) share it, each workgroup taking the path of its item, so
-// the smaller items fill the tail of the larger ones.
-template <int TPT>
-__global__ __launch_bounds__(256) void k_far_mix(const DomDev* __restrict__ doms, const int4* __restrict__ items,
-                                                 int nitems, int lead, int data, const int* __restrict__ active) {
+template <int NR, int TPT>
+__global__ __launch_bounds__(256) void k_far(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+                                             int nitems, int lead, int data, const int* __restrict__ active) {
+  // the four waves' staging areas (64 sources x kFarStage floats each) and,
+  // after them, the reduction tile (2 x 64 x 17 doubles) share one buffer
   __shared__ double smem[4 * 64 * kFarStage / 2];
-  static_assert(2 * 64 * 33 <= 4 * 64 * kFarStage / 2, "the reduction tile exceeds the shared buffer");
+  static_assert(2 * 64 * 17 <= 4 * 64 * kFarStage / 2, "the reduction tile exceeds the shared buffer");
+  double(*fl)[64][17] = reinterpret_cast<double(*)[64][17]>(smem);
   float* stg = reinterpret_cast<float*>(smem) + (threadIdx.x >> 6) * 64 * kFarStage;
   const int it = blockIdx.x;
   if (it >= nitems) return;
   const int4 w = items[it];
   const DomDev& D = doms[w.x];
   const int wcols = lead + data * D.ncols;
+  // first column, and the group's width (an 8-column group padded from fewer
+  // columns carries its width in bits 20 and up)
   const int col0 = w.w & 0xFFFFF;
-  const int width = (w.w >> 20) ? (w.w >> 20) : 8;
+  const int width = (w.w >> 20) ? (w.w >> 20) : NR;
   if (active != nullptr) {
     bool any = false;
-    for (int q = 0; q < width; ++q) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
       const int col = col0 + q - lead;
-      any = any || col < 0 || active[D.c0 + col] != 0;
+      any = any || (q < width && (col < 0 || active[D.c0 + col] != 0));
     }
     if (!any) return;
   }
   const int chunk = D.chunk;
   const int jb0 = w.z * chunk;
   const int jb1 = min(D.N, jb0 + chunk);
-  if (width > 8)
-    far_item<16, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.far32, (gptr<const double4>)D.sb,
-                      (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), wcols,
-                      col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, smem, stg);
-  else
-    far_item<8, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.far32, (gptr<const double4>)D.sb,
-                     (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), wcols,
-                     col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, smem, stg);
+  far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.far32, (gptr<const double4>)D.sb,
+                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), wcols,
+                    col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, fl, stg);
 }
 
 // bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of
@@ -817,8 +771,8 @@ void launch_k(const DomDev* doms, const int4* items, int nitems, int lead, int d
   k_pairs<NR, TPT, MODE><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
 }
 
-// FP64: one launch. Mixed: 1-2 columns in one M_MIXED launch (groups of 3 or
-// more columns go through launch_far_mixed; launch_pairs rejects them).
+// FP64: one launch. Mixed: 1-2 columns in one M_MIXED launch; 4-8 columns as
+// k_far then M_NEAR over the same items (the second adds to the first's sums).
 template <int NR, int TPT>
 void launch_t(const DomDev* doms, const int4* items, int nitems, int lead, int data, bool mixed, bool ext,
               const int* active, int grid, hipStream_t st) {
@@ -826,7 +780,10 @@ void launch_t(const DomDev* doms, const int4* items, int nitems, int lead, int d
     launch_k<NR, TPT, M_EXT>(doms, items, nitems, lead, data, active, grid, st);
   } else if (!mixed) {
     launch_k<NR, TPT, M_FP64>(doms, items, nitems, lead, data, active, grid, st);
-  } else if constexpr (NR <= 2) {
+  } else if constexpr (NR >= 4) {
+    k_far<NR, TPT><<<grid, 256, 0, st>>>(doms, items, nitems, lead, data, active);
+    launch_k<NR, TPT, M_NEAR>(doms, items, nitems, lead, data, active, grid, st);
+  } else {
     launch_k<NR, TPT, M_MIXED>(doms, items, nitems, lead, data, active, grid, st);
   }
 }
@@ -884,26 +841,12 @@ hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int w
                         bool mixed, bool ext, const int* active, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   if (ext && mixed) return hipErrorInvalidValue;
-  if (mixed && width >= 4) return hipErrorInvalidValue;   // launch_far_mixed takes these
   const int grid = nitems;
   switch (width) {
     case 8: launch_w<8>(doms, items, nitems, tpt, lead, data, mixed, ext, active, grid, st); break;
     case 4: launch_w<4>(doms, items, nitems, tpt, lead, data, mixed, ext, active, grid, st); break;
     case 2: launch_w<2>(doms, items, nitems, tpt, lead, data, mixed, ext, active, grid, st); break;
     default: launch_w<1>(doms, items, nitems, tpt, lead, data, mixed, ext, active, grid, st); break;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_far_mixed(const DomDev* doms, const int4* items, int nitems, const int4* near_items, int nnear,
-                            int tpt, int lead, int data, const int* active, hipStream_t st) {
-  if (nitems <= 0) return hipSuccess;
-  if (tpt == 2) {
-    k_far_mix<2><<<nitems, 256, 0, st>>>(doms, items, nitems, lead, data, active);
-    launch_k<8, 2, M_NEAR>(doms, near_items, nnear, lead, data, active, nnear, st);
-  } else {
-    k_far_mix<1><<<nitems, 256, 0, st>>>(doms, items, nitems, lead, data, active);
-    launch_k<8, 1, M_NEAR>(doms, near_items, nnear, lead, data, active, nnear, st);
   }
   return hipGetLastError();
 }

@@ -85,21 +85,12 @@ struct ColDev {
 // domain's data columns):
 //   parts_d[(g*wcols_d + q)*N_d + i] = sum_{j in split g, j != i} w_jq / (eta_i - eta_j)
 // items: int4 {d, target tile, split, first weight column}; `width` columns per
-// item (8, 4, 2 or 1), one workgroup per item. mixed (1 or 2 columns; wider
-// groups go through launch_far_mixed): FP32 for far 64-node source tiles
-// (rec32, sb, tb). active: optional per global column mask; an item whose data
-// columns are all inactive is skipped.
+// item (8, 4, 2 or 1), one workgroup per item. mixed: FP32 for far 64-node
+// source tiles (rec32, sb, tb). active: optional per global column mask; an
+// item whose data columns are all inactive is skipped.
 // ext: the single domain's targets are doms[0].tz (FP64 only)
 hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int width, int tpt, int lead, int data,
                         bool mixed, bool ext, const int* active, hipStream_t st);
-// Mixed Arnoldi products of groups of 3 to 16 columns: the far tiles of every
-// item on the matrix cores in one launch (items of 16 columns carry width 16
-// in bits 20 and up, padded groups their width), then the near-only FP64
-// launch over near_items, the items' 8-column parts (the same domain, target
-// tile and split; a 16-column item's halves start at col0 and col0 + 8), which
-// adds to the partial sums the first launch wrote.
-hipError_t launch_far_mixed(const DomDev* doms, const int4* items, int nitems, const int4* near_items, int nnear,
-                            int tpt, int lead, int data, const int* active, hipStream_t st);
 // resident workgroups per CU of the pair-kernel variant (width columns, tpt, mixed)
 int pairs_blocks_per_cu(int width, int tpt, bool mixed);
 

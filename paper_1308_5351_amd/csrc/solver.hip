@@ -243,12 +243,9 @@ struct Batch {
   bool mixed = false;
   bool adjoint = false;
   bool second = false;   // eta'' and A' present (adjoint or no-subtraction operators)
-  // item lists by column-group width 8, 4, 2, 1; mixed Arnoldi products put
-  // their groups of 3 to 16 columns in index 4 (the far tiles, one launch) and
-  // the 8-column parts of those items in index 5 (their near tiles)
   struct ItemSet {
-    int4* d[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    int cnt[6] = {0, 0, 0, 0, 0, 0};
+    int4* d[4] = {nullptr, nullptr, nullptr, nullptr};
+    int cnt[4] = {0, 0, 0, 0};
     double pair_cols = 0, flops = 0, pairs1 = 0;
     bool built = false;
   } sets[4];
@@ -469,7 +466,7 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
   std::vector<int> order(B.ndom);
   for (int d = 0; d < B.ndom; ++d) order[d] = d;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.dom[a].N > B.dom[b].N; });
-  std::vector<int4> lists[6];
+  std::vector<int4> lists[4];
   S.pair_cols = S.flops = S.pairs1 = 0;
   for (int d : order) {
     const DomDev& D = B.dom[d];
@@ -481,31 +478,7 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
     S.pair_cols += pairs * wcols;
     S.flops += pairs * (16.0 + 8.0 * (wcols - 1));
     if (wcols == 1) S.pairs1 += pairs;
-    // Records larger than half an XCD's L2 (4 MB): split-major, so the
-    // workgroups resident together read one source range (measured at
-    // N = 133120: 28% shorter products than tile-major). Smaller ones stay
-    // in L2 either way and go tile-major, whose last round is cheaper
-    // (3% at N = 17408).
-    const bool split_major = (int64_t)D.N * rec_stride(wcols) * (int64_t)sizeof(double2) > (int64_t)2 << 20;
     int r0 = 0;
-    // mixed Arnoldi products: 16-column groups first (the far kernel shares
-    // each pair's factor between four MFMAs), listed with the 8-column groups
-    // below for one far launch; the near-only launch takes 8-column parts
-    while (p == P_GM_MIXED && wcols - r0 >= 16) {
-      auto push = [&](int t, int g) {
-        lists[4].push_back(make_int4(d, t, g, r0 | (16 << 20)));
-        lists[5].push_back(make_int4(d, t, g, r0));
-        lists[5].push_back(make_int4(d, t, g, r0 + 8));
-      };
-      if (split_major) {
-        for (int g = 0; g < D.splits; ++g)
-          for (int t = 0; t < tiles; ++t) push(t, g);
-      } else {
-        for (int t = 0; t < tiles; ++t)
-          for (int g = 0; g < D.splits; ++g) push(t, g);
-      }
-      r0 += 16;
-    }
     while (r0 < wcols) {
       int wi = 3;
       for (int k = 0; k < 4; ++k)
@@ -521,27 +494,22 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
         w = wcols - r0;
         code = r0 | (w << 20);
       }
-      // mixed Arnoldi products: groups of 3 to 8 columns join the far launch
-      const bool far_mix = p == P_GM_MIXED && wi == 0;
-      auto push = [&](int t, int g) {
-        if (far_mix) {
-          lists[4].push_back(make_int4(d, t, g, code));
-          lists[5].push_back(make_int4(d, t, g, code));
-        } else {
-          lists[wi].push_back(make_int4(d, t, g, code));
-        }
-      };
-      if (split_major) {
+      // Records larger than half an XCD's L2 (4 MB): split-major, so the
+      // workgroups resident together read one source range (measured at
+      // N = 133120: 28% shorter products than tile-major). Smaller ones stay
+      // in L2 either way and go tile-major, whose last round is cheaper
+      // (3% at N = 17408).
+      if ((int64_t)D.N * rec_stride(wcols) * (int64_t)sizeof(double2) > (int64_t)2 << 20) {
         for (int g = 0; g < D.splits; ++g)
-          for (int t = 0; t < tiles; ++t) push(t, g);
+          for (int t = 0; t < tiles; ++t) lists[wi].push_back(make_int4(d, t, g, code));
       } else {
         for (int t = 0; t < tiles; ++t)
-          for (int g = 0; g < D.splits; ++g) push(t, g);
+          for (int g = 0; g < D.splits; ++g) lists[wi].push_back(make_int4(d, t, g, code));
       }
       r0 += w;
     }
   }
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < 4; ++k) {
     S.cnt[k] = (int)lists[k].size();
     S.d[k] = upload(c, "b_items" + std::to_string(p) + "_" + std::to_string(k), lists[k]);
   }
@@ -848,9 +816,6 @@ void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
                           S.pairs1 > 0 && S.pairs1 == S.pair_cols};
     HIPCHK(c, hipEventRecord(pr.a, c->stream));
   }
-  if (S.cnt[4])
-    HIPCHK(c, launch_far_mixed(B.d_dom, S.d[4], S.cnt[4], S.d[5], S.cnt[5], B.shape.tpt, kLead[p], kData[p],
-                               active, c->stream));
   for (int k = 0; k < 4; ++k) {
     if (!S.cnt[k]) continue;
     HIPCHK(c, launch_pairs(B.d_dom, S.d[k], S.cnt[k], kWidths[k], B.shape.tpt, kLead[p], kData[p], mixed,
