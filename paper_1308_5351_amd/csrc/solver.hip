@@ -942,19 +942,44 @@ void setup_evec(gnk_ctx* c, Batch& B) {
 }
 
 // --------------------------------------------------------- operator product
-// y = op(x) for every column of the batch. scale/xout: optional per-column
-// scaling of x written back (GMRES normalisation); active: optional mask.
+// The operators as a record weight (cw: x times rho or A) and an epilogue
+//   y = a0 x + dsign dg x + cI Im(Cout S) + cR Re(Cout S) (+ Phat x when mean)
+struct OpForm {
+  int cw = C_RHO, cout = C_A, dsel = D_NONE;
+  double a0 = 0.0, dsign = 0.0, cI = 0.0, cR = 0.0;
+  bool mean = false;
+};
+
+OpForm op_form(gnk_ctx* c, int op) {
+  OpForm f;
+  switch (op) {
+    case GNK_OP_FB:   // 2x + diag(B1) x - B x,  B x = -(2/n) Im(A E(rho x))
+      f.cw = C_RHO; f.cout = C_A; f.a0 = 2.0; f.dsel = D_B; f.dsign = 1.0; f.cI = 1.0; break;
+    case GNK_OP_FC:   // D x - diag(D1) x (+ Lhat x),  D x = -(2/n) Re(A E(rho x))
+      f.cw = C_RHO; f.cout = C_A; f.dsel = D_D; f.dsign = -1.0; f.cR = -1.0; break;
+    case GNK_OP_GB:   // e x + B^T x + Phat x,  B^T x = (2/n) Im(rho E(A x))
+      f.cw = C_A; f.cout = C_RHO; f.dsel = D_E; f.dsign = 1.0; f.cI = 1.0; f.mean = true; break;
+    case GNK_OP_FB_T: // 2x + diag(B1) x - B^T x
+      f.cw = C_A; f.cout = C_RHO; f.a0 = 2.0; f.dsel = D_B; f.dsign = 1.0; f.cI = -1.0; break;
+    case GNK_OP_FC_T: // D^T x - diag(D1) x - Lhat x,  D^T x = (2/n) Re(rho E(A x))
+      f.cw = C_A; f.cout = C_RHO; f.dsel = D_D; f.dsign = -1.0; f.cR = 1.0; break;
+    case GNK_OP_GB_T: // e x + B x + Phat x
+      f.cw = C_RHO; f.cout = C_A; f.dsel = D_E; f.dsign = 1.0; f.cI = -1.0; f.mean = true; break;
+    case GNK_OP_FB_U: // x - B x - Nd x  (no subtraction)
+      f.cw = C_RHO; f.cout = C_A; f.a0 = 1.0; f.dsel = D_BU; f.dsign = -1.0; f.cI = 1.0; break;
+    case GNK_OP_GB_U: // x + B^T x + Nd x + Phat x  (no subtraction)
+      f.cw = C_A; f.cout = C_RHO; f.a0 = 1.0; f.dsel = D_BU; f.dsign = 1.0; f.cI = 1.0; f.mean = true; break;
+    default:
+      set_err(c, "unknown operator %d", op);
+      throw Fail{GNK_ERR_ARG};
+  }
+  return f;
+}
+
+// y = op(x) for every column of the batch; active: optional mask.
 struct ApplyArgs {
-  const double* scale = nullptr;
-  double* xout = nullptr;
   const int* active = nullptr;
   bool mixed = false;        // FP32 far tiles (batch built with mixed records)
-  const int* step = nullptr; // x = V_l (x, xout advanced by l*stepT), y = V_{l+1}; l read on the device
-  int64_t stepT = 0;
-  // inside an Arnoldi step: the epilogue also takes the first Gram-Schmidt
-  // pass (dots of V_{l+1} with V_0..V_l per block of per_blk elements)
-  double* dots = nullptr;
-  int per_blk = 0, nblk = 0, ldp = 0;
   // the partial sums of E(w x) from the last pair launch are those this
   // operator needs (same weights and x): apply only the epilogue
   bool reuse_sums = false;
@@ -967,58 +992,23 @@ void apply_op(gnk_ctx* c, Batch& B, int op, const double* x, double* y, const Ap
     circulant(c, B, x, y, 1.0);
     return;
   }
-  const bool need_mean = (op == GNK_OP_GB || op == GNK_OP_GB_T || op == GNK_OP_GB_U);
-  int cw = C_RHO, cout = C_A, dsel = D_NONE;
-  double a0 = 0.0, dsign = 0.0, cI = 0.0, cR = 0.0;
-  switch (op) {
-    case GNK_OP_FB:   // 2x + diag(B1) x - B x,  B x = -(2/n) Im(A E(rho x))
-      cw = C_RHO; cout = C_A; a0 = 2.0; dsel = D_B; dsign = 1.0; cI = 1.0; break;
-    case GNK_OP_FC:   // D x - diag(D1) x (+ Lhat x),  D x = -(2/n) Re(A E(rho x))
-      cw = C_RHO; cout = C_A; dsel = D_D; dsign = -1.0; cR = -1.0; break;
-    case GNK_OP_GB:   // e x + B^T x + Phat x,  B^T x = (2/n) Im(rho E(A x))
-      cw = C_A; cout = C_RHO; dsel = D_E; dsign = 1.0; cI = 1.0; break;
-    case GNK_OP_FB_T: // 2x + diag(B1) x - B^T x
-      cw = C_A; cout = C_RHO; a0 = 2.0; dsel = D_B; dsign = 1.0; cI = -1.0; break;
-    case GNK_OP_FC_T: // D^T x - diag(D1) x - Lhat x,  D^T x = (2/n) Re(rho E(A x))
-      cw = C_A; cout = C_RHO; dsel = D_D; dsign = -1.0; cR = 1.0; break;
-    case GNK_OP_GB_T: // e x + B x + Phat x
-      cw = C_RHO; cout = C_A; dsel = D_E; dsign = 1.0; cI = -1.0; break;
-    case GNK_OP_FB_U: // x - B x - Nd x  (no subtraction)
-      cw = C_RHO; cout = C_A; a0 = 1.0; dsel = D_BU; dsign = -1.0; cI = 1.0; break;
-    case GNK_OP_GB_U: // x + B^T x + Nd x + Phat x  (no subtraction)
-      cw = C_A; cout = C_RHO; a0 = 1.0; dsel = D_BU; dsign = 1.0; cI = 1.0; break;
-    default:
-      set_err(c, "unknown operator %d", op);
-      throw Fail{GNK_ERR_ARG};
-  }
+  const OpForm f = op_form(c, op);
   const int M = B.maxm1;
-  double* mean = need_mean ? ws<double>(c, "mean", (size_t)B.ncol * M) : nullptr;
-  if (a.reuse_sums && (need_mean || a.dots || a.xout || a.step || a.scale)) {
+  double* mean = f.mean ? ws<double>(c, "mean", (size_t)B.ncol * M) : nullptr;
+  if (a.reuse_sums && f.mean) {
     set_err(c, "internal: reused sums need a plain product of x");
     throw Fail{GNK_ERR_ARG};
   }
   if (!a.reuse_sums) {
-    k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
-        B.d_dom, B.d_col, cw, x, a.scale, a.active, a.xout, 0, mean, M, a.step, a.stepT);
+    k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(B.d_dom, B.d_col, f.cw, x, a.active,
+                                                                               0, mean, M);
     LAUNCHCHK(c);
+    pairs(c, B, P_GM, a.mixed, a.active);
   }
-  const double* xin = a.xout ? a.xout : x;
-  if (!a.reuse_sums) pairs(c, B, P_GM, a.mixed, a.active);
-  if (a.dots) {
-    if (!a.step || x != y || op == GNK_OP_FC || op == GNK_OP_FC_T || op == GNK_OP_LHAT) {
-      set_err(c, "internal: fused Gram-Schmidt epilogue needs an Arnoldi step of FB, FB_T, GB or GB_T");
-      throw Fail{GNK_ERR_ARG};
-    }
-    k_epilogue_dots<<<dim3((unsigned)a.nblk, (unsigned)B.ncol), kT, 0, c->stream>>>(
-        B.d_dom, B.d_col, y, a.stepT, cout, dsel, a0, dsign, cI, cR, mean, M, a.active, a.step, a.per_blk, a.dots,
-        a.ldp);
-    LAUNCHCHK(c);
-    return;
-  }
-  k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, xin, cout, dsel, a0, dsign, cI, cR, mean, M,
-                                                a.active, 0, y, a.step, a.stepT);
+  k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, x, f.cout, f.dsel, f.a0, f.dsign, f.cI, f.cR, mean,
+                                                M, a.active, 0, y);
   LAUNCHCHK(c);
-  if (op == GNK_OP_FC || op == GNK_OP_FC_T) circulant(c, B, xin, y, op == GNK_OP_FC ? 1.0 : -1.0);
+  if (op == GNK_OP_FC || op == GNK_OP_FC_T) circulant(c, B, x, y, op == GNK_OP_FC ? 1.0 : -1.0);
 }
 
 // ------------------------------------------------------------------ GMRES
@@ -1056,7 +1046,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   st.hstride = st.ldh * restart;
   double* dbl = ws<double>(c, "gmdbl", (size_t)ncol * (4 + st.hstride + 2 * kMaxRestart + (kMaxRestart + 1) +
                                                      kMaxRestart));
-  int* ints = ws<int>(c, "gmint", (size_t)ncol * 5 + 3);
+  int* ints = ws<int>(c, "gmint", (size_t)ncol * 5 + 4);
   {
     double* q = dbl;
     st.bnorm = q; q += ncol;
@@ -1077,6 +1067,24 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     st.step = r + 1;
     st.done = r + 2;
   }
+  // the step index of odd steps (see k_gs_finish)
+  int* const step_odd = ints + (size_t)ncol * 5 + 3;
+  // component sums of the Arnoldi vectors for operators with Phat: S slots
+  // per block (a chunk of per_blk entries meets at most (per_blk-1)/n + 2
+  // components)
+  if (op == GNK_OP_FC || op == GNK_OP_FC_T || op == GNK_OP_LHAT) {
+    set_err(c, "internal: the Arnoldi step has no circulant part (operator %d)", op);
+    throw Fail{GNK_ERR_ARG};
+  }
+  const OpForm form = op_form(c, op);
+  int nmin = B.dom[0].n;
+  for (const DomDev& D : B.dom) nmin = std::min(nmin, D.n);
+  const int S = (per_blk - 1) / nmin + 2;
+  if (form.mean && S > kMaxMeanSlots) {
+    set_err(c, "internal: %d component sums per block exceed %d", S, kMaxMeanSlots);
+    throw Fail{GNK_ERR_ARG};
+  }
+  double* mpart = form.mean ? ws<double>(c, "gmmp", (size_t)ncol * nblk * S) : nullptr;
   const unsigned cb = nblocks(ncol, 256);
   k_gmres_init<<<cb, 256, 0, c->stream>>>(ncol, st);
   LAUNCHCHK(c);
@@ -1090,6 +1098,9 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     k_cycle_reset<<<1, 1, 0, c->stream>>>(st);
     LAUNCHCHK(c);
     k_cycle_start<<<(unsigned)ncol, 64, 0, c->stream>>>(partial, nblk, ldp, o.tol, st);
+    LAUNCHCHK(c);
+    // V_0 = r / beta and its pair records for the cycle's first step
+    k_stage<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, per_blk, form.cw, st, mpart, S);
     LAUNCHCHK(c);
   };
   // r0 = b - A x0 into V_0
@@ -1128,27 +1139,21 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   // convergence test itself always uses the FP64 true residual.
   const double stop_tol = mixed ? 0.5 * o.tol : o.tol;
   // One Arnoldi step for every column; the step index l lives on the device
-  // (reset at each cycle start, advanced by the last kernel of the step), so
-  // the same sequence of launches serves every step and can be captured once.
-  auto enqueue_step = [&](bool use_mixed) {
-    ApplyArgs aa;
-    aa.scale = st.invbeta;
-    aa.xout = V;
-    aa.active = st.active;
-    aa.mixed = use_mixed;
-    aa.step = st.step;
-    aa.stepT = T;
-    aa.dots = P1;
-    aa.per_blk = per_blk;
-    aa.nblk = nblk;
-    aa.ldp = ldp;
-    apply_op(c, B, op, V, V, aa);
-    k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, st.active, P1, P2, ldp, st, 0, 1);
+  // (reset at each cycle start, advanced by the last kernel of the step, in
+  // st.step for even l and step_odd for odd l), so the same sequence of
+  // launches serves every pair of steps and can be captured once.
+  auto enqueue_step = [&](bool use_mixed, int odd) {
+    GmresState sl = st;
+    if (odd) sl.step = step_odd;
+    int* const next = odd ? st.step : step_odd;
+    pairs(c, B, P_GM, use_mixed, st.active);
+    k_epilogue_dots<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, form.cout, form.dsel, form.a0, form.dsign,
+                                              form.cI, form.cR, mpart, S, st.active, sl.step, per_blk, P1, ldp);
     LAUNCHCHK(c);
-    k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, st.active, P2, P1, ldp, st, 1, 0);
+    k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, P1, P2, ldp, sl);
     LAUNCHCHK(c);
-    k_arnoldi_finish<<<(unsigned)ncol, 64, 0, c->stream>>>(P1, nblk, ldp, restart, stop_tol, st, host_live,
-                                                           (mixed || want_hist) ? host_rel : nullptr, ncol);
+    k_gs_finish<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, P2, ldp, sl, next, restart, stop_tol,
+                                          host_live, (mixed || want_hist) ? host_rel : nullptr, form.cw, mpart, S);
     LAUNCHCHK(c);
   };
   // Every buffer the step touches exists before a capture (no allocation,
@@ -1156,7 +1161,6 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   // launch with events and so runs the steps without a graph.
   build_items(c, B, P_GM);
   if (mixed) build_items(c, B, P_GM_MIXED);
-  if (op == GNK_OP_GB || op == GNK_OP_GB_T) (void)ws<double>(c, "mean", (size_t)B.ncol * B.maxm1);
   const bool use_graph = c->graphs && !c->prof;
   bool fresh[4] = {false, false, false, false};   // cached graph matches this solve's step
   // k (1 or 2) consecutive Arnoldi steps in one launch: the step index lives on
@@ -1173,7 +1177,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
       hipGraph_t graph = nullptr;
       HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
       try {
-        for (int i = 0; i < k; ++i) enqueue_step(use_mixed);
+        for (int i = 0; i < k; ++i) enqueue_step(use_mixed, i);
       } catch (...) {
         hipGraph_t g2 = nullptr;
         (void)hipStreamEndCapture(c->stream, &g2);
@@ -1205,7 +1209,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     if (!use_graph) {
       for (int i = 0; i < k; ++i) {
         const size_t r0 = c->prof_pending.size();
-        enqueue_step(use_mixed);
+        enqueue_step(use_mixed, i);
         step_recs.emplace_back(r0, c->prof_pending.size());
       }
       return;
@@ -1281,6 +1285,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     // three speculative steps run (fully masked) after the last column stops.
     step_recs.clear();
     bool cycle_mixed = false;
+    // (l is even at every launch: its steps are the even-odd pairs of enqueue_step)
     for (int l = 0; l < restart;) {
       const bool use_mixed = mixed && mixed_now;
       cycle_mixed = cycle_mixed || use_mixed;
@@ -1470,7 +1475,7 @@ PairShape tuned_shape(gnk_ctx* c, int ndom, const gnk_domain* doms, const int* n
     k_rho<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom);
     LAUNCHCHK(c);
     k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
-        B.d_dom, B.d_col, C_RHO, x_flat, nullptr, nullptr, nullptr, 0, nullptr, B.maxm1, nullptr, 0);
+        B.d_dom, B.d_col, C_RHO, x_flat, nullptr, 0, nullptr, B.maxm1);
     LAUNCHCHK(c);
     build_items(c, B, P_GM);
     if (&p == &cand[0]) pairs(c, B, P_GM, mixed, nullptr);   // first launch of the kernels
@@ -1504,7 +1509,7 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
   LAUNCHCHK(c);
   // one launch for E(rho) (leading column) and E(rho gamma) (data columns)
   k_weights<<<dim3((unsigned)B.maxm1, (unsigned)B.ncol), kT, 0, c->stream>>>(
-      B.d_dom, B.d_col, C_RHO, gam, nullptr, nullptr, nullptr, 1, nullptr, B.maxm1, nullptr, 0);
+      B.d_dom, B.d_col, C_RHO, gam, nullptr, 1, nullptr, B.maxm1);
   LAUNCHCHK(c);
   pairs(c, B, P_SETUP, false, nullptr);
   k_diag_fbie<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, 1, 1);
@@ -1512,7 +1517,7 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
   // b = -y = -(D - diag(D1) + Lhat) gamma
   double* b = ws<double>(c, "rhs", T);
   k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_D, 0.0, 1.0, 0.0, 1.0, nullptr, 0,
-                                                nullptr, 1, b, nullptr, 0);
+                                                nullptr, 1, b);
   LAUNCHCHK(c);
   circulant(c, B, gam, b, -1.0);
   // f_B(gamma) from the same sums, for h; without singularity subtraction the
@@ -1524,10 +1529,10 @@ GmresOut fbie_batch(gnk_ctx* c, Batch& B, const double* gam, const gnk_opts& o, 
     fbg = ws<double>(c, "fbg", T);
     if (unsub)
       k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_BU, 1.0, -1.0, 1.0, 0.0, nullptr,
-                                                    0, nullptr, 1, fbg, nullptr, 0);
+                                                    0, nullptr, 1, fbg);
     else
       k_epilogue<<<col_grid(B), kT, 0, c->stream>>>(B.d_dom, B.d_col, gam, C_A, D_B, 2.0, 1.0, 1.0, 0.0, nullptr, 0,
-                                                    nullptr, 1, fbg, nullptr, 0);
+                                                    nullptr, 1, fbg);
     LAUNCHCHK(c);
   }
   validate_finish(c);

@@ -175,37 +175,26 @@ __global__ void k_evec(const DomDev* __restrict__ doms) {
 //   (c the centre of j's far-form tile of kFarTile nodes),
 //   [3 + q] w_q, [3 + wcols + q] b_q = w_q conj(eta'_j),
 // with weight column q = 0 the leading coefficient C_j when lead, and
-// q = lead + r the value C_j * v_j of the domain's column r, where
-//   v = x * scale[c]                  (optional; written back to xout)
-//   mean[c*M + k] = (1/n) sum_p v_{k n + p}   (optional, component means)
+// q = lead + r the value C_j * x_j of the domain's column r, and
+//   mean[c*M + k] = (1/n) sum_p x_{k n + p}   (optional, component means)
 // grid (max m1, ncol): block (k, c) covers component k of column c.
-// step/stepT: when step is given, x and xout are advanced by (*step) * stepT
-// (the Arnoldi vector of the current step, so one captured graph serves every step).
 __global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
                                                 int csel, const double* __restrict__ x,
-                                                const double* __restrict__ scale, const int* __restrict__ active,
-                                                double* __restrict__ xout, int lead, double* __restrict__ mean,
-                                                int M, const int* __restrict__ step, int64_t stepT) {
+                                                const int* __restrict__ active, int lead, double* __restrict__ mean,
+                                                int M) {
   __shared__ double sh[kT / 64];
   const int k = blockIdx.x, c = blockIdx.y;
-  if (step) {
-    const int64_t sh_ = (int64_t)(*step) * stepT;
-    x += sh_;
-    if (xout) xout += sh_;
-  }
   const ColDev C = cols[c];
   const DomDev& D = doms[C.d];
   if (k >= D.m1) return;
   if (active && !active[c]) return;
-  const double s = scale ? scale[c] : 1.0;
   const int wcols = lead + D.ncols;
   const int stride = rec_stride(wcols);
   const double* xr = x + C.off + (size_t)k * D.n;
   double acc = 0.0;
   for (int p = threadIdx.x; p < D.n; p += blockDim.x) {
     const int j = k * D.n + p;
-    const double v = xr[p] * s;
-    if (xout) xout[C.off + j] = v;
+    const double v = xr[p];
     const double2 cf = coef(D, csel, j);
     const double2 ep = eta_rel(D, j);
     double2* rj = D.rec + (size_t)j * stride;
@@ -224,6 +213,35 @@ __global__ __launch_bounds__(kT) void k_weights(const DomDev* __restrict__ doms,
   if (mean) {
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) mean[(size_t)c * M + k] = t / (double)D.n;
+  }
+}
+
+// Weight fields of node j, column r, in records without a leading column
+// (wcols = ncols): w = C_j q and w conj(eta'_j); with `head`, the node's head too.
+__device__ __forceinline__ void stage_weight(const DomDev& D, int csel, int r, int j, double q, bool head) {
+  const int wcols = D.ncols;
+  const double2 ep = eta_rel(D, j);
+  const double2 cf = coef(D, csel, j);
+  double2* rj = D.rec + (size_t)j * rec_stride(wcols);
+  const double2 w = make_double2(cf.x * q, cf.y * q);
+  rj[kRecHead + r] = w;
+  rj[kRecHead + wcols + r] = cmul_conj(w, ep);
+  if (head) record_head(rj, D.eta[j], ep);
+}
+
+// Sums of a chunk's entries over each component of n entries that it meets:
+// out[k - i0/n] for components k = i0/n .. (i1-1)/n, from the chunk held in
+// LDS (sq[i - i0]); wavefront q takes components i0/n + q, + q + 4, ...
+__device__ __forceinline__ void chunk_component_sums(const double* sq, int i0, int i1, int n,
+                                                     double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int k0 = i0 / n, k1 = (i1 - 1) / n;
+  for (int k = k0 + wv; k <= k1; k += nw) {
+    const int lo = max(i0, k * n), hi = min(i1, (k + 1) * n);
+    double acc = 0.0;
+    for (int i = lo + lane; i < hi; i += 64) acc += sq[i - i0];
+    acc = wave_sum(acc);
+    if (lane == 0) out[k - k0] = acc;
   }
 }
 
@@ -444,12 +462,8 @@ __global__ void k_reduce_parts(const DomDev* __restrict__ doms, double2* __restr
 __global__ void k_epilogue(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
                            const double* __restrict__ x, int csel_out, int dsel, double a0, double dsign, double cI,
                            double cR, const double* __restrict__ mean, int M, const int* __restrict__ active,
-                           int lead, double* __restrict__ y, const int* __restrict__ step, int64_t stepT) {
+                           int lead, double* __restrict__ y) {
   const int c = blockIdx.y;
-  if (step) {   // x = V_l, y = V_{l+1}
-    x += (int64_t)(*step) * stepT;
-    y += (int64_t)(*step + 1) * stepT;
-  }
   const ColDev C = cols[c];
   const DomDev& D = doms[C.d];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -503,17 +517,73 @@ __device__ __forceinline__ void chunk_dots(const double* __restrict__ V, int64_t
   }
 }
 
-// The epilogue of the operator inside an Arnoldi step l = *step, fused with
-// the first Gram-Schmidt pass: w = V_{l+1} = op(V_l) on this block's chunk of
-// per_blk elements (grid (nblk, ncol)), then the chunk's dots of w with
-// V_0..V_l into partial (c*nblk + blk)*ldp. V is the basis (vector q at V + q*T).
+// One Arnoldi step l = *st.step of every iterating column takes four launches:
+// the Cauchy sums of V_l (whose pair records the step before wrote), then
+//   k_epilogue_dots  w = op(V_l) into V_{l+1}; dots of w with V_0..V_l
+//   k_gs_update      w -= V h1; dots of w with V_0..V_l and |w|^2
+//   k_gs_finish      w -= V h2, |w| = beta, V_{l+1} = w / beta and its pair
+//                    records; block 0 closes Hessenberg column l.
+// (classical Gram-Schmidt with one re-orthogonalisation). Every kernel works
+// on chunks of per_blk elements of a column (grid (nblk, ncol)) and writes its
+// partial sums to (c*nblk + blk)*ldp. V is the basis (vector q at V + q*T).
+// For operators with the component means (P-hat x), the kernel that writes a
+// vector also writes its chunk's sums over each component it meets to mpart
+// ((c*nblk + blk)*S + slot), which the next epilogue adds up.
+
+// Component means of V_l on the block's chunk [i0, i1), from the partial sums
+// of the blocks whose chunks meet each component (fixed order): sm[k - i0/n].
+__device__ __forceinline__ void chunk_means(const double* __restrict__ mpart, int S, int c, int nblk, int per_blk,
+                                            int i0, int i1, int n, double* sm) {
+  const int k0 = i0 / n, k1 = (i1 - 1) / n;
+  for (int k = k0 + (int)threadIdx.x; k <= k1; k += blockDim.x) {
+    const int b0 = (int)(((int64_t)k * n) / per_blk);
+    const int b1 = (int)(((int64_t)(k + 1) * n - 1) / per_blk);
+    double s = 0.0;
+    for (int b = b0; b <= b1; ++b)
+      s += mpart[((size_t)c * nblk + b) * S + (k - (int)(((int64_t)b * per_blk) / n))];
+    sm[k - k0] = s / (double)n;
+  }
+  __syncthreads();
+}
+
+// Start of a cycle: V_0 = r / beta in place (beta from k_cycle_start), the
+// pair records of V_0 (with the node heads) and, when mpart is given, the
+// chunk's component sums.
+__global__ __launch_bounds__(kT) void k_stage(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
+                                              double* __restrict__ V, int per_blk, int csel, GmresState st,
+                                              double* __restrict__ mpart, int S) {
+  __shared__ double sq[kMaxChunk];
+  const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  if (!st.active[c]) return;
+  const ColDev C = cols[c];
+  const DomDev& D = doms[C.d];
+  const int i0 = blk * per_blk, i1 = min(D.N, i0 + per_blk);
+  if (i0 >= D.N) return;
+  const double s = st.invbeta[c];
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double q = V[C.off + i] * s;
+    V[C.off + i] = q;
+    sq[i - i0] = q;
+    // every iterating column writes the heads (the same values), so they are
+    // there whichever columns of the domain iterate
+    stage_weight(D, csel, C.r, i, q, true);
+  }
+  if (mpart) {
+    __syncthreads();
+    chunk_component_sums(sq, i0, i1, D.n, mpart + ((size_t)c * nblk + blk) * S);
+  }
+}
+
+// w = V_{l+1} = op(V_l) on the block's chunk from the Cauchy sums of the last
+// pair launch, then the chunk's dots of w with V_0..V_l.
 __global__ __launch_bounds__(kT) void k_epilogue_dots(const DomDev* __restrict__ doms,
                                                       const ColDev* __restrict__ cols, double* __restrict__ V,
                                                       int64_t T, int csel_out, int dsel, double a0, double dsign,
-                                                      double cI, double cR, const double* __restrict__ mean, int M,
+                                                      double cI, double cR, const double* __restrict__ mpart, int S,
                                                       const int* __restrict__ active, const int* __restrict__ step,
                                                       int per_blk, double* __restrict__ partial, int ldp) {
   __shared__ double sw[kMaxChunk];
+  __shared__ double sm[kMaxMeanSlots];
   const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
   if (!active[c]) return;
   const int l = *step;
@@ -529,6 +599,8 @@ __global__ __launch_bounds__(kT) void k_epilogue_dots(const DomDev* __restrict__
     for (int q = threadIdx.x; q < nvec; q += blockDim.x) out[q] = 0.0;
     return;
   }
+  if (mpart) chunk_means(mpart, S, c, nblk, per_blk, i0, i1, D.n, sm);
+  const int k0 = i0 / D.n;
   const double two_n = 2.0 / (double)D.n;
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const double2 s = reduce_parts(D, D.ncols, C.r, i);
@@ -536,7 +608,7 @@ __global__ __launch_bounds__(kT) void k_epilogue_dots(const DomDev* __restrict__
     const double xv = xl[C.off + i];
     double v = a0 * xv + two_n * (cI * cs.y + cR * cs.x);
     if (dsel != D_NONE) v += dsign * diagv(D, dsel, i) * xv;
-    if (mean) v += mean[(size_t)c * M + i / D.n];
+    if (mpart) v += sm[i / D.n - k0];
     w[C.off + i] = v;
     sw[i - i0] = v;
   }
@@ -544,42 +616,46 @@ __global__ __launch_bounds__(kT) void k_epilogue_dots(const DomDev* __restrict__
   chunk_dots(V, T, C.off, nvec, sw, i0, i1, out);
 }
 
-// h_l = sum over blocks of pin (fixed order); w -= sum_l h_l V_l on this
-// block's chunk; H[:, col] (+)= h (block 0); then pout = the chunk's dots of
-// the updated w with V_0..V_{nvec-1} (do_dots) or its squared norm (entry 0).
-// Arnoldi step l = *step: w = V_{l+1} against V_0..V_l, Hessenberg column l
+// h_q = sum over blocks of the partials in[.. + q] for q = 0..nq-1 (fixed
+// order), into LDS; wavefront v takes q = v, v + 4, ...
+__device__ __forceinline__ void sum_partials(const double* __restrict__ in, int c, int nblk, int ldp, int nq,
+                                             double* h) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int q = wv; q < nq; q += nw) {
+    double acc = 0.0;
+    for (int b = lane; b < nblk; b += 64) acc += in[((size_t)c * nblk + b) * ldp + q];
+    acc = wave_sum(acc);
+    if (lane == 0) h[q] = acc;
+  }
+  __syncthreads();
+}
+
+// First pass: h1 = V^T w from the epilogue's partials, H(:, l) = h1 (block 0),
+// w -= V h1 on the chunk, then the chunk's dots of the updated w with
+// V_0..V_l (entries 0..l) and its squared norm (entry l + 1).
 __global__ __launch_bounds__(kT) void k_gs_update(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
                                                   double* __restrict__ V, int64_t T, int per_blk,
-                                                  const int* __restrict__ active, const double* __restrict__ pin,
-                                                  double* __restrict__ pout, int ldp, GmresState st,
-                                                  int accumulate_h, int do_dots) {
+                                                  const double* __restrict__ pin, double* __restrict__ pout,
+                                                  int ldp, GmresState st) {
   __shared__ double h[kMaxRestart + 1];
   __shared__ double sw[kMaxChunk];
   __shared__ double sh[kT / 64];
   const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
-  if (!active[c]) return;
+  if (!st.active[c]) return;
   const int col = *st.step;
   const int nvec = col + 1;
   double* __restrict__ w = V + (size_t)nvec * T;
   const ColDev C = cols[c];
   const int N = doms[C.d].N;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int l = wv; l < nvec; l += nw) {
-    double acc = 0.0;
-    for (int b = lane; b < nblk; b += 64) acc += pin[((size_t)c * nblk + b) * ldp + l];
-    acc = wave_sum(acc);
-    if (lane == 0) h[l] = acc;
-  }
-  __syncthreads();
+  sum_partials(pin, c, nblk, ldp, nvec, h);
   if (blk == 0) {
     double* Hr = st.H + (size_t)c * st.hstride + (size_t)col * st.ldh;
-    for (int l = threadIdx.x; l < nvec; l += blockDim.x) Hr[l] = accumulate_h ? Hr[l] + h[l] : h[l];
+    for (int l = threadIdx.x; l < nvec; l += blockDim.x) Hr[l] = h[l];
   }
   double* out = pout + ((size_t)c * nblk + blk) * ldp;
   const int i0 = blk * per_blk, i1 = min(N, i0 + per_blk);
   if (i0 >= N) {
-    const int nout = do_dots ? nvec : 1;
-    for (int l = threadIdx.x; l < nout; l += blockDim.x) out[l] = 0.0;
+    for (int l = threadIdx.x; l <= nvec; l += blockDim.x) out[l] = 0.0;
     return;
   }
   double* wr = w + C.off;
@@ -591,13 +667,10 @@ __global__ __launch_bounds__(kT) void k_gs_update(const DomDev* __restrict__ dom
     sw[i - i0] = v;
     nrm = __builtin_fma(v, v, nrm);
   }
-  if (do_dots) {
-    __syncthreads();
-    chunk_dots(V, T, C.off, nvec, sw, i0, i1, out);
-  } else {
-    const double t = block_sum(nrm, sh);
-    if (threadIdx.x == 0) out[0] = t;
-  }
+  __syncthreads();
+  chunk_dots(V, T, C.off, nvec, sw, i0, i1, out);
+  const double t = block_sum(nrm, sh);
+  if (threadIdx.x == 0) out[nvec] = t;
 }
 
 // partial norms^2 of the columns of x (grid (nblk, ncol)); entry (c*nblk + blk)*ldp
@@ -686,32 +759,24 @@ __global__ void k_cycle_reset(GmresState st) {
   *st.done = 0;
 }
 
-// End of Arnoldi step `col`; one 64-lane block per column c: beta = ||w||
-// from the partials, H(col+1, col) = beta, Givens rotations applied in LDS,
-// residual estimate, stop test for this cycle. The block that finishes last
-// (counted in *st.done after a device-scope fence) publishes the number of
-// iterating columns to host_live[col] and, when given, the residual estimates
-// to host_rel[col*ncol ..] (host-mapped memory the host reads after an event),
-// then advances the step counter: every block of the launch has read it.
-__device__ void arnoldi_column(const double* partial, int nblk, int ldp, int restart, double tol, GmresState st,
-                               int c, int col, double* hc, double* cs_, double* sn_) {
-  const int lane = threadIdx.x;
-  double s = 0.0;
-  for (int b = lane; b < nblk; b += 64) s += partial[((size_t)c * nblk + b) * ldp];
-  s = wave_sum(s);
-  const double beta = sqrt(s);
+// Close Hessenberg column `col` of GMRES column c (all threads of one block):
+// H(0..col, col) += h2 (the first pass stored h1), H(col+1, col) = beta, the
+// column's earlier Givens rotations and a new one applied, the residual
+// estimate |g_{col+1}| / ||b||, and the cycle's stop test.
+__device__ void arnoldi_close(GmresState st, int c, int col, const double* h2, double beta, int restart,
+                              double tol, double* hc, double* cs_, double* sn_) {
   double* Hc = st.H + (size_t)c * st.hstride + (size_t)col * st.ldh;
   double* cs = st.cs + (size_t)c * kMaxRestart;
   double* sn = st.sn + (size_t)c * kMaxRestart;
-  for (int k = lane; k <= col; k += 64) {
-    hc[k] = Hc[k];
+  for (int k = threadIdx.x; k <= col; k += blockDim.x) {
+    hc[k] = Hc[k] + h2[k];
     if (k < col) {
       cs_[k] = cs[k];
       sn_[k] = sn[k];
     }
   }
   __syncthreads();
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     hc[col + 1] = beta;
     for (int k = 0; k < col; ++k) {
       const double t = cs_[k] * hc[k] + sn_[k] * hc[k + 1];
@@ -738,38 +803,86 @@ __device__ void arnoldi_column(const double* partial, int nblk, int ldp, int res
     if (stop) {
       st.active[c] = 0;
       atomicSub(st.live, 1);
-    } else {
-      st.invbeta[c] = 1.0 / beta;
     }
   }
   __syncthreads();
-  for (int k = lane; k <= col + 1; k += 64) Hc[k] = hc[k];
+  for (int k = threadIdx.x; k <= col + 1; k += blockDim.x) Hc[k] = hc[k];
 }
 
-__global__ __launch_bounds__(64) void k_arnoldi_finish(const double* partial, int nblk, int ldp, int restart,
-                                                       double tol, GmresState st, int* host_live, double* host_rel,
-                                                       int ncol) {
+// Second pass and end of the step. Every block: h2 = V^T w and |w|^2 from
+// the first pass's partials, w -= V h2 on its chunk; as h2 is orthogonal to
+// the updated w, |w|^2 - |h2|^2 is its squared norm beta^2 (the first pass has
+// already removed all but rounding-size components along V, so no
+// cancellation occurs short of a breakdown); V_{l+1} = w / beta, its pair
+// records and component sums. Block 0 of each column then closes Hessenberg
+// column l. Those blocks count themselves in *st.done (after a device-scope
+// fence); the last publishes the number of iterating columns to host_live[l]
+// and, when given, the residual estimates to host_rel[l*ncol ..] (host-mapped
+// memory the host reads after an event) and sets *step_next = l + 1. The
+// step index is double-buffered (st.step is read by all of this step's
+// launches, step_next by the next step's), so no block can read an index
+// that another has already advanced. A block of a column that block 0 has
+// just stopped may still write V_{l+1} and its records: no later step or the
+// solution update reads them.
+__global__ __launch_bounds__(kT) void k_gs_finish(const DomDev* __restrict__ doms, const ColDev* __restrict__ cols,
+                                                  double* __restrict__ V, int64_t T, int per_blk,
+                                                  const double* __restrict__ pin, int ldp, GmresState st,
+                                                  int* __restrict__ step_next, int restart, double tol,
+                                                  int* host_live, double* host_rel, int csel,
+                                                  double* __restrict__ mpart, int S) {
+  __shared__ double h[kMaxRestart + 2];
+  __shared__ double sq[kMaxChunk];
   __shared__ double hc[kMaxRestart + 2];
-  __shared__ double cs_[kMaxRestart + 1];
-  __shared__ double sn_[kMaxRestart + 1];
+  __shared__ double cs_[kMaxRestart], sn_[kMaxRestart];
   __shared__ int last;
-  const int c = blockIdx.x, lane = threadIdx.x;
+  const int c = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x, ncol = gridDim.y;
+  const bool act = st.active[c] != 0;
+  if (!act && blk != 0) return;
   const int col = *st.step;
-  if (st.active[c]) arnoldi_column(partial, nblk, ldp, restart, tol, st, c, col, hc, cs_, sn_);
+  const int nvec = col + 1;
+  double beta = 0.0;
+  if (act) {
+    sum_partials(pin, c, nblk, ldp, nvec + 1, h);
+    double hh = 0.0;
+    for (int l = 0; l < nvec; ++l) hh = __builtin_fma(h[l], h[l], hh);
+    const double b2 = h[nvec] - hh;
+    beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+    const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+    const ColDev C = cols[c];
+    const DomDev& D = doms[C.d];
+    const int i0 = blk * per_blk, i1 = min(D.N, i0 + per_blk);
+    if (i0 < D.N) {
+      double* wr = V + (size_t)nvec * T + C.off;
+      for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        double v = wr[i];
+        for (int l = 0; l < nvec; ++l) v = __builtin_fma(-h[l], V[(size_t)l * T + C.off + i], v);
+        const double q = v * inv;
+        wr[i] = q;
+        sq[i - i0] = q;
+        stage_weight(D, csel, C.r, i, q, false);
+      }
+      if (mpart) {
+        __syncthreads();
+        chunk_component_sums(sq, i0, i1, D.n, mpart + ((size_t)c * nblk + blk) * S);
+      }
+    }
+  }
+  if (blk != 0) return;
+  if (act) arnoldi_close(st, c, col, h, beta, restart, tol, hc, cs_, sn_);
   __syncthreads();
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     __threadfence();
-    last = atomicAdd(st.done, 1) == (int)gridDim.x - 1;
+    last = atomicAdd(st.done, 1) == ncol - 1;
   }
   __syncthreads();
   if (!last) return;
   __threadfence();
   if (host_rel)
-    for (int q = lane; q < ncol; q += 64) host_rel[(size_t)col * ncol + q] = st.relres[q];
-  if (lane == 0) {
+    for (int q = threadIdx.x; q < ncol; q += blockDim.x) host_rel[(size_t)col * ncol + q] = st.relres[q];
+  if (threadIdx.x == 0) {
     host_live[col] = atomicAdd(st.live, 0);
     *st.done = 0;
-    *st.step = col + 1;
+    *step_next = col + 1;
   }
 }
 
