@@ -46,7 +46,7 @@ struct gnk_ctx {
   // instantiated Arnoldi-step graphs (FP64, mixed), kept across solves: each
   // solve captures its step and refreshes these with hipGraphExecUpdate, which
   // avoids a new instantiation when only kernel arguments changed
-  hipGraphExec_t step_exec[4] = {nullptr, nullptr, nullptr, nullptr};   // [mixed + 2 (steps - 1)]
+  hipGraphExec_t step_exec[6] = {};   // [mixed + 2 log2(steps)], 1, 2 or 4 steps
   std::string err;
   int num_cu = 256;
   size_t ws_limit = 0;   // bytes, 0 = unlimited
@@ -1142,7 +1142,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   // (reset at each cycle start, advanced by the last kernel of the step, in
   // st.step for even l and step_odd for odd l), so the same sequence of
   // launches serves every pair of steps and can be captured once.
-  auto enqueue_step = [&](bool use_mixed, int odd) {
+  auto enqueue_step = [&](bool use_mixed, bool odd) {
     GmresState sl = st;
     if (odd) sl.step = step_odd;
     int* const next = odd ? st.step : step_odd;
@@ -1162,22 +1162,25 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   build_items(c, B, P_GM);
   if (mixed) build_items(c, B, P_GM_MIXED);
   const bool use_graph = c->graphs && !c->prof;
-  bool fresh[4] = {false, false, false, false};   // cached graph matches this solve's step
-  // k (1 or 2) consecutive Arnoldi steps in one launch: the step index lives on
-  // the device, and inside a graph the kernels follow each other with no gap,
-  // while each graph launch costs a gap of about 13 us
+  bool fresh[6] = {};   // cached graph matches this solve's step
+  // k (1, 2 or 4) consecutive Arnoldi steps in one launch: the step index
+  // lives on the device, and inside a graph the kernels follow each other with
+  // no gap, while each graph launch costs a gap of about 13 us
   // profiling: the pair records of each step of the cycle, so that those of the
   // fully masked speculative steps can be left out of the totals
   std::vector<std::pair<size_t, size_t>> step_recs;
+  // steps of the launch that starts at step l (even): four while four remain
+  // in the cycle, then two, then one
+  auto steps_per_launch = [&](int l) { return l + 4 <= restart ? 4 : (l + 2 <= restart ? 2 : 1); };
   // capture (or update the cached executable of) the graph of k steps
   auto prepare_step = [&](bool use_mixed, int k) {
-    const int m = (use_mixed ? 1 : 0) + 2 * (k - 1);
+    const int m = (use_mixed ? 1 : 0) + (k == 4 ? 4 : 2 * (k - 1));
     hipGraphExec_t& ge = c->step_exec[m];
     if (!fresh[m]) {
       hipGraph_t graph = nullptr;
       HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
       try {
-        for (int i = 0; i < k; ++i) enqueue_step(use_mixed, i);
+        for (int i = 0; i < k; ++i) enqueue_step(use_mixed, (i & 1) != 0);
       } catch (...) {
         hipGraph_t g2 = nullptr;
         (void)hipStreamEndCapture(c->stream, &g2);
@@ -1209,7 +1212,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     if (!use_graph) {
       for (int i = 0; i < k; ++i) {
         const size_t r0 = c->prof_pending.size();
-        enqueue_step(use_mixed, i);
+        enqueue_step(use_mixed, (i & 1) != 0);
         step_recs.emplace_back(r0, c->prof_pending.size());
       }
       return;
@@ -1222,7 +1225,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   // start. A mixed solve from a zero start takes mixed steps at once when
   // inner_tol >= 1 (its starting relative residual is 1); a wrong guess only
   // costs a capture.
-  if (use_graph) (void)prepare_step(mixed && !o.x0 && o.inner_tol >= 1.0, restart >= 2 ? 2 : 1);
+  if (use_graph) (void)prepare_step(mixed && !o.x0 && o.inner_tol >= 1.0, steps_per_launch(0));
 
   std::vector<int> outer(ncol, 0), conv(ncol, 0), mixed_steps(ncol, 0), refine(ncol, 0);
   std::vector<int> hist_cnt(ncol, 0), prev_inner(ncol, 0);
@@ -1278,18 +1281,18 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     }
     for (int q = 0; q < ncol; ++q)
       if (!conv[q]) outer[q] += 1;
-    // Arnoldi steps, two per launch while two remain in the cycle. The host
-    // looks one launch behind the device: before enqueuing the next launch it
-    // waits for the last step of the one before the current and reads how
-    // many columns are still iterating, so the queue never drains and at most
-    // three speculative steps run (fully masked) after the last column stops.
+    // Arnoldi steps, up to four per launch. The host looks one launch behind
+    // the device: before enqueuing the next launch it waits for the last step
+    // of the one before the current and reads how many columns are still
+    // iterating, so the queue never drains and at most seven speculative steps
+    // run (fully masked) after the last column stops.
     step_recs.clear();
     bool cycle_mixed = false;
     // (l is even at every launch: its steps are the even-odd pairs of enqueue_step)
     for (int l = 0; l < restart;) {
       const bool use_mixed = mixed && mixed_now;
       cycle_mixed = cycle_mixed || use_mixed;
-      const int k = (l + 2 <= restart) ? 2 : 1;
+      const int k = steps_per_launch(l);
       if (use_mixed)
         for (int q = 0; q < ncol; ++q)
           if (!conv[q]) mixed_steps[q] += k;
