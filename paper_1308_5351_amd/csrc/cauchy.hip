@@ -690,11 +690,11 @@ __global__ __launch_bounds__(256) void k_far(const DomDev* __restrict__ doms, co
                     col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, fl, stg);
 }
 
-// bounding circle {cx, cy, r, 0} (centre of the bounding box) of each tile of
-// `tile` consecutive nodes; one wavefront per (tile, domain)
-__global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ doms, int tile, int which) {
-  const DomDev& D = doms[blockIdx.y];
-  const int b = blockIdx.x, lane = threadIdx.x;
+// bounding circle {cx, cy, r, 0} (centre of the bounding box) of tile b of
+// `tile` consecutive nodes (which 0, 1, 2: of the nodes into sb, tb, sbf;
+// 3: of the target points into tb); one wavefront per (tile, domain)
+__device__ __forceinline__ void tile_bounds(const DomDev& D, int tile, int which, int b) {
+  const int lane = threadIdx.x;
   const double2* pts = which == 3 ? D.tz : D.eta;
   const int np = which == 3 ? D.Nt : D.N;
   const int i0 = b * tile;
@@ -724,6 +724,17 @@ __global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ d
   // widen by a relative margin so rounding of the centre cannot hide a node
   double4* out = (which == 1 || which == 3) ? D.tb : (which == 2 ? D.sbf : D.sb);
   if (lane == 0) out[b] = make_double4(cx, cy, r * (1.0 + 1e-12) + 1e-300, 0.0);
+}
+
+__global__ __launch_bounds__(64) void k_tile_bounds(const DomDev* __restrict__ doms, int tile, int which) {
+  tile_bounds(doms[blockIdx.y], tile, which, blockIdx.x);
+}
+
+// the three node tilings in one launch (grid.z = which): 64-node source
+// tiles, 64 tpt-node target tiles and the far-form tiles of kFarTile nodes
+__global__ __launch_bounds__(64) void k_node_tile_bounds(const DomDev* __restrict__ doms, int tpt) {
+  const int which = blockIdx.z;
+  tile_bounds(doms[blockIdx.y], which == 0 ? 64 : (which == 1 ? 64 * tpt : kFarTile), which, blockIdx.x);
 }
 
 // FP32 records {v_j = (eta_j - c_s)/r_s ((c_s, r_s) the node's 64-node tile),
@@ -854,6 +865,13 @@ hipError_t launch_pairs(const DomDev* doms, const int4* items, int nitems, int w
 hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, int which, hipStream_t st) {
   dim3 grid((unsigned)((maxN + tile - 1) / tile), (unsigned)ndom);
   k_tile_bounds<<<grid, 64, 0, st>>>(doms, tile, which);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_tile_bounds(const DomDev* doms, int ndom, int maxN, int tpt, hipStream_t st) {
+  // the 64-node tiling has the most tiles
+  dim3 grid((unsigned)((maxN + 63) / 64), (unsigned)ndom, 3);
+  k_node_tile_bounds<<<grid, 64, 0, st>>>(doms, tpt);
   return hipGetLastError();
 }
 

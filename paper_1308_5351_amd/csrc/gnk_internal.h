@@ -99,6 +99,7 @@ int pairs_blocks_per_cu(int width, int tpt, bool mixed);
 // which: 0 source tiles (sb), 1 target tiles (tb), 2 far-form source tiles (sbf),
 // 3 target tiles of the separate targets tz (tb)
 hipError_t launch_tile_bounds(const DomDev* doms, int ndom, int maxN, int tile, int which, hipStream_t st);
+hipError_t launch_node_tile_bounds(const DomDev* doms, int ndom, int maxN, int tpt, hipStream_t st);
 // Treecode (csrc/tree.hip): boxes of kLeaf << l consecutive nodes at level l
 constexpr int kLeaf = 256;
 constexpr int kTreeMaxP = 48;

@@ -47,6 +47,9 @@ struct gnk_ctx {
   // solve captures its step and refreshes these with hipGraphExecUpdate, which
   // avoids a new instantiation when only kernel arguments changed
   hipGraphExec_t step_exec[6] = {};   // [mixed + 2 log2(steps)], 1, 2 or 4 steps
+  // every value a cached step graph's launches take (see step_signature);
+  // empty when the graph must be captured again
+  std::vector<uint64_t> step_sig[6];
   std::string err;
   int num_cu = 256;
   size_t ws_limit = 0;   // bytes, 0 = unlimited
@@ -452,9 +455,7 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
   }
   B.d_dom = upload(c, "b_dom", B.dom);
   B.d_col = upload(c, "b_col", B.col);
-  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64, 0, c->stream));
-  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, 64 * B.shape.tpt, 1, c->stream));
-  HIPCHK(c, launch_tile_bounds(B.d_dom, ndom, B.maxN, kFarTile, 2, c->stream));
+  HIPCHK(c, launch_node_tile_bounds(B.d_dom, ndom, B.maxN, B.shape.tpt, c->stream));
 }
 
 // Work items of a pattern: every domain (largest first), column group, target
@@ -871,40 +872,38 @@ dim3 node_grid(const Batch& B) { return dim3(nblocks(B.maxN), (unsigned)B.ndom);
 dim3 col_grid(const Batch& B) { return dim3(nblocks(B.maxN), (unsigned)B.ncol); }
 
 // Input checks on the device (finite values, A and, where the operator needs
-// it, eta' nonzero). validate_enqueue queues them and the copy of their flags
-// to host-pinned memory; validate_finish waits for that copy alone and throws
+// it, eta' nonzero). validate_enqueue queues them, writing their flags to
+// host-mapped memory; validate_finish waits for that launch alone and throws
 // on a failed check. Between the two a caller may queue work that writes only
 // the library's workspace (the right-hand side product, diagonals), so that
 // the wait overlaps it; nothing the caller owns is written before the finish,
-// and an error return synchronises the stream first.
+// and an error return synchronises the stream first. (Every call ends
+// synchronised, so no earlier check can still write the flags the host zeroes.)
 void validate_enqueue(gnk_ctx* c, Batch& B, const double* x, int64_t len) {
-  int* flags = ws<int>(c, "flags", 1);
-  HIPCHK(c, hipMemsetAsync(flags, 0, sizeof(int), c->stream));
-  k_validate<<<node_grid(B), kT, 0, c->stream>>>(B.d_dom, (B.adjoint || B.second) ? 1 : 0, flags);
-  LAUNCHCHK(c);
-  if (x && len > 0) {
-    k_check_finite<<<nblocks(len), kT, 0, c->stream>>>(x, len, flags);
-    LAUNCHCHK(c);
-  }
-  if (!c->vflags) HIPCHK(c, hipHostMalloc((void**)&c->vflags, sizeof(int), 0));
+  if (!c->vflags) HIPCHK(c, hipHostMalloc((void**)&c->vflags, 3 * sizeof(int), 0));
   if (!c->val_ev) HIPCHK(c, hipEventCreateWithFlags(&c->val_ev, hipEventDisableTiming));
-  k_publish_ints<<<1, 64, 0, c->stream>>>(flags, 1, hostio_dev(c, c->vflags));
+  volatile int* fl = c->vflags;
+  fl[0] = fl[1] = fl[2] = 0;
+  if (!x) len = 0;
+  const dim3 grid(std::max(nblocks(B.maxN), nblocks(std::max<int64_t>(len, 1))), (unsigned)B.ndom + 1);
+  k_validate_inputs<<<grid, kT, 0, c->stream>>>(B.d_dom, B.ndom, (B.adjoint || B.second) ? 1 : 0, x, len,
+                                                hostio_dev(c, c->vflags));
   LAUNCHCHK(c);
   HIPCHK(c, hipEventRecord(c->val_ev, c->stream));
 }
 
 void validate_finish(gnk_ctx* c) {
   HIPCHK(c, hipEventSynchronize(c->val_ev));
-  const int h = *reinterpret_cast<volatile int*>(c->vflags);
-  if (h & 1) {
+  const volatile int* fl = c->vflags;
+  if (fl[0]) {
     set_err(c, "non-finite value in the inputs");
     throw Fail{GNK_ERR_NONFINITE};
   }
-  if (h & 2) {
+  if (fl[1]) {
     set_err(c, "A vanishes at a node");
     throw Fail{GNK_ERR_ZERO_A};
   }
-  if (h & 4) {
+  if (fl[2]) {
     set_err(c, "eta' vanishes at a node (the adjoint equation divides by eta')");
     throw Fail{GNK_ERR_ZERO_ETAP};
   }
@@ -1172,11 +1171,47 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   // steps of the launch that starts at step l (even): four while four remain
   // in the cycle, then two, then one
   auto steps_per_launch = [&](int l) { return l + 4 <= restart ? 4 : (l + 2 <= restart ? 2 : 1); };
+  // Every argument of the step's launches (enqueue_step and, through pairs,
+  // the pair kernels' work lists, shape and variant): the kernels read the
+  // domains, columns, work items and vectors through these pointers when they
+  // run, so a cached graph whose signature matches needs no new capture. The
+  // treecode's launches are not listed: with it the graph is always captured.
+  auto step_signature = [&](bool use_mixed, int k) {
+    std::vector<uint64_t> sg;
+    auto u = [&](uint64_t v) { sg.push_back(v); };
+    auto pt = [&](const void* q) { u((uint64_t)(uintptr_t)q); };
+    auto fp = [&](double v) { uint64_t b; memcpy(&b, &v, 8); u(b); };
+    u((uint64_t)use_mixed); u((uint64_t)k);
+    const Batch::ItemSet& IS = B.sets[use_mixed ? P_GM_MIXED : P_GM];
+    for (int q = 0; q < 4; ++q) { pt(IS.d[q]); u((uint64_t)IS.cnt[q]); }
+    u((uint64_t)B.shape.tpt); pt(B.d_dom); pt(B.d_col); u((uint64_t)B.ndom); u((uint64_t)B.maxN);
+    u((uint64_t)(B.dom[0].tz != nullptr));
+    for (const void* q : {(const void*)st.bnorm, (const void*)st.true_relres, (const void*)st.relres,
+                          (const void*)st.invbeta, (const void*)st.H, (const void*)st.cs, (const void*)st.sn,
+                          (const void*)st.g, (const void*)st.y, (const void*)st.active, (const void*)st.converged,
+                          (const void*)st.kdim, (const void*)st.inner_it, (const void*)st.live, (const void*)st.step,
+                          (const void*)st.done})
+      pt(q);
+    u((uint64_t)st.ldh); u((uint64_t)st.hstride);
+    pt(V); u((uint64_t)T); u((uint64_t)per_blk); u((uint64_t)nblk); u((uint64_t)ncol); pt(P1); pt(P2);
+    u((uint64_t)ldp); pt(step_odd); u((uint64_t)restart); fp(stop_tol); pt(host_live);
+    pt((mixed || want_hist) ? host_rel : nullptr);
+    u((uint64_t)form.cw); u((uint64_t)form.cout); u((uint64_t)form.dsel); fp(form.a0); fp(form.dsign); fp(form.cI);
+    fp(form.cR); pt(mpart); u((uint64_t)S); pt(c->stream);
+    return sg;
+  };
   // capture (or update the cached executable of) the graph of k steps
   auto prepare_step = [&](bool use_mixed, int k) {
     const int m = (use_mixed ? 1 : 0) + (k == 4 ? 4 : 2 * (k - 1));
     hipGraphExec_t& ge = c->step_exec[m];
     if (!fresh[m]) {
+      std::vector<uint64_t> sig;
+      if (!B.tree.on) sig = step_signature(use_mixed, k);
+      if (ge && !sig.empty() && c->step_sig[m] == sig) {
+        fresh[m] = true;
+        return ge;
+      }
+      c->step_sig[m].clear();
       hipGraph_t graph = nullptr;
       HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
       try {
@@ -1204,6 +1239,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) ge = nullptr;
       HIPCHK(c, e);
+      c->step_sig[m] = std::move(sig);
       fresh[m] = true;
     }
     return ge;
@@ -1260,16 +1296,23 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
       prev_inner[q] = inner_q;
     }
   };
+  // From a zero start the first cycle's residual is b itself, so every column
+  // with b != 0 iterates and the host need not wait for the cycle-start state
+  // (a column with b = 0 takes no Arnoldi step, and its outer count is set
+  // back at the end). Mixed solves and residual histories read that state.
+  const bool lazy_start = !o.x0 && !mixed && !want_hist;
   for (int cyc = 0; cyc < o.maxit; ++cyc) {
-    k_publish_cycle<<<nblocks(ncol + 1), kT, 0, c->stream>>>(st, ncol, hi_dev, hd_dev);
-    LAUNCHCHK(c);
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    record_hist(cyc == 0);
-    const int live = hi[0];
-    for (int q = 0; q < ncol; ++q) conv[q] = hi[1 + q];
-    if (live == 0) {
-      published = true;
-      break;
+    if (cyc > 0 || !lazy_start) {
+      k_publish_cycle<<<nblocks(ncol + 1), kT, 0, c->stream>>>(st, ncol, hi_dev, hd_dev);
+      LAUNCHCHK(c);
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      record_hist(cyc == 0);
+      const int live = hi[0];
+      for (int q = 0; q < ncol; ++q) conv[q] = hi[1 + q];
+      if (live == 0) {
+        published = true;
+        break;
+      }
     }
     // a cycle whose starting (FP64) residual is already below inner_tol
     // takes mixed products from its first step
@@ -1366,6 +1409,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     inner[q] = hi[1 + ncol + q];
     trel[q] = hd[q];
     rel[q] = hd[ncol + q];
+    if (lazy_start && inner[q] == 0) outer[q] = 0;
   }
   out.all_converged = true;
   for (int q = 0; q < ncol; ++q) {

@@ -87,6 +87,30 @@ __global__ void k_validate(const DomDev* __restrict__ doms, int adjoint, int* fl
   if (f) atomicOr(flags, f);
 }
 
+// The node checks of k_validate and the finiteness of x (len entries) in one
+// launch (grid (blocks over max(max N, len), ndom + 1); row ndom takes x),
+// with one flag word per failure (plain stores of 1 into host-mapped memory
+// that the host zeroes before the launch): fl[0] non-finite, fl[1] A = 0,
+// fl[2] eta' = 0 (adjoint).
+__global__ void k_validate_inputs(const DomDev* __restrict__ doms, int ndom, int adjoint,
+                                  const double* __restrict__ x, int64_t len, int* fl) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int)blockIdx.y == ndom) {
+    if (i < len && !isfinite(x[i])) fl[0] = 1;
+    return;
+  }
+  const DomDev& D = doms[blockIdx.y];
+  if (i >= D.N) return;
+  const double2 a = D.A[i];
+  if (!finite2(a) || !finite2(D.eta[i]) || !finite2(D.etap[i])) fl[0] = 1;
+  if (a.x == 0.0 && a.y == 0.0) fl[1] = 1;
+  if (adjoint) {
+    if (!finite2(D.etapp[i]) || !finite2(D.Ap[i])) fl[0] = 1;
+    const double2 ep = D.etap[i];
+    if (ep.x == 0.0 && ep.y == 0.0) fl[2] = 1;
+  }
+}
+
 __global__ void k_check_finite(const double* x, int64_t n, int* flags) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n && !isfinite(x[i])) atomicOr(flags, 1);
@@ -923,14 +947,9 @@ __global__ void k_xupdate(const DomDev* __restrict__ doms, const ColDev* __restr
   x[C.off + i] = v;
 }
 
-// copies of small device results into host-mapped memory (read by the host
-// after a stream synchronisation)
-__global__ void k_publish_ints(const int* __restrict__ src, int n, int* __restrict__ dst) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i];
-}
-
-// cycle start (and end of a solve): dst[0] = iterating columns, dst[1 + c] =
+// copy of the GMRES state into host-mapped memory (read by the host after a
+// stream synchronisation) at a cycle start (and the end of a solve):
+// dst[0] = iterating columns, dst[1 + c] =
 // converged flags, dst[1 + ncol + c] = inner iterations, rel[c] = true
 // relative residual, rel[ncol + c] = residual estimate
 __global__ void k_publish_cycle(GmresState st, int ncol, int* __restrict__ dst, double* __restrict__ rel) {
