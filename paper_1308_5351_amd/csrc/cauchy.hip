@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((NR <= 2 &
                             (gptr<const double4>)D.sbf, (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N,
                             (gptr<const double2>)D.tz, D.Nt, rec_stride(wcols), rec32_stride(wcols), wcols, col0,
                             width,
-                            w.y * 64 * TPT, w.y, w.z, j0, j1, D.far2, red);
+                            w.y * 64 * TPT, w.y, w.z, j0, j1, MIXED ? D.far2 : D.far2d, red);
 }
 
 // Far tiles of one item (the items of an M_NEAR launch, 4 or 8 columns) on

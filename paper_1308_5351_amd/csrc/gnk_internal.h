@@ -66,6 +66,7 @@ struct DomDev {
                      // points), or null: the targets are the nodes themselves
   int Nt;            // number of those targets
   double far2;       // mixed precision: far when |c_t - c_s|^2 > far2 (r_t + r_s)^2
+  double far2d;      // FP64 far form: far when |c_t - c_s|^2 > far2d (r_t + r_s)^2
   int N, n, m1;
   int ncols;         // real columns of the domain
   int c0;            // first global column index

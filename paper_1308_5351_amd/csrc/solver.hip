@@ -443,6 +443,11 @@ void build_batch(gnk_ctx* c, Batch& B, int ndom, const gnk_domain* doms, const i
     D.tb = tb ? tb + otb : nullptr;
     D.sbf = sbf + osbf;
     D.far2 = (1.0 + theta) * (1.0 + theta);
+    // The FP64 far form sums conj(z') w m - b m about the source tile's centre
+    // (exact algebra); separation only bounds how much rounding the two terms'
+    // cancellation and the expanded |z' - v|^2 amplify: (2 + t)/t and its
+    // square for separation (1 + t)(r_t + r_s), 25 at t = 0.5.
+    D.far2d = 2.25;
     on += D.N;
     orc += (int64_t)D.N * rec_stride(D.ncols + 1);
     orc32 += (int64_t)D.N * rec32_stride(D.ncols + 1);
