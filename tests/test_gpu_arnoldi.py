@@ -1,0 +1,111 @@
+"""The device-resident Arnoldi step on cases that its blocking and the host's
+launch pipeline make special (GPU, through the C ABI), against the oracle.
+
+* Component means (the P-hat term of FBIEad, eq. (e:sys*)) are added up from
+  per-chunk partial sums: many short components per chunk, components that
+  straddle two chunks, several columns, FP64 and mixed products.
+* A cached step graph is replayed for a later solve whose kernel arguments are
+  all equal (same shapes, so the same workspace): a different domain of the
+  same size in between must not leak into the results.
+* A zero right-hand side next to nonzero ones: the first cycle starts without
+  the host reading the cycle-start state, and that column takes no step.
+
+Tolerance: relative L-infinity 1e-10 (error / max(|ref|, |gamma|)).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import nystrom as orc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gk():
+    from paper_1308_5351_amd import gnk
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return gnk
+
+
+@pytest.fixture(scope="module")
+def ctx(gk):
+    c = gk.Context(0)
+    yield c
+    c.close()
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _grid_circles(n, rows, cols, spacing, radius, shift=0j):
+    centers = [shift + spacing * (c + 1j * r) for r in range(rows) for c in range(cols)]
+    return wl.circles_unbounded(n, centers, [radius] * len(centers))
+
+
+@pytest.mark.parametrize("n,rows,cols", [(24, 5, 6), (16, 5, 8), (300, 1, 3)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fbiead_component_means_across_chunks(gk, ctx, n, rows, cols, prec):
+    """n = 24 and 16: a chunk of 256 entries holds 10-16 components and cuts
+    through one at each end; n = 300: every component spans two chunks."""
+    dom = _grid_circles(n, rows, cols, 1.0, 0.3)
+    rng = np.random.default_rng([n, rows, cols])
+    gam = np.stack([(dom.eta ** 2).real, rng.normal(size=dom.N), np.ones(dom.N)], axis=1)
+    print(f"[means] n={n} m1={dom.m1} N={dom.N} {prec}", flush=True)
+    dd = gk.DeviceDomain.from_host(dom)
+    p = gk.MIXED if prec == "mixed" else gk.FP64
+    mu, infos, st = ctx.fbie_ad(dd, _cuda(gam), tol=1e-13, restart=40, prec=p)
+    ref = orc.fbiead(dom.eta, dom.etap, dom.etapp, dom.A, dom.Ap, gam, dom.n, dom.c)
+    err = orc.rel_linf(mu.cpu().numpy(), ref, np.max(np.abs(gam)))
+    print(f"  err {err:.2e} iterations {[i['inner_it'] for i in infos]}", flush=True)
+    assert st == 0 and err < 1e-10
+
+
+def test_step_graph_reused_across_domains(gk, ctx):
+    """Solves of two domains with equal shapes in the order A, B, A (each solve
+    after the first replays the cached step graph, its arguments all equal):
+    every result matches the oracle for its own domain."""
+    da = _grid_circles(64, 2, 3, 1.1, 0.35)
+    db = _grid_circles(64, 2, 3, 1.3, 0.4, shift=0.2 + 0.1j)
+    assert da.N == db.N and da.m1 == db.m1
+    refs = {}
+    for name, dom in (("A", da), ("B", db)):
+        gam = (dom.eta ** 2).real + 0.3 * dom.eta.imag
+        refs[name] = (dom, gam, orc.fbie(dom.eta, dom.etap, dom.A, gam, dom.n),
+                      orc.fbiead(dom.eta, dom.etap, dom.etapp, dom.A, dom.Ap, gam, dom.n, dom.c))
+    for name in ("A", "B", "A"):
+        dom, gam, (mu_o, h_o), ad_o = refs[name]
+        print(f"[reuse] domain {name}", flush=True)
+        dd = gk.DeviceDomain.from_host(dom)
+        g = _cuda(gam)
+        mu, h, _, st = ctx.fbie(dd, g, tol=1e-13)
+        ad, _, sta = ctx.fbie_ad(dd, g, tol=1e-13)
+        s = np.max(np.abs(gam))
+        e = (orc.rel_linf(mu.cpu().numpy(), mu_o, s), orc.rel_linf(h.cpu().numpy(), h_o, s),
+             orc.rel_linf(ad.cpu().numpy(), ad_o, s))
+        print(f"  err mu {e[0]:.2e} h {e[1]:.2e} fbiead {e[2]:.2e}", flush=True)
+        assert st == 0 and sta == 0 and max(e) < 1e-10
+
+
+def test_zero_column_takes_no_step(gk, ctx):
+    """gamma = 0 in one of three columns: that column is converged at the
+    first cycle start (no outer cycle, no Arnoldi step, mu = h = 0) while the
+    others match the oracle."""
+    dom = _grid_circles(96, 1, 3, 1.2, 0.4)
+    gam = np.stack([(dom.eta ** 2).real, np.zeros(dom.N), dom.eta.real], axis=1)
+    print("[zero column] fbie", flush=True)
+    dd = gk.DeviceDomain.from_host(dom)
+    mu, h, infos, st = ctx.fbie(dd, _cuda(gam), tol=1e-13)
+    mu_o, h_o = orc.fbie(dom.eta, dom.etap, dom.A, gam, dom.n)
+    print(f"  infos {infos}", flush=True)
+    assert st == 0
+    z = infos[1]
+    assert z["flag"] == 0 and z["outer_it"] == 0 and z["inner_it"] == 0
+    assert np.all(mu.cpu().numpy()[:, 1] == 0.0) and np.all(h.cpu().numpy()[:, 1] == 0.0)
+    for q in (0, 2):
+        assert infos[q]["outer_it"] >= 1 and infos[q]["inner_it"] >= 1
+        s = np.max(np.abs(gam[:, q]))
+        assert orc.rel_linf(mu.cpu().numpy()[:, q], mu_o[:, q], s) < 1e-10
+        assert orc.rel_linf(h.cpu().numpy()[:, q], h_o[:, q], s) < 1e-10
