@@ -508,9 +508,23 @@ void build_items(gnk_ctx* c, Batch& B, int p) {
       if ((int64_t)D.N * rec_stride(wcols) * (int64_t)sizeof(double2) > (int64_t)2 << 20) {
         for (int g = 0; g < D.splits; ++g)
           for (int t = 0; t < tiles; ++t) lists[wi].push_back(make_int4(d, t, g, code));
-      } else {
+      } else if (D.tz) {
         for (int t = 0; t < tiles; ++t)
           for (int g = 0; g < D.splits; ++g) lists[wi].push_back(make_int4(d, t, g, code));
+      } else {
+        // the items whose source range meets the target tile's own component
+        // (mostly near tiles, the costliest) go first, so that the cheap ones
+        // fill the end of the launch
+        std::vector<int4> rest;
+        for (int t = 0; t < tiles; ++t) {
+          const int64_t c0 = (int64_t)(t * tile / D.n) * D.n;
+          const int64_t c1 = std::min<int64_t>(D.N, ((int64_t)(std::min(D.N, (t + 1) * tile) - 1) / D.n + 1) * D.n);
+          for (int g = 0; g < D.splits; ++g) {
+            const int64_t a0 = (int64_t)g * D.chunk, a1 = std::min<int64_t>(D.N, a0 + D.chunk);
+            (std::max(a0, c0) < std::min(a1, c1) ? lists[wi] : rest).push_back(make_int4(d, t, g, code));
+          }
+        }
+        lists[wi].insert(lists[wi].end(), rest.begin(), rest.end());
       }
       r0 += w;
     }
