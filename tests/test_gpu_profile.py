@@ -46,8 +46,8 @@ def test_profile_separates_circulant_products(gk, ctx):
 
 
 def test_profile_leaves_out_speculative_steps(gk, ctx):
-    # GMRES runs a few fully masked steps after its column stops (two steps per graph
-    # launch, one launch ahead); the profile counts only the products that do work, so
+    # GMRES runs a few fully masked steps after its column stops (up to four steps per
+    # graph launch, one launch ahead); the profile counts only the products that do work, so
     # products minus Arnoldi steps is the same for solves of different lengths
     dom, gam = wl.config1(n=256)
     dd = gk.DeviceDomain.from_host(dom)
