@@ -97,7 +97,8 @@ __global__ void k_box_centres(const double4* __restrict__ bbox, int nbox, double
 }
 
 struct LevelTable {
-  int off[32];
+  int off[32];   // first box of each level
+  int nb[32];    // boxes of each level
 };
 
 __global__ __launch_bounds__(256) void k_box_radii(const double2* __restrict__ eta, int N, LevelTable lv, int levels,
@@ -170,35 +171,65 @@ __global__ __launch_bounds__(64) void k_leaf_moments(const double2* __restrict__
   }
 }
 
-// Moments of the parents (level l + 1, boxes par0 .. par0 + npar - 1 of the
-// global numbering) from their children (level l, from child0, nchild of
-// them): a_k(parent) = sum over children sum_{q <= k} C(k, q) a_q(child) d^(k-q),
-// d = c_child - c_parent. One thread per (parent, k).
-__global__ void k_m2m(const double4* __restrict__ bounds, int child0, int nchild, int par0, int npar, int p,
-                      double2* __restrict__ mom) {
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= npar * p) return;
-  const int b = tid / p, k = tid - b * p;
-  const double4 cp = bounds[par0 + b];
-  double ax = 0.0, ay = 0.0;
-  for (int ch = 2 * b; ch < min(2 * b + 2, nchild); ++ch) {
-    const double4 cc = bounds[child0 + ch];
-    const double ddx = cc.x - cp.x, ddy = cc.y - cp.y;
-    const double2* a = mom + (size_t)(child0 + ch) * p;
-    // sum over q = k down to 0 of C(k, q) a_q d^(k - q)
-    double px = 1.0, py = 0.0, binom = 1.0;
+// Moments of levels l0 + 1 .. l0 + nlev from those of level l0 in one launch:
+// a_k(parent) = sum over its two children sum_{q <= k} C(k, q) a_q(child) d^(k-q),
+// d = c_child - c_parent. One workgroup per box B of level l0 + nlev takes the
+// boxes of its subtree level by level (at most 2^kM2MLevels of the lowest),
+// the children's moments of each level in LDS, one thread per (parent, k).
+// C(k, q) comes from a table that the workgroup fills first (integers below
+// 2^53, exact). Each parent's sums run in the same order whatever the
+// grouping of levels.
+constexpr int kM2MLevels = 4;
+constexpr int kM2MThreads = 512;
+
+__global__ __launch_bounds__(kM2MThreads) void k_m2m_levels(const double4* __restrict__ bounds, LevelTable lt,
+                                                            int l0, int nlev, int p, double2* __restrict__ mom) {
+  __shared__ double2 sm[2][(1 << kM2MLevels) * kTreeMaxP];
+  __shared__ double binom[kTreeMaxP][kTreeMaxP];
+  const int B = blockIdx.x;
+  for (int k = threadIdx.x; k < p; k += blockDim.x) {
+    double c = 1.0;   // C(k, k), then C(k, q - 1) from C(k, q)
     for (int q = k; q >= 0; --q) {
-      const double2 aq = a[q];
-      const double tx = aq.x * px - aq.y * py, ty = aq.x * py + aq.y * px;
-      ax = __builtin_fma(binom, tx, ax);
-      ay = __builtin_fma(binom, ty, ay);
-      const double nx = px * ddx - py * ddy;
-      py = px * ddy + py * ddx;
-      px = nx;
-      binom = binom * (double)q / (double)(k - q + 1);   // C(k, q - 1) from C(k, q)
+      binom[k][q] = c;
+      c = c * (double)q / (double)(k - q + 1);
     }
   }
-  mom[(size_t)(par0 + b) * p + k] = make_double2(ax, ay);
+  int c0 = B << nlev;   // first box of the subtree at the child level
+  int cnt = min(lt.nb[l0] - c0, 1 << nlev);
+  for (int i = threadIdx.x; i < cnt * p; i += blockDim.x) sm[0][i] = mom[(size_t)(lt.off[l0] + c0) * p + i];
+  __syncthreads();
+  int cur = 0;
+  for (int lev = 1; lev <= nlev; ++lev) {
+    const int l = l0 + lev;
+    const int p0 = B << (nlev - lev);
+    const int np = min(lt.nb[l] - p0, 1 << (nlev - lev));
+    for (int tid = threadIdx.x; tid < np * p; tid += blockDim.x) {
+      const int b = tid / p, k = tid - b * p;
+      const double4 cp = bounds[lt.off[l] + p0 + b];
+      double ax = 0.0, ay = 0.0;
+      for (int ch = 2 * b; ch < min(2 * b + 2, cnt); ++ch) {
+        const double4 cc = bounds[lt.off[l - 1] + c0 + ch];
+        const double ddx = cc.x - cp.x, ddy = cc.y - cp.y;
+        const double2* a = &sm[cur][ch * p];
+        double px = 1.0, py = 0.0;
+        for (int q = k; q >= 0; --q) {
+          const double2 aq = a[q];
+          const double tx = aq.x * px - aq.y * py, ty = aq.x * py + aq.y * px;
+          ax = __builtin_fma(binom[k][q], tx, ax);
+          ay = __builtin_fma(binom[k][q], ty, ay);
+          const double nx = px * ddx - py * ddy;
+          py = px * ddy + py * ddx;
+          px = nx;
+        }
+      }
+      sm[cur ^ 1][b * p + k] = make_double2(ax, ay);
+      mom[(size_t)(lt.off[l] + p0 + b) * p + k] = make_double2(ax, ay);
+    }
+    __syncthreads();
+    cur ^= 1;
+    c0 = p0;
+    cnt = np;
+  }
 }
 
 // One workgroup per (target tile, split): wave wv takes the entries
@@ -368,12 +399,18 @@ hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, co
   k_leaf_moments<<<level_nb[0], 64, 0, st>>>(rec, stride, wo, N, bounds, perm, p, mom);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int l = 0; l + 1 < levels; ++l) {
-    const int npar = level_nb[l + 1];
-    const int threads = npar * p;
-    k_m2m<<<(threads + 255) / 256, 256, 0, st>>>(bounds, level_off[l], level_nb[l], level_off[l + 1], npar, p, mom);
+  if (levels > 32 || p > kTreeMaxP) return hipErrorInvalidValue;
+  LevelTable lt{};
+  for (int l = 0; l < levels; ++l) {
+    lt.off[l] = level_off[l];
+    lt.nb[l] = level_nb[l];
+  }
+  for (int l = 0; l + 1 < levels;) {
+    const int nlev = min(kM2MLevels, levels - 1 - l);
+    k_m2m_levels<<<level_nb[l + nlev], kM2MThreads, 0, st>>>(bounds, lt, l, nlev, p, mom);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    l += nlev;
   }
   return hipSuccess;
 }
