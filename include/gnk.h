@@ -154,12 +154,13 @@ typedef struct {
 
 /* Per right-hand side outcome (host memory, one entry per column).
  *   flag        : 0 converged, 1 not converged
- *   outer_it    : restart cycles used;  inner_it: total Arnoldi steps
+ *   outer_it    : restart cycles used (0 for a column converged at the start, e.g. b = 0);
+ *                 inner_it: total Arnoldi steps
  *   relres      : GMRES residual estimate at exit
  *   true_relres : ||b - A x|| / ||b|| recomputed with an FP64 product
  *   mixed_steps : Arnoldi steps whose product used FP32 far tiles (GNK_MIXED); at most
  *                 inner_it, and in a solve that switches to mixed products part-way it
- *                 may include up to three speculative steps after the column stopped
+ *                 may include up to seven speculative steps after the column stopped
  *   refine_steps: GNK_MIXED: restart cycles of this column that took mixed products,
  *                 each followed by an FP64 residual (refinement steps); 0 for GNK_FP64
  *   hist_count  : entries written to this column's residual history (0 without one) */
