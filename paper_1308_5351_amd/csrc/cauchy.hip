@@ -496,7 +496,10 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
             x += p.x;
             y += p.y;
           }
-          part[o] = make_double2(x, y);
+          // streamed past the L2 (read once, by the epilogue), so that the
+          // source and target records stay there
+          typedef double nt2 __attribute__((ext_vector_type(2)));
+          __builtin_nontemporal_store(nt2{x, y}, (gptr<nt2>)(part + o));
         }
       }
     }
