@@ -46,8 +46,8 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # KiB, the factors from a 256 MiB copy of known size; profiles/*_hbm_counters.md).
 # Valid only for that N and the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "pair_steps.inl", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "168baad3aecd5aa5fcd38817047b899c5d8263de9797bb880f21174aa508c047",
-                "N": 264192, "bytes_per_launch": 676641518}
+                "sha256": "2136a39d9d9622684aef020bca1afe53d0a2e36f3039aafbe09c0fa3342a8540",
+                "N": 264192, "bytes_per_launch": 518437546}
 
 
 def pair_traffic(N):

@@ -309,8 +309,9 @@ __device__ __forceinline__ void far_tile_mfma(f32x16 (&acc)[2], const float (&ux
 // MFMA accumulators do not share a register file).
 enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2, M_EXT = 3 };
 
-// One work item: the tile of 64*TPT targets starting at `base`, a range of
-// sources of the domain, weight columns col0 .. col0+NR-1. The four
+// One work item: the tile of 64*TPT targets pts[base ..] (the nodes, read from
+// their own 16-byte array rather than the records, or for M_EXT the separate
+// points), a range of sources of the domain, weight columns col0 .. col0+NR-1. The four
 // wavefronts of the workgroup take consecutive parts [j0, j1) of the range;
 // their sums are added through LDS in wave order. MIXED: far source tiles of 64
 // nodes are summed in FP32 (see above). All pointers are restrict-qualified
@@ -319,7 +320,7 @@ enum : int { M_FP64 = 0, M_MIXED = 1, M_NEAR = 2, M_EXT = 3 };
 template <int NR, int TPT, int MODE>
 __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const float2> rec32, gptr<const double4> sb,
                                           gptr<const double4> sbf, gptr<const double4> tb, gptr<double2> part, int N,
-                                          gptr<const double2> tz, int Nt, int stride, int stride32, int wcols,
+                                          gptr<const double2> pts, int Nt, int stride, int stride32, int wcols,
                                           int col0, int width, int base, int tile_idx, int g, int j0, int j1,
                                           double far2, double (&red)[3][TPT][2][64]) {
   constexpr int kTile = 64 * TPT;
@@ -328,7 +329,7 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
   const int wo32 = 2 + col0;          // FP32 record: weights of the item's first column
   const int wb32 = 2 + wcols + col0;  // FP32 record: its b = w conj(v)
   constexpr bool MIXED = MODE == M_MIXED || MODE == M_NEAR;
-  // M_EXT: FP64 with targets tz[0..Nt) that are not nodes (no j != i window)
+  // M_EXT: FP64 with targets pts[0..Nt) that are not nodes (no j != i window)
   constexpr bool EXT = MODE == M_EXT;
   const int NT = EXT ? Nt : N;
   const int lane = threadIdx.x & 63;
@@ -339,8 +340,7 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
     ti[t] = base + t * 64 + lane;
-    if constexpr (EXT) tg[t] = tz[min(ti[t], NT - 1)];
-    else tg[t] = rec[(size_t)min(ti[t], N - 1) * stride];
+    tg[t] = pts[min(ti[t], NT - 1)];
   }
   Acc<NR, TPT> acc;
 #pragma unroll
@@ -546,7 +546,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((NR <= 2 &
   const int j1 = min(jb1, j0 + wchunk);
   pair_item<NR, TPT, MODE>((gptr<const double2>)D.rec, (gptr<const float2>)D.rec32, (gptr<const double4>)D.sb,
                             (gptr<const double4>)D.sbf, (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N,
-                            (gptr<const double2>)D.tz, D.Nt, rec_stride(wcols), rec32_stride(wcols), wcols, col0,
+                            (gptr<const double2>)(MODE == M_EXT ? D.tz : D.eta), MODE == M_EXT ? D.Nt : D.N,
+                            rec_stride(wcols), rec32_stride(wcols), wcols, col0,
                             width,
                             w.y * 64 * TPT, w.y, w.z, j0, j1, MIXED ? D.far2 : D.far2d, red);
 }
@@ -559,8 +560,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((NR <= 2 &
 // threads write the complex outputs to the partial sums (the M_NEAR launch
 // that follows adds the near tiles).
 template <int NR, int TPT>
-__device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const float2> far32, gptr<const double4> sb,
-                                         gptr<const double4> tb, gptr<double2> part, int N, int stride,
+__device__ __forceinline__ void far_item(gptr<const double2> eta, gptr<const float2> far32, gptr<const double4> sb,
+                                         gptr<const double4> tb, gptr<double2> part, int N,
                                          int wcols, int col0, int width, int base, int tile_idx, int g, int jb0,
                                          int jb1, double far2, double (*fl)[64][17], float* stg) {
   const int lane = threadIdx.x & 63;
@@ -576,7 +577,7 @@ __device__ __forceinline__ void far_item(gptr<const double2> rec, gptr<const flo
     // 32q + j of the slot is held by the lanes j and j + 32
     float ux[2], uy[2];
     {
-      const double2 tg = rec[(size_t)min(base + t * 64 + lane, N - 1) * stride];
+      const double2 tg = eta[min(base + t * 64 + lane, N - 1)];
       const float fx = (float)((tg.x - tbd.x) * inv_r), fy = (float)((tg.y - tbd.y) * inv_r);
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -688,8 +689,8 @@ __global__ __launch_bounds__(256) void k_far(const DomDev* __restrict__ doms, co
   const int chunk = D.chunk;
   const int jb0 = w.z * chunk;
   const int jb1 = min(D.N, jb0 + chunk);
-  far_item<NR, TPT>((gptr<const double2>)D.rec, (gptr<const float2>)D.far32, (gptr<const double4>)D.sb,
-                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, rec_stride(wcols), wcols,
+  far_item<NR, TPT>((gptr<const double2>)D.eta, (gptr<const float2>)D.far32, (gptr<const double4>)D.sb,
+                    (gptr<const double4>)D.tb, (gptr<double2>)D.parts, D.N, wcols,
                     col0, width, w.y * 64 * TPT, w.y, w.z, jb0, jb1, D.far2, fl, stg);
 }
 

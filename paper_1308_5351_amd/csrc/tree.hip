@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 #pragma unroll
   for (int t = 0; t < TPT; ++t) {
     ti[t] = base + t * 64 + lane;
-    tg[t] = ext ? D.tz[min(ti[t], NT - 1)] : rec[(size_t)min(ti[t], N - 1) * stride];
+    tg[t] = ext ? D.tz[min(ti[t], NT - 1)] : D.eta[min(ti[t], N - 1)];
   }
   Acc<1, TPT> acc;
 #pragma unroll
