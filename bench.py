@@ -46,7 +46,7 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # KiB, the factors from a 256 MiB copy of known size; profiles/*_hbm_counters.md).
 # Valid only for that N and the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "pair_steps.inl", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "2136a39d9d9622684aef020bca1afe53d0a2e36f3039aafbe09c0fa3342a8540",
+                "sha256": "0893a94de840036bf7980a8e4bcf10574b51bd12397abc110aa321e148dfe8b9",
                 "N": 264192, "bytes_per_launch": 518437546}
 
 

@@ -46,9 +46,11 @@ namespace {
 // b_j = w_j conj(eta'_j) taken from the record: per pair two FMAs per part
 // and no product for q. The squared distance comes from the record's
 // u_j = -2 eta'_j and a_j = |eta'_j|^2 and the target's |z'|^2 as
-// a_j + |z'|^2 + u_j . z' (one add, two FMAs). The tile pair is far, so
-// |z'| > 2 |eta'_j|: the sums do not cancel, and |z' - eta'_j|^2 is at least a
-// fifth of a_j + |z'|^2, so the distance keeps all but a few bits.
+// a_j + |z'|^2 + u_j . z' (one add, two FMAs). The tile pair is far (centres
+// more than 1.5 (r_t + r_s) apart), so |z'| > 1.5 |eta'_j|: |z' - eta'_j|^2 is
+// at least a thirteenth of a_j + |z'|^2 and the distance keeps all but about
+// four bits; |z'| + |eta'_j| is at most five times |z' - eta'_j|, which bounds
+// the cancellation of conj(z') A against B the same way.
 template <int NR, int TPT>
 struct AccAB {
   double ax[TPT][NR], ay[TPT][NR], bx[TPT][NR], by[TPT][NR];
