@@ -9,6 +9,8 @@ launch pipeline make special (GPU, through the C ABI), against the oracle.
   same size in between must not leak into the results.
 * A zero right-hand side next to nonzero ones: the first cycle starts without
   the host reading the cycle-start state, and that column takes no step.
+* Cycles of every length from 1 to 7 steps (graphs of four, two and one steps;
+  the step index alternates between two words).
 
 Tolerance: relative L-infinity 1e-10 (error / max(|ref|, |gamma|)).
 """
@@ -109,3 +111,26 @@ def test_zero_column_takes_no_step(gk, ctx):
         s = np.max(np.abs(gam[:, q]))
         assert orc.rel_linf(mu.cpu().numpy()[:, q], mu_o[:, q], s) < 1e-10
         assert orc.rel_linf(h.cpu().numpy()[:, q], h_o[:, q], s) < 1e-10
+
+
+@pytest.mark.parametrize("restart", [1, 2, 3, 5, 6, 7])
+def test_every_cycle_length(gk, ctx, restart):
+    """Cycles of 1 to 7 steps: step graphs of four, two and one steps, cycles
+    that end on an even or an odd step index (the two words the step index
+    alternates between), FBIE and FBIEad against the oracle."""
+    dom = _grid_circles(64, 1, 2, 1.2, 0.4)
+    gam = (dom.eta ** 2).real + 0.5 * dom.eta.imag
+    mu_o, h_o = orc.fbie(dom.eta, dom.etap, dom.A, gam, dom.n)
+    ad_o = orc.fbiead(dom.eta, dom.etap, dom.etapp, dom.A, dom.Ap, gam, dom.n, dom.c)
+    print(f"[cycle length] restart {restart}", flush=True)
+    dd = gk.DeviceDomain.from_host(dom)
+    g = _cuda(gam)
+    mu, h, infos, st = ctx.fbie(dd, g, tol=1e-12, restart=restart, maxit=600)
+    ad, infa, sta = ctx.fbie_ad(dd, g, tol=1e-12, restart=restart, maxit=600)
+    s = np.max(np.abs(gam))
+    e = (orc.rel_linf(mu.cpu().numpy(), mu_o, s), orc.rel_linf(h.cpu().numpy(), h_o, s),
+         orc.rel_linf(ad.cpu().numpy(), ad_o, s))
+    print(f"  cycles {infos[0]['outer_it']}/{infa[0]['outer_it']} steps {infos[0]['inner_it']}/"
+          f"{infa[0]['inner_it']} err mu {e[0]:.2e} h {e[1]:.2e} fbiead {e[2]:.2e}", flush=True)
+    assert st == 0 and sta == 0 and max(e) < 1e-10
+    assert infos[0]["inner_it"] <= restart * infos[0]["outer_it"]
