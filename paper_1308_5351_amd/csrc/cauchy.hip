@@ -748,37 +748,38 @@ __global__ __launch_bounds__(64) void k_node_tile_bounds(const DomDev* __restric
 // the FP64 records (head, w.., b..), and the far-tile sources of the matrix
 // cores (eta_j - c_s unscaled, and the weights by 8-column block)
 __global__ void k_records32(const DomDev* __restrict__ doms, int lead, int data) {
+  // one thread per (node, weight column), the columns padded to a multiple of
+  // 8 where the matrix-core sources are kept, so that the consecutive lanes of
+  // a wave read and write consecutive fields
   const DomDev& D = doms[blockIdx.y];
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= D.N) return;
   const int wcols = lead + data * D.ncols;
+  const int Q = D.far32 != nullptr ? (wcols + 7) / 8 * 8 : wcols;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)D.N * Q) return;
+  const int j = (int)(t / Q), q = (int)(t - (int64_t)j * Q);
   const double2* r = D.rec + (size_t)j * rec_stride(wcols);
   float2* o = D.rec32 + (size_t)j * rec32_stride(wcols);
   const double4 c = D.sb[j >> 6];
-  const float2 v = make_float2((float)(r[0].x - c.x), (float)(r[0].y - c.y));
+  const double dx = r[0].x - c.x, dy = r[0].y - c.y;
   const double inv_r = 1.0 / c.z;
-  const float2 vs = make_float2((float)((r[0].x - c.x) * inv_r), (float)((r[0].y - c.y) * inv_r));
+  const float2 vs = make_float2((float)(dx * inv_r), (float)(dy * inv_r));
   const double vx = vs.x, vy = vs.y;
-  o[0] = vs;
-  o[1] = make_float2((float)(vx * vx + vy * vy), 0.f);
-  for (int q = 0; q < wcols; ++q) {
+  if (q == 0) {
+    o[0] = vs;
+    o[1] = make_float2((float)(vx * vx + vy * vy), 0.f);
+  }
+  float2 w32 = make_float2(0.f, 0.f);
+  if (q < wcols) {
     const double2 w = r[kRecHead + q];
-    o[2 + q] = make_float2((float)w.x, (float)w.y);
+    w32 = make_float2((float)w.x, (float)w.y);
+    o[2 + q] = w32;
     o[2 + wcols + q] = make_float2((float)(w.x * vx + w.y * vy), (float)(w.y * vx - w.x * vy));
   }
   if (D.far32 != nullptr) {
     const int ntl = (D.N + 63) / 64;
-    for (int gb = 0; gb < (wcols + 7) / 8; ++gb) {
-      float2* f = D.far32 + ((size_t)(gb * ntl + (j >> 6)) * kFar32Fields) * 64 + (j & 63);
-      f[0] = v;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int col = 8 * gb + q;
-        float2 w = make_float2(0.f, 0.f);
-        if (col < wcols) w = make_float2((float)r[kRecHead + col].x, (float)r[kRecHead + col].y);
-        f[64 * (1 + q)] = w;
-      }
-    }
+    float2* f = D.far32 + ((size_t)((q >> 3) * ntl + (j >> 6)) * kFar32Fields) * 64 + (j & 63);
+    if ((q & 7) == 0) f[0] = make_float2((float)dx, (float)dy);
+    f[64 * (1 + (q & 7))] = w32;
   }
 }
 
@@ -881,8 +882,8 @@ hipError_t launch_node_tile_bounds(const DomDev* doms, int ndom, int maxN, int t
   return hipGetLastError();
 }
 
-hipError_t launch_records32(const DomDev* doms, int ndom, int maxN, int lead, int data, hipStream_t st) {
-  dim3 grid((unsigned)((maxN + 255) / 256), (unsigned)ndom);
+hipError_t launch_records32(const DomDev* doms, int ndom, int64_t threads, int lead, int data, hipStream_t st) {
+  dim3 grid((unsigned)((threads + 255) / 256), (unsigned)ndom);
   k_records32<<<grid, 256, 0, st>>>(doms, lead, data);
   return hipGetLastError();
 }

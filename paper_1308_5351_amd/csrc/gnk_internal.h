@@ -123,8 +123,9 @@ hipError_t launch_tree_moments(const double2* rec, int stride, int wo, int N, co
 hipError_t launch_tree_eval(const DomDev* doms, int tiles, int tpt, const int* seg, const int* list,
                             const double4* bounds, const double2* mom, int p, int splits, int col, int wcols,
                             const int* active, int lead, bool ext, hipStream_t st);
-// FP32 records from the FP64 records of every domain
-hipError_t launch_records32(const DomDev* doms, int ndom, int maxN, int lead, int data, hipStream_t st);
+// FP32 records from the FP64 records of every domain; threads: the largest
+// N_d * (weight columns rounded up to a multiple of 8) over the domains
+hipError_t launch_records32(const DomDev* doms, int ndom, int64_t threads, int lead, int data, hipStream_t st);
 
 // One block length of a circulant product: nvec length-n vectors at the flat
 // offsets offs; tw the twiddle table of n (or the direct product's column).

@@ -820,6 +820,17 @@ void tree_pairs(gnk_ctx* c, Batch& B, int p, const int* active) {
   }
 }
 
+// threads of k_records32 for pattern p: one per node and weight column, the
+// columns rounded up to a multiple of 8, for the largest domain of the batch
+int64_t records32_threads(const Batch& B, int p) {
+  int64_t t = 0;
+  for (const DomDev& D : B.dom) {
+    const int wc = kLead[p] + kData[p] * D.ncols;
+    t = std::max(t, (int64_t)D.N * ((wc + 7) / 8 * 8));
+  }
+  return t;
+}
+
 // All Cauchy sums of a pattern for the batch (one launch per column-group width).
 void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
   if (B.tree.on && !mixed) {
@@ -829,7 +840,7 @@ void pairs(gnk_ctx* c, Batch& B, int p, bool mixed, const int* active) {
   if (mixed && p == P_GM) p = P_GM_MIXED;
   build_items(c, B, p);
   auto& S = B.sets[p];
-  if (mixed) HIPCHK(c, launch_records32(B.d_dom, B.ndom, B.maxN, kLead[p], kData[p], c->stream));
+  if (mixed) HIPCHK(c, launch_records32(B.d_dom, B.ndom, records32_threads(B, p), kLead[p], kData[p], c->stream));
   gnk_ctx::ProfRec pr{};
   if (c->prof) {
     pr = gnk_ctx::ProfRec{pool_event(c), pool_event(c), S.pair_cols, S.flops, S.pairs1, mixed,
@@ -1205,6 +1216,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     for (int q = 0; q < 4; ++q) { pt(IS.d[q]); u((uint64_t)IS.cnt[q]); }
     u((uint64_t)B.shape.tpt); pt(B.d_dom); pt(B.d_col); u((uint64_t)B.ndom); u((uint64_t)B.maxN);
     u((uint64_t)(B.dom[0].tz != nullptr));
+    u((uint64_t)records32_threads(B, use_mixed ? P_GM_MIXED : P_GM));
     for (const void* q : {(const void*)st.bnorm, (const void*)st.true_relres, (const void*)st.relres,
                           (const void*)st.invbeta, (const void*)st.H, (const void*)st.cs, (const void*)st.sn,
                           (const void*)st.g, (const void*)st.y, (const void*)st.active, (const void*)st.converged,
