@@ -1063,8 +1063,13 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
   const int64_t T = B.T;
   const int restart = o.restart;
   const int ldp = restart + 1;
-  // vector-kernel blocking: 256..kMaxChunk elements per block, about 256 blocks
-  const int per_blk = (int)std::max<int64_t>(kT, std::min<int64_t>(kMaxChunk, ((int64_t)B.maxN + 255) / 256));
+  // vector-kernel blocking: 256..kMaxChunk elements per block, about 256
+  // blocks per column of the largest domain, or fewer per column when the
+  // batch's columns give more than about 8192 blocks together (each block
+  // sums its column's block partials, so fewer blocks per column also means
+  // less of that)
+  const int per_blk = (int)std::max<int64_t>(
+      kT, std::min<int64_t>(kMaxChunk, std::max<int64_t>(((int64_t)B.maxN + 255) / 256, (T + 8191) / 8192)));
   const int nblk = (B.maxN + per_blk - 1) / per_blk;
 
   double* V = ws<double>(c, "V", (size_t)(restart + 1) * T);
