@@ -1187,7 +1187,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     k_gs_update<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, P1, P2, ldp, sl);
     LAUNCHCHK(c);
     k_gs_finish<<<gv, kT, 0, c->stream>>>(B.d_dom, B.d_col, V, T, per_blk, P2, ldp, sl, next, restart, stop_tol,
-                                          host_live, (mixed || want_hist) ? host_rel : nullptr, form.cw, mpart, S);
+                                          host_live, host_rel, form.cw, mpart, S);
     LAUNCHCHK(c);
   };
   // Every buffer the step touches exists before a capture (no allocation,
@@ -1231,7 +1231,7 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     u((uint64_t)st.ldh); u((uint64_t)st.hstride);
     pt(V); u((uint64_t)T); u((uint64_t)per_blk); u((uint64_t)nblk); u((uint64_t)ncol); pt(P1); pt(P2);
     u((uint64_t)ldp); pt(step_odd); u((uint64_t)restart); fp(stop_tol); pt(host_live);
-    pt((mixed || want_hist) ? host_rel : nullptr);
+    pt(host_rel);
     u((uint64_t)form.cw); u((uint64_t)form.cout); u((uint64_t)form.dsel); fp(form.a0); fp(form.dsign); fp(form.cI);
     fp(form.cR); pt(mpart); u((uint64_t)S); pt(c->stream);
     return sg;
@@ -1367,6 +1367,13 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
     // run (fully masked) after the last column stops.
     step_recs.clear();
     bool cycle_mixed = false;
+    // The host also tracks the largest residual estimate of the steps it
+    // reads: when the estimates' geometric rate over its last two readings
+    // says that the launch just enqueued ends the cycle (every column at the
+    // stop tolerance), it waits for that launch instead of enqueuing another
+    // one of fully masked steps; a wrong guess costs a round trip.
+    double seen_rel = -1.0;
+    int seen_step = -1;
     // (l is even at every launch: its steps are the even-odd pairs of enqueue_step)
     for (int l = 0; l < restart;) {
       const bool use_mixed = mixed && mixed_now;
@@ -1382,11 +1389,19 @@ GmresOut gmres(gnk_ctx* c, Batch& B, int op, const double* b, const gnk_opts& o,
       if (prev >= 0) {
         HIPCHK(c, hipEventSynchronize(c->step_ev[prev]));
         if (c->pinned[prev] == 0) break;
-        if (mixed && !mixed_now && !refine_capped) {
-          double mx = 0.0;
-          for (int q = 0; q < ncol; ++q) mx = std::max(mx, c->pinned_rel[(size_t)prev * ncol + q]);
-          if (mx <= o.inner_tol) mixed_now = true;
+        double mx = 0.0;
+        for (int q = 0; q < ncol; ++q) mx = std::max(mx, c->pinned_rel[(size_t)prev * ncol + q]);
+        if (mixed && !mixed_now && !refine_capped && mx <= o.inner_tol) mixed_now = true;
+        if (seen_step >= 0 && mx > stop_tol && mx < seen_rel && l < restart) {
+          const double rate = std::log(mx / seen_rel) / (double)(prev - seen_step);   // per step, < 0
+          const double need = std::log(stop_tol / mx) / rate;                       // steps after prev
+          if (need <= (double)(l - 1 - prev)) {
+            HIPCHK(c, hipEventSynchronize(c->step_ev[l - 1]));
+            if (c->pinned[l - 1] == 0) break;
+          }
         }
+        seen_rel = mx;
+        seen_step = prev;
       }
     }
     if (c->prof && !step_recs.empty()) {
