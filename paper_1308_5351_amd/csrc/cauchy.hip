@@ -381,10 +381,12 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
   };
 
   bool any_near = false;
-  if constexpr (!MIXED && NR == 1) {
+  if constexpr (!MIXED && (NR == 1 || (NR == 2 && !EXT))) {
     // source tiles of kFarTile nodes (segments of them at the range ends): far
     // ones by the A/B form on coordinates relative to the tile centre, the
-    // rest as above
+    // rest as above (one column, or two with node targets: separate points in
+    // the caller's order seldom make far tiles, and the two-column far form
+    // needs more registers)
     const double4 tbd = tb[tile_idx];
     for (int ts = j0; ts < j1;) {
       const int te = min(((ts >> kFarTileLog2) + 1) << kFarTileLog2, j1);
@@ -512,10 +514,12 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 // One launch: one workgroup per item of the list. (A workgroup that looped
 // over several items would store partial sums before loading the next item's
 // records, and the records could then no longer be fetched with scalar loads.)
-// FP64 variants with one or two columns are held to 64 VGPRs (8 waves per
-// SIMD), which they reach without spilling; the others keep their registers.
+// The one-column variants (but M_NEAR) and the two-column one with separate
+// targets are held to 64 VGPRs (8 waves per SIMD), which they reach without
+// spilling; the two-column FP64 one, whose far form keeps A and B sums of
+// both columns, to 80 (6 waves); the others keep their registers.
 template <int NR, int TPT, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((NR <= 2 && (MODE == M_FP64 || MODE == M_EXT)) || (NR == 1 && MODE == M_MIXED)) ? 8 : 1))) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(((NR == 1 && MODE != M_NEAR) || (NR == 2 && MODE == M_EXT)) ? 8 : ((NR == 2 && MODE == M_FP64) ? 6 : 1)))) void k_pairs(const DomDev* __restrict__ doms, const int4* __restrict__ items,
                                                int nitems, int lead, int data, const int* __restrict__ active) {
   __shared__ double red[3][TPT][2][64];
   constexpr bool MIXED = MODE == M_MIXED || MODE == M_NEAR;
