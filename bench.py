@@ -600,7 +600,7 @@ def main():
                     help="end with a plain copy of 256 MiB (3 launches), the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
+        print("bench.py: the solver runs on one GPU (it has no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
