@@ -10,8 +10,10 @@
 //     field; eta' = eta - centre of the node's 64-node tile, b = w conj(eta'));
 //     the source loop index is wave-uniform, so whole records arrive with wide
 //     scalar loads into SGPRs and are broadcast to all lanes (no LDS traffic,
-//     no bank conflicts); four sources are fetched per iteration so one wait
-//     covers four reciprocals;
+//     no bank conflicts); near tiles fetch four sources per iteration so one
+//     wait covers four reciprocals; far tiles (FP64 far form) and the near
+//     tiles of 8-column mixed products take one source per step, with the
+//     next source's fields loading meanwhile;
 //   * each lane owns TPT target nodes (a tile of TPT*64 consecutive targets),
 //     which reuses every fetched source TPT times and gives independent chains;
 //   * the four wavefronts of a workgroup share the tile and split its source
@@ -21,9 +23,11 @@
 //     width, one workgroup per item (largest domains first); the consumer
 //     adds the split partial sums in a fixed order, so results are bitwise
 //     reproducible;
-//   * 1/|d|^2 comes from v_rcp_f64 refined by one Newton step; two sources
+//   * 1/|d|^2 comes from v_rcp_f64 refined by one Newton step; two pairs
 //     share one reciprocal: 1/a = b/(ab), 1/b = a/(ab) (simultaneous
-//     inversion), which halves the v_rcp_f64 issues;
+//     inversion), which halves the v_rcp_f64 issues; the pairs are two
+//     sources against one target, or, in the one-source steps, one source
+//     against the lane's two targets;
 //   * only the window of sources equal to the wave's own targets needs the
 //     j != i test; it runs a separate masked loop.
 #include <algorithm>
@@ -98,6 +102,73 @@ __device__ __forceinline__ void single_step_far(AccAB<NR, TPT>& acc, const doubl
     accumulate_ab<NR, TPT>(acc, t, r, wo, wb, refine_rcp(far_dist2(r, zx[t], zy[t], zz[t])));
 }
 
+
+// The far form with one source per step (TPT even): the lane's targets are
+// taken in twos that share one reciprocal (m_0 = d_1/(d_0 d_1)), and the next
+// source's fields (u, a, w, b: 7 + 4(NR - 1) doubles) load into scalar
+// registers during the step's arithmetic, issued after the current fields'
+// first use (scalar loads may return out of order, so the wait before that
+// use covers every scalar load issued before it).
+template <int NR>
+struct FarRec {
+  double2 u;
+  double a;
+  double2 w[NR], b[NR];
+};
+
+template <int NR, class P>
+__device__ __forceinline__ void load_far(FarRec<NR>& s, P r, int wo, int wb) {
+  s.u = r[1];
+  s.a = r[2].x;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    s.w[q] = r[wo + q];
+    s.b[q] = r[wb + q];
+  }
+}
+
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void stream_step_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT],
+                                                const double (&zy)[TPT], const double (&zz)[TPT],
+                                                const FarRec<NR>& s, FarRec<NR>& nx, P rn, int wo, int wb) {
+  double d[TPT];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) d[t] = __builtin_fma(s.u.x, zx[t], __builtin_fma(s.u.y, zy[t], s.a + zz[t]));
+  __builtin_amdgcn_sched_barrier(0);
+  load_far<NR>(nx, rn, wo, wb);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int t = 0; t < TPT; t += 2) {
+    const double R = refine_rcp(d[t] * d[t + 1]);
+    const double m[2] = {d[t + 1] * R, d[t] * R};
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        acc.ax[t + v][q] = __builtin_fma(s.w[q].x, m[v], acc.ax[t + v][q]);
+        acc.ay[t + v][q] = __builtin_fma(s.w[q].y, m[v], acc.ay[t + v][q]);
+        acc.bx[t + v][q] = __builtin_fma(s.b[q].x, m[v], acc.bx[t + v][q]);
+        acc.by[t + v][q] = __builtin_fma(s.b[q].y, m[v], acc.by[t + v][q]);
+      }
+  }
+}
+
+// sources [ja, jb) of a far tile; the last prefetch re-reads source jb - 1
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void stream_far(AccAB<NR, TPT>& acc, const double (&zx)[TPT], const double (&zy)[TPT],
+                                           const double (&zz)[TPT], P rec, int stride, int wo, int wb, int ja,
+                                           int jb) {
+  static_assert(TPT % 2 == 0, "targets are paired");
+  if (ja >= jb) return;
+  FarRec<NR> a, b;
+  load_far<NR>(a, rec + (size_t)ja * stride, wo, wb);
+  int j = ja;
+  for (; j + 1 < jb; j += 2) {
+    stream_step_far<NR, TPT>(acc, zx, zy, zz, a, b, rec + (size_t)(j + 1) * stride, wo, wb);
+    stream_step_far<NR, TPT>(acc, zx, zy, zz, b, a, rec + (size_t)min(j + 2, jb - 1) * stride, wo, wb);
+  }
+  if (j < jb) stream_step_far<NR, TPT>(acc, zx, zy, zz, a, b, rec + (size_t)j * stride, wo, wb);
+}
 
 // ---------------------------------------------------------------------------
 // Mixed precision: well-separated source tiles in FP32, the rest in FP64.
@@ -352,6 +423,10 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 
   // sources outside the tile's own window need no j != i test
   auto plain = [&](int ja, int jb) {
+    if constexpr (MODE == M_NEAR && NR >= 8 && TPT % 2 == 0) {
+      stream_range<NR, TPT>(acc, tg, rec, stride, wo, ja, jb);
+      return;
+    }
     int j = ja;
     for (; j + 3 < jb; j += 4) {
       gptr<const double2> r = rec + (size_t)j * stride;
@@ -404,14 +479,18 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 #pragma unroll
           for (int r = 0; r < NR; ++r) ab.ax[t][r] = ab.ay[t][r] = ab.bx[t][r] = ab.by[t][r] = 0.0;
         }
-        int j = ts;
-        // two sources per reciprocal: four records (u, a, w, b each) would not
-        // fit in the scalar registers of an 8-wave launch
-        for (; j + 1 < te; j += 2) {
-          gptr<const double2> r = rec + (size_t)j * stride;
-          pair_step_far<NR, TPT>(ab, zx, zy, zz, r, r + stride, wo, wb);
+        if constexpr (TPT % 2 == 0) {
+          stream_far<NR, TPT>(ab, zx, zy, zz, rec, stride, wo, wb, ts, te);
+        } else {
+          int j = ts;
+          // one target per lane: two sources per reciprocal (four records
+          // would not fit in the scalar registers of an 8-wave launch)
+          for (; j + 1 < te; j += 2) {
+            gptr<const double2> r = rec + (size_t)j * stride;
+            pair_step_far<NR, TPT>(ab, zx, zy, zz, r, r + stride, wo, wb);
+          }
+          for (; j < te; ++j) single_step_far<NR, TPT>(ab, zx, zy, zz, rec + (size_t)j * stride, wo, wb);
         }
-        for (; j < te; ++j) single_step_far<NR, TPT>(ab, zx, zy, zz, rec + (size_t)j * stride, wo, wb);
 #pragma unroll
         for (int t = 0; t < TPT; ++t)
 #pragma unroll

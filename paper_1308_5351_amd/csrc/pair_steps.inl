@@ -80,3 +80,78 @@ __device__ __forceinline__ void single_step(Acc<NR, TPT>& acc, const double2 (&t
     accumulate<NR, TPT>(acc, t, rj + wo, dx * r, -dy * r);
   }
 }
+
+// One source record held in scalar registers: its node and the launch's NR
+// weight columns.
+template <int NR>
+struct SrcRec {
+  double2 e;
+  double2 w[NR];
+};
+
+template <int NR, class P>
+__device__ __forceinline__ void load_src(SrcRec<NR>& s, P r, int wo) {
+  s.e = r[0];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) s.w[q] = r[wo + q];
+}
+
+// Source s against every target of the lane (TPT even). The lane's targets
+// are taken in twos that share one reciprocal: with R = 1/(|d0|^2 |d1|^2),
+// 1/|d0|^2 = R |d1|^2 and 1/|d1|^2 = R |d0|^2. The record of the following
+// source is loaded into nx (from rn) only after s has first been used: scalar
+// loads may return out of order, so the wait before a use of s covers every
+// scalar load issued before it, and a load issued earlier would be waited for
+// at once instead of during this step's arithmetic.
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void stream_step(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], const SrcRec<NR>& s,
+                                            SrcRec<NR>& nx, P rn, int wo) {
+  double dx[TPT], dy[TPT];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    dx[t] = tg[t].x - s.e.x;
+    dy[t] = tg[t].y - s.e.y;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  load_src<NR>(nx, rn, wo);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int t = 0; t < TPT; t += 2) {
+    const double d0 = __builtin_fma(dy[t], dy[t], dx[t] * dx[t]);
+    const double d1 = __builtin_fma(dy[t + 1], dy[t + 1], dx[t + 1] * dx[t + 1]);
+    const double R = refine_rcp(d0 * d1);
+    const double q0 = d1 * R, q1 = d0 * R;
+    const double qx[2] = {dx[t] * q0, dx[t + 1] * q1};
+    const double qy[2] = {-dy[t] * q0, -dy[t + 1] * q1};
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const double2 w = s.w[r];
+        acc.x[t + u][r] = __builtin_fma(w.x, qx[u], acc.x[t + u][r]);
+        acc.x[t + u][r] = __builtin_fma(-w.y, qy[u], acc.x[t + u][r]);
+        acc.y[t + u][r] = __builtin_fma(w.x, qy[u], acc.y[t + u][r]);
+        acc.y[t + u][r] = __builtin_fma(w.y, qx[u], acc.y[t + u][r]);
+      }
+  }
+}
+
+// Sources [ja, jb) (none of them a target of the lane) one at a time, the
+// next record in flight while the current one is summed: the near tiles of
+// 8-column mixed products (short runs of 64 sources between tile tests), whose
+// two records per step would fill the scalar registers and leave no room to
+// load ahead. The last prefetch re-reads source jb - 1.
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void stream_range(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], P rec, int stride, int wo,
+                                             int ja, int jb) {
+  static_assert(TPT % 2 == 0, "targets are paired");
+  if (ja >= jb) return;
+  SrcRec<NR> a, b;
+  load_src<NR>(a, rec + (size_t)ja * stride, wo);
+  int j = ja;
+  for (; j + 1 < jb; j += 2) {
+    stream_step<NR, TPT>(acc, tg, a, b, rec + (size_t)(j + 1) * stride, wo);
+    stream_step<NR, TPT>(acc, tg, b, a, rec + (size_t)min(j + 2, jb - 1) * stride, wo);
+  }
+  if (j < jb) stream_step<NR, TPT>(acc, tg, a, b, rec + (size_t)j * stride, wo);
+}
