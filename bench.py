@@ -46,8 +46,8 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # KiB, the factors from a 256 MiB copy of known size; profiles/*_hbm_counters.md).
 # Valid only for that N and the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "pair_steps.inl", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "aec5c11be741d829a32d9e2b06f8b804e42d4ff3bfa5b9dd966389b312f442bd",
-                "N": 264192, "bytes_per_launch": 518437055}
+                "sha256": "d4fd8278e0450ec679b8219296d97323acb6d203f520cc269c357739a3e21d18",
+                "N": 264192, "bytes_per_launch": 518435964}
 
 
 def pair_traffic(N):
