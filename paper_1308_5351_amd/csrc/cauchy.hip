@@ -11,9 +11,10 @@
 //     the source loop index is wave-uniform, so whole records arrive with wide
 //     scalar loads into SGPRs and are broadcast to all lanes (no LDS traffic,
 //     no bank conflicts); near tiles fetch four sources per iteration so one
-//     wait covers four reciprocals; far tiles (FP64 far form) and the near
-//     tiles of 8-column mixed products take one source per step, with the
-//     next source's fields loading meanwhile;
+//     wait covers four reciprocals; far tiles (FP64 far form: two sources per
+//     step with one column, one with two) and the near tiles of 8-column
+//     mixed products stream their sources, the next step's fields loading
+//     during the current step;
 //   * each lane owns TPT target nodes (a tile of TPT*64 consecutive targets),
 //     which reuses every fetched source TPT times and gives independent chains;
 //   * the four wavefronts of a workgroup share the tile and split its source
@@ -27,7 +28,9 @@
 //     share one reciprocal: 1/a = b/(ab), 1/b = a/(ab) (simultaneous
 //     inversion), which halves the v_rcp_f64 issues; the pairs are two
 //     sources against one target, or, in the one-source steps, one source
-//     against the lane's two targets;
+//     against the lane's two targets. The one-column far form and the
+//     near tiles with <= 2 columns share one reciprocal among four pairs
+//     (two sources and two targets, or four sources);
 //   * only the window of sources equal to the wave's own targets needs the
 //     j != i test; it runs a separate masked loop.
 #include <algorithm>
@@ -151,6 +154,84 @@ __device__ __forceinline__ void stream_step_far(AccAB<NR, TPT>& acc, const doubl
         acc.by[t + v][q] = __builtin_fma(s.b[q].y, m[v], acc.by[t + v][q]);
       }
   }
+}
+
+// Two sources per step: one reciprocal for the four pairs of two sources and
+// the lane's two targets (R = 1/(d00 d01 d10 d11), m00 = R d01 (d10 d11), ...;
+// the product stays in range while every squared distance lies in
+// [1e-75, 1e75]); the next two sources' fields load during the step.
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void stream_step_far2(AccAB<NR, TPT>& acc, const double (&zx)[TPT],
+                                                 const double (&zy)[TPT], const double (&zz)[TPT],
+                                                 const FarRec<NR>& s0, const FarRec<NR>& s1, FarRec<NR>& n0,
+                                                 FarRec<NR>& n1, P rn0, P rn1, int wo, int wb) {
+  double d0[TPT], d1[TPT];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    d0[t] = __builtin_fma(s0.u.x, zx[t], __builtin_fma(s0.u.y, zy[t], s0.a + zz[t]));
+    d1[t] = __builtin_fma(s1.u.x, zx[t], __builtin_fma(s1.u.y, zy[t], s1.a + zz[t]));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  load_far<NR>(n0, rn0, wo, wb);
+  load_far<NR>(n1, rn1, wo, wb);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int t = 0; t < TPT; t += 2) {
+    const double p0 = d0[t] * d0[t + 1], p1 = d1[t] * d1[t + 1];
+    const double R = refine_rcp(p0 * p1);
+    const double r0 = R * p1, r1 = R * p0;
+    const double m[2][2] = {{r0 * d0[t + 1], r0 * d0[t]}, {r1 * d1[t + 1], r1 * d1[t]}};
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        acc.ax[t + v][q] = __builtin_fma(s0.w[q].x, m[0][v], acc.ax[t + v][q]);
+        acc.ay[t + v][q] = __builtin_fma(s0.w[q].y, m[0][v], acc.ay[t + v][q]);
+        acc.bx[t + v][q] = __builtin_fma(s0.b[q].x, m[0][v], acc.bx[t + v][q]);
+        acc.by[t + v][q] = __builtin_fma(s0.b[q].y, m[0][v], acc.by[t + v][q]);
+        acc.ax[t + v][q] = __builtin_fma(s1.w[q].x, m[1][v], acc.ax[t + v][q]);
+        acc.ay[t + v][q] = __builtin_fma(s1.w[q].y, m[1][v], acc.ay[t + v][q]);
+        acc.bx[t + v][q] = __builtin_fma(s1.b[q].x, m[1][v], acc.bx[t + v][q]);
+        acc.by[t + v][q] = __builtin_fma(s1.b[q].y, m[1][v], acc.by[t + v][q]);
+      }
+  }
+}
+
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void stream_far4(AccAB<NR, TPT>& acc, const double (&zx)[TPT], const double (&zy)[TPT],
+                                            const double (&zz)[TPT], P rec, int stride, int wo, int wb, int ja,
+                                            int jb) {
+  static_assert(TPT % 2 == 0, "targets are paired");
+  if (jb - ja < 4) {
+    // short tail segment
+    FarRec<NR> a, b;
+    if (ja >= jb) return;
+    load_far<NR>(a, rec + (size_t)ja * stride, wo, wb);
+    for (int j = ja; j < jb; ++j) {
+      stream_step_far<NR, TPT>(acc, zx, zy, zz, a, b, rec + (size_t)min(j + 1, jb - 1) * stride, wo, wb);
+      a = b;
+    }
+    return;
+  }
+  FarRec<NR> a0, a1, b0, b1;
+  load_far<NR>(a0, rec + (size_t)ja * stride, wo, wb);
+  load_far<NR>(a1, rec + (size_t)(ja + 1) * stride, wo, wb);
+  int j = ja;
+  const int last = jb - 1;
+  for (; j + 3 < jb; j += 4) {
+    stream_step_far2<NR, TPT>(acc, zx, zy, zz, a0, a1, b0, b1, rec + (size_t)(j + 2) * stride,
+                              rec + (size_t)(j + 3) * stride, wo, wb);
+    stream_step_far2<NR, TPT>(acc, zx, zy, zz, b0, b1, a0, a1, rec + (size_t)min(j + 4, last) * stride,
+                              rec + (size_t)min(j + 5, last) * stride, wo, wb);
+  }
+  // 0-3 sources left: a0, a1 hold sources j and j + 1 when they exist
+  if (j + 1 < jb) {
+    stream_step_far2<NR, TPT>(acc, zx, zy, zz, a0, a1, b0, b1, rec + (size_t)min(j + 2, last) * stride,
+                              rec + (size_t)min(j + 3, last) * stride, wo, wb);
+    j += 2;
+    a0 = b0;
+  }
+  if (j < jb) stream_step_far<NR, TPT>(acc, zx, zy, zz, a0, b0, rec + (size_t)j * stride, wo, wb);
 }
 
 // sources [ja, jb) of a far tile; the last prefetch re-reads source jb - 1
@@ -479,7 +560,10 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
 #pragma unroll
           for (int r = 0; r < NR; ++r) ab.ax[t][r] = ab.ay[t][r] = ab.bx[t][r] = ab.by[t][r] = 0.0;
         }
-        if constexpr (TPT % 2 == 0) {
+        if constexpr (NR == 1 && TPT % 2 == 0) {
+          stream_far4<NR, TPT>(ab, zx, zy, zz, rec, stride, wo, wb, ts, te);
+        } else if constexpr (TPT % 2 == 0) {
+          // two columns: four records of two-column fields would spill
           stream_far<NR, TPT>(ab, zx, zy, zz, rec, stride, wo, wb, ts, te);
         } else {
           int j = ts;
