@@ -46,8 +46,8 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # KiB, the factors from a 256 MiB copy of known size; profiles/*_hbm_counters.md).
 # Valid only for that N and the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "pair_steps.inl", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "d4fd8278e0450ec679b8219296d97323acb6d203f520cc269c357739a3e21d18",
-                "N": 264192, "bytes_per_launch": 518435964}
+                "sha256": "38eeb31c1bb0b47712df0425636475efe4d9e122f287395ed11703c91f7bed6a",
+                "N": 264192, "bytes_per_launch": 518457089}
 
 
 def pair_traffic(N):
