@@ -46,7 +46,7 @@ FLOPS_PER_PAIR = 16.0            # one column: 2 sub, |d|^2 (3), reciprocal (1),
 # KiB, the factors from a 256 MiB copy of known size; profiles/*_hbm_counters.md).
 # Valid only for that N and the kernel sources they were taken on (hash below), else null.
 PAIR_TRAFFIC = {"sources": ("cauchy.hip", "pair_steps.inl", "gnk_device.h", "gnk_internal.h"),
-                "sha256": "38eeb31c1bb0b47712df0425636475efe4d9e122f287395ed11703c91f7bed6a",
+                "sha256": "ee869c570c521e57036ff54079c03cab365223db8583a3842d9b03f430a3ae44",
                 "N": 264192, "bytes_per_launch": 518457089}
 
 

@@ -515,8 +515,15 @@ __device__ __forceinline__ void pair_item(gptr<const double2> rec, gptr<const fl
         quad_step<NR, TPT>(acc, tg, r, r + stride, r + 2 * stride, r + 3 * stride, wo);
       } else {
         // four wide records would not fit in scalar registers together
-        pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
-        pair_step<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
+        if constexpr (NR == 8 && TPT % 2 == 0) {
+          // one reciprocal for two sources and two targets (4 columns: the
+          // extra registers cost a wave per SIMD)
+          pair_step_t2<NR, TPT>(acc, tg, r, r + stride, wo);
+          pair_step_t2<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
+        } else {
+          pair_step<NR, TPT>(acc, tg, r, r + stride, wo);
+          pair_step<NR, TPT>(acc, tg, r + 2 * stride, r + 3 * stride, wo);
+        }
       }
     }
     for (; j + 1 < jb; j += 2) {

@@ -155,3 +155,35 @@ __device__ __forceinline__ void stream_range(Acc<NR, TPT>& acc, const double2 (&
   }
   if (j < jb) stream_step<NR, TPT>(acc, tg, a, b, rec + (size_t)j * stride, wo);
 }
+
+// Two sources a, b against the lane's targets taken in twos (TPT even), one
+// reciprocal for the four pairs: with P_t = |da_t|^2 |db_t|^2 and
+// R = 1/(P_0 P_1), 1/|da_0|^2 = R P_1 |db_0|^2 and so on (the product stays in
+// range while every squared distance lies in [1e-75, 1e75]).
+template <int NR, int TPT, class P>
+__device__ __forceinline__ void pair_step_t2(Acc<NR, TPT>& acc, const double2 (&tg)[TPT], P ra, P rb, int wo) {
+  static_assert(TPT % 2 == 0, "targets are paired");
+  const double2 ea = ra[0], eb = rb[0];
+#pragma unroll
+  for (int t = 0; t < TPT; t += 2) {
+    double dxa[2], dya[2], dxb[2], dyb[2], da[2], db[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      dxa[u] = tg[t + u].x - ea.x;
+      dya[u] = tg[t + u].y - ea.y;
+      dxb[u] = tg[t + u].x - eb.x;
+      dyb[u] = tg[t + u].y - eb.y;
+      da[u] = __builtin_fma(dya[u], dya[u], dxa[u] * dxa[u]);
+      db[u] = __builtin_fma(dyb[u], dyb[u], dxb[u] * dxb[u]);
+    }
+    const double p0 = da[0] * db[0], p1 = da[1] * db[1];
+    const double R = refine_rcp(p0 * p1);
+    const double r[2] = {R * p1, R * p0};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double qa = db[u] * r[u], qb = da[u] * r[u];
+      accumulate<NR, TPT>(acc, t + u, ra + wo, dxa[u] * qa, -dya[u] * qa);
+      accumulate<NR, TPT>(acc, t + u, rb + wo, dxb[u] * qb, -dyb[u] * qb);
+    }
+  }
+}
