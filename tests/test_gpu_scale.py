@@ -1,9 +1,13 @@
 """Scale invariance of the discrete system (GPU): with A = 1 the kernel
 K_ij = (2/n) eta'_j/(eta_j - eta_i) (eqs. (e:N), (e:M)) is unchanged by
 eta -> s eta, so mu and h of FBIE are those of the unscaled domain for the
-same gamma. Solved at s = 1e6 and 1e-6 in FP64 and in mixed precision (the
-FP32 far tiles: one column on the VALU, several on the matrix cores) and
-compared with the oracle's unscaled solution at 1e-10."""
+same gamma. Solved at s = 1e6, 1e-6, 1e15 and 1e-15 in FP64 and in mixed
+precision (the FP32 far tiles: one column on the VALU, several on the matrix
+cores) and compared with the oracle's unscaled solution at 1e-10. At 1e-15
+the closest nodes of the close-boundary case are about 1e-20 apart: the FP64
+loops share one reciprocal among four pairs, so they invert products of four
+squared distances (about 1e-160 there, 1e127 at the far end of 1e15), which
+must stay in the normal FP64 range."""
 import copy
 
 import numpy as np
@@ -56,7 +60,7 @@ def sep_many():
     return dom, gam, mu, h
 
 
-@pytest.mark.parametrize("s", [1e6, 1e-6])
+@pytest.mark.parametrize("s", [1e6, 1e-6, 1e15, 1e-15])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", ["close_one", "sep_many"])
 def test_scaled_domain_matches_unscaled_oracle(gk, ctx, request, s, prec, case):
